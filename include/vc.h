@@ -1,0 +1,209 @@
+/*
+ * vc.h -- C ABI of libvc, an MI355X (gfx950) implementation of the
+ * vertex-centric (Pregel) superstep.
+ *
+ * What is computed (paper, Section I): a program runs as a sequence of
+ * supersteps.  In each superstep every active vertex broadcasts a message
+ * along its CSR out-edges; the messages addressed to one vertex are merged
+ * into that vertex's mailbox by a combiner (paper, Section III); at the next
+ * superstep a vertex that received a message is active again.  The run ends
+ * when no vertex is active.  Programs (paper, Section VI-C, "Benchmarks"):
+ *
+ *   VC_PAGERANK    rank(0) = 1/N; for s = 1..T:
+ *                  rank = (1-d)/N + d * sum of incoming rank(u)/outdeg(u);
+ *                  vertices without out-edges send nothing (their mass is
+ *                  dropped).  Combiner: sum.  Result: rank after T updates.
+ *   VC_PPR         personalised PageRank: rank(0) = [v == source] and the
+ *                  teleport term is (1-d) * [v == source].  Combiner: sum.
+ *   VC_CC_HASHMIN  label(0) = v; a vertex adopts the smallest label it
+ *                  receives when that is below its own and broadcasts it.
+ *                  Combiner: min.  Result: on a symmetric graph, the smallest
+ *                  vertex id of each connected component.
+ *   VC_SSSP        dist(0) = 0 at the source, "unreached" (0xFFFFFFFF)
+ *                  elsewhere; a vertex adopts the smallest dist(u) + w(u,v)
+ *                  it receives when that is below its own and sends
+ *                  dist + w(e) along each out-edge e.  Combiner: min.  Result:
+ *                  shortest-path distances; no weight array = unit weights.
+ *
+ * Data types: results are IEEE binary32 ranks or uint32 labels / distances.
+ * An SSSP distance that would reach 0xFFFFFFFF saturates there and reads as
+ * "unreached".  The sum combiner of PageRank / PPR is, by default, exact: each
+ * message is a uint64 multiple of 2^-62 (ranks never exceed 1), mailboxes add
+ * them with 64-bit integer atomics, the vertex update runs in binary64 and
+ * only the returned rank is rounded to binary32, so results do not depend on
+ * message arrival order.  VC_OPT_F32_ACCUMULATE selects binary32 messages and
+ * float atomics instead (half the mailbox bytes, order-dependent rounding).
+ *
+ * Memory: every pointer named "device" is device memory of the GPU that is
+ * current when the call is made; every pointer named "host" is host memory.
+ * The library never frees caller memory.
+ *
+ * Errors: every call returns a vc_status; nothing throws across the ABI.
+ * vc_last_error() returns a thread-local text describing the last failure of
+ * the calling thread.
+ *
+ * Threads and streams: a vc_graph may be used by one host thread at a time.
+ * All device work is enqueued on the stream passed to the call.
+ */
+#ifndef VC_H_
+#define VC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VC_ABI_VERSION 1
+
+typedef enum {
+  VC_OK = 0,
+  VC_ERR_INVALID_ARG = 1,   /* null / misaligned pointer, bad enum, wrong struct_size, source >= N */
+  VC_ERR_BAD_GRAPH = 2,     /* CSR failed validation (see VC_GRAPH_VALIDATE) */
+  VC_ERR_OUT_OF_MEMORY = 3, /* a device allocation failed */
+  VC_ERR_HIP = 4,           /* a HIP runtime call failed; vc_last_error() names it */
+  VC_ERR_UNSUPPORTED = 5,   /* the combination of arguments is not implemented */
+  VC_ERR_NOT_CONVERGED = 6  /* CC / SSSP hit the superstep cap before quiescence */
+} vc_status;
+
+typedef enum { VC_PAGERANK = 0, VC_CC_HASHMIN = 1, VC_SSSP = 2, VC_PPR = 3 } vc_program;
+
+/* How a superstep's messages are delivered and combined.
+ *   VC_SCHED_VERTEX  push, one thread per active vertex (paper, Section V:
+ *                    vertex-centric work distribution);
+ *   VC_SCHED_EDGE    push, equal numbers of edges per workgroup (paper,
+ *                    Section V: edge-centric; merge-path partition over the
+ *                    CSR offsets / frontier degree prefix);
+ *   VC_SCHED_PULL    receivers read the outbox of their in-neighbours over
+ *                    the transposed graph and combine in place (paper,
+ *                    Section VI-C: single-broadcast); needs the transpose,
+ *                    which the library builds on first use;
+ *   VC_SCHED_AUTO    per superstep: pull for dense frontiers, edge-centric
+ *                    push otherwise (vertex push for tiny ones). */
+typedef enum { VC_SCHED_AUTO = 0, VC_SCHED_VERTEX = 1, VC_SCHED_EDGE = 2, VC_SCHED_PULL = 3 } vc_schedule;
+
+typedef enum { VC_IDX_I32 = 0, VC_IDX_I64 = 1 } vc_index_type;
+
+/* vc_graph_desc.flags */
+enum {
+  VC_GRAPH_BORROW = 1u,    /* keep the caller's device arrays instead of copying them */
+  VC_GRAPH_VALIDATE = 2u,  /* check the CSR on the device at creation */
+  VC_GRAPH_SYMMETRIC = 4u  /* caller asserts the graph equals its transpose, weights included
+                              (not checked); the pull form then reads the CSR itself */
+};
+
+/* vc_params.options */
+enum {
+  VC_OPT_NO_HUB_AGGREGATION = 1u, /* disable workgroup-level pre-combination for hub targets */
+  VC_OPT_NO_TEST_BEFORE_ATOMIC = 2u, /* min programs: skip the mailbox read before the atomic (for measurement) */
+  VC_OPT_F32_ACCUMULATE = 4u         /* PageRank / PPR: binary32 messages and float atomics */
+};
+
+typedef struct vc_graph_s* vc_graph;
+
+/* A CSR graph of out-edges.
+ *   offsets   device, num_vertices + 1 entries of int32 or int64
+ *             (offset_type); offsets[0] = 0, non-decreasing,
+ *             offsets[num_vertices] = num_edges.  int32 requires
+ *             num_edges < 2^31.
+ *   dst       device, num_edges int32 targets in [0, num_vertices).
+ *   weights   device, num_edges uint32 SSSP weights, or NULL (unit weights).
+ * Every entry is an edge: parallel edges count in the out-degree and in the
+ * sums, and a self-loop delivers to its own source. */
+typedef struct {
+  uint32_t struct_size; /* sizeof(vc_graph_desc) */
+  uint32_t flags;       /* VC_GRAPH_* */
+  int64_t num_vertices; /* 1 .. 2^31 - 1 */
+  int64_t num_edges;    /* >= 0 */
+  vc_index_type offset_type;
+  const void* offsets;
+  const int32_t* dst;
+  const uint32_t* weights;
+} vc_graph_desc;
+
+typedef struct {
+  uint32_t struct_size;   /* sizeof(vc_params) */
+  int32_t max_supersteps; /* PageRank / PPR: T, the number of rank updates (>= 0).
+                             CC / SSSP: superstep cap; 0 selects N + 1, which no
+                             valid run exceeds. */
+  double damping;         /* PageRank / PPR damping d in [0, 1]; 0.85 in the benchmarks */
+  uint32_t source;        /* SSSP / PPR source vertex, < N */
+  vc_schedule schedule;   /* VC_SCHED_AUTO picks per superstep from |F| and E_F */
+  int32_t tile;           /* merge-path items per workgroup tile; 0 = library default */
+  uint32_t options;       /* VC_OPT_* */
+} vc_params;
+
+/* Per-run statistics.  The caller owns every array (host memory) and sets
+ * capacity to their length; entries beyond capacity are not written.
+ * Superstep s reports |F_s| (vertices that broadcast, including those without
+ * out-edges) and E_s (messages sent = out-edges of F_s). */
+typedef struct {
+  uint32_t struct_size;  /* sizeof(vc_stats) */
+  int32_t supersteps;    /* out: supersteps executed */
+  int64_t edges_relaxed; /* out: sum of E_s */
+  double elapsed_ms;     /* out: host wall time of vc_run */
+  int32_t capacity;      /* in: length of the arrays below (0 = none) */
+  int64_t* frontier;     /* out, host, or NULL: |F_s| */
+  int64_t* edges;        /* out, host, or NULL: E_s */
+  float* scatter_ms;     /* out, host, or NULL: device time of the broadcast+combine
+                            kernel(s) of superstep s, from HIP events on the run's
+                            stream (recording them adds small gaps) */
+  float* step_ms;        /* out, host, or NULL: device time of the whole superstep */
+  int32_t* schedule;     /* out, host, or NULL: schedule used (VC_SCHED_VERTEX / _EDGE /
+                            _PULL), 0 for supersteps without a broadcast */
+} vc_stats;
+
+/* Creates a graph object from a CSR (paper, Section I: vertices with
+ * out-edges and mailboxes; Section IV: the hot per-vertex fields are kept in
+ * their own arrays, separate from everything else).
+ *   desc     host; arrays per vc_graph_desc.
+ *   stream   stream for the copy / validation work; the call returns after
+ *            that work has completed.
+ *   out      host; receives the new handle.
+ * Without VC_GRAPH_BORROW the arrays are copied into library-owned device
+ * memory and may be freed by the caller on return; with it the caller keeps
+ * them alive and unchanged until vc_graph_destroy.
+ * Errors: VC_ERR_INVALID_ARG (null pointer, struct_size, N out of range,
+ * int32 offsets with num_edges >= 2^31), VC_ERR_BAD_GRAPH (VALIDATE only),
+ * VC_ERR_OUT_OF_MEMORY, VC_ERR_HIP.  On error *out is left unchanged. */
+vc_status vc_graph_create(const vc_graph_desc* desc, hipStream_t stream, vc_graph* out);
+
+/* Releases a graph and its device workspace.  Waits for the device to finish
+ * work that uses it.  NULL is accepted.  Errors: VC_ERR_HIP. */
+vc_status vc_graph_destroy(vc_graph g);
+
+/* Device bytes held for the graph (CSR copies + workspace already allocated)
+ * and the bytes a run of `program` would add.  Used for admission by HBM
+ * footprint.  bytes_held / bytes_run are host pointers, either may be NULL. */
+vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held, size_t* bytes_run);
+
+/* Runs one program to completion (paper, Section I) with its combiner (paper,
+ * Section III): sum for VC_PAGERANK / VC_PPR, min for VC_CC_HASHMIN / VC_SSSP.
+ *   params   host, may be NULL for defaults (T = 10, d = 0.85, source 0, AUTO).
+ *   out      device, N x 4 bytes, caller-owned: float ranks (PageRank, PPR) or
+ *            uint32 labels / distances (CC, SSSP).
+ *   stream   all device work is enqueued here; the call returns after `out`
+ *            is complete.
+ *   stats    host, may be NULL.
+ * Errors: VC_ERR_INVALID_ARG (bad program / params / source, null out),
+ * VC_ERR_NOT_CONVERGED (cap reached; `out` holds the values at the cap),
+ * VC_ERR_OUT_OF_MEMORY, VC_ERR_HIP.  On any other error the contents of `out`
+ * are unspecified. */
+vc_status vc_run(vc_graph g, vc_program program, const vc_params* params, void* out, hipStream_t stream,
+                 vc_stats* stats);
+
+/* Fills *p with the defaults used when vc_run receives NULL params. */
+void vc_params_default(vc_params* p);
+
+const char* vc_status_string(vc_status s);
+const char* vc_last_error(void);
+int vc_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VC_H_ */

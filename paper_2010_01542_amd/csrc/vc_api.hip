@@ -1,0 +1,634 @@
+// C ABI of libvc: graph objects, workspace, and the superstep driver.
+//
+// The driver runs the superstep loop of the paper's Section I on the host:
+// per superstep it enqueues the broadcast + combine kernels and the vertex
+// update, then (CC / SSSP) reads back the size of the next frontier to decide
+// termination and the work distribution of the next broadcast (Section V:
+// one thread per vertex, or edge-balanced merge-path tiles).
+#include <chrono>
+#include <cstdlib>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "vc_internal.h"
+
+namespace {
+
+thread_local std::string t_last_error;
+
+vc_status fail(vc_status st, const std::string& msg) {
+  t_last_error = msg;
+  return st;
+}
+
+vc_status hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? VC_ERR_OUT_OF_MEMORY : VC_ERR_HIP,
+              std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
+}
+
+#define VC_TRY(call)                                  \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+
+// A device buffer owned by a graph, grown on demand and kept across runs.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t want) {
+    if (want <= bytes) return hipSuccess;
+    if (p) {
+      hipError_t e = hipFree(p);
+      if (e != hipSuccess) return e;
+      p = nullptr;
+      bytes = 0;
+    }
+    if (want == 0) return hipSuccess;
+    hipError_t e = hipMalloc(&p, want);
+    if (e == hipSuccess) bytes = want;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+}  // namespace
+
+struct vc_graph_s {
+  int64_t n = 0, m = 0;
+  bool off64 = false;
+  uint32_t flags = 0;
+  int device = 0;
+  const void* off = nullptr;
+  const int32_t* dst = nullptr;
+  const uint32_t* w = nullptr;
+  DevBuf own_off, own_dst, own_w;  // copies when not borrowed
+  // workspace
+  DevBuf contrib, mb;                             // PageRank / PPR
+  DevBuf vm, bitmap, bitmap2, fq, prefix, scan_blocks;  // CC / SSSP (two bitmaps: improved / active)
+  DevBuf list_tiles;                              // per-superstep merge-path partition
+  DevBuf dense_tiles;                             // merge-path partition of the CSR itself
+  int64_t dense_tile = 0, dense_ntiles = 0;
+  // transpose (CSC) for the pull form; for symmetric graphs only csc_off is
+  // owned (int64 copy of the offsets) and csc_src / csc_w alias the CSR
+  DevBuf csc_off, csc_src, csc_w, csc_tiles;
+  const int32_t* in_src = nullptr;
+  const uint32_t* in_w = nullptr;
+  bool csc_ready = false;
+  int64_t csc_tile = 0, csc_ntiles = 0;
+  DevBuf counters;
+  size_t max_lds = 65536;            // dynamic LDS limit per workgroup on the graph's device
+  vc::Counters* host_ctr = nullptr;  // pinned
+  std::vector<hipEvent_t> events;
+};
+
+namespace {
+
+size_t workspace_bytes(int64_t n, int64_t m, vc_program p, int64_t tile) {
+  const size_t N = (size_t)n;
+  const size_t tiles = (size_t)((n + m) / tile + 2) * sizeof(int32_t);
+  if (p == VC_PAGERANK || p == VC_PPR) return 2 * N * 8 + tiles;
+  return N * 8 + ((N + 31) / 32) * 4 + N * 4 + (N + 1) * 8 + (size_t)vc::scan_scratch_entries(n) * 8 + 2 * tiles +
+         sizeof(vc::Counters);
+}
+
+hipError_t ensure_events(vc_graph g, size_t count) {
+  while (g->events.size() < count) {
+    hipEvent_t e;
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return err;
+    g->events.push_back(e);
+  }
+  return hipSuccess;
+}
+
+// Statistics recorder; tolerates a NULL vc_stats.
+struct Recorder {
+  vc_stats* st;
+  bool timed;
+  explicit Recorder(vc_stats* s) : st(s), timed(s && s->capacity > 0 && (s->scatter_ms || s->step_ms)) {}
+  void step(int64_t s, int64_t frontier, int64_t edges, int sched) {
+    if (!st) return;
+    st->edges_relaxed += edges;
+    if (s >= st->capacity) return;
+    if (st->frontier) st->frontier[s] = frontier;
+    if (st->edges) st->edges[s] = edges;
+    if (st->schedule) st->schedule[s] = sched;
+    if (st->scatter_ms) st->scatter_ms[s] = 0.0f;
+    if (st->step_ms) st->step_ms[s] = 0.0f;
+  }
+  bool want_time(int64_t s) const { return timed && s < st->capacity; }
+  void times(int64_t s, float scatter, float step) {
+    if (!want_time(s)) return;
+    if (st->scatter_ms) st->scatter_ms[s] = scatter;
+    if (st->step_ms) st->step_ms[s] = step;
+  }
+};
+
+// Merge-path tile: the requested size clamped to [64, kMaxTile] and to what
+// the largest scatter variant can stage in LDS on this device.
+int64_t pick_tile(const vc_params& p, vc_graph g) {
+  int64_t t = p.tile > 0 ? p.tile : vc::kDefaultTile;
+  if (t < 64) t = 64;
+  if (t > vc::kMaxTile) t = vc::kMaxTile;
+  while (t > 64 && (vc::min_mp_lds_bytes(t, true) > g->max_lds || vc::pr_mp_lds_bytes(t, true) > g->max_lds ||
+                    vc::pull_lds_bytes(t) > g->max_lds))
+    t -= 64;
+  return t;
+}
+
+vc_status dense_partition(vc_graph g, int64_t tile, hipStream_t s) {
+  if (g->dense_tile == tile && g->dense_tiles.p) return VC_OK;
+  const int64_t ntiles = (g->n + g->m + tile - 1) / tile;
+  VC_TRY(g->dense_tiles.ensure((size_t)(ntiles + 1) * sizeof(int32_t)));
+  VC_TRY(vc::launch_mp_partition(g->off, g->off64, g->n, g->n + g->m, tile, ntiles, g->dense_tiles.as<int32_t>(), s));
+  g->dense_tile = tile;
+  g->dense_ntiles = ntiles;
+  return VC_OK;
+}
+
+// Builds the transpose once per graph: in-degree histogram, exclusive scan,
+// then every edge placed at its target's cursor.  Symmetric graphs (flag)
+// read the CSR itself.
+vc_status ensure_csc(vc_graph g, hipStream_t s) {
+  if (g->csc_ready) return VC_OK;
+  const int64_t n = g->n, m = g->m;
+  VC_TRY(g->csc_off.ensure((size_t)(n + 1) * 8));
+  int64_t* in_off = g->csc_off.as<int64_t>();
+  if (g->flags & VC_GRAPH_SYMMETRIC) {
+    if (g->off64) {
+      VC_TRY(hipMemcpyAsync(in_off, g->off, (size_t)(n + 1) * 8, hipMemcpyDeviceToDevice, s));
+    } else {
+      VC_TRY(vc::launch_widen_offsets((const int32_t*)g->off, n + 1, in_off, s));
+    }
+    g->in_src = g->dst;
+    g->in_w = g->w;
+  } else {
+    VC_TRY(g->csc_src.ensure((size_t)m * 4 + 4));
+    if (g->w) VC_TRY(g->csc_w.ensure((size_t)m * 4 + 4));
+    DevBuf blocks, cursor;
+    VC_TRY(blocks.ensure((size_t)vc::scan_scratch_entries(n) * 8));
+    VC_TRY(cursor.ensure((size_t)(n + 1) * 8));
+    VC_TRY(vc::launch_fill_u32(reinterpret_cast<uint32_t*>(in_off), 2 * (n + 1), 0u, s));
+    VC_TRY(vc::launch_csc_count(g->dst, m, reinterpret_cast<unsigned long long*>(in_off), s));
+    VC_TRY(vc::launch_exclusive_scan(in_off, n, blocks.as<int64_t>(), s));
+    VC_TRY(hipMemcpyAsync(cursor.p, in_off, (size_t)(n + 1) * 8, hipMemcpyDeviceToDevice, s));
+    const int64_t tile = vc::kDefaultTile;
+    vc_status st = dense_partition(g, tile, s);
+    if (st != VC_OK) return st;
+    VC_TRY(vc::launch_csc_fill(g->off, g->off64, g->dst, g->w, n, m, g->dense_tiles.as<int32_t>(), tile,
+                               g->dense_ntiles, cursor.as<unsigned long long>(), g->csc_src.as<int32_t>(),
+                               g->w ? g->csc_w.as<uint32_t>() : nullptr, s));
+    VC_TRY(hipStreamSynchronize(s));
+    blocks.release();
+    cursor.release();
+    g->in_src = g->csc_src.as<int32_t>();
+    g->in_w = g->w ? g->csc_w.as<uint32_t>() : nullptr;
+  }
+  g->csc_ready = true;
+  return VC_OK;
+}
+
+vc_status csc_partition(vc_graph g, int64_t tile, hipStream_t s) {
+  if (g->csc_tile == tile && g->csc_tiles.p) return VC_OK;
+  const int64_t ntiles = (g->n + g->m + tile - 1) / tile;
+  VC_TRY(g->csc_tiles.ensure((size_t)(ntiles + 1) * sizeof(int32_t)));
+  VC_TRY(vc::launch_mp_partition(g->csc_off.p, true, g->n, g->n + g->m, tile, ntiles, g->csc_tiles.as<int32_t>(), s));
+  g->csc_tile = tile;
+  g->csc_ntiles = ntiles;
+  return VC_OK;
+}
+
+// ---------------------------------------------------------------- PageRank / PPR
+
+vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hipStream_t s, Recorder& rec,
+                   int32_t* supersteps) {
+  const int64_t n = g->n, T = p.max_supersteps;
+  const int64_t source = personal ? (int64_t)p.source : -1;
+  const bool fx = !(p.options & VC_OPT_F32_ACCUMULATE);
+  const size_t vb = fx ? 8 : 4;
+  VC_TRY(g->contrib.ensure((size_t)n * vb));
+  VC_TRY(g->mb.ensure((size_t)n * vb));
+  void* contrib = g->contrib.p;
+  void* mb = g->mb.p;
+  const double r0 = 1.0 / (double)n;
+  if (T == 0) {
+    VC_TRY(vc::launch_pr_init(fx, g->off, g->off64, n, r0, source, contrib, mb, out, s));
+    VC_TRY(hipStreamSynchronize(s));
+    rec.step(0, 0, 0, 0);
+    *supersteps = 1;
+    return VC_OK;
+  }
+  const double d = p.damping;
+  const double teleport = personal ? (1.0 - d) : (1.0 - d) / (double)n;
+  const int64_t tile = pick_tile(p, g);
+  const int sched = p.schedule == VC_SCHED_AUTO ? VC_SCHED_PULL : p.schedule;
+  if (g->m > 0) {
+    vc_status st = VC_OK;
+    if (sched == VC_SCHED_PULL) {
+      st = ensure_csc(g, s);
+      if (st == VC_OK) st = csc_partition(g, tile, s);
+    } else if (sched == VC_SCHED_EDGE) {
+      st = dense_partition(g, tile, s);
+    }
+    if (st != VC_OK) return st;
+  }
+  if (rec.timed) VC_TRY(ensure_events(g, (size_t)(3 * T)));
+  VC_TRY(vc::launch_pr_init(fx, g->off, g->off64, n, r0, source, contrib, mb, nullptr, s));
+  for (int64_t step = 0; step < T; ++step) {
+    const bool timed = rec.want_time(step);
+    if (timed) VC_TRY(hipEventRecord(g->events[3 * step], s));
+    if (g->m > 0) {
+      if (sched == VC_SCHED_PULL)
+        VC_TRY(vc::launch_pr_pull(fx, g->csc_off.as<int64_t>(), g->in_src, n, g->m, g->csc_tiles.as<int32_t>(), tile,
+                                  g->csc_ntiles, contrib, mb, s));
+      else if (sched == VC_SCHED_EDGE)
+        VC_TRY(vc::launch_pr_scatter_mp(fx, g->off, g->off64, g->dst, n, g->m, g->dense_tiles.as<int32_t>(), tile,
+                                        g->dense_ntiles, contrib, mb, s));
+      else
+        VC_TRY(vc::launch_pr_scatter_vertex(fx, g->off, g->off64, g->dst, n, contrib, mb, s));
+    }
+    if (timed) VC_TRY(hipEventRecord(g->events[3 * step + 1], s));
+    VC_TRY(vc::launch_pr_apply(fx, g->off, g->off64, n, teleport, d, source, mb, contrib, out, step + 1 == T, s));
+    if (timed) VC_TRY(hipEventRecord(g->events[3 * step + 2], s));
+    rec.step(step, n, g->m, sched);
+  }
+  rec.step(T, 0, 0, 0);
+  VC_TRY(hipStreamSynchronize(s));
+  for (int64_t step = 0; step < T && rec.want_time(step); ++step) {
+    float a = 0, b = 0;
+    VC_TRY(hipEventElapsedTime(&a, g->events[3 * step], g->events[3 * step + 1]));
+    VC_TRY(hipEventElapsedTime(&b, g->events[3 * step], g->events[3 * step + 2]));
+    rec.times(step, a, b);
+  }
+  *supersteps = (int32_t)(T + 1);
+  return VC_OK;
+}
+
+// ---------------------------------------------------------------- CC / SSSP
+
+// Fraction of the edges above which a CC / SSSP superstep is pulled: the
+// pull form streams every in-edge, the push form only the frontier's
+// out-edges, so pull pays off once the frontier carries a large share of them.
+double pull_threshold() {
+  static const double v = [] {
+    const char* e = std::getenv("VC_PULL_FRACTION");
+    double x = e ? std::atof(e) : 0.1;
+    return x > 0 ? x : 0.1;
+  }();
+  return v;
+}
+
+vc_status run_min(vc_graph g, const vc_params& p, int kind, uint32_t* out, hipStream_t s, Recorder& rec,
+                  int32_t* supersteps) {
+  const int64_t n = g->n, m = g->m;
+  const int64_t tile = pick_tile(p, g);
+  const bool tba = !(p.options & VC_OPT_NO_TEST_BEFORE_ATOMIC);
+  const int64_t nwords = (n + 31) / 32;
+  VC_TRY(g->vm.ensure((size_t)n * 8));
+  VC_TRY(g->bitmap.ensure((size_t)nwords * 4));
+  VC_TRY(g->bitmap2.ensure((size_t)nwords * 4));
+  VC_TRY(g->fq.ensure((size_t)n * 4));
+  VC_TRY(g->prefix.ensure((size_t)(n + 1) * 8));
+  VC_TRY(g->scan_blocks.ensure((size_t)vc::scan_scratch_entries(n) * 8));
+  VC_TRY(g->list_tiles.ensure((size_t)((n + m) / tile + 3) * sizeof(int32_t)));
+  VC_TRY(g->counters.ensure(sizeof(vc::Counters)));
+  if (!g->host_ctr) VC_TRY(hipHostMalloc((void**)&g->host_ctr, sizeof(vc::Counters), hipHostMallocDefault));
+  uint2* vm = g->vm.as<uint2>();
+  uint32_t* bits[2] = {g->bitmap.as<uint32_t>(), g->bitmap2.as<uint32_t>()};
+  int32_t* fq = g->fq.as<int32_t>();
+  int64_t* P = g->prefix.as<int64_t>();
+  int32_t* list_tiles = g->list_tiles.as<int32_t>();
+  vc::Counters* ctr = g->counters.as<vc::Counters>();
+
+  const int64_t source = kind == vc::kCC ? -1 : (int64_t)p.source;
+  VC_TRY(vc::launch_min_init(kind, n, source, vm, s));
+  VC_TRY(vc::launch_fill_u32(bits[0], nwords, 0u, s));
+  VC_TRY(vc::launch_fill_u32(bits[1], nwords, 0u, s));
+  VC_TRY(vc::launch_zero_counters(ctr, s));
+  if (rec.timed) VC_TRY(ensure_events(g, 4));
+
+  // improvements of superstep s go to bits[cur]; bits[1 - cur] holds F_s
+  int cur = 0;
+  bool dense = kind == vc::kCC;  // superstep 0: every vertex broadcasts (CC) or only the source (SSSP)
+  bool prefix_ready = false;
+  int64_t frontier = 0, listed = 0, edges = 0;
+  if (dense) {
+    frontier = n;
+    listed = n;
+    edges = m;
+  } else {
+    int64_t o[2] = {0, 0};
+    if (g->off64) {
+      VC_TRY(hipMemcpyAsync(o, (const int64_t*)g->off + source, 16, hipMemcpyDeviceToHost, s));
+      VC_TRY(hipStreamSynchronize(s));
+    } else {
+      int32_t o32[2] = {0, 0};
+      VC_TRY(hipMemcpyAsync(o32, (const int32_t*)g->off + source, 8, hipMemcpyDeviceToHost, s));
+      VC_TRY(hipStreamSynchronize(s));
+      o[0] = o32[0];
+      o[1] = o32[1];
+    }
+    frontier = 1;
+    edges = o[1] - o[0];
+    listed = edges > 0 ? 1 : 0;
+    VC_TRY(vc::launch_min_seed_source(g->off, g->off64, source, fq, P, bits[1], s));
+    prefix_ready = true;
+  }
+  const int64_t cap = p.max_supersteps > 0 ? (int64_t)p.max_supersteps : n + 1;
+  vc_status status = VC_OK;
+  int64_t step = 0;
+  for (;;) {
+    if (frontier == 0 || edges == 0) {
+      rec.step(step, frontier, edges, 0);
+      *supersteps = (int32_t)(step + 1);
+      break;
+    }
+    int sched = p.schedule;
+    if (sched == VC_SCHED_AUTO) {
+      if ((double)edges >= pull_threshold() * (double)m)
+        sched = VC_SCHED_PULL;
+      else
+        sched = edges <= 256 ? VC_SCHED_VERTEX : VC_SCHED_EDGE;
+    }
+    rec.step(step, frontier, edges, sched);
+    const bool timed = rec.want_time(step);
+    if (timed) VC_TRY(hipEventRecord(g->events[0], s));
+    uint32_t* improved = bits[cur];
+    if (sched == VC_SCHED_PULL) {
+      vc_status st = ensure_csc(g, s);
+      if (st == VC_OK) st = csc_partition(g, tile, s);
+      if (st != VC_OK) return st;
+      if (timed) VC_TRY(hipEventRecord(g->events[1], s));
+      VC_TRY(vc::launch_min_pull(kind, g->csc_off.as<int64_t>(), g->in_src, g->in_w, n, m, g->csc_tiles.as<int32_t>(),
+                                 tile, g->csc_ntiles, vm, dense ? nullptr : bits[1 - cur], improved, s));
+    } else if (sched == VC_SCHED_EDGE) {
+      if (dense) {
+        vc_status st = dense_partition(g, tile, s);
+        if (st != VC_OK) return st;
+        if (timed) VC_TRY(hipEventRecord(g->events[1], s));
+        VC_TRY(vc::launch_min_scatter_mp(kind, false, tba, g->off, g->off64, g->dst, g->w, n, n + m, nullptr, nullptr,
+                                         g->dense_tiles.as<int32_t>(), tile, g->dense_ntiles, vm, improved, s));
+      } else {
+        if (!prefix_ready) VC_TRY(vc::launch_exclusive_scan(P, listed, g->scan_blocks.as<int64_t>(), s));
+        const int64_t total = listed + edges;
+        const int64_t ntiles = (total + tile - 1) / tile;
+        VC_TRY(vc::launch_mp_partition(P, true, listed, total, tile, ntiles, list_tiles, s));
+        if (timed) VC_TRY(hipEventRecord(g->events[1], s));
+        VC_TRY(vc::launch_min_scatter_mp(kind, true, tba, g->off, g->off64, g->dst, g->w, listed, total, P, fq,
+                                         list_tiles, tile, ntiles, vm, improved, s));
+      }
+    } else {
+      if (timed) VC_TRY(hipEventRecord(g->events[1], s));
+      VC_TRY(vc::launch_min_scatter_vertex(kind, !dense, tba, g->off, g->off64, g->dst, g->w, dense ? n : listed, fq,
+                                           vm, improved, s));
+    }
+    if (timed) VC_TRY(hipEventRecord(g->events[2], s));
+    VC_TRY(vc::launch_min_compact(g->off, g->off64, n, vm, improved, bits[1 - cur], fq, P, ctr, s));
+    if (timed) VC_TRY(hipEventRecord(g->events[3], s));
+    VC_TRY(hipMemcpyAsync(g->host_ctr, ctr, sizeof(vc::Counters), hipMemcpyDeviceToHost, s));
+    VC_TRY(vc::launch_zero_counters(ctr, s));
+    VC_TRY(hipStreamSynchronize(s));
+    if (timed) {
+      float a = 0, b = 0;
+      VC_TRY(hipEventElapsedTime(&a, g->events[1], g->events[2]));
+      VC_TRY(hipEventElapsedTime(&b, g->events[0], g->events[3]));
+      rec.times(step, a, b);
+    }
+    frontier = (int64_t)g->host_ctr->active;
+    listed = (int64_t)g->host_ctr->listed;
+    edges = (int64_t)g->host_ctr->edges;
+    dense = false;
+    prefix_ready = false;
+    cur = 1 - cur;
+    ++step;
+    if (step >= cap) {
+      *supersteps = (int32_t)step;
+      status = fail(VC_ERR_NOT_CONVERGED, "superstep cap reached before quiescence");
+      break;
+    }
+  }
+  VC_TRY(vc::launch_min_output(n, vm, out, s));
+  VC_TRY(hipStreamSynchronize(s));
+  return status;
+}
+
+bool valid_params(const vc_params& p, vc_program prog, int64_t n, std::string* why) {
+  if (p.struct_size != sizeof(vc_params)) return *why = "vc_params.struct_size mismatch", false;
+  if (p.schedule < VC_SCHED_AUTO || p.schedule > VC_SCHED_PULL) return *why = "bad schedule", false;
+  if (p.tile < 0) return *why = "negative tile", false;
+  if (prog == VC_PAGERANK || prog == VC_PPR) {
+    if (p.max_supersteps < 0) return *why = "PageRank needs T >= 0", false;
+    if (!(p.damping >= 0.0 && p.damping <= 1.0)) return *why = "damping outside [0, 1]", false;
+  } else if (p.max_supersteps < 0) {
+    return *why = "negative superstep cap", false;
+  }
+  if ((prog == VC_SSSP || prog == VC_PPR) && (int64_t)p.source >= n) return *why = "source >= N", false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vc_abi_version(void) { return VC_ABI_VERSION; }
+
+const char* vc_last_error(void) { return t_last_error.c_str(); }
+
+const char* vc_status_string(vc_status s) {
+  switch (s) {
+    case VC_OK: return "ok";
+    case VC_ERR_INVALID_ARG: return "invalid argument";
+    case VC_ERR_BAD_GRAPH: return "bad graph";
+    case VC_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case VC_ERR_HIP: return "HIP runtime error";
+    case VC_ERR_UNSUPPORTED: return "unsupported";
+    case VC_ERR_NOT_CONVERGED: return "superstep cap reached";
+  }
+  return "unknown status";
+}
+
+void vc_params_default(vc_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->struct_size = sizeof(vc_params);
+  p->max_supersteps = 10;
+  p->damping = 0.85;
+  p->source = 0;
+  p->schedule = VC_SCHED_AUTO;
+  p->tile = 0;
+  p->options = 0;
+}
+
+vc_status vc_graph_create(const vc_graph_desc* d, hipStream_t stream, vc_graph* out) {
+  if (!d || !out) return fail(VC_ERR_INVALID_ARG, "null desc or out");
+  if (d->struct_size != sizeof(vc_graph_desc)) return fail(VC_ERR_INVALID_ARG, "vc_graph_desc.struct_size mismatch");
+  if (d->num_vertices < 1 || d->num_vertices > 2147483647LL)
+    return fail(VC_ERR_INVALID_ARG, "num_vertices must be in [1, 2^31 - 1]");
+  if (d->num_edges < 0) return fail(VC_ERR_INVALID_ARG, "negative num_edges");
+  if (d->offset_type != VC_IDX_I32 && d->offset_type != VC_IDX_I64) return fail(VC_ERR_INVALID_ARG, "bad offset_type");
+  if (d->offset_type == VC_IDX_I32 && d->num_edges >= 2147483648LL)
+    return fail(VC_ERR_INVALID_ARG, "int32 offsets need num_edges < 2^31");
+  if (!d->offsets || (d->num_edges > 0 && !d->dst)) return fail(VC_ERR_INVALID_ARG, "null offsets or dst");
+  const size_t ow = d->offset_type == VC_IDX_I64 ? 8 : 4;
+  if (((uintptr_t)d->offsets % ow) || ((uintptr_t)d->dst % 4) || ((uintptr_t)d->weights % 4))
+    return fail(VC_ERR_INVALID_ARG, "misaligned array");
+
+  vc_graph g = new (std::nothrow) vc_graph_s();
+  if (!g) return fail(VC_ERR_OUT_OF_MEMORY, "host allocation failed");
+  auto cleanup = [g](vc_status st) {
+    vc_graph_destroy(g);
+    return st;
+  };
+  hipError_t e = hipGetDevice(&g->device);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "hipGetDevice"));
+  int lds = 0;
+  e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "hipDeviceGetAttribute"));
+  if (lds > 0) g->max_lds = (size_t)lds;
+  g->n = d->num_vertices;
+  g->m = d->num_edges;
+  g->off64 = d->offset_type == VC_IDX_I64;
+  g->flags = d->flags;
+  if (d->flags & VC_GRAPH_BORROW) {
+    g->off = d->offsets;
+    g->dst = d->dst;
+    g->w = d->weights;
+  } else {
+    const size_t ob = (size_t)(g->n + 1) * ow, eb = (size_t)g->m * 4;
+    if ((e = g->own_off.ensure(ob)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc offsets"));
+    if ((e = hipMemcpyAsync(g->own_off.p, d->offsets, ob, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
+      return cleanup(hip_fail(e, "copy offsets"));
+    g->off = g->own_off.p;
+    if (eb) {
+      if ((e = g->own_dst.ensure(eb)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc dst"));
+      if ((e = hipMemcpyAsync(g->own_dst.p, d->dst, eb, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
+        return cleanup(hip_fail(e, "copy dst"));
+      g->dst = g->own_dst.as<int32_t>();
+      if (d->weights) {
+        if ((e = g->own_w.ensure(eb)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc weights"));
+        if ((e = hipMemcpyAsync(g->own_w.p, d->weights, eb, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
+          return cleanup(hip_fail(e, "copy weights"));
+        g->w = g->own_w.as<uint32_t>();
+      }
+    }
+  }
+  if (d->flags & VC_GRAPH_VALIDATE) {
+    if ((e = g->counters.ensure(sizeof(vc::Counters))) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+    vc::Counters h{};
+    if ((e = vc::launch_zero_counters(g->counters.as<vc::Counters>(), stream)) != hipSuccess ||
+        (e = vc::launch_validate(g->off, g->off64, g->dst, g->n, g->m, g->counters.as<vc::Counters>(), stream)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(&h, g->counters.p, sizeof h, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(stream)) != hipSuccess)
+      return cleanup(hip_fail(e, "validation"));
+    if (h.flags) {
+      std::string why;
+      if (h.flags & 1) why += " offsets[0] != 0;";
+      if (h.flags & 2) why += " offsets[N] != num_edges;";
+      if (h.flags & 4) why += " offsets decrease;";
+      if (h.flags & 8) why += " dst out of range;";
+      return cleanup(fail(VC_ERR_BAD_GRAPH, "CSR validation failed:" + why));
+    }
+  }
+  if ((e = hipStreamSynchronize(stream)) != hipSuccess) return cleanup(hip_fail(e, "graph create"));
+  *out = g;
+  return VC_OK;
+}
+
+vc_status vc_graph_destroy(vc_graph g) {
+  if (!g) return VC_OK;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(g->device);
+  (void)hipDeviceSynchronize();
+  for (DevBuf* b : {&g->own_off, &g->own_dst, &g->own_w, &g->contrib, &g->mb, &g->vm, &g->bitmap, &g->bitmap2,
+                    &g->fq, &g->prefix, &g->scan_blocks, &g->list_tiles, &g->dense_tiles, &g->csc_off, &g->csc_src,
+                    &g->csc_w, &g->csc_tiles, &g->counters})
+    b->release();
+  if (g->host_ctr) (void)hipHostFree(g->host_ctr);
+  for (hipEvent_t e : g->events) (void)hipEventDestroy(e);
+  (void)hipSetDevice(prev);
+  delete g;
+  return VC_OK;
+}
+
+vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held, size_t* bytes_run) {
+  if (!g) return fail(VC_ERR_INVALID_ARG, "null graph");
+  if (program < VC_PAGERANK || program > VC_PPR) return fail(VC_ERR_INVALID_ARG, "bad program");
+  size_t held = g->own_off.bytes + g->own_dst.bytes + g->own_w.bytes;
+  for (const DevBuf* b : {&g->contrib, &g->mb, &g->vm, &g->bitmap, &g->bitmap2, &g->fq, &g->prefix, &g->scan_blocks,
+                          &g->list_tiles, &g->dense_tiles, &g->csc_off, &g->csc_src, &g->csc_w, &g->csc_tiles,
+                          &g->counters})
+    held += b->bytes;
+  if (bytes_held) *bytes_held = held;
+  if (bytes_run) {
+    // workspace of the program plus the transpose the pull form reads
+    const size_t want = workspace_bytes(g->n, g->m, program, vc::kDefaultTile);
+    size_t have = 0;
+    if (program == VC_PAGERANK || program == VC_PPR)
+      have = g->contrib.bytes + g->mb.bytes + g->dense_tiles.bytes;
+    else
+      have = g->vm.bytes + g->bitmap.bytes + g->bitmap2.bytes + g->fq.bytes + g->prefix.bytes +
+             g->scan_blocks.bytes + g->list_tiles.bytes + g->dense_tiles.bytes + g->counters.bytes;
+    const size_t csc_want = (size_t)(g->n + 1) * 8 + (size_t)((g->n + g->m) / vc::kDefaultTile + 2) * 4 +
+                            ((g->flags & VC_GRAPH_SYMMETRIC) ? 0 : (size_t)g->m * (g->w ? 8 : 4));
+    const size_t csc_have = g->csc_off.bytes + g->csc_src.bytes + g->csc_w.bytes + g->csc_tiles.bytes;
+    *bytes_run = (want > have ? want - have : 0) + (csc_want > csc_have ? csc_want - csc_have : 0);
+  }
+  return VC_OK;
+}
+
+vc_status vc_run(vc_graph g, vc_program program, const vc_params* params, void* out, hipStream_t stream,
+                 vc_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!g) return fail(VC_ERR_INVALID_ARG, "null graph");
+  if (!out) return fail(VC_ERR_INVALID_ARG, "null out");
+  if ((uintptr_t)out % 4) return fail(VC_ERR_INVALID_ARG, "misaligned out");
+  if (program < VC_PAGERANK || program > VC_PPR) return fail(VC_ERR_INVALID_ARG, "bad program");
+  vc_params p;
+  if (params) {
+    p = *params;
+  } else {
+    vc_params_default(&p);
+  }
+  std::string why;
+  if (!valid_params(p, program, g->n, &why)) return fail(VC_ERR_INVALID_ARG, why);
+  if (stats) {
+    if (stats->struct_size != sizeof(vc_stats)) return fail(VC_ERR_INVALID_ARG, "vc_stats.struct_size mismatch");
+    if (stats->capacity < 0) return fail(VC_ERR_INVALID_ARG, "negative stats capacity");
+    stats->supersteps = 0;
+    stats->edges_relaxed = 0;
+    stats->elapsed_ms = 0;
+  }
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != g->device) return fail(VC_ERR_INVALID_ARG, "graph lives on another device than the current one");
+  Recorder rec(stats);
+  int32_t supersteps = 0;
+  vc_status st;
+  if (program == VC_PAGERANK || program == VC_PPR)
+    st = run_rank(g, p, program == VC_PPR, static_cast<float*>(out), stream, rec, &supersteps);
+  else
+    st = run_min(g, p, program == VC_CC_HASHMIN ? vc::kCC : (g->w ? vc::kSsspWeighted : vc::kSsspUnit),
+                 static_cast<uint32_t*>(out), stream, rec, &supersteps);
+  if (stats) {
+    stats->supersteps = supersteps;
+    stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return st;
+}
+
+}  // extern "C"

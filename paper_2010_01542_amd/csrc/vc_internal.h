@@ -1,0 +1,96 @@
+// Internal declarations shared by the kernel and host translation units of
+// libvc.  Not part of the public ABI (include/vc.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vc.h"
+
+namespace vc {
+
+constexpr int kWG = 256;                    // threads per workgroup (4 waves of 64)
+constexpr uint32_t kInf = 0xFFFFFFFFu;      // min-combiner neutral value / "unreached"
+constexpr int64_t kDefaultTile = 2048;      // merge-path items (vertex-ends + edges) per workgroup
+constexpr int64_t kMaxTile = 8192;
+
+// Device counters written by the frontier compaction of the min programs.
+struct Counters {
+  unsigned long long active;  // |F_{s+1}|: vertices whose value improved
+  unsigned long long listed;  // those with at least one out-edge (the broadcast list)
+  unsigned long long edges;   // E_{s+1}: out-edges of the improved vertices
+  unsigned long long flags;   // validation error bits
+};
+
+enum MinKind { kCC = 0, kSsspUnit = 1, kSsspWeighted = 2 };
+
+// Bytes of dynamic LDS a merge-path scatter tile of `tile` items needs.
+size_t pr_mp_lds_bytes(int64_t tile, bool off64);
+size_t min_mp_lds_bytes(int64_t tile, bool list);
+
+// ---------------------------------------------------------------- launchers
+// Every launcher enqueues on `s` and returns the launch status.  `off` points
+// at int32 or int64 offsets (off64 selects).
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t s);
+hipError_t launch_validate(const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m, Counters* ctr,
+                           hipStream_t s);
+
+// Merge-path partition of the merged (edge, vertex-end) sequence of a
+// non-decreasing prefix array P[0..items]: tile_v[t] = number of vertex-ends
+// before position min(t * tile, items + P[items]).
+hipError_t launch_mp_partition(const void* P, bool p64, int64_t items, int64_t total, int64_t tile, int64_t ntiles,
+                               int32_t* tile_v, hipStream_t s);
+
+// PageRank / PPR.  `source` < 0 selects PageRank, else PPR from `source`.
+// fx selects the fixed-point (uint64, 2^-62) combiner, else binary32; the
+// contrib and mb buffers hold 8- or 4-byte values accordingly.
+hipError_t launch_pr_init(bool fx, const void* off, bool off64, int64_t n, double r0, int64_t source, void* contrib,
+                          void* mb, float* out_if_t0, hipStream_t s);
+hipError_t launch_pr_scatter_vertex(bool fx, const void* off, bool off64, const int32_t* dst, int64_t n,
+                                    const void* contrib, void* mb, hipStream_t s);
+hipError_t launch_pr_scatter_mp(bool fx, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
+                                const int32_t* tile_v, int64_t tile, int64_t ntiles, const void* contrib, void* mb,
+                                hipStream_t s);
+hipError_t launch_pr_apply(bool fx, const void* off, bool off64, int64_t n, double teleport, double damping,
+                           int64_t source, void* mb, void* contrib, float* out, bool last, hipStream_t s);
+
+// Hash-min CC and SSSP.  vm holds (value, mailbox) pairs.
+hipError_t launch_min_init(int kind, int64_t n, int64_t source, uint2* vm, hipStream_t s);
+hipError_t launch_min_seed_source(const void* off, bool off64, int64_t source, int32_t* fq, int64_t* P,
+                                  uint32_t* active, hipStream_t s);
+hipError_t launch_min_scatter_vertex(int kind, bool list, bool tba, const void* off, bool off64, const int32_t* dst,
+                                     const uint32_t* w, int64_t items, const int32_t* fq, uint2* vm, uint32_t* bitmap,
+                                     hipStream_t s);
+hipError_t launch_min_scatter_mp(int kind, bool list, bool tba, const void* off, bool off64, const int32_t* dst,
+                                 const uint32_t* w, int64_t items, int64_t total, const int64_t* P, const int32_t* fq,
+                                 const int32_t* tile_v, int64_t tile, int64_t ntiles, uint2* vm, uint32_t* bitmap,
+                                 hipStream_t s);
+hipError_t launch_min_compact(const void* off, bool off64, int64_t n, uint2* vm, const uint32_t* bitmap,
+                              uint32_t* stale, int32_t* fq, int64_t* P, Counters* ctr, hipStream_t s);
+hipError_t launch_min_output(int64_t n, const uint2* vm, uint32_t* out, hipStream_t s);
+hipError_t launch_zero_counters(Counters* ctr, hipStream_t s);
+
+// ---------------------------------------------------------------- pull form
+// Transpose: in-degree histogram (cnt: n + 1 zeroed entries), then placement
+// of every edge at cursor[dst]++ (cursor = exclusive scan of cnt).
+hipError_t launch_csc_count(const int32_t* dst, int64_t m, unsigned long long* cnt, hipStream_t s);
+hipError_t launch_widen_offsets(const int32_t* a, int64_t count, int64_t* b, hipStream_t s);
+hipError_t launch_csc_fill(const void* off, bool off64, const int32_t* dst, const uint32_t* w, int64_t n, int64_t m,
+                           const int32_t* tile_v, int64_t tile, int64_t ntiles, unsigned long long* cursor,
+                           int32_t* in_src, uint32_t* in_w, hipStream_t s);
+size_t pull_lds_bytes(int64_t tile);
+hipError_t launch_pr_pull(bool fx, const int64_t* in_off, const int32_t* in_src, int64_t n, int64_t m,
+                          const int32_t* tile_v, int64_t tile, int64_t ntiles, const void* contrib, void* mb,
+                          hipStream_t s);
+// active = NULL: every vertex broadcast this superstep.
+hipError_t launch_min_pull(int kind, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w, int64_t n,
+                           int64_t m, const int32_t* tile_v, int64_t tile, int64_t ntiles, uint2* vm,
+                           const uint32_t* active, uint32_t* improved, hipStream_t s);
+
+// In-place exclusive scan of P[0..count) with P[count] = total; `blocks`
+// is scratch of scan_scratch_entries(count) int64 values.
+int64_t scan_scratch_entries(int64_t count);
+hipError_t launch_exclusive_scan(int64_t* P, int64_t count, int64_t* blocks, hipStream_t s);
+
+}  // namespace vc

@@ -1,0 +1,690 @@
+// HIP kernels of the vertex-centric superstep for CDNA4 (gfx950).
+//
+// One superstep = broadcast along CSR out-edges + combine into per-vertex
+// mailboxes (paper, Sections I and III), followed by the vertex update.
+//
+// Layout (paper, Section IV: keep the fields touched per message together and
+// apart from everything else):
+//   PageRank  contrib[N] f32 (the message each vertex sends: rank / outdeg)
+//             mb[N]      f32 (sum mailbox, neutral 0)
+//   CC/SSSP   vm[N]      (value, mailbox) u32 pairs: the per-target check,
+//                        the combine and the update all touch one 8-byte slot
+//             bitmap     one bit per vertex: "value improved this superstep"
+//
+// Work distribution (paper, Section V): either one thread per active vertex,
+// or merge-path tiles that give every workgroup the same number of items of
+// the merged (edge, vertex-end) sequence, so hubs are split across
+// workgroups and runs of edge-less vertices cost one item each.
+#include "vc_device.h"
+
+namespace vc {
+namespace {
+
+using namespace dev;
+
+// ------------------------------------------------------------------ generic
+
+__global__ __launch_bounds__(kWG) void k_fill_u32(uint32_t* __restrict__ p, int64_t count, uint32_t value) {
+  const int64_t i = gid();
+  if (i < count) p[i] = value;
+}
+
+__global__ void k_zero_counters(Counters* c) {
+  if (threadIdx.x == 0) {
+    c->active = 0;
+    c->listed = 0;
+    c->edges = 0;
+    c->flags = 0;
+  }
+}
+
+// CSR checks: off[0] = 0, off[n] = m, non-decreasing, targets in range.
+template <class OffT>
+__global__ __launch_bounds__(kWG) void k_validate(const OffT* __restrict__ off, const int32_t* __restrict__ dst,
+                                                  int64_t n, int64_t m, Counters* ctr) {
+  const int64_t i = gid();
+  unsigned long long bad = 0;
+  if (i == 0) {
+    if ((int64_t)off[0] != 0) bad |= 1;
+    if ((int64_t)off[n] != m) bad |= 2;
+  }
+  if (i < n && (int64_t)off[i + 1] < (int64_t)off[i]) bad |= 4;
+  for (int64_t e = i; e < m; e += (int64_t)gridDim.x * kWG) {
+    const int32_t d = dst[e];
+    if (d < 0 || (int64_t)d >= n) bad |= 8;
+  }
+  if (bad) atomicOr(&ctr->flags, bad);
+}
+
+// tile_v[t] = #{x in [0, items) : P[x+1] + x + 1 <= k}, k = min(t * tile, total):
+// the number of vertex-ends that precede merged position k when edge e of
+// item x sits at position e + x and the end of item x at P[x+1] + x.
+template <class PT>
+__global__ __launch_bounds__(kWG) void k_mp_partition(const PT* __restrict__ P, int64_t items, int64_t total,
+                                                      int64_t tile, int64_t ntiles, int32_t* __restrict__ tile_v) {
+  const int64_t t = gid();
+  if (t > ntiles) return;
+  const int64_t k = t * tile < total ? t * tile : total;
+  int64_t lo = 0, hi = items;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)P[mid + 1] + mid + 1 <= k)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  tile_v[t] = (int32_t)lo;
+}
+
+// ------------------------------------------------------------------ PageRank
+// Two combiners for the sum mailboxes:
+//  * fixed point (default): messages and mailboxes are uint64 multiples of
+//    2^-62 (ranks and their sums never exceed 1).  Integer addition is exact
+//    and associative, so a mailbox holds the exact sum of its messages in any
+//    arrival order; the vertex update runs in binary64 and only the final
+//    result is rounded to binary32.
+//  * binary32: float messages combined with hardware float atomics (rounding
+//    at every combination, in arrival order).
+constexpr double kFxScale = 4611686018427387904.0;  // 2^62
+constexpr double kFxInv = 1.0 / 4611686018427387904.0;
+
+template <class V>
+__device__ __forceinline__ void sum_combine(V* __restrict__ mb, int32_t d, V msg);
+template <>
+__device__ __forceinline__ void sum_combine<float>(float* __restrict__ mb, int32_t d, float msg) {
+  unsafeAtomicAdd(&mb[d], msg);
+}
+template <>
+__device__ __forceinline__ void sum_combine<unsigned long long>(unsigned long long* __restrict__ mb, int32_t d,
+                                                                unsigned long long msg) {
+  atomicAdd(&mb[d], msg);
+}
+
+// The message a vertex with out-degree `deg` and rank r sends on each edge.
+template <class V>
+__device__ __forceinline__ V rank_message(double r, int64_t deg);
+template <>
+__device__ __forceinline__ float rank_message<float>(double r, int64_t deg) {
+  return deg > 0 ? (float)r / (float)deg : 0.0f;
+}
+template <>
+__device__ __forceinline__ unsigned long long rank_message<unsigned long long>(double r, int64_t deg) {
+  return deg > 0 ? __double2ull_rn(r / (double)deg * kFxScale) : 0ull;
+}
+
+template <class OffT, class V>
+__global__ __launch_bounds__(kWG) void k_pr_init(const OffT* __restrict__ off, int64_t n, double r0, int64_t source,
+                                                 V* __restrict__ contrib, V* __restrict__ mb,
+                                                 float* __restrict__ out_if_t0) {
+  const int64_t v = gid();
+  if (v >= n) return;
+  const double r = source >= 0 ? (v == source ? 1.0 : 0.0) : r0;
+  if (out_if_t0) {
+    out_if_t0[v] = (float)r;
+    return;
+  }
+  const int64_t deg = (int64_t)off[v + 1] - (int64_t)off[v];
+  contrib[v] = rank_message<V>(r, deg);
+  mb[v] = V(0);
+}
+
+// Vertex-per-thread broadcast: thread v sends contrib[v] along its out-edges.
+template <class OffT, class V>
+__global__ __launch_bounds__(kWG) void k_pr_scatter_vertex(const OffT* __restrict__ off,
+                                                           const int32_t* __restrict__ dst, int64_t n,
+                                                           const V* __restrict__ contrib, V* __restrict__ mb) {
+  const int64_t v = gid();
+  if (v >= n) return;
+  const V c = contrib[v];
+  if (c == V(0)) return;  // adding zero changes no sum (PPR vertices the walk has not reached)
+  const int64_t e1 = (int64_t)off[v + 1];
+  for (int64_t e = (int64_t)off[v]; e < e1; ++e) sum_combine<V>(mb, dst[e], c);
+}
+
+// Merge-path broadcast: workgroup t owns merged positions [t*tile, (t+1)*tile).
+template <class OffT, class V>
+__global__ __launch_bounds__(kWG) void k_pr_scatter_mp(const OffT* __restrict__ off, const int32_t* __restrict__ dst,
+                                                       int64_t n, int64_t m, const int32_t* __restrict__ tile_v,
+                                                       int64_t tile, const V* __restrict__ contrib,
+                                                       V* __restrict__ mb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t t = blockIdx.x;
+  const int64_t k0 = t * tile;
+  const int64_t k1 = (k0 + tile < n + m) ? k0 + tile : n + m;
+  const int64_t i0 = tile_v[t], i1 = tile_v[t + 1];
+  const int64_t j0 = k0 - i0, j1 = k1 - i1;
+  if (j1 <= j0) return;  // only vertex-ends in this tile (uniform over the workgroup)
+  const int64_t ilast = i1 < n ? i1 : n - 1;
+  const int cnt = (int)(ilast - i0 + 1);  // vertices i0..ilast own the tile's edges
+  V* s_val = reinterpret_cast<V*>(smem);                                         // tile + 1
+  OffT* s_off = reinterpret_cast<OffT*>(smem + align16((tile + 1) * sizeof(V)));  // tile + 2
+  for (int x = threadIdx.x; x <= cnt; x += kWG) s_off[x] = off[i0 + x];
+  for (int x = threadIdx.x; x < cnt; x += kWG) s_val[x] = contrib[i0 + x];
+  __syncthreads();
+  for (int64_t e = j0 + threadIdx.x; e < j1; e += kWG) {
+    int lo = 0, hi = cnt - 1;  // owner = last x with s_off[x] <= e
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if ((int64_t)s_off[mid] <= e)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const V c = s_val[lo];
+    const int32_t d = dst[e];
+    if (c != V(0)) sum_combine<V>(mb, d, c);
+  }
+}
+
+// rank = teleport + d * (sum of messages); reset the mailbox; next message.
+template <class OffT, class V>
+__global__ __launch_bounds__(kWG) void k_pr_apply(const OffT* __restrict__ off, int64_t n, double teleport,
+                                                  double damping, int64_t source, V* __restrict__ mb,
+                                                  V* __restrict__ contrib, float* __restrict__ out, int last) {
+  const int64_t v = gid();
+  if (v >= n) return;
+  const double tele = source >= 0 ? (v == source ? teleport : 0.0) : teleport;
+  double r;
+  if constexpr (sizeof(V) == 8) {
+    r = fma(damping, (double)mb[v] * kFxInv, tele);
+  } else {
+    r = (double)fmaf((float)damping, mb[v], (float)tele);
+  }
+  if (last) {
+    out[v] = (float)r;
+    return;
+  }
+  mb[v] = V(0);
+  const int64_t deg = (int64_t)off[v + 1] - (int64_t)off[v];
+  contrib[v] = rank_message<V>(r, deg);
+}
+
+// ------------------------------------------------------------------ CC / SSSP
+
+__global__ __launch_bounds__(kWG) void k_min_init(int kind, int64_t n, int64_t source, uint2* __restrict__ vm) {
+  const int64_t v = gid();
+  if (v >= n) return;
+  const uint32_t val = kind == kCC ? (uint32_t)v : (v == source ? 0u : kInf);
+  vm[v] = make_uint2(val, kInf);
+}
+
+template <class OffT>
+__global__ void k_min_seed_source(const OffT* __restrict__ off, int64_t source, int32_t* __restrict__ fq,
+                                  int64_t* __restrict__ P, uint32_t* __restrict__ active) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    fq[0] = (int32_t)source;
+    P[0] = 0;
+    P[1] = (int64_t)off[source + 1] - (int64_t)off[source];
+    active[source >> 5] |= 1u << (source & 31);
+  }
+}
+
+template <int KIND>
+__device__ __forceinline__ uint32_t message(uint32_t val, const uint32_t* __restrict__ w, int64_t pos) {
+  if (KIND == kCC) return val;
+  if (KIND == kSsspUnit) return sat_add(val, 1u);
+  return sat_add(val, w[pos]);
+}
+
+// Min combine into target d.  Messages that cannot lower d's value are
+// dropped; the mailbox is read first and the atomic skipped when it cannot
+// win (the skip of a no-op combination, paper Section III, Figure 1).  The
+// message that first lowers an untouched mailbox marks d as improved.
+template <bool TBA>
+__device__ __forceinline__ void relax(uint2* __restrict__ vm, uint32_t* __restrict__ bitmap, int32_t d,
+                                      uint32_t msg) {
+  const uint2 cur = vm[d];
+  if (msg < cur.x && (!TBA || msg < cur.y)) {
+    const uint32_t old = atomicMin(&reinterpret_cast<uint32_t*>(vm)[2 * (int64_t)d + 1], msg);
+    if (old == kInf) atomicOr(&bitmap[d >> 5], 1u << (d & 31));
+  }
+}
+
+template <class OffT, int KIND, bool LIST, bool TBA>
+__global__ __launch_bounds__(kWG) void k_min_scatter_vertex(const OffT* __restrict__ off,
+                                                            const int32_t* __restrict__ dst,
+                                                            const uint32_t* __restrict__ w, int64_t items,
+                                                            const int32_t* __restrict__ fq, uint2* __restrict__ vm,
+                                                            uint32_t* __restrict__ bitmap) {
+  const int64_t x = gid();
+  if (x >= items) return;
+  const int64_t v = LIST ? (int64_t)fq[x] : x;
+  const uint32_t val = vm[v].x;
+  const int64_t e1 = (int64_t)off[v + 1];
+  for (int64_t e = (int64_t)off[v]; e < e1; ++e) relax<TBA>(vm, bitmap, dst[e], message<KIND>(val, w, e));
+}
+
+// Merge-path broadcast for the min programs.  Dense mode: items are all
+// vertices and P is the CSR offsets.  List mode: items are the broadcast
+// list fq and P its degree prefix; item x's edges start at off[fq[x]].
+template <class PT, class OffT, int KIND, bool LIST, bool TBA>
+__global__ __launch_bounds__(kWG) void k_min_scatter_mp(const OffT* __restrict__ off,
+                                                        const int32_t* __restrict__ dst,
+                                                        const uint32_t* __restrict__ w, int64_t items, int64_t total,
+                                                        const PT* __restrict__ P, const int32_t* __restrict__ fq,
+                                                        const int32_t* __restrict__ tile_v, int64_t tile,
+                                                        uint2* __restrict__ vm, uint32_t* __restrict__ bitmap) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t t = blockIdx.x;
+  const int64_t k0 = t * tile;
+  const int64_t k1 = (k0 + tile < total) ? k0 + tile : total;
+  const int64_t i0 = tile_v[t], i1 = tile_v[t + 1];
+  const int64_t j0 = k0 - i0, j1 = k1 - i1;
+  if (j1 <= j0) return;
+  const int64_t ilast = i1 < items ? i1 : items - 1;
+  const int cnt = (int)(ilast - i0 + 1);
+  int64_t* s_p = reinterpret_cast<int64_t*>(smem);  // tile + 2 entries
+  int64_t* s_base = s_p + tile + 2;                 // tile + 1 entries (list mode; 8-byte aligned)
+  uint32_t* s_val = reinterpret_cast<uint32_t*>(LIST ? s_base + tile + 1 : s_base);
+  for (int x = threadIdx.x; x <= cnt; x += kWG) s_p[x] = (int64_t)P[i0 + x];
+  for (int x = threadIdx.x; x < cnt; x += kWG) {
+    const int64_t v = LIST ? (int64_t)fq[i0 + x] : i0 + x;
+    if (LIST) s_base[x] = (int64_t)off[v] - (int64_t)P[i0 + x];
+    s_val[x] = vm[v].x;
+  }
+  __syncthreads();
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += kWG) {
+    int lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_p[mid] <= j)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const int64_t pos = LIST ? j + s_base[lo] : j;
+    relax<TBA>(vm, bitmap, dst[pos], message<KIND>(s_val[lo], w, pos));
+  }
+}
+
+// Vertex update + frontier compaction.  One thread per bitmap word: every
+// improved vertex adopts its mailbox (value = mailbox, mailbox = neutral);
+// those with out-edges are appended, in id order within the workgroup, to
+// the broadcast list with their degree (for the next merge-path prefix).
+// `bitmap` (this superstep's improvements) is kept: it is the next
+// superstep's active set for the pull form.  `stale` (the previous active
+// set) is cleared so it can collect the next improvements.
+template <class OffT>
+__global__ __launch_bounds__(kWG) void k_min_compact(const OffT* __restrict__ off, int64_t n, uint2* __restrict__ vm,
+                                                     const uint32_t* __restrict__ bitmap, uint32_t* __restrict__ stale,
+                                                     int64_t nwords, int32_t* __restrict__ fq,
+                                                     int64_t* __restrict__ P, Counters* __restrict__ ctr) {
+  const int64_t wi = gid();
+  uint32_t word = 0;
+  if (wi < nwords) {
+    word = bitmap[wi];
+    if (stale[wi]) stale[wi] = 0;
+  }
+  uint32_t active = 0, listed = 0;
+  unsigned long long edges = 0;
+  for (uint32_t bits = word; bits; bits &= bits - 1) {
+    const int64_t v = wi * 32 + (__ffs(bits) - 1);
+    const uint2 p = vm[v];
+    vm[v] = make_uint2(p.y, kInf);
+    const int64_t deg = (int64_t)off[v + 1] - (int64_t)off[v];
+    ++active;
+    if (deg > 0) {
+      ++listed;
+      edges += (unsigned long long)deg;
+    }
+  }
+  uint32_t tot_listed;
+  uint32_t pos = block_excl_scan<uint32_t>(listed, &tot_listed);
+  const uint32_t tot_active = block_sum<uint32_t>(active);
+  const unsigned long long tot_edges = block_sum<unsigned long long>(edges);
+  __shared__ unsigned long long s_base;
+  if (threadIdx.x == 0) {
+    s_base = tot_listed ? atomicAdd(&ctr->listed, (unsigned long long)tot_listed) : 0ull;
+    if (tot_active) atomicAdd(&ctr->active, (unsigned long long)tot_active);
+    if (tot_edges) atomicAdd(&ctr->edges, tot_edges);
+  }
+  __syncthreads();
+  if (!listed) return;
+  int64_t at = (int64_t)s_base + pos;
+  for (uint32_t bits = word; bits; bits &= bits - 1) {
+    const int64_t v = wi * 32 + (__ffs(bits) - 1);
+    const int64_t deg = (int64_t)off[v + 1] - (int64_t)off[v];
+    if (deg > 0) {
+      fq[at] = (int32_t)v;
+      P[at] = deg;
+      ++at;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_min_output(int64_t n, const uint2* __restrict__ vm,
+                                                    uint32_t* __restrict__ out) {
+  const int64_t v = gid();
+  if (v < n) out[v] = vm[v].x;
+}
+
+// ------------------------------------------------------------------ scan
+// Reduce-then-scan over blocks of kScanItems int64 values.
+constexpr int kScanPer = 8;
+constexpr int64_t kScanItems = (int64_t)kWG * kScanPer;
+
+__global__ __launch_bounds__(kWG) void k_scan_reduce(const int64_t* __restrict__ P, int64_t count,
+                                                     int64_t* __restrict__ blocks) {
+  const int64_t base = (int64_t)blockIdx.x * kScanItems;
+  long long acc = 0;
+  for (int k = 0; k < kScanPer; ++k) {
+    const int64_t i = base + (int64_t)k * kWG + threadIdx.x;
+    if (i < count) acc += P[i];
+  }
+  acc = block_sum<long long>(acc);
+  if (threadIdx.x == 0) blocks[blockIdx.x] = acc;
+}
+
+// One workgroup scans the block sums in place and writes P[count] = total.
+__global__ __launch_bounds__(1024) void k_scan_top(int64_t* __restrict__ blocks, int64_t nblocks,
+                                                   int64_t* __restrict__ P, int64_t count) {
+  __shared__ long long s_w[1024 / 64];
+  __shared__ long long s_carry;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (int64_t b0 = 0; b0 < nblocks; b0 += 1024) {
+    const int64_t i = b0 + threadIdx.x;
+    const long long x = i < nblocks ? blocks[i] : 0;
+    const long long inc = wave_incl_scan<long long>(x);
+    if (lane_id() == 63) s_w[threadIdx.x >> 6] = inc;
+    __syncthreads();
+    long long before = s_carry, tot = 0;
+    for (int k = 0; k < 1024 / 64; ++k) {
+      if (k < (int)(threadIdx.x >> 6)) before += s_w[k];
+      tot += s_w[k];
+    }
+    if (i < nblocks) blocks[i] = before + inc - x;
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) P[count] = s_carry;
+}
+
+__global__ __launch_bounds__(kWG) void k_scan_down(int64_t* __restrict__ P, int64_t count,
+                                                   const int64_t* __restrict__ blocks) {
+  const int64_t base = (int64_t)blockIdx.x * kScanItems + (int64_t)threadIdx.x * kScanPer;
+  long long v[kScanPer];
+  long long sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = (base + k < count) ? P[base + k] : 0;
+    sum += v[k];
+  }
+  long long tot;
+  long long run = block_excl_scan<long long>(sum, &tot) + blocks[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    if (base + k < count) P[base + k] = run;
+    run += v[k];
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+size_t pr_mp_lds_bytes(int64_t tile, bool off64) {
+  return align16((size_t)(tile + 1) * 8) + (size_t)(tile + 2) * (off64 ? 8 : 4);
+}
+
+size_t min_mp_lds_bytes(int64_t tile, bool list) {
+  return (size_t)(tile + 2) * 8 + (list ? (size_t)(tile + 1) * 8 : 0) + (size_t)(tile + 1) * 4;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(count)), dim3(kWG), 0, s, p, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_counters(Counters* ctr, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m, Counters* ctr,
+                           hipStream_t s) {
+  const int64_t blocks = (n + kWG) / kWG;
+  const unsigned g = (unsigned)(blocks < 65536 ? blocks : 65536);
+  if (off64)
+    hipLaunchKernelGGL(k_validate<int64_t>, dim3(g), dim3(kWG), 0, s, (const int64_t*)off, dst, n, m, ctr);
+  else
+    hipLaunchKernelGGL(k_validate<int32_t>, dim3(g), dim3(kWG), 0, s, (const int32_t*)off, dst, n, m, ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_mp_partition(const void* P, bool p64, int64_t items, int64_t total, int64_t tile, int64_t ntiles,
+                               int32_t* tile_v, hipStream_t s) {
+  const unsigned g = grid_for(ntiles + 1);
+  if (p64)
+    hipLaunchKernelGGL(k_mp_partition<int64_t>, dim3(g), dim3(kWG), 0, s, (const int64_t*)P, items, total, tile,
+                       ntiles, tile_v);
+  else
+    hipLaunchKernelGGL(k_mp_partition<int32_t>, dim3(g), dim3(kWG), 0, s, (const int32_t*)P, items, total, tile,
+                       ntiles, tile_v);
+  return hipGetLastError();
+}
+
+namespace {
+template <class V>
+hipError_t pr_launch_all(int what, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
+                         const int32_t* tile_v, int64_t tile, int64_t ntiles, double a, double b, int64_t source,
+                         void* contrib, void* mb, float* out, bool last, hipStream_t s) {
+  V* c = static_cast<V*>(contrib);
+  V* mbx = static_cast<V*>(mb);
+  switch (what) {
+    case 0:  // init; a = r0
+      if (off64)
+        hipLaunchKernelGGL((k_pr_init<int64_t, V>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int64_t*)off, n, a,
+                           source, c, mbx, out);
+      else
+        hipLaunchKernelGGL((k_pr_init<int32_t, V>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int32_t*)off, n, a,
+                           source, c, mbx, out);
+      break;
+    case 1:  // vertex-per-thread broadcast
+      if (off64)
+        hipLaunchKernelGGL((k_pr_scatter_vertex<int64_t, V>), dim3(grid_for(n)), dim3(kWG), 0, s,
+                           (const int64_t*)off, dst, n, c, mbx);
+      else
+        hipLaunchKernelGGL((k_pr_scatter_vertex<int32_t, V>), dim3(grid_for(n)), dim3(kWG), 0, s,
+                           (const int32_t*)off, dst, n, c, mbx);
+      break;
+    case 2: {  // merge-path broadcast
+      const size_t lds = align16((size_t)(tile + 1) * sizeof(V)) + (size_t)(tile + 2) * (off64 ? 8 : 4);
+      if (off64)
+        hipLaunchKernelGGL((k_pr_scatter_mp<int64_t, V>), dim3((unsigned)ntiles), dim3(kWG), lds, s,
+                           (const int64_t*)off, dst, n, m, tile_v, tile, c, mbx);
+      else
+        hipLaunchKernelGGL((k_pr_scatter_mp<int32_t, V>), dim3((unsigned)ntiles), dim3(kWG), lds, s,
+                           (const int32_t*)off, dst, n, m, tile_v, tile, c, mbx);
+      break;
+    }
+    default:  // apply; a = teleport, b = damping
+      if (off64)
+        hipLaunchKernelGGL((k_pr_apply<int64_t, V>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int64_t*)off, n, a,
+                           b, source, mbx, c, out, (int)last);
+      else
+        hipLaunchKernelGGL((k_pr_apply<int32_t, V>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int32_t*)off, n, a,
+                           b, source, mbx, c, out, (int)last);
+  }
+  return hipGetLastError();
+}
+
+inline hipError_t pr_launch(bool fx, int what, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
+                            const int32_t* tile_v, int64_t tile, int64_t ntiles, double a, double b, int64_t source,
+                            void* contrib, void* mb, float* out, bool last, hipStream_t s) {
+  return fx ? pr_launch_all<unsigned long long>(what, off, off64, dst, n, m, tile_v, tile, ntiles, a, b, source,
+                                                contrib, mb, out, last, s)
+            : pr_launch_all<float>(what, off, off64, dst, n, m, tile_v, tile, ntiles, a, b, source, contrib, mb, out,
+                                   last, s);
+}
+}  // namespace
+
+hipError_t launch_pr_init(bool fx, const void* off, bool off64, int64_t n, double r0, int64_t source, void* contrib,
+                          void* mb, float* out_if_t0, hipStream_t s) {
+  return pr_launch(fx, 0, off, off64, nullptr, n, 0, nullptr, 0, 0, r0, 0, source, contrib, mb, out_if_t0, false, s);
+}
+
+hipError_t launch_pr_scatter_vertex(bool fx, const void* off, bool off64, const int32_t* dst, int64_t n,
+                                    const void* contrib, void* mb, hipStream_t s) {
+  return pr_launch(fx, 1, off, off64, dst, n, 0, nullptr, 0, 0, 0, 0, -1, const_cast<void*>(contrib), mb, nullptr,
+                   false, s);
+}
+
+hipError_t launch_pr_scatter_mp(bool fx, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
+                                const int32_t* tile_v, int64_t tile, int64_t ntiles, const void* contrib, void* mb,
+                                hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  return pr_launch(fx, 2, off, off64, dst, n, m, tile_v, tile, ntiles, 0, 0, -1, const_cast<void*>(contrib), mb,
+                   nullptr, false, s);
+}
+
+hipError_t launch_pr_apply(bool fx, const void* off, bool off64, int64_t n, double teleport, double damping,
+                           int64_t source, void* mb, void* contrib, float* out, bool last, hipStream_t s) {
+  return pr_launch(fx, 3, off, off64, nullptr, n, 0, nullptr, 0, 0, teleport, damping, source, contrib, mb, out, last,
+                   s);
+}
+
+hipError_t launch_min_init(int kind, int64_t n, int64_t source, uint2* vm, hipStream_t s) {
+  hipLaunchKernelGGL(k_min_init, dim3(grid_for(n)), dim3(kWG), 0, s, kind, n, source, vm);
+  return hipGetLastError();
+}
+
+hipError_t launch_min_seed_source(const void* off, bool off64, int64_t source, int32_t* fq, int64_t* P,
+                                  uint32_t* active, hipStream_t s) {
+  if (off64)
+    hipLaunchKernelGGL(k_min_seed_source<int64_t>, dim3(1), dim3(64), 0, s, (const int64_t*)off, source, fq, P,
+                       active);
+  else
+    hipLaunchKernelGGL(k_min_seed_source<int32_t>, dim3(1), dim3(64), 0, s, (const int32_t*)off, source, fq, P,
+                       active);
+  return hipGetLastError();
+}
+
+namespace {
+template <class OffT, int KIND, bool LIST, bool TBA>
+void vertex_launch(const void* off, const int32_t* dst, const uint32_t* w, int64_t items, const int32_t* fq,
+                   uint2* vm, uint32_t* bitmap, hipStream_t s) {
+  hipLaunchKernelGGL((k_min_scatter_vertex<OffT, KIND, LIST, TBA>), dim3(grid_for(items)), dim3(kWG), 0, s,
+                     (const OffT*)off, dst, w, items, fq, vm, bitmap);
+}
+
+template <class OffT, int KIND, bool LIST, bool TBA>
+void mp_launch(const void* off, const int32_t* dst, const uint32_t* w, int64_t items, int64_t total,
+               const int64_t* P, const int32_t* fq, const int32_t* tile_v, int64_t tile, int64_t ntiles, uint2* vm,
+               uint32_t* bitmap, hipStream_t s) {
+  const size_t lds = min_mp_lds_bytes(tile, LIST);
+  if (LIST)
+    hipLaunchKernelGGL((k_min_scatter_mp<int64_t, OffT, KIND, LIST, TBA>), dim3((unsigned)ntiles), dim3(kWG), lds,
+                       s, (const OffT*)off, dst, w, items, total, P, fq, tile_v, tile, vm, bitmap);
+  else  // dense: the prefix is the CSR offsets themselves
+    hipLaunchKernelGGL((k_min_scatter_mp<OffT, OffT, KIND, LIST, TBA>), dim3((unsigned)ntiles), dim3(kWG), lds, s,
+                       (const OffT*)off, dst, w, items, total, (const OffT*)off, fq, tile_v, tile, vm, bitmap);
+}
+
+template <class OffT, int KIND>
+void vertex_dispatch(bool list, bool tba, const void* off, const int32_t* dst, const uint32_t* w, int64_t items,
+                     const int32_t* fq, uint2* vm, uint32_t* bitmap, hipStream_t s) {
+  if (list) {
+    if (tba)
+      vertex_launch<OffT, KIND, true, true>(off, dst, w, items, fq, vm, bitmap, s);
+    else
+      vertex_launch<OffT, KIND, true, false>(off, dst, w, items, fq, vm, bitmap, s);
+  } else {
+    if (tba)
+      vertex_launch<OffT, KIND, false, true>(off, dst, w, items, fq, vm, bitmap, s);
+    else
+      vertex_launch<OffT, KIND, false, false>(off, dst, w, items, fq, vm, bitmap, s);
+  }
+}
+
+template <class OffT, int KIND>
+void mp_dispatch(bool list, bool tba, const void* off, const int32_t* dst, const uint32_t* w, int64_t items,
+                 int64_t total, const int64_t* P, const int32_t* fq, const int32_t* tile_v, int64_t tile,
+                 int64_t ntiles, uint2* vm, uint32_t* bitmap, hipStream_t s) {
+  if (list) {
+    if (tba)
+      mp_launch<OffT, KIND, true, true>(off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap, s);
+    else
+      mp_launch<OffT, KIND, true, false>(off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap, s);
+  } else {
+    if (tba)
+      mp_launch<OffT, KIND, false, true>(off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap, s);
+    else
+      mp_launch<OffT, KIND, false, false>(off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap, s);
+  }
+}
+}  // namespace
+
+hipError_t launch_min_scatter_vertex(int kind, bool list, bool tba, const void* off, bool off64, const int32_t* dst,
+                                     const uint32_t* w, int64_t items, const int32_t* fq, uint2* vm, uint32_t* bitmap,
+                                     hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  if (off64) {
+    if (kind == kCC) vertex_dispatch<int64_t, kCC>(list, tba, off, dst, w, items, fq, vm, bitmap, s);
+    else if (kind == kSsspUnit) vertex_dispatch<int64_t, kSsspUnit>(list, tba, off, dst, w, items, fq, vm, bitmap, s);
+    else vertex_dispatch<int64_t, kSsspWeighted>(list, tba, off, dst, w, items, fq, vm, bitmap, s);
+  } else {
+    if (kind == kCC) vertex_dispatch<int32_t, kCC>(list, tba, off, dst, w, items, fq, vm, bitmap, s);
+    else if (kind == kSsspUnit) vertex_dispatch<int32_t, kSsspUnit>(list, tba, off, dst, w, items, fq, vm, bitmap, s);
+    else vertex_dispatch<int32_t, kSsspWeighted>(list, tba, off, dst, w, items, fq, vm, bitmap, s);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_min_scatter_mp(int kind, bool list, bool tba, const void* off, bool off64, const int32_t* dst,
+                                 const uint32_t* w, int64_t items, int64_t total, const int64_t* P, const int32_t* fq,
+                                 const int32_t* tile_v, int64_t tile, int64_t ntiles, uint2* vm, uint32_t* bitmap,
+                                 hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (off64) {
+    if (kind == kCC)
+      mp_dispatch<int64_t, kCC>(list, tba, off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap, s);
+    else if (kind == kSsspUnit)
+      mp_dispatch<int64_t, kSsspUnit>(list, tba, off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap,
+                                      s);
+    else
+      mp_dispatch<int64_t, kSsspWeighted>(list, tba, off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm,
+                                          bitmap, s);
+  } else {
+    if (kind == kCC)
+      mp_dispatch<int32_t, kCC>(list, tba, off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap, s);
+    else if (kind == kSsspUnit)
+      mp_dispatch<int32_t, kSsspUnit>(list, tba, off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap,
+                                      s);
+    else
+      mp_dispatch<int32_t, kSsspWeighted>(list, tba, off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm,
+                                          bitmap, s);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_min_compact(const void* off, bool off64, int64_t n, uint2* vm, const uint32_t* bitmap,
+                              uint32_t* stale, int32_t* fq, int64_t* P, Counters* ctr, hipStream_t s) {
+  const int64_t nwords = (n + 31) / 32;
+  if (off64)
+    hipLaunchKernelGGL(k_min_compact<int64_t>, dim3(grid_for(nwords)), dim3(kWG), 0, s, (const int64_t*)off, n, vm,
+                       bitmap, stale, nwords, fq, P, ctr);
+  else
+    hipLaunchKernelGGL(k_min_compact<int32_t>, dim3(grid_for(nwords)), dim3(kWG), 0, s, (const int32_t*)off, n, vm,
+                       bitmap, stale, nwords, fq, P, ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_min_output(int64_t n, const uint2* vm, uint32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_min_output, dim3(grid_for(n)), dim3(kWG), 0, s, n, vm, out);
+  return hipGetLastError();
+}
+
+int64_t scan_scratch_entries(int64_t count) { return (count + kScanItems - 1) / kScanItems + 1; }
+
+hipError_t launch_exclusive_scan(int64_t* P, int64_t count, int64_t* blocks, hipStream_t s) {
+  const int64_t nb = (count + kScanItems - 1) / kScanItems;
+  if (nb > 0) hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kWG), 0, s, P, count, blocks);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, blocks, nb, P, count);
+  if (nb > 0) hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kWG), 0, s, P, count, blocks);
+  return hipGetLastError();
+}
+
+}  // namespace vc

@@ -1,0 +1,347 @@
+// Pull (receiver-side) form of the superstep and the transpose it reads.
+//
+// In the pull form every vertex writes one outbox message (its contribution
+// or its value) and receivers iterate over their in-edges, fetch the outbox
+// messages of the in-neighbours that broadcast, and combine them (paper,
+// Section VI-C: the "single-broadcast" versions used for PageRank and CC;
+// Section IV: the per-neighbour flag + message read).  Because the combine
+// happens in registers and LDS of the workgroup that owns the receiver, no
+// per-message global atomic is issued; only receivers whose in-edges span two
+// merge-path tiles are combined across workgroups (at most two per tile).
+//
+// Work distribution: merge-path tiles over the merged (in-edge, vertex-end)
+// sequence of the CSC, so every workgroup gets the same number of items.  In
+// a tile each thread walks a contiguous run of in-edges, keeps a running
+// combination while the receiver stays the same, and flushes it to the LDS
+// slot of that receiver when the receiver changes.
+#include "vc_device.h"
+
+namespace vc {
+namespace {
+
+using namespace dev;
+
+// --------------------------------------------------------------- transpose
+
+__global__ __launch_bounds__(kWG) void k_widen(const int32_t* __restrict__ a, int64_t count, int64_t* __restrict__ b) {
+  const int64_t i = gid();
+  if (i < count) b[i] = a[i];
+}
+
+// in-degree histogram: cnt[d] += 1 for every edge (cnt has n + 1 zeroed entries)
+__global__ __launch_bounds__(kWG) void k_csc_count(const int32_t* __restrict__ dst, int64_t m,
+                                                   unsigned long long* __restrict__ cnt) {
+  for (int64_t e = gid(); e < m; e += (int64_t)gridDim.x * kWG) atomicAdd(&cnt[dst[e]], 1ull);
+}
+
+// Places every edge u->v at cursor[v]++ in the CSC.  Workgroups own merge-path
+// tiles of the CSR so hubs are split; the source of an edge is found by a
+// binary search over the tile's offsets staged in LDS.
+template <class OffT>
+__global__ __launch_bounds__(kWG) void k_csc_fill(const OffT* __restrict__ off, const int32_t* __restrict__ dst,
+                                                  const uint32_t* __restrict__ w, int64_t n, int64_t m,
+                                                  const int32_t* __restrict__ tile_v, int64_t tile,
+                                                  unsigned long long* __restrict__ cursor,
+                                                  int32_t* __restrict__ in_src, uint32_t* __restrict__ in_w) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t t = blockIdx.x;
+  const int64_t k0 = t * tile;
+  const int64_t k1 = (k0 + tile < n + m) ? k0 + tile : n + m;
+  const int64_t i0 = tile_v[t], i1 = tile_v[t + 1];
+  const int64_t j0 = k0 - i0, j1 = k1 - i1;
+  if (j1 <= j0) return;
+  const int64_t ilast = i1 < n ? i1 : n - 1;
+  const int cnt = (int)(ilast - i0 + 1);
+  int64_t* s_off = reinterpret_cast<int64_t*>(smem);
+  for (int x = threadIdx.x; x <= cnt; x += kWG) s_off[x] = (int64_t)off[i0 + x];
+  __syncthreads();
+  for (int64_t e = j0 + threadIdx.x; e < j1; e += kWG) {
+    int lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_off[mid] <= e)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const int32_t v = dst[e];
+    const unsigned long long p = atomicAdd(&cursor[v], 1ull);
+    in_src[p] = (int32_t)(i0 + lo);
+    if (w) in_w[p] = w[e];
+  }
+}
+
+// --------------------------------------------------------------- tile set-up
+struct Tile {
+  int64_t i0, j0, j1;
+  int cnt;
+};
+
+__device__ __forceinline__ bool tile_bounds(const int32_t* __restrict__ tile_v, int64_t tile, int64_t items,
+                                            int64_t edges, Tile* tl) {
+  const int64_t t = blockIdx.x;
+  const int64_t k0 = t * tile;
+  const int64_t k1 = (k0 + tile < items + edges) ? k0 + tile : items + edges;
+  const int64_t i0 = tile_v[t], i1 = tile_v[t + 1];
+  tl->i0 = i0;
+  tl->j0 = k0 - i0;
+  tl->j1 = k1 - i1;
+  const int64_t ilast = i1 < items ? i1 : items - 1;
+  tl->cnt = (int)(ilast - i0 + 1);
+  return tl->j1 > tl->j0;
+}
+
+// Owner (local receiver index) of in-edge e: last x with s_off[x] <= e.
+__device__ __forceinline__ int owner_of(const int64_t* __restrict__ s_off, int cnt, int64_t e) {
+  int lo = 0, hi = cnt - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_off[mid] <= e)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// --------------------------------------------------------------- PageRank pull
+
+template <class V>
+__device__ __forceinline__ void lds_add(V* p, V x);
+template <>
+__device__ __forceinline__ void lds_add<float>(float* p, float x) {
+  atomicAdd(p, x);
+}
+template <>
+__device__ __forceinline__ void lds_add<unsigned long long>(unsigned long long* p, unsigned long long x) {
+  atomicAdd(p, x);
+}
+template <class V>
+__device__ __forceinline__ void global_add(V* p, V x);
+template <>
+__device__ __forceinline__ void global_add<float>(float* p, float x) {
+  unsafeAtomicAdd(p, x);
+}
+template <>
+__device__ __forceinline__ void global_add<unsigned long long>(unsigned long long* p, unsigned long long x) {
+  atomicAdd(p, x);
+}
+
+// mb[v] = sum of contrib[u] over in-edges u->v.  mb must be zero on entry for
+// receivers whose in-edges cross a tile boundary (the update step leaves
+// every mailbox at zero).
+template <class V>
+__global__ __launch_bounds__(kWG) void k_pr_pull(const int64_t* __restrict__ in_off, const int32_t* __restrict__ in_src,
+                                                 int64_t n, int64_t m, const int32_t* __restrict__ tile_v,
+                                                 int64_t tile, const V* __restrict__ contrib, V* __restrict__ mb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Tile tl;
+  if (!tile_bounds(tile_v, tile, n, m, &tl)) return;
+  V* s_acc = reinterpret_cast<V*>(smem);                                              // tile + 1
+  int64_t* s_off = reinterpret_cast<int64_t*>(smem + align16((tile + 1) * sizeof(V)));  // tile + 2
+  for (int x = threadIdx.x; x <= tl.cnt; x += kWG) s_off[x] = in_off[tl.i0 + x];
+  for (int x = threadIdx.x; x < tl.cnt; x += kWG) s_acc[x] = V(0);
+  __syncthreads();
+  // each thread: a contiguous run of in-edges
+  const int64_t ne = tl.j1 - tl.j0;
+  const int64_t per = (ne + kWG - 1) / kWG;
+  int64_t e = tl.j0 + (int64_t)threadIdx.x * per;
+  const int64_t e_end = e + per < tl.j1 ? e + per : tl.j1;
+  if (e < e_end) {
+    int x = owner_of(s_off, tl.cnt, e);
+    int64_t next = s_off[x + 1];
+    V run = V(0);
+    for (; e < e_end; ++e) {
+      while (e >= next) {  // receiver changes: flush the running sum
+        if (run != V(0)) lds_add<V>(&s_acc[x], run);
+        run = V(0);
+        ++x;
+        next = s_off[x + 1];
+      }
+      run += contrib[in_src[e]];
+    }
+    if (run != V(0)) lds_add<V>(&s_acc[x], run);
+  }
+  __syncthreads();
+  for (int x = threadIdx.x; x < tl.cnt; x += kWG) {
+    const V a = s_acc[x];
+    if (a == V(0)) continue;
+    const int64_t v = tl.i0 + x;
+    if (s_off[x] >= tl.j0 && s_off[x + 1] <= tl.j1)
+      mb[v] = a;  // every in-edge of v is in this tile
+    else
+      global_add<V>(&mb[v], a);
+  }
+}
+
+// --------------------------------------------------------------- CC / SSSP pull
+
+template <int KIND>
+__device__ __forceinline__ uint32_t pull_message(uint32_t val, const uint32_t* __restrict__ in_w, int64_t e) {
+  if (KIND == kCC) return val;
+  if (KIND == kSsspUnit) return sat_add(val, 1u);
+  return sat_add(val, in_w[e]);
+}
+
+__device__ __forceinline__ bool bit_set(const uint32_t* __restrict__ bits, int64_t u) {
+  return (bits[u >> 5] >> (u & 31)) & 1u;
+}
+
+// For every receiver v: best = min over in-edges u->v with u active of
+// value(u) (+ w).  When best lowers value(v), the mailbox of v takes it and
+// v is marked in `improved` (the same outcome as the push form, so the
+// compaction step is shared).  `active` = NULL means every vertex broadcast.
+template <int KIND, bool CHECK>
+__global__ __launch_bounds__(kWG) void k_min_pull(const int64_t* __restrict__ in_off,
+                                                  const int32_t* __restrict__ in_src,
+                                                  const uint32_t* __restrict__ in_w, int64_t n, int64_t m,
+                                                  const int32_t* __restrict__ tile_v, int64_t tile,
+                                                  uint2* __restrict__ vm, const uint32_t* __restrict__ active,
+                                                  uint32_t* __restrict__ improved) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Tile tl;
+  const bool has_edges = tile_bounds(tile_v, tile, n, m, &tl);
+  if (!has_edges) return;
+  uint32_t* s_min = reinterpret_cast<uint32_t*>(smem);                                      // tile + 1
+  int64_t* s_off = reinterpret_cast<int64_t*>(smem + align16((tile + 1) * 4));  // tile + 2
+  for (int x = threadIdx.x; x <= tl.cnt; x += kWG) s_off[x] = in_off[tl.i0 + x];
+  for (int x = threadIdx.x; x < tl.cnt; x += kWG) s_min[x] = kInf;
+  __syncthreads();
+  const uint32_t* val = reinterpret_cast<const uint32_t*>(vm);  // value of u at val[2u]
+  const int64_t ne = tl.j1 - tl.j0;
+  const int64_t per = (ne + kWG - 1) / kWG;
+  int64_t e = tl.j0 + (int64_t)threadIdx.x * per;
+  const int64_t e_end = e + per < tl.j1 ? e + per : tl.j1;
+  if (e < e_end) {
+    int x = owner_of(s_off, tl.cnt, e);
+    int64_t next = s_off[x + 1];
+    uint32_t run = kInf;
+    for (; e < e_end; ++e) {
+      while (e >= next) {
+        if (run != kInf) atomicMin(&s_min[x], run);
+        run = kInf;
+        ++x;
+        next = s_off[x + 1];
+      }
+      const int32_t u = in_src[e];
+      if (!CHECK || bit_set(active, u)) {
+        const uint32_t msg = pull_message<KIND>(val[2 * (int64_t)u], in_w, e);
+        run = msg < run ? msg : run;
+      }
+    }
+    if (run != kInf) atomicMin(&s_min[x], run);
+  }
+  __syncthreads();
+  // per receiver: complete ones are owned by this tile; boundary ones are
+  // combined with an atomic min.  Improvement bits are OR-ed per word from a
+  // wave ballot (lanes hold consecutive receivers).
+  for (int base = 0; base < tl.cnt; base += kWG) {
+    const int x = base + (int)threadIdx.x;
+    bool imp = false;
+    int64_t v = tl.i0 + x;
+    if (x < tl.cnt) {
+      const uint32_t best = s_min[x];
+      if (best != kInf) {
+        const uint2 cur = vm[v];
+        if (best < cur.x) {
+          if (s_off[x] >= tl.j0 && s_off[x + 1] <= tl.j1) {
+            vm[v].y = best;
+            imp = true;
+          } else if (best < cur.y) {
+            const uint32_t old = atomicMin(&reinterpret_cast<uint32_t*>(vm)[2 * v + 1], best);
+            imp = old == kInf;
+          }
+        }
+      }
+    }
+    const unsigned long long mask = __ballot(imp);
+    const int lane = (int)lane_id();
+    const int64_t v_lane = tl.i0 + base + (threadIdx.x & ~63u) + lane;  // receiver of this lane
+    const bool leader = lane == 0 || (v_lane & 31) == 0;
+    if (leader && mask) {
+      const int len = (int)(32 - (v_lane & 31)) < 64 - lane ? (int)(32 - (v_lane & 31)) : 64 - lane;
+      const unsigned long long seg = len >= 64 ? ~0ull : ((1ull << len) - 1ull);
+      const uint32_t bits = (uint32_t)(((mask >> lane) & seg) << (v_lane & 31));
+      if (bits) atomicOr(&improved[v_lane >> 5], bits);
+    }
+  }
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- launchers
+
+size_t pull_lds_bytes(int64_t tile) { return align16((size_t)(tile + 1) * 8) + (size_t)(tile + 2) * 8; }
+
+hipError_t launch_widen_offsets(const int32_t* a, int64_t count, int64_t* b, hipStream_t s) {
+  hipLaunchKernelGGL(k_widen, dim3(grid_for(count)), dim3(kWG), 0, s, a, count, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_csc_count(const int32_t* dst, int64_t m, unsigned long long* cnt, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const int64_t blocks = (m + kWG - 1) / kWG;
+  hipLaunchKernelGGL(k_csc_count, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(kWG), 0, s, dst, m, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_csc_fill(const void* off, bool off64, const int32_t* dst, const uint32_t* w, int64_t n, int64_t m,
+                           const int32_t* tile_v, int64_t tile, int64_t ntiles, unsigned long long* cursor,
+                           int32_t* in_src, uint32_t* in_w, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  const size_t lds = (size_t)(tile + 2) * 8;
+  if (off64)
+    hipLaunchKernelGGL(k_csc_fill<int64_t>, dim3((unsigned)ntiles), dim3(kWG), lds, s, (const int64_t*)off, dst, w, n,
+                       m, tile_v, tile, cursor, in_src, in_w);
+  else
+    hipLaunchKernelGGL(k_csc_fill<int32_t>, dim3((unsigned)ntiles), dim3(kWG), lds, s, (const int32_t*)off, dst, w, n,
+                       m, tile_v, tile, cursor, in_src, in_w);
+  return hipGetLastError();
+}
+
+hipError_t launch_pr_pull(bool fx, const int64_t* in_off, const int32_t* in_src, int64_t n, int64_t m,
+                          const int32_t* tile_v, int64_t tile, int64_t ntiles, const void* contrib, void* mb,
+                          hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (fx) {
+    const size_t lds = align16((size_t)(tile + 1) * 8) + (size_t)(tile + 2) * 8;
+    hipLaunchKernelGGL(k_pr_pull<unsigned long long>, dim3((unsigned)ntiles), dim3(kWG), lds, s, in_off, in_src, n, m,
+                       tile_v, tile, (const unsigned long long*)contrib, (unsigned long long*)mb);
+  } else {
+    const size_t lds = align16((size_t)(tile + 1) * 4) + (size_t)(tile + 2) * 8;
+    hipLaunchKernelGGL(k_pr_pull<float>, dim3((unsigned)ntiles), dim3(kWG), lds, s, in_off, in_src, n, m, tile_v,
+                       tile, (const float*)contrib, (float*)mb);
+  }
+  return hipGetLastError();
+}
+
+namespace {
+template <int KIND>
+void min_pull_launch(bool check, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w, int64_t n,
+                     int64_t m, const int32_t* tile_v, int64_t tile, int64_t ntiles, uint2* vm,
+                     const uint32_t* active, uint32_t* improved, hipStream_t s) {
+  const size_t lds = align16((size_t)(tile + 1) * 4) + (size_t)(tile + 2) * 8;
+  if (check)
+    hipLaunchKernelGGL((k_min_pull<KIND, true>), dim3((unsigned)ntiles), dim3(kWG), lds, s, in_off, in_src, in_w, n,
+                       m, tile_v, tile, vm, active, improved);
+  else
+    hipLaunchKernelGGL((k_min_pull<KIND, false>), dim3((unsigned)ntiles), dim3(kWG), lds, s, in_off, in_src, in_w, n,
+                       m, tile_v, tile, vm, active, improved);
+}
+}  // namespace
+
+hipError_t launch_min_pull(int kind, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w, int64_t n,
+                           int64_t m, const int32_t* tile_v, int64_t tile, int64_t ntiles, uint2* vm,
+                           const uint32_t* active, uint32_t* improved, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  const bool check = active != nullptr;
+  if (kind == kCC)
+    min_pull_launch<kCC>(check, in_off, in_src, in_w, n, m, tile_v, tile, ntiles, vm, active, improved, s);
+  else if (kind == kSsspUnit)
+    min_pull_launch<kSsspUnit>(check, in_off, in_src, in_w, n, m, tile_v, tile, ntiles, vm, active, improved, s);
+  else
+    min_pull_launch<kSsspWeighted>(check, in_off, in_src, in_w, n, m, tile_v, tile, ntiles, vm, active, improved, s);
+  return hipGetLastError();
+}
+
+}  // namespace vc

@@ -1,0 +1,248 @@
+"""ctypes binding of libvc (include/vc.h): argument marshalling only.
+
+Every step of a run executes in libvc's HIP kernels; PyTorch supplies device
+memory and streams.  There is no CPU fallback: if the library cannot be
+loaded, importing the binding's entry points raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libvc.so")
+
+PAGERANK, CC_HASHMIN, SSSP, PPR = 0, 1, 2, 3
+PROGRAMS = {"pagerank": PAGERANK, "pr": PAGERANK, "cc": CC_HASHMIN, "cc_hashmin": CC_HASHMIN, "sssp": SSSP,
+            "ppr": PPR}
+SCHED_AUTO, SCHED_VERTEX, SCHED_EDGE, SCHED_PULL = 0, 1, 2, 3
+SCHEDULES = {"auto": SCHED_AUTO, "vertex": SCHED_VERTEX, "edge": SCHED_EDGE, "pull": SCHED_PULL}
+IDX_I32, IDX_I64 = 0, 1
+GRAPH_BORROW, GRAPH_VALIDATE, GRAPH_SYMMETRIC = 1, 2, 4
+OPT_NO_HUB_AGGREGATION, OPT_NO_TEST_BEFORE_ATOMIC, OPT_F32_ACCUMULATE = 1, 2, 4
+UNREACHED = 0xFFFFFFFF
+
+OK, ERR_INVALID_ARG, ERR_BAD_GRAPH, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_UNSUPPORTED, ERR_NOT_CONVERGED = range(7)
+ABI_VERSION = 1
+EXPORTS = ("vc_graph_create", "vc_graph_destroy", "vc_graph_footprint", "vc_run", "vc_params_default",
+           "vc_status_string", "vc_last_error", "vc_abi_version")
+
+
+class GraphDesc(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("num_vertices", ctypes.c_int64),
+                ("num_edges", ctypes.c_int64), ("offset_type", ctypes.c_int), ("offsets", ctypes.c_void_p),
+                ("dst", ctypes.c_void_p), ("weights", ctypes.c_void_p)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("max_supersteps", ctypes.c_int32), ("damping", ctypes.c_double),
+                ("source", ctypes.c_uint32), ("schedule", ctypes.c_int), ("tile", ctypes.c_int32),
+                ("options", ctypes.c_uint32)]
+
+
+class StatsStruct(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("supersteps", ctypes.c_int32),
+                ("edges_relaxed", ctypes.c_int64), ("elapsed_ms", ctypes.c_double), ("capacity", ctypes.c_int32),
+                ("frontier", ctypes.c_void_p), ("edges", ctypes.c_void_p), ("scatter_ms", ctypes.c_void_p),
+                ("step_ms", ctypes.c_void_p), ("schedule", ctypes.c_void_p)]
+
+
+class VcError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status}: {detail}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libvc.so, building it first only when no build exists."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        from . import build as _build
+        _build.build()
+    lib = ctypes.CDLL(path)
+    vp, i32 = ctypes.c_void_p, ctypes.c_int
+    lib.vc_graph_create.restype = i32
+    lib.vc_graph_create.argtypes = [ctypes.POINTER(GraphDesc), vp, ctypes.POINTER(vp)]
+    lib.vc_graph_destroy.restype = i32
+    lib.vc_graph_destroy.argtypes = [vp]
+    lib.vc_graph_footprint.restype = i32
+    lib.vc_graph_footprint.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+    lib.vc_run.restype = i32
+    lib.vc_run.argtypes = [vp, i32, ctypes.POINTER(Params), vp, vp, ctypes.POINTER(StatsStruct)]
+    lib.vc_params_default.restype = None
+    lib.vc_params_default.argtypes = [ctypes.POINTER(Params)]
+    lib.vc_status_string.restype = ctypes.c_char_p
+    lib.vc_status_string.argtypes = [i32]
+    lib.vc_last_error.restype = ctypes.c_char_p
+    lib.vc_last_error.argtypes = []
+    lib.vc_abi_version.restype = i32
+    if lib.vc_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"{path}: ABI version {lib.vc_abi_version()} != {ABI_VERSION}; rebuild the library")
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        lib = load()
+        raise VcError(status, where, lib.vc_last_error().decode() or lib.vc_status_string(status).decode())
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _program(p) -> int:
+    return PROGRAMS[p.lower()] if isinstance(p, str) else int(p)
+
+
+@dataclass
+class Stats:
+    supersteps: int
+    edges_relaxed: int
+    elapsed_ms: float
+    frontier: np.ndarray
+    edges: np.ndarray
+    scatter_ms: Optional[np.ndarray] = None
+    step_ms: Optional[np.ndarray] = None
+    schedule: Optional[np.ndarray] = None
+    extra: dict = field(default_factory=dict)
+
+
+class Graph:
+    """A CSR graph resident on the current GPU (vc_graph_create).
+
+    offsets: int32 / int64 tensor of N+1 entries, dst: int32 tensor of M
+    entries, weights: optional int32 / uint32 tensor of M entries (read as
+    uint32); all on the current CUDA (HIP) device and contiguous.  With
+    borrow=True the tensors are kept referenced by this object and must not be
+    modified while it lives.
+    """
+
+    def __init__(self, offsets, dst, weights=None, *, borrow: bool = True, validate: bool = False,
+                 symmetric: bool = False, stream=None):
+        import torch
+        lib = load()
+        for name, t in (("offsets", offsets), ("dst", dst), ("weights", weights)):
+            if t is None:
+                continue
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+                raise TypeError(f"{name} must be a contiguous CUDA tensor")
+        if offsets.dtype not in (torch.int32, torch.int64):
+            raise TypeError("offsets must be int32 or int64")
+        if dst.dtype != torch.int32:
+            raise TypeError("dst must be int32")
+        if weights is not None and weights.dtype not in (torch.int32, getattr(torch, "uint32", torch.int32)):
+            raise TypeError("weights must be int32 or uint32")
+        n = offsets.numel() - 1
+        m = dst.numel()
+        if weights is not None and weights.numel() != m:
+            raise ValueError("weights and dst differ in length")
+        desc = GraphDesc(ctypes.sizeof(GraphDesc),
+                         (GRAPH_BORROW if borrow else 0) | (GRAPH_VALIDATE if validate else 0) |
+                         (GRAPH_SYMMETRIC if symmetric else 0),
+                         n, m, IDX_I64 if offsets.dtype == torch.int64 else IDX_I32, offsets.data_ptr(),
+                         dst.data_ptr() if m else None, weights.data_ptr() if weights is not None and m else None)
+        handle = ctypes.c_void_p()
+        _check(lib.vc_graph_create(ctypes.byref(desc), _stream_handle(stream), ctypes.byref(handle)),
+               "vc_graph_create")
+        self._h = handle
+        self._keep = (offsets, dst, weights) if borrow else None
+        self.n, self.m = n, m
+        self.weighted = weights is not None
+        self.device = offsets.device
+
+    @classmethod
+    def from_csr(cls, csr, device=None, **kw) -> "Graph":
+        """Uploads an rmatgen.Csr (host arrays) and creates the graph (borrowed)."""
+        import torch
+        device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        off = torch.from_numpy(np.ascontiguousarray(csr.off)).to(device)
+        dst = torch.from_numpy(np.ascontiguousarray(csr.dst)).to(device)
+        w = None
+        if csr.w is not None:
+            w = torch.from_numpy(np.ascontiguousarray(csr.w).view(np.int32)).to(device)
+        torch.cuda.synchronize(device)
+        return cls(off, dst, w, borrow=True, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().vc_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def footprint(self, program="sssp"):
+        held, run = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(load().vc_graph_footprint(self._h, _program(program), ctypes.byref(held), ctypes.byref(run)),
+               "vc_graph_footprint")
+        return held.value, run.value
+
+    def run(self, program, out=None, *, T: int = 10, damping: float = 0.85, source: int = 0,
+            max_supersteps: int = 0, schedule="auto", tile: int = 0, options: int = 0, stream=None,
+            stats: bool = False, timing: bool = False, capacity: int = 4096):
+        """vc_run: returns (out, Stats | None).  out: float32 ranks or int32-stored uint32 labels."""
+        import torch
+        lib = load()
+        prog = _program(program)
+        rank = prog in (PAGERANK, PPR)
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float32 if rank else torch.int32, device=self.device)
+        if not out.is_cuda or not out.is_contiguous() or out.numel() != self.n or out.element_size() != 4:
+            raise TypeError("out must be a contiguous CUDA tensor of N 4-byte elements")
+        p = Params()
+        lib.vc_params_default(ctypes.byref(p))
+        p.max_supersteps = int(T) if rank else int(max_supersteps)
+        p.damping = float(damping)
+        p.source = int(source)
+        p.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
+        p.tile = int(tile)
+        p.options = int(options)
+        st = None
+        arrays = {}
+        if stats or timing:
+            cap = int(capacity)
+            arrays = {"frontier": np.zeros(cap, np.int64), "edges": np.zeros(cap, np.int64),
+                      "schedule": np.zeros(cap, np.int32)}
+            if timing:
+                arrays["scatter_ms"] = np.zeros(cap, np.float32)
+                arrays["step_ms"] = np.zeros(cap, np.float32)
+            st = StatsStruct(ctypes.sizeof(StatsStruct), 0, 0, 0.0, cap,
+                             arrays["frontier"].ctypes.data, arrays["edges"].ctypes.data,
+                             arrays["scatter_ms"].ctypes.data if timing else None,
+                             arrays["step_ms"].ctypes.data if timing else None,
+                             arrays["schedule"].ctypes.data)
+        rc = lib.vc_run(self._h, prog, ctypes.byref(p), out.data_ptr(), _stream_handle(stream),
+                        ctypes.byref(st) if st is not None else None)
+        _check(rc, "vc_run")
+        if st is None:
+            return out, None
+        k = min(st.supersteps, int(capacity))
+        res = Stats(st.supersteps, st.edges_relaxed, st.elapsed_ms, arrays["frontier"][:k].copy(),
+                    arrays["edges"][:k].copy(),
+                    arrays["scatter_ms"][:k].copy() if timing else None,
+                    arrays["step_ms"][:k].copy() if timing else None, arrays["schedule"][:k].copy())
+        return out, res

@@ -1,0 +1,88 @@
+"""The C ABI library on the CPU: it loads, exports every declared symbol, and
+rejects bad arguments before touching the device (no compute calls)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2010_01542_amd import vc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(vc_[a-z_]+)\s*\(", text,
+                                 flags=re.M)))
+
+
+def test_header_declares_the_binding_exports():
+    assert sorted(vc.EXPORTS) == declared_functions()
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(vc.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_abi_version_and_status_strings():
+    lib = vc.load()
+    assert lib.vc_abi_version() == vc.ABI_VERSION
+    for s in range(7):
+        assert lib.vc_status_string(s)
+    assert lib.vc_status_string(99) == b"unknown status"
+
+
+def test_params_default():
+    lib = vc.load()
+    p = vc.Params()
+    lib.vc_params_default(ctypes.byref(p))
+    assert p.struct_size == ctypes.sizeof(vc.Params)
+    assert p.max_supersteps == 10 and p.damping == pytest.approx(0.85) and p.schedule == vc.SCHED_AUTO
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """sizeof / offsetof of every ABI struct field, from the C compiler, equal ctypes'."""
+    structs = {"vc_graph_desc": vc.GraphDesc, "vc_params": vc.Params, "vc_stats": vc.StatsStruct}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "vc.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"), "-I",
+                           "/opt/rocm/include", "-o", str(exe), str(src)])
+    got = dict(line.rsplit(" ", 1) for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, cls in structs.items():
+        assert int(got[f"{cname} sizeof"]) == ctypes.sizeof(cls)
+        for fname, _ in cls._fields_:
+            assert int(got[f"{cname} {fname}"]) == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_argument_errors_need_no_device():
+    lib = vc.load()
+    h = ctypes.c_void_p()
+    assert lib.vc_graph_create(None, None, ctypes.byref(h)) == vc.ERR_INVALID_ARG
+    d = vc.GraphDesc(ctypes.sizeof(vc.GraphDesc) + 1, 0, 4, 0, vc.IDX_I32, 8, 8, None)
+    assert lib.vc_graph_create(ctypes.byref(d), None, ctypes.byref(h)) == vc.ERR_INVALID_ARG
+    assert b"struct_size" in lib.vc_last_error()
+    d = vc.GraphDesc(ctypes.sizeof(vc.GraphDesc), 0, 0, 0, vc.IDX_I32, 8, 8, None)
+    assert lib.vc_graph_create(ctypes.byref(d), None, ctypes.byref(h)) == vc.ERR_INVALID_ARG
+    d = vc.GraphDesc(ctypes.sizeof(vc.GraphDesc), 0, 4, 2**31, vc.IDX_I32, 8, 8, None)
+    assert lib.vc_graph_create(ctypes.byref(d), None, ctypes.byref(h)) == vc.ERR_INVALID_ARG
+    assert b"int32 offsets" in lib.vc_last_error()
+    d = vc.GraphDesc(ctypes.sizeof(vc.GraphDesc), 0, 4, 3, vc.IDX_I64, 12, 8, None)
+    assert lib.vc_graph_create(ctypes.byref(d), None, ctypes.byref(h)) == vc.ERR_INVALID_ARG
+    assert b"misaligned" in lib.vc_last_error()
+    assert lib.vc_run(None, vc.SSSP, None, 16, None, None) == vc.ERR_INVALID_ARG
+    assert lib.vc_graph_destroy(None) == vc.OK
+    held = ctypes.c_size_t()
+    assert lib.vc_graph_footprint(None, 0, ctypes.byref(held), None) == vc.ERR_INVALID_ARG

@@ -1,0 +1,202 @@
+"""HIP path vs the CPU oracle on small and mid-size graphs (GPU).
+
+Sizes span several merge-path tiles with ragged tails; every program runs
+under both work distributions, int32 and int64 offsets, unit and uint32
+weights; edge cases include empty graphs, isolated vertices, sources without
+out-edges, hubs longer than a tile, multigraphs and self-loops.
+"""
+import numpy as np
+import pytest
+
+import rmatgen
+from gpu_util import check_min, check_rank, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+SCHEDS = ["vertex", "edge", "pull", "auto"]
+
+
+def make(csr, **kw):
+    from paper_2010_01542_amd import Graph
+    return Graph.from_csr(csr, **kw)
+
+
+def hand_graphs():
+    return {
+        "single": rmatgen.raw_csr(1, [], []),
+        "isolated100": rmatgen.raw_csr(100, [], []),
+        "path2": rmatgen.path(2),
+        "path60": rmatgen.path(60),
+        "cycle7": rmatgen.cycle(7),
+        "outstar5000": rmatgen.out_star(5000),
+        "instar5000": rmatgen.in_star(5000),
+        "bistar300": rmatgen.bi_star(300),
+        "cliques": rmatgen.cliques([3, 1, 40, 2], isolated=5),
+        "complete40": rmatgen.complete_digraph(40),
+        "multigraph": rmatgen.raw_csr(6, [0, 0, 0, 1, 1, 2, 3, 3, 5, 5], [1, 1, 0, 2, 2, 2, 0, 1, 5, 4],
+                                      [5, 2, 1, 9, 3, 7, 1, 1, 4, 250]),
+    }
+
+
+@pytest.fixture(scope="module")
+def hand(device):
+    gs = hand_graphs()
+    return {k: (c, make(c)) for k, c in gs.items()}
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+@pytest.mark.parametrize("name", sorted(hand_graphs()))
+def test_hand_graphs_all_programs(hand, name, sched):
+    csr, g = hand[name]
+    print(f"case hand/{name}/{sched}", flush=True)
+    sym = rmatgen.from_edges(csr.n, np.repeat(np.arange(csr.n), csr.outdeg), csr.dst, directed=False)
+    check_min(sym, make(sym), "cc", schedule=sched)
+    check_min(sym, make(sym, symmetric=True), "cc", schedule=sched)
+    for src in sorted({0, csr.n - 1}):
+        check_min(csr, g, "sssp", source=src, schedule=sched)
+    check_rank(csr, g, "pagerank", T=10, schedule=sched)
+    check_rank(csr, g, "ppr", T=7, source=0, schedule=sched)
+
+
+@pytest.mark.parametrize("tile", [64, 256, 2048, 8192])
+@pytest.mark.parametrize("off_dtype", [np.int32, np.int64])
+@pytest.mark.parametrize("seed", [1, 2])
+def test_rmat_tiles_offsets(device, tile, off_dtype, seed):
+    print(f"case rmat s12 tile={tile} off={np.dtype(off_dtype).name} seed={seed}", flush=True)
+    d = rmatgen.rmat(12, 16, seed=seed, weighted=True, offset_dtype=off_dtype)
+    u = rmatgen.rmat(12, 16, seed=seed, directed=False, offset_dtype=off_dtype)
+    gd, gu = make(d), make(u)
+    for sched in ("vertex", "edge", "pull"):
+        check_min(d, gd, "sssp", source=0, schedule=sched, tile=tile)
+        check_min(u, gu, "cc", schedule=sched, tile=tile)
+        check_rank(d, gd, "pagerank", T=10, schedule=sched, tile=tile)
+    check_min(u, make(u, symmetric=True), "cc", schedule="pull", tile=tile)
+
+
+@pytest.mark.parametrize("scale,ef", [(10, 4), (14, 8), (16, 16), (18, 16)])
+def test_rmat_sizes(device, scale, ef):
+    print(f"case rmat scale={scale} ef={ef}", flush=True)
+    d = rmatgen.rmat(scale, ef, seed=scale, weighted=True)
+    gd = make(d)
+    for src in (0, 3, d.n - 1):
+        check_min(d, gd, "sssp", source=src)
+    u = rmatgen.rmat(scale, ef, seed=scale + 50, directed=False, offset_dtype=np.int32)
+    check_min(u, make(u), "cc")
+    unit = rmatgen.Csr(d.n, d.m, d.off, d.dst, None)
+    check_min(unit, make(unit), "sssp", source=0)  # unit weights = BFS levels
+    check_rank(d, gd, "pagerank", T=20)
+    check_rank(d, gd, "ppr", T=20, source=1)
+
+
+def test_schedules_agree_exactly_on_min_programs(device):
+    u = rmatgen.rmat(15, 16, seed=77, directed=False)
+    g = make(u)
+    a, sa = run_gpu(g, "cc", schedule="vertex")
+    b, sb = run_gpu(g, "cc", schedule="edge", tile=512)
+    c, sc = run_gpu(g, "cc", schedule="pull", tile=1024)
+    assert np.array_equal(a, b) and sa.frontier.tolist() == sb.frontier.tolist()
+    assert np.array_equal(a, c) and sa.frontier.tolist() == sc.frontier.tolist()
+
+
+def test_test_before_atomic_is_a_pure_optimisation(device):
+    from paper_2010_01542_amd import vc
+    d = rmatgen.rmat(14, 16, seed=3, weighted=True)
+    g = make(d)
+    a, sa = run_gpu(g, "sssp", source=0)
+    b, sb = run_gpu(g, "sssp", source=0, options=vc.OPT_NO_TEST_BEFORE_ATOMIC)
+    assert np.array_equal(a, b) and sa.frontier.tolist() == sb.frontier.tolist()
+
+
+def test_repeated_runs_reuse_workspace(device):
+    d = rmatgen.rmat(13, 8, seed=5, weighted=True)
+    g = make(d)
+    first = run_gpu(g, "sssp", source=0)[0]
+    run_gpu(g, "pagerank", T=3)
+    run_gpu(g, "cc")
+    again = run_gpu(g, "sssp", source=0)[0]
+    assert np.array_equal(first, again)
+
+
+def test_copy_mode_and_validation(device):
+    import torch
+    from paper_2010_01542_amd import Graph, VcError
+    d = rmatgen.rmat(11, 8, seed=8, weighted=True)
+    off = torch.from_numpy(d.off).cuda()
+    dst = torch.from_numpy(d.dst).cuda()
+    w = torch.from_numpy(d.w.view(np.int32)).cuda()
+    g = Graph(off, dst, w, borrow=False, validate=True)
+    del off, dst, w
+    torch.cuda.synchronize()
+    check_min(d, g, "sssp", source=0)
+    bad = d.dst.copy()
+    bad[17] = d.n  # out of range
+    with pytest.raises(VcError):
+        Graph(torch.from_numpy(d.off).cuda(), torch.from_numpy(bad).cuda(), None, validate=True)
+    off_bad = d.off.copy()
+    off_bad[-1] -= 1
+    with pytest.raises(VcError):
+        Graph(torch.from_numpy(off_bad).cuda(), torch.from_numpy(d.dst).cuda(), None, validate=True)
+
+
+def test_argument_errors(device):
+    from paper_2010_01542_amd import VcError
+    g = make(rmatgen.path(4, directed=True))
+    with pytest.raises(VcError):
+        g.run("sssp", source=4)
+    with pytest.raises(VcError):
+        g.run("pagerank", T=-1)
+    with pytest.raises(VcError):
+        g.run("pagerank", damping=1.5)
+
+
+def test_superstep_cap(device):
+    from paper_2010_01542_amd import VcError, vc
+    g = make(rmatgen.path(50))
+    with pytest.raises(VcError) as e:
+        g.run("cc", max_supersteps=10)
+    assert e.value.status == vc.ERR_NOT_CONVERGED
+
+
+def test_timing_stats_are_recorded(device):
+    d = rmatgen.rmat(14, 16, seed=2, weighted=True)
+    g = make(d)
+    _, st = g.run("pagerank", T=5, timing=True)
+    assert st.scatter_ms.shape[0] == 6 and np.all(st.scatter_ms[:5] > 0) and np.all(st.step_ms[:5] >= st.scatter_ms[:5])
+    _, st = g.run("sssp", source=0, timing=True)
+    assert np.all(st.scatter_ms[: st.supersteps - 1] > 0)
+
+
+def test_fixed_point_pagerank_is_order_independent(device):
+    d = rmatgen.rmat(15, 16, seed=4)
+    g = make(d)
+    a = run_gpu(g, "pagerank", T=10, schedule="vertex")[0]
+    b = run_gpu(g, "pagerank", T=10, schedule="edge", tile=256)[0]
+    c = run_gpu(g, "pagerank", T=10, schedule="edge", tile=4096)[0]
+    d2 = run_gpu(g, "pagerank", T=10, schedule="pull", tile=512)[0]
+    assert np.array_equal(a, b) and np.array_equal(a, c) and np.array_equal(a, d2)
+
+
+@pytest.mark.parametrize("program", ["pagerank", "ppr"])
+def test_fixed_point_rank_within_one_ulp_of_oracle(device, program):
+    import oracle
+    d = rmatgen.rmat(14, 16, seed=6)
+    ref = oracle.run_csr(program, d, T=10, source=2).values
+    got = run_gpu(make(d), program, T=10, source=2)[0]
+    ulp = np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(got.astype(np.float64) - ref) <= ulp)
+
+
+@pytest.mark.parametrize("scale", [12, 16])
+def test_f32_accumulate_meets_tolerance_on_rmat(device, scale):
+    from paper_2010_01542_amd import vc
+    d = rmatgen.rmat(scale, 16, seed=scale)
+    g = make(d)
+    for sched in ("vertex", "edge", "pull"):
+        check_rank(d, g, "pagerank", T=10, schedule=sched, options=vc.OPT_F32_ACCUMULATE)
+
+
+def test_auto_schedule_mixes_push_and_pull(device):
+    d = rmatgen.rmat(16, 16, seed=21, weighted=True)
+    got, st, ref = check_min(d, make(d), "sssp", source=0, schedule="auto")
+    used = set(st.schedule.tolist())
+    assert 3 in used and (1 in used or 2 in used), used
