@@ -91,8 +91,13 @@ typedef enum { VC_IDX_I32 = 0, VC_IDX_I64 = 1 } vc_index_type;
 enum {
   VC_GRAPH_BORROW = 1u,    /* keep the caller's device arrays instead of copying them */
   VC_GRAPH_VALIDATE = 2u,  /* check the CSR on the device at creation */
-  VC_GRAPH_SYMMETRIC = 4u  /* caller asserts the graph equals its transpose, weights included
-                              (not checked); the pull form then reads the CSR itself */
+  VC_GRAPH_SYMMETRIC = 4u,  /* caller asserts the graph equals its transpose, weights included
+                               (not checked); the pull form then reads the CSR itself */
+  VC_GRAPH_NO_RELABEL = 8u  /* keep the input vertex order.  By default the library stores a
+                               copy of the graph with vertices ordered by degree class,
+                               highest first, so the most-accessed per-vertex data shares
+                               cache lines; ids in and out of the ABI are always the
+                               caller's */
 };
 
 /* vc_params.options */
@@ -165,7 +170,10 @@ typedef struct {
  *   out      host; receives the new handle.
  * Without VC_GRAPH_BORROW the arrays are copied into library-owned device
  * memory and may be freed by the caller on return; with it the caller keeps
- * them alive and unchanged until vc_graph_destroy.
+ * them alive and unchanged until vc_graph_destroy.  Unless
+ * VC_GRAPH_NO_RELABEL is set, the library builds its relabelled copy during
+ * this call and no longer reads the caller's arrays afterwards (BORROW then
+ * only avoids an intermediate copy).
  * Errors: VC_ERR_INVALID_ARG (null pointer, struct_size, N out of range,
  * int32 offsets with num_edges >= 2^31), VC_ERR_BAD_GRAPH (VALIDATE only),
  * VC_ERR_OUT_OF_MEMORY, VC_ERR_HIP.  On error *out is left unchanged. */

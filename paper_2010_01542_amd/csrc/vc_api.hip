@@ -74,6 +74,9 @@ struct vc_graph_s {
   const int32_t* dst = nullptr;
   const uint32_t* w = nullptr;
   DevBuf own_off, own_dst, own_w;  // copies when not borrowed
+  // relabelled copy (hot-first vertex order); perm[old] = new, inv[new] = old
+  bool relabeled = false;
+  DevBuf perm, inv, rel_off, rel_dst, rel_w;
   // workspace
   DevBuf contrib, mb;                             // PageRank / PPR
   DevBuf vm, bitmap, bitmap2, fq, prefix, scan_blocks;  // CC / SSSP (two bitmaps: improved / active)
@@ -210,12 +213,72 @@ vc_status csc_partition(vc_graph g, int64_t tile, hipStream_t s) {
   return VC_OK;
 }
 
+// Builds the hot-first relabelled copy of the graph and switches the graph
+// object to it.  The caller's arrays are not read afterwards.
+vc_status relabel(vc_graph g, hipStream_t s) {
+  const int64_t n = g->n, m = g->m;
+  const int64_t nblocks = (n + vc::kWG - 1) / vc::kWG;
+  const int64_t hist_count = (int64_t)vc::relabel_classes() * nblocks;
+  DevBuf indeg, hist, blocks, tiles;
+  VC_TRY(indeg.ensure((size_t)(n + 1) * 8));
+  VC_TRY(hist.ensure((size_t)(hist_count + 1) * 8));
+  const int64_t scan_need = vc::scan_scratch_entries(hist_count > n ? hist_count : n);
+  VC_TRY(blocks.ensure((size_t)scan_need * 8));
+  VC_TRY(g->perm.ensure((size_t)n * 4));
+  VC_TRY(g->inv.ensure((size_t)n * 4));
+  VC_TRY(g->rel_off.ensure((size_t)(n + 1) * 8));
+  VC_TRY(g->rel_dst.ensure((size_t)m * 4 + 4));
+  if (g->w) VC_TRY(g->rel_w.ensure((size_t)m * 4 + 4));
+  unsigned long long* deg_in = indeg.as<unsigned long long>();
+  VC_TRY(vc::launch_fill_u32(reinterpret_cast<uint32_t*>(deg_in), 2 * (n + 1), 0u, s));
+  VC_TRY(vc::launch_csc_count(g->dst, m, deg_in, s));
+  VC_TRY(vc::launch_relabel_perm(g->off, g->off64, deg_in, n, hist.as<int64_t>(), blocks.as<int64_t>(),
+                                 g->perm.as<int32_t>(), g->inv.as<int32_t>(), s));
+  int64_t* noff = g->rel_off.as<int64_t>();
+  VC_TRY(vc::launch_relabel_degrees(g->off, g->off64, g->inv.as<int32_t>(), n, noff, s));
+  VC_TRY(vc::launch_exclusive_scan(noff, n, blocks.as<int64_t>(), s));
+  const int64_t tile = vc::kDefaultTile;
+  const int64_t ntiles = (n + m + tile - 1) / tile;
+  VC_TRY(tiles.ensure((size_t)(ntiles + 1) * 4));
+  VC_TRY(vc::launch_mp_partition(noff, true, n, n + m, tile, ntiles, tiles.as<int32_t>(), s));
+  VC_TRY(vc::launch_relabel_edges(g->off, g->off64, g->dst, g->w, noff, g->inv.as<int32_t>(), g->perm.as<int32_t>(),
+                                  n, m, tiles.as<int32_t>(), tile, ntiles, g->rel_dst.as<int32_t>(),
+                                  g->w ? g->rel_w.as<uint32_t>() : nullptr, s));
+  VC_TRY(hipStreamSynchronize(s));
+  g->off = noff;
+  g->off64 = true;
+  g->dst = g->rel_dst.as<int32_t>();
+  g->w = g->w ? g->rel_w.as<uint32_t>() : nullptr;
+  g->relabeled = true;
+  g->own_off.release();
+  g->own_dst.release();
+  g->own_w.release();
+  return VC_OK;
+}
+
+// The internal id of a caller's vertex id (a 4-byte device read when relabelled).
+vc_status internal_id(vc_graph g, int64_t v, hipStream_t s, int64_t* out) {
+  if (!g->relabeled) {
+    *out = v;
+    return VC_OK;
+  }
+  int32_t x = 0;
+  VC_TRY(hipMemcpyAsync(&x, g->perm.as<int32_t>() + v, 4, hipMemcpyDeviceToHost, s));
+  VC_TRY(hipStreamSynchronize(s));
+  *out = x;
+  return VC_OK;
+}
+
 // ---------------------------------------------------------------- PageRank / PPR
 
 vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hipStream_t s, Recorder& rec,
                    int32_t* supersteps) {
   const int64_t n = g->n, T = p.max_supersteps;
-  const int64_t source = personal ? (int64_t)p.source : -1;
+  int64_t source = -1;
+  if (personal) {
+    vc_status st = internal_id(g, (int64_t)p.source, s, &source);
+    if (st != VC_OK) return st;
+  }
   const bool fx = !(p.options & VC_OPT_F32_ACCUMULATE);
   const size_t vb = fx ? 8 : 4;
   VC_TRY(g->contrib.ensure((size_t)n * vb));
@@ -223,8 +286,14 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
   void* contrib = g->contrib.p;
   void* mb = g->mb.p;
   const double r0 = 1.0 / (double)n;
+  // ranks come out in internal order; relabelled graphs stage them in the
+  // message buffer (no longer needed at the last step) and un-permute
+  float* rank_out = g->relabeled ? static_cast<float*>(contrib) : out;
   if (T == 0) {
-    VC_TRY(vc::launch_pr_init(fx, g->off, g->off64, n, r0, source, contrib, mb, out, s));
+    VC_TRY(vc::launch_pr_init(fx, g->off, g->off64, n, r0, source, contrib, mb, rank_out, s));
+    if (g->relabeled)
+      VC_TRY(vc::launch_unpermute(reinterpret_cast<const uint32_t*>(rank_out), 1, g->perm.as<int32_t>(), n,
+                                  reinterpret_cast<uint32_t*>(out), s));
     VC_TRY(hipStreamSynchronize(s));
     rec.step(0, 0, 0, 0);
     *supersteps = 1;
@@ -238,7 +307,7 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
     vc_status st = VC_OK;
     if (sched == VC_SCHED_PULL) {
       st = ensure_csc(g, s);
-      if (st == VC_OK) st = csc_partition(g, tile, s);
+      if (st == VC_OK) st = csc_partition(g, vc::pull_tile(tile), s);
     } else if (sched == VC_SCHED_EDGE) {
       st = dense_partition(g, tile, s);
     }
@@ -251,8 +320,8 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
     if (timed) VC_TRY(hipEventRecord(g->events[3 * step], s));
     if (g->m > 0) {
       if (sched == VC_SCHED_PULL)
-        VC_TRY(vc::launch_pr_pull(fx, g->csc_off.as<int64_t>(), g->in_src, n, g->m, g->csc_tiles.as<int32_t>(), tile,
-                                  g->csc_ntiles, contrib, mb, s));
+        VC_TRY(vc::launch_pr_pull(fx, g->csc_off.as<int64_t>(), g->in_src, n, g->m, g->csc_tiles.as<int32_t>(),
+                                  g->csc_tile, g->csc_ntiles, contrib, mb, s));
       else if (sched == VC_SCHED_EDGE)
         VC_TRY(vc::launch_pr_scatter_mp(fx, g->off, g->off64, g->dst, n, g->m, g->dense_tiles.as<int32_t>(), tile,
                                         g->dense_ntiles, contrib, mb, s));
@@ -260,11 +329,14 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
         VC_TRY(vc::launch_pr_scatter_vertex(fx, g->off, g->off64, g->dst, n, contrib, mb, s));
     }
     if (timed) VC_TRY(hipEventRecord(g->events[3 * step + 1], s));
-    VC_TRY(vc::launch_pr_apply(fx, g->off, g->off64, n, teleport, d, source, mb, contrib, out, step + 1 == T, s));
+    VC_TRY(vc::launch_pr_apply(fx, g->off, g->off64, n, teleport, d, source, mb, contrib, rank_out, step + 1 == T, s));
     if (timed) VC_TRY(hipEventRecord(g->events[3 * step + 2], s));
     rec.step(step, n, g->m, sched);
   }
   rec.step(T, 0, 0, 0);
+  if (g->relabeled)
+    VC_TRY(vc::launch_unpermute(reinterpret_cast<const uint32_t*>(rank_out), 1, g->perm.as<int32_t>(), n,
+                                reinterpret_cast<uint32_t*>(out), s));
   VC_TRY(hipStreamSynchronize(s));
   for (int64_t step = 0; step < T && rec.want_time(step); ++step) {
     float a = 0, b = 0;
@@ -312,8 +384,12 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, uint32_t* out, hipSt
   int32_t* list_tiles = g->list_tiles.as<int32_t>();
   vc::Counters* ctr = g->counters.as<vc::Counters>();
 
-  const int64_t source = kind == vc::kCC ? -1 : (int64_t)p.source;
-  VC_TRY(vc::launch_min_init(kind, n, source, vm, s));
+  int64_t source = -1;
+  if (kind != vc::kCC) {
+    vc_status st = internal_id(g, (int64_t)p.source, s, &source);
+    if (st != VC_OK) return st;
+  }
+  VC_TRY(vc::launch_min_init(kind, n, source, g->relabeled ? g->inv.as<int32_t>() : nullptr, vm, s));
   VC_TRY(vc::launch_fill_u32(bits[0], nwords, 0u, s));
   VC_TRY(vc::launch_fill_u32(bits[1], nwords, 0u, s));
   VC_TRY(vc::launch_zero_counters(ctr, s));
@@ -368,11 +444,11 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, uint32_t* out, hipSt
     uint32_t* improved = bits[cur];
     if (sched == VC_SCHED_PULL) {
       vc_status st = ensure_csc(g, s);
-      if (st == VC_OK) st = csc_partition(g, tile, s);
+      if (st == VC_OK) st = csc_partition(g, vc::pull_tile(tile), s);
       if (st != VC_OK) return st;
       if (timed) VC_TRY(hipEventRecord(g->events[1], s));
       VC_TRY(vc::launch_min_pull(kind, g->csc_off.as<int64_t>(), g->in_src, g->in_w, n, m, g->csc_tiles.as<int32_t>(),
-                                 tile, g->csc_ntiles, vm, dense ? nullptr : bits[1 - cur], improved, s));
+                                 g->csc_tile, g->csc_ntiles, vm, dense ? nullptr : bits[1 - cur], improved, s));
     } else if (sched == VC_SCHED_EDGE) {
       if (dense) {
         vc_status st = dense_partition(g, tile, s);
@@ -419,7 +495,10 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, uint32_t* out, hipSt
       break;
     }
   }
-  VC_TRY(vc::launch_min_output(n, vm, out, s));
+  if (g->relabeled)
+    VC_TRY(vc::launch_unpermute(reinterpret_cast<const uint32_t*>(vm), 2, g->perm.as<int32_t>(), n, out, s));
+  else
+    VC_TRY(vc::launch_min_output(n, vm, out, s));
   VC_TRY(hipStreamSynchronize(s));
   return status;
 }
@@ -542,6 +621,10 @@ vc_status vc_graph_create(const vc_graph_desc* d, hipStream_t stream, vc_graph* 
       return cleanup(fail(VC_ERR_BAD_GRAPH, "CSR validation failed:" + why));
     }
   }
+  if (!(d->flags & VC_GRAPH_NO_RELABEL)) {
+    vc_status st = relabel(g, stream);
+    if (st != VC_OK) return cleanup(st);
+  }
   if ((e = hipStreamSynchronize(stream)) != hipSuccess) return cleanup(hip_fail(e, "graph create"));
   *out = g;
   return VC_OK;
@@ -553,7 +636,8 @@ vc_status vc_graph_destroy(vc_graph g) {
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(g->device);
   (void)hipDeviceSynchronize();
-  for (DevBuf* b : {&g->own_off, &g->own_dst, &g->own_w, &g->contrib, &g->mb, &g->vm, &g->bitmap, &g->bitmap2,
+  for (DevBuf* b : {&g->own_off, &g->own_dst, &g->own_w, &g->perm, &g->inv, &g->rel_off, &g->rel_dst, &g->rel_w,
+                    &g->contrib, &g->mb, &g->vm, &g->bitmap, &g->bitmap2,
                     &g->fq, &g->prefix, &g->scan_blocks, &g->list_tiles, &g->dense_tiles, &g->csc_off, &g->csc_src,
                     &g->csc_w, &g->csc_tiles, &g->counters})
     b->release();
@@ -567,7 +651,8 @@ vc_status vc_graph_destroy(vc_graph g) {
 vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held, size_t* bytes_run) {
   if (!g) return fail(VC_ERR_INVALID_ARG, "null graph");
   if (program < VC_PAGERANK || program > VC_PPR) return fail(VC_ERR_INVALID_ARG, "bad program");
-  size_t held = g->own_off.bytes + g->own_dst.bytes + g->own_w.bytes;
+  size_t held = g->own_off.bytes + g->own_dst.bytes + g->own_w.bytes + g->perm.bytes + g->inv.bytes +
+                g->rel_off.bytes + g->rel_dst.bytes + g->rel_w.bytes;
   for (const DevBuf* b : {&g->contrib, &g->mb, &g->vm, &g->bitmap, &g->bitmap2, &g->fq, &g->prefix, &g->scan_blocks,
                           &g->list_tiles, &g->dense_tiles, &g->csc_off, &g->csc_src, &g->csc_w, &g->csc_tiles,
                           &g->counters})

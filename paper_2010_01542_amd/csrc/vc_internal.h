@@ -56,7 +56,9 @@ hipError_t launch_pr_apply(bool fx, const void* off, bool off64, int64_t n, doub
                            int64_t source, void* mb, void* contrib, float* out, bool last, hipStream_t s);
 
 // Hash-min CC and SSSP.  vm holds (value, mailbox) pairs.
-hipError_t launch_min_init(int kind, int64_t n, int64_t source, uint2* vm, hipStream_t s);
+// ids: the label each vertex starts CC with (its original id after
+// relabelling), or NULL for the vertex index itself.
+hipError_t launch_min_init(int kind, int64_t n, int64_t source, const int32_t* ids, uint2* vm, hipStream_t s);
 hipError_t launch_min_seed_source(const void* off, bool off64, int64_t source, int32_t* fq, int64_t* P,
                                   uint32_t* active, hipStream_t s);
 hipError_t launch_min_scatter_vertex(int kind, bool list, bool tba, const void* off, bool off64, const int32_t* dst,
@@ -80,6 +82,8 @@ hipError_t launch_csc_fill(const void* off, bool off64, const int32_t* dst, cons
                            const int32_t* tile_v, int64_t tile, int64_t ntiles, unsigned long long* cursor,
                            int32_t* in_src, uint32_t* in_w, hipStream_t s);
 size_t pull_lds_bytes(int64_t tile);
+// Tile size the pull kernels use for a requested tile: kWG * {4, 8, 16}.
+int64_t pull_tile(int64_t requested);
 hipError_t launch_pr_pull(bool fx, const int64_t* in_off, const int32_t* in_src, int64_t n, int64_t m,
                           const int32_t* tile_v, int64_t tile, int64_t ntiles, const void* contrib, void* mb,
                           hipStream_t s);
@@ -87,6 +91,23 @@ hipError_t launch_pr_pull(bool fx, const int64_t* in_off, const int32_t* in_src,
 hipError_t launch_min_pull(int kind, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w, int64_t n,
                            int64_t m, const int32_t* tile_v, int64_t tile, int64_t ntiles, uint2* vm,
                            const uint32_t* active, uint32_t* improved, hipStream_t s);
+
+// ---------------------------------------------------------------- relabelling
+int relabel_classes();
+// perm[v] = new id of v, inv[new] = v.  hist_scratch: relabel_classes() *
+// ceil(n / kWG) + 1 entries; scan_blocks: scan_scratch_entries of that count.
+hipError_t launch_relabel_perm(const void* off, bool off64, const unsigned long long* indeg, int64_t n,
+                               int64_t* hist_scratch, int64_t* scan_blocks, int32_t* perm, int32_t* inv,
+                               hipStream_t s);
+hipError_t launch_relabel_degrees(const void* off, bool off64, const int32_t* inv, int64_t n, int64_t* P,
+                                  hipStream_t s);
+hipError_t launch_relabel_edges(const void* off, bool off64, const int32_t* dst, const uint32_t* w,
+                                const int64_t* noff, const int32_t* inv, const int32_t* perm, int64_t n, int64_t m,
+                                const int32_t* tile_v, int64_t tile, int64_t ntiles, int32_t* ndst, uint32_t* nw,
+                                hipStream_t s);
+// out[u] = vals[perm[u] * stride]
+hipError_t launch_unpermute(const uint32_t* vals, int64_t stride, const int32_t* perm, int64_t n, uint32_t* out,
+                            hipStream_t s);
 
 // In-place exclusive scan of P[0..count) with P[count] = total; `blocks`
 // is scratch of scan_scratch_entries(count) int64 values.

@@ -201,10 +201,11 @@ __global__ __launch_bounds__(kWG) void k_pr_apply(const OffT* __restrict__ off, 
 
 // ------------------------------------------------------------------ CC / SSSP
 
-__global__ __launch_bounds__(kWG) void k_min_init(int kind, int64_t n, int64_t source, uint2* __restrict__ vm) {
+__global__ __launch_bounds__(kWG) void k_min_init(int kind, int64_t n, int64_t source, const int32_t* __restrict__ ids,
+                                                  uint2* __restrict__ vm) {
   const int64_t v = gid();
   if (v >= n) return;
-  const uint32_t val = kind == kCC ? (uint32_t)v : (v == source ? 0u : kInf);
+  const uint32_t val = kind == kCC ? (uint32_t)(ids ? (int64_t)ids[v] : v) : (v == source ? 0u : kInf);
   vm[v] = make_uint2(val, kInf);
 }
 
@@ -546,8 +547,8 @@ hipError_t launch_pr_apply(bool fx, const void* off, bool off64, int64_t n, doub
                    s);
 }
 
-hipError_t launch_min_init(int kind, int64_t n, int64_t source, uint2* vm, hipStream_t s) {
-  hipLaunchKernelGGL(k_min_init, dim3(grid_for(n)), dim3(kWG), 0, s, kind, n, source, vm);
+hipError_t launch_min_init(int kind, int64_t n, int64_t source, const int32_t* ids, uint2* vm, hipStream_t s) {
+  hipLaunchKernelGGL(k_min_init, dim3(grid_for(n)), dim3(kWG), 0, s, kind, n, source, ids, vm);
   return hipGetLastError();
 }
 

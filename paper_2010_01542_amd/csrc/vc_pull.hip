@@ -129,11 +129,14 @@ __device__ __forceinline__ void global_add<unsigned long long>(unsigned long lon
 
 // mb[v] = sum of contrib[u] over in-edges u->v.  mb must be zero on entry for
 // receivers whose in-edges cross a tile boundary (the update step leaves
-// every mailbox at zero).
-template <class V>
+// every mailbox at zero).  Tiles hold kWG * VT items, so a thread's run is at
+// most VT in-edges: all of its source ids are loaded first, then all of its
+// gathers are issued back to back, and only then combined.
+template <class V, int VT>
 __global__ __launch_bounds__(kWG) void k_pr_pull(const int64_t* __restrict__ in_off, const int32_t* __restrict__ in_src,
                                                  int64_t n, int64_t m, const int32_t* __restrict__ tile_v,
-                                                 int64_t tile, const V* __restrict__ contrib, V* __restrict__ mb) {
+                                                 const V* __restrict__ contrib, V* __restrict__ mb) {
+  constexpr int64_t tile = (int64_t)kWG * VT;
   extern __shared__ __align__(16) unsigned char smem[];
   Tile tl;
   if (!tile_bounds(tile_v, tile, n, m, &tl)) return;
@@ -141,24 +144,32 @@ __global__ __launch_bounds__(kWG) void k_pr_pull(const int64_t* __restrict__ in_
   int64_t* s_off = reinterpret_cast<int64_t*>(smem + align16((tile + 1) * sizeof(V)));  // tile + 2
   for (int x = threadIdx.x; x <= tl.cnt; x += kWG) s_off[x] = in_off[tl.i0 + x];
   for (int x = threadIdx.x; x < tl.cnt; x += kWG) s_acc[x] = V(0);
-  __syncthreads();
-  // each thread: a contiguous run of in-edges
   const int64_t ne = tl.j1 - tl.j0;
-  const int64_t per = (ne + kWG - 1) / kWG;
-  int64_t e = tl.j0 + (int64_t)threadIdx.x * per;
-  const int64_t e_end = e + per < tl.j1 ? e + per : tl.j1;
-  if (e < e_end) {
-    int x = owner_of(s_off, tl.cnt, e);
+  const int per = (int)((ne + kWG - 1) / kWG);  // <= VT
+  const int64_t e0 = tl.j0 + (int64_t)threadIdx.x * per;
+  const int run_len = e0 < tl.j1 ? (int)((tl.j1 - e0) < per ? (tl.j1 - e0) : per) : 0;
+  int32_t src[VT];
+#pragma unroll
+  for (int k = 0; k < VT; ++k) src[k] = k < run_len ? __builtin_nontemporal_load(&in_src[e0 + k]) : 0;
+  V c[VT];
+#pragma unroll
+  for (int k = 0; k < VT; ++k) c[k] = k < run_len ? contrib[src[k]] : V(0);
+  __syncthreads();
+  if (run_len > 0) {
+    int x = owner_of(s_off, tl.cnt, e0);
     int64_t next = s_off[x + 1];
     V run = V(0);
-    for (; e < e_end; ++e) {
-      while (e >= next) {  // receiver changes: flush the running sum
-        if (run != V(0)) lds_add<V>(&s_acc[x], run);
-        run = V(0);
-        ++x;
-        next = s_off[x + 1];
+#pragma unroll
+    for (int k = 0; k < VT; ++k) {
+      if (k < run_len) {
+        while (e0 + k >= next) {  // receiver changes: flush the running sum
+          if (run != V(0)) lds_add<V>(&s_acc[x], run);
+          run = V(0);
+          ++x;
+          next = s_off[x + 1];
+        }
+        run += c[k];
       }
-      run += contrib[in_src[e]];
     }
     if (run != V(0)) lds_add<V>(&s_acc[x], run);
   }
@@ -191,42 +202,59 @@ __device__ __forceinline__ bool bit_set(const uint32_t* __restrict__ bits, int64
 // value(u) (+ w).  When best lowers value(v), the mailbox of v takes it and
 // v is marked in `improved` (the same outcome as the push form, so the
 // compaction step is shared).  `active` = NULL means every vertex broadcast.
-template <int KIND, bool CHECK>
+// As in the PageRank pull, a thread first loads its run of VT in-edges, then
+// the activity words of their sources, then the values of the active ones.
+template <int KIND, bool CHECK, int VT>
 __global__ __launch_bounds__(kWG) void k_min_pull(const int64_t* __restrict__ in_off,
                                                   const int32_t* __restrict__ in_src,
                                                   const uint32_t* __restrict__ in_w, int64_t n, int64_t m,
-                                                  const int32_t* __restrict__ tile_v, int64_t tile,
-                                                  uint2* __restrict__ vm, const uint32_t* __restrict__ active,
+                                                  const int32_t* __restrict__ tile_v, uint2* __restrict__ vm,
+                                                  const uint32_t* __restrict__ active,
                                                   uint32_t* __restrict__ improved) {
+  constexpr int64_t tile = (int64_t)kWG * VT;
   extern __shared__ __align__(16) unsigned char smem[];
   Tile tl;
-  const bool has_edges = tile_bounds(tile_v, tile, n, m, &tl);
-  if (!has_edges) return;
-  uint32_t* s_min = reinterpret_cast<uint32_t*>(smem);                                      // tile + 1
+  if (!tile_bounds(tile_v, tile, n, m, &tl)) return;
+  uint32_t* s_min = reinterpret_cast<uint32_t*>(smem);                          // tile + 1
   int64_t* s_off = reinterpret_cast<int64_t*>(smem + align16((tile + 1) * 4));  // tile + 2
   for (int x = threadIdx.x; x <= tl.cnt; x += kWG) s_off[x] = in_off[tl.i0 + x];
   for (int x = threadIdx.x; x < tl.cnt; x += kWG) s_min[x] = kInf;
-  __syncthreads();
   const uint32_t* val = reinterpret_cast<const uint32_t*>(vm);  // value of u at val[2u]
   const int64_t ne = tl.j1 - tl.j0;
-  const int64_t per = (ne + kWG - 1) / kWG;
-  int64_t e = tl.j0 + (int64_t)threadIdx.x * per;
-  const int64_t e_end = e + per < tl.j1 ? e + per : tl.j1;
-  if (e < e_end) {
-    int x = owner_of(s_off, tl.cnt, e);
+  const int per = (int)((ne + kWG - 1) / kWG);
+  const int64_t e0 = tl.j0 + (int64_t)threadIdx.x * per;
+  const int run_len = e0 < tl.j1 ? (int)((tl.j1 - e0) < per ? (tl.j1 - e0) : per) : 0;
+  int32_t src[VT];
+#pragma unroll
+  for (int k = 0; k < VT; ++k) src[k] = k < run_len ? __builtin_nontemporal_load(&in_src[e0 + k]) : 0;
+  bool act[VT];
+#pragma unroll
+  for (int k = 0; k < VT; ++k) act[k] = k < run_len && (!CHECK || bit_set(active, src[k]));
+  uint32_t msg[VT];
+#pragma unroll
+  for (int k = 0; k < VT; ++k) {
+    msg[k] = kInf;
+    if (act[k]) {
+      const uint32_t wv = KIND == kSsspWeighted ? __builtin_nontemporal_load(&in_w[e0 + k]) : 1u;
+      const uint32_t x = val[2 * (int64_t)src[k]];
+      msg[k] = KIND == kCC ? x : sat_add(x, wv);
+    }
+  }
+  __syncthreads();
+  if (run_len > 0) {
+    int x = owner_of(s_off, tl.cnt, e0);
     int64_t next = s_off[x + 1];
     uint32_t run = kInf;
-    for (; e < e_end; ++e) {
-      while (e >= next) {
-        if (run != kInf) atomicMin(&s_min[x], run);
-        run = kInf;
-        ++x;
-        next = s_off[x + 1];
-      }
-      const int32_t u = in_src[e];
-      if (!CHECK || bit_set(active, u)) {
-        const uint32_t msg = pull_message<KIND>(val[2 * (int64_t)u], in_w, e);
-        run = msg < run ? msg : run;
+#pragma unroll
+    for (int k = 0; k < VT; ++k) {
+      if (k < run_len) {
+        while (e0 + k >= next) {
+          if (run != kInf) atomicMin(&s_min[x], run);
+          run = kInf;
+          ++x;
+          next = s_off[x + 1];
+        }
+        run = msg[k] < run ? msg[k] : run;
       }
     }
     if (run != kInf) atomicMin(&s_min[x], run);
@@ -237,8 +265,8 @@ __global__ __launch_bounds__(kWG) void k_min_pull(const int64_t* __restrict__ in
   // wave ballot (lanes hold consecutive receivers).
   for (int base = 0; base < tl.cnt; base += kWG) {
     const int x = base + (int)threadIdx.x;
+    const int64_t v = tl.i0 + x;
     bool imp = false;
-    int64_t v = tl.i0 + x;
     if (x < tl.cnt) {
       const uint32_t best = s_min[x];
       if (best != kInf) {
@@ -256,13 +284,13 @@ __global__ __launch_bounds__(kWG) void k_min_pull(const int64_t* __restrict__ in
     }
     const unsigned long long mask = __ballot(imp);
     const int lane = (int)lane_id();
-    const int64_t v_lane = tl.i0 + base + (threadIdx.x & ~63u) + lane;  // receiver of this lane
-    const bool leader = lane == 0 || (v_lane & 31) == 0;
+    const bool leader = lane == 0 || (v & 31) == 0;
     if (leader && mask) {
-      const int len = (int)(32 - (v_lane & 31)) < 64 - lane ? (int)(32 - (v_lane & 31)) : 64 - lane;
+      const int room = (int)(32 - (v & 31));
+      const int len = room < 64 - lane ? room : 64 - lane;
       const unsigned long long seg = len >= 64 ? ~0ull : ((1ull << len) - 1ull);
-      const uint32_t bits = (uint32_t)(((mask >> lane) & seg) << (v_lane & 31));
-      if (bits) atomicOr(&improved[v_lane >> 5], bits);
+      const uint32_t bits = (uint32_t)(((mask >> lane) & seg) << (v & 31));
+      if (bits) atomicOr(&improved[v >> 5], bits);
     }
   }
 }
@@ -272,6 +300,13 @@ __global__ __launch_bounds__(kWG) void k_min_pull(const int64_t* __restrict__ in
 // --------------------------------------------------------------- launchers
 
 size_t pull_lds_bytes(int64_t tile) { return align16((size_t)(tile + 1) * 8) + (size_t)(tile + 2) * 8; }
+
+// The pull kernels use tiles of kWG * VT items with VT in {4, 8, 16}.
+int64_t pull_tile(int64_t requested) {
+  if (requested <= (int64_t)kWG * 4) return (int64_t)kWG * 4;
+  if (requested <= (int64_t)kWG * 8) return (int64_t)kWG * 8;
+  return (int64_t)kWG * 16;
+}
 
 hipError_t launch_widen_offsets(const int32_t* a, int64_t count, int64_t* b, hipStream_t s) {
   hipLaunchKernelGGL(k_widen, dim3(grid_for(count)), dim3(kWG), 0, s, a, count, b);
@@ -299,48 +334,70 @@ hipError_t launch_csc_fill(const void* off, bool off64, const int32_t* dst, cons
   return hipGetLastError();
 }
 
+namespace {
+template <class V, int VT>
+void pr_pull_launch(const int64_t* in_off, const int32_t* in_src, int64_t n, int64_t m, const int32_t* tile_v,
+                    int64_t ntiles, const void* contrib, void* mb, hipStream_t s) {
+  const int64_t tile = (int64_t)kWG * VT;
+  const size_t lds = align16((size_t)(tile + 1) * sizeof(V)) + (size_t)(tile + 2) * 8;
+  hipLaunchKernelGGL((k_pr_pull<V, VT>), dim3((unsigned)ntiles), dim3(kWG), lds, s, in_off, in_src, n, m, tile_v,
+                     (const V*)contrib, (V*)mb);
+}
+template <int KIND, int VT>
+void min_pull_launch(bool check, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w, int64_t n,
+                     int64_t m, const int32_t* tile_v, int64_t ntiles, uint2* vm, const uint32_t* active,
+                     uint32_t* improved, hipStream_t s) {
+  const int64_t tile = (int64_t)kWG * VT;
+  const size_t lds = align16((size_t)(tile + 1) * 4) + (size_t)(tile + 2) * 8;
+  if (check)
+    hipLaunchKernelGGL((k_min_pull<KIND, true, VT>), dim3((unsigned)ntiles), dim3(kWG), lds, s, in_off, in_src, in_w,
+                       n, m, tile_v, vm, active, improved);
+  else
+    hipLaunchKernelGGL((k_min_pull<KIND, false, VT>), dim3((unsigned)ntiles), dim3(kWG), lds, s, in_off, in_src,
+                       in_w, n, m, tile_v, vm, active, improved);
+}
+template <int KIND>
+void min_pull_vt(int64_t tile, bool check, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w,
+                 int64_t n, int64_t m, const int32_t* tile_v, int64_t ntiles, uint2* vm, const uint32_t* active,
+                 uint32_t* improved, hipStream_t s) {
+  if (tile == kWG * 4)
+    min_pull_launch<KIND, 4>(check, in_off, in_src, in_w, n, m, tile_v, ntiles, vm, active, improved, s);
+  else if (tile == kWG * 8)
+    min_pull_launch<KIND, 8>(check, in_off, in_src, in_w, n, m, tile_v, ntiles, vm, active, improved, s);
+  else
+    min_pull_launch<KIND, 16>(check, in_off, in_src, in_w, n, m, tile_v, ntiles, vm, active, improved, s);
+}
+}  // namespace
+
 hipError_t launch_pr_pull(bool fx, const int64_t* in_off, const int32_t* in_src, int64_t n, int64_t m,
                           const int32_t* tile_v, int64_t tile, int64_t ntiles, const void* contrib, void* mb,
                           hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
+  if (tile != pull_tile(tile)) return hipErrorInvalidValue;
   if (fx) {
-    const size_t lds = align16((size_t)(tile + 1) * 8) + (size_t)(tile + 2) * 8;
-    hipLaunchKernelGGL(k_pr_pull<unsigned long long>, dim3((unsigned)ntiles), dim3(kWG), lds, s, in_off, in_src, n, m,
-                       tile_v, tile, (const unsigned long long*)contrib, (unsigned long long*)mb);
+    if (tile == kWG * 4) pr_pull_launch<unsigned long long, 4>(in_off, in_src, n, m, tile_v, ntiles, contrib, mb, s);
+    else if (tile == kWG * 8) pr_pull_launch<unsigned long long, 8>(in_off, in_src, n, m, tile_v, ntiles, contrib, mb, s);
+    else pr_pull_launch<unsigned long long, 16>(in_off, in_src, n, m, tile_v, ntiles, contrib, mb, s);
   } else {
-    const size_t lds = align16((size_t)(tile + 1) * 4) + (size_t)(tile + 2) * 8;
-    hipLaunchKernelGGL(k_pr_pull<float>, dim3((unsigned)ntiles), dim3(kWG), lds, s, in_off, in_src, n, m, tile_v,
-                       tile, (const float*)contrib, (float*)mb);
+    if (tile == kWG * 4) pr_pull_launch<float, 4>(in_off, in_src, n, m, tile_v, ntiles, contrib, mb, s);
+    else if (tile == kWG * 8) pr_pull_launch<float, 8>(in_off, in_src, n, m, tile_v, ntiles, contrib, mb, s);
+    else pr_pull_launch<float, 16>(in_off, in_src, n, m, tile_v, ntiles, contrib, mb, s);
   }
   return hipGetLastError();
 }
-
-namespace {
-template <int KIND>
-void min_pull_launch(bool check, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w, int64_t n,
-                     int64_t m, const int32_t* tile_v, int64_t tile, int64_t ntiles, uint2* vm,
-                     const uint32_t* active, uint32_t* improved, hipStream_t s) {
-  const size_t lds = align16((size_t)(tile + 1) * 4) + (size_t)(tile + 2) * 8;
-  if (check)
-    hipLaunchKernelGGL((k_min_pull<KIND, true>), dim3((unsigned)ntiles), dim3(kWG), lds, s, in_off, in_src, in_w, n,
-                       m, tile_v, tile, vm, active, improved);
-  else
-    hipLaunchKernelGGL((k_min_pull<KIND, false>), dim3((unsigned)ntiles), dim3(kWG), lds, s, in_off, in_src, in_w, n,
-                       m, tile_v, tile, vm, active, improved);
-}
-}  // namespace
 
 hipError_t launch_min_pull(int kind, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w, int64_t n,
                            int64_t m, const int32_t* tile_v, int64_t tile, int64_t ntiles, uint2* vm,
                            const uint32_t* active, uint32_t* improved, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
+  if (tile != pull_tile(tile)) return hipErrorInvalidValue;
   const bool check = active != nullptr;
   if (kind == kCC)
-    min_pull_launch<kCC>(check, in_off, in_src, in_w, n, m, tile_v, tile, ntiles, vm, active, improved, s);
+    min_pull_vt<kCC>(tile, check, in_off, in_src, in_w, n, m, tile_v, ntiles, vm, active, improved, s);
   else if (kind == kSsspUnit)
-    min_pull_launch<kSsspUnit>(check, in_off, in_src, in_w, n, m, tile_v, tile, ntiles, vm, active, improved, s);
+    min_pull_vt<kSsspUnit>(tile, check, in_off, in_src, in_w, n, m, tile_v, ntiles, vm, active, improved, s);
   else
-    min_pull_launch<kSsspWeighted>(check, in_off, in_src, in_w, n, m, tile_v, tile, ntiles, vm, active, improved, s);
+    min_pull_vt<kSsspWeighted>(tile, check, in_off, in_src, in_w, n, m, tile_v, ntiles, vm, active, improved, s);
   return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ PROGRAMS = {"pagerank": PAGERANK, "pr": PAGERANK, "cc": CC_HASHMIN, "cc_hashmin"
 SCHED_AUTO, SCHED_VERTEX, SCHED_EDGE, SCHED_PULL = 0, 1, 2, 3
 SCHEDULES = {"auto": SCHED_AUTO, "vertex": SCHED_VERTEX, "edge": SCHED_EDGE, "pull": SCHED_PULL}
 IDX_I32, IDX_I64 = 0, 1
-GRAPH_BORROW, GRAPH_VALIDATE, GRAPH_SYMMETRIC = 1, 2, 4
+GRAPH_BORROW, GRAPH_VALIDATE, GRAPH_SYMMETRIC, GRAPH_NO_RELABEL = 1, 2, 4, 8
 OPT_NO_HUB_AGGREGATION, OPT_NO_TEST_BEFORE_ATOMIC, OPT_F32_ACCUMULATE = 1, 2, 4
 UNREACHED = 0xFFFFFFFF
 
@@ -132,7 +132,7 @@ class Graph:
     """
 
     def __init__(self, offsets, dst, weights=None, *, borrow: bool = True, validate: bool = False,
-                 symmetric: bool = False, stream=None):
+                 symmetric: bool = False, relabel: bool = True, stream=None):
         import torch
         lib = load()
         for name, t in (("offsets", offsets), ("dst", dst), ("weights", weights)):
@@ -152,14 +152,14 @@ class Graph:
             raise ValueError("weights and dst differ in length")
         desc = GraphDesc(ctypes.sizeof(GraphDesc),
                          (GRAPH_BORROW if borrow else 0) | (GRAPH_VALIDATE if validate else 0) |
-                         (GRAPH_SYMMETRIC if symmetric else 0),
+                         (GRAPH_SYMMETRIC if symmetric else 0) | (0 if relabel else GRAPH_NO_RELABEL),
                          n, m, IDX_I64 if offsets.dtype == torch.int64 else IDX_I32, offsets.data_ptr(),
                          dst.data_ptr() if m else None, weights.data_ptr() if weights is not None and m else None)
         handle = ctypes.c_void_p()
         _check(lib.vc_graph_create(ctypes.byref(desc), _stream_handle(stream), ctypes.byref(handle)),
                "vc_graph_create")
         self._h = handle
-        self._keep = (offsets, dst, weights) if borrow else None
+        self._keep = (offsets, dst, weights) if borrow and not relabel else None
         self.n, self.m = n, m
         self.weighted = weights is not None
         self.device = offsets.device

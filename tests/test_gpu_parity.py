@@ -41,17 +41,18 @@ def hand_graphs():
 @pytest.fixture(scope="module")
 def hand(device):
     gs = hand_graphs()
-    return {k: (c, make(c)) for k, c in gs.items()}
+    return {(k, rl): (c, make(c, relabel=rl)) for k, c in gs.items() for rl in (True, False)}
 
 
+@pytest.mark.parametrize("relabel", [True, False])
 @pytest.mark.parametrize("sched", SCHEDS)
 @pytest.mark.parametrize("name", sorted(hand_graphs()))
-def test_hand_graphs_all_programs(hand, name, sched):
-    csr, g = hand[name]
-    print(f"case hand/{name}/{sched}", flush=True)
+def test_hand_graphs_all_programs(hand, name, sched, relabel):
+    csr, g = hand[(name, relabel)]
+    print(f"case hand/{name}/{sched}/relabel={relabel}", flush=True)
     sym = rmatgen.from_edges(csr.n, np.repeat(np.arange(csr.n), csr.outdeg), csr.dst, directed=False)
-    check_min(sym, make(sym), "cc", schedule=sched)
-    check_min(sym, make(sym, symmetric=True), "cc", schedule=sched)
+    check_min(sym, make(sym, relabel=relabel), "cc", schedule=sched)
+    check_min(sym, make(sym, symmetric=True, relabel=relabel), "cc", schedule=sched)
     for src in sorted({0, csr.n - 1}):
         check_min(csr, g, "sssp", source=src, schedule=sched)
     check_rank(csr, g, "pagerank", T=10, schedule=sched)
@@ -65,7 +66,7 @@ def test_rmat_tiles_offsets(device, tile, off_dtype, seed):
     print(f"case rmat s12 tile={tile} off={np.dtype(off_dtype).name} seed={seed}", flush=True)
     d = rmatgen.rmat(12, 16, seed=seed, weighted=True, offset_dtype=off_dtype)
     u = rmatgen.rmat(12, 16, seed=seed, directed=False, offset_dtype=off_dtype)
-    gd, gu = make(d), make(u)
+    gd, gu = make(d, relabel=seed == 1), make(u, relabel=seed == 1)
     for sched in ("vertex", "edge", "pull"):
         check_min(d, gd, "sssp", source=0, schedule=sched, tile=tile)
         check_min(u, gu, "cc", schedule=sched, tile=tile)
@@ -200,3 +201,13 @@ def test_auto_schedule_mixes_push_and_pull(device):
     got, st, ref = check_min(d, make(d), "sssp", source=0, schedule="auto")
     used = set(st.schedule.tolist())
     assert 3 in used and (1 in used or 2 in used), used
+
+
+def test_relabelled_and_input_order_agree_bit_for_bit(device):
+    d = rmatgen.rmat(15, 16, seed=31, weighted=True)
+    a, b = make(d, relabel=True), make(d, relabel=False)
+    for prog, kw in (("sssp", dict(source=7)), ("cc", {}), ("pagerank", dict(T=10)), ("ppr", dict(T=10, source=7))):
+        x, sx = run_gpu(a, prog, **kw)
+        y, sy = run_gpu(b, prog, **kw)
+        assert np.array_equal(x, y), prog
+        assert sx.frontier.tolist() == sy.frontier.tolist(), prog
