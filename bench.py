@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--f32-accumulate", action="store_true", help="binary32 PageRank combiner (float atomics)")
     ap.add_argument("--gen-threads", type=int, default=16)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 1 GiB device-to-device copy first (reference for traffic counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -104,6 +106,15 @@ def main():
     else:
         jobs = [("pagerank", dict(T=10))]
         dominant = "pagerank"
+
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read + 1 GiB written")
+        del a, b
 
     out_f = torch.empty(n, dtype=torch.float32, device=dev)
     out_u = torch.empty(n, dtype=torch.int32, device=dev)
