@@ -52,6 +52,30 @@ def host_info():
     return info
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_2010_01542_amd/csrc/vc_pull.hip", "paper_2010_01542_amd/csrc/vc_device.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the PageRank pull kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs, or None when the kernel source
+    changed since they were taken (or none exist for this workload)."""
+    path = os.path.join(ROOT, "profiles", "pr_pull_s26_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except OSError:
+        return None
+    if rec.get("workload") != workload or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return int(rec["traffic_bytes_per_launch"])
+
+
 def pr_scatter_bytes(n, m, off_bytes):
     """Algorithmic bytes of one PageRank broadcast+combine launch:
     offsets (N+1) + per-vertex message (4N) + targets (4M) + 4-byte mailbox
@@ -165,9 +189,12 @@ def main():
         avg_ms = float(scat.mean())
         bytes_launch = pr_scatter_bytes(n, m, off_bytes)
         achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+        sched = records[0]["pagerank"].schedule[0]
+        kname = {1: "k_pr_scatter_vertex", 2: "k_pr_scatter_mp", 3: "k_pr_pull"}.get(int(sched), "?")
+        traffic = measured_traffic(csr.name) if (kname == "k_pr_pull" and not args.f32_accumulate) else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                    "kernel": "k_pr_scatter_mp (PageRank broadcast+combine)", "launches": int(scat.size),
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "kernel": f"{kname} (PageRank broadcast+combine)", "launches": int(scat.size),
                     "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(bytes_launch),
                     "gteps_per_launch": round(m / (avg_ms * 1e-3) / 1e9, 2)}
 
