@@ -203,6 +203,44 @@ vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held,
 vc_status vc_run(vc_graph g, vc_program program, const vc_params* params, void* out, hipStream_t stream,
                  vc_stats* stats);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent CC / SSSP queries on many graphs in one run.  Hash-min CC
+ * is min-plus propagation with zero edge weights and each vertex's id as its
+ * initial value (paper, Section VI-C, CC and SSSP share the min combiner), so
+ * a batch runs as one superstep loop (paper, Section I) over the disjoint
+ * union of its members: CC members contribute weight-0 edges and their local
+ * ids, SSSP members their weights (1 if none) and 0 at their source.  A
+ * member's result is exactly its result alone: no edge joins two members. */
+typedef struct vc_batch_s* vc_batch;
+
+typedef struct {
+  uint32_t struct_size; /* sizeof(vc_batch_query) */
+  vc_program program;   /* VC_CC_HASHMIN or VC_SSSP */
+  uint32_t source;      /* VC_SSSP: source vertex of the member (member-local id) */
+} vc_batch_query;
+
+/* Builds the union of `count` member graphs (device CSRs as in vc_graph_desc;
+ * member i runs queries[i]).  The members are copied; the caller may free
+ * them on return.  flags: VC_GRAPH_VALIDATE and VC_GRAPH_NO_RELABEL apply to
+ * the union.  CC members must be symmetric for component semantics.
+ * Errors: VC_ERR_INVALID_ARG (null, count < 1, bad member, source >= N_i,
+ * union over 2^31 - 1 vertices), VC_ERR_UNSUPPORTED (program other than CC
+ * or SSSP), VC_ERR_BAD_GRAPH, VC_ERR_OUT_OF_MEMORY, VC_ERR_HIP. */
+vc_status vc_batch_create(const vc_graph_desc* members, const vc_batch_query* queries, int32_t count, uint32_t flags,
+                          hipStream_t stream, vc_batch* out);
+
+/* vertex_base (host, count + 1 entries): member i's results occupy
+ * out[vertex_base[i] .. vertex_base[i+1]) of vc_batch_run's output. */
+vc_status vc_batch_layout(vc_batch b, int64_t* vertex_base);
+
+/* Runs every member's query (params: schedule, tile, options, superstep cap;
+ * source is taken from the queries).  out: device, sum of N_i uint32,
+ * caller-owned: CC labels (member-local minimum ids) and SSSP distances.
+ * stats report the union's supersteps.  Returns after out is complete. */
+vc_status vc_batch_run(vc_batch b, const vc_params* params, uint32_t* out, hipStream_t stream, vc_stats* stats);
+
+vc_status vc_batch_destroy(vc_batch b);
+
 /* Fills *p with the defaults used when vc_run receives NULL params. */
 void vc_params_default(vc_params* p);
 

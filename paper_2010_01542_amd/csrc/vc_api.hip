@@ -35,10 +35,15 @@ vc_status hip_fail(hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail(e_, #call); \
   } while (0)
 
-// A device buffer owned by a graph, grown on demand and kept across runs.
+// A device buffer, grown on demand and kept across runs; freed when its
+// owner goes away (graph, batch, or a temporary of a build step).
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
   hipError_t ensure(size_t want) {
     if (want <= bytes) return hipSuccess;
     if (p) {
@@ -362,8 +367,12 @@ double pull_threshold() {
   return v;
 }
 
-vc_status run_min(vc_graph g, const vc_params& p, int kind, uint32_t* out, hipStream_t s, Recorder& rec,
-                  int32_t* supersteps) {
+// seed (device, internal vertex order, may be NULL): initial values of a
+// seeded min-plus run; every vertex with a finite initial value broadcasts at
+// superstep 0.  Without it the program's own start is used (CC: ids; SSSP:
+// the source).
+vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed, uint32_t* out, hipStream_t s,
+                  Recorder& rec, int32_t* supersteps) {
   const int64_t n = g->n, m = g->m;
   const int64_t tile = pick_tile(p, g);
   const bool tba = !(p.options & VC_OPT_NO_TEST_BEFORE_ATOMIC);
@@ -385,11 +394,10 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, uint32_t* out, hipSt
   vc::Counters* ctr = g->counters.as<vc::Counters>();
 
   int64_t source = -1;
-  if (kind != vc::kCC) {
+  if (kind != vc::kCC && !seed) {
     vc_status st = internal_id(g, (int64_t)p.source, s, &source);
     if (st != VC_OK) return st;
   }
-  VC_TRY(vc::launch_min_init(kind, n, source, g->relabeled ? g->inv.as<int32_t>() : nullptr, vm, s));
   VC_TRY(vc::launch_fill_u32(bits[0], nwords, 0u, s));
   VC_TRY(vc::launch_fill_u32(bits[1], nwords, 0u, s));
   VC_TRY(vc::launch_zero_counters(ctr, s));
@@ -397,14 +405,27 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, uint32_t* out, hipSt
 
   // improvements of superstep s go to bits[cur]; bits[1 - cur] holds F_s
   int cur = 0;
-  bool dense = kind == vc::kCC;  // superstep 0: every vertex broadcasts (CC) or only the source (SSSP)
+  bool dense = kind == vc::kCC && !seed;  // superstep 0: every vertex (CC), the source (SSSP), or the seeded ones
   bool prefix_ready = false;
   int64_t frontier = 0, listed = 0, edges = 0;
-  if (dense) {
+  if (seed) {
+    // the seeded senders become F_0: bitmap, broadcast list and counters as
+    // if they had just improved
+    VC_TRY(vc::launch_min_init_from(seed, n, vm, bits[1], s));
+    VC_TRY(vc::launch_min_compact(g->off, g->off64, n, vm, bits[1], bits[0], fq, P, ctr, true, s));
+    VC_TRY(hipMemcpyAsync(g->host_ctr, ctr, sizeof(vc::Counters), hipMemcpyDeviceToHost, s));
+    VC_TRY(vc::launch_zero_counters(ctr, s));
+    VC_TRY(hipStreamSynchronize(s));
+    frontier = (int64_t)g->host_ctr->active;
+    listed = (int64_t)g->host_ctr->listed;
+    edges = (int64_t)g->host_ctr->edges;
+  } else if (dense) {
+    VC_TRY(vc::launch_min_init(kind, n, source, g->relabeled ? g->inv.as<int32_t>() : nullptr, vm, s));
     frontier = n;
     listed = n;
     edges = m;
   } else {
+    VC_TRY(vc::launch_min_init(kind, n, source, g->relabeled ? g->inv.as<int32_t>() : nullptr, vm, s));
     int64_t o[2] = {0, 0};
     if (g->off64) {
       VC_TRY(hipMemcpyAsync(o, (const int64_t*)g->off + source, 16, hipMemcpyDeviceToHost, s));
@@ -471,7 +492,7 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, uint32_t* out, hipSt
                                            vm, improved, s));
     }
     if (timed) VC_TRY(hipEventRecord(g->events[2], s));
-    VC_TRY(vc::launch_min_compact(g->off, g->off64, n, vm, improved, bits[1 - cur], fq, P, ctr, s));
+    VC_TRY(vc::launch_min_compact(g->off, g->off64, n, vm, improved, bits[1 - cur], fq, P, ctr, false, s));
     if (timed) VC_TRY(hipEventRecord(g->events[3], s));
     VC_TRY(hipMemcpyAsync(g->host_ctr, ctr, sizeof(vc::Counters), hipMemcpyDeviceToHost, s));
     VC_TRY(vc::launch_zero_counters(ctr, s));
@@ -707,13 +728,147 @@ vc_status vc_run(vc_graph g, vc_program program, const vc_params* params, void* 
   if (program == VC_PAGERANK || program == VC_PPR)
     st = run_rank(g, p, program == VC_PPR, static_cast<float*>(out), stream, rec, &supersteps);
   else
-    st = run_min(g, p, program == VC_CC_HASHMIN ? vc::kCC : (g->w ? vc::kSsspWeighted : vc::kSsspUnit),
+    st = run_min(g, p, program == VC_CC_HASHMIN ? vc::kCC : (g->w ? vc::kSsspWeighted : vc::kSsspUnit), nullptr,
                  static_cast<uint32_t*>(out), stream, rec, &supersteps);
   if (stats) {
     stats->supersteps = supersteps;
     stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   return st;
+}
+
+// ---------------------------------------------------------------- batches
+
+struct vc_batch_s {
+  vc_graph g = nullptr;             // the disjoint union of the members
+  std::vector<int64_t> vbase;       // member i owns union vertices [vbase[i], vbase[i+1])
+  DevBuf u_off, u_dst, u_w;         // union CSR in member order (kept only without relabelling)
+  DevBuf init;                      // initial values, internal order
+};
+
+vc_status vc_batch_create(const vc_graph_desc* members, const vc_batch_query* queries, int32_t count, uint32_t flags,
+                          hipStream_t stream, vc_batch* out) {
+  if (!members || !queries || !out || count < 1) return fail(VC_ERR_INVALID_ARG, "null argument or count < 1");
+  int64_t n = 0, m = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    const vc_graph_desc& d = members[i];
+    const vc_batch_query& q = queries[i];
+    if (d.struct_size != sizeof(vc_graph_desc) || q.struct_size != sizeof(vc_batch_query))
+      return fail(VC_ERR_INVALID_ARG, "struct_size mismatch in member " + std::to_string(i));
+    if (d.num_vertices < 1 || d.num_edges < 0 || !d.offsets || (d.num_edges > 0 && !d.dst))
+      return fail(VC_ERR_INVALID_ARG, "bad member graph " + std::to_string(i));
+    if (d.offset_type != VC_IDX_I32 && d.offset_type != VC_IDX_I64)
+      return fail(VC_ERR_INVALID_ARG, "bad offset_type in member " + std::to_string(i));
+    if (q.program != VC_CC_HASHMIN && q.program != VC_SSSP)
+      return fail(VC_ERR_UNSUPPORTED, "batched members run VC_CC_HASHMIN or VC_SSSP");
+    if (q.program == VC_SSSP && (int64_t)q.source >= d.num_vertices)
+      return fail(VC_ERR_INVALID_ARG, "source >= N in member " + std::to_string(i));
+    n += d.num_vertices;
+    m += d.num_edges;
+  }
+  if (n > 2147483647LL) return fail(VC_ERR_INVALID_ARG, "the union exceeds 2^31 - 1 vertices");
+  vc_batch b = new (std::nothrow) vc_batch_s();
+  if (!b) return fail(VC_ERR_OUT_OF_MEMORY, "host allocation failed");
+  auto cleanup = [b](vc_status st) {
+    vc_batch_destroy(b);
+    return st;
+  };
+  hipError_t e;
+  if ((e = b->u_off.ensure((size_t)(n + 1) * 8)) != hipSuccess || (e = b->u_dst.ensure((size_t)m * 4 + 4)) != hipSuccess ||
+      (e = b->u_w.ensure((size_t)m * 4 + 4)) != hipSuccess || (e = b->init.ensure((size_t)n * 4)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipMalloc union"));
+  b->vbase.assign((size_t)count + 1, 0);
+  int64_t vb = 0, eb = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    const vc_graph_desc& d = members[i];
+    const vc_batch_query& q = queries[i];
+    b->vbase[i] = vb;
+    const int wmode = q.program == VC_CC_HASHMIN ? 0 : (d.weights ? 1 : 2);
+    if ((e = vc::launch_union_member(d.offsets, d.offset_type == VC_IDX_I64, d.dst, d.weights, d.num_vertices,
+                                     d.num_edges, vb, eb, wmode, b->u_off.as<int64_t>(), b->u_dst.as<int32_t>(),
+                                     b->u_w.as<uint32_t>(), stream)) != hipSuccess ||
+        (e = vc::launch_union_init(d.num_vertices, vb, q.program == VC_CC_HASHMIN ? 0 : 1, (int64_t)q.source,
+                                   b->init.as<uint32_t>(), stream)) != hipSuccess)
+      return cleanup(hip_fail(e, "union member"));
+    vb += d.num_vertices;
+    eb += d.num_edges;
+  }
+  b->vbase[count] = vb;
+  if ((e = hipMemcpyAsync(b->u_off.as<int64_t>() + n, &m, 8, hipMemcpyHostToDevice, stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(stream)) != hipSuccess)
+    return cleanup(hip_fail(e, "union offsets"));
+  vc_graph_desc ud;
+  std::memset(&ud, 0, sizeof ud);
+  ud.struct_size = sizeof ud;
+  ud.flags = VC_GRAPH_BORROW | (flags & (VC_GRAPH_VALIDATE | VC_GRAPH_NO_RELABEL));
+  ud.num_vertices = n;
+  ud.num_edges = m;
+  ud.offset_type = VC_IDX_I64;
+  ud.offsets = b->u_off.p;
+  ud.dst = b->u_dst.as<int32_t>();
+  ud.weights = b->u_w.as<uint32_t>();
+  vc_status st = vc_graph_create(&ud, stream, &b->g);
+  if (st != VC_OK) return cleanup(st);
+  if (b->g->relabeled) {
+    DevBuf tmp;
+    if ((e = tmp.ensure((size_t)n * 4)) != hipSuccess ||
+        (e = vc::launch_permute(b->init.as<uint32_t>(), b->g->perm.as<int32_t>(), n, tmp.as<uint32_t>(), stream)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(stream)) != hipSuccess)
+      return cleanup(hip_fail(e, "permute initial values"));
+    std::swap(b->init.p, tmp.p);
+    std::swap(b->init.bytes, tmp.bytes);
+    b->u_off.release();
+    b->u_dst.release();
+    b->u_w.release();
+  }
+  *out = b;
+  return VC_OK;
+}
+
+vc_status vc_batch_layout(vc_batch b, int64_t* vertex_base) {
+  if (!b || !vertex_base) return fail(VC_ERR_INVALID_ARG, "null argument");
+  std::memcpy(vertex_base, b->vbase.data(), b->vbase.size() * sizeof(int64_t));
+  return VC_OK;
+}
+
+vc_status vc_batch_run(vc_batch b, const vc_params* params, uint32_t* out, hipStream_t stream, vc_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!b) return fail(VC_ERR_INVALID_ARG, "null batch");
+  if (!out || ((uintptr_t)out % 4)) return fail(VC_ERR_INVALID_ARG, "null or misaligned out");
+  vc_params p;
+  if (params)
+    p = *params;
+  else
+    vc_params_default(&p);
+  p.source = 0;
+  std::string why;
+  if (!valid_params(p, VC_SSSP, b->g->n, &why)) return fail(VC_ERR_INVALID_ARG, why);
+  if (stats) {
+    if (stats->struct_size != sizeof(vc_stats) || stats->capacity < 0)
+      return fail(VC_ERR_INVALID_ARG, "bad vc_stats");
+    stats->supersteps = 0;
+    stats->edges_relaxed = 0;
+  }
+  Recorder rec(stats);
+  int32_t supersteps = 0;
+  vc_status st = run_min(b->g, p, vc::kSsspWeighted, b->init.as<uint32_t>(), out, stream, rec, &supersteps);
+  if (stats) {
+    stats->supersteps = supersteps;
+    stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return st;
+}
+
+vc_status vc_batch_destroy(vc_batch b) {
+  if (!b) return VC_OK;
+  vc_graph_destroy(b->g);
+  b->u_off.release();
+  b->u_dst.release();
+  b->u_w.release();
+  b->init.release();
+  delete b;
+  return VC_OK;
 }
 
 }  // extern "C"

@@ -69,7 +69,20 @@ hipError_t launch_min_scatter_mp(int kind, bool list, bool tba, const void* off,
                                  const int32_t* tile_v, int64_t tile, int64_t ntiles, uint2* vm, uint32_t* bitmap,
                                  hipStream_t s);
 hipError_t launch_min_compact(const void* off, bool off64, int64_t n, uint2* vm, const uint32_t* bitmap,
-                              uint32_t* stale, int32_t* fq, int64_t* P, Counters* ctr, hipStream_t s);
+                              uint32_t* stale, int32_t* fq, int64_t* P, Counters* ctr, bool seed, hipStream_t s);
+// Seeded start: vm = (init, neutral); bitmap word = vertices with init < 0xFFFFFFFF.
+hipError_t launch_min_init_from(const uint32_t* init, int64_t n, uint2* vm, uint32_t* bitmap, hipStream_t s);
+
+// ---------------------------------------------------------------- batches
+// Appends member graph i to the union CSR: offsets shifted by ebase, targets
+// by vbase; weights copied (mode 1), all 1 (mode 2) or all 0 (mode 0).
+hipError_t launch_union_member(const void* off, bool off64, const int32_t* dst, const uint32_t* w, int64_t n, int64_t m,
+                               int64_t vbase, int64_t ebase, int weight_mode, int64_t* u_off, int32_t* u_dst,
+                               uint32_t* u_w, hipStream_t s);
+// init[vbase + v] = v (mode 0: CC labels) or (v == source ? 0 : 0xFFFFFFFF) (mode 1: SSSP)
+hipError_t launch_union_init(int64_t n, int64_t vbase, int mode, int64_t source, uint32_t* init, hipStream_t s);
+// out[perm[u]] = vals[u]
+hipError_t launch_permute(const uint32_t* vals, const int32_t* perm, int64_t n, uint32_t* out, hipStream_t s);
 hipError_t launch_min_output(int64_t n, const uint2* vm, uint32_t* out, hipStream_t s);
 hipError_t launch_zero_counters(Counters* ctr, hipStream_t s);
 

@@ -305,11 +305,13 @@ __global__ __launch_bounds__(kWG) void k_min_scatter_mp(const OffT* __restrict__
 // `bitmap` (this superstep's improvements) is kept: it is the next
 // superstep's active set for the pull form.  `stale` (the previous active
 // set) is cleared so it can collect the next improvements.
+// With `seed` set the values are already in place (the initial senders of a
+// seeded run) and only the list and counters are built.
 template <class OffT>
 __global__ __launch_bounds__(kWG) void k_min_compact(const OffT* __restrict__ off, int64_t n, uint2* __restrict__ vm,
                                                      const uint32_t* __restrict__ bitmap, uint32_t* __restrict__ stale,
                                                      int64_t nwords, int32_t* __restrict__ fq,
-                                                     int64_t* __restrict__ P, Counters* __restrict__ ctr) {
+                                                     int64_t* __restrict__ P, Counters* __restrict__ ctr, int seed) {
   const int64_t wi = gid();
   uint32_t word = 0;
   if (wi < nwords) {
@@ -320,8 +322,10 @@ __global__ __launch_bounds__(kWG) void k_min_compact(const OffT* __restrict__ of
   unsigned long long edges = 0;
   for (uint32_t bits = word; bits; bits &= bits - 1) {
     const int64_t v = wi * 32 + (__ffs(bits) - 1);
-    const uint2 p = vm[v];
-    vm[v] = make_uint2(p.y, kInf);
+    if (!seed) {
+      const uint2 p = vm[v];
+      vm[v] = make_uint2(p.y, kInf);
+    }
     const int64_t deg = (int64_t)off[v + 1] - (int64_t)off[v];
     ++active;
     if (deg > 0) {
@@ -351,6 +355,23 @@ __global__ __launch_bounds__(kWG) void k_min_compact(const OffT* __restrict__ of
       ++at;
     }
   }
+}
+
+// Seeded start: value = init, mailbox neutral; every vertex with a finite
+// initial value broadcasts at superstep 0 (bit set).  One thread per word.
+__global__ __launch_bounds__(kWG) void k_min_init_from(const uint32_t* __restrict__ init, int64_t n, int64_t nwords,
+                                                       uint2* __restrict__ vm, uint32_t* __restrict__ bitmap) {
+  const int64_t wi = gid();
+  if (wi >= nwords) return;
+  uint32_t word = 0;
+  for (int b = 0; b < 32; ++b) {
+    const int64_t v = wi * 32 + b;
+    if (v >= n) break;
+    const uint32_t x = init[v];
+    vm[v] = make_uint2(x, kInf);
+    if (x != kInf) word |= 1u << b;
+  }
+  bitmap[wi] = word;
 }
 
 __global__ __launch_bounds__(kWG) void k_min_output(int64_t n, const uint2* __restrict__ vm,
@@ -662,14 +683,20 @@ hipError_t launch_min_scatter_mp(int kind, bool list, bool tba, const void* off,
 }
 
 hipError_t launch_min_compact(const void* off, bool off64, int64_t n, uint2* vm, const uint32_t* bitmap,
-                              uint32_t* stale, int32_t* fq, int64_t* P, Counters* ctr, hipStream_t s) {
+                              uint32_t* stale, int32_t* fq, int64_t* P, Counters* ctr, bool seed, hipStream_t s) {
   const int64_t nwords = (n + 31) / 32;
   if (off64)
     hipLaunchKernelGGL(k_min_compact<int64_t>, dim3(grid_for(nwords)), dim3(kWG), 0, s, (const int64_t*)off, n, vm,
-                       bitmap, stale, nwords, fq, P, ctr);
+                       bitmap, stale, nwords, fq, P, ctr, (int)seed);
   else
     hipLaunchKernelGGL(k_min_compact<int32_t>, dim3(grid_for(nwords)), dim3(kWG), 0, s, (const int32_t*)off, n, vm,
-                       bitmap, stale, nwords, fq, P, ctr);
+                       bitmap, stale, nwords, fq, P, ctr, (int)seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_min_init_from(const uint32_t* init, int64_t n, uint2* vm, uint32_t* bitmap, hipStream_t s) {
+  const int64_t nwords = (n + 31) / 32;
+  hipLaunchKernelGGL(k_min_init_from, dim3(grid_for(nwords)), dim3(kWG), 0, s, init, n, nwords, vm, bitmap);
   return hipGetLastError();
 }
 

@@ -131,7 +131,58 @@ __global__ __launch_bounds__(kWG) void k_unpermute(const uint32_t* __restrict__ 
   if (u < n) out[u] = vals[(int64_t)perm[u] * stride];
 }
 
+template <class OffT>
+__global__ __launch_bounds__(kWG) void k_union_member(const OffT* __restrict__ off, const int32_t* __restrict__ dst,
+                                                      const uint32_t* __restrict__ w, int64_t n, int64_t m,
+                                                      int64_t vbase, int64_t ebase, int weight_mode,
+                                                      int64_t* __restrict__ u_off, int32_t* __restrict__ u_dst,
+                                                      uint32_t* __restrict__ u_w) {
+  const int64_t stride = (int64_t)gridDim.x * kWG;
+  for (int64_t v = gid(); v < n; v += stride) u_off[vbase + v] = ebase + (int64_t)off[v];
+  for (int64_t e = gid(); e < m; e += stride) {
+    u_dst[ebase + e] = (int32_t)(vbase + dst[e]);
+    u_w[ebase + e] = weight_mode == 1 ? w[e] : (weight_mode == 2 ? 1u : 0u);
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_union_init(int64_t n, int64_t vbase, int mode, int64_t source,
+                                                    uint32_t* __restrict__ init) {
+  const int64_t v = gid();
+  if (v < n) init[vbase + v] = mode == 0 ? (uint32_t)v : (v == source ? 0u : 0xFFFFFFFFu);
+}
+
+__global__ __launch_bounds__(kWG) void k_permute(const uint32_t* __restrict__ vals, const int32_t* __restrict__ perm,
+                                                 int64_t n, uint32_t* __restrict__ out) {
+  const int64_t u = gid();
+  if (u < n) out[perm[u]] = vals[u];
+}
+
 }  // namespace
+
+hipError_t launch_union_member(const void* off, bool off64, const int32_t* dst, const uint32_t* w, int64_t n, int64_t m,
+                               int64_t vbase, int64_t ebase, int weight_mode, int64_t* u_off, int32_t* u_dst,
+                               uint32_t* u_w, hipStream_t s) {
+  const int64_t work = n > m ? n : m;
+  const int64_t blocks = (work + kWG - 1) / kWG;
+  const unsigned g = (unsigned)(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096);
+  if (off64)
+    hipLaunchKernelGGL(k_union_member<int64_t>, dim3(g), dim3(kWG), 0, s, (const int64_t*)off, dst, w, n, m, vbase,
+                       ebase, weight_mode, u_off, u_dst, u_w);
+  else
+    hipLaunchKernelGGL(k_union_member<int32_t>, dim3(g), dim3(kWG), 0, s, (const int32_t*)off, dst, w, n, m, vbase,
+                       ebase, weight_mode, u_off, u_dst, u_w);
+  return hipGetLastError();
+}
+
+hipError_t launch_union_init(int64_t n, int64_t vbase, int mode, int64_t source, uint32_t* init, hipStream_t s) {
+  hipLaunchKernelGGL(k_union_init, dim3(grid_for(n)), dim3(kWG), 0, s, n, vbase, mode, source, init);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute(const uint32_t* vals, const int32_t* perm, int64_t n, uint32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_permute, dim3(grid_for(n)), dim3(kWG), 0, s, vals, perm, n, out);
+  return hipGetLastError();
+}
 
 int relabel_classes() { return kClasses; }
 

@@ -29,7 +29,8 @@ UNREACHED = 0xFFFFFFFF
 OK, ERR_INVALID_ARG, ERR_BAD_GRAPH, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_UNSUPPORTED, ERR_NOT_CONVERGED = range(7)
 ABI_VERSION = 1
 EXPORTS = ("vc_graph_create", "vc_graph_destroy", "vc_graph_footprint", "vc_run", "vc_params_default",
-           "vc_status_string", "vc_last_error", "vc_abi_version")
+           "vc_status_string", "vc_last_error", "vc_abi_version", "vc_batch_create", "vc_batch_layout",
+           "vc_batch_run", "vc_batch_destroy")
 
 
 class GraphDesc(ctypes.Structure):
@@ -49,6 +50,10 @@ class StatsStruct(ctypes.Structure):
                 ("edges_relaxed", ctypes.c_int64), ("elapsed_ms", ctypes.c_double), ("capacity", ctypes.c_int32),
                 ("frontier", ctypes.c_void_p), ("edges", ctypes.c_void_p), ("scatter_ms", ctypes.c_void_p),
                 ("step_ms", ctypes.c_void_p), ("schedule", ctypes.c_void_p)]
+
+
+class BatchQuery(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("program", ctypes.c_int), ("source", ctypes.c_uint32)]
 
 
 class VcError(RuntimeError):
@@ -85,6 +90,15 @@ def load(path: str = LIB_PATH):
     lib.vc_last_error.restype = ctypes.c_char_p
     lib.vc_last_error.argtypes = []
     lib.vc_abi_version.restype = i32
+    lib.vc_batch_create.restype = i32
+    lib.vc_batch_create.argtypes = [ctypes.POINTER(GraphDesc), ctypes.POINTER(BatchQuery), ctypes.c_int32,
+                                    ctypes.c_uint32, vp, ctypes.POINTER(vp)]
+    lib.vc_batch_layout.restype = i32
+    lib.vc_batch_layout.argtypes = [vp, vp]
+    lib.vc_batch_run.restype = i32
+    lib.vc_batch_run.argtypes = [vp, ctypes.POINTER(Params), vp, vp, ctypes.POINTER(StatsStruct)]
+    lib.vc_batch_destroy.restype = i32
+    lib.vc_batch_destroy.argtypes = [vp]
     if lib.vc_abi_version() != ABI_VERSION:
         raise RuntimeError(f"{path}: ABI version {lib.vc_abi_version()} != {ABI_VERSION}; rebuild the library")
     _lib = lib
@@ -213,36 +227,120 @@ class Graph:
             out = torch.empty(self.n, dtype=torch.float32 if rank else torch.int32, device=self.device)
         if not out.is_cuda or not out.is_contiguous() or out.numel() != self.n or out.element_size() != 4:
             raise TypeError("out must be a contiguous CUDA tensor of N 4-byte elements")
-        p = Params()
-        lib.vc_params_default(ctypes.byref(p))
-        p.max_supersteps = int(T) if rank else int(max_supersteps)
-        p.damping = float(damping)
-        p.source = int(source)
-        p.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
-        p.tile = int(tile)
-        p.options = int(options)
-        st = None
-        arrays = {}
-        if stats or timing:
-            cap = int(capacity)
-            arrays = {"frontier": np.zeros(cap, np.int64), "edges": np.zeros(cap, np.int64),
-                      "schedule": np.zeros(cap, np.int32)}
-            if timing:
-                arrays["scatter_ms"] = np.zeros(cap, np.float32)
-                arrays["step_ms"] = np.zeros(cap, np.float32)
-            st = StatsStruct(ctypes.sizeof(StatsStruct), 0, 0, 0.0, cap,
-                             arrays["frontier"].ctypes.data, arrays["edges"].ctypes.data,
-                             arrays["scatter_ms"].ctypes.data if timing else None,
-                             arrays["step_ms"].ctypes.data if timing else None,
-                             arrays["schedule"].ctypes.data)
+        p = _params(T if rank else max_supersteps, damping, source, schedule, tile, options)
+        st, arrays = _stats_struct(stats or timing, timing, capacity)
         rc = lib.vc_run(self._h, prog, ctypes.byref(p), out.data_ptr(), _stream_handle(stream),
                         ctypes.byref(st) if st is not None else None)
         _check(rc, "vc_run")
-        if st is None:
-            return out, None
-        k = min(st.supersteps, int(capacity))
-        res = Stats(st.supersteps, st.edges_relaxed, st.elapsed_ms, arrays["frontier"][:k].copy(),
-                    arrays["edges"][:k].copy(),
-                    arrays["scatter_ms"][:k].copy() if timing else None,
-                    arrays["step_ms"][:k].copy() if timing else None, arrays["schedule"][:k].copy())
-        return out, res
+        return out, _stats_result(st, arrays, capacity)
+
+
+def _params(steps, damping, source, schedule, tile, options) -> Params:
+    p = Params()
+    load().vc_params_default(ctypes.byref(p))
+    p.max_supersteps = int(steps)
+    p.damping = float(damping)
+    p.source = int(source)
+    p.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
+    p.tile = int(tile)
+    p.options = int(options)
+    return p
+
+
+def _stats_struct(want: bool, timing: bool, capacity: int):
+    if not want:
+        return None, {}
+    cap = int(capacity)
+    arrays = {"frontier": np.zeros(cap, np.int64), "edges": np.zeros(cap, np.int64),
+              "schedule": np.zeros(cap, np.int32)}
+    if timing:
+        arrays["scatter_ms"] = np.zeros(cap, np.float32)
+        arrays["step_ms"] = np.zeros(cap, np.float32)
+    st = StatsStruct(ctypes.sizeof(StatsStruct), 0, 0, 0.0, cap, arrays["frontier"].ctypes.data,
+                     arrays["edges"].ctypes.data, arrays["scatter_ms"].ctypes.data if timing else None,
+                     arrays["step_ms"].ctypes.data if timing else None, arrays["schedule"].ctypes.data)
+    return st, arrays
+
+
+def _stats_result(st, arrays, capacity):
+    if st is None:
+        return None
+    k = min(st.supersteps, int(capacity))
+    timing = "scatter_ms" in arrays
+    return Stats(st.supersteps, st.edges_relaxed, st.elapsed_ms, arrays["frontier"][:k].copy(),
+                 arrays["edges"][:k].copy(), arrays["scatter_ms"][:k].copy() if timing else None,
+                 arrays["step_ms"][:k].copy() if timing else None, arrays["schedule"][:k].copy())
+
+
+class Batch:
+    """Many CC / SSSP queries over many graphs in one run (vc_batch_*).
+
+    members: list of rmatgen.Csr (host) or (offsets, dst, weights) CUDA
+    tensor triples; queries: list of ("cc" | "sssp", source).  The library
+    copies the members into one device-resident union.
+    """
+
+    def __init__(self, members, queries, *, validate: bool = False, relabel: bool = True, stream=None, device=None):
+        import torch
+        lib = load()
+        if len(members) != len(queries) or not members:
+            raise ValueError("members and queries must be non-empty and of equal length")
+        device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        keep = []
+        descs = (GraphDesc * len(members))()
+        qs = (BatchQuery * len(members))()
+        for i, (mem, (prog, src)) in enumerate(zip(members, queries)):
+            if isinstance(mem, tuple):
+                off, dst, w = mem
+            else:
+                off = torch.from_numpy(np.ascontiguousarray(mem.off)).to(device)
+                dst = torch.from_numpy(np.ascontiguousarray(mem.dst)).to(device)
+                w = None if mem.w is None else torch.from_numpy(np.ascontiguousarray(mem.w).view(np.int32)).to(device)
+            keep.append((off, dst, w))
+            n, m = off.numel() - 1, dst.numel()
+            descs[i] = GraphDesc(ctypes.sizeof(GraphDesc), 0, n, m,
+                                 IDX_I64 if off.dtype == torch.int64 else IDX_I32, off.data_ptr(),
+                                 dst.data_ptr() if m else None, w.data_ptr() if (w is not None and m) else None)
+            qs[i] = BatchQuery(ctypes.sizeof(BatchQuery), _program(prog), int(src))
+        torch.cuda.synchronize(device)
+        h = ctypes.c_void_p()
+        flags = (GRAPH_VALIDATE if validate else 0) | (0 if relabel else GRAPH_NO_RELABEL)
+        _check(lib.vc_batch_create(descs, qs, len(members), flags, _stream_handle(stream), ctypes.byref(h)),
+               "vc_batch_create")
+        self._h = h
+        self.count = len(members)
+        base = np.zeros(self.count + 1, np.int64)
+        _check(lib.vc_batch_layout(h, base.ctypes.data), "vc_batch_layout")
+        self.vertex_base = base
+        self.n = int(base[-1])
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().vc_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, out=None, *, max_supersteps: int = 0, schedule="auto", tile: int = 0, options: int = 0,
+            stream=None, stats: bool = False, timing: bool = False, capacity: int = 4096):
+        import torch
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        if not out.is_cuda or not out.is_contiguous() or out.numel() != self.n or out.element_size() != 4:
+            raise TypeError("out must be a contiguous CUDA tensor of sum(N_i) 4-byte elements")
+        p = _params(max_supersteps, 0.85, 0, schedule, tile, options)
+        st, arrays = _stats_struct(stats or timing, timing, capacity)
+        rc = load().vc_batch_run(self._h, ctypes.byref(p), out.data_ptr(), _stream_handle(stream),
+                                 ctypes.byref(st) if st is not None else None)
+        _check(rc, "vc_batch_run")
+        return out, _stats_result(st, arrays, capacity)
+
+    def split(self, out):
+        """Host numpy uint32 results, one array per member."""
+        vals = out.cpu().numpy().view(np.uint32)
+        return [vals[self.vertex_base[i]:self.vertex_base[i + 1]] for i in range(self.count)]

@@ -48,7 +48,8 @@ def test_params_default():
 
 def test_struct_layout_matches_header(tmp_path):
     """sizeof / offsetof of every ABI struct field, from the C compiler, equal ctypes'."""
-    structs = {"vc_graph_desc": vc.GraphDesc, "vc_params": vc.Params, "vc_stats": vc.StatsStruct}
+    structs = {"vc_graph_desc": vc.GraphDesc, "vc_params": vc.Params, "vc_stats": vc.StatsStruct,
+               "vc_batch_query": vc.BatchQuery}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "vc.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
@@ -86,3 +87,12 @@ def test_argument_errors_need_no_device():
     assert lib.vc_graph_destroy(None) == vc.OK
     held = ctypes.c_size_t()
     assert lib.vc_graph_footprint(None, 0, ctypes.byref(held), None) == vc.ERR_INVALID_ARG
+    b = ctypes.c_void_p()
+    assert lib.vc_batch_create(None, None, 0, 0, None, ctypes.byref(b)) == vc.ERR_INVALID_ARG
+    descs = (vc.GraphDesc * 1)(vc.GraphDesc(ctypes.sizeof(vc.GraphDesc), 0, 4, 0, vc.IDX_I32, 8, 8, None))
+    qs = (vc.BatchQuery * 1)(vc.BatchQuery(ctypes.sizeof(vc.BatchQuery), vc.PAGERANK, 0))
+    assert lib.vc_batch_create(descs, qs, 1, 0, None, ctypes.byref(b)) == vc.ERR_UNSUPPORTED
+    qs[0] = vc.BatchQuery(ctypes.sizeof(vc.BatchQuery), vc.SSSP, 4)
+    assert lib.vc_batch_create(descs, qs, 1, 0, None, ctypes.byref(b)) == vc.ERR_INVALID_ARG
+    assert lib.vc_batch_run(None, None, 16, None, None) == vc.ERR_INVALID_ARG
+    assert lib.vc_batch_destroy(None) == vc.OK
