@@ -203,6 +203,23 @@ vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held,
 vc_status vc_run(vc_graph g, vc_program program, const vc_params* params, void* out, hipStream_t stream,
                  vc_stats* stats);
 
+/* Many-source SSSP: k (1..256) SSSP programs on one graph, run side by side
+ * in one superstep loop (paper, Section I) with the min combiner (Section
+ * III), in the pull form (Section VI-C): each superstep a vertex takes, per
+ * source, the minimum of dist(u) + w(u, v) over in-neighbours u whose
+ * distance to that source improved in the previous superstep.
+ *   sources  host, k caller vertex ids (< N; repeats allowed).
+ *   out      device, N * k uint32, caller-owned, row-major by vertex:
+ *            out[v * k + i] = distance from sources[i] to v (0xFFFFFFFF:
+ *            unreached).
+ *   stats    |F_s| counts vertices with at least one improved source.
+ * The device state is N x 64*ceil(k/64) distances and mailboxes (8 bytes per
+ * vertex and source), kept with the graph for reuse.
+ * Errors: VC_ERR_INVALID_ARG (null, k outside 1..256, source >= N),
+ * VC_ERR_NOT_CONVERGED, VC_ERR_OUT_OF_MEMORY, VC_ERR_HIP. */
+vc_status vc_run_multi_source(vc_graph g, const uint32_t* sources, int32_t k, const vc_params* params, uint32_t* out,
+                              hipStream_t stream, vc_stats* stats);
+
 /* ---------------------------------------------------------------- batches
  * Many independent CC / SSSP queries on many graphs in one run.  Hash-min CC
  * is min-plus propagation with zero edge weights and each vertex's id as its

@@ -95,6 +95,7 @@ struct vc_graph_s {
   const uint32_t* in_w = nullptr;
   bool csc_ready = false;
   int64_t csc_tile = 0, csc_ntiles = 0;
+  DevBuf ms_d, ms_mb, ms_a0, ms_a1, ms_src;  // many-source SSSP: distances, mailboxes, lane masks
   DevBuf counters;
   size_t max_lds = 65536;            // dynamic LDS limit per workgroup on the graph's device
   vc::Counters* host_ctr = nullptr;  // pinned
@@ -660,7 +661,7 @@ vc_status vc_graph_destroy(vc_graph g) {
   for (DevBuf* b : {&g->own_off, &g->own_dst, &g->own_w, &g->perm, &g->inv, &g->rel_off, &g->rel_dst, &g->rel_w,
                     &g->contrib, &g->mb, &g->vm, &g->bitmap, &g->bitmap2,
                     &g->fq, &g->prefix, &g->scan_blocks, &g->list_tiles, &g->dense_tiles, &g->csc_off, &g->csc_src,
-                    &g->csc_w, &g->csc_tiles, &g->counters})
+                    &g->csc_w, &g->csc_tiles, &g->ms_d, &g->ms_mb, &g->ms_a0, &g->ms_a1, &g->ms_src, &g->counters})
     b->release();
   if (g->host_ctr) (void)hipHostFree(g->host_ctr);
   for (hipEvent_t e : g->events) (void)hipEventDestroy(e);
@@ -676,7 +677,7 @@ vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held,
                 g->rel_off.bytes + g->rel_dst.bytes + g->rel_w.bytes;
   for (const DevBuf* b : {&g->contrib, &g->mb, &g->vm, &g->bitmap, &g->bitmap2, &g->fq, &g->prefix, &g->scan_blocks,
                           &g->list_tiles, &g->dense_tiles, &g->csc_off, &g->csc_src, &g->csc_w, &g->csc_tiles,
-                          &g->counters})
+                          &g->ms_d, &g->ms_mb, &g->ms_a0, &g->ms_a1, &g->ms_src, &g->counters})
     held += b->bytes;
   if (bytes_held) *bytes_held = held;
   if (bytes_run) {
@@ -869,6 +870,116 @@ vc_status vc_batch_destroy(vc_batch b) {
   b->init.release();
   delete b;
   return VC_OK;
+}
+
+vc_status vc_run_multi_source(vc_graph g, const uint32_t* sources, int32_t k, const vc_params* params, uint32_t* out,
+                              hipStream_t s, vc_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!g || !sources || !out) return fail(VC_ERR_INVALID_ARG, "null argument");
+  if (k < 1 || k > 256) return fail(VC_ERR_INVALID_ARG, "need 1 <= k <= 256 sources");
+  if ((uintptr_t)out % 4) return fail(VC_ERR_INVALID_ARG, "misaligned out");
+  for (int32_t i = 0; i < k; ++i)
+    if ((int64_t)sources[i] >= g->n) return fail(VC_ERR_INVALID_ARG, "source >= N");
+  vc_params p;
+  if (params)
+    p = *params;
+  else
+    vc_params_default(&p);
+  p.source = 0;
+  std::string why;
+  if (!valid_params(p, VC_SSSP, g->n, &why)) return fail(VC_ERR_INVALID_ARG, why);
+  if (stats) {
+    if (stats->struct_size != sizeof(vc_stats) || stats->capacity < 0) return fail(VC_ERR_INVALID_ARG, "bad vc_stats");
+    stats->supersteps = 0;
+    stats->edges_relaxed = 0;
+  }
+  Recorder rec(stats);
+  const int64_t n = g->n, m = g->m;
+  const int C = vc::ms_chunks(k);
+  const int64_t K = 64 * (int64_t)C;
+  const int64_t nwords = (n + 31) / 32;
+  VC_TRY(g->ms_d.ensure((size_t)(n * K) * 4));
+  VC_TRY(g->ms_mb.ensure((size_t)(n * K) * 4));
+  VC_TRY(g->ms_a0.ensure((size_t)(n * C) * 8));
+  VC_TRY(g->ms_a1.ensure((size_t)(n * C) * 8));
+  VC_TRY(g->ms_src.ensure((size_t)k * 4));
+  VC_TRY(g->bitmap.ensure((size_t)nwords * 4));
+  VC_TRY(g->counters.ensure(sizeof(vc::Counters)));
+  if (!g->host_ctr) VC_TRY(hipHostMalloc((void**)&g->host_ctr, sizeof(vc::Counters), hipHostMallocDefault));
+  {
+    vc_status st = ensure_csc(g, s);
+    if (st != VC_OK) return st;
+    st = csc_partition(g, vc::pull_tile(pick_tile(p, g)), s);
+    if (st != VC_OK) return st;
+  }
+  uint32_t* D = g->ms_d.as<uint32_t>();
+  uint32_t* MB = g->ms_mb.as<uint32_t>();
+  unsigned long long* A[2] = {g->ms_a0.as<unsigned long long>(), g->ms_a1.as<unsigned long long>()};
+  uint32_t* bits = g->bitmap.as<uint32_t>();
+  vc::Counters* ctr = g->counters.as<vc::Counters>();
+  VC_TRY(vc::launch_fill_u32(D, n * K, vc::kInf, s));
+  VC_TRY(vc::launch_fill_u32(MB, n * K, vc::kInf, s));
+  VC_TRY(vc::launch_fill_u32(reinterpret_cast<uint32_t*>(A[0]), 2 * n * C, 0u, s));
+  VC_TRY(vc::launch_fill_u32(reinterpret_cast<uint32_t*>(A[1]), 2 * n * C, 0u, s));
+  VC_TRY(vc::launch_fill_u32(bits, nwords, 0u, s));
+  VC_TRY(vc::launch_zero_counters(ctr, s));
+  VC_TRY(hipMemcpyAsync(g->ms_src.p, sources, (size_t)k * 4, hipMemcpyHostToDevice, s));
+  VC_TRY(vc::launch_ms_seed(C, g->ms_src.as<int32_t>(), g->relabeled ? g->perm.as<int32_t>() : nullptr, k, D, A[0],
+                            bits, s));
+  VC_TRY(vc::launch_ms_count(g->off, g->off64, n, bits, ctr, s));
+  VC_TRY(vc::launch_fill_u32(bits, nwords, 0u, s));
+  VC_TRY(hipMemcpyAsync(g->host_ctr, ctr, sizeof(vc::Counters), hipMemcpyDeviceToHost, s));
+  VC_TRY(vc::launch_zero_counters(ctr, s));
+  VC_TRY(hipStreamSynchronize(s));
+  if (rec.timed) VC_TRY(ensure_events(g, 4));
+  int64_t frontier = (int64_t)g->host_ctr->active, edges = (int64_t)g->host_ctr->edges;
+  const int64_t cap = p.max_supersteps > 0 ? (int64_t)p.max_supersteps : n + 1;
+  const bool weighted = g->w != nullptr;
+  vc_status status = VC_OK;
+  int cur = 0;
+  int64_t step = 0;
+  int32_t supersteps = 0;
+  for (;;) {
+    if (frontier == 0 || edges == 0) {
+      rec.step(step, frontier, edges, 0);
+      supersteps = (int32_t)(step + 1);
+      break;
+    }
+    rec.step(step, frontier, edges, VC_SCHED_PULL);
+    const bool timed = rec.want_time(step);
+    if (timed) VC_TRY(hipEventRecord(g->events[0], s));
+    VC_TRY(vc::launch_ms_pull(C, weighted, g->csc_off.as<int64_t>(), g->in_src, g->in_w, n, m,
+                              g->csc_tiles.as<int32_t>(), g->csc_tile, g->csc_ntiles, D, MB, A[cur], bits, s));
+    if (timed) VC_TRY(hipEventRecord(g->events[1], s));
+    VC_TRY(vc::launch_fill_u32(reinterpret_cast<uint32_t*>(A[1 - cur]), 2 * n * C, 0u, s));
+    VC_TRY(vc::launch_ms_apply(C, g->off, g->off64, n, D, MB, A[1 - cur], bits, ctr, s));
+    if (timed) VC_TRY(hipEventRecord(g->events[2], s));
+    VC_TRY(hipMemcpyAsync(g->host_ctr, ctr, sizeof(vc::Counters), hipMemcpyDeviceToHost, s));
+    VC_TRY(vc::launch_zero_counters(ctr, s));
+    VC_TRY(hipStreamSynchronize(s));
+    if (timed) {
+      float a = 0, b = 0;
+      VC_TRY(hipEventElapsedTime(&a, g->events[0], g->events[1]));
+      VC_TRY(hipEventElapsedTime(&b, g->events[0], g->events[2]));
+      rec.times(step, a, b);
+    }
+    frontier = (int64_t)g->host_ctr->active;
+    edges = (int64_t)g->host_ctr->edges;
+    cur = 1 - cur;
+    ++step;
+    if (step >= cap) {
+      supersteps = (int32_t)step;
+      status = fail(VC_ERR_NOT_CONVERGED, "superstep cap reached before quiescence");
+      break;
+    }
+  }
+  VC_TRY(vc::launch_ms_output(C, D, g->relabeled ? g->perm.as<int32_t>() : nullptr, n, k, out, s));
+  VC_TRY(hipStreamSynchronize(s));
+  if (stats) {
+    stats->supersteps = supersteps;
+    stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return status;
 }
 
 }  // extern "C"

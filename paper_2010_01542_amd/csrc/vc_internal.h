@@ -122,6 +122,22 @@ hipError_t launch_relabel_edges(const void* off, bool off64, const int32_t* dst,
 hipError_t launch_unpermute(const uint32_t* vals, int64_t stride, const int32_t* perm, int64_t n, uint32_t* out,
                             hipStream_t s);
 
+// ---------------------------------------------------------------- many sources
+// K sources run side by side in an N x (64 * C) distance matrix.
+int ms_chunks(int k);
+hipError_t launch_ms_seed(int C, const int32_t* src, const int32_t* perm, int k_real, uint32_t* D,
+                          unsigned long long* A, uint32_t* bits, hipStream_t s);
+hipError_t launch_ms_pull(int C, bool weighted, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w,
+                          int64_t n, int64_t m, const int32_t* tile_v, int64_t tile, int64_t ntiles,
+                          const uint32_t* D, uint32_t* MB, const unsigned long long* A, uint32_t* improved,
+                          hipStream_t s);
+hipError_t launch_ms_apply(int C, const void* off, bool off64, int64_t n, uint32_t* D, uint32_t* MB,
+                           unsigned long long* A_next, uint32_t* improved, Counters* ctr, hipStream_t s);
+hipError_t launch_ms_count(const void* off, bool off64, int64_t n, const uint32_t* bits, Counters* ctr,
+                           hipStream_t s);
+hipError_t launch_ms_output(int C, const uint32_t* D, const int32_t* perm, int64_t n, int k_real, uint32_t* out,
+                            hipStream_t s);
+
 // In-place exclusive scan of P[0..count) with P[count] = total; `blocks`
 // is scratch of scan_scratch_entries(count) int64 values.
 int64_t scan_scratch_entries(int64_t count);

@@ -30,7 +30,7 @@ OK, ERR_INVALID_ARG, ERR_BAD_GRAPH, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_UNSUPPORTED,
 ABI_VERSION = 1
 EXPORTS = ("vc_graph_create", "vc_graph_destroy", "vc_graph_footprint", "vc_run", "vc_params_default",
            "vc_status_string", "vc_last_error", "vc_abi_version", "vc_batch_create", "vc_batch_layout",
-           "vc_batch_run", "vc_batch_destroy")
+           "vc_batch_run", "vc_batch_destroy", "vc_run_multi_source")
 
 
 class GraphDesc(ctypes.Structure):
@@ -99,6 +99,9 @@ def load(path: str = LIB_PATH):
     lib.vc_batch_run.argtypes = [vp, ctypes.POINTER(Params), vp, vp, ctypes.POINTER(StatsStruct)]
     lib.vc_batch_destroy.restype = i32
     lib.vc_batch_destroy.argtypes = [vp]
+    lib.vc_run_multi_source.restype = i32
+    lib.vc_run_multi_source.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(Params), vp, vp,
+                                        ctypes.POINTER(StatsStruct)]
     if lib.vc_abi_version() != ABI_VERSION:
         raise RuntimeError(f"{path}: ABI version {lib.vc_abi_version()} != {ABI_VERSION}; rebuild the library")
     _lib = lib
@@ -214,6 +217,23 @@ class Graph:
         _check(load().vc_graph_footprint(self._h, _program(program), ctypes.byref(held), ctypes.byref(run)),
                "vc_graph_footprint")
         return held.value, run.value
+
+    def run_multi_source(self, sources, out=None, *, max_supersteps: int = 0, tile: int = 0, stream=None,
+                         stats: bool = False, timing: bool = False, capacity: int = 4096):
+        """vc_run_multi_source: distances from every source, as an (N, k) int32-stored uint32 tensor."""
+        import torch
+        src = np.ascontiguousarray(np.asarray(sources, dtype=np.uint32))
+        k = int(src.size)
+        if out is None:
+            out = torch.empty((self.n, k), dtype=torch.int32, device=self.device)
+        if not out.is_cuda or not out.is_contiguous() or out.numel() != self.n * k or out.element_size() != 4:
+            raise TypeError("out must be a contiguous CUDA tensor of N * k 4-byte elements")
+        p = _params(max_supersteps, 0.85, 0, "pull", tile, 0)
+        st, arrays = _stats_struct(stats or timing, timing, capacity)
+        rc = load().vc_run_multi_source(self._h, src.ctypes.data, k, ctypes.byref(p), out.data_ptr(),
+                                        _stream_handle(stream), ctypes.byref(st) if st is not None else None)
+        _check(rc, "vc_run_multi_source")
+        return out, _stats_result(st, arrays, capacity)
 
     def run(self, program, out=None, *, T: int = 10, damping: float = 0.85, source: int = 0,
             max_supersteps: int = 0, schedule="auto", tile: int = 0, options: int = 0, stream=None,
