@@ -104,7 +104,13 @@ enum {
 enum {
   VC_OPT_NO_HUB_AGGREGATION = 1u, /* disable workgroup-level pre-combination for hub targets */
   VC_OPT_NO_TEST_BEFORE_ATOMIC = 2u, /* min programs: skip the mailbox read before the atomic (for measurement) */
-  VC_OPT_F32_ACCUMULATE = 4u         /* PageRank / PPR: binary32 messages and float atomics */
+  VC_OPT_F32_ACCUMULATE = 4u,        /* PageRank / PPR: binary32 messages and float atomics */
+  VC_OPT_GRAPH_CAPTURE = 8u          /* run the superstep loop as a captured HIP graph: PageRank /
+                                        PPR as one graph of all T supersteps; CC / SSSP from
+                                        superstep 1 on as pull supersteps with termination decided
+                                        on the device (no per-superstep host round trip).  Graphs
+                                        are cached per graph object; per-superstep timings are not
+                                        recorded in this mode */
 };
 
 typedef struct vc_graph_s* vc_graph;
@@ -139,6 +145,8 @@ typedef struct {
   vc_schedule schedule;   /* VC_SCHED_AUTO picks per superstep from |F| and E_F */
   int32_t tile;           /* merge-path items per workgroup tile; 0 = library default */
   uint32_t options;       /* VC_OPT_* */
+  float pull_fraction;    /* CC / SSSP with VC_SCHED_AUTO: pull a superstep once its frontier's
+                             out-edges reach this fraction of all edges; 0 = library default (0.1) */
 } vc_params;
 
 /* Per-run statistics.  The caller owns every array (host memory) and sets
@@ -257,6 +265,18 @@ vc_status vc_batch_layout(vc_batch b, int64_t* vertex_base);
 vc_status vc_batch_run(vc_batch b, const vc_params* params, uint32_t* out, hipStream_t stream, vc_stats* stats);
 
 vc_status vc_batch_destroy(vc_batch b);
+
+/* Autotuner for a batch: like vc_graph_autotune, over vc_batch_run. */
+vc_status vc_batch_autotune(vc_batch b, const vc_params* base, hipStream_t stream, vc_params* best);
+
+/* Autotuner: times `program` on this graph under candidate work distributions
+ * (schedule, merge-path tile, pull threshold, captured loop), keeps the
+ * fastest as the graph's setting for that program (used by later runs with
+ * VC_SCHED_AUTO, tile 0 and pull_fraction 0) and returns it in *best (host).
+ * base (host, may be NULL) supplies T, damping and source.  Runs the program
+ * several times on `stream`.  Errors as vc_run. */
+vc_status vc_graph_autotune(vc_graph g, vc_program program, const vc_params* base, hipStream_t stream,
+                            vc_params* best);
 
 /* Fills *p with the defaults used when vc_run receives NULL params. */
 void vc_params_default(vc_params* p);

@@ -96,6 +96,17 @@ struct vc_graph_s {
   bool csc_ready = false;
   int64_t csc_tile = 0, csc_ntiles = 0;
   DevBuf ms_d, ms_mb, ms_a0, ms_a1, ms_src;  // many-source SSSP: distances, mailboxes, lane masks
+  // captured superstep loops (HIP graphs), replayed on the caller's stream
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t min_exec[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  int64_t min_exec_tile[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  hipGraphExec_t pr_exec = nullptr;
+  std::string pr_exec_key;
+  DevBuf loop_state, loop_steps;
+  vc::LoopState* host_loop = nullptr;  // pinned
+  // autotuned settings per program (used by VC_SCHED_AUTO runs with tile 0)
+  bool tuned[4] = {false, false, false, false};
+  vc_params tuned_params[4];
   DevBuf counters;
   size_t max_lds = 65536;            // dynamic LDS limit per workgroup on the graph's device
   vc::Counters* host_ctr = nullptr;  // pinned
@@ -120,6 +131,11 @@ hipError_t ensure_events(vc_graph g, size_t count) {
     g->events.push_back(e);
   }
   return hipSuccess;
+}
+
+hipError_t ensure_capture_stream(vc_graph g) {
+  if (g->cap_stream) return hipSuccess;
+  return hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking);
 }
 
 // Statistics recorder; tolerates a NULL vc_stats.
@@ -319,6 +335,57 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
     }
     if (st != VC_OK) return st;
   }
+  if (p.options & VC_OPT_GRAPH_CAPTURE) {
+    // the whole loop as one captured HIP graph; ranks land in the staging
+    // buffer (fixed address) and are copied / un-permuted afterwards
+    float* stage = static_cast<float*>(contrib);
+    char keybuf[160];
+    std::snprintf(keybuf, sizeof keybuf, "%d/%lld/%lld/%.17g/%d/%lld", (int)fx, (long long)T, (long long)source, d,
+                  sched, (long long)tile);
+    if (g->pr_exec && g->pr_exec_key != keybuf) {
+      VC_TRY(hipGraphExecDestroy(g->pr_exec));
+      g->pr_exec = nullptr;
+    }
+    if (!g->pr_exec) {
+      VC_TRY(ensure_capture_stream(g));
+      hipStream_t cs = g->cap_stream;
+      VC_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      hipError_t e = vc::launch_pr_init(fx, g->off, g->off64, n, r0, source, contrib, mb, nullptr, cs);
+      for (int64_t step = 0; step < T && e == hipSuccess; ++step) {
+        if (g->m > 0) {
+          if (sched == VC_SCHED_PULL)
+            e = vc::launch_pr_pull(fx, g->csc_off.as<int64_t>(), g->in_src, n, g->m, g->csc_tiles.as<int32_t>(),
+                                   g->csc_tile, g->csc_ntiles, contrib, mb, cs);
+          else if (sched == VC_SCHED_EDGE)
+            e = vc::launch_pr_scatter_mp(fx, g->off, g->off64, g->dst, n, g->m, g->dense_tiles.as<int32_t>(), tile,
+                                         g->dense_ntiles, contrib, mb, cs);
+          else
+            e = vc::launch_pr_scatter_vertex(fx, g->off, g->off64, g->dst, n, contrib, mb, cs);
+        }
+        if (e == hipSuccess)
+          e = vc::launch_pr_apply(fx, g->off, g->off64, n, teleport, d, source, mb, contrib, stage, step + 1 == T, cs);
+      }
+      hipGraph_t graph = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+      if (e != hipSuccess) return hip_fail(e, "capture PageRank");
+      if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+      const hipError_t e3 = hipGraphInstantiate(&g->pr_exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e3 != hipSuccess) return hip_fail(e3, "hipGraphInstantiate");
+      g->pr_exec_key = keybuf;
+    }
+    VC_TRY(hipGraphLaunch(g->pr_exec, s));
+    for (int64_t step = 0; step < T; ++step) rec.step(step, n, g->m, sched);
+    rec.step(T, 0, 0, 0);
+    if (g->relabeled)
+      VC_TRY(vc::launch_unpermute(reinterpret_cast<const uint32_t*>(stage), 1, g->perm.as<int32_t>(), n,
+                                  reinterpret_cast<uint32_t*>(out), s));
+    else
+      VC_TRY(hipMemcpyAsync(out, stage, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+    VC_TRY(hipStreamSynchronize(s));
+    *supersteps = (int32_t)(T + 1);
+    return VC_OK;
+  }
   if (rec.timed) VC_TRY(ensure_events(g, (size_t)(3 * T)));
   VC_TRY(vc::launch_pr_init(fx, g->off, g->off64, n, r0, source, contrib, mb, nullptr, s));
   for (int64_t step = 0; step < T; ++step) {
@@ -359,13 +426,85 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
 // Fraction of the edges above which a CC / SSSP superstep is pulled: the
 // pull form streams every in-edge, the push form only the frontier's
 // out-edges, so pull pays off once the frontier carries a large share of them.
-double pull_threshold() {
+double pull_threshold(const vc_params& p) {
+  if (p.pull_fraction > 0.0f) return (double)p.pull_fraction;
   static const double v = [] {
     const char* e = std::getenv("VC_PULL_FRACTION");
     double x = e ? std::atof(e) : 0.1;
     return x > 0 ? x : 0.1;
   }();
   return v;
+}
+
+constexpr int64_t kMaxRecordedSteps = 1 << 16;
+
+// Runs supersteps `step`.. of a CC / SSSP program as a captured HIP graph of
+// two pull supersteps (one per bitmap parity), replayed until the step-end
+// kernel reports quiescence or the cap; one 32-byte read per replay.
+vc_status run_min_device_loop(vc_graph g, int kind, int64_t tile, int cur, int64_t step, int64_t cap, uint2* vm,
+                              uint32_t* bits[2], int32_t* fq, int64_t* P, vc::Counters* ctr, hipStream_t s,
+                              Recorder& rec, int32_t* supersteps, bool* capped) {
+  const int64_t n = g->n, m = g->m;
+  vc_status st = ensure_csc(g, s);
+  if (st == VC_OK) st = csc_partition(g, vc::pull_tile(tile), s);
+  if (st != VC_OK) return st;
+  VC_TRY(g->loop_state.ensure(sizeof(vc::LoopState)));
+  VC_TRY(g->loop_steps.ensure((size_t)kMaxRecordedSteps * 16));
+  if (!g->host_loop) VC_TRY(hipHostMalloc((void**)&g->host_loop, sizeof(vc::LoopState), hipHostMallocDefault));
+  vc::LoopState* loop = g->loop_state.as<vc::LoopState>();
+  long long* steps = g->loop_steps.as<long long>();
+  hipGraphExec_t& exec = g->min_exec[kind][cur];
+  if (exec && g->min_exec_tile[kind][cur] != g->csc_tile) {
+    VC_TRY(hipGraphExecDestroy(exec));
+    exec = nullptr;
+  }
+  if (!exec) {
+    VC_TRY(ensure_capture_stream(g));
+    hipStream_t cs = g->cap_stream;
+    VC_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int half = 0; half < 2 && e == hipSuccess; ++half) {
+      const int a = half == 0 ? cur : 1 - cur;
+      e = vc::launch_min_pull(kind, g->csc_off.as<int64_t>(), g->in_src, g->in_w, n, m, g->csc_tiles.as<int32_t>(),
+                              g->csc_tile, g->csc_ntiles, vm, bits[1 - a], bits[a], loop, cs);
+      if (e == hipSuccess)
+        e = vc::launch_min_compact(g->off, g->off64, n, vm, bits[a], bits[1 - a], fq, P, ctr, false, loop, cs);
+      if (e == hipSuccess) e = vc::launch_loop_step(ctr, loop, steps, kMaxRecordedSteps, cs);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (e != hipSuccess) return hip_fail(e, "capture superstep");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+    const hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) return hip_fail(e3, "hipGraphInstantiate");
+    g->min_exec_tile[kind][cur] = g->csc_tile;
+  }
+  vc::LoopState init{0, step, cap, 0};
+  *g->host_loop = init;
+  VC_TRY(hipMemcpyAsync(loop, g->host_loop, sizeof init, hipMemcpyHostToDevice, s));
+  for (;;) {
+    VC_TRY(hipGraphLaunch(exec, s));
+    VC_TRY(hipMemcpyAsync(g->host_loop, loop, sizeof init, hipMemcpyDeviceToHost, s));
+    VC_TRY(hipStreamSynchronize(s));
+    if (g->host_loop->done) break;
+  }
+  const int64_t last = g->host_loop->step;
+  const int64_t first = step + 1;
+  const int64_t upto = last < kMaxRecordedSteps ? last : kMaxRecordedSteps - 1;
+  if (upto >= first) {
+    std::vector<long long> h((size_t)(2 * (upto - first + 1)));
+    VC_TRY(hipMemcpyAsync(h.data(), steps + 2 * first, h.size() * 8, hipMemcpyDeviceToHost, s));
+    VC_TRY(hipStreamSynchronize(s));
+    for (int64_t t = first; t <= upto; ++t) {
+      const long long f = h[2 * (t - first)], e = h[2 * (t - first) + 1];
+      if (g->host_loop->capped && t == last) break;
+      rec.step(t, f, e, (f > 0 && e > 0) ? VC_SCHED_PULL : 0);
+    }
+  }
+  *capped = g->host_loop->capped != 0;
+  *supersteps = (int32_t)(*capped ? last : last + 1);
+  return VC_OK;
 }
 
 // seed (device, internal vertex order, may be NULL): initial values of a
@@ -413,7 +552,7 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
     // the seeded senders become F_0: bitmap, broadcast list and counters as
     // if they had just improved
     VC_TRY(vc::launch_min_init_from(seed, n, vm, bits[1], s));
-    VC_TRY(vc::launch_min_compact(g->off, g->off64, n, vm, bits[1], bits[0], fq, P, ctr, true, s));
+    VC_TRY(vc::launch_min_compact(g->off, g->off64, n, vm, bits[1], bits[0], fq, P, ctr, true, nullptr, s));
     VC_TRY(hipMemcpyAsync(g->host_ctr, ctr, sizeof(vc::Counters), hipMemcpyDeviceToHost, s));
     VC_TRY(vc::launch_zero_counters(ctr, s));
     VC_TRY(hipStreamSynchronize(s));
@@ -447,15 +586,26 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
   const int64_t cap = p.max_supersteps > 0 ? (int64_t)p.max_supersteps : n + 1;
   vc_status status = VC_OK;
   int64_t step = 0;
+  const bool capture = (p.options & VC_OPT_GRAPH_CAPTURE) != 0;
   for (;;) {
     if (frontier == 0 || edges == 0) {
       rec.step(step, frontier, edges, 0);
       *supersteps = (int32_t)(step + 1);
       break;
     }
+    if (capture && step >= 1) {
+      // the rest runs on the device: pull every superstep, termination checked there
+      rec.step(step, frontier, edges, VC_SCHED_PULL);
+      bool capped = false;
+      vc_status st = run_min_device_loop(g, kind, tile, cur, step, cap, vm, bits, fq, P, ctr, s, rec, supersteps,
+                                         &capped);
+      if (st != VC_OK) return st;
+      if (capped) status = fail(VC_ERR_NOT_CONVERGED, "superstep cap reached before quiescence");
+      break;
+    }
     int sched = p.schedule;
     if (sched == VC_SCHED_AUTO) {
-      if ((double)edges >= pull_threshold() * (double)m)
+      if ((double)edges >= pull_threshold(p) * (double)m)
         sched = VC_SCHED_PULL;
       else
         sched = edges <= 256 ? VC_SCHED_VERTEX : VC_SCHED_EDGE;
@@ -470,7 +620,8 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
       if (st != VC_OK) return st;
       if (timed) VC_TRY(hipEventRecord(g->events[1], s));
       VC_TRY(vc::launch_min_pull(kind, g->csc_off.as<int64_t>(), g->in_src, g->in_w, n, m, g->csc_tiles.as<int32_t>(),
-                                 g->csc_tile, g->csc_ntiles, vm, dense ? nullptr : bits[1 - cur], improved, s));
+                                 g->csc_tile, g->csc_ntiles, vm, dense ? nullptr : bits[1 - cur], improved, nullptr,
+                                 s));
     } else if (sched == VC_SCHED_EDGE) {
       if (dense) {
         vc_status st = dense_partition(g, tile, s);
@@ -493,7 +644,7 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
                                            vm, improved, s));
     }
     if (timed) VC_TRY(hipEventRecord(g->events[2], s));
-    VC_TRY(vc::launch_min_compact(g->off, g->off64, n, vm, improved, bits[1 - cur], fq, P, ctr, false, s));
+    VC_TRY(vc::launch_min_compact(g->off, g->off64, n, vm, improved, bits[1 - cur], fq, P, ctr, false, nullptr, s));
     if (timed) VC_TRY(hipEventRecord(g->events[3], s));
     VC_TRY(hipMemcpyAsync(g->host_ctr, ctr, sizeof(vc::Counters), hipMemcpyDeviceToHost, s));
     VC_TRY(vc::launch_zero_counters(ctr, s));
@@ -525,10 +676,22 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
   return status;
 }
 
+// A run that leaves the distribution to the library (AUTO, tile 0, default
+// pull threshold) takes the graph's autotuned setting for the program.
+void apply_tuned(vc_graph g, vc_program prog, vc_params* p) {
+  if (!g->tuned[prog] || p->schedule != VC_SCHED_AUTO || p->tile != 0 || p->pull_fraction != 0.0f) return;
+  const vc_params& t = g->tuned_params[prog];
+  p->schedule = t.schedule;
+  p->tile = t.tile;
+  p->pull_fraction = t.pull_fraction;
+  p->options |= t.options & VC_OPT_GRAPH_CAPTURE;
+}
+
 bool valid_params(const vc_params& p, vc_program prog, int64_t n, std::string* why) {
   if (p.struct_size != sizeof(vc_params)) return *why = "vc_params.struct_size mismatch", false;
   if (p.schedule < VC_SCHED_AUTO || p.schedule > VC_SCHED_PULL) return *why = "bad schedule", false;
   if (p.tile < 0) return *why = "negative tile", false;
+  if (!(p.pull_fraction >= 0.0f)) return *why = "negative pull_fraction", false;
   if (prog == VC_PAGERANK || prog == VC_PPR) {
     if (p.max_supersteps < 0) return *why = "PageRank needs T >= 0", false;
     if (!(p.damping >= 0.0 && p.damping <= 1.0)) return *why = "damping outside [0, 1]", false;
@@ -570,6 +733,7 @@ void vc_params_default(vc_params* p) {
   p->schedule = VC_SCHED_AUTO;
   p->tile = 0;
   p->options = 0;
+  p->pull_fraction = 0.0f;
 }
 
 vc_status vc_graph_create(const vc_graph_desc* d, hipStream_t stream, vc_graph* out) {
@@ -663,7 +827,15 @@ vc_status vc_graph_destroy(vc_graph g) {
                     &g->fq, &g->prefix, &g->scan_blocks, &g->list_tiles, &g->dense_tiles, &g->csc_off, &g->csc_src,
                     &g->csc_w, &g->csc_tiles, &g->ms_d, &g->ms_mb, &g->ms_a0, &g->ms_a1, &g->ms_src, &g->counters})
     b->release();
+  g->loop_state.release();
+  g->loop_steps.release();
   if (g->host_ctr) (void)hipHostFree(g->host_ctr);
+  if (g->host_loop) (void)hipHostFree(g->host_loop);
+  for (auto& row : g->min_exec)
+    for (hipGraphExec_t& e : row)
+      if (e) (void)hipGraphExecDestroy(e);
+  if (g->pr_exec) (void)hipGraphExecDestroy(g->pr_exec);
+  if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
   for (hipEvent_t e : g->events) (void)hipEventDestroy(e);
   (void)hipSetDevice(prev);
   delete g;
@@ -712,6 +884,7 @@ vc_status vc_run(vc_graph g, vc_program program, const vc_params* params, void* 
   }
   std::string why;
   if (!valid_params(p, program, g->n, &why)) return fail(VC_ERR_INVALID_ARG, why);
+  apply_tuned(g, program, &p);
   if (stats) {
     if (stats->struct_size != sizeof(vc_stats)) return fail(VC_ERR_INVALID_ARG, "vc_stats.struct_size mismatch");
     if (stats->capacity < 0) return fail(VC_ERR_INVALID_ARG, "negative stats capacity");
@@ -845,6 +1018,7 @@ vc_status vc_batch_run(vc_batch b, const vc_params* params, uint32_t* out, hipSt
   p.source = 0;
   std::string why;
   if (!valid_params(p, VC_SSSP, b->g->n, &why)) return fail(VC_ERR_INVALID_ARG, why);
+  apply_tuned(b->g, VC_SSSP, &p);
   if (stats) {
     if (stats->struct_size != sizeof(vc_stats) || stats->capacity < 0)
       return fail(VC_ERR_INVALID_ARG, "bad vc_stats");
@@ -980,6 +1154,107 @@ vc_status vc_run_multi_source(vc_graph g, const uint32_t* sources, int32_t k, co
     stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   return status;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Candidate distributions for a program: PageRank / PPR vary schedule, tile
+// and capture; CC / SSSP vary the pull threshold, tile and capture.
+std::vector<vc_params> tune_candidates(vc_program program, const vc_params& base) {
+  std::vector<vc_params> out;
+  const int32_t tiles[] = {1024, 2048, 4096};
+  for (uint32_t capture : {0u, (uint32_t)VC_OPT_GRAPH_CAPTURE})
+    for (int32_t tile : tiles) {
+      if (program == VC_PAGERANK || program == VC_PPR) {
+        for (vc_schedule sc : {VC_SCHED_PULL, VC_SCHED_EDGE}) {
+          vc_params p = base;
+          p.schedule = sc;
+          p.tile = tile;
+          p.options = (base.options & ~(uint32_t)VC_OPT_GRAPH_CAPTURE) | capture;
+          out.push_back(p);
+        }
+      } else {
+        for (float frac : {0.03f, 0.1f, 0.3f, 2.0f}) {
+          vc_params p = base;
+          p.schedule = VC_SCHED_AUTO;
+          p.tile = tile;
+          p.pull_fraction = frac;
+          p.options = (base.options & ~(uint32_t)VC_OPT_GRAPH_CAPTURE) | capture;
+          out.push_back(p);
+        }
+      }
+    }
+  return out;
+}
+
+template <class Run>
+vc_status pick_fastest(const std::vector<vc_params>& cands, Run run, vc_params* best) {
+  double best_ms = 1e300;
+  for (const vc_params& c : cands) {
+    vc_status st = run(c);  // warm-up: workspace, transpose, captured graph
+    if (st != VC_OK) return st;
+    const auto t0 = std::chrono::steady_clock::now();
+    st = run(c);
+    if (st != VC_OK) return st;
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (ms < best_ms) {
+      best_ms = ms;
+      *best = c;
+    }
+  }
+  return VC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vc_status vc_graph_autotune(vc_graph g, vc_program program, const vc_params* base, hipStream_t stream,
+                            vc_params* best) {
+  if (!g || !best) return fail(VC_ERR_INVALID_ARG, "null argument");
+  if (program < VC_PAGERANK || program > VC_PPR) return fail(VC_ERR_INVALID_ARG, "bad program");
+  vc_params b;
+  if (base)
+    b = *base;
+  else
+    vc_params_default(&b);
+  std::string why;
+  if (!valid_params(b, program, g->n, &why)) return fail(VC_ERR_INVALID_ARG, why);
+  DevBuf out;
+  VC_TRY(out.ensure((size_t)g->n * 4));
+  vc_params pick = b;
+  vc_status st = pick_fastest(tune_candidates(program, b),
+                              [&](const vc_params& c) { return vc_run(g, program, &c, out.p, stream, nullptr); }, &pick);
+  if (st != VC_OK) return st;
+  g->tuned[program] = true;
+  g->tuned_params[program] = pick;
+  *best = pick;
+  return VC_OK;
+}
+
+vc_status vc_batch_autotune(vc_batch b, const vc_params* base, hipStream_t stream, vc_params* best) {
+  if (!b || !best) return fail(VC_ERR_INVALID_ARG, "null argument");
+  vc_params p;
+  if (base)
+    p = *base;
+  else
+    vc_params_default(&p);
+  p.source = 0;
+  std::string why;
+  if (!valid_params(p, VC_SSSP, b->g->n, &why)) return fail(VC_ERR_INVALID_ARG, why);
+  DevBuf out;
+  VC_TRY(out.ensure((size_t)b->g->n * 4));
+  vc_params pick = p;
+  vc_status st = pick_fastest(
+      tune_candidates(VC_SSSP, p),
+      [&](const vc_params& c) { return vc_batch_run(b, &c, out.as<uint32_t>(), stream, nullptr); }, &pick);
+  if (st != VC_OK) return st;
+  b->g->tuned[VC_SSSP] = true;
+  b->g->tuned_params[VC_SSSP] = pick;
+  *best = pick;
+  return VC_OK;
 }
 
 }  // extern "C"

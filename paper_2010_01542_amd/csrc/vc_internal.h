@@ -24,6 +24,16 @@ struct Counters {
 
 enum MinKind { kCC = 0, kSsspUnit = 1, kSsspWeighted = 2 };
 
+// State of a device-driven superstep loop (captured HIP graph): kernels of a
+// superstep return at once when `done` is set; the step-end kernel records
+// |F_s|, E_s and sets `done` at quiescence or at the cap.
+struct LoopState {
+  long long done;
+  long long step;   // index of the superstep whose frontier was computed last
+  long long cap;    // superstep cap
+  long long capped;
+};
+
 // Bytes of dynamic LDS a merge-path scatter tile of `tile` items needs.
 size_t pr_mp_lds_bytes(int64_t tile, bool off64);
 size_t min_mp_lds_bytes(int64_t tile, bool list);
@@ -69,7 +79,10 @@ hipError_t launch_min_scatter_mp(int kind, bool list, bool tba, const void* off,
                                  const int32_t* tile_v, int64_t tile, int64_t ntiles, uint2* vm, uint32_t* bitmap,
                                  hipStream_t s);
 hipError_t launch_min_compact(const void* off, bool off64, int64_t n, uint2* vm, const uint32_t* bitmap,
-                              uint32_t* stale, int32_t* fq, int64_t* P, Counters* ctr, bool seed, hipStream_t s);
+                              uint32_t* stale, int32_t* fq, int64_t* P, Counters* ctr, bool seed,
+                              const LoopState* loop, hipStream_t s);
+// steps[2s], steps[2s+1] = |F_s|, E_s for s < max_recorded.
+hipError_t launch_loop_step(Counters* ctr, LoopState* loop, long long* steps, int64_t max_recorded, hipStream_t s);
 // Seeded start: vm = (init, neutral); bitmap word = vertices with init < 0xFFFFFFFF.
 hipError_t launch_min_init_from(const uint32_t* init, int64_t n, uint2* vm, uint32_t* bitmap, hipStream_t s);
 
@@ -103,7 +116,7 @@ hipError_t launch_pr_pull(bool fx, const int64_t* in_off, const int32_t* in_src,
 // active = NULL: every vertex broadcast this superstep.
 hipError_t launch_min_pull(int kind, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w, int64_t n,
                            int64_t m, const int32_t* tile_v, int64_t tile, int64_t ntiles, uint2* vm,
-                           const uint32_t* active, uint32_t* improved, hipStream_t s);
+                           const uint32_t* active, uint32_t* improved, const LoopState* loop, hipStream_t s);
 
 // ---------------------------------------------------------------- relabelling
 int relabel_classes();

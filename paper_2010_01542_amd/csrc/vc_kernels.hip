@@ -311,7 +311,9 @@ template <class OffT>
 __global__ __launch_bounds__(kWG) void k_min_compact(const OffT* __restrict__ off, int64_t n, uint2* __restrict__ vm,
                                                      const uint32_t* __restrict__ bitmap, uint32_t* __restrict__ stale,
                                                      int64_t nwords, int32_t* __restrict__ fq,
-                                                     int64_t* __restrict__ P, Counters* __restrict__ ctr, int seed) {
+                                                     int64_t* __restrict__ P, Counters* __restrict__ ctr, int seed,
+                                                     const LoopState* loop) {
+  if (loop && loop->done) return;  // device-driven loop already quiescent
   const int64_t wi = gid();
   uint32_t word = 0;
   if (wi < nwords) {
@@ -683,14 +685,43 @@ hipError_t launch_min_scatter_mp(int kind, bool list, bool tba, const void* off,
 }
 
 hipError_t launch_min_compact(const void* off, bool off64, int64_t n, uint2* vm, const uint32_t* bitmap,
-                              uint32_t* stale, int32_t* fq, int64_t* P, Counters* ctr, bool seed, hipStream_t s) {
+                              uint32_t* stale, int32_t* fq, int64_t* P, Counters* ctr, bool seed,
+                              const LoopState* loop, hipStream_t s) {
   const int64_t nwords = (n + 31) / 32;
   if (off64)
     hipLaunchKernelGGL(k_min_compact<int64_t>, dim3(grid_for(nwords)), dim3(kWG), 0, s, (const int64_t*)off, n, vm,
-                       bitmap, stale, nwords, fq, P, ctr, (int)seed);
+                       bitmap, stale, nwords, fq, P, ctr, (int)seed, loop);
   else
     hipLaunchKernelGGL(k_min_compact<int32_t>, dim3(grid_for(nwords)), dim3(kWG), 0, s, (const int32_t*)off, n, vm,
-                       bitmap, stale, nwords, fq, P, ctr, (int)seed);
+                       bitmap, stale, nwords, fq, P, ctr, (int)seed, loop);
+  return hipGetLastError();
+}
+
+// End of a device-driven superstep: record |F|, E of the next superstep,
+// decide termination, reset the counters.
+__global__ void k_loop_step(Counters* __restrict__ ctr, LoopState* __restrict__ loop, long long* __restrict__ steps,
+                            int64_t max_recorded) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || loop->done) return;
+  const long long s = loop->step + 1;
+  const long long f = (long long)ctr->active, e = (long long)ctr->edges;
+  if (s < max_recorded) {
+    steps[2 * s] = f;
+    steps[2 * s + 1] = e;
+  }
+  loop->step = s;
+  ctr->active = 0;
+  ctr->listed = 0;
+  ctr->edges = 0;
+  if (f == 0 || e == 0) {
+    loop->done = 1;
+  } else if (s >= loop->cap) {
+    loop->done = 1;
+    loop->capped = 1;
+  }
+}
+
+hipError_t launch_loop_step(Counters* ctr, LoopState* loop, long long* steps, int64_t max_recorded, hipStream_t s) {
+  hipLaunchKernelGGL(k_loop_step, dim3(1), dim3(64), 0, s, ctr, loop, steps, max_recorded);
   return hipGetLastError();
 }
 

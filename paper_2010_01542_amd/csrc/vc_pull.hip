@@ -210,9 +210,10 @@ __global__ __launch_bounds__(kWG) void k_min_pull(const int64_t* __restrict__ in
                                                   const uint32_t* __restrict__ in_w, int64_t n, int64_t m,
                                                   const int32_t* __restrict__ tile_v, uint2* __restrict__ vm,
                                                   const uint32_t* __restrict__ active,
-                                                  uint32_t* __restrict__ improved) {
+                                                  uint32_t* __restrict__ improved, const LoopState* loop) {
   constexpr int64_t tile = (int64_t)kWG * VT;
   extern __shared__ __align__(16) unsigned char smem[];
+  if (loop && loop->done) return;  // device-driven loop already quiescent
   Tile tl;
   if (!tile_bounds(tile_v, tile, n, m, &tl)) return;
   uint32_t* s_min = reinterpret_cast<uint32_t*>(smem);                          // tile + 1
@@ -346,26 +347,26 @@ void pr_pull_launch(const int64_t* in_off, const int32_t* in_src, int64_t n, int
 template <int KIND, int VT>
 void min_pull_launch(bool check, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w, int64_t n,
                      int64_t m, const int32_t* tile_v, int64_t ntiles, uint2* vm, const uint32_t* active,
-                     uint32_t* improved, hipStream_t s) {
+                     uint32_t* improved, const LoopState* loop, hipStream_t s) {
   const int64_t tile = (int64_t)kWG * VT;
   const size_t lds = align16((size_t)(tile + 1) * 4) + (size_t)(tile + 2) * 8;
   if (check)
     hipLaunchKernelGGL((k_min_pull<KIND, true, VT>), dim3((unsigned)ntiles), dim3(kWG), lds, s, in_off, in_src, in_w,
-                       n, m, tile_v, vm, active, improved);
+                       n, m, tile_v, vm, active, improved, loop);
   else
     hipLaunchKernelGGL((k_min_pull<KIND, false, VT>), dim3((unsigned)ntiles), dim3(kWG), lds, s, in_off, in_src,
-                       in_w, n, m, tile_v, vm, active, improved);
+                       in_w, n, m, tile_v, vm, active, improved, loop);
 }
 template <int KIND>
 void min_pull_vt(int64_t tile, bool check, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w,
                  int64_t n, int64_t m, const int32_t* tile_v, int64_t ntiles, uint2* vm, const uint32_t* active,
-                 uint32_t* improved, hipStream_t s) {
+                 uint32_t* improved, const LoopState* loop, hipStream_t s) {
   if (tile == kWG * 4)
-    min_pull_launch<KIND, 4>(check, in_off, in_src, in_w, n, m, tile_v, ntiles, vm, active, improved, s);
+    min_pull_launch<KIND, 4>(check, in_off, in_src, in_w, n, m, tile_v, ntiles, vm, active, improved, loop, s);
   else if (tile == kWG * 8)
-    min_pull_launch<KIND, 8>(check, in_off, in_src, in_w, n, m, tile_v, ntiles, vm, active, improved, s);
+    min_pull_launch<KIND, 8>(check, in_off, in_src, in_w, n, m, tile_v, ntiles, vm, active, improved, loop, s);
   else
-    min_pull_launch<KIND, 16>(check, in_off, in_src, in_w, n, m, tile_v, ntiles, vm, active, improved, s);
+    min_pull_launch<KIND, 16>(check, in_off, in_src, in_w, n, m, tile_v, ntiles, vm, active, improved, loop, s);
 }
 }  // namespace
 
@@ -388,16 +389,17 @@ hipError_t launch_pr_pull(bool fx, const int64_t* in_off, const int32_t* in_src,
 
 hipError_t launch_min_pull(int kind, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w, int64_t n,
                            int64_t m, const int32_t* tile_v, int64_t tile, int64_t ntiles, uint2* vm,
-                           const uint32_t* active, uint32_t* improved, hipStream_t s) {
+                           const uint32_t* active, uint32_t* improved, const LoopState* loop, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (tile != pull_tile(tile)) return hipErrorInvalidValue;
   const bool check = active != nullptr;
   if (kind == kCC)
-    min_pull_vt<kCC>(tile, check, in_off, in_src, in_w, n, m, tile_v, ntiles, vm, active, improved, s);
+    min_pull_vt<kCC>(tile, check, in_off, in_src, in_w, n, m, tile_v, ntiles, vm, active, improved, loop, s);
   else if (kind == kSsspUnit)
-    min_pull_vt<kSsspUnit>(tile, check, in_off, in_src, in_w, n, m, tile_v, ntiles, vm, active, improved, s);
+    min_pull_vt<kSsspUnit>(tile, check, in_off, in_src, in_w, n, m, tile_v, ntiles, vm, active, improved, loop, s);
   else
-    min_pull_vt<kSsspWeighted>(tile, check, in_off, in_src, in_w, n, m, tile_v, ntiles, vm, active, improved, s);
+    min_pull_vt<kSsspWeighted>(tile, check, in_off, in_src, in_w, n, m, tile_v, ntiles, vm, active, improved, loop,
+                               s);
   return hipGetLastError();
 }
 

@@ -23,14 +23,14 @@ SCHED_AUTO, SCHED_VERTEX, SCHED_EDGE, SCHED_PULL = 0, 1, 2, 3
 SCHEDULES = {"auto": SCHED_AUTO, "vertex": SCHED_VERTEX, "edge": SCHED_EDGE, "pull": SCHED_PULL}
 IDX_I32, IDX_I64 = 0, 1
 GRAPH_BORROW, GRAPH_VALIDATE, GRAPH_SYMMETRIC, GRAPH_NO_RELABEL = 1, 2, 4, 8
-OPT_NO_HUB_AGGREGATION, OPT_NO_TEST_BEFORE_ATOMIC, OPT_F32_ACCUMULATE = 1, 2, 4
+OPT_NO_HUB_AGGREGATION, OPT_NO_TEST_BEFORE_ATOMIC, OPT_F32_ACCUMULATE, OPT_GRAPH_CAPTURE = 1, 2, 4, 8
 UNREACHED = 0xFFFFFFFF
 
 OK, ERR_INVALID_ARG, ERR_BAD_GRAPH, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_UNSUPPORTED, ERR_NOT_CONVERGED = range(7)
 ABI_VERSION = 1
 EXPORTS = ("vc_graph_create", "vc_graph_destroy", "vc_graph_footprint", "vc_run", "vc_params_default",
            "vc_status_string", "vc_last_error", "vc_abi_version", "vc_batch_create", "vc_batch_layout",
-           "vc_batch_run", "vc_batch_destroy", "vc_run_multi_source")
+           "vc_batch_run", "vc_batch_destroy", "vc_run_multi_source", "vc_graph_autotune", "vc_batch_autotune")
 
 
 class GraphDesc(ctypes.Structure):
@@ -42,7 +42,7 @@ class GraphDesc(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("max_supersteps", ctypes.c_int32), ("damping", ctypes.c_double),
                 ("source", ctypes.c_uint32), ("schedule", ctypes.c_int), ("tile", ctypes.c_int32),
-                ("options", ctypes.c_uint32)]
+                ("options", ctypes.c_uint32), ("pull_fraction", ctypes.c_float)]
 
 
 class StatsStruct(ctypes.Structure):
@@ -99,6 +99,10 @@ def load(path: str = LIB_PATH):
     lib.vc_batch_run.argtypes = [vp, ctypes.POINTER(Params), vp, vp, ctypes.POINTER(StatsStruct)]
     lib.vc_batch_destroy.restype = i32
     lib.vc_batch_destroy.argtypes = [vp]
+    lib.vc_graph_autotune.restype = i32
+    lib.vc_graph_autotune.argtypes = [vp, i32, ctypes.POINTER(Params), vp, ctypes.POINTER(Params)]
+    lib.vc_batch_autotune.restype = i32
+    lib.vc_batch_autotune.argtypes = [vp, ctypes.POINTER(Params), vp, ctypes.POINTER(Params)]
     lib.vc_run_multi_source.restype = i32
     lib.vc_run_multi_source.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(Params), vp, vp,
                                         ctypes.POINTER(StatsStruct)]
@@ -218,6 +222,15 @@ class Graph:
                "vc_graph_footprint")
         return held.value, run.value
 
+    def autotune(self, program, *, T: int = 10, damping: float = 0.85, source: int = 0, stream=None) -> dict:
+        """vc_graph_autotune: picks and keeps the fastest distribution for `program`."""
+        prog = _program(program)
+        base = _params(T if prog in (PAGERANK, PPR) else 0, damping, source, "auto", 0, 0)
+        best = Params()
+        _check(load().vc_graph_autotune(self._h, prog, ctypes.byref(base), _stream_handle(stream), ctypes.byref(best)),
+               "vc_graph_autotune")
+        return _params_dict(best)
+
     def run_multi_source(self, sources, out=None, *, max_supersteps: int = 0, tile: int = 0, stream=None,
                          stats: bool = False, timing: bool = False, capacity: int = 4096):
         """vc_run_multi_source: distances from every source, as an (N, k) int32-stored uint32 tensor."""
@@ -236,8 +249,8 @@ class Graph:
         return out, _stats_result(st, arrays, capacity)
 
     def run(self, program, out=None, *, T: int = 10, damping: float = 0.85, source: int = 0,
-            max_supersteps: int = 0, schedule="auto", tile: int = 0, options: int = 0, stream=None,
-            stats: bool = False, timing: bool = False, capacity: int = 4096):
+            max_supersteps: int = 0, schedule="auto", tile: int = 0, options: int = 0, pull_fraction: float = 0.0,
+            stream=None, stats: bool = False, timing: bool = False, capacity: int = 4096):
         """vc_run: returns (out, Stats | None).  out: float32 ranks or int32-stored uint32 labels."""
         import torch
         lib = load()
@@ -247,7 +260,7 @@ class Graph:
             out = torch.empty(self.n, dtype=torch.float32 if rank else torch.int32, device=self.device)
         if not out.is_cuda or not out.is_contiguous() or out.numel() != self.n or out.element_size() != 4:
             raise TypeError("out must be a contiguous CUDA tensor of N 4-byte elements")
-        p = _params(T if rank else max_supersteps, damping, source, schedule, tile, options)
+        p = _params(T if rank else max_supersteps, damping, source, schedule, tile, options, pull_fraction)
         st, arrays = _stats_struct(stats or timing, timing, capacity)
         rc = lib.vc_run(self._h, prog, ctypes.byref(p), out.data_ptr(), _stream_handle(stream),
                         ctypes.byref(st) if st is not None else None)
@@ -255,7 +268,7 @@ class Graph:
         return out, _stats_result(st, arrays, capacity)
 
 
-def _params(steps, damping, source, schedule, tile, options) -> Params:
+def _params(steps, damping, source, schedule, tile, options, pull_fraction=0.0) -> Params:
     p = Params()
     load().vc_params_default(ctypes.byref(p))
     p.max_supersteps = int(steps)
@@ -264,7 +277,14 @@ def _params(steps, damping, source, schedule, tile, options) -> Params:
     p.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
     p.tile = int(tile)
     p.options = int(options)
+    p.pull_fraction = float(pull_fraction)
     return p
+
+
+def _params_dict(p: Params) -> dict:
+    inv = {v: k for k, v in SCHEDULES.items()}
+    return {"schedule": inv.get(p.schedule, p.schedule), "tile": p.tile, "pull_fraction": round(p.pull_fraction, 4),
+            "capture": bool(p.options & OPT_GRAPH_CAPTURE)}
 
 
 def _stats_struct(want: bool, timing: bool, capacity: int):
@@ -346,14 +366,23 @@ class Batch:
         except Exception:
             pass
 
+    def autotune(self, stream=None) -> dict:
+        """vc_batch_autotune: picks and keeps the fastest distribution for the batch."""
+        base = _params(0, 0.85, 0, "auto", 0, 0)
+        best = Params()
+        _check(load().vc_batch_autotune(self._h, ctypes.byref(base), _stream_handle(stream), ctypes.byref(best)),
+               "vc_batch_autotune")
+        return _params_dict(best)
+
     def run(self, out=None, *, max_supersteps: int = 0, schedule="auto", tile: int = 0, options: int = 0,
-            stream=None, stats: bool = False, timing: bool = False, capacity: int = 4096):
+            pull_fraction: float = 0.0, stream=None, stats: bool = False, timing: bool = False,
+            capacity: int = 4096):
         import torch
         if out is None:
             out = torch.empty(self.n, dtype=torch.int32, device=self.device)
         if not out.is_cuda or not out.is_contiguous() or out.numel() != self.n or out.element_size() != 4:
             raise TypeError("out must be a contiguous CUDA tensor of sum(N_i) 4-byte elements")
-        p = _params(max_supersteps, 0.85, 0, schedule, tile, options)
+        p = _params(max_supersteps, 0.85, 0, schedule, tile, options, pull_fraction)
         st, arrays = _stats_struct(stats or timing, timing, capacity)
         rc = load().vc_batch_run(self._h, ctypes.byref(p), out.data_ptr(), _stream_handle(stream),
                                  ctypes.byref(st) if st is not None else None)
