@@ -278,6 +278,106 @@ vc_status vc_batch_autotune(vc_batch b, const vc_params* base, hipStream_t strea
 vc_status vc_graph_autotune(vc_graph g, vc_program program, const vc_params* base, hipStream_t stream,
                             vc_params* best);
 
+/* ---------------------------------------------------------------- serving
+ * A request server over resident graphs.  Requests are independent program
+ * runs (paper, Section I) that arrive over time and complete out of order.
+ *
+ * Min programs (CC, SSSP) on a graph registered with lanes > 0 are served by
+ * continuous batching: the graph keeps an N x lanes value / mailbox table
+ * and one thread runs its superstep loop with every occupied lane side by
+ * side, in the pull form of the min combiner (paper, Sections III and
+ * VI-C).  A lane whose program has quiesced (no active vertex with an
+ * out-edge) is retired after the superstep that found it so, its column is
+ * copied to the request's `out`, and a waiting request is seeded into it
+ * before the next superstep.  A lane's values, superstep count and status
+ * are exactly those of the same request run alone with vc_run.
+ *
+ * Every other request (PageRank, PPR, and min programs on graphs without
+ * lanes) runs on one of `workers` threads, each with its own stream and a
+ * private workspace that shares the graph's read-only arrays.  A worker
+ * takes the oldest waiting request once its workspace fits the HBM budget
+ * (admission by footprint), first dropping workspaces it keeps for other
+ * graphs.  A request that cannot fit even with every workspace dropped
+ * completes with VC_ERR_OUT_OF_MEMORY without running.
+ *
+ * Threading: every vc_server_* call may be made from any host thread.  The
+ * caller must not run, autotune or destroy a registered graph while the
+ * server exists. */
+typedef struct vc_server_s* vc_server;
+
+typedef struct {
+  uint32_t struct_size; /* sizeof(vc_server_config) */
+  int32_t workers;      /* threads for the single-run path, 1..64 (0 = 2) */
+  uint64_t hbm_budget;  /* device bytes for lane tables and workspaces (0 = 80% of
+                           the device memory free at creation) */
+} vc_server_config;
+
+typedef struct {
+  uint32_t struct_size; /* sizeof(vc_request) */
+  int32_t graph;        /* id from vc_server_add_graph */
+  vc_program program;
+  int32_t reserved;
+  vc_params params;     /* as vc_run; lanes honour source and max_supersteps only */
+  void* out;            /* device, N x 4 bytes, caller-owned, untouched by the
+                           caller until the request completes */
+  uint64_t tag;         /* returned in the completion */
+} vc_request;
+
+typedef struct {
+  uint64_t ticket;      /* from vc_server_submit */
+  uint64_t tag;
+  vc_status status;     /* as vc_run would return for the request alone */
+  int32_t supersteps;
+  int32_t lane;         /* lane that served it, or -1 (worker) */
+  int32_t reserved;
+  double queue_ms;      /* submit -> start (lane seeded or worker began) */
+  double service_ms;    /* start -> `out` complete */
+  char message[120];    /* error text when status != VC_OK */
+} vc_completion;
+
+typedef struct {
+  uint32_t struct_size;    /* sizeof(vc_server_info) */
+  int32_t graphs;
+  uint64_t hbm_budget;
+  uint64_t bytes_reserved; /* lane tables */
+  uint64_t bytes_held;     /* worker workspaces */
+  uint64_t submitted, completed;
+  int64_t lane_supersteps; /* supersteps run by all lane tables */
+  int64_t lane_requests;   /* requests served by lanes */
+} vc_server_info;
+
+/* Creates a server on the current device.  config: host, may be NULL.
+ * Errors: VC_ERR_INVALID_ARG, VC_ERR_HIP. */
+vc_status vc_server_create(const vc_server_config* config, vc_server* out);
+
+/* Registers a graph (borrowed: it must outlive the server).  lanes: 0, or a
+ * multiple of 64 up to 256: width of the graph's lane table, reserved from
+ * the budget now (8 bytes per vertex and lane plus 16 per vertex and 64
+ * lanes).  Builds the graph's transpose if needed.  *id: host.
+ * Errors: VC_ERR_INVALID_ARG (null, bad lanes, graph on another device),
+ * VC_ERR_OUT_OF_MEMORY (lane table over budget), VC_ERR_HIP. */
+vc_status vc_server_add_graph(vc_server s, vc_graph g, int32_t lanes, int32_t* id);
+
+/* Queues a request.  The request is checked here (graph id, program,
+ * params, out); a bad request returns VC_ERR_INVALID_ARG and is not queued.
+ * *ticket (host, may be NULL) identifies its completion. */
+vc_status vc_server_submit(vc_server s, const vc_request* req, uint64_t* ticket);
+
+/* Moves up to cap completions (host array) to `done`, waiting up to
+ * timeout_ms (0: no wait, < 0: until one is available) for the first one.
+ * *count: number written. */
+vc_status vc_server_poll(vc_server s, vc_completion* done, int32_t cap, int32_t timeout_ms, int32_t* count);
+
+/* Blocks until every request submitted so far has completed. */
+vc_status vc_server_drain(vc_server s);
+
+vc_status vc_server_info_get(vc_server s, vc_server_info* info);
+
+/* Waits for every submitted request to complete, stops the threads and
+ * frees lane tables and workspaces (not the registered graphs).  NULL is
+ * accepted. */
+vc_status vc_server_destroy(vc_server s);
+
 /* Fills *p with the defaults used when vc_run receives NULL params. */
 void vc_params_default(vc_params* p);
 

@@ -13,11 +13,13 @@
 #include <string>
 #include <vector>
 
-#include "vc_internal.h"
+#include "vc_graph.h"
+
+namespace vc {
 
 namespace {
-
 thread_local std::string t_last_error;
+}
 
 vc_status fail(vc_status st, const std::string& msg) {
   t_last_error = msg;
@@ -29,89 +31,11 @@ vc_status hip_fail(hipError_t e, const char* what) {
               std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
 }
 
-#define VC_TRY(call)                                  \
-  do {                                                \
-    hipError_t e_ = (call);                           \
-    if (e_ != hipSuccess) return hip_fail(e_, #call); \
-  } while (0)
+}  // namespace vc
 
-// A device buffer, grown on demand and kept across runs; freed when its
-// owner goes away (graph, batch, or a temporary of a build step).
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-  DevBuf() = default;
-  DevBuf(const DevBuf&) = delete;
-  DevBuf& operator=(const DevBuf&) = delete;
-  ~DevBuf() { release(); }
-  hipError_t ensure(size_t want) {
-    if (want <= bytes) return hipSuccess;
-    if (p) {
-      hipError_t e = hipFree(p);
-      if (e != hipSuccess) return e;
-      p = nullptr;
-      bytes = 0;
-    }
-    if (want == 0) return hipSuccess;
-    hipError_t e = hipMalloc(&p, want);
-    if (e == hipSuccess) bytes = want;
-    return e;
-  }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-  template <class T>
-  T* as() const {
-    return static_cast<T*>(p);
-  }
-};
-
-}  // namespace
-
-struct vc_graph_s {
-  int64_t n = 0, m = 0;
-  bool off64 = false;
-  uint32_t flags = 0;
-  int device = 0;
-  const void* off = nullptr;
-  const int32_t* dst = nullptr;
-  const uint32_t* w = nullptr;
-  DevBuf own_off, own_dst, own_w;  // copies when not borrowed
-  // relabelled copy (hot-first vertex order); perm[old] = new, inv[new] = old
-  bool relabeled = false;
-  DevBuf perm, inv, rel_off, rel_dst, rel_w;
-  // workspace
-  DevBuf contrib, mb;                             // PageRank / PPR
-  DevBuf vm, bitmap, bitmap2, fq, prefix, scan_blocks;  // CC / SSSP (two bitmaps: improved / active)
-  DevBuf list_tiles;                              // per-superstep merge-path partition
-  DevBuf dense_tiles;                             // merge-path partition of the CSR itself
-  int64_t dense_tile = 0, dense_ntiles = 0;
-  // transpose (CSC) for the pull form; for symmetric graphs only csc_off is
-  // owned (int64 copy of the offsets) and csc_src / csc_w alias the CSR
-  DevBuf csc_off, csc_src, csc_w, csc_tiles;
-  const int32_t* in_src = nullptr;
-  const uint32_t* in_w = nullptr;
-  bool csc_ready = false;
-  int64_t csc_tile = 0, csc_ntiles = 0;
-  DevBuf ms_d, ms_mb, ms_a0, ms_a1, ms_src;  // many-source SSSP: distances, mailboxes, lane masks
-  // captured superstep loops (HIP graphs), replayed on the caller's stream
-  hipStream_t cap_stream = nullptr;
-  hipGraphExec_t min_exec[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
-  int64_t min_exec_tile[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-  hipGraphExec_t pr_exec = nullptr;
-  std::string pr_exec_key;
-  DevBuf loop_state, loop_steps;
-  vc::LoopState* host_loop = nullptr;  // pinned
-  // autotuned settings per program (used by VC_SCHED_AUTO runs with tile 0)
-  bool tuned[4] = {false, false, false, false};
-  vc_params tuned_params[4];
-  DevBuf counters;
-  size_t max_lds = 65536;            // dynamic LDS limit per workgroup on the graph's device
-  vc::Counters* host_ctr = nullptr;  // pinned
-  std::vector<hipEvent_t> events;
-};
+using vc::DevBuf;
+using vc::fail;
+using vc::hip_fail;
 
 namespace {
 
@@ -161,6 +85,10 @@ struct Recorder {
   }
 };
 
+}  // namespace
+
+namespace vc {
+
 // Merge-path tile: the requested size clamped to [64, kMaxTile] and to what
 // the largest scatter variant can stage in LDS on this device.
 int64_t pick_tile(const vc_params& p, vc_graph g) {
@@ -174,10 +102,15 @@ int64_t pick_tile(const vc_params& p, vc_graph g) {
 }
 
 vc_status dense_partition(vc_graph g, int64_t tile, hipStream_t s) {
-  if (g->dense_tile == tile && g->dense_tiles.p) return VC_OK;
+  if (g->dense_tile == tile && g->dense_tiles_p) return VC_OK;
   const int64_t ntiles = (g->n + g->m + tile - 1) / tile;
-  VC_TRY(g->dense_tiles.ensure((size_t)(ntiles + 1) * sizeof(int32_t)));
-  VC_TRY(vc::launch_mp_partition(g->off, g->off64, g->n, g->n + g->m, tile, ntiles, g->dense_tiles.as<int32_t>(), s));
+  DevBuf* b = g->dense_parts.find(tile);
+  if (!b) {
+    b = g->dense_parts.add(tile);
+    VC_TRY(b->ensure((size_t)(ntiles + 1) * sizeof(int32_t)));
+    VC_TRY(vc::launch_mp_partition(g->off, g->off64, g->n, g->n + g->m, tile, ntiles, b->as<int32_t>(), s));
+  }
+  g->dense_tiles_p = b->as<int32_t>();
   g->dense_tile = tile;
   g->dense_ntiles = ntiles;
   return VC_OK;
@@ -191,6 +124,7 @@ vc_status ensure_csc(vc_graph g, hipStream_t s) {
   const int64_t n = g->n, m = g->m;
   VC_TRY(g->csc_off.ensure((size_t)(n + 1) * 8));
   int64_t* in_off = g->csc_off.as<int64_t>();
+  g->csc_off_p = in_off;
   if (g->flags & VC_GRAPH_SYMMETRIC) {
     if (g->off64) {
       VC_TRY(hipMemcpyAsync(in_off, g->off, (size_t)(n + 1) * 8, hipMemcpyDeviceToDevice, s));
@@ -212,7 +146,7 @@ vc_status ensure_csc(vc_graph g, hipStream_t s) {
     const int64_t tile = vc::kDefaultTile;
     vc_status st = dense_partition(g, tile, s);
     if (st != VC_OK) return st;
-    VC_TRY(vc::launch_csc_fill(g->off, g->off64, g->dst, g->w, n, m, g->dense_tiles.as<int32_t>(), tile,
+    VC_TRY(vc::launch_csc_fill(g->off, g->off64, g->dst, g->w, n, m, g->dense_tiles_p, tile,
                                g->dense_ntiles, cursor.as<unsigned long long>(), g->csc_src.as<int32_t>(),
                                g->w ? g->csc_w.as<uint32_t>() : nullptr, s));
     VC_TRY(hipStreamSynchronize(s));
@@ -226,14 +160,29 @@ vc_status ensure_csc(vc_graph g, hipStream_t s) {
 }
 
 vc_status csc_partition(vc_graph g, int64_t tile, hipStream_t s) {
-  if (g->csc_tile == tile && g->csc_tiles.p) return VC_OK;
+  if (g->csc_tile == tile && g->csc_tiles_p) return VC_OK;
   const int64_t ntiles = (g->n + g->m + tile - 1) / tile;
-  VC_TRY(g->csc_tiles.ensure((size_t)(ntiles + 1) * sizeof(int32_t)));
-  VC_TRY(vc::launch_mp_partition(g->csc_off.p, true, g->n, g->n + g->m, tile, ntiles, g->csc_tiles.as<int32_t>(), s));
+  DevBuf* b = g->csc_parts.find(tile);
+  if (!b) {
+    b = g->csc_parts.add(tile);
+    VC_TRY(b->ensure((size_t)(ntiles + 1) * sizeof(int32_t)));
+    VC_TRY(vc::launch_mp_partition(g->csc_off_p, true, g->n, g->n + g->m, tile, ntiles, b->as<int32_t>(), s));
+  }
+  g->csc_tiles_p = b->as<int32_t>();
   g->csc_tile = tile;
   g->csc_ntiles = ntiles;
   return VC_OK;
 }
+
+}  // namespace vc
+
+using vc::csc_partition;
+using vc::dense_partition;
+using vc::ensure_csc;
+using vc::pick_tile;
+using vc::valid_params;
+
+namespace {
 
 // Builds the hot-first relabelled copy of the graph and switches the graph
 // object to it.  The caller's arrays are not read afterwards.
@@ -248,6 +197,8 @@ vc_status relabel(vc_graph g, hipStream_t s) {
   VC_TRY(blocks.ensure((size_t)scan_need * 8));
   VC_TRY(g->perm.ensure((size_t)n * 4));
   VC_TRY(g->inv.ensure((size_t)n * 4));
+  int32_t* perm = g->perm.as<int32_t>();
+  int32_t* inv = g->inv.as<int32_t>();
   VC_TRY(g->rel_off.ensure((size_t)(n + 1) * 8));
   VC_TRY(g->rel_dst.ensure((size_t)m * 4 + 4));
   if (g->w) VC_TRY(g->rel_w.ensure((size_t)m * 4 + 4));
@@ -255,20 +206,22 @@ vc_status relabel(vc_graph g, hipStream_t s) {
   VC_TRY(vc::launch_fill_u32(reinterpret_cast<uint32_t*>(deg_in), 2 * (n + 1), 0u, s));
   VC_TRY(vc::launch_csc_count(g->dst, m, deg_in, s));
   VC_TRY(vc::launch_relabel_perm(g->off, g->off64, deg_in, n, hist.as<int64_t>(), blocks.as<int64_t>(),
-                                 g->perm.as<int32_t>(), g->inv.as<int32_t>(), s));
+                                 perm, inv, s));
   int64_t* noff = g->rel_off.as<int64_t>();
-  VC_TRY(vc::launch_relabel_degrees(g->off, g->off64, g->inv.as<int32_t>(), n, noff, s));
+  VC_TRY(vc::launch_relabel_degrees(g->off, g->off64, inv, n, noff, s));
   VC_TRY(vc::launch_exclusive_scan(noff, n, blocks.as<int64_t>(), s));
   const int64_t tile = vc::kDefaultTile;
   const int64_t ntiles = (n + m + tile - 1) / tile;
   VC_TRY(tiles.ensure((size_t)(ntiles + 1) * 4));
   VC_TRY(vc::launch_mp_partition(noff, true, n, n + m, tile, ntiles, tiles.as<int32_t>(), s));
-  VC_TRY(vc::launch_relabel_edges(g->off, g->off64, g->dst, g->w, noff, g->inv.as<int32_t>(), g->perm.as<int32_t>(),
+  VC_TRY(vc::launch_relabel_edges(g->off, g->off64, g->dst, g->w, noff, inv, perm,
                                   n, m, tiles.as<int32_t>(), tile, ntiles, g->rel_dst.as<int32_t>(),
                                   g->w ? g->rel_w.as<uint32_t>() : nullptr, s));
   VC_TRY(hipStreamSynchronize(s));
   g->off = noff;
   g->off64 = true;
+  g->perm_p = perm;
+  g->inv_p = inv;
   g->dst = g->rel_dst.as<int32_t>();
   g->w = g->w ? g->rel_w.as<uint32_t>() : nullptr;
   g->relabeled = true;
@@ -285,7 +238,7 @@ vc_status internal_id(vc_graph g, int64_t v, hipStream_t s, int64_t* out) {
     return VC_OK;
   }
   int32_t x = 0;
-  VC_TRY(hipMemcpyAsync(&x, g->perm.as<int32_t>() + v, 4, hipMemcpyDeviceToHost, s));
+  VC_TRY(hipMemcpyAsync(&x, g->perm_p + v, 4, hipMemcpyDeviceToHost, s));
   VC_TRY(hipStreamSynchronize(s));
   *out = x;
   return VC_OK;
@@ -314,7 +267,7 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
   if (T == 0) {
     VC_TRY(vc::launch_pr_init(fx, g->off, g->off64, n, r0, source, contrib, mb, rank_out, s));
     if (g->relabeled)
-      VC_TRY(vc::launch_unpermute(reinterpret_cast<const uint32_t*>(rank_out), 1, g->perm.as<int32_t>(), n,
+      VC_TRY(vc::launch_unpermute(reinterpret_cast<const uint32_t*>(rank_out), 1, g->perm_p, n,
                                   reinterpret_cast<uint32_t*>(out), s));
     VC_TRY(hipStreamSynchronize(s));
     rec.step(0, 0, 0, 0);
@@ -354,10 +307,10 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
       for (int64_t step = 0; step < T && e == hipSuccess; ++step) {
         if (g->m > 0) {
           if (sched == VC_SCHED_PULL)
-            e = vc::launch_pr_pull(fx, g->csc_off.as<int64_t>(), g->in_src, n, g->m, g->csc_tiles.as<int32_t>(),
+            e = vc::launch_pr_pull(fx, g->csc_off_p, g->in_src, n, g->m, g->csc_tiles_p,
                                    g->csc_tile, g->csc_ntiles, contrib, mb, cs);
           else if (sched == VC_SCHED_EDGE)
-            e = vc::launch_pr_scatter_mp(fx, g->off, g->off64, g->dst, n, g->m, g->dense_tiles.as<int32_t>(), tile,
+            e = vc::launch_pr_scatter_mp(fx, g->off, g->off64, g->dst, n, g->m, g->dense_tiles_p, tile,
                                          g->dense_ntiles, contrib, mb, cs);
           else
             e = vc::launch_pr_scatter_vertex(fx, g->off, g->off64, g->dst, n, contrib, mb, cs);
@@ -378,7 +331,7 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
     for (int64_t step = 0; step < T; ++step) rec.step(step, n, g->m, sched);
     rec.step(T, 0, 0, 0);
     if (g->relabeled)
-      VC_TRY(vc::launch_unpermute(reinterpret_cast<const uint32_t*>(stage), 1, g->perm.as<int32_t>(), n,
+      VC_TRY(vc::launch_unpermute(reinterpret_cast<const uint32_t*>(stage), 1, g->perm_p, n,
                                   reinterpret_cast<uint32_t*>(out), s));
     else
       VC_TRY(hipMemcpyAsync(out, stage, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
@@ -393,10 +346,10 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
     if (timed) VC_TRY(hipEventRecord(g->events[3 * step], s));
     if (g->m > 0) {
       if (sched == VC_SCHED_PULL)
-        VC_TRY(vc::launch_pr_pull(fx, g->csc_off.as<int64_t>(), g->in_src, n, g->m, g->csc_tiles.as<int32_t>(),
+        VC_TRY(vc::launch_pr_pull(fx, g->csc_off_p, g->in_src, n, g->m, g->csc_tiles_p,
                                   g->csc_tile, g->csc_ntiles, contrib, mb, s));
       else if (sched == VC_SCHED_EDGE)
-        VC_TRY(vc::launch_pr_scatter_mp(fx, g->off, g->off64, g->dst, n, g->m, g->dense_tiles.as<int32_t>(), tile,
+        VC_TRY(vc::launch_pr_scatter_mp(fx, g->off, g->off64, g->dst, n, g->m, g->dense_tiles_p, tile,
                                         g->dense_ntiles, contrib, mb, s));
       else
         VC_TRY(vc::launch_pr_scatter_vertex(fx, g->off, g->off64, g->dst, n, contrib, mb, s));
@@ -408,7 +361,7 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
   }
   rec.step(T, 0, 0, 0);
   if (g->relabeled)
-    VC_TRY(vc::launch_unpermute(reinterpret_cast<const uint32_t*>(rank_out), 1, g->perm.as<int32_t>(), n,
+    VC_TRY(vc::launch_unpermute(reinterpret_cast<const uint32_t*>(rank_out), 1, g->perm_p, n,
                                 reinterpret_cast<uint32_t*>(out), s));
   VC_TRY(hipStreamSynchronize(s));
   for (int64_t step = 0; step < T && rec.want_time(step); ++step) {
@@ -465,7 +418,7 @@ vc_status run_min_device_loop(vc_graph g, int kind, int64_t tile, int cur, int64
     hipError_t e = hipSuccess;
     for (int half = 0; half < 2 && e == hipSuccess; ++half) {
       const int a = half == 0 ? cur : 1 - cur;
-      e = vc::launch_min_pull(kind, g->csc_off.as<int64_t>(), g->in_src, g->in_w, n, m, g->csc_tiles.as<int32_t>(),
+      e = vc::launch_min_pull(kind, g->csc_off_p, g->in_src, g->in_w, n, m, g->csc_tiles_p,
                               g->csc_tile, g->csc_ntiles, vm, bits[1 - a], bits[a], loop, cs);
       if (e == hipSuccess)
         e = vc::launch_min_compact(g->off, g->off64, n, vm, bits[a], bits[1 - a], fq, P, ctr, false, loop, cs);
@@ -560,12 +513,12 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
     listed = (int64_t)g->host_ctr->listed;
     edges = (int64_t)g->host_ctr->edges;
   } else if (dense) {
-    VC_TRY(vc::launch_min_init(kind, n, source, g->relabeled ? g->inv.as<int32_t>() : nullptr, vm, s));
+    VC_TRY(vc::launch_min_init(kind, n, source, g->relabeled ? g->inv_p : nullptr, vm, s));
     frontier = n;
     listed = n;
     edges = m;
   } else {
-    VC_TRY(vc::launch_min_init(kind, n, source, g->relabeled ? g->inv.as<int32_t>() : nullptr, vm, s));
+    VC_TRY(vc::launch_min_init(kind, n, source, g->relabeled ? g->inv_p : nullptr, vm, s));
     int64_t o[2] = {0, 0};
     if (g->off64) {
       VC_TRY(hipMemcpyAsync(o, (const int64_t*)g->off + source, 16, hipMemcpyDeviceToHost, s));
@@ -619,7 +572,7 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
       if (st == VC_OK) st = csc_partition(g, vc::pull_tile(tile), s);
       if (st != VC_OK) return st;
       if (timed) VC_TRY(hipEventRecord(g->events[1], s));
-      VC_TRY(vc::launch_min_pull(kind, g->csc_off.as<int64_t>(), g->in_src, g->in_w, n, m, g->csc_tiles.as<int32_t>(),
+      VC_TRY(vc::launch_min_pull(kind, g->csc_off_p, g->in_src, g->in_w, n, m, g->csc_tiles_p,
                                  g->csc_tile, g->csc_ntiles, vm, dense ? nullptr : bits[1 - cur], improved, nullptr,
                                  s));
     } else if (sched == VC_SCHED_EDGE) {
@@ -628,7 +581,7 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
         if (st != VC_OK) return st;
         if (timed) VC_TRY(hipEventRecord(g->events[1], s));
         VC_TRY(vc::launch_min_scatter_mp(kind, false, tba, g->off, g->off64, g->dst, g->w, n, n + m, nullptr, nullptr,
-                                         g->dense_tiles.as<int32_t>(), tile, g->dense_ntiles, vm, improved, s));
+                                         g->dense_tiles_p, tile, g->dense_ntiles, vm, improved, s));
       } else {
         if (!prefix_ready) VC_TRY(vc::launch_exclusive_scan(P, listed, g->scan_blocks.as<int64_t>(), s));
         const int64_t total = listed + edges;
@@ -669,7 +622,7 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
     }
   }
   if (g->relabeled)
-    VC_TRY(vc::launch_unpermute(reinterpret_cast<const uint32_t*>(vm), 2, g->perm.as<int32_t>(), n, out, s));
+    VC_TRY(vc::launch_unpermute(reinterpret_cast<const uint32_t*>(vm), 2, g->perm_p, n, out, s));
   else
     VC_TRY(vc::launch_min_output(n, vm, out, s));
   VC_TRY(hipStreamSynchronize(s));
@@ -687,6 +640,10 @@ void apply_tuned(vc_graph g, vc_program prog, vc_params* p) {
   p->options |= t.options & VC_OPT_GRAPH_CAPTURE;
 }
 
+}  // namespace
+
+namespace vc {
+
 bool valid_params(const vc_params& p, vc_program prog, int64_t n, std::string* why) {
   if (p.struct_size != sizeof(vc_params)) return *why = "vc_params.struct_size mismatch", false;
   if (p.schedule < VC_SCHED_AUTO || p.schedule > VC_SCHED_PULL) return *why = "bad schedule", false;
@@ -702,13 +659,58 @@ bool valid_params(const vc_params& p, vc_program prog, int64_t n, std::string* w
   return true;
 }
 
-}  // namespace
+
+vc_status make_view(vc_graph base, hipStream_t s, vc_graph* out) {
+  if (!base || !out) return fail(VC_ERR_INVALID_ARG, "null graph or out");
+  if (base->is_view) return fail(VC_ERR_INVALID_ARG, "a view cannot serve as the base of another view");
+  vc_params p;
+  vc_params_default(&p);
+  const int64_t tile = pick_tile(p, base);
+  vc_status st = ensure_csc(base, s);
+  if (st == VC_OK) st = csc_partition(base, pull_tile(tile), s);
+  if (st == VC_OK) st = dense_partition(base, tile, s);
+  if (st != VC_OK) return st;
+  VC_TRY(hipStreamSynchronize(s));
+  vc_graph v = new (std::nothrow) vc_graph_s();
+  if (!v) return fail(VC_ERR_OUT_OF_MEMORY, "host allocation failed");
+  v->n = base->n;
+  v->m = base->m;
+  v->off64 = base->off64;
+  v->flags = base->flags | VC_GRAPH_BORROW;
+  v->device = base->device;
+  v->off = base->off;
+  v->dst = base->dst;
+  v->w = base->w;
+  v->relabeled = base->relabeled;
+  v->perm_p = base->perm_p;
+  v->inv_p = base->inv_p;
+  v->csc_off_p = base->csc_off_p;
+  v->csc_tiles_p = base->csc_tiles_p;
+  v->csc_tile = base->csc_tile;
+  v->csc_ntiles = base->csc_ntiles;
+  v->dense_tiles_p = base->dense_tiles_p;
+  v->dense_tile = base->dense_tile;
+  v->dense_ntiles = base->dense_ntiles;
+  v->in_src = base->in_src;
+  v->in_w = base->in_w;
+  v->csc_ready = base->csc_ready;
+  v->max_lds = base->max_lds;
+  for (int i = 0; i < 4; ++i) {
+    v->tuned[i] = base->tuned[i];
+    v->tuned_params[i] = base->tuned_params[i];
+  }
+  v->is_view = true;
+  *out = v;
+  return VC_OK;
+}
+
+}  // namespace vc
 
 extern "C" {
 
 int vc_abi_version(void) { return VC_ABI_VERSION; }
 
-const char* vc_last_error(void) { return t_last_error.c_str(); }
+const char* vc_last_error(void) { return vc::t_last_error.c_str(); }
 
 const char* vc_status_string(vc_status s) {
   switch (s) {
@@ -824,9 +826,11 @@ vc_status vc_graph_destroy(vc_graph g) {
   (void)hipDeviceSynchronize();
   for (DevBuf* b : {&g->own_off, &g->own_dst, &g->own_w, &g->perm, &g->inv, &g->rel_off, &g->rel_dst, &g->rel_w,
                     &g->contrib, &g->mb, &g->vm, &g->bitmap, &g->bitmap2,
-                    &g->fq, &g->prefix, &g->scan_blocks, &g->list_tiles, &g->dense_tiles, &g->csc_off, &g->csc_src,
-                    &g->csc_w, &g->csc_tiles, &g->ms_d, &g->ms_mb, &g->ms_a0, &g->ms_a1, &g->ms_src, &g->counters})
+                    &g->fq, &g->prefix, &g->scan_blocks, &g->list_tiles, &g->csc_off, &g->csc_src,
+                    &g->csc_w, &g->ms_d, &g->ms_mb, &g->ms_a0, &g->ms_a1, &g->ms_src, &g->counters})
     b->release();
+  g->dense_parts.release();
+  g->csc_parts.release();
   g->loop_state.release();
   g->loop_steps.release();
   if (g->host_ctr) (void)hipHostFree(g->host_ctr);
@@ -848,23 +852,25 @@ vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held,
   size_t held = g->own_off.bytes + g->own_dst.bytes + g->own_w.bytes + g->perm.bytes + g->inv.bytes +
                 g->rel_off.bytes + g->rel_dst.bytes + g->rel_w.bytes;
   for (const DevBuf* b : {&g->contrib, &g->mb, &g->vm, &g->bitmap, &g->bitmap2, &g->fq, &g->prefix, &g->scan_blocks,
-                          &g->list_tiles, &g->dense_tiles, &g->csc_off, &g->csc_src, &g->csc_w, &g->csc_tiles,
+                          &g->list_tiles, &g->csc_off, &g->csc_src, &g->csc_w,
                           &g->ms_d, &g->ms_mb, &g->ms_a0, &g->ms_a1, &g->ms_src, &g->counters})
     held += b->bytes;
+  held += g->dense_parts.bytes() + g->csc_parts.bytes();
   if (bytes_held) *bytes_held = held;
   if (bytes_run) {
     // workspace of the program plus the transpose the pull form reads
     const size_t want = workspace_bytes(g->n, g->m, program, vc::kDefaultTile);
     size_t have = 0;
     if (program == VC_PAGERANK || program == VC_PPR)
-      have = g->contrib.bytes + g->mb.bytes + g->dense_tiles.bytes;
+      have = g->contrib.bytes + g->mb.bytes + g->dense_parts.bytes();
     else
       have = g->vm.bytes + g->bitmap.bytes + g->bitmap2.bytes + g->fq.bytes + g->prefix.bytes +
-             g->scan_blocks.bytes + g->list_tiles.bytes + g->dense_tiles.bytes + g->counters.bytes;
+             g->scan_blocks.bytes + g->list_tiles.bytes + g->dense_parts.bytes() + g->counters.bytes;
     const size_t csc_want = (size_t)(g->n + 1) * 8 + (size_t)((g->n + g->m) / vc::kDefaultTile + 2) * 4 +
                             ((g->flags & VC_GRAPH_SYMMETRIC) ? 0 : (size_t)g->m * (g->w ? 8 : 4));
-    const size_t csc_have = g->csc_off.bytes + g->csc_src.bytes + g->csc_w.bytes + g->csc_tiles.bytes;
-    *bytes_run = (want > have ? want - have : 0) + (csc_want > csc_have ? csc_want - csc_have : 0);
+    const size_t csc_have = g->csc_off.bytes + g->csc_src.bytes + g->csc_w.bytes + g->csc_parts.bytes();
+    const size_t csc_need = g->csc_ready ? 0 : (csc_want > csc_have ? csc_want - csc_have : 0);
+    *bytes_run = (want > have ? want - have : 0) + csc_need;
   }
   return VC_OK;
 }
@@ -986,7 +992,7 @@ vc_status vc_batch_create(const vc_graph_desc* members, const vc_batch_query* qu
   if (b->g->relabeled) {
     DevBuf tmp;
     if ((e = tmp.ensure((size_t)n * 4)) != hipSuccess ||
-        (e = vc::launch_permute(b->init.as<uint32_t>(), b->g->perm.as<int32_t>(), n, tmp.as<uint32_t>(), stream)) !=
+        (e = vc::launch_permute(b->init.as<uint32_t>(), b->g->perm_p, n, tmp.as<uint32_t>(), stream)) !=
             hipSuccess ||
         (e = hipStreamSynchronize(stream)) != hipSuccess)
       return cleanup(hip_fail(e, "permute initial values"));
@@ -1098,7 +1104,7 @@ vc_status vc_run_multi_source(vc_graph g, const uint32_t* sources, int32_t k, co
   VC_TRY(vc::launch_fill_u32(bits, nwords, 0u, s));
   VC_TRY(vc::launch_zero_counters(ctr, s));
   VC_TRY(hipMemcpyAsync(g->ms_src.p, sources, (size_t)k * 4, hipMemcpyHostToDevice, s));
-  VC_TRY(vc::launch_ms_seed(C, g->ms_src.as<int32_t>(), g->relabeled ? g->perm.as<int32_t>() : nullptr, k, D, A[0],
+  VC_TRY(vc::launch_ms_seed(C, g->ms_src.as<int32_t>(), g->relabeled ? g->perm_p : nullptr, k, D, A[0],
                             bits, s));
   VC_TRY(vc::launch_ms_count(g->off, g->off64, n, bits, ctr, s));
   VC_TRY(vc::launch_fill_u32(bits, nwords, 0u, s));
@@ -1122,11 +1128,11 @@ vc_status vc_run_multi_source(vc_graph g, const uint32_t* sources, int32_t k, co
     rec.step(step, frontier, edges, VC_SCHED_PULL);
     const bool timed = rec.want_time(step);
     if (timed) VC_TRY(hipEventRecord(g->events[0], s));
-    VC_TRY(vc::launch_ms_pull(C, weighted, g->csc_off.as<int64_t>(), g->in_src, g->in_w, n, m,
-                              g->csc_tiles.as<int32_t>(), g->csc_tile, g->csc_ntiles, D, MB, A[cur], bits, s));
+    VC_TRY(vc::launch_ms_pull(C, weighted, g->csc_off_p, g->in_src, g->in_w, n, m,
+                              g->csc_tiles_p, g->csc_tile, g->csc_ntiles, D, MB, A[cur], bits, vc::LaneMask{}, s));
     if (timed) VC_TRY(hipEventRecord(g->events[1], s));
     VC_TRY(vc::launch_fill_u32(reinterpret_cast<uint32_t*>(A[1 - cur]), 2 * n * C, 0u, s));
-    VC_TRY(vc::launch_ms_apply(C, g->off, g->off64, n, D, MB, A[1 - cur], bits, ctr, s));
+    VC_TRY(vc::launch_ms_apply(C, g->off, g->off64, n, D, MB, A[1 - cur], bits, ctr, nullptr, s));
     if (timed) VC_TRY(hipEventRecord(g->events[2], s));
     VC_TRY(hipMemcpyAsync(g->host_ctr, ctr, sizeof(vc::Counters), hipMemcpyDeviceToHost, s));
     VC_TRY(vc::launch_zero_counters(ctr, s));
@@ -1147,7 +1153,7 @@ vc_status vc_run_multi_source(vc_graph g, const uint32_t* sources, int32_t k, co
       break;
     }
   }
-  VC_TRY(vc::launch_ms_output(C, D, g->relabeled ? g->perm.as<int32_t>() : nullptr, n, k, out, s));
+  VC_TRY(vc::launch_ms_output(C, D, g->relabeled ? g->perm_p : nullptr, n, k, out, s));
   VC_TRY(hipStreamSynchronize(s));
   if (stats) {
     stats->supersteps = supersteps;

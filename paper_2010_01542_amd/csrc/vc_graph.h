@@ -1,0 +1,151 @@
+// Host-side internals of libvc shared by the API and server translation
+// units: device buffers, the graph object, error reporting and the graph
+// preparation steps.  Not part of the public ABI (include/vc.h is).
+#pragma once
+
+#include <memory>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "vc_internal.h"
+
+namespace vc {
+
+// Records `msg` as this thread's last error (vc_last_error) and returns st.
+vc_status fail(vc_status st, const std::string& msg);
+vc_status hip_fail(hipError_t e, const char* what);
+
+#define VC_TRY(call)                                      \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return ::vc::hip_fail(e_, #call); \
+  } while (0)
+
+// A device buffer, grown on demand and kept across runs; freed when its
+// owner goes away (graph, batch, or a temporary of a build step).
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  hipError_t ensure(size_t want) {
+    if (want <= bytes) return hipSuccess;
+    if (p) {
+      hipError_t e = hipFree(p);
+      if (e != hipSuccess) return e;
+      p = nullptr;
+      bytes = 0;
+    }
+    if (want == 0) return hipSuccess;
+    hipError_t e = hipMalloc(&p, want);
+    if (e == hipSuccess) bytes = want;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+
+// Merge-path partitions by tile size.  Entries live until the owning graph
+// is destroyed, so views may keep pointers into them.
+struct PartCache {
+  std::vector<std::pair<int64_t, std::unique_ptr<DevBuf>>> parts;
+  DevBuf* find(int64_t tile) const {
+    for (const auto& e : parts)
+      if (e.first == tile) return e.second.get();
+    return nullptr;
+  }
+  DevBuf* add(int64_t tile) {
+    parts.emplace_back(tile, std::unique_ptr<DevBuf>(new DevBuf()));
+    return parts.back().second.get();
+  }
+  size_t bytes() const {
+    size_t b = 0;
+    for (const auto& e : parts) b += e.second->bytes;
+    return b;
+  }
+  void release() { parts.clear(); }
+};
+
+}  // namespace vc
+
+struct vc_graph_s {
+  int64_t n = 0, m = 0;
+  bool off64 = false;
+  uint32_t flags = 0;
+  int device = 0;
+  const void* off = nullptr;
+  const int32_t* dst = nullptr;
+  const uint32_t* w = nullptr;
+  vc::DevBuf own_off, own_dst, own_w;  // copies when not borrowed
+  // relabelled copy (hot-first vertex order); perm[old] = new, inv[new] = old
+  bool relabeled = false;
+  vc::DevBuf perm, inv, rel_off, rel_dst, rel_w;
+  // read-only arrays shared with views (see make_view): plain pointers to
+  // buffers owned by the base graph, or by this object for its own partitions
+  const int32_t* perm_p = nullptr;
+  const int32_t* inv_p = nullptr;
+  const int64_t* csc_off_p = nullptr;
+  const int32_t* csc_tiles_p = nullptr;
+  const int32_t* dense_tiles_p = nullptr;
+  bool is_view = false;
+  // workspace
+  vc::DevBuf contrib, mb;                             // PageRank / PPR
+  vc::DevBuf vm, bitmap, bitmap2, fq, prefix, scan_blocks;  // CC / SSSP (two bitmaps: improved / active)
+  vc::DevBuf list_tiles;                              // per-superstep merge-path partition
+  vc::PartCache dense_parts;                      // merge-path partitions of the CSR itself
+  int64_t dense_tile = 0, dense_ntiles = 0;
+  // transpose (CSC) for the pull form; for symmetric graphs only csc_off is
+  // owned (int64 copy of the offsets) and csc_src / csc_w alias the CSR
+  vc::DevBuf csc_off, csc_src, csc_w;
+  vc::PartCache csc_parts;
+  const int32_t* in_src = nullptr;
+  const uint32_t* in_w = nullptr;
+  bool csc_ready = false;
+  int64_t csc_tile = 0, csc_ntiles = 0;
+  vc::DevBuf ms_d, ms_mb, ms_a0, ms_a1, ms_src;  // many-source SSSP: distances, mailboxes, lane masks
+  // captured superstep loops (HIP graphs), replayed on the caller's stream
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t min_exec[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  int64_t min_exec_tile[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  hipGraphExec_t pr_exec = nullptr;
+  std::string pr_exec_key;
+  vc::DevBuf loop_state, loop_steps;
+  vc::LoopState* host_loop = nullptr;  // pinned
+  // autotuned settings per program (used by VC_SCHED_AUTO runs with tile 0)
+  bool tuned[4] = {false, false, false, false};
+  vc_params tuned_params[4];
+  vc::DevBuf counters;
+  size_t max_lds = 65536;            // dynamic LDS limit per workgroup on the graph's device
+  vc::Counters* host_ctr = nullptr;  // pinned
+  std::vector<hipEvent_t> events;
+};
+
+namespace vc {
+
+// Transpose (CSC) of the graph, built once; in_src / in_w / csc_off_p set.
+vc_status ensure_csc(vc_graph g, hipStream_t s);
+// Merge-path partition of the transpose for pull tiles of `tile` items.
+vc_status csc_partition(vc_graph g, int64_t tile, hipStream_t s);
+// Requested merge-path tile clamped to what the device's LDS can stage.
+int64_t pick_tile(const vc_params& p, vc_graph g);
+// Checks params for a run of prog on a graph of n vertices; *why on failure.
+bool valid_params(const vc_params& p, vc_program prog, int64_t n, std::string* why);
+// A graph object that shares every read-only array of `base` (structure,
+// relabelling, transpose, partitions) and owns only its own workspace,
+// events and streams.  The base must outlive the view.  The base's transpose
+// and default partitions are built first (on stream s) so views never build
+// their own.
+vc_status make_view(vc_graph base, hipStream_t s, vc_graph* out);
+
+}  // namespace vc

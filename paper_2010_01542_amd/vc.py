@@ -30,7 +30,9 @@ OK, ERR_INVALID_ARG, ERR_BAD_GRAPH, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_UNSUPPORTED,
 ABI_VERSION = 1
 EXPORTS = ("vc_graph_create", "vc_graph_destroy", "vc_graph_footprint", "vc_run", "vc_params_default",
            "vc_status_string", "vc_last_error", "vc_abi_version", "vc_batch_create", "vc_batch_layout",
-           "vc_batch_run", "vc_batch_destroy", "vc_run_multi_source", "vc_graph_autotune", "vc_batch_autotune")
+           "vc_batch_run", "vc_batch_destroy", "vc_run_multi_source", "vc_graph_autotune", "vc_batch_autotune",
+           "vc_server_create", "vc_server_add_graph", "vc_server_submit", "vc_server_poll", "vc_server_drain",
+           "vc_server_info_get", "vc_server_destroy")
 
 
 class GraphDesc(ctypes.Structure):
@@ -54,6 +56,28 @@ class StatsStruct(ctypes.Structure):
 
 class BatchQuery(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("program", ctypes.c_int), ("source", ctypes.c_uint32)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("workers", ctypes.c_int32), ("hbm_budget", ctypes.c_uint64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("graph", ctypes.c_int32), ("program", ctypes.c_int),
+                ("reserved", ctypes.c_int32), ("params", Params), ("out", ctypes.c_void_p), ("tag", ctypes.c_uint64)]
+
+
+class CompletionStruct(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int),
+                ("supersteps", ctypes.c_int32), ("lane", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("queue_ms", ctypes.c_double), ("service_ms", ctypes.c_double), ("message", ctypes.c_char * 120)]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("graphs", ctypes.c_int32), ("hbm_budget", ctypes.c_uint64),
+                ("bytes_reserved", ctypes.c_uint64), ("bytes_held", ctypes.c_uint64), ("submitted", ctypes.c_uint64),
+                ("completed", ctypes.c_uint64), ("lane_supersteps", ctypes.c_int64),
+                ("lane_requests", ctypes.c_int64)]
 
 
 class VcError(RuntimeError):
@@ -106,6 +130,21 @@ def load(path: str = LIB_PATH):
     lib.vc_run_multi_source.restype = i32
     lib.vc_run_multi_source.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(Params), vp, vp,
                                         ctypes.POINTER(StatsStruct)]
+    lib.vc_server_create.restype = i32
+    lib.vc_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+    lib.vc_server_add_graph.restype = i32
+    lib.vc_server_add_graph.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.vc_server_submit.restype = i32
+    lib.vc_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    lib.vc_server_poll.restype = i32
+    lib.vc_server_poll.argtypes = [vp, ctypes.POINTER(CompletionStruct), ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_int32)]
+    lib.vc_server_drain.restype = i32
+    lib.vc_server_drain.argtypes = [vp]
+    lib.vc_server_info_get.restype = i32
+    lib.vc_server_info_get.argtypes = [vp, ctypes.POINTER(ServerInfo)]
+    lib.vc_server_destroy.restype = i32
+    lib.vc_server_destroy.argtypes = [vp]
     if lib.vc_abi_version() != ABI_VERSION:
         raise RuntimeError(f"{path}: ABI version {lib.vc_abi_version()} != {ABI_VERSION}; rebuild the library")
     _lib = lib
@@ -393,3 +432,102 @@ class Batch:
         """Host numpy uint32 results, one array per member."""
         vals = out.cpu().numpy().view(np.uint32)
         return [vals[self.vertex_base[i]:self.vertex_base[i + 1]] for i in range(self.count)]
+
+
+@dataclass
+class Completion:
+    ticket: int
+    tag: int
+    status: int
+    supersteps: int
+    lane: int
+    queue_ms: float
+    service_ms: float
+    message: str
+
+    @property
+    def latency_ms(self) -> float:
+        return self.queue_ms + self.service_ms
+
+
+class Server:
+    """Request server over resident graphs (vc_server_*).
+
+    Graphs are registered with add_graph (lanes > 0 gives the graph a lane
+    table for continuous batching of CC / SSSP requests); submit queues one
+    request and returns its ticket; poll / drain collect completions.  A
+    request's `out` tensor is referenced until its completion is polled.
+    """
+
+    def __init__(self, *, workers: int = 2, hbm_budget: int = 0, device=None):
+        import torch
+        lib = load()
+        cfg = ServerConfig(ctypes.sizeof(ServerConfig), int(workers), int(hbm_budget))
+        h = ctypes.c_void_p()
+        _check(lib.vc_server_create(ctypes.byref(cfg), ctypes.byref(h)), "vc_server_create")
+        self._h = h
+        self._graphs = []
+        self._pending = {}
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+
+    def add_graph(self, graph: Graph, lanes: int = 0) -> int:
+        gid = ctypes.c_int32()
+        _check(load().vc_server_add_graph(self._h, graph._h, int(lanes), ctypes.byref(gid)), "vc_server_add_graph")
+        self._graphs.append(graph)
+        return gid.value
+
+    def submit(self, graph_id: int, program, out, *, source: int = 0, T: int = 10, damping: float = 0.85,
+               max_supersteps: int = 0, schedule="auto", tile: int = 0, options: int = 0, tag: int = 0) -> int:
+        prog = _program(program)
+        rank = prog in (PAGERANK, PPR)
+        if not out.is_cuda or not out.is_contiguous() or out.element_size() != 4:
+            raise TypeError("out must be a contiguous CUDA tensor of 4-byte elements")
+        n = self._graphs[graph_id].n if 0 <= graph_id < len(self._graphs) else None
+        if n is not None and out.numel() != n:
+            raise TypeError("out must hold N elements")
+        req = Request(ctypes.sizeof(Request), int(graph_id), prog, 0,
+                      _params(T if rank else max_supersteps, damping, source, schedule, tile, options),
+                      out.data_ptr(), int(tag))
+        ticket = ctypes.c_uint64()
+        _check(load().vc_server_submit(self._h, ctypes.byref(req), ctypes.byref(ticket)), "vc_server_submit")
+        self._pending[ticket.value] = out
+        return ticket.value
+
+    def poll(self, timeout_ms: int = 0, cap: int = 256):
+        buf = (CompletionStruct * cap)()
+        k = ctypes.c_int32()
+        _check(load().vc_server_poll(self._h, buf, cap, int(timeout_ms), ctypes.byref(k)), "vc_server_poll")
+        res = []
+        for c in buf[:k.value]:
+            self._pending.pop(c.ticket, None)
+            res.append(Completion(c.ticket, c.tag, c.status, c.supersteps, c.lane, c.queue_ms, c.service_ms,
+                                  c.message.decode(errors="replace")))
+        return res
+
+    def drain(self):
+        _check(load().vc_server_drain(self._h), "vc_server_drain")
+
+    def info(self) -> dict:
+        st = ServerInfo()
+        st.struct_size = ctypes.sizeof(ServerInfo)
+        _check(load().vc_server_info_get(self._h, ctypes.byref(st)), "vc_server_info_get")
+        return {f: getattr(st, f) for f, _ in ServerInfo._fields_ if f != "struct_size"}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().vc_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._pending.clear()
+            self._graphs = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

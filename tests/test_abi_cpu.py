@@ -49,7 +49,8 @@ def test_params_default():
 def test_struct_layout_matches_header(tmp_path):
     """sizeof / offsetof of every ABI struct field, from the C compiler, equal ctypes'."""
     structs = {"vc_graph_desc": vc.GraphDesc, "vc_params": vc.Params, "vc_stats": vc.StatsStruct,
-               "vc_batch_query": vc.BatchQuery}
+               "vc_batch_query": vc.BatchQuery, "vc_server_config": vc.ServerConfig, "vc_request": vc.Request,
+               "vc_completion": vc.CompletionStruct, "vc_server_info": vc.ServerInfo}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "vc.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
@@ -96,3 +97,19 @@ def test_argument_errors_need_no_device():
     assert lib.vc_batch_create(descs, qs, 1, 0, None, ctypes.byref(b)) == vc.ERR_INVALID_ARG
     assert lib.vc_batch_run(None, None, 16, None, None) == vc.ERR_INVALID_ARG
     assert lib.vc_batch_destroy(None) == vc.OK
+    # request server
+    srv = ctypes.c_void_p()
+    assert lib.vc_server_create(None, None) == vc.ERR_INVALID_ARG
+    cfg = vc.ServerConfig(ctypes.sizeof(vc.ServerConfig) - 8, 2, 0)
+    assert lib.vc_server_create(ctypes.byref(cfg), ctypes.byref(srv)) == vc.ERR_INVALID_ARG
+    cfg = vc.ServerConfig(ctypes.sizeof(vc.ServerConfig), 65, 0)
+    assert lib.vc_server_create(ctypes.byref(cfg), ctypes.byref(srv)) == vc.ERR_INVALID_ARG
+    assert b"workers" in lib.vc_last_error()
+    gid = ctypes.c_int32()
+    assert lib.vc_server_add_graph(None, None, 64, ctypes.byref(gid)) == vc.ERR_INVALID_ARG
+    assert lib.vc_server_submit(None, None, None) == vc.ERR_INVALID_ARG
+    cnt = ctypes.c_int32()
+    assert lib.vc_server_poll(None, None, 0, 0, ctypes.byref(cnt)) == vc.ERR_INVALID_ARG
+    assert lib.vc_server_drain(None) == vc.ERR_INVALID_ARG
+    assert lib.vc_server_info_get(None, None) == vc.ERR_INVALID_ARG
+    assert lib.vc_server_destroy(None) == vc.OK

@@ -1,0 +1,189 @@
+"""Request server (GPU): every request's result is the same alone and in the
+mix.
+
+* Lane tables (continuous batching of CC / SSSP): values bit-exact and
+  superstep counts equal to the same request run alone with vc_run, and to
+  the oracle; more requests than lanes, so lanes are retired and reseeded
+  many times; a request stopped at its superstep cap frees its lane cleanly.
+* Workers: PageRank / PPR (and min programs on graphs without lanes) equal
+  their alone runs bit for bit (the default combiner sums in exact fixed
+  point, so the order of additions cannot change a result) and the oracle
+  within the PageRank bars.
+* Admission: with a budget that holds one workspace, requests still all
+  complete correctly; a request whose workspace can never fit completes
+  with VC_ERR_OUT_OF_MEMORY alone; a bad request is refused at submission.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import rmatgen
+from gpu_util import L1_TOL, MAX_ABS_TOL, rank_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def make(csr, **kw):
+    from paper_2010_01542_amd import Graph
+    return Graph.from_csr(csr, **kw)
+
+
+def alone(csr, program, **kw):
+    """Result and superstep count of the request run alone (its own graph object)."""
+    import torch
+    from paper_2010_01542_amd import VcError, vc
+    g = make(csr, symmetric=kw.pop("symmetric", False))
+    rank = program in ("pagerank", "ppr")
+    out = torch.empty(csr.n, dtype=torch.float32 if rank else torch.int32, device="cuda")
+    try:
+        _, st = g.run(program, out, stats=True, **kw)
+        status, steps = vc.OK, st.supersteps
+    except VcError as e:
+        status, steps = e.status, None
+    vals = out.cpu().numpy()
+    return (vals if rank else vals.view(np.uint32)), status, steps
+
+
+def collect(srv, count):
+    done = {}
+    srv.drain()
+    while len(done) < count:
+        for c in srv.poll(timeout_ms=1000, cap=512):
+            done[c.ticket] = c
+    return done
+
+
+@pytest.mark.parametrize("lanes", [64, 256])
+def test_lanes_equal_alone_runs(device, lanes):
+    import torch
+    from paper_2010_01542_amd import Server, vc
+    print(f"case serve lanes={lanes}", flush=True)
+    d = rmatgen.rmat(11, 10, seed=5, weighted=True)
+    rng = np.random.default_rng(lanes)
+    sources = rng.integers(0, d.n, 3 * lanes // 2 + 7)
+    deg = d.outdeg
+    sources[0] = int(np.flatnonzero(deg == 0)[0])  # cannot send: ends after one superstep
+    sources[1] = sources[2]
+    progs = ["sssp"] * len(sources)
+    for i in range(5, len(progs), 17):
+        progs[i] = "cc"
+    g = make(d)
+    with Server(workers=1) as srv:
+        gid = srv.add_graph(g, lanes=lanes)
+        outs = [torch.full((d.n,), -7, dtype=torch.int32, device=device) for _ in progs]
+        tickets = [srv.submit(gid, p, o, source=int(s), tag=i)
+                   for i, (p, s, o) in enumerate(zip(progs, sources, outs))]
+        done = collect(srv, len(tickets))
+        info = srv.info()
+    assert info["lane_requests"] == len(progs) and info["submitted"] == info["completed"] == len(progs)
+    cache = {}
+    for i, (t, p, s) in enumerate(zip(tickets, progs, sources)):
+        c = done[t]
+        assert c.tag == i and c.status == vc.OK and 0 <= c.lane < lanes, (i, c)
+        key = (p, int(s) if p == "sssp" else 0)
+        if key not in cache:
+            cache[key] = alone(d, p, source=key[1])
+        ref, status, steps = cache[key]
+        got = outs[i].cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, ref), (i, p, int(s), int((got != ref).sum()))
+        assert status == vc.OK and c.supersteps == steps, (i, p, c.supersteps, steps)
+    for p, s in list(cache)[:6]:
+        o = oracle.run(p, d.n, d.off, d.dst, d.w if p == "sssp" else None, source=s)
+        assert np.array_equal(cache[(p, s)][0], o.values) and cache[(p, s)][2] == o.supersteps
+
+
+def test_lane_superstep_cap_frees_the_lane(device):
+    import torch
+    from paper_2010_01542_amd import Server, vc
+    print("case serve lane cap", flush=True)
+    d = rmatgen.path(200, directed=True)
+    g = make(d)
+    with Server(workers=1) as srv:
+        gid = srv.add_graph(g, lanes=64)
+        capped = torch.full((d.n,), -7, dtype=torch.int32, device=device)
+        t_cap = srv.submit(gid, "sssp", capped, source=0, max_supersteps=7)
+        outs = [torch.full((d.n,), -7, dtype=torch.int32, device=device) for _ in range(150)]
+        ts = [srv.submit(gid, "sssp", o, source=i) for i, o in enumerate(outs)]
+        done = collect(srv, 151)
+    c = done[t_cap]
+    ref, status, _ = alone(d, "sssp", source=0, max_supersteps=7)
+    assert c.status == status == vc.ERR_NOT_CONVERGED and c.supersteps == 7
+    assert np.array_equal(capped.cpu().numpy().view(np.uint32), ref)
+    for i, (t, o) in enumerate(zip(ts, outs)):
+        got = o.cpu().numpy().view(np.uint32)
+        expect = np.where(np.arange(d.n) >= i, np.arange(d.n) - i, 0xFFFFFFFF).astype(np.uint32)
+        assert done[t].status == vc.OK and np.array_equal(got, expect), i
+        assert done[t].supersteps == d.n - i, (i, done[t].supersteps)
+
+
+def test_mixed_programs_on_workers_and_lanes(device):
+    import torch
+    from paper_2010_01542_amd import Server, vc
+    print("case serve mixed programs", flush=True)
+    a = rmatgen.rmat(12, 8, seed=21, weighted=True)             # lanes for its CC / SSSP
+    b = rmatgen.rmat(11, 8, seed=22, directed=False)            # no lanes: everything on workers
+    ga, gb = make(a), make(b, symmetric=True)
+    rng = np.random.default_rng(3)
+    reqs = []
+    for i in range(60):
+        csr, gname = (a, "a") if i % 2 == 0 else (b, "b")
+        prog = ["sssp", "ppr", "pagerank", "cc", "sssp"][i % 5]
+        reqs.append((csr, gname, prog, int(rng.integers(0, csr.n)), 5 + i % 7))
+    with Server(workers=3) as srv:
+        ids = {"a": srv.add_graph(ga, lanes=64), "b": srv.add_graph(gb, lanes=0)}
+        outs, tickets = [], []
+        for csr, gname, prog, src, T in reqs:
+            rank = prog in ("pagerank", "ppr")
+            o = torch.full((csr.n,), -7, dtype=torch.float32 if rank else torch.int32, device=device)
+            outs.append(o)
+            tickets.append(srv.submit(ids[gname], prog, o, source=src, T=T))
+        done = collect(srv, len(reqs))
+    for (csr, gname, prog, src, T), o, t in zip(reqs, outs, tickets):
+        c = done[t]
+        assert c.status == vc.OK, c
+        assert (c.lane >= 0) == (gname == "a" and prog in ("cc", "sssp"))
+        rank = prog in ("pagerank", "ppr")
+        kw = {"T": T} if rank else {}
+        ref, status, steps = alone(csr, prog, source=src, symmetric=gname == "b", **kw)
+        got = o.cpu().numpy() if rank else o.cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, ref), (gname, prog, src)
+        assert c.supersteps == steps
+        if rank and src % 3 == 0:
+            ora = oracle.run(prog, csr.n, csr.off, csr.dst, T=T, source=src).values
+            l1, mx = rank_errors(got, ora)
+            assert l1 <= L1_TOL and mx <= MAX_ABS_TOL
+
+
+def test_admission_under_a_small_budget(device):
+    import torch
+    from paper_2010_01542_amd import Server, VcError, vc
+    print("case serve admission", flush=True)
+    small = rmatgen.rmat(10, 8, seed=7)
+    big = rmatgen.rmat(14, 8, seed=8)
+    gs, gb = make(small), make(big)
+    _, need_small = make(small).footprint("pagerank")
+    _, need_big = make(big).footprint("pagerank")
+    assert need_big > 2 * need_small
+    budget = int(need_small * 1.5)
+    with Server(workers=3, hbm_budget=budget) as srv:
+        i_s, i_b = srv.add_graph(gs), srv.add_graph(gb)
+        with pytest.raises(VcError) as e:  # a lane table of the big graph is over budget
+            srv.add_graph(gb, lanes=64)
+        assert e.value.status == vc.ERR_OUT_OF_MEMORY
+        with pytest.raises(VcError):
+            srv.submit(i_s, "sssp", torch.empty(small.n, dtype=torch.int32, device=device), source=small.n)
+        with pytest.raises(VcError):
+            srv.submit(99, "sssp", torch.empty(small.n, dtype=torch.int32, device=device))
+        outs = [torch.empty(small.n, dtype=torch.float32, device=device) for _ in range(12)]
+        ts = [srv.submit(i_s, "ppr", o, source=k, T=6) for k, o in enumerate(outs)]
+        t_big = srv.submit(i_b, "pagerank", torch.empty(big.n, dtype=torch.float32, device=device), T=3)
+        t_tail = srv.submit(i_s, "pagerank", torch.empty(small.n, dtype=torch.float32, device=device), T=2)
+        done = collect(srv, len(ts) + 2)
+        info = srv.info()
+    assert done[t_big].status == vc.ERR_OUT_OF_MEMORY and "workspace" in done[t_big].message
+    assert done[t_tail].status == vc.OK
+    assert info["bytes_held"] <= budget
+    for k, (t, o) in enumerate(zip(ts, outs)):
+        assert done[t].status == vc.OK
+        ref, _, _ = alone(small, "ppr", source=k, T=6)
+        assert np.array_equal(o.cpu().numpy(), ref), k
