@@ -125,9 +125,25 @@ def bench_batch(args, dev):
         edges_plain += st.edges_relaxed
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t0
+    # the same plain runs with each graph's superstep loop captured as a HIP graph
+    from paper_2010_01542_amd import vc
+    cap = vc.OPT_GRAPH_CAPTURE
+    for g, o, (prog, src) in zip(graphs, outs, queries):
+        g.run(prog, o, source=src, options=cap)
+    torch.cuda.synchronize()
+    lat_cap = []
+    t0 = time.perf_counter()
+    for g, o, (prog, src) in zip(graphs, outs, queries):
+        a = time.perf_counter()
+        g.run(prog, o, source=src, options=cap)
+        lat_cap.append(time.perf_counter() - a)
+    torch.cuda.synchronize()
+    plain_cap_s = time.perf_counter() - t0
     del graphs
     torch.cuda.empty_cache()
     b = Batch(csrs, queries, device=dev)
+    tuned = b.autotune()
+    log(f"batch autotune picked {tuned}")
     out = torch.empty(b.n, dtype=torch.int32, device=dev)
     for _ in range(args.warmup):
         b.run(out)
@@ -153,6 +169,10 @@ def bench_batch(args, dev):
                   "queries_per_s": round(len(csrs) / plain_s, 1),
                   "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 3),
                   "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 3)},
+        "plain_captured": {"ms": round(plain_cap_s * 1e3, 3), "queries_per_s": round(len(csrs) / plain_cap_s, 1),
+                           "latency_ms_p50": round(float(np.percentile(np.array(lat_cap) * 1e3, 50)), 3),
+                           "latency_ms_p99": round(float(np.percentile(np.array(lat_cap) * 1e3, 99)), 3)},
+        "batch_autotuned": tuned,
         "speedup_vs_plain": round(plain_s / batch_s, 2),
         "edges_relaxed": int(edges_plain),
     }
@@ -211,14 +231,174 @@ def bench_multi(args, dev):
     }
 
 
+SERVE_GRAPHS = (  # name, scale, directed, weighted, lanes, share of SSSP / PPR traffic
+    ("s18", 18, True, True, 256, 0.50),
+    ("s22", 22, True, True, 256, 0.35),
+    ("s24", 24, True, True, 256, 0.15),
+)
+SERVE_CC = ("cc-s20", 20, False, False, 64)
+
+
+def serve_requests(count, graphs, seed):
+    """Seeded request stream: 70% SSSP, 20% PPR (T = 20), 10% CC; SSSP and PPR
+    pick a graph by its share and a uniform source with out-edges; CC runs on
+    the symmetrised graph."""
+    rng = np.random.default_rng(seed)
+    names = [g[0] for g in SERVE_GRAPHS]
+    share = np.array([g[5] for g in SERVE_GRAPHS])
+    senders = {k: np.flatnonzero(c.outdeg > 0) for k, c in graphs.items()}
+    reqs = []
+    for _ in range(count):
+        u = rng.random()
+        if u < 0.1:
+            reqs.append((SERVE_CC[0], "cc", 0))
+            continue
+        name = names[int(rng.choice(len(names), p=share))]
+        src = int(rng.choice(senders[name]))
+        reqs.append((name, "sssp" if u < 0.8 else "ppr", src))
+    return reqs
+
+
+def bench_serve(args, dev):
+    """Request serving on resident graphs.  Baseline: every request run alone
+    with vc_run, one after another (first-come-first-served, one stream).
+    Server: lane tables (continuous batching) and worker threads, CC / SSSP
+    routed between them by expected completion time, PPR on the workers.  Reports saturation throughput (all requests queued at once) and the
+    latency of an open-loop Poisson arrival stream at 80% of the baseline's
+    capacity, the baseline's latencies simulated from its measured service
+    times on the same arrival times."""
+    import torch
+    import rmatgen
+    from paper_2010_01542_amd import Graph, Server, vc
+    t = time.time()
+    csrs = {}
+    for name, scale, directed, weighted, _, _ in SERVE_GRAPHS:
+        csrs[name] = rmatgen.rmat(scale, 16, seed=rmatgen.BASE_SEED + scale, directed=directed, weighted=weighted,
+                                  threads=args.gen_threads)
+    name, scale, directed, weighted, _ = SERVE_CC
+    csrs[name] = rmatgen.rmat(scale, 16, seed=rmatgen.BASE_SEED + 100 + scale, directed=directed,
+                              weighted=weighted, threads=args.gen_threads)
+    log(f"generated serving graphs in {time.time() - t:.1f}s: " +
+        ", ".join(f"{k} n={c.n} m={c.m}" for k, c in csrs.items()))
+    graphs = {k: Graph.from_csr(c, device=dev, symmetric=(k == SERVE_CC[0])) for k, c in csrs.items()}
+    reqs = serve_requests(args.requests, csrs, rmatgen.BASE_SEED + 5)
+    pool = {}
+
+    def out_for(i, name, prog):
+        key = (name, prog == "ppr", i)
+        if key not in pool:
+            pool[key] = torch.empty(csrs[name].n, dtype=torch.float32 if prog == "ppr" else torch.int32, device=dev)
+        return pool[key]
+
+    # baseline: each request alone, in order (warm-up: one of each kind first)
+    for name, prog, src in {(r[0], r[1]): r for r in reqs}.values():
+        graphs[name].run(prog, out_for(0, name, prog), source=src, T=20)
+    torch.cuda.synchronize()
+    service = np.zeros(len(reqs))
+    t0 = time.perf_counter()
+    for i, (name, prog, src) in enumerate(reqs):
+        a = time.perf_counter()
+        graphs[name].run(prog, out_for(0, name, prog), source=src, T=20)
+        service[i] = time.perf_counter() - a
+    base_s = time.perf_counter() - t0
+    log(f"sequential: {len(reqs)} requests in {base_s:.2f}s")
+    checks = [i for i in range(len(reqs)) if reqs[i][1] != "ppr"][:8]
+    ref = {}
+    for i in checks:
+        name, prog, src = reqs[i]
+        ref[i] = graphs[name].run(prog, source=src)[0].cpu()
+
+    def run_server(arrivals):
+        """Submits request i at arrivals[i] (seconds from start); returns the
+        makespan and per-request latencies (submit -> result complete)."""
+        srv = Server(workers=args.workers)
+        ids = {k: srv.add_graph(g, lanes=(SERVE_CC[4] if k == SERVE_CC[0] else
+                                          dict((x[0], x[4]) for x in SERVE_GRAPHS)[k])) for k, g in graphs.items()}
+        outs = [out_for(i, name, prog) for i, (name, prog, _) in enumerate(reqs)]
+        lat = np.zeros(len(reqs))
+        lanes_used = 0
+        tick = {}
+        t_start = time.perf_counter()
+        got = 0
+        for i, (name, prog, src) in enumerate(reqs):
+            wait = arrivals[i] - (time.perf_counter() - t_start)
+            while wait > 0:
+                for c in srv.poll(timeout_ms=max(1, int(wait * 1e3)), cap=1024):
+                    lat[tick[c.ticket]] = c.latency_ms
+                    lanes_used += c.lane >= 0
+                    got += 1
+                    assert c.status == vc.OK, c.message
+                wait = arrivals[i] - (time.perf_counter() - t_start)
+            tick[srv.submit(ids[name], prog, outs[i], source=src, T=20)] = i
+        while got < len(reqs):
+            for c in srv.poll(timeout_ms=1000, cap=1024):
+                lat[tick[c.ticket]] = c.latency_ms
+                lanes_used += c.lane >= 0
+                got += 1
+                assert c.status == vc.OK, c.message
+        span = time.perf_counter() - t_start
+        info = srv.info()
+        srv.close()
+        for i in checks:
+            assert torch.equal(outs[i].cpu(), ref[i]), f"served request {i} differs from its alone run"
+        return span, lat, info, lanes_used
+
+    span, lat_sat, info, lanes_used = run_server(np.zeros(len(reqs)))
+    log(f"server, all queued: {len(reqs)} requests in {span:.2f}s; {info}")
+    rate = 0.8 * len(reqs) / base_s
+    gaps = np.random.default_rng(rmatgen.BASE_SEED + 6).exponential(1.0 / rate, len(reqs))
+    arrivals = np.cumsum(gaps) - gaps[0]
+    span_open, lat_open, info_open, lanes_open = run_server(arrivals)
+    # the baseline on the same arrivals: one FIFO server with the measured service times
+    fin, lat_base = 0.0, np.zeros(len(reqs))
+    for i in range(len(reqs)):
+        fin = max(fin, arrivals[i]) + service[i]
+        lat_base[i] = (fin - arrivals[i]) * 1e3
+    kinds = {}
+    for (name, prog, _), s in zip(reqs, service):
+        kinds.setdefault(f"{prog}@{name}", []).append(s * 1e3)
+
+    def pct(a, q):
+        return round(float(np.percentile(a, q)), 3)
+
+    def by_kind(lat):
+        out = {}
+        for i, (name, prog, _) in enumerate(reqs):
+            out.setdefault(f"{prog}@{name}", []).append(lat[i])
+        return {k: [pct(v, 50), pct(v, 99)] for k, v in sorted(out.items())}
+
+    return {
+        "metric": "served requests/s (70% SSSP, 20% PPR T=20, 10% CC on resident R-MAT graphs)",
+        "value": round(len(reqs) / span, 2), "unit": "requests/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(span * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32+f32", "data": "synthetic R-MAT (seeded)",
+        "config": {"workload": f"serve-{len(reqs)}", "graphs": {k: [c.n, c.m] for k, c in csrs.items()},
+                   "lanes": {k: (SERVE_CC[4] if k == SERVE_CC[0] else dict((x[0], x[4]) for x in SERVE_GRAPHS)[k])
+                             for k in csrs}, "workers": args.workers},
+        "sequential": {"requests_per_s": round(len(reqs) / base_s, 2),
+                       "service_ms_mean": {k: round(float(np.mean(v)), 3) for k, v in kinds.items()}},
+        "speedup_vs_sequential": round(base_s / span, 2),
+        "saturated": {"latency_ms_p50": pct(lat_sat, 50), "latency_ms_p99": pct(lat_sat, 99),
+                      "p50_p99_by_kind": by_kind(lat_sat),
+                      "lane_requests": lanes_used, "lane_supersteps": info["lane_supersteps"]},
+        "open_loop": {"arrival_rate_per_s": round(rate, 2), "latency_ms_p50": pct(lat_open, 50),
+                      "latency_ms_p99": pct(lat_open, 99), "sequential_latency_ms_p50": pct(lat_base, 50),
+                      "sequential_latency_ms_p99": pct(lat_base, 99), "makespan_s": round(span_open, 3),
+                      "lane_requests": lanes_open, "lane_supersteps": info_open["lane_supersteps"],
+                      "p50_p99_by_kind": by_kind(lat_open), "sequential_p50_p99_by_kind": by_kind(lat_base)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sssp-s26", choices=["sssp-s26", "cc-s22", "pr-s16", "batch", "multi"])
+    ap.add_argument("--workload", default="sssp-s26", choices=["sssp-s26", "cc-s22", "pr-s16", "batch", "multi", "serve"])
     ap.add_argument("--sources", type=int, default=256, help="multi workload: SSSP sources")
     ap.add_argument("--members", type=int, default=1024, help="batch workload: number of graphs")
+    ap.add_argument("--requests", type=int, default=600, help="serve workload: number of requests")
+    ap.add_argument("--workers", type=int, default=4, help="serve workload: worker threads")
     ap.add_argument("--scale", type=int, default=None, help="override the graph scale (same shape)")
     ap.add_argument("--schedule", default="auto", choices=["auto", "vertex", "edge", "pull"])
     ap.add_argument("--tile", type=int, default=0)
@@ -230,8 +410,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
-              "(multi-GPU sharding is a design note, not an implemented path).", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(libvc runs on one GPU; sharding across GPUs is not implemented).", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -245,6 +425,9 @@ def main():
         return
     if args.workload == "multi":
         print(json.dumps(bench_multi(args, dev)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps(bench_serve(args, dev)), flush=True)
         return
     t = time.time()
     csr = rmatgen.workload(args.workload, scale=args.scale, threads=args.gen_threads)

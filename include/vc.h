@@ -285,15 +285,28 @@ vc_status vc_graph_autotune(vc_graph g, vc_program program, const vc_params* bas
  * Min programs (CC, SSSP) on a graph registered with lanes > 0 are served by
  * continuous batching: the graph keeps an N x lanes value / mailbox table
  * and one thread runs its superstep loop with every occupied lane side by
- * side, in the pull form of the min combiner (paper, Sections III and
- * VI-C).  A lane whose program has quiesced (no active vertex with an
+ * side, with the min combiner (paper, Section III) in the push form while
+ * few vertices are active and in the pull form (Section VI-C) otherwise.  A lane whose program has quiesced (no active vertex with an
  * out-edge) is retired after the superstep that found it so, its column is
  * copied to the request's `out`, and a waiting request is seeded into it
  * before the next superstep.  A lane's values, superstep count and status
  * are exactly those of the same request run alone with vc_run.
  *
- * Every other request (PageRank, PPR, and min programs on graphs without
- * lanes) runs on one of `workers` threads, each with its own stream and a
+ * PageRank / PPR requests on a graph registered with rank_lanes > 0 are
+ * batched the same way: every busy lane takes one rank update per superstep
+ * (sum combiner in exact fixed point, so a lane's ranks equal the request
+ * run alone bit for bit) and retires after its T-th.  Requests with
+ * VC_OPT_F32_ACCUMULATE or T = 0 run on workers.
+ *
+ * Lanes pay off under load: a superstep costs about the same however many
+ * lanes are busy.  With VC_ROUTE_AUTO a CC / SSSP request goes to the lane
+ * table only while its expected completion there (running means of the
+ * table's superstep time and supersteps per request) beats the worker path
+ * (the backlog of queued and running worker jobs plus the mean worker time
+ * of the program on that graph).
+ *
+ * Every other request (PageRank, PPR, and min programs routed to workers)
+ * runs on one of `workers` threads, each with its own stream and a
  * private workspace that shares the graph's read-only arrays.  A worker
  * takes the oldest waiting request once its workspace fits the HBM budget
  * (admission by footprint), first dropping workspaces it keeps for other
@@ -312,11 +325,18 @@ typedef struct {
                            the device memory free at creation) */
 } vc_server_config;
 
+/* Path of a CC / SSSP request on a graph with a lane table. */
+typedef enum {
+  VC_ROUTE_AUTO = 0,   /* the path with the shorter expected completion time */
+  VC_ROUTE_LANES = 1,  /* the lane table */
+  VC_ROUTE_WORKER = 2  /* a worker */
+} vc_route;
+
 typedef struct {
   uint32_t struct_size; /* sizeof(vc_request) */
   int32_t graph;        /* id from vc_server_add_graph */
   vc_program program;
-  int32_t reserved;
+  vc_route route;       /* lane table or worker (graphs with lane tables only) */
   vc_params params;     /* as vc_run; lanes honour source and max_supersteps only */
   void* out;            /* device, N x 4 bytes, caller-owned, untouched by the
                            caller until the request completes */
@@ -343,20 +363,27 @@ typedef struct {
   uint64_t bytes_held;     /* worker workspaces */
   uint64_t submitted, completed;
   int64_t lane_supersteps; /* supersteps run by all lane tables */
+  int64_t lane_push_supersteps; /* of which pushed from a broadcast list */
   int64_t lane_requests;   /* requests served by lanes */
+  int64_t rank_supersteps; /* supersteps run by all rank lane tables */
+  int64_t rank_requests;   /* requests served by rank lanes */
 } vc_server_info;
 
 /* Creates a server on the current device.  config: host, may be NULL.
  * Errors: VC_ERR_INVALID_ARG, VC_ERR_HIP. */
 vc_status vc_server_create(const vc_server_config* config, vc_server* out);
 
-/* Registers a graph (borrowed: it must outlive the server).  lanes: 0, or a
- * multiple of 64 up to 256: width of the graph's lane table, reserved from
- * the budget now (8 bytes per vertex and lane plus 16 per vertex and 64
- * lanes).  Builds the graph's transpose if needed.  *id: host.
- * Errors: VC_ERR_INVALID_ARG (null, bad lanes, graph on another device),
- * VC_ERR_OUT_OF_MEMORY (lane table over budget), VC_ERR_HIP. */
-vc_status vc_server_add_graph(vc_server s, vc_graph g, int32_t lanes, int32_t* id);
+/* Registers a graph (borrowed: it must outlive the server).
+ *   lanes       0, or a multiple of 64 up to 256: width of the graph's CC /
+ *               SSSP lane table (8 bytes per vertex and lane, 16 per vertex
+ *               and 64 lanes, about 12 per vertex for the broadcast list).
+ *   rank_lanes  likewise for its PageRank / PPR lane table (16 bytes per
+ *               vertex and lane).
+ * Both tables are reserved from the budget now.  Builds the graph's
+ * transpose if needed.  *id: host.
+ * Errors: VC_ERR_INVALID_ARG (null, bad lane count, graph on another
+ * device), VC_ERR_OUT_OF_MEMORY (tables over budget), VC_ERR_HIP. */
+vc_status vc_server_add_graph(vc_server s, vc_graph g, int32_t lanes, int32_t rank_lanes, int32_t* id);
 
 /* Queues a request.  The request is checked here (graph id, program,
  * params, out); a bad request returns VC_ERR_INVALID_ARG and is not queued.

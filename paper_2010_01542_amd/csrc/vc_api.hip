@@ -827,8 +827,9 @@ vc_status vc_graph_destroy(vc_graph g) {
   for (DevBuf* b : {&g->own_off, &g->own_dst, &g->own_w, &g->perm, &g->inv, &g->rel_off, &g->rel_dst, &g->rel_w,
                     &g->contrib, &g->mb, &g->vm, &g->bitmap, &g->bitmap2,
                     &g->fq, &g->prefix, &g->scan_blocks, &g->list_tiles, &g->csc_off, &g->csc_src,
-                    &g->csc_w, &g->ms_d, &g->ms_mb, &g->ms_a0, &g->ms_a1, &g->ms_src, &g->counters})
+                    &g->csc_w, &g->ms_src, &g->counters})
     b->release();
+  g->ms.release();
   g->dense_parts.release();
   g->csc_parts.release();
   g->loop_state.release();
@@ -853,8 +854,9 @@ vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held,
                 g->rel_off.bytes + g->rel_dst.bytes + g->rel_w.bytes;
   for (const DevBuf* b : {&g->contrib, &g->mb, &g->vm, &g->bitmap, &g->bitmap2, &g->fq, &g->prefix, &g->scan_blocks,
                           &g->list_tiles, &g->csc_off, &g->csc_src, &g->csc_w,
-                          &g->ms_d, &g->ms_mb, &g->ms_a0, &g->ms_a1, &g->ms_src, &g->counters})
+                          &g->ms_src, &g->counters})
     held += b->bytes;
+  held += g->ms.bytes();
   held += g->dense_parts.bytes() + g->csc_parts.bytes();
   if (bytes_held) *bytes_held = held;
   if (bytes_run) {
@@ -1074,47 +1076,28 @@ vc_status vc_run_multi_source(vc_graph g, const uint32_t* sources, int32_t k, co
     stats->edges_relaxed = 0;
   }
   Recorder rec(stats);
-  const int64_t n = g->n, m = g->m;
+  const int64_t n = g->n;
   const int C = vc::ms_chunks(k);
-  const int64_t K = 64 * (int64_t)C;
   const int64_t nwords = (n + 31) / 32;
-  VC_TRY(g->ms_d.ensure((size_t)(n * K) * 4));
-  VC_TRY(g->ms_mb.ensure((size_t)(n * K) * 4));
-  VC_TRY(g->ms_a0.ensure((size_t)(n * C) * 8));
-  VC_TRY(g->ms_a1.ensure((size_t)(n * C) * 8));
   VC_TRY(g->ms_src.ensure((size_t)k * 4));
-  VC_TRY(g->bitmap.ensure((size_t)nwords * 4));
-  VC_TRY(g->counters.ensure(sizeof(vc::Counters)));
-  if (!g->host_ctr) VC_TRY(hipHostMalloc((void**)&g->host_ctr, sizeof(vc::Counters), hipHostMallocDefault));
   {
     vc_status st = ensure_csc(g, s);
-    if (st != VC_OK) return st;
-    st = csc_partition(g, vc::pull_tile(pick_tile(p, g)), s);
+    if (st == VC_OK) st = vc::ms_reset(g->ms, g, C, s);
     if (st != VC_OK) return st;
   }
-  uint32_t* D = g->ms_d.as<uint32_t>();
-  uint32_t* MB = g->ms_mb.as<uint32_t>();
-  unsigned long long* A[2] = {g->ms_a0.as<unsigned long long>(), g->ms_a1.as<unsigned long long>()};
-  uint32_t* bits = g->bitmap.as<uint32_t>();
-  vc::Counters* ctr = g->counters.as<vc::Counters>();
-  VC_TRY(vc::launch_fill_u32(D, n * K, vc::kInf, s));
-  VC_TRY(vc::launch_fill_u32(MB, n * K, vc::kInf, s));
-  VC_TRY(vc::launch_fill_u32(reinterpret_cast<uint32_t*>(A[0]), 2 * n * C, 0u, s));
-  VC_TRY(vc::launch_fill_u32(reinterpret_cast<uint32_t*>(A[1]), 2 * n * C, 0u, s));
-  VC_TRY(vc::launch_fill_u32(bits, nwords, 0u, s));
+  vc::MsState& ms = g->ms;
+  vc::Counters* ctr = ms.ctr.as<vc::Counters>();
   VC_TRY(vc::launch_zero_counters(ctr, s));
   VC_TRY(hipMemcpyAsync(g->ms_src.p, sources, (size_t)k * 4, hipMemcpyHostToDevice, s));
-  VC_TRY(vc::launch_ms_seed(C, g->ms_src.as<int32_t>(), g->relabeled ? g->perm_p : nullptr, k, D, A[0],
-                            bits, s));
-  VC_TRY(vc::launch_ms_count(g->off, g->off64, n, bits, ctr, s));
-  VC_TRY(vc::launch_fill_u32(bits, nwords, 0u, s));
-  VC_TRY(hipMemcpyAsync(g->host_ctr, ctr, sizeof(vc::Counters), hipMemcpyDeviceToHost, s));
-  VC_TRY(vc::launch_zero_counters(ctr, s));
+  VC_TRY(vc::launch_ms_seed(g->ms_src.as<int32_t>(), g->relabeled ? g->perm_p : nullptr, k, n, ms.D.as<uint32_t>(),
+                            ms.A[0].as<unsigned long long>(), ms.bits.as<uint32_t>(), s));
+  VC_TRY(vc::launch_ms_count(g->off, g->off64, n, ms.bits.as<uint32_t>(), ctr, s));
+  VC_TRY(vc::launch_fill_u32(ms.bits.as<uint32_t>(), nwords, 0u, s));
+  VC_TRY(hipMemcpyAsync(ms.host, ctr, sizeof(vc::Counters), hipMemcpyDeviceToHost, s));
   VC_TRY(hipStreamSynchronize(s));
   if (rec.timed) VC_TRY(ensure_events(g, 4));
-  int64_t frontier = (int64_t)g->host_ctr->active, edges = (int64_t)g->host_ctr->edges;
+  int64_t frontier = (int64_t)ms.host[0].active, edges = (int64_t)ms.host[0].edges;
   const int64_t cap = p.max_supersteps > 0 ? (int64_t)p.max_supersteps : n + 1;
-  const bool weighted = g->w != nullptr;
   vc_status status = VC_OK;
   int cur = 0;
   int64_t step = 0;
@@ -1125,26 +1108,21 @@ vc_status vc_run_multi_source(vc_graph g, const uint32_t* sources, int32_t k, co
       supersteps = (int32_t)(step + 1);
       break;
     }
-    rec.step(step, frontier, edges, VC_SCHED_PULL);
     const bool timed = rec.want_time(step);
     if (timed) VC_TRY(hipEventRecord(g->events[0], s));
-    VC_TRY(vc::launch_ms_pull(C, weighted, g->csc_off_p, g->in_src, g->in_w, n, m,
-                              g->csc_tiles_p, g->csc_tile, g->csc_ntiles, D, MB, A[cur], bits, vc::LaneMask{}, s));
-    if (timed) VC_TRY(hipEventRecord(g->events[1], s));
-    VC_TRY(vc::launch_fill_u32(reinterpret_cast<uint32_t*>(A[1 - cur]), 2 * n * C, 0u, s));
-    VC_TRY(vc::launch_ms_apply(C, g->off, g->off64, n, D, MB, A[1 - cur], bits, ctr, nullptr, s));
+    bool pushed = false;
+    vc_status st = vc::ms_superstep(ms, g, cur, C, edges, false, vc::LaneMask{}, nullptr, &pushed, s);
+    if (st != VC_OK) return st;
     if (timed) VC_TRY(hipEventRecord(g->events[2], s));
-    VC_TRY(hipMemcpyAsync(g->host_ctr, ctr, sizeof(vc::Counters), hipMemcpyDeviceToHost, s));
-    VC_TRY(vc::launch_zero_counters(ctr, s));
     VC_TRY(hipStreamSynchronize(s));
+    rec.step(step, frontier, edges, pushed ? VC_SCHED_EDGE : VC_SCHED_PULL);
     if (timed) {
-      float a = 0, b = 0;
-      VC_TRY(hipEventElapsedTime(&a, g->events[0], g->events[1]));
+      float b = 0;
       VC_TRY(hipEventElapsedTime(&b, g->events[0], g->events[2]));
-      rec.times(step, a, b);
+      rec.times(step, b, b);
     }
-    frontier = (int64_t)g->host_ctr->active;
-    edges = (int64_t)g->host_ctr->edges;
+    frontier = (int64_t)ms.host[0].active;
+    edges = (int64_t)ms.host[0].edges;
     cur = 1 - cur;
     ++step;
     if (step >= cap) {
@@ -1153,7 +1131,7 @@ vc_status vc_run_multi_source(vc_graph g, const uint32_t* sources, int32_t k, co
       break;
     }
   }
-  VC_TRY(vc::launch_ms_output(C, D, g->relabeled ? g->perm_p : nullptr, n, k, out, s));
+  VC_TRY(vc::launch_ms_output(ms.D.as<uint32_t>(), g->relabeled ? g->perm_p : nullptr, n, k, out, s));
   VC_TRY(hipStreamSynchronize(s));
   if (stats) {
     stats->supersteps = supersteps;

@@ -73,5 +73,15 @@ __host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) & ~(siz
 
 inline unsigned grid_for(int64_t count) { return (unsigned)((count + kWG - 1) / kWG); }
 
+// Grid of a grid-stride loop over `count` items.  A dispatch counts its
+// work-items in 32 bits, so one thread per item fails beyond 2^32 items;
+// 2^20 workgroups stay far below that and still give every CU thousands of
+// waves.
+inline unsigned grid_stride_for(int64_t count) {
+  const int64_t g = (count + kWG - 1) / kWG;
+  return (unsigned)(g < (1 << 20) ? g : (1 << 20));
+}
+__device__ __forceinline__ int64_t grid_threads() { return (int64_t)gridDim.x * blockDim.x; }
+
 }  // namespace dev
 }  // namespace vc

@@ -77,6 +77,48 @@ struct PartCache {
   void release() { parts.clear(); }
 };
 
+// Device state of a many-lane min-plus superstep loop (many-source SSSP,
+// request-server lane tables): lanes form cs chunks of 64, and every array
+// is chunk-major (chunk c of vertex v at c * n + v; a value row is 64
+// lanes), so a loop whose busy lanes sit in the first ceff chunks touches
+// only a prefix of each array.
+struct MsState {
+  int64_t n = 0, m = 0;
+  int cs = 0;
+  DevBuf D, MB, A[2], bits, list, P, scan_blocks, push_tiles, ctr;
+  DevBuf pull_tiles[4];              // pull partitions for 1..4 chunks
+  int64_t pull_ntiles[4] = {0, 0, 0, 0};
+  int dirty[2] = {0, 0};             // chunks of A[b] that may hold set bits
+  Counters* host = nullptr;          // pinned: [0] apply counters, [1] broadcast-list counters
+  MsState() = default;
+  MsState(const MsState&) = delete;
+  MsState& operator=(const MsState&) = delete;
+  ~MsState() { release(); }
+  void release();
+  size_t bytes() const;
+};
+
+// Lane-step tiles: a pull tile of 512 items per chunk keeps the LDS of one
+// wavefront at 4 KiB; push tiles are small so a sparse frontier still
+// spreads over many wavefronts.
+constexpr int64_t kMsPullTilePerChunk = 512;
+constexpr int64_t kMsPushTile = 256;
+// A superstep is pushed from a broadcast list while its active vertices'
+// out-edges stay below this fraction of all edges, else pulled.
+constexpr double kMsPullFraction = 0.05;
+
+// Allocates st for (g, cs) and resets every lane to unreached with no
+// active vertex.  Needs g's transpose.
+vc_status ms_reset(MsState& st, vc_graph g, int cs, hipStream_t s);
+// One superstep over the first ceff chunks (seeds already in A[cur]): push
+// from a compacted broadcast list when force_pull is false and the active
+// vertices' out-edges (next_edges estimates them; counted exactly before a
+// push) stay below kMsPullFraction * m, else pull; then apply into
+// A[1 - cur].  The apply counters are copied to st.host[0] on s; the caller
+// synchronises s before reading them.
+vc_status ms_superstep(MsState& st, vc_graph g, int cur, int ceff, int64_t next_edges, bool force_pull,
+                       const LaneMask& zero, unsigned long long* live, bool* pushed, hipStream_t s);
+
 }  // namespace vc
 
 struct vc_graph_s {
@@ -113,7 +155,8 @@ struct vc_graph_s {
   const uint32_t* in_w = nullptr;
   bool csc_ready = false;
   int64_t csc_tile = 0, csc_ntiles = 0;
-  vc::DevBuf ms_d, ms_mb, ms_a0, ms_a1, ms_src;  // many-source SSSP: distances, mailboxes, lane masks
+  vc::MsState ms;                                 // many-source SSSP
+  vc::DevBuf ms_src;
   // captured superstep loops (HIP graphs), replayed on the caller's stream
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t min_exec[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};

@@ -136,35 +136,49 @@ hipError_t launch_unpermute(const uint32_t* vals, int64_t stride, const int32_t*
                             hipStream_t s);
 
 // ---------------------------------------------------------------- many sources
-// K sources run side by side in an N x (64 * C) distance matrix.
+// Up to 256 lanes side by side in cs chunks of 64; values, mailboxes and
+// masks chunk-major (chunk c of vertex v at c * n + v, value rows of 64).
+// The superstep itself (pull / push / apply) is driven by ms_superstep.
 int ms_chunks(int k);
-hipError_t launch_ms_seed(int C, const int32_t* src, const int32_t* perm, int k_real, uint32_t* D,
-                          unsigned long long* A, uint32_t* bits, hipStream_t s);
 // One bit per lane (chunk c holds lanes 64c .. 64c + 63), passed by value.
 struct LaneMask {
   unsigned long long bits[4];
 };
-// zero: lanes whose edges cost nothing (CC lanes of the request server).
-hipError_t launch_ms_pull(int C, bool weighted, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w,
-                          int64_t n, int64_t m, const int32_t* tile_v, int64_t tile, int64_t ntiles,
-                          const uint32_t* D, uint32_t* MB, const unsigned long long* A, uint32_t* improved,
-                          const LaneMask& zero, hipStream_t s);
-// live: NULL, or 64 * C words that collect the OR of the new active masks.
-hipError_t launch_ms_apply(int C, const void* off, bool off64, int64_t n, uint32_t* D, uint32_t* MB,
-                           unsigned long long* A_next, uint32_t* improved, Counters* ctr, unsigned long long* live,
-                           hipStream_t s);
+hipError_t launch_ms_seed(const int32_t* src, const int32_t* perm, int k_real, int64_t n, uint32_t* D,
+                          unsigned long long* A, uint32_t* bits, hipStream_t s);
 hipError_t launch_ms_count(const void* off, bool off64, int64_t n, const uint32_t* bits, Counters* ctr,
                            hipStream_t s);
-hipError_t launch_ms_output(int C, const uint32_t* D, const int32_t* perm, int64_t n, int k_real, uint32_t* out,
+hipError_t launch_ms_output(const uint32_t* D, const int32_t* perm, int64_t n, int k_real, uint32_t* out,
                             hipStream_t s);
 // Request-server lanes.  ids / perm may be NULL (graph not relabelled).
-hipError_t launch_lane_seed_cc(int C, const void* off, bool off64, const int32_t* ids, int64_t n,
-                               const int32_t* lanes, int r, uint32_t* D, unsigned long long* A, hipStream_t s);
-hipError_t launch_lane_seed_sssp(int C, const void* off, bool off64, const int32_t* perm, const int32_t* seeds, int r,
-                                 uint32_t* D, unsigned long long* A, unsigned long long* stillborn, hipStream_t s);
-hipError_t launch_lane_retire(int C, uint32_t* D, const int32_t* perm, int64_t n, const int32_t* lanes,
+hipError_t launch_lane_seed_cc(const void* off, bool off64, const int32_t* ids, int64_t n, const int32_t* lanes,
+                               int r, uint32_t* D, unsigned long long* A, hipStream_t s);
+hipError_t launch_lane_seed_sssp(const void* off, bool off64, const int32_t* perm, int64_t n, const int32_t* seeds,
+                                 int r, uint32_t* D, unsigned long long* A, unsigned long long* stillborn,
+                                 hipStream_t s);
+hipError_t launch_lane_retire(uint32_t* D, const int32_t* perm, int64_t n, const int32_t* lanes,
                               uint32_t* const* outs, int r, hipStream_t s);
-hipError_t launch_lane_clear(int C, unsigned long long* A, int64_t n, const LaneMask& drop, hipStream_t s);
+hipError_t launch_lane_clear(unsigned long long* A, int64_t n, int cs, const LaneMask& drop, hipStream_t s);
+
+// ---------------------------------------------------------------- rank lanes
+// Per-lane parameters of a PageRank / PPR lane table (device array of 64 *
+// chunks entries, rewritten by the host before every superstep).
+struct RankLane {
+  double damping;
+  double teleport;   // (1 - d) / N for PageRank, (1 - d) for PPR
+  float* out;        // request output, caller's vertex order
+  int32_t source;    // PPR source (caller id), -1 for PageRank
+  int32_t state;     // 0 idle, 1 running, 2 running its last update
+};
+// seeds[2j] = lane, seeds[2j + 1] = PPR source (caller id) or -1; ids[x] =
+// caller id of internal vertex x (NULL: identity).
+hipError_t launch_rl_seed(const void* off, bool off64, const int32_t* ids, int64_t n, const int32_t* seeds, int r,
+                          unsigned long long* contrib, hipStream_t s);
+hipError_t launch_rl_pull(int C, const int64_t* in_off, const int32_t* in_src, int64_t n, int64_t m,
+                          const int32_t* tile_v, int64_t tile, int64_t ntiles, const unsigned long long* contrib,
+                          unsigned long long* mb, hipStream_t s);
+hipError_t launch_rl_apply(const void* off, bool off64, const int32_t* ids, int64_t n, int ceff,
+                           const RankLane* lanes, unsigned long long* contrib, unsigned long long* mb, hipStream_t s);
 
 // In-place exclusive scan of P[0..count) with P[count] = total; `blocks`
 // is scratch of scan_scratch_entries(count) int64 values.

@@ -25,8 +25,7 @@ using namespace dev;
 // ------------------------------------------------------------------ generic
 
 __global__ __launch_bounds__(kWG) void k_fill_u32(uint32_t* __restrict__ p, int64_t count, uint32_t value) {
-  const int64_t i = gid();
-  if (i < count) p[i] = value;
+  for (int64_t i = gid(); i < count; i += grid_threads()) p[i] = value;
 }
 
 __global__ void k_zero_counters(Counters* c) {
@@ -458,7 +457,7 @@ size_t min_mp_lds_bytes(int64_t tile, bool list) {
 
 hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(count)), dim3(kWG), 0, s, p, count, value);
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_stride_for(count)), dim3(kWG), 0, s, p, count, value);
   return hipGetLastError();
 }
 

@@ -1,17 +1,25 @@
-// Many SSSP sources on one graph in one superstep loop.
+// Many min-plus programs on one graph in one superstep loop.
 //
-// K <= 256 sources run side by side: distances form an N x K row-major
-// matrix (K padded to 64 * C), one wavefront lane per source.  Each superstep
-// is the pull form of the min combiner (paper, Section III) applied to all K
-// programs at once: a receiver's row takes, lane by lane, the minimum of
-// dist(u) + w(u, v) over in-neighbours u whose lane improved in the previous
-// superstep (paper, Section I: only vertices that received a better message
-// broadcast).  An in-edge moves one 256-byte row chunk per 64 sources, so the
-// loads are coalesced and no per-lane atomic is needed for receivers owned by
-// one tile.  Per (vertex, chunk) a 64-bit mask records which lanes are
-// active.  Values and mailboxes are separate matrices, so the superstep stays
-// bulk-synchronous.
+// Up to 256 lanes (SSSP sources, or the requests of a server lane table)
+// run side by side, one wavefront lane each, in cs chunks of 64 lanes.
+// Values, mailboxes and per-vertex active masks are chunk-major: chunk c of
+// vertex v sits at c * n + v (a value row holds the chunk's 64 lanes, 256
+// bytes), so loops over the first ceff chunks touch array prefixes only.
+// Each superstep applies the min combiner (paper, Section III) to all lanes
+// at once, either in the pull form (paper, Section VI-C: a receiver's row
+// takes, lane by lane, the minimum of dist(u) + w(u, v) over in-neighbours u
+// whose lane improved in the previous superstep) or, when few vertices are
+// active, in the push form (each active vertex broadcasts along its
+// out-edges, paper, Section I).  Every lane of a wavefront handles the same
+// edge, so row loads are coalesced.  Values and mailboxes are separate
+// arrays, so the superstep stays bulk-synchronous.
+//
+// A lane may run hash-min CC instead of SSSP (paper, Section VI: CC is the
+// min combiner over labels with no edge cost): its column starts at the
+// vertex labels with every vertex active, and a per-lane mask zeroes the
+// edge weight.
 #include "vc_device.h"
+#include "vc_graph.h"
 
 namespace vc {
 namespace {
@@ -49,21 +57,23 @@ __device__ __forceinline__ int owner_of(const int64_t* __restrict__ s_off, int c
   return lo;
 }
 
-// D = MB = unreached; masks and bitmap cleared by the host with fills.
+// Row of chunk c of vertex v in a chunk-major value array.
+__device__ __forceinline__ int64_t row(int c, int64_t n, int64_t v) { return ((int64_t)c * n + v) * 64; }
+
 // Source k (internal id src[k]) starts at distance 0 with lane k active.
-template <int C>
-__global__ void k_ms_seed(const int32_t* __restrict__ src, const int32_t* __restrict__ perm, int k_real,
+__global__ void k_ms_seed(const int32_t* __restrict__ src, const int32_t* __restrict__ perm, int k_real, int64_t n,
                           uint32_t* __restrict__ D, unsigned long long* __restrict__ A, uint32_t* __restrict__ bits) {
-  constexpr int K = 64 * C;
   const int k = threadIdx.x + blockIdx.x * blockDim.x;
   if (k >= k_real) return;
   const int64_t x = perm ? (int64_t)perm[src[k]] : (int64_t)src[k];
-  D[x * K + k] = 0u;
-  atomicOr(&A[x * C + (k >> 6)], 1ull << (k & 63));
+  D[row(k >> 6, n, x) + (k & 63)] = 0u;
+  atomicOr(&A[(int64_t)(k >> 6) * n + x], 1ull << (k & 63));
   atomicOr(&bits[x >> 5], 1u << (x & 31));
 }
 
-// Per receiver v and lane: best = min over active in-neighbours of D[u] + w.
+// Pull: per receiver v and lane, best = min over active in-neighbours of
+// D[u] + w; written to the mailbox when it beats the current value.  One
+// wavefront per chunk walks the tile's in-edges.
 template <int C, bool WEIGHTED>
 __global__ __launch_bounds__(64 * C) void k_ms_pull(const int64_t* __restrict__ in_off,
                                                     const int32_t* __restrict__ in_src,
@@ -72,7 +82,6 @@ __global__ __launch_bounds__(64 * C) void k_ms_pull(const int64_t* __restrict__ 
                                                     const uint32_t* __restrict__ D, uint32_t* __restrict__ MB,
                                                     const unsigned long long* __restrict__ A,
                                                     uint32_t* __restrict__ improved, LaneMask zero) {
-  constexpr int K = 64 * C;
   constexpr int U = 8;
   extern __shared__ __align__(16) unsigned char smem[];
   Tile tl;
@@ -83,6 +92,8 @@ __global__ __launch_bounds__(64 * C) void k_ms_pull(const int64_t* __restrict__ 
   const int c = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const bool zero_w = (zero.bits[c] >> lane) & 1ull;  // CC lane: labels travel without cost
+  const unsigned long long* Ac = A + (int64_t)c * n;
+  const uint32_t* Dc = D + row(c, n, 0) + lane;
   int x = owner_of(s_off, tl.cnt, tl.j0);
   int64_t next = s_off[x + 1];
   uint32_t run = kInf;
@@ -90,7 +101,7 @@ __global__ __launch_bounds__(64 * C) void k_ms_pull(const int64_t* __restrict__ 
     const int64_t v = tl.i0 + xo;
     bool imp = false;
     if (best != kInf) {
-      const int64_t idx = v * K + c * 64 + lane;
+      const int64_t idx = row(c, n, v) + lane;
       if (best < D[idx]) {
         if (s_off[xo] >= tl.j0 && s_off[xo + 1] <= tl.j1) {
           MB[idx] = best;  // every in-edge of v is in this tile
@@ -110,11 +121,11 @@ __global__ __launch_bounds__(64 * C) void k_ms_pull(const int64_t* __restrict__ 
 #pragma unroll
     for (int k = 0; k < U; ++k) u[k] = e0 + k < tl.j1 ? in_src[e0 + k] : 0;
 #pragma unroll
-    for (int k = 0; k < U; ++k) msk[k] = e0 + k < tl.j1 ? A[(int64_t)u[k] * C + c] : 0ull;
+    for (int k = 0; k < U; ++k) msk[k] = e0 + k < tl.j1 ? Ac[u[k]] : 0ull;
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       wv[k] = (WEIGHTED && e0 + k < tl.j1) ? in_w[e0 + k] : 1u;
-      val[k] = ((msk[k] >> lane) & 1ull) ? D[(int64_t)u[k] * K + c * 64 + lane] : kInf;
+      val[k] = ((msk[k] >> lane) & 1ull) ? Dc[(int64_t)u[k] * 64] : kInf;
     }
 #pragma unroll
     for (int k = 0; k < U; ++k) {
@@ -136,39 +147,135 @@ __global__ __launch_bounds__(64 * C) void k_ms_pull(const int64_t* __restrict__ 
   flush(x, run);
 }
 
-// For every improved vertex (one workgroup per bitmap word): adopt the
-// mailbox lane by lane, reset it, record the improved lanes as the vertex's
-// active mask for the next superstep, and count |F| and E.  A vertex without
-// out-edges keeps an empty mask: it has nobody to broadcast to.  live (may be
-// NULL) collects the OR of all masks, spread over 64 words per chunk to keep
-// same-address atomics rare: a lane is live while some word holds its bit.
+// Push: the listed vertices (list[0..items), out-degree prefix P) broadcast
+// along their out-edges, lane by lane, with a test-before-atomic min into
+// the receiver's mailbox.  Edge-balanced merge-path tiles over (list, P);
+// one wavefront per chunk; the loads of U edges are issued together.
+template <int C, bool WEIGHTED, class OffT>
+__global__ __launch_bounds__(64 * C) void k_ms_push(const OffT* __restrict__ off, const int32_t* __restrict__ dst,
+                                                    const uint32_t* __restrict__ w, int64_t n,
+                                                    const int32_t* __restrict__ list, const int64_t* __restrict__ P,
+                                                    int64_t items, int64_t edges, const int32_t* __restrict__ tile_v,
+                                                    int64_t tile, const uint32_t* __restrict__ D,
+                                                    uint32_t* __restrict__ MB, const unsigned long long* __restrict__ A,
+                                                    uint32_t* __restrict__ improved, LaneMask zero) {
+  constexpr int U = 8;
+  extern __shared__ __align__(16) unsigned char smem[];
+  Tile tl;
+  if (!tile_bounds(tile_v, tile, items, edges, &tl)) return;
+  int64_t* s_off = reinterpret_cast<int64_t*>(smem);                                      // cnt + 1 <= tile + 2
+  int64_t* s_base = reinterpret_cast<int64_t*>(smem + align16((size_t)(tile + 2) * 8));   // cnt <= tile + 1
+  int32_t* s_u = reinterpret_cast<int32_t*>(smem + align16((size_t)(tile + 2) * 8) + align16((size_t)(tile + 1) * 8));
+  for (int x = threadIdx.x; x <= tl.cnt; x += 64 * C) {
+    const int64_t p = P[tl.i0 + x];
+    s_off[x] = p;
+    if (x < tl.cnt) {
+      const int32_t u = list[tl.i0 + x];
+      s_u[x] = u;
+      s_base[x] = (int64_t)off[u] - p;  // CSR position of the owner's edge e is e + base
+    }
+  }
+  __syncthreads();
+  const int c = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const bool zero_w = (zero.bits[c] >> lane) & 1ull;
+  const unsigned long long* Ac = A + (int64_t)c * n;
+  const uint32_t* Dc = D + row(c, n, 0) + lane;
+  uint32_t* MBc = MB + row(c, n, 0) + lane;
+  int x = owner_of(s_off, tl.cnt, tl.j0) - 1;
+  int64_t next = tl.j0, base = 0;
+  for (int64_t e0 = tl.j0; e0 < tl.j1; e0 += U) {
+    int32_t v[U], u[U];
+    uint32_t wv[U], du[U], dv[U], mv[U];
+    int64_t eb[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {  // owners of the next U edges (uniform over the wavefront)
+      const int64_t e = e0 + k;
+      while (e < tl.j1 && e >= next) {
+        ++x;
+        next = s_off[x + 1];
+        base = s_base[x];
+      }
+      u[k] = s_u[x < 0 ? 0 : x];
+      eb[k] = e + base;
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) v[k] = e0 + k < tl.j1 ? dst[eb[k]] : 0;
+#pragma unroll
+    for (int k = 0; k < U; ++k) wv[k] = (WEIGHTED && e0 + k < tl.j1) ? w[eb[k]] : 1u;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const unsigned long long msk = e0 + k < tl.j1 ? Ac[u[k]] : 0ull;
+      du[k] = ((msk >> lane) & 1ull) ? Dc[(int64_t)u[k] * 64] : kInf;
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      dv[k] = du[k] != kInf ? Dc[(int64_t)v[k] * 64] : 0u;
+      mv[k] = du[k] != kInf ? MBc[(int64_t)v[k] * 64] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      if (e0 + k < tl.j1) {
+        bool imp = false;
+        if (du[k] != kInf) {
+          const uint32_t cand = zero_w ? du[k] : sat_add(du[k], wv[k]);
+          if (cand < dv[k] && cand < mv[k]) {
+            atomicMin(&MBc[(int64_t)v[k] * 64], cand);
+            imp = true;
+          }
+        }
+        if (__ballot(imp) && lane == 0) atomicOr(&improved[v[k] >> 5], 1u << (v[k] & 31));
+      }
+    }
+  }
+}
+
+// For every improved vertex (one workgroup of four wavefronts per bitmap
+// word, each taking (vertex, chunk) pairs in turn): adopt the mailbox lane
+// by lane, reset it, record the improved lanes as the vertex's active mask
+// for the next superstep, and count |F| and E.  A vertex without out-edges
+// keeps an empty mask: it has nobody to broadcast to.  live (may be NULL)
+// collects the OR of all masks, spread over 64 words per chunk (stride cs)
+// to keep same-address atomics rare: a lane is live while a word holds its
+// bit.
 template <int C, class OffT>
-__global__ __launch_bounds__(64 * C) void k_ms_apply(const OffT* __restrict__ off, int64_t nwords,
-                                                     uint32_t* __restrict__ D, uint32_t* __restrict__ MB,
-                                                     unsigned long long* __restrict__ A_next,
-                                                     uint32_t* __restrict__ improved, Counters* __restrict__ ctr,
-                                                     unsigned long long* __restrict__ live) {
-  constexpr int K = 64 * C;
+__global__ __launch_bounds__(kWG) void k_ms_apply(const OffT* __restrict__ off, int64_t n, int64_t nwords, int cs,
+                                                  uint32_t* __restrict__ D, uint32_t* __restrict__ MB,
+                                                  unsigned long long* __restrict__ A_next,
+                                                  uint32_t* __restrict__ improved, Counters* __restrict__ ctr,
+                                                  unsigned long long* __restrict__ live) {
   const int64_t wi = blockIdx.x;
   if (wi >= nwords) return;
   const uint32_t word = improved[wi];
   if (!word) return;
-  const int c = threadIdx.x >> 6;
+  const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  unsigned long long any = 0;
-  for (uint32_t bits = word; bits; bits &= bits - 1) {
-    const int64_t v = wi * 32 + (__ffs(bits) - 1);
-    const int64_t idx = v * K + c * 64 + lane;
+  const int cnt = __popc(word);
+  unsigned long long any[C];
+#pragma unroll
+  for (int q = 0; q < C; ++q) any[q] = 0;
+  for (int t = wave; t < cnt * C; t += kWG / 64) {
+    const int j = t / C, c = t - j * C;
+    uint32_t b = word;
+    for (int q = 0; q < j; ++q) b &= b - 1;  // j-th set bit
+    const int64_t v = wi * 32 + (__ffs(b) - 1);
+    const int64_t idx = row(c, n, v) + lane;
     const uint32_t mb = MB[idx];
     const bool act = mb < D[idx];
     if (act) D[idx] = mb;
     if (mb != kInf) MB[idx] = kInf;
     const bool sends = off[v + 1] > off[v];
     const unsigned long long mask = sends ? __ballot(act) : 0ull;
-    any |= mask;
-    if (lane == 0) A_next[v * C + c] = mask;
+#pragma unroll
+    for (int q = 0; q < C; ++q)
+      if (q == c) any[q] |= mask;
+    if (lane == 0) A_next[(int64_t)c * n + v] = mask;
   }
-  if (live && any && lane == 0) atomicOr(&live[(wi & 63) * C + c], any);
+  if (live && lane == 0) {
+#pragma unroll
+    for (int q = 0; q < C; ++q)
+      if (any[q]) atomicOr(&live[(wi & 63) * cs + q], any[q]);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long edges = 0;
@@ -176,10 +283,39 @@ __global__ __launch_bounds__(64 * C) void k_ms_apply(const OffT* __restrict__ of
       const int64_t v = wi * 32 + (__ffs(bits) - 1);
       edges += (unsigned long long)((int64_t)off[v + 1] - (int64_t)off[v]);
     }
-    atomicAdd(&ctr->active, (unsigned long long)__popc(word));
+    atomicAdd(&ctr->active, (unsigned long long)cnt);
     if (edges) atomicAdd(&ctr->edges, edges);
     improved[wi] = 0;
   }
+}
+
+// Broadcast list of a push superstep: every vertex with an active lane in
+// the first ceff chunks, with its out-degree (the prefix is scanned after).
+// ctr->listed / ctr->edges receive the list length and its out-edges.
+template <class OffT>
+__global__ __launch_bounds__(kWG) void k_ms_compact(const OffT* __restrict__ off,
+                                                    const unsigned long long* __restrict__ A, int64_t n, int ceff,
+                                                    int32_t* __restrict__ list, int64_t* __restrict__ P,
+                                                    Counters* __restrict__ ctr) {
+  const int64_t x = gid();
+  bool act = false;
+  int64_t deg = 0;
+  if (x < n) {
+    for (int c = 0; c < ceff; ++c) act |= A[(int64_t)c * n + x] != 0ull;
+    if (act) deg = (int64_t)off[x + 1] - (int64_t)off[x];
+  }
+  const unsigned long long b = __ballot(act);
+  const unsigned lane = lane_id();
+  unsigned long long pos = 0;
+  if (lane == 0 && b) pos = atomicAdd(&ctr->listed, (unsigned long long)__popcll(b));
+  pos = __shfl(pos, 0, 64);
+  if (act) {
+    const unsigned long long at = pos + __popcll(b & ((1ull << lane) - 1ull));
+    list[at] = (int32_t)x;
+    P[at] = deg;
+  }
+  const unsigned long long e = block_sum<unsigned long long>((unsigned long long)deg);
+  if (threadIdx.x == 0 && e) atomicAdd(&ctr->edges, e);
 }
 
 // |F_0|, E_0 of the seeded sources (bitmap left in place for the first pull).
@@ -204,44 +340,36 @@ __global__ __launch_bounds__(kWG) void k_ms_count(const OffT* __restrict__ off, 
   }
 }
 
-// out[v * k_real + k] = D[perm[v] * K + k]
-template <int C>
+// out[v * k_real + k] = value of lane k at perm[v]
 __global__ __launch_bounds__(kWG) void k_ms_output(const uint32_t* __restrict__ D, const int32_t* __restrict__ perm,
                                                    int64_t n, int k_real, uint32_t* __restrict__ out) {
-  constexpr int K = 64 * C;
-  const int64_t i = gid();
-  if (i >= n * k_real) return;
-  const int64_t v = i / k_real;
-  const int k = (int)(i - v * k_real);
-  const int64_t x = perm ? (int64_t)perm[v] : v;
-  out[i] = D[x * K + k];
+  for (int64_t i = gid(); i < n * k_real; i += grid_threads()) {
+    const int64_t v = i / k_real;
+    const int k = (int)(i - v * k_real);
+    const int64_t x = perm ? (int64_t)perm[v] : v;
+    out[i] = D[row(k >> 6, n, x) + (k & 63)];
+  }
 }
 
 // Lane seeding, CC: every vertex x takes its label ids[x] (x itself when
 // ids is NULL) in each listed lane and is active there if it has out-edges.
 // One thread per vertex, so the mask update needs no atomic.
-template <int C, class OffT>
+template <class OffT>
 __global__ __launch_bounds__(kWG) void k_lane_seed_cc(const OffT* __restrict__ off, const int32_t* __restrict__ ids,
                                                       int64_t n, const int32_t* __restrict__ lanes, int r,
                                                       uint32_t* __restrict__ D, unsigned long long* __restrict__ A) {
-  constexpr int K = 64 * C;
   const int64_t x = gid();
   if (x >= n) return;
   const uint32_t label = ids ? (uint32_t)ids[x] : (uint32_t)x;
-  unsigned long long acc[C];
-#pragma unroll
-  for (int c = 0; c < C; ++c) acc[c] = 0;
+  unsigned long long acc[4] = {0, 0, 0, 0};
   for (int j = 0; j < r; ++j) {
     const int l = lanes[j];
-    D[x * K + l] = label;
-#pragma unroll
-    for (int c = 0; c < C; ++c)
-      if ((l >> 6) == c) acc[c] |= 1ull << (l & 63);
+    D[row(l >> 6, n, x) + (l & 63)] = label;
+    acc[l >> 6] |= 1ull << (l & 63);
   }
   if (off[x + 1] > off[x]) {
-#pragma unroll
-    for (int c = 0; c < C; ++c)
-      if (acc[c]) A[x * C + c] |= acc[c];
+    for (int c = 0; c < 4; ++c)
+      if (acc[c]) A[(int64_t)c * n + x] |= acc[c];
   }
 }
 
@@ -249,71 +377,58 @@ __global__ __launch_bounds__(kWG) void k_lane_seed_cc(const OffT* __restrict__ o
 // id).  The source starts at 0 and is active if it has out-edges; a lane
 // whose source has none is flagged in stillborn (it ends after one
 // superstep with nothing sent).
-template <int C, class OffT>
+template <class OffT>
 __global__ __launch_bounds__(kWG) void k_lane_seed_sssp(const OffT* __restrict__ off, const int32_t* __restrict__ perm,
-                                                        const int32_t* __restrict__ seeds, int r,
+                                                        int64_t n, const int32_t* __restrict__ seeds, int r,
                                                         uint32_t* __restrict__ D, unsigned long long* __restrict__ A,
                                                         unsigned long long* __restrict__ stillborn) {
-  constexpr int K = 64 * C;
   const int j = (int)gid();
   if (j >= r) return;
   const int l = seeds[2 * j];
   const int64_t src = seeds[2 * j + 1];
   const int64_t x = perm ? (int64_t)perm[src] : src;
-  D[x * K + l] = 0u;
+  D[row(l >> 6, n, x) + (l & 63)] = 0u;
   if (off[x + 1] > off[x])
-    atomicOr(&A[x * C + (l >> 6)], 1ull << (l & 63));
+    atomicOr(&A[(int64_t)(l >> 6) * n + x], 1ull << (l & 63));
   else
     atomicOr(&stillborn[l >> 6], 1ull << (l & 63));
 }
 
-// Lane retirement: outs[j][v] = D[perm[v], lanes[j]], and the column is
-// reset to unreached for the next request of that lane.
-template <int C>
+// Lane retirement: outs[j][v] = value of lane lanes[j] at perm[v], and the
+// lane is reset to unreached for its next request.
 __global__ __launch_bounds__(kWG) void k_lane_retire(uint32_t* __restrict__ D, const int32_t* __restrict__ perm,
                                                      int64_t n, const int32_t* __restrict__ lanes,
                                                      uint32_t* const* __restrict__ outs, int r) {
-  constexpr int K = 64 * C;
-  const int64_t i = gid();
-  if (i >= n * r) return;
-  const int64_t v = i / r;
-  const int j = (int)(i - v * r);
-  const int64_t x = perm ? (int64_t)perm[v] : v;
-  const int64_t idx = x * K + lanes[j];
-  outs[j][v] = D[idx];
-  D[idx] = kInf;
-}
-
-// Clears the listed lanes from every active mask (lanes stopped at their
-// superstep cap while still active).
-template <int C>
-__global__ __launch_bounds__(kWG) void k_lane_clear(unsigned long long* __restrict__ A, int64_t n, LaneMask drop) {
-  const int64_t i = gid();
-  if (i >= n * C) return;
-  const int c = (int)(i % C);
-  if (drop.bits[c]) A[i] &= ~drop.bits[c];
-}
-
-}  // namespace
-
-int ms_chunks(int k) { return (k + 63) / 64; }
-
-hipError_t launch_ms_seed(int C, const int32_t* src, const int32_t* perm, int k_real, uint32_t* D,
-                          unsigned long long* A, uint32_t* bits, hipStream_t s) {
-  switch (C) {
-    case 1: hipLaunchKernelGGL(k_ms_seed<1>, dim3(1), dim3(256), 0, s, src, perm, k_real, D, A, bits); break;
-    case 2: hipLaunchKernelGGL(k_ms_seed<2>, dim3(1), dim3(256), 0, s, src, perm, k_real, D, A, bits); break;
-    case 3: hipLaunchKernelGGL(k_ms_seed<3>, dim3(1), dim3(256), 0, s, src, perm, k_real, D, A, bits); break;
-    default: hipLaunchKernelGGL(k_ms_seed<4>, dim3(1), dim3(256), 0, s, src, perm, k_real, D, A, bits);
+  for (int64_t i = gid(); i < n * r; i += grid_threads()) {
+    const int64_t v = i / r;
+    const int j = (int)(i - v * r);
+    const int64_t x = perm ? (int64_t)perm[v] : v;
+    const int l = lanes[j];
+    const int64_t idx = row(l >> 6, n, x) + (l & 63);
+    outs[j][v] = D[idx];
+    D[idx] = kInf;
   }
-  return hipGetLastError();
 }
 
-namespace {
+// Clears the listed lanes from every active mask of the first cs chunks
+// (lanes stopped at their superstep cap while still active).
+__global__ __launch_bounds__(kWG) void k_lane_clear(unsigned long long* __restrict__ A, int64_t n, int cs,
+                                                    LaneMask drop) {
+  for (int64_t i = gid(); i < n * cs; i += grid_threads()) {
+    const int c = (int)(i / n);
+    if (drop.bits[c]) A[i] &= ~drop.bits[c];
+  }
+}
+
+size_t push_lds_bytes(int64_t tile) {
+  return align16((size_t)(tile + 2) * 8) + align16((size_t)(tile + 1) * 8) + (size_t)(tile + 1) * 4;
+}
+
 template <int C>
-void ms_pull_launch(bool weighted, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w, int64_t n,
-                    int64_t m, const int32_t* tile_v, int64_t tile, int64_t ntiles, const uint32_t* D, uint32_t* MB,
-                    const unsigned long long* A, uint32_t* improved, const LaneMask& zero, hipStream_t s) {
+hipError_t ms_pull_launch(bool weighted, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w,
+                          int64_t n, int64_t m, const int32_t* tile_v, int64_t tile, int64_t ntiles, const uint32_t* D,
+                          uint32_t* MB, const unsigned long long* A, uint32_t* improved, const LaneMask& zero,
+                          hipStream_t s) {
   const size_t lds = (size_t)(tile + 2) * 8;
   if (weighted)
     hipLaunchKernelGGL((k_ms_pull<C, true>), dim3((unsigned)ntiles), dim3(64 * C), lds, s, in_off, in_src, in_w, n, m,
@@ -321,19 +436,37 @@ void ms_pull_launch(bool weighted, const int64_t* in_off, const int32_t* in_src,
   else
     hipLaunchKernelGGL((k_ms_pull<C, false>), dim3((unsigned)ntiles), dim3(64 * C), lds, s, in_off, in_src, in_w, n, m,
                        tile_v, tile, D, MB, A, improved, zero);
+  return hipGetLastError();
 }
-template <int C>
-void ms_apply_launch(const void* off, bool off64, int64_t nwords, uint32_t* D, uint32_t* MB,
-                     unsigned long long* A_next, uint32_t* improved, Counters* ctr, unsigned long long* live,
-                     hipStream_t s) {
-  if (off64)
-    hipLaunchKernelGGL((k_ms_apply<C, int64_t>), dim3((unsigned)nwords), dim3(64 * C), 0, s, (const int64_t*)off,
-                       nwords, D, MB, A_next, improved, ctr, live);
+
+template <int C, class OffT>
+hipError_t ms_push_launch(bool weighted, const OffT* off, const int32_t* dst, const uint32_t* w, int64_t n,
+                          const int32_t* list, const int64_t* P, int64_t items, int64_t edges, const int32_t* tile_v,
+                          int64_t tile, int64_t ntiles, const uint32_t* D, uint32_t* MB, const unsigned long long* A,
+                          uint32_t* improved, const LaneMask& zero, hipStream_t s) {
+  const size_t lds = push_lds_bytes(tile);
+  if (weighted)
+    hipLaunchKernelGGL((k_ms_push<C, true, OffT>), dim3((unsigned)ntiles), dim3(64 * C), lds, s, off, dst, w, n, list,
+                       P, items, edges, tile_v, tile, D, MB, A, improved, zero);
   else
-    hipLaunchKernelGGL((k_ms_apply<C, int32_t>), dim3((unsigned)nwords), dim3(64 * C), 0, s, (const int32_t*)off,
-                       nwords, D, MB, A_next, improved, ctr, live);
+    hipLaunchKernelGGL((k_ms_push<C, false, OffT>), dim3((unsigned)ntiles), dim3(64 * C), lds, s, off, dst, w, n,
+                       list, P, items, edges, tile_v, tile, D, MB, A, improved, zero);
+  return hipGetLastError();
 }
-}  // namespace
+
+template <int C>
+hipError_t ms_apply_launch(const void* off, bool off64, int64_t n, int cs, uint32_t* D, uint32_t* MB,
+                           unsigned long long* A_next, uint32_t* improved, Counters* ctr, unsigned long long* live,
+                           hipStream_t s) {
+  const int64_t nwords = (n + 31) / 32;
+  if (off64)
+    hipLaunchKernelGGL((k_ms_apply<C, int64_t>), dim3((unsigned)nwords), dim3(kWG), 0, s, (const int64_t*)off, n,
+                       nwords, cs, D, MB, A_next, improved, ctr, live);
+  else
+    hipLaunchKernelGGL((k_ms_apply<C, int32_t>), dim3((unsigned)nwords), dim3(kWG), 0, s, (const int32_t*)off, n,
+                       nwords, cs, D, MB, A_next, improved, ctr, live);
+  return hipGetLastError();
+}
 
 hipError_t launch_ms_pull(int C, bool weighted, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w,
                           int64_t n, int64_t m, const int32_t* tile_v, int64_t tile, int64_t ntiles,
@@ -341,24 +474,59 @@ hipError_t launch_ms_pull(int C, bool weighted, const int64_t* in_off, const int
                           const LaneMask& zero, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   switch (C) {
-    case 1: ms_pull_launch<1>(weighted, in_off, in_src, in_w, n, m, tile_v, tile, ntiles, D, MB, A, improved, zero, s); break;
-    case 2: ms_pull_launch<2>(weighted, in_off, in_src, in_w, n, m, tile_v, tile, ntiles, D, MB, A, improved, zero, s); break;
-    case 3: ms_pull_launch<3>(weighted, in_off, in_src, in_w, n, m, tile_v, tile, ntiles, D, MB, A, improved, zero, s); break;
-    default: ms_pull_launch<4>(weighted, in_off, in_src, in_w, n, m, tile_v, tile, ntiles, D, MB, A, improved, zero, s);
+    case 1: return ms_pull_launch<1>(weighted, in_off, in_src, in_w, n, m, tile_v, tile, ntiles, D, MB, A, improved, zero, s);
+    case 2: return ms_pull_launch<2>(weighted, in_off, in_src, in_w, n, m, tile_v, tile, ntiles, D, MB, A, improved, zero, s);
+    case 3: return ms_pull_launch<3>(weighted, in_off, in_src, in_w, n, m, tile_v, tile, ntiles, D, MB, A, improved, zero, s);
+    case 4: return ms_pull_launch<4>(weighted, in_off, in_src, in_w, n, m, tile_v, tile, ntiles, D, MB, A, improved, zero, s);
   }
+  return hipErrorInvalidValue;
+}
+
+template <class OffT>
+hipError_t launch_ms_push(int C, bool weighted, const OffT* off, const int32_t* dst, const uint32_t* w, int64_t n,
+                          const int32_t* list, const int64_t* P, int64_t items, int64_t edges, const int32_t* tile_v,
+                          int64_t tile, int64_t ntiles, const uint32_t* D, uint32_t* MB, const unsigned long long* A,
+                          uint32_t* improved, const LaneMask& zero, hipStream_t s) {
+  if (ntiles <= 0 || edges <= 0) return hipSuccess;
+  switch (C) {
+    case 1: return ms_push_launch<1>(weighted, off, dst, w, n, list, P, items, edges, tile_v, tile, ntiles, D, MB, A, improved, zero, s);
+    case 2: return ms_push_launch<2>(weighted, off, dst, w, n, list, P, items, edges, tile_v, tile, ntiles, D, MB, A, improved, zero, s);
+    case 3: return ms_push_launch<3>(weighted, off, dst, w, n, list, P, items, edges, tile_v, tile, ntiles, D, MB, A, improved, zero, s);
+    case 4: return ms_push_launch<4>(weighted, off, dst, w, n, list, P, items, edges, tile_v, tile, ntiles, D, MB, A, improved, zero, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_ms_apply(int C, int cs, const void* off, bool off64, int64_t n, uint32_t* D, uint32_t* MB,
+                           unsigned long long* A_next, uint32_t* improved, Counters* ctr, unsigned long long* live,
+                           hipStream_t s) {
+  switch (C) {
+    case 1: return ms_apply_launch<1>(off, off64, n, cs, D, MB, A_next, improved, ctr, live, s);
+    case 2: return ms_apply_launch<2>(off, off64, n, cs, D, MB, A_next, improved, ctr, live, s);
+    case 3: return ms_apply_launch<3>(off, off64, n, cs, D, MB, A_next, improved, ctr, live, s);
+    case 4: return ms_apply_launch<4>(off, off64, n, cs, D, MB, A_next, improved, ctr, live, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_ms_compact(const void* off, bool off64, const unsigned long long* A, int64_t n, int ceff,
+                             int32_t* list, int64_t* P, Counters* ctr, hipStream_t s) {
+  if (off64)
+    hipLaunchKernelGGL(k_ms_compact<int64_t>, dim3(grid_for(n)), dim3(kWG), 0, s, (const int64_t*)off, A, n, ceff,
+                       list, P, ctr);
+  else
+    hipLaunchKernelGGL(k_ms_compact<int32_t>, dim3(grid_for(n)), dim3(kWG), 0, s, (const int32_t*)off, A, n, ceff,
+                       list, P, ctr);
   return hipGetLastError();
 }
 
-hipError_t launch_ms_apply(int C, const void* off, bool off64, int64_t n, uint32_t* D, uint32_t* MB,
-                           unsigned long long* A_next, uint32_t* improved, Counters* ctr, unsigned long long* live,
-                           hipStream_t s) {
-  const int64_t nwords = (n + 31) / 32;
-  switch (C) {
-    case 1: ms_apply_launch<1>(off, off64, nwords, D, MB, A_next, improved, ctr, live, s); break;
-    case 2: ms_apply_launch<2>(off, off64, nwords, D, MB, A_next, improved, ctr, live, s); break;
-    case 3: ms_apply_launch<3>(off, off64, nwords, D, MB, A_next, improved, ctr, live, s); break;
-    default: ms_apply_launch<4>(off, off64, nwords, D, MB, A_next, improved, ctr, live, s);
-  }
+}  // namespace
+
+int ms_chunks(int k) { return (k + 63) / 64; }
+
+hipError_t launch_ms_seed(const int32_t* src, const int32_t* perm, int k_real, int64_t n, uint32_t* D,
+                          unsigned long long* A, uint32_t* bits, hipStream_t s) {
+  hipLaunchKernelGGL(k_ms_seed, dim3(1), dim3(256), 0, s, src, perm, k_real, n, D, A, bits);
   return hipGetLastError();
 }
 
@@ -374,87 +542,162 @@ hipError_t launch_ms_count(const void* off, bool off64, int64_t n, const uint32_
   return hipGetLastError();
 }
 
-hipError_t launch_ms_output(int C, const uint32_t* D, const int32_t* perm, int64_t n, int k_real, uint32_t* out,
+hipError_t launch_ms_output(const uint32_t* D, const int32_t* perm, int64_t n, int k_real, uint32_t* out,
                             hipStream_t s) {
-  const int64_t total = n * k_real;
-  switch (C) {
-    case 1: hipLaunchKernelGGL(k_ms_output<1>, dim3(grid_for(total)), dim3(kWG), 0, s, D, perm, n, k_real, out); break;
-    case 2: hipLaunchKernelGGL(k_ms_output<2>, dim3(grid_for(total)), dim3(kWG), 0, s, D, perm, n, k_real, out); break;
-    case 3: hipLaunchKernelGGL(k_ms_output<3>, dim3(grid_for(total)), dim3(kWG), 0, s, D, perm, n, k_real, out); break;
-    default: hipLaunchKernelGGL(k_ms_output<4>, dim3(grid_for(total)), dim3(kWG), 0, s, D, perm, n, k_real, out);
-  }
+  hipLaunchKernelGGL(k_ms_output, dim3(grid_stride_for(n * k_real)), dim3(kWG), 0, s, D, perm, n, k_real, out);
   return hipGetLastError();
 }
 
-namespace {
-template <int C>
-void lane_seed_cc_launch(const void* off, bool off64, const int32_t* ids, int64_t n, const int32_t* lanes, int r,
-                         uint32_t* D, unsigned long long* A, hipStream_t s) {
+hipError_t launch_lane_seed_cc(const void* off, bool off64, const int32_t* ids, int64_t n, const int32_t* lanes,
+                               int r, uint32_t* D, unsigned long long* A, hipStream_t s) {
+  if (r <= 0) return hipSuccess;
   if (off64)
-    hipLaunchKernelGGL((k_lane_seed_cc<C, int64_t>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int64_t*)off, ids, n,
-                       lanes, r, D, A);
+    hipLaunchKernelGGL(k_lane_seed_cc<int64_t>, dim3(grid_for(n)), dim3(kWG), 0, s, (const int64_t*)off, ids, n, lanes,
+                       r, D, A);
   else
-    hipLaunchKernelGGL((k_lane_seed_cc<C, int32_t>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int32_t*)off, ids, n,
-                       lanes, r, D, A);
+    hipLaunchKernelGGL(k_lane_seed_cc<int32_t>, dim3(grid_for(n)), dim3(kWG), 0, s, (const int32_t*)off, ids, n, lanes,
+                       r, D, A);
+  return hipGetLastError();
 }
-template <int C>
-void lane_seed_sssp_launch(const void* off, bool off64, const int32_t* perm, const int32_t* seeds, int r, uint32_t* D,
-                           unsigned long long* A, unsigned long long* stillborn, hipStream_t s) {
+
+hipError_t launch_lane_seed_sssp(const void* off, bool off64, const int32_t* perm, int64_t n, const int32_t* seeds,
+                                 int r, uint32_t* D, unsigned long long* A, unsigned long long* stillborn,
+                                 hipStream_t s) {
+  if (r <= 0) return hipSuccess;
   if (off64)
-    hipLaunchKernelGGL((k_lane_seed_sssp<C, int64_t>), dim3(grid_for(r)), dim3(kWG), 0, s, (const int64_t*)off, perm,
+    hipLaunchKernelGGL(k_lane_seed_sssp<int64_t>, dim3(grid_for(r)), dim3(kWG), 0, s, (const int64_t*)off, perm, n,
                        seeds, r, D, A, stillborn);
   else
-    hipLaunchKernelGGL((k_lane_seed_sssp<C, int32_t>), dim3(grid_for(r)), dim3(kWG), 0, s, (const int32_t*)off, perm,
+    hipLaunchKernelGGL(k_lane_seed_sssp<int32_t>, dim3(grid_for(r)), dim3(kWG), 0, s, (const int32_t*)off, perm, n,
                        seeds, r, D, A, stillborn);
-}
-}  // namespace
-
-hipError_t launch_lane_seed_cc(int C, const void* off, bool off64, const int32_t* ids, int64_t n,
-                               const int32_t* lanes, int r, uint32_t* D, unsigned long long* A, hipStream_t s) {
-  if (r <= 0) return hipSuccess;
-  switch (C) {
-    case 1: lane_seed_cc_launch<1>(off, off64, ids, n, lanes, r, D, A, s); break;
-    case 2: lane_seed_cc_launch<2>(off, off64, ids, n, lanes, r, D, A, s); break;
-    case 3: lane_seed_cc_launch<3>(off, off64, ids, n, lanes, r, D, A, s); break;
-    default: lane_seed_cc_launch<4>(off, off64, ids, n, lanes, r, D, A, s);
-  }
   return hipGetLastError();
 }
 
-hipError_t launch_lane_seed_sssp(int C, const void* off, bool off64, const int32_t* perm, const int32_t* seeds, int r,
-                                 uint32_t* D, unsigned long long* A, unsigned long long* stillborn, hipStream_t s) {
-  if (r <= 0) return hipSuccess;
-  switch (C) {
-    case 1: lane_seed_sssp_launch<1>(off, off64, perm, seeds, r, D, A, stillborn, s); break;
-    case 2: lane_seed_sssp_launch<2>(off, off64, perm, seeds, r, D, A, stillborn, s); break;
-    case 3: lane_seed_sssp_launch<3>(off, off64, perm, seeds, r, D, A, stillborn, s); break;
-    default: lane_seed_sssp_launch<4>(off, off64, perm, seeds, r, D, A, stillborn, s);
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_lane_retire(int C, uint32_t* D, const int32_t* perm, int64_t n, const int32_t* lanes,
+hipError_t launch_lane_retire(uint32_t* D, const int32_t* perm, int64_t n, const int32_t* lanes,
                               uint32_t* const* outs, int r, hipStream_t s) {
   if (r <= 0 || n <= 0) return hipSuccess;
-  const int64_t total = n * r;
-  switch (C) {
-    case 1: hipLaunchKernelGGL(k_lane_retire<1>, dim3(grid_for(total)), dim3(kWG), 0, s, D, perm, n, lanes, outs, r); break;
-    case 2: hipLaunchKernelGGL(k_lane_retire<2>, dim3(grid_for(total)), dim3(kWG), 0, s, D, perm, n, lanes, outs, r); break;
-    case 3: hipLaunchKernelGGL(k_lane_retire<3>, dim3(grid_for(total)), dim3(kWG), 0, s, D, perm, n, lanes, outs, r); break;
-    default: hipLaunchKernelGGL(k_lane_retire<4>, dim3(grid_for(total)), dim3(kWG), 0, s, D, perm, n, lanes, outs, r);
-  }
+  hipLaunchKernelGGL(k_lane_retire, dim3(grid_stride_for(n * r)), dim3(kWG), 0, s, D, perm, n, lanes, outs, r);
   return hipGetLastError();
 }
 
-hipError_t launch_lane_clear(int C, unsigned long long* A, int64_t n, const LaneMask& drop, hipStream_t s) {
-  const int64_t total = n * C;
-  switch (C) {
-    case 1: hipLaunchKernelGGL(k_lane_clear<1>, dim3(grid_for(total)), dim3(kWG), 0, s, A, n, drop); break;
-    case 2: hipLaunchKernelGGL(k_lane_clear<2>, dim3(grid_for(total)), dim3(kWG), 0, s, A, n, drop); break;
-    case 3: hipLaunchKernelGGL(k_lane_clear<3>, dim3(grid_for(total)), dim3(kWG), 0, s, A, n, drop); break;
-    default: hipLaunchKernelGGL(k_lane_clear<4>, dim3(grid_for(total)), dim3(kWG), 0, s, A, n, drop);
-  }
+hipError_t launch_lane_clear(unsigned long long* A, int64_t n, int cs, const LaneMask& drop, hipStream_t s) {
+  hipLaunchKernelGGL(k_lane_clear, dim3(grid_stride_for(n * cs)), dim3(kWG), 0, s, A, n, cs, drop);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- host loop
+
+void MsState::release() {
+  for (DevBuf* b : {&D, &MB, &A[0], &A[1], &bits, &list, &P, &scan_blocks, &push_tiles, &ctr, &pull_tiles[0],
+                    &pull_tiles[1], &pull_tiles[2], &pull_tiles[3]})
+    b->release();
+  if (host) (void)hipHostFree(host);
+  host = nullptr;
+  n = m = 0;
+  cs = 0;
+}
+
+size_t MsState::bytes() const {
+  size_t b = 0;
+  for (const DevBuf* x : {&D, &MB, &A[0], &A[1], &bits, &list, &P, &scan_blocks, &push_tiles, &ctr, &pull_tiles[0],
+                          &pull_tiles[1], &pull_tiles[2], &pull_tiles[3]})
+    b += x->bytes;
+  return b;
+}
+
+vc_status ms_reset(MsState& st, vc_graph g, int cs, hipStream_t s) {
+  if (cs < 1 || cs > 4) return fail(VC_ERR_INVALID_ARG, "lane chunks must be 1..4");
+  if (!g->csc_ready) return fail(VC_ERR_INVALID_ARG, "many-lane loop needs the transpose");
+  if (push_lds_bytes(kMsPushTile) > g->max_lds || (size_t)(4 * kMsPullTilePerChunk + 2) * 8 > g->max_lds)
+    return fail(VC_ERR_UNSUPPORTED, "lane tiles exceed the device's LDS");
+  const int64_t n = g->n, m = g->m;
+  const size_t rows = (size_t)cs * n;
+  VC_TRY(st.D.ensure(rows * 64 * 4));
+  VC_TRY(st.MB.ensure(rows * 64 * 4));
+  VC_TRY(st.A[0].ensure(rows * 8));
+  VC_TRY(st.A[1].ensure(rows * 8));
+  VC_TRY(st.bits.ensure((size_t)((n + 31) / 32) * 4));
+  VC_TRY(st.list.ensure((size_t)n * 4 + 4));
+  VC_TRY(st.P.ensure((size_t)(n + 1) * 8));
+  VC_TRY(st.scan_blocks.ensure((size_t)scan_scratch_entries(n) * 8));
+  VC_TRY(st.push_tiles.ensure((size_t)((n + m) / kMsPushTile + 2) * 4));
+  VC_TRY(st.ctr.ensure(2 * sizeof(Counters)));
+  if (!st.host) VC_TRY(hipHostMalloc((void**)&st.host, 2 * sizeof(Counters), hipHostMallocDefault));
+  if (st.n != n || st.m != m || st.cs < cs) {
+    for (int c = 1; c <= 4; ++c) {
+      if (c > cs) {
+        st.pull_tiles[c - 1].release();
+        st.pull_ntiles[c - 1] = 0;
+        continue;
+      }
+      const int64_t tile = kMsPullTilePerChunk * c;
+      const int64_t ntiles = (n + m + tile - 1) / tile;
+      VC_TRY(st.pull_tiles[c - 1].ensure((size_t)(ntiles + 1) * 4));
+      VC_TRY(launch_mp_partition(g->csc_off_p, true, n, n + m, tile, ntiles, st.pull_tiles[c - 1].as<int32_t>(), s));
+      st.pull_ntiles[c - 1] = ntiles;
+    }
+  }
+  st.n = n;
+  st.m = m;
+  st.cs = cs;
+  VC_TRY(launch_fill_u32(st.D.as<uint32_t>(), (int64_t)rows * 64, kInf, s));
+  VC_TRY(launch_fill_u32(st.MB.as<uint32_t>(), (int64_t)rows * 64, kInf, s));
+  VC_TRY(launch_fill_u32(st.A[0].as<uint32_t>(), (int64_t)rows * 2, 0u, s));
+  VC_TRY(launch_fill_u32(st.A[1].as<uint32_t>(), (int64_t)rows * 2, 0u, s));
+  VC_TRY(launch_fill_u32(st.bits.as<uint32_t>(), (n + 31) / 32, 0u, s));
+  st.dirty[0] = st.dirty[1] = 0;
+  return VC_OK;
+}
+
+vc_status ms_superstep(MsState& st, vc_graph g, int cur, int ceff, int64_t next_edges, bool force_pull,
+                       const LaneMask& zero, unsigned long long* live, bool* pushed, hipStream_t s) {
+  if (ceff < 1 || ceff > st.cs) return fail(VC_ERR_INVALID_ARG, "lane chunks out of range");
+  const int64_t n = st.n, m = st.m;
+  Counters* dctr = st.ctr.as<Counters>();
+  unsigned long long* Acur = st.A[cur].as<unsigned long long>();
+  unsigned long long* Anext = st.A[1 - cur].as<unsigned long long>();
+  uint32_t* D = st.D.as<uint32_t>();
+  uint32_t* MB = st.MB.as<uint32_t>();
+  uint32_t* bits = st.bits.as<uint32_t>();
+  if (st.dirty[cur] < ceff) st.dirty[cur] = ceff;  // seeds
+  const double dense = kMsPullFraction * (double)m;
+  bool pull = force_pull || (double)next_edges >= dense;
+  *pushed = false;
+  if (!pull) {
+    VC_TRY(launch_zero_counters(dctr + 1, s));
+    VC_TRY(launch_ms_compact(g->off, g->off64, Acur, n, ceff, st.list.as<int32_t>(), st.P.as<int64_t>(), dctr + 1, s));
+    VC_TRY(hipMemcpyAsync(st.host + 1, dctr + 1, sizeof(Counters), hipMemcpyDeviceToHost, s));
+    VC_TRY(hipStreamSynchronize(s));
+    const int64_t items = (int64_t)st.host[1].listed, edges = (int64_t)st.host[1].edges;
+    if ((double)edges >= dense) {
+      pull = true;
+    } else if (edges > 0) {
+      int64_t* P = st.P.as<int64_t>();
+      const int64_t ntiles = (items + edges + kMsPushTile - 1) / kMsPushTile;
+      VC_TRY(launch_exclusive_scan(P, items, st.scan_blocks.as<int64_t>(), s));
+      VC_TRY(launch_mp_partition(P, true, items, items + edges, kMsPushTile, ntiles, st.push_tiles.as<int32_t>(), s));
+      if (g->off64)
+        VC_TRY(launch_ms_push(ceff, g->w != nullptr, (const int64_t*)g->off, g->dst, g->w, n, st.list.as<int32_t>(), P,
+                              items, edges, st.push_tiles.as<int32_t>(), kMsPushTile, ntiles, D, MB, Acur, bits, zero,
+                              s));
+      else
+        VC_TRY(launch_ms_push(ceff, g->w != nullptr, (const int32_t*)g->off, g->dst, g->w, n, st.list.as<int32_t>(), P,
+                              items, edges, st.push_tiles.as<int32_t>(), kMsPushTile, ntiles, D, MB, Acur, bits, zero,
+                              s));
+      *pushed = true;
+    }
+  }
+  if (pull)
+    VC_TRY(launch_ms_pull(ceff, g->w != nullptr, g->csc_off_p, g->in_src, g->in_w, n, m,
+                          st.pull_tiles[ceff - 1].as<int32_t>(), kMsPullTilePerChunk * ceff, st.pull_ntiles[ceff - 1],
+                          D, MB, Acur, bits, zero, s));
+  const int clear = st.dirty[1 - cur] > ceff ? st.dirty[1 - cur] : ceff;
+  VC_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(Anext), 2 * n * clear, 0u, s));
+  st.dirty[1 - cur] = ceff;
+  VC_TRY(launch_zero_counters(dctr, s));
+  VC_TRY(launch_ms_apply(ceff, st.cs, g->off, g->off64, n, D, MB, Anext, bits, dctr, live, s));
+  VC_TRY(hipMemcpyAsync(st.host, dctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
+  return VC_OK;
 }
 
 }  // namespace vc

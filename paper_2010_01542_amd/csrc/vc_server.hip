@@ -42,6 +42,17 @@ struct Job {
   uint64_t ticket = 0;
   vc_request req{};
   Clock::time_point submitted, started;
+  double est_ms = 0;  // expected worker service time, counted in the worker backlog
+};
+
+// Running estimate (exponentially weighted mean).
+struct Ema {
+  double v = 0;
+  int64_t n = 0;
+  void add(double x) {
+    v = n ? 0.75 * v + 0.25 * x : x;
+    ++n;
+  }
 };
 
 constexpr int kMaxLanes = 256;
@@ -56,7 +67,6 @@ struct LaneCtl {
   uint32_t* outs[kMaxLanes];     // their requests' outputs
   unsigned long long live[64 * 4];
   unsigned long long stillborn[4];
-  vc::Counters ctr;
 };
 constexpr size_t kCtlIn = offsetof(LaneCtl, live);
 static_assert(kCtlIn % 8 == 0 && (sizeof(LaneCtl) - kCtlIn) % 4 == 0, "control block layout");
@@ -72,8 +82,11 @@ struct Lane {
 
 struct LaneTable {
   vc_graph g = nullptr;
-  int C = 1, K = 64;
-  DevBuf D, MB, A0, A1, bits, ctl;
+  int C = 1, K = 64;     // C chunks of 64 lanes
+  vc::MsState ms;        // values, mailboxes, masks, broadcast list
+  DevBuf ctl;
+  int64_t next_edges = 0;  // out-edges of the vertices the last apply activated
+  Ema step_ms, steps;      // superstep wall time, supersteps per request
   LaneCtl* host = nullptr;  // pinned
   hipStream_t stream = nullptr;
   std::thread th;
@@ -85,10 +98,47 @@ struct LaneTable {
   size_t bytes = 0;
 };
 
+// PageRank / PPR lanes: every busy lane takes one rank update per
+// superstep; a lane retires after its T-th.
+struct RankSlot {
+  bool busy = false;
+  int64_t age = 0;  // updates done
+  int64_t T = 0;
+  Job job;
+};
+
+struct RankTable {
+  vc_graph g = nullptr;
+  int C = 1, K = 64;
+  DevBuf contrib, mb, params, seeds;
+  DevBuf pull_tiles[4];
+  int64_t pull_ntiles[4] = {0, 0, 0, 0};
+  vc::RankLane* hparams = nullptr;  // pinned, kMaxLanes entries
+  int32_t* hseeds = nullptr;        // pinned, 2 * kMaxLanes entries
+  hipStream_t stream = nullptr;
+  std::thread th;
+  std::deque<Job> queue;  // guarded by the server mutex
+  std::vector<RankSlot> lanes;
+  int busy = 0;
+  bool broken = false;
+  std::string broken_why;
+  size_t bytes = 0;
+  Ema step_ms;
+};
+
 struct GraphEntry {
   vc_graph g = nullptr;
   std::unique_ptr<LaneTable> lanes;
+  std::unique_ptr<RankTable> ranks;
+  Ema alone[4];  // worker service time per program
 };
+
+size_t rank_table_bytes(int64_t n, int64_t m, int K) {
+  const int C = K / 64;
+  size_t b = (size_t)n * K * 16 + kMaxLanes * sizeof(vc::RankLane) + 2 * kMaxLanes * 4;
+  for (int c = 1; c <= C; ++c) b += (size_t)((n + m + vc::kMsPullTilePerChunk * c - 1) / (vc::kMsPullTilePerChunk * c) + 1) * 4;
+  return b;
+}
 
 struct View {
   int32_t graph = -1;
@@ -103,9 +153,13 @@ struct Worker {
   std::vector<View> views;  // touched only by this worker's thread
 };
 
-size_t lane_table_bytes(int64_t n, int K) {
+size_t lane_table_bytes(int64_t n, int64_t m, int K) {
   const int C = K / 64;
-  return (size_t)n * K * 8 + (size_t)n * C * 16 + (size_t)((n + 31) / 32) * 4 + sizeof(LaneCtl);
+  size_t b = (size_t)n * K * 8 + (size_t)n * C * 16 + (size_t)((n + 31) / 32) * 4 + sizeof(LaneCtl) +
+             (size_t)n * 4 + 4 + (size_t)(n + 1) * 8 + (size_t)vc::scan_scratch_entries(n) * 8 +
+             (size_t)((n + m) / vc::kMsPushTile + 2) * 4 + 2 * sizeof(vc::Counters);
+  for (int c = 1; c <= C; ++c) b += (size_t)((n + m + vc::kMsPullTilePerChunk * c - 1) / (vc::kMsPullTilePerChunk * c) + 1) * 4;
+  return b;
 }
 
 }  // namespace
@@ -125,7 +179,10 @@ struct vc_server_s {
   size_t reserved = 0;              // lane tables
   size_t held = 0;                  // worker workspaces (incl. admitted reservations)
   int running = 0;                  // worker jobs in progress
-  int64_t lane_steps = 0, lane_requests = 0;
+  double backlog_ms = 0;            // expected service time of the queued worker jobs
+  double running_ms = 0;            // and of the running ones
+  int64_t lane_steps = 0, lane_requests = 0, lane_push_steps = 0;
+  int64_t rank_steps = 0, rank_requests = 0;
   std::vector<std::unique_ptr<Worker>> workers;
 };
 
@@ -175,6 +232,7 @@ void worker_main(vc_server s, Worker* w) {
       if (vc::make_view(s->graphs[gid].g, w->stream, &v) != VC_OK) {
         Job j = std::move(head);
         s->queue.pop_front();
+        s->backlog_ms -= j.est_ms;
         j.started = Clock::now();
         complete(s, j, VC_ERR_OUT_OF_MEMORY, 0, -1, std::string("workspace view: ") + vc_last_error());
         continue;
@@ -213,6 +271,7 @@ void worker_main(vc_server s, Worker* w) {
       if (s->running == 0 && s->held == 0) {
         Job j = std::move(head);
         s->queue.pop_front();
+        s->backlog_ms -= j.est_ms;
         j.started = Clock::now();
         complete(s, j, VC_ERR_OUT_OF_MEMORY, 0, -1,
                  "request needs " + std::to_string(need) + " bytes of workspace; budget left after lane tables: " +
@@ -235,6 +294,8 @@ void worker_main(vc_server s, Worker* w) {
     job.started = Clock::now();
     s->held += need;
     ++s->running;
+    s->backlog_ms -= job.est_ms;
+    s->running_ms += job.est_ms;
     View& view = w->views[vi];
     view.used = job.started;
     vc_graph vg = view.g;
@@ -253,6 +314,8 @@ void worker_main(vc_server s, Worker* w) {
     s->held = s->held - need - before + after;
     w->views[vi].held = after;
     --s->running;
+    s->running_ms -= job.est_ms;
+    if (rc == VC_OK) s->graphs[gid].alone[job.req.program].add(ms_between(job.started, Clock::now()));
     complete(s, job, rc, st.supersteps, -1, msg);
   }
   lk.unlock();
@@ -262,16 +325,18 @@ void worker_main(vc_server s, Worker* w) {
 
 // ---------------------------------------------------------------- lanes
 
-// One superstep of a lane table: seeds the listed lanes, pulls, applies and
-// reads back which lanes are still live.  Runs without the server lock.
-vc_status lane_superstep(LaneTable* t, int cur, const std::vector<int>& sssp, const std::vector<int>& cc,
-                         const vc::LaneMask& zero) {
+// One superstep of a lane table over its first ceff chunks: seeds the
+// listed lanes, runs the superstep (pulled when a CC lane was seeded, which
+// activates every vertex) and reads back which lanes are still live.  Runs
+// without the server lock.
+vc_status lane_superstep(LaneTable* t, int cur, int ceff, const std::vector<int>& sssp, const std::vector<int>& cc,
+                         const vc::LaneMask& zero, bool* pushed) {
   vc_graph g = t->g;
-  const int64_t n = g->n, m = g->m;
+  const int64_t n = g->n;
   hipStream_t s = t->stream;
   LaneCtl* h = t->host;
   LaneCtl* d = t->ctl.as<LaneCtl>();
-  unsigned long long* A[2] = {t->A0.as<unsigned long long>(), t->A1.as<unsigned long long>()};
+  vc::MsState& ms = t->ms;
   for (size_t j = 0; j < sssp.size(); ++j) {
     h->seeds[2 * j] = sssp[j];
     h->seeds[2 * j + 1] = (int32_t)t->lanes[sssp[j]].job.req.params.source;
@@ -280,18 +345,16 @@ vc_status lane_superstep(LaneTable* t, int cur, const std::vector<int>& sssp, co
   if (!sssp.empty() || !cc.empty())
     VC_TRY(hipMemcpyAsync(d, h, offsetof(LaneCtl, ret_lanes), hipMemcpyHostToDevice, s));
   VC_TRY(vc::launch_fill_u32(reinterpret_cast<uint32_t*>(d->live), (int64_t)(sizeof(LaneCtl) - kCtlIn) / 4, 0u, s));
-  VC_TRY(vc::launch_lane_seed_cc(t->C, g->off, g->off64, g->relabeled ? g->inv_p : nullptr, n, d->cc_lanes,
-                                 (int)cc.size(), t->D.as<uint32_t>(), A[cur], s));
-  VC_TRY(vc::launch_lane_seed_sssp(t->C, g->off, g->off64, g->relabeled ? g->perm_p : nullptr, d->seeds,
-                                   (int)sssp.size(), t->D.as<uint32_t>(), A[cur], d->stillborn, s));
-  VC_TRY(vc::launch_ms_pull(t->C, g->w != nullptr, g->csc_off_p, g->in_src, g->in_w, n, m, g->csc_tiles_p,
-                            g->csc_tile, g->csc_ntiles, t->D.as<uint32_t>(), t->MB.as<uint32_t>(), A[cur],
-                            t->bits.as<uint32_t>(), zero, s));
-  VC_TRY(vc::launch_fill_u32(reinterpret_cast<uint32_t*>(A[1 - cur]), 2 * n * t->C, 0u, s));
-  VC_TRY(vc::launch_ms_apply(t->C, g->off, g->off64, n, t->D.as<uint32_t>(), t->MB.as<uint32_t>(), A[1 - cur],
-                             t->bits.as<uint32_t>(), &d->ctr, d->live, s));
+  VC_TRY(vc::launch_lane_seed_cc(g->off, g->off64, g->relabeled ? g->inv_p : nullptr, n, d->cc_lanes, (int)cc.size(),
+                                 ms.D.as<uint32_t>(), ms.A[cur].as<unsigned long long>(), s));
+  VC_TRY(vc::launch_lane_seed_sssp(g->off, g->off64, g->relabeled ? g->perm_p : nullptr, n, d->seeds,
+                                   (int)sssp.size(), ms.D.as<uint32_t>(), ms.A[cur].as<unsigned long long>(),
+                                   d->stillborn, s));
+  vc_status st = vc::ms_superstep(ms, g, cur, ceff, t->next_edges, !cc.empty(), zero, d->live, pushed, s);
+  if (st != VC_OK) return st;
   VC_TRY(hipMemcpyAsync(&h->live, &d->live, sizeof(LaneCtl) - kCtlIn, hipMemcpyDeviceToHost, s));
   VC_TRY(hipStreamSynchronize(s));
+  t->next_edges = (int64_t)ms.host[0].edges;
   return VC_OK;
 }
 
@@ -313,10 +376,8 @@ vc_status lane_retire(LaneTable* t, int next, const std::vector<Retired>& r, con
     h->outs[j] = static_cast<uint32_t*>(t->lanes[r[j].lane].job.req.out);
   }
   VC_TRY(hipMemcpyAsync(d->ret_lanes, h->ret_lanes, kCtlIn - offsetof(LaneCtl, ret_lanes), hipMemcpyHostToDevice, s));
-  if (any_drop)
-    VC_TRY(vc::launch_lane_clear(t->C, next ? t->A1.as<unsigned long long>() : t->A0.as<unsigned long long>(), g->n,
-                                 drop, s));
-  VC_TRY(vc::launch_lane_retire(t->C, t->D.as<uint32_t>(), g->relabeled ? g->perm_p : nullptr, g->n, d->ret_lanes,
+  if (any_drop) VC_TRY(vc::launch_lane_clear(t->ms.A[next].as<unsigned long long>(), g->n, t->C, drop, s));
+  VC_TRY(vc::launch_lane_retire(t->ms.D.as<uint32_t>(), g->relabeled ? g->perm_p : nullptr, g->n, d->ret_lanes,
                                 d->outs, (int)r.size(), s));
   VC_TRY(hipStreamSynchronize(s));
   return VC_OK;
@@ -332,6 +393,7 @@ void lane_main(vc_server s, LaneTable* t) {
     sssp.clear();
     cc.clear();
     vc::LaneMask zero{};
+    int ceff = 1;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       s->cv_work.wait(lk, [&] { return s->stopping || t->busy > 0 || !t->queue.empty(); });
@@ -360,9 +422,14 @@ void lane_main(vc_server s, LaneTable* t) {
         (ln.cc ? cc : sssp).push_back(l);
       }
       for (int l = 0; l < t->K; ++l)
-        if (t->lanes[l].busy && t->lanes[l].cc) zero.bits[l >> 6] |= 1ull << (l & 63);
+        if (t->lanes[l].busy) {
+          if (t->lanes[l].cc) zero.bits[l >> 6] |= 1ull << (l & 63);
+          ceff = (l >> 6) + 1;  // busy lanes fill the table from the front
+        }
     }
-    vc_status st = lane_superstep(t, cur, sssp, cc, zero);
+    bool pushed = false;
+    const Clock::time_point t_step = Clock::now();
+    vc_status st = lane_superstep(t, cur, ceff, sssp, cc, zero, &pushed);
     retired.clear();
     vc::LaneMask drop{};
     bool any_drop = false;
@@ -396,6 +463,8 @@ void lane_main(vc_server s, LaneTable* t) {
     std::string why = st == VC_OK ? std::string() : std::string(vc_last_error());
     std::lock_guard<std::mutex> lk(s->mu);
     ++s->lane_steps;
+    if (pushed) ++s->lane_push_steps;
+    t->step_ms.add(ms_between(t_step, Clock::now()));
     if (st != VC_OK) {
       // a failed launch or copy leaves the table unusable: fail its requests
       t->broken = true;
@@ -412,6 +481,7 @@ void lane_main(vc_server s, LaneTable* t) {
       Lane& ln = t->lanes[r.lane];
       complete(s, ln.job, r.status, r.supersteps, r.lane,
                r.status == VC_OK ? std::string() : std::string("superstep cap reached before quiescence"));
+      t->steps.add(r.supersteps);
       ln.busy = false;
       --t->busy;
       ++s->lane_requests;
@@ -420,38 +490,216 @@ void lane_main(vc_server s, LaneTable* t) {
   }
 }
 
-vc_status lane_table_init(vc_server s, LaneTable* t, vc_graph g, int K) {
+vc_status lane_table_init(LaneTable* t, vc_graph g, int K) {
   t->g = g;
   t->K = K;
   t->C = K / 64;
-  const int64_t n = g->n;
   VC_TRY(hipStreamCreateWithFlags(&t->stream, hipStreamNonBlocking));
-  VC_TRY(t->D.ensure((size_t)n * K * 4));
-  VC_TRY(t->MB.ensure((size_t)n * K * 4));
-  VC_TRY(t->A0.ensure((size_t)n * t->C * 8));
-  VC_TRY(t->A1.ensure((size_t)n * t->C * 8));
-  VC_TRY(t->bits.ensure((size_t)((n + 31) / 32) * 4));
   VC_TRY(t->ctl.ensure(sizeof(LaneCtl)));
   VC_TRY(hipHostMalloc((void**)&t->host, sizeof(LaneCtl), hipHostMallocDefault));
   std::memset(t->host, 0, sizeof(LaneCtl));
-  VC_TRY(vc::launch_fill_u32(t->D.as<uint32_t>(), n * K, vc::kInf, t->stream));
-  VC_TRY(vc::launch_fill_u32(t->MB.as<uint32_t>(), n * K, vc::kInf, t->stream));
-  VC_TRY(vc::launch_fill_u32(t->A0.as<uint32_t>(), 2 * n * t->C, 0u, t->stream));
-  VC_TRY(vc::launch_fill_u32(t->A1.as<uint32_t>(), 2 * n * t->C, 0u, t->stream));
-  VC_TRY(vc::launch_fill_u32(t->bits.as<uint32_t>(), (n + 31) / 32, 0u, t->stream));
+  vc_status st = vc::ms_reset(t->ms, g, t->C, t->stream);
+  if (st != VC_OK) return st;
   VC_TRY(hipStreamSynchronize(t->stream));
   t->lanes.resize(K);
-  t->bytes = lane_table_bytes(n, K);
-  (void)s;
+  t->bytes = lane_table_bytes(g->n, g->m, K);
   return VC_OK;
 }
 
 void lane_table_free(LaneTable* t) {
-  for (DevBuf* b : {&t->D, &t->MB, &t->A0, &t->A1, &t->bits, &t->ctl}) b->release();
+  t->ms.release();
+  t->ctl.release();
   if (t->host) (void)hipHostFree(t->host);
   t->host = nullptr;
   if (t->stream) (void)hipStreamDestroy(t->stream);
   t->stream = nullptr;
+}
+
+// ---------------------------------------------------------------- rank lanes
+
+void rank_main(vc_server s, RankTable* t) {
+  (void)hipSetDevice(s->device);
+  vc_graph g = t->g;
+  const int64_t n = g->n;
+  std::vector<int> seeded;
+  std::vector<int> finished;
+  for (;;) {
+    seeded.clear();
+    finished.clear();
+    int ceff = 1;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_work.wait(lk, [&] { return s->stopping || t->busy > 0 || !t->queue.empty(); });
+      if (t->busy == 0 && t->queue.empty()) break;  // stopping
+      if (t->broken) {
+        while (!t->queue.empty()) {
+          Job j = std::move(t->queue.front());
+          t->queue.pop_front();
+          j.started = Clock::now();
+          complete(s, j, VC_ERR_HIP, 0, -1, t->broken_why);
+        }
+        continue;
+      }
+      for (int l = 0; l < t->K && !t->queue.empty(); ++l) {
+        RankSlot& sl = t->lanes[l];
+        if (sl.busy) continue;
+        sl.job = std::move(t->queue.front());
+        t->queue.pop_front();
+        sl.job.started = Clock::now();
+        sl.busy = true;
+        sl.age = 0;
+        sl.T = sl.job.req.params.max_supersteps;
+        ++t->busy;
+        seeded.push_back(l);
+      }
+      for (int l = 0; l < t->K; ++l)
+        if (t->lanes[l].busy) ceff = (l >> 6) + 1;
+    }
+    const Clock::time_point t0 = Clock::now();
+    for (size_t j = 0; j < seeded.size(); ++j) {
+      const vc_request& r = t->lanes[seeded[j]].job.req;
+      t->hseeds[2 * j] = seeded[j];
+      t->hseeds[2 * j + 1] = r.program == VC_PPR ? (int32_t)r.params.source : -1;
+    }
+    for (int l = 0; l < 64 * ceff; ++l) {
+      const RankSlot& sl = t->lanes[l];
+      vc::RankLane& P = t->hparams[l];
+      if (!sl.busy) {
+        P.state = 0;
+        continue;
+      }
+      const vc_request& r = sl.job.req;
+      const double d = r.params.damping;
+      P.damping = d;
+      P.teleport = r.program == VC_PPR ? (1.0 - d) : (1.0 - d) / (double)n;
+      P.out = static_cast<float*>(r.out);
+      P.source = r.program == VC_PPR ? (int32_t)r.params.source : -1;
+      P.state = sl.age + 1 == sl.T ? 2 : 1;
+    }
+    hipError_t e = hipMemcpyAsync(t->params.p, t->hparams, sizeof(vc::RankLane) * 64 * ceff, hipMemcpyHostToDevice,
+                                  t->stream);
+    if (e == hipSuccess && !seeded.empty())
+      e = hipMemcpyAsync(t->seeds.p, t->hseeds, seeded.size() * 8, hipMemcpyHostToDevice, t->stream);
+    const int32_t* ids = g->relabeled ? g->inv_p : nullptr;
+    if (e == hipSuccess)
+      e = vc::launch_rl_seed(g->off, g->off64, ids, n, t->seeds.as<int32_t>(), (int)seeded.size(),
+                             t->contrib.as<unsigned long long>(), t->stream);
+    if (e == hipSuccess)
+      e = vc::launch_rl_pull(ceff, g->csc_off_p, g->in_src, n, g->m, t->pull_tiles[ceff - 1].as<int32_t>(),
+                             vc::kMsPullTilePerChunk * ceff, t->pull_ntiles[ceff - 1],
+                             t->contrib.as<unsigned long long>(), t->mb.as<unsigned long long>(), t->stream);
+    if (e == hipSuccess)
+      e = vc::launch_rl_apply(g->off, g->off64, ids, n, ceff, t->params.as<vc::RankLane>(),
+                              t->contrib.as<unsigned long long>(), t->mb.as<unsigned long long>(), t->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(t->stream);
+    std::lock_guard<std::mutex> lk(s->mu);
+    ++s->rank_steps;
+    t->step_ms.add(ms_between(t0, Clock::now()));
+    if (e != hipSuccess) {
+      hip_fail(e, "rank lane superstep");
+      t->broken = true;
+      t->broken_why = vc_last_error();
+      for (RankSlot& sl : t->lanes)
+        if (sl.busy) {
+          complete(s, sl.job, VC_ERR_HIP, 0, -1, t->broken_why);
+          sl.busy = false;
+        }
+      t->busy = 0;
+      continue;
+    }
+    for (int l = 0; l < t->K; ++l) {
+      RankSlot& sl = t->lanes[l];
+      if (!sl.busy || ++sl.age < sl.T) continue;
+      complete(s, sl.job, VC_OK, (int32_t)(sl.T + 1), l, std::string());
+      sl.busy = false;
+      --t->busy;
+      ++s->rank_requests;
+    }
+  }
+}
+
+vc_status rank_table_init(RankTable* t, vc_graph g, int K) {
+  t->g = g;
+  t->K = K;
+  t->C = K / 64;
+  const int64_t n = g->n, m = g->m;
+  if ((size_t)(4 * vc::kMsPullTilePerChunk + 2) * 8 > g->max_lds) return fail(VC_ERR_UNSUPPORTED, "pull tile exceeds LDS");
+  VC_TRY(hipStreamCreateWithFlags(&t->stream, hipStreamNonBlocking));
+  VC_TRY(t->contrib.ensure((size_t)n * K * 8));
+  VC_TRY(t->mb.ensure((size_t)n * K * 8));
+  VC_TRY(t->params.ensure(kMaxLanes * sizeof(vc::RankLane)));
+  VC_TRY(t->seeds.ensure(2 * kMaxLanes * 4));
+  VC_TRY(hipHostMalloc((void**)&t->hparams, kMaxLanes * sizeof(vc::RankLane), hipHostMallocDefault));
+  VC_TRY(hipHostMalloc((void**)&t->hseeds, 2 * kMaxLanes * 4, hipHostMallocDefault));
+  std::memset(t->hparams, 0, kMaxLanes * sizeof(vc::RankLane));
+  for (int c = 1; c <= t->C; ++c) {
+    const int64_t tile = vc::kMsPullTilePerChunk * c;
+    const int64_t ntiles = (n + m + tile - 1) / tile;
+    VC_TRY(t->pull_tiles[c - 1].ensure((size_t)(ntiles + 1) * 4));
+    VC_TRY(vc::launch_mp_partition(g->csc_off_p, true, n, n + m, tile, ntiles, t->pull_tiles[c - 1].as<int32_t>(),
+                                   t->stream));
+    t->pull_ntiles[c - 1] = ntiles;
+  }
+  VC_TRY(vc::launch_fill_u32(t->contrib.as<uint32_t>(), n * K * 2, 0u, t->stream));
+  VC_TRY(vc::launch_fill_u32(t->mb.as<uint32_t>(), n * K * 2, 0u, t->stream));
+  VC_TRY(hipStreamSynchronize(t->stream));
+  t->lanes.resize(K);
+  t->bytes = rank_table_bytes(n, m, K);
+  return VC_OK;
+}
+
+void rank_table_free(RankTable* t) {
+  for (DevBuf* b : {&t->contrib, &t->mb, &t->params, &t->seeds, &t->pull_tiles[0], &t->pull_tiles[1],
+                    &t->pull_tiles[2], &t->pull_tiles[3]})
+    b->release();
+  if (t->hparams) (void)hipHostFree(t->hparams);
+  if (t->hseeds) (void)hipHostFree(t->hseeds);
+  t->hparams = nullptr;
+  t->hseeds = nullptr;
+  if (t->stream) (void)hipStreamDestroy(t->stream);
+  t->stream = nullptr;
+}
+
+// Expected worker service time of a request: the mean of the graph's past
+// worker runs of the program, before any a prior from the edge count (about
+// 0.1 ns per edge for a min program, 12 ps per edge and iteration for a
+// rank program, as measured on R-MAT graphs).
+double worker_estimate(const GraphEntry& ge, const vc_request& r) {
+  if (ge.alone[r.program].n) return ge.alone[r.program].v;
+  const double m = (double)ge.g->m;
+  if (r.program == VC_PAGERANK || r.program == VC_PPR) return (double)r.params.max_supersteps * (0.05 + m * 1.2e-8);
+  return 0.5 + m * 1e-7;
+}
+
+// Routing of a CC / SSSP request on a graph with a lane table: the lane
+// table when its expected completion time is shorter than the worker
+// path's.  Worker path: the queued and running worker jobs' expected service
+// times shared by the workers, plus this request's.  Lane table: supersteps per request times superstep time
+// (means of its past runs; before any, 20 supersteps of a model time that
+// reads every edge and value row once), once more for every table-full of
+// requests queued ahead.  Caller holds s->mu.
+// Rank lanes: T updates of the table's superstep time (model before any
+// run: every edge's message row and every value row read once).
+bool rank_lane_is_faster(vc_server s, const GraphEntry& ge, const vc_request& r) {
+  const RankTable& t = *ge.ranks;
+  const double worker = (s->backlog_ms + 0.5 * s->running_ms) / (double)s->workers.size() + worker_estimate(ge, r);
+  const double step = t.step_ms.n ? t.step_ms.v
+                                  : ((double)t.g->m * 512.0 * t.C + (double)t.g->n * t.C * 64.0 * 24.0) / 3e9;
+  const int64_t ahead = (int64_t)t.queue.size() - (t.K - t.busy);
+  const double rounds = 1.0 + (ahead >= 0 ? (double)(ahead / t.K + 1) : 0.0);
+  return rounds * (double)r.params.max_supersteps * step < worker;
+}
+
+bool lane_is_faster(vc_server s, const GraphEntry& ge, const vc_request& r) {
+  const LaneTable& t = *ge.lanes;
+  const double alone = worker_estimate(ge, r);
+  const double worker = (s->backlog_ms + 0.5 * s->running_ms) / (double)s->workers.size() + alone;
+  const double step = t.step_ms.n ? t.step_ms.v
+                                  : ((double)t.g->m * 64.0 + (double)t.g->n * t.C * 1024.0) / 2e9;
+  const double steps = t.steps.n ? t.steps.v : 20.0;
+  const int64_t ahead = (int64_t)t.queue.size() - (t.K - t.busy);
+  const double rounds = 1.0 + (ahead >= 0 ? (double)(ahead / t.K + 1) : 0.0);
+  return rounds * steps * step < worker;
 }
 
 }  // namespace
@@ -496,9 +744,11 @@ vc_status vc_server_create(const vc_server_config* config, vc_server* out) {
   return VC_OK;
 }
 
-vc_status vc_server_add_graph(vc_server s, vc_graph g, int32_t lanes, int32_t* id) {
+vc_status vc_server_add_graph(vc_server s, vc_graph g, int32_t lanes, int32_t rank_lanes, int32_t* id) {
   if (!s || !g || !id) return fail(VC_ERR_INVALID_ARG, "null argument");
   if (lanes < 0 || lanes > kMaxLanes || lanes % 64) return fail(VC_ERR_INVALID_ARG, "lanes must be 0, 64, 128, 192 or 256");
+  if (rank_lanes < 0 || rank_lanes > kMaxLanes || rank_lanes % 64)
+    return fail(VC_ERR_INVALID_ARG, "rank_lanes must be 0, 64, 128, 192 or 256");
   if (g->is_view) return fail(VC_ERR_INVALID_ARG, "not a graph handle");
   if (g->device != s->device) return fail(VC_ERR_INVALID_ARG, "graph lives on another device than the server");
   std::lock_guard<std::mutex> lk(s->mu);
@@ -515,19 +765,42 @@ vc_status vc_server_add_graph(vc_server s, vc_graph g, int32_t lanes, int32_t* i
   GraphEntry e;
   e.g = g;
   if (lanes > 0) {
-    const size_t need = lane_table_bytes(g->n, lanes);
+    const size_t need = lane_table_bytes(g->n, g->m, lanes);
     if (s->reserved + s->held + need > s->budget)
       return fail(VC_ERR_OUT_OF_MEMORY, "lane table of " + std::to_string(need) + " bytes exceeds the budget left");
     std::unique_ptr<LaneTable> t(new LaneTable());
-    rc = lane_table_init(s, t.get(), g, lanes);
+    rc = lane_table_init(t.get(), g, lanes);
     if (rc != VC_OK) {
       lane_table_free(t.get());
       return rc;
     }
     s->reserved += t->bytes;
-    t->th = std::thread(lane_main, s, t.get());
     e.lanes = std::move(t);
   }
+  if (rank_lanes > 0) {
+    const size_t need = rank_table_bytes(g->n, g->m, rank_lanes);
+    if (s->reserved + s->held + need > s->budget) {
+      if (e.lanes) {
+        lane_table_free(e.lanes.get());
+        s->reserved -= e.lanes->bytes;
+      }
+      return fail(VC_ERR_OUT_OF_MEMORY, "rank lane table of " + std::to_string(need) + " bytes exceeds the budget left");
+    }
+    std::unique_ptr<RankTable> t(new RankTable());
+    rc = rank_table_init(t.get(), g, rank_lanes);
+    if (rc != VC_OK) {
+      rank_table_free(t.get());
+      if (e.lanes) {
+        lane_table_free(e.lanes.get());
+        s->reserved -= e.lanes->bytes;
+      }
+      return rc;
+    }
+    s->reserved += t->bytes;
+    e.ranks = std::move(t);
+  }
+  if (e.lanes) e.lanes->th = std::thread(lane_main, s, e.lanes.get());
+  if (e.ranks) e.ranks->th = std::thread(rank_main, s, e.ranks.get());
   s->graphs.push_back(std::move(e));
   *id = (int32_t)s->graphs.size() - 1;
   return VC_OK;
@@ -548,11 +821,23 @@ vc_status vc_server_submit(vc_server s, const vc_request* req, uint64_t* ticket)
   j.ticket = s->next_ticket++;
   j.req = *req;
   j.submitted = Clock::now();
-  const bool lane = ge.lanes && (req->program == VC_CC_HASHMIN || req->program == VC_SSSP);
-  if (lane)
+  if (req->route < VC_ROUTE_AUTO || req->route > VC_ROUTE_WORKER) return fail(VC_ERR_INVALID_ARG, "bad route");
+  const bool min_prog = req->program == VC_CC_HASHMIN || req->program == VC_SSSP;
+  bool lane = ge.lanes && min_prog && req->route != VC_ROUTE_WORKER;
+  if (lane && req->route == VC_ROUTE_AUTO) lane = lane_is_faster(s, ge, *req);
+  // rank lanes sum in exact fixed point: binary32 requests and T = 0 stay on workers
+  bool rank = ge.ranks && !min_prog && req->route != VC_ROUTE_WORKER && req->params.max_supersteps > 0 &&
+              !(req->params.options & VC_OPT_F32_ACCUMULATE);
+  if (rank && req->route == VC_ROUTE_AUTO) rank = rank_lane_is_faster(s, ge, *req);
+  if (lane) {
     ge.lanes->queue.push_back(j);
-  else
+  } else if (rank) {
+    ge.ranks->queue.push_back(j);
+  } else {
+    j.est_ms = worker_estimate(ge, *req);
+    s->backlog_ms += j.est_ms;
     s->queue.push_back(j);
+  }
   ++s->submitted;
   ++s->epoch;
   s->cv_work.notify_all();
@@ -599,6 +884,9 @@ vc_status vc_server_info_get(vc_server s, vc_server_info* info) {
   info->completed = s->completed;
   info->lane_supersteps = s->lane_steps;
   info->lane_requests = s->lane_requests;
+  info->lane_push_supersteps = s->lane_push_steps;
+  info->rank_supersteps = s->rank_steps;
+  info->rank_requests = s->rank_requests;
   return VC_OK;
 }
 
@@ -613,15 +901,19 @@ vc_status vc_server_destroy(vc_server s) {
   }
   for (auto& w : s->workers)
     if (w->th.joinable()) w->th.join();
-  for (GraphEntry& e : s->graphs)
+  for (GraphEntry& e : s->graphs) {
     if (e.lanes && e.lanes->th.joinable()) e.lanes->th.join();
+    if (e.ranks && e.ranks->th.joinable()) e.ranks->th.join();
+  }
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(s->device);
   for (auto& w : s->workers)
     if (w->stream) (void)hipStreamDestroy(w->stream);
-  for (GraphEntry& e : s->graphs)
+  for (GraphEntry& e : s->graphs) {
     if (e.lanes) lane_table_free(e.lanes.get());
+    if (e.ranks) rank_table_free(e.ranks.get());
+  }
   (void)hipSetDevice(prev);
   delete s;
   return VC_OK;

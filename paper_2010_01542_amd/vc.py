@@ -25,6 +25,8 @@ IDX_I32, IDX_I64 = 0, 1
 GRAPH_BORROW, GRAPH_VALIDATE, GRAPH_SYMMETRIC, GRAPH_NO_RELABEL = 1, 2, 4, 8
 OPT_NO_HUB_AGGREGATION, OPT_NO_TEST_BEFORE_ATOMIC, OPT_F32_ACCUMULATE, OPT_GRAPH_CAPTURE = 1, 2, 4, 8
 UNREACHED = 0xFFFFFFFF
+ROUTE_AUTO, ROUTE_LANES, ROUTE_WORKER = 0, 1, 2
+ROUTES = {"auto": ROUTE_AUTO, "lanes": ROUTE_LANES, "worker": ROUTE_WORKER}
 
 OK, ERR_INVALID_ARG, ERR_BAD_GRAPH, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_UNSUPPORTED, ERR_NOT_CONVERGED = range(7)
 ABI_VERSION = 1
@@ -64,7 +66,7 @@ class ServerConfig(ctypes.Structure):
 
 class Request(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("graph", ctypes.c_int32), ("program", ctypes.c_int),
-                ("reserved", ctypes.c_int32), ("params", Params), ("out", ctypes.c_void_p), ("tag", ctypes.c_uint64)]
+                ("route", ctypes.c_int), ("params", Params), ("out", ctypes.c_void_p), ("tag", ctypes.c_uint64)]
 
 
 class CompletionStruct(ctypes.Structure):
@@ -77,7 +79,8 @@ class ServerInfo(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("graphs", ctypes.c_int32), ("hbm_budget", ctypes.c_uint64),
                 ("bytes_reserved", ctypes.c_uint64), ("bytes_held", ctypes.c_uint64), ("submitted", ctypes.c_uint64),
                 ("completed", ctypes.c_uint64), ("lane_supersteps", ctypes.c_int64),
-                ("lane_requests", ctypes.c_int64)]
+                ("lane_push_supersteps", ctypes.c_int64), ("lane_requests", ctypes.c_int64),
+                ("rank_supersteps", ctypes.c_int64), ("rank_requests", ctypes.c_int64)]
 
 
 class VcError(RuntimeError):
@@ -133,7 +136,7 @@ def load(path: str = LIB_PATH):
     lib.vc_server_create.restype = i32
     lib.vc_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
     lib.vc_server_add_graph.restype = i32
-    lib.vc_server_add_graph.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.vc_server_add_graph.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.vc_server_submit.restype = i32
     lib.vc_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
     lib.vc_server_poll.restype = i32
@@ -470,14 +473,16 @@ class Server:
         self._pending = {}
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
 
-    def add_graph(self, graph: Graph, lanes: int = 0) -> int:
+    def add_graph(self, graph: Graph, lanes: int = 0, rank_lanes: int = 0) -> int:
         gid = ctypes.c_int32()
-        _check(load().vc_server_add_graph(self._h, graph._h, int(lanes), ctypes.byref(gid)), "vc_server_add_graph")
+        _check(load().vc_server_add_graph(self._h, graph._h, int(lanes), int(rank_lanes), ctypes.byref(gid)),
+               "vc_server_add_graph")
         self._graphs.append(graph)
         return gid.value
 
     def submit(self, graph_id: int, program, out, *, source: int = 0, T: int = 10, damping: float = 0.85,
-               max_supersteps: int = 0, schedule="auto", tile: int = 0, options: int = 0, tag: int = 0) -> int:
+               max_supersteps: int = 0, schedule="auto", tile: int = 0, options: int = 0, tag: int = 0,
+               route="auto") -> int:
         prog = _program(program)
         rank = prog in (PAGERANK, PPR)
         if not out.is_cuda or not out.is_contiguous() or out.element_size() != 4:
@@ -485,7 +490,7 @@ class Server:
         n = self._graphs[graph_id].n if 0 <= graph_id < len(self._graphs) else None
         if n is not None and out.numel() != n:
             raise TypeError("out must hold N elements")
-        req = Request(ctypes.sizeof(Request), int(graph_id), prog, 0,
+        req = Request(ctypes.sizeof(Request), int(graph_id), prog, ROUTES[route] if isinstance(route, str) else int(route),
                       _params(T if rank else max_supersteps, damping, source, schedule, tile, options),
                       out.data_ptr(), int(tag))
         ticket = ctypes.c_uint64()

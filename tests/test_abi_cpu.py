@@ -106,7 +106,7 @@ def test_argument_errors_need_no_device():
     assert lib.vc_server_create(ctypes.byref(cfg), ctypes.byref(srv)) == vc.ERR_INVALID_ARG
     assert b"workers" in lib.vc_last_error()
     gid = ctypes.c_int32()
-    assert lib.vc_server_add_graph(None, None, 64, ctypes.byref(gid)) == vc.ERR_INVALID_ARG
+    assert lib.vc_server_add_graph(None, None, 64, 0, ctypes.byref(gid)) == vc.ERR_INVALID_ARG
     assert lib.vc_server_submit(None, None, None) == vc.ERR_INVALID_ARG
     cnt = ctypes.c_int32()
     assert lib.vc_server_poll(None, None, 0, 0, ctypes.byref(cnt)) == vc.ERR_INVALID_ARG

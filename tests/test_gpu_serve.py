@@ -4,11 +4,13 @@ mix.
 * Lane tables (continuous batching of CC / SSSP): values bit-exact and
   superstep counts equal to the same request run alone with vc_run, and to
   the oracle; more requests than lanes, so lanes are retired and reseeded
-  many times; a request stopped at its superstep cap frees its lane cleanly.
-* Workers: PageRank / PPR (and min programs on graphs without lanes) equal
-  their alone runs bit for bit (the default combiner sums in exact fixed
-  point, so the order of additions cannot change a result) and the oracle
-  within the PageRank bars.
+  many times, and supersteps run in both the push and the pull form; a
+  request stopped at its superstep cap frees its lane cleanly.
+* Rank lanes and workers: PageRank / PPR equal their alone runs bit for bit
+  (the default combiner sums in exact fixed point, so neither the order of
+  additions nor the company of other lanes can change a result) and the
+  oracle within the PageRank bars; lanes at different iteration counts
+  share supersteps.
 * Admission: with a budget that holds one workspace, requests still all
   complete correctly; a request whose workspace can never fit completes
   with VC_ERR_OUT_OF_MEMORY alone; a bad request is refused at submission.
@@ -71,11 +73,13 @@ def test_lanes_equal_alone_runs(device, lanes):
     with Server(workers=1) as srv:
         gid = srv.add_graph(g, lanes=lanes)
         outs = [torch.full((d.n,), -7, dtype=torch.int32, device=device) for _ in progs]
-        tickets = [srv.submit(gid, p, o, source=int(s), tag=i)
+        tickets = [srv.submit(gid, p, o, source=int(s), tag=i, route="lanes")
                    for i, (p, s, o) in enumerate(zip(progs, sources, outs))]
         done = collect(srv, len(tickets))
         info = srv.info()
     assert info["lane_requests"] == len(progs) and info["submitted"] == info["completed"] == len(progs)
+    # both superstep forms ran: pushed from a broadcast list, and pulled
+    assert 0 < info["lane_push_supersteps"] < info["lane_supersteps"], info
     cache = {}
     for i, (t, p, s) in enumerate(zip(tickets, progs, sources)):
         c = done[t]
@@ -101,25 +105,26 @@ def test_lane_superstep_cap_frees_the_lane(device):
     with Server(workers=1) as srv:
         gid = srv.add_graph(g, lanes=64)
         capped = torch.full((d.n,), -7, dtype=torch.int32, device=device)
-        t_cap = srv.submit(gid, "sssp", capped, source=0, max_supersteps=7)
+        t_cap = srv.submit(gid, "sssp", capped, source=0, max_supersteps=7, route="lanes")
         outs = [torch.full((d.n,), -7, dtype=torch.int32, device=device) for _ in range(150)]
-        ts = [srv.submit(gid, "sssp", o, source=i) for i, o in enumerate(outs)]
+        ts = [srv.submit(gid, "sssp", o, source=i, route="lanes") for i, o in enumerate(outs)]
         done = collect(srv, 151)
     c = done[t_cap]
     ref, status, _ = alone(d, "sssp", source=0, max_supersteps=7)
-    assert c.status == status == vc.ERR_NOT_CONVERGED and c.supersteps == 7
+    assert c.status == status == vc.ERR_NOT_CONVERGED and c.supersteps == 7 and c.lane >= 0
     assert np.array_equal(capped.cpu().numpy().view(np.uint32), ref)
     for i, (t, o) in enumerate(zip(ts, outs)):
         got = o.cpu().numpy().view(np.uint32)
         expect = np.where(np.arange(d.n) >= i, np.arange(d.n) - i, 0xFFFFFFFF).astype(np.uint32)
-        assert done[t].status == vc.OK and np.array_equal(got, expect), i
+        assert done[t].status == vc.OK and done[t].lane >= 0 and np.array_equal(got, expect), i
         assert done[t].supersteps == d.n - i, (i, done[t].supersteps)
 
 
-def test_mixed_programs_on_workers_and_lanes(device):
+@pytest.mark.parametrize("route", ["auto", "lanes", "worker"])
+def test_mixed_programs_on_workers_and_lanes(device, route):
     import torch
     from paper_2010_01542_amd import Server, vc
-    print("case serve mixed programs", flush=True)
+    print(f"case serve mixed programs route={route}", flush=True)
     a = rmatgen.rmat(12, 8, seed=21, weighted=True)             # lanes for its CC / SSSP
     b = rmatgen.rmat(11, 8, seed=22, directed=False)            # no lanes: everything on workers
     ga, gb = make(a), make(b, symmetric=True)
@@ -130,18 +135,21 @@ def test_mixed_programs_on_workers_and_lanes(device):
         prog = ["sssp", "ppr", "pagerank", "cc", "sssp"][i % 5]
         reqs.append((csr, gname, prog, int(rng.integers(0, csr.n)), 5 + i % 7))
     with Server(workers=3) as srv:
-        ids = {"a": srv.add_graph(ga, lanes=64), "b": srv.add_graph(gb, lanes=0)}
+        ids = {"a": srv.add_graph(ga, lanes=64, rank_lanes=64), "b": srv.add_graph(gb, lanes=0)}
         outs, tickets = [], []
         for csr, gname, prog, src, T in reqs:
             rank = prog in ("pagerank", "ppr")
             o = torch.full((csr.n,), -7, dtype=torch.float32 if rank else torch.int32, device=device)
             outs.append(o)
-            tickets.append(srv.submit(ids[gname], prog, o, source=src, T=T))
+            tickets.append(srv.submit(ids[gname], prog, o, source=src, T=T, route=route))
         done = collect(srv, len(reqs))
     for (csr, gname, prog, src, T), o, t in zip(reqs, outs, tickets):
         c = done[t]
         assert c.status == vc.OK, c
-        assert (c.lane >= 0) == (gname == "a" and prog in ("cc", "sssp"))
+        if c.lane >= 0:  # routed by expected completion time; only graph a has lane tables
+            assert gname == "a" and route != "worker"
+        elif route == "lanes":
+            assert gname != "a"
         rank = prog in ("pagerank", "ppr")
         kw = {"T": T} if rank else {}
         ref, status, steps = alone(csr, prog, source=src, symmetric=gname == "b", **kw)
@@ -187,3 +195,41 @@ def test_admission_under_a_small_budget(device):
         assert done[t].status == vc.OK
         ref, _, _ = alone(small, "ppr", source=k, T=6)
         assert np.array_equal(o.cpu().numpy(), ref), k
+
+
+@pytest.mark.parametrize("rank_lanes", [64, 128])
+def test_rank_lanes_equal_alone_runs(device, rank_lanes):
+    import torch
+    from paper_2010_01542_amd import Server, vc
+    print(f"case serve rank lanes={rank_lanes}", flush=True)
+    d = rmatgen.rmat(11, 12, seed=9)
+    rng = np.random.default_rng(rank_lanes)
+    reqs = []
+    for i in range(rank_lanes + 40):
+        prog = "pagerank" if i % 9 == 0 else "ppr"
+        reqs.append((prog, int(rng.integers(0, d.n)), int([1, 3, 7, 12, 20][i % 5]), [0.85, 0.5][i % 2]))
+    reqs.append(("ppr", int(np.flatnonzero(d.outdeg == 0)[0]), 6, 0.85))  # a source without out-edges
+    g = make(d)
+    with Server(workers=1) as srv:
+        gid = srv.add_graph(g, rank_lanes=rank_lanes)
+        outs = [torch.full((d.n,), -1.0, dtype=torch.float32, device=device) for _ in reqs]
+        ts = [srv.submit(gid, p, o, source=src, T=T, damping=dd, route="lanes")
+              for (p, src, T, dd), o in zip(reqs, outs)]
+        t0 = srv.submit(gid, "ppr", torch.empty(d.n, dtype=torch.float32, device=device), source=3, T=0)
+        t32 = srv.submit(gid, "ppr", torch.empty(d.n, dtype=torch.float32, device=device), source=3, T=4,
+                         options=vc.OPT_F32_ACCUMULATE)
+        done = collect(srv, len(ts) + 2)
+        info = srv.info()
+    assert done[t0].status == vc.OK and done[t0].lane == -1  # T = 0 and binary32 sums run on workers
+    assert done[t32].status == vc.OK and done[t32].lane == -1
+    assert info["rank_requests"] == len(reqs)
+    for k, ((p, src, T, dd), o, t) in enumerate(zip(reqs, outs, ts)):
+        c = done[t]
+        assert c.status == vc.OK and 0 <= c.lane < rank_lanes and c.supersteps == T + 1, (k, c)
+        ref, status, steps = alone(d, p, source=src, T=T, damping=dd)
+        got = o.cpu().numpy()
+        assert np.array_equal(got, ref), (k, p, src, T, float(np.abs(got - ref).max()))
+        if k < 6:
+            ora = oracle.run(p, d.n, d.off, d.dst, T=T, damping=dd, source=src).values
+            l1, mx = rank_errors(got, ora)
+            assert l1 <= L1_TOL and mx <= MAX_ABS_TOL, (k, l1, mx)
