@@ -231,10 +231,10 @@ def bench_multi(args, dev):
     }
 
 
-SERVE_GRAPHS = (  # name, scale, directed, weighted, lanes, share of SSSP / PPR traffic
-    ("s18", 18, True, True, 256, 0.50),
-    ("s22", 22, True, True, 256, 0.35),
-    ("s24", 24, True, True, 256, 0.15),
+SERVE_GRAPHS = (  # name, scale, directed, weighted, lanes, share of SSSP / PPR traffic, rank lanes
+    ("s18", 18, True, True, 256, 0.50, 256),
+    ("s22", 22, True, True, 256, 0.35, 128),
+    ("s24", 24, True, True, 256, 0.15, 64),
 )
 SERVE_CC = ("cc-s20", 20, False, False, 64)
 
@@ -272,7 +272,7 @@ def bench_serve(args, dev):
     from paper_2010_01542_amd import Graph, Server, vc
     t = time.time()
     csrs = {}
-    for name, scale, directed, weighted, _, _ in SERVE_GRAPHS:
+    for name, scale, directed, weighted, _, _, _ in SERVE_GRAPHS:
         csrs[name] = rmatgen.rmat(scale, 16, seed=rmatgen.BASE_SEED + scale, directed=directed, weighted=weighted,
                                   threads=args.gen_threads)
     name, scale, directed, weighted, _ = SERVE_CC
@@ -282,6 +282,10 @@ def bench_serve(args, dev):
         ", ".join(f"{k} n={c.n} m={c.m}" for k, c in csrs.items()))
     graphs = {k: Graph.from_csr(c, device=dev, symmetric=(k == SERVE_CC[0])) for k, c in csrs.items()}
     reqs = serve_requests(args.requests, csrs, rmatgen.BASE_SEED + 5)
+    lanes_of = {x[0]: x[4] for x in SERVE_GRAPHS}
+    lanes_of[SERVE_CC[0]] = SERVE_CC[4]
+    rank_lanes_of = {x[0]: x[6] for x in SERVE_GRAPHS}
+    rank_lanes_of[SERVE_CC[0]] = 0
     pool = {}
 
     def out_for(i, name, prog):
@@ -312,8 +316,7 @@ def bench_serve(args, dev):
         """Submits request i at arrivals[i] (seconds from start); returns the
         makespan and per-request latencies (submit -> result complete)."""
         srv = Server(workers=args.workers)
-        ids = {k: srv.add_graph(g, lanes=(SERVE_CC[4] if k == SERVE_CC[0] else
-                                          dict((x[0], x[4]) for x in SERVE_GRAPHS)[k])) for k, g in graphs.items()}
+        ids = {k: srv.add_graph(g, lanes=lanes_of[k], rank_lanes=rank_lanes_of[k]) for k, g in graphs.items()}
         outs = [out_for(i, name, prog) for i, (name, prog, _) in enumerate(reqs)]
         lat = np.zeros(len(reqs))
         lanes_used = 0
@@ -373,18 +376,20 @@ def bench_serve(args, dev):
         "ms_per_step": round(span * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32+f32", "data": "synthetic R-MAT (seeded)",
         "config": {"workload": f"serve-{len(reqs)}", "graphs": {k: [c.n, c.m] for k, c in csrs.items()},
-                   "lanes": {k: (SERVE_CC[4] if k == SERVE_CC[0] else dict((x[0], x[4]) for x in SERVE_GRAPHS)[k])
-                             for k in csrs}, "workers": args.workers},
+                   "lanes": lanes_of, "rank_lanes": rank_lanes_of, "workers": args.workers,
+                   "hw_queues": args.hw_queues},
         "sequential": {"requests_per_s": round(len(reqs) / base_s, 2),
                        "service_ms_mean": {k: round(float(np.mean(v)), 3) for k, v in kinds.items()}},
         "speedup_vs_sequential": round(base_s / span, 2),
         "saturated": {"latency_ms_p50": pct(lat_sat, 50), "latency_ms_p99": pct(lat_sat, 99),
                       "p50_p99_by_kind": by_kind(lat_sat),
-                      "lane_requests": lanes_used, "lane_supersteps": info["lane_supersteps"]},
+                      "lane_requests": lanes_used, "lane_supersteps": info["lane_supersteps"],
+                      "rank_supersteps": info["rank_supersteps"]},
         "open_loop": {"arrival_rate_per_s": round(rate, 2), "latency_ms_p50": pct(lat_open, 50),
                       "latency_ms_p99": pct(lat_open, 99), "sequential_latency_ms_p50": pct(lat_base, 50),
                       "sequential_latency_ms_p99": pct(lat_base, 99), "makespan_s": round(span_open, 3),
                       "lane_requests": lanes_open, "lane_supersteps": info_open["lane_supersteps"],
+                      "rank_supersteps": info_open["rank_supersteps"],
                       "p50_p99_by_kind": by_kind(lat_open), "sequential_p50_p99_by_kind": by_kind(lat_base)},
     }
 
@@ -399,6 +404,9 @@ def main():
     ap.add_argument("--members", type=int, default=1024, help="batch workload: number of graphs")
     ap.add_argument("--requests", type=int, default=600, help="serve workload: number of requests")
     ap.add_argument("--workers", type=int, default=4, help="serve workload: worker threads")
+    ap.add_argument("--hw-queues", type=int, default=None,
+                    help="serve workload: hardware queues of the process (GPU_MAX_HW_QUEUES, at most 32); "
+                         "lane tables, rank tables and workers each use their own stream")
     ap.add_argument("--scale", type=int, default=None, help="override the graph scale (same shape)")
     ap.add_argument("--schedule", default="auto", choices=["auto", "vertex", "edge", "pull"])
     ap.add_argument("--tile", type=int, default=0)
@@ -413,6 +421,13 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(libvc runs on one GPU; sharding across GPUs is not implemented).", file=sys.stderr)
         sys.exit(2)
+
+    if args.hw_queues is None and args.workload == "serve":
+        args.hw_queues = 16  # one per lane table, rank table and worker stream
+    if args.hw_queues:
+        if not 1 <= args.hw_queues <= 32:
+            sys.exit("--hw-queues must be in 1..32")
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)  # read when the HIP runtime starts, below
 
     import torch
     import rmatgen

@@ -671,35 +671,50 @@ double worker_estimate(const GraphEntry& ge, const vc_request& r) {
   return 0.5 + m * 1e-7;
 }
 
-// Routing of a CC / SSSP request on a graph with a lane table: the lane
-// table when its expected completion time is shorter than the worker
-// path's.  Worker path: the queued and running worker jobs' expected service
-// times shared by the workers, plus this request's.  Lane table: supersteps per request times superstep time
-// (means of its past runs; before any, 20 supersteps of a model time that
-// reads every edge and value row once), once more for every table-full of
-// requests queued ahead.  Caller holds s->mu.
-// Rank lanes: T updates of the table's superstep time (model before any
-// run: every edge's message row and every value row read once).
+// Workers share one GPU: bandwidth-bound runs overlap little, so the
+// backlog drains at about this many runs' worth at a time, however many
+// worker threads there are.
+constexpr double kWorkerOverlap = 2.0;
+// Lanes trade latency for throughput (a lane waits for whole-graph
+// supersteps), so they are chosen only when clearly ahead.
+constexpr double kLaneMargin = 2.0;
+
+double worker_wait(vc_server s) {
+  const double w = s->workers.size() < kWorkerOverlap ? (double)s->workers.size() : kWorkerOverlap;
+  return (s->backlog_ms + 0.5 * s->running_ms) / w;
+}
+
+// Routing of a request on a graph with a lane table: the lane table when its
+// expected completion time is shorter than the worker path's.  Worker path:
+// the queued and running worker jobs' expected service times, drained
+// kWorkerOverlap at a time, plus this request's.  Lane table (counted
+// kLaneMargin times): supersteps per request times superstep time (means of its past runs; before any, 20
+// supersteps of a model time that reads every edge and the value rows of
+// the chunks in use once), once more for every table-full of requests
+// queued ahead.  Rank lanes: T updates of the table's superstep time (model
+// before any run: every edge's message row and every value row of the
+// chunks in use read once).  Caller holds s->mu.
 bool rank_lane_is_faster(vc_server s, const GraphEntry& ge, const vc_request& r) {
   const RankTable& t = *ge.ranks;
-  const double worker = (s->backlog_ms + 0.5 * s->running_ms) / (double)s->workers.size() + worker_estimate(ge, r);
-  const double step = t.step_ms.n ? t.step_ms.v
-                                  : ((double)t.g->m * 512.0 * t.C + (double)t.g->n * t.C * 64.0 * 24.0) / 3e9;
+  const double worker = worker_wait(s) + worker_estimate(ge, r);
+  const int64_t want = t.busy + (int64_t)t.queue.size() + 1;
+  const double c = (double)(want >= t.K ? t.C : (want + 63) / 64);
+  const double step = t.step_ms.n ? t.step_ms.v : ((double)t.g->m * 512.0 * c + (double)t.g->n * c * 64.0 * 24.0) / 3e9;
   const int64_t ahead = (int64_t)t.queue.size() - (t.K - t.busy);
   const double rounds = 1.0 + (ahead >= 0 ? (double)(ahead / t.K + 1) : 0.0);
-  return rounds * (double)r.params.max_supersteps * step < worker;
+  return kLaneMargin * rounds * (double)r.params.max_supersteps * step < worker;
 }
 
 bool lane_is_faster(vc_server s, const GraphEntry& ge, const vc_request& r) {
   const LaneTable& t = *ge.lanes;
-  const double alone = worker_estimate(ge, r);
-  const double worker = (s->backlog_ms + 0.5 * s->running_ms) / (double)s->workers.size() + alone;
-  const double step = t.step_ms.n ? t.step_ms.v
-                                  : ((double)t.g->m * 64.0 + (double)t.g->n * t.C * 1024.0) / 2e9;
+  const double worker = worker_wait(s) + worker_estimate(ge, r);
+  const int64_t want = t.busy + (int64_t)t.queue.size() + 1;
+  const double c = (double)(want >= t.K ? t.C : (want + 63) / 64);
+  const double step = t.step_ms.n ? t.step_ms.v : ((double)t.g->m * 64.0 + (double)t.g->n * c * 1024.0) / 2e9;
   const double steps = t.steps.n ? t.steps.v : 20.0;
   const int64_t ahead = (int64_t)t.queue.size() - (t.K - t.busy);
   const double rounds = 1.0 + (ahead >= 0 ? (double)(ahead / t.K + 1) : 0.0);
-  return rounds * steps * step < worker;
+  return kLaneMargin * rounds * steps * step < worker;
 }
 
 }  // namespace
