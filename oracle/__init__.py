@@ -51,15 +51,22 @@ def _bind(path):
     lib.oracle_run.argtypes = [ctypes.c_int, i64, vp, vp, vp, i32, ctypes.c_double, i64, i64, vp, vp, i64,
                                ctypes.POINTER(i64)]
     lib.oracle_version.restype = ctypes.c_int
+    lib.oracle_combine.restype = ctypes.c_int
+    lib.oracle_combine.argtypes = [ctypes.c_int, i64, vp, vp, vp, vp, vp, vp]
     return lib
+
+
+VERSION = 2
 
 
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build()
         _lib = _bind(_LIB)
+        if _lib.oracle_version() != VERSION:
+            raise OracleError(f"{_LIB} is a stale build; delete it and rebuild")
     return _lib
 
 
@@ -101,6 +108,32 @@ def run(program, n, off, dst, w=None, T: int = 10, damping: float = 0.85, source
     k = min(int(nsteps.value), cap)
     arr = np.frombuffer(steps, dtype=np.int64).reshape(cap, 3)[:k].copy()
     return Result(out, int(nsteps.value), arr[:, 0], arr[:, 1], arr[:, 2])
+
+
+COMBINERS = {"sum_u64": 0, "prod_u64": 1, "max_f64": 2, "minarg": 3, "sum_f64": 4}
+
+
+def combine(op, n, off, dst, msg, active=None, lib=None):
+    """One superstep of message passing with combiner `op` (see COMBINERS):
+    every active vertex sends its 8-byte message msg[v] along its out-edges.
+    Returns (mailbox uint64 words, has-message flags as bool)."""
+    lib = _load() if lib is None else lib
+    code = COMBINERS[op] if isinstance(op, str) else int(op)
+    off64 = np.ascontiguousarray(off, dtype=np.int64)
+    dst32 = np.ascontiguousarray(dst, dtype=np.int32)
+    words = np.ascontiguousarray(np.asarray(msg).view(np.uint64) if np.asarray(msg).dtype != np.uint64 else msg,
+                                 dtype=np.uint64)
+    if off64.shape[0] != n + 1 or words.shape[0] != n:
+        raise ValueError("arrays do not match n")
+    act = None if active is None else np.ascontiguousarray(active, dtype=np.uint8)
+    box = np.empty(n, np.uint64)
+    has = np.empty(n, np.uint8)
+    rc = lib.oracle_combine(code, int(n), off64.ctypes.data, dst32.ctypes.data if dst32.size else None,
+                            words.ctypes.data, None if act is None else act.ctypes.data, box.ctypes.data,
+                            has.ctypes.data)
+    if rc != 0:
+        raise OracleError(_ERRORS.get(rc, f"error {rc}"))
+    return box, has.astype(bool)
 
 
 def run_csr(program, g, **kw) -> Result:

@@ -317,5 +317,92 @@ int oracle_run(int program, int64_t n, const int64_t* off, const int32_t* dst, c
   return status;
 }
 
+/*
+ * One superstep of message passing with a chosen combiner (paper, Section
+ * III, and its hybrid combiner of Figure 1): every active vertex v sends
+ * msg[v] along each of its out-edges; v = 0, 1, ... in turn, edges in CSR
+ * order.  A receiver's first message is stored as is and its flag set;
+ * every later one is merged into the stored message with the combiner.  No
+ * neutral value is assumed.  Messages are 8-byte words:
+ *   ORACLE_COMBINE_SUM_U64   wrapping sum of uint64
+ *   ORACLE_COMBINE_PROD_U64  wrapping product of uint64
+ *   ORACLE_COMBINE_MAX_F64   maximum of binary64 (inputs without NaN)
+ *   ORACLE_COMBINE_MINARG    pair (value: binary32 in the low word, id:
+ *                            uint32 in the high word); the smaller value
+ *                            wins, equal values go to the smaller id
+ *                            (inputs without NaN)
+ *   ORACLE_COMBINE_SUM_F64   binary64 sum, added in the order above
+ * active may be NULL (every vertex sends).  Results: mailbox[u] (undefined
+ * where has[u] == 0) and has[u] in {0, 1}.
+ */
+#define ORACLE_COMBINE_SUM_U64 0
+#define ORACLE_COMBINE_PROD_U64 1
+#define ORACLE_COMBINE_MAX_F64 2
+#define ORACLE_COMBINE_MINARG 3
+#define ORACLE_COMBINE_SUM_F64 4
+
+static double word_f64(uint64_t x) {
+  double d;
+  memcpy(&d, &x, sizeof d);
+  return d;
+}
+
+static uint64_t f64_word(double d) {
+  uint64_t x;
+  memcpy(&x, &d, sizeof x);
+  return x;
+}
+
+static float word_f32_lo(uint64_t x) {
+  uint32_t lo = (uint32_t)(x & 0xFFFFFFFFu);
+  float f;
+  memcpy(&f, &lo, sizeof f);
+  return f;
+}
+
+static uint64_t combine_words(int op, uint64_t stored, uint64_t msg) {
+  switch (op) {
+    case ORACLE_COMBINE_SUM_U64: return stored + msg;
+    case ORACLE_COMBINE_PROD_U64: return stored * msg;
+    case ORACLE_COMBINE_MAX_F64: return word_f64(msg) > word_f64(stored) ? msg : stored;
+    case ORACLE_COMBINE_MINARG: {
+      const float a = word_f32_lo(stored), b = word_f32_lo(msg);
+      const uint32_t ia = (uint32_t)(stored >> 32), ib = (uint32_t)(msg >> 32);
+      return (b < a || (b == a && ib < ia)) ? msg : stored;
+    }
+    default: return f64_word(word_f64(stored) + word_f64(msg));
+  }
+}
+
+int oracle_combine(int op, int64_t n, const int64_t* off, const int32_t* dst, const uint64_t* msg,
+                   const uint8_t* active, uint64_t* mailbox, uint8_t* has) {
+  if (op < ORACLE_COMBINE_SUM_U64 || op > ORACLE_COMBINE_SUM_F64) return ORACLE_EINVAL;
+  if (n < 0 || !off || !msg || !mailbox || !has || off[0] != 0) return ORACLE_EINVAL;
+  for (int64_t v = 0; v < n; ++v) {
+    if (off[v + 1] < off[v]) return ORACLE_EINVAL;
+  }
+  if (off[n] > 0 && !dst) return ORACLE_EINVAL;
+  for (int64_t e = 0; e < off[n]; ++e) {
+    if (dst[e] < 0 || dst[e] >= n) return ORACLE_EINVAL;
+  }
+  for (int64_t u = 0; u < n; ++u) {
+    has[u] = 0;
+    mailbox[u] = 0;
+  }
+  for (int64_t v = 0; v < n; ++v) {
+    if (active && !active[v]) continue;
+    for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+      const int64_t u = dst[e];
+      if (!has[u]) {
+        mailbox[u] = msg[v]; /* first message: stored, flag set */
+        has[u] = 1;
+      } else {
+        mailbox[u] = combine_words(op, mailbox[u], msg[v]);
+      }
+    }
+  }
+  return ORACLE_OK;
+}
+
 /* Library version tag, so a stale build is detected by its loader. */
-int oracle_version(void) { return 1; }
+int oracle_version(void) { return 2; }

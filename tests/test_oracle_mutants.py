@@ -32,6 +32,11 @@ MUTANTS = {
     "cc-accepts-equal": ("g->has_cur[v] && g->umsg_cur[v] < g->label[v]) {\n    g->label[v] = g->umsg_cur[v];\n    broadcast_min",
                          "g->has_cur[v] && g->umsg_cur[v] <= g->label[v] + 1) {\n    g->label[v] = g->umsg_cur[v];\n    broadcast_min"),
     "stale-mailbox": ("    memset(g.has_next, 0, nn);\n", ""),
+    "first-message-combined-with-zero": ("mailbox[u] = msg[v]; /* first message: stored, flag set */",
+                                         "mailbox[u] = combine_words(op, 0, msg[v]);"),
+    "minarg-tie-to-larger-id": ("(b == a && ib < ia)", "(b == a && ib > ia)"),
+    "max-becomes-min": ("word_f64(msg) > word_f64(stored)", "word_f64(msg) < word_f64(stored)"),
+    "inactive-vertices-send": ("if (active && !active[v]) continue;", "if (active && !active[v] && v < 0) continue;"),
 }
 
 
@@ -84,6 +89,32 @@ def _pins_pass(lib) -> bool:
         r = oracle.run_csr("cc", rmatgen.path(6), lib=lib)
         if r.senders.tolist() != [6, 5, 4, 3, 2, 1, 0]:
             return False
+        # combiners vs numpy ufunc.at and brute force (first message stored, no neutral value)
+        g = rmatgen.rmat(8, 6, seed=11)
+        rng = np.random.default_rng(11)
+        act = rng.random(g.n) < 0.7
+        src = np.repeat(np.arange(g.n), np.diff(g.off))
+        keep = act[src]
+        msg = rng.integers(0, 2**64, g.n, dtype=np.uint64) | np.uint64(1)
+        box, has = oracle.combine("prod_u64", g.n, g.off, g.dst, msg, act, lib=lib)
+        ref = np.ones(g.n, np.uint64)
+        np.multiply.at(ref, g.dst[keep], msg[src[keep]])
+        if not (np.array_equal(has, np.bincount(g.dst[keep], minlength=g.n) > 0) and np.array_equal(box[has], ref[has])):
+            return False
+        vals = rng.standard_normal(g.n)
+        box, has = oracle.combine("max_f64", g.n, g.off, g.dst, vals, act, lib=lib)
+        ref = np.full(g.n, -np.inf)
+        np.maximum.at(ref, g.dst[keep], vals[src[keep]])
+        if not np.array_equal(box.view(np.float64)[has], ref[has]):
+            return False
+        v32 = rng.integers(-2, 3, g.n).astype(np.float32)
+        ids = rng.permutation(g.n).astype(np.uint32)
+        words = (ids.astype(np.uint64) << np.uint64(32)) | v32.view(np.uint32).astype(np.uint64)
+        box, has = oracle.combine("minarg", g.n, g.off, g.dst, words, act, lib=lib)
+        for u in range(g.n):
+            senders = src[(g.dst == u) & act[src]]
+            if senders.size and box[u] != words[min(senders, key=lambda v: (v32[v], ids[v]))]:
+                return False
     except oracle.OracleError:
         return False
     return True

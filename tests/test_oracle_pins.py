@@ -393,3 +393,91 @@ def test_oracle_reports_cap():
     g = rmatgen.path(10)
     with pytest.raises(oracle.OracleError):
         oracle.run_csr("cc", g, max_supersteps=5)
+
+
+# ---------------------------------------------------------------- combiners
+# One superstep of message passing with a chosen combiner (paper, Section III
+# and Figure 1: the first message is stored, later ones merged; no neutral
+# value).  Pinned against numpy's unbuffered ufunc.at, which applies an
+# operation at repeated indices one at a time in index order, and against
+# brute force over each receiver's sorted incoming messages.
+
+def _edges(g):
+    src = np.repeat(np.arange(g.n), np.diff(g.off))
+    return src, np.asarray(g.dst, dtype=np.int64)
+
+
+def _combine_case(seed):
+    g = rmatgen.rmat(9, 6, seed=seed)
+    rng = np.random.default_rng(seed)
+    active = rng.random(g.n) < 0.7
+    return g, rng, active
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_combine_integer_sum_and_product_match_ufunc_at(seed):
+    g, rng, active = _combine_case(seed)
+    msg = rng.integers(0, 2**64, g.n, dtype=np.uint64)
+    src, dst = _edges(g)
+    keep = active[src]
+    counts = np.bincount(dst[keep], minlength=g.n)
+    box, has = oracle.combine("sum_u64", g.n, g.off, g.dst, msg, active)
+    ref = np.zeros(g.n, np.uint64)
+    np.add.at(ref, dst[keep], msg[src[keep]])
+    assert np.array_equal(has, counts > 0) and np.array_equal(box[has], ref[has])
+    # product: a neutral-initialised mailbox would agree (1 * x = x); a
+    # zero-initialised one would not, and the flags must still match
+    box, has = oracle.combine("prod_u64", g.n, g.off, g.dst, msg | np.uint64(1), active)
+    ref = np.ones(g.n, np.uint64)
+    np.multiply.at(ref, dst[keep], (msg | np.uint64(1))[src[keep]])
+    assert np.array_equal(has, counts > 0) and np.array_equal(box[has], ref[has])
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_combine_float_max_and_ordered_sum(seed):
+    g, rng, active = _combine_case(seed)
+    vals = rng.standard_normal(g.n)
+    src, dst = _edges(g)
+    keep = active[src]
+    box, has = oracle.combine("max_f64", g.n, g.off, g.dst, vals, active)
+    ref = np.full(g.n, -np.inf)
+    np.maximum.at(ref, dst[keep], vals[src[keep]])
+    assert np.array_equal(box.view(np.float64)[has], ref[has])
+    # sum in sender order: identical bits to sequential ufunc.at from +0.0
+    # (no message is -0.0, so the stored first message equals 0.0 + it)
+    box, has = oracle.combine("sum_f64", g.n, g.off, g.dst, vals, active)
+    ref = np.zeros(g.n)
+    np.add.at(ref, dst[keep], vals[src[keep]])
+    assert np.array_equal(box.view(np.float64)[has], ref[has])
+    assert not has[np.bincount(dst[keep], minlength=g.n) == 0].any()
+
+
+def _pack(val32, ids):
+    return (ids.astype(np.uint64) << np.uint64(32)) | val32.view(np.uint32).astype(np.uint64)
+
+
+@pytest.mark.parametrize("seed", [6, 7])
+def test_combine_minarg_brute_force_with_ties(seed):
+    g, rng, active = _combine_case(seed)
+    vals = rng.integers(-3, 4, g.n).astype(np.float32)  # many ties
+    ids = rng.permutation(g.n).astype(np.uint32)
+    box, has = oracle.combine("minarg", g.n, g.off, g.dst, _pack(vals, ids), active)
+    src, dst = _edges(g)
+    for u in range(g.n):
+        senders = src[(dst == u) & active[src]]
+        assert has[u] == (senders.size > 0)
+        if senders.size:
+            best = min(senders, key=lambda v: (vals[v], ids[v]))
+            assert box[u] == _pack(vals[best:best + 1], ids[best:best + 1])[0], u
+
+
+def test_combine_inactive_and_duplicate_edges():
+    c = rmatgen.raw_csr(4, [0, 0, 1, 3, 3], [1, 1, 1, 1, 2])
+    msg = np.array([3, 5, 7, 11], np.uint64)
+    box, has = oracle.combine("prod_u64", 4, c.off, c.dst, msg, np.array([1, 1, 0, 1]))
+    assert has.tolist() == [False, True, True, False]
+    assert box[1] == 3 * 3 * 5 * 11 and box[2] == 11
+    box, has = oracle.combine("sum_u64", 4, c.off, c.dst, msg)
+    assert box[1] == 3 + 3 + 5 + 11 and box[2] == 11
+    with pytest.raises(oracle.OracleError):
+        oracle.combine(9, 4, c.off, c.dst, msg)
