@@ -231,6 +231,66 @@ def bench_multi(args, dev):
     }
 
 
+def bench_combine(args, dev):
+    """One superstep of message passing on the directed R-MAT graph (scale 24
+    by default) with each generic combiner (flag + compare-and-swap; every
+    vertex active, so the pull form runs), against the native-atomic push
+    superstep of PageRank (uint64 atomic add per message) on the same graph."""
+    import torch
+    import rmatgen
+    from paper_2010_01542_amd import Graph
+    from paper_2010_01542_amd.vc import COMBINERS
+    scale = args.scale or 24
+    csr = rmatgen.workload("sssp-s26", scale=scale, threads=args.gen_threads)
+    g = Graph.from_csr(csr, device=dev)
+    rng = np.random.default_rng(rmatgen.BASE_SEED + 7)
+    n, m = csr.n, csr.m
+    words = {"sum_u64": rng.integers(0, 2**62, n, dtype=np.uint64),
+             "prod_u64": rng.integers(0, 2**62, n, dtype=np.uint64) | np.uint64(1),
+             "max_f64": rng.standard_normal(n).view(np.uint64),
+             "minarg": ((rng.permutation(n).astype(np.uint64) << np.uint64(32)) |
+                        rng.integers(0, 1000, n).astype(np.float32).view(np.uint32).astype(np.uint64)),
+             "sum_f64": rng.standard_normal(n).view(np.uint64)}
+    box = torch.empty(n, dtype=torch.int64, device=dev)
+    has = torch.empty(n, dtype=torch.int32, device=dev)
+    res = {}
+    for op in COMBINERS:
+        msg = torch.from_numpy(words[op].view(np.int64)).to(dev)
+        for _ in range(args.warmup):
+            g.combine(op, msg, None, box, has)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.combine(op, msg, None, box, has)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        res[op] = {"ms": round(dt * 1e3, 3), "gteps": round(m / dt / 1e9, 2)}
+        log(f"combine {op}: {dt * 1e3:.2f} ms")
+    out = torch.empty(n, dtype=torch.float32, device=dev)
+    g.run("pagerank", out, T=1, schedule="edge")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.run("pagerank", out, T=1, schedule="edge")
+    torch.cuda.synchronize()
+    native = (time.perf_counter() - t0) / args.steps
+    worst = max(v["ms"] for v in res.values())
+    # pull form: per in-edge the source id and the sender's message; per
+    # receiver its transpose offset, message and flag written once
+    alg = 12 * m + 12 * n + (n + 1) * 8
+    return {
+        "metric": "messages combined per second with combiners without native atomics",
+        "value": round(m / (worst / 1e3) / 1e9, 2), "unit": "GTEPS (slowest combiner)", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": worst, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64/f64", "data": "synthetic R-MAT (seeded)",
+        "config": {"workload": f"combine@{csr.name}", "vertices": n, "edges": m},
+        "combiners": res,
+        "native_atomic_pagerank_push_superstep": {"ms": round(native * 1e3, 3), "gteps": round(m / native / 1e9, 2)},
+        "roofline": {"bound": "hbm", "achieved": round(alg / (worst / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(alg / (worst / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None},
+    }
+
+
 SERVE_GRAPHS = (  # name, scale, directed, weighted, lanes, share of SSSP / PPR traffic, rank lanes
     ("s18", 18, True, True, 256, 0.50, 256),
     ("s22", 22, True, True, 256, 0.35, 128),
@@ -399,7 +459,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sssp-s26", choices=["sssp-s26", "cc-s22", "pr-s16", "batch", "multi", "serve"])
+    ap.add_argument("--workload", default="sssp-s26", choices=["sssp-s26", "cc-s22", "pr-s16", "batch", "multi", "serve", "combine"])
     ap.add_argument("--sources", type=int, default=256, help="multi workload: SSSP sources")
     ap.add_argument("--members", type=int, default=1024, help="batch workload: number of graphs")
     ap.add_argument("--requests", type=int, default=600, help="serve workload: number of requests")
@@ -443,6 +503,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps(bench_serve(args, dev)), flush=True)
+        return
+    if args.workload == "combine":
+        print(json.dumps(bench_combine(args, dev)), flush=True)
         return
     t = time.time()
     csr = rmatgen.workload(args.workload, scale=args.scale, threads=args.gen_threads)

@@ -278,6 +278,37 @@ vc_status vc_batch_autotune(vc_batch b, const vc_params* base, hipStream_t strea
 vc_status vc_graph_autotune(vc_graph g, vc_program program, const vc_params* base, hipStream_t stream,
                             vc_params* best);
 
+/* ---------------------------------------------------------------- combiners
+ * One superstep of message passing with a combiner that has no native
+ * atomic: the paper's hybrid combiner (Section III, Figure 1).  Every vertex
+ * v with active[v] != 0 sends its 8-byte message msg[v] along each of its
+ * out-edges; a receiver's first message is stored as is and flagged, later
+ * ones are merged into it (no neutral value is assumed).  The mailbox and
+ * its flag form a three-state word claimed by compare-and-swap and
+ * published with a release store, and merges are compare-and-swap loops
+ * that skip the swap when the merge changes nothing; no lock is taken. */
+typedef enum {
+  VC_COMBINE_SUM_U64 = 0,  /* wrapping sum of uint64 */
+  VC_COMBINE_PROD_U64 = 1, /* wrapping product of uint64 */
+  VC_COMBINE_MAX_F64 = 2,  /* maximum of binary64 (no NaN) */
+  VC_COMBINE_MINARG = 3,   /* (binary32 value in the low word, uint32 id in the high
+                              word): the smaller value, equal values to the smaller
+                              id (no NaN) */
+  VC_COMBINE_SUM_F64 = 4   /* binary64 sum; the order of additions is unspecified */
+} vc_combiner;
+
+/*   msg      device, N uint64 words, caller's vertex order.
+ *   active   device, N bytes (0 = does not send), or NULL: every vertex sends.
+ *   mailbox  device, N uint64, caller-owned: the merged message, 0 where
+ *            has is 0.
+ *   has      device, N uint32, caller-owned: 1 where a message arrived, else 0.
+ * Returns after the outputs are complete.  The results are exact for every
+ * combiner but VC_COMBINE_SUM_F64, whose rounding depends on the order.
+ * Errors: VC_ERR_INVALID_ARG (null, misaligned, bad combiner),
+ * VC_ERR_OUT_OF_MEMORY, VC_ERR_HIP. */
+vc_status vc_combine(vc_graph g, vc_combiner op, const uint64_t* msg, const uint8_t* active, uint64_t* mailbox,
+                     uint32_t* has, hipStream_t stream);
+
 /* ---------------------------------------------------------------- serving
  * A request server over resident graphs.  Requests are independent program
  * runs (paper, Section I) that arrive over time and complete out of order.

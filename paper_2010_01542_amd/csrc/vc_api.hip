@@ -919,6 +919,61 @@ vc_status vc_run(vc_graph g, vc_program program, const vc_params* params, void* 
   return st;
 }
 
+vc_status vc_combine(vc_graph g, vc_combiner op, const uint64_t* msg, const uint8_t* active, uint64_t* mailbox,
+                     uint32_t* has, hipStream_t stream) {
+  if (!g || !msg || !mailbox || !has) return fail(VC_ERR_INVALID_ARG, "null argument");
+  if (op < VC_COMBINE_SUM_U64 || op > VC_COMBINE_SUM_F64) return fail(VC_ERR_INVALID_ARG, "bad combiner");
+  if ((uintptr_t)msg % 8 || (uintptr_t)mailbox % 8 || (uintptr_t)has % 4)
+    return fail(VC_ERR_INVALID_ARG, "misaligned array");
+  int cur = 0;
+  VC_TRY(hipGetDevice(&cur));
+  if (cur != g->device) return fail(VC_ERR_INVALID_ARG, "graph lives on another device than the current one");
+  const int64_t n = g->n, m = g->m;
+  const int32_t* inv = g->relabeled ? g->inv_p : nullptr;
+  const auto* words = reinterpret_cast<const unsigned long long*>(msg);
+  auto* box = reinterpret_cast<unsigned long long*>(mailbox);
+  VC_TRY(vc::launch_fill_u32(has, n, 0u, stream));
+  VC_TRY(vc::launch_fill_u32(reinterpret_cast<uint32_t*>(mailbox), 2 * n, 0u, stream));
+  if (m == 0) {
+    VC_TRY(hipStreamSynchronize(stream));
+    return VC_OK;
+  }
+  vc_params p;
+  vc_params_default(&p);
+  // Direction: push (contention only at the few receivers of a sparse set of
+  // senders) when the senders' out-edges are under the pull threshold, else
+  // pull (receivers fold their in-edges; no contention).
+  bool pull = true;
+  if (active) {
+    VC_TRY(g->counters.ensure(sizeof(vc::Counters)));
+    if (!g->host_ctr) VC_TRY(hipHostMalloc((void**)&g->host_ctr, sizeof(vc::Counters), hipHostMallocDefault));
+    VC_TRY(vc::launch_zero_counters(g->counters.as<vc::Counters>(), stream));
+    VC_TRY(vc::launch_active_edges(g->off, g->off64, n, inv, active, g->counters.as<vc::Counters>(), stream));
+    VC_TRY(hipMemcpyAsync(g->host_ctr, g->counters.p, sizeof(vc::Counters), hipMemcpyDeviceToHost, stream));
+    VC_TRY(hipStreamSynchronize(stream));
+    pull = (double)g->host_ctr->edges >= pull_threshold(p) * (double)m;
+    if (g->host_ctr->edges == 0) return VC_OK;
+  }
+  if (pull) {
+    int64_t tile = vc::pull_tile(pick_tile(p, g));
+    while (tile > 256 && vc::combine_pull_lds_bytes(tile) > g->max_lds) tile /= 2;
+    vc_status st = ensure_csc(g, stream);
+    if (st == VC_OK) st = csc_partition(g, tile, stream);
+    if (st != VC_OK) return st;
+    VC_TRY(vc::launch_combine_pull((int)op, g->csc_off_p, g->in_src, n, m, g->csc_tiles_p, g->csc_tile,
+                                   g->csc_ntiles, inv, words, active, box, has, stream));
+  } else {
+    int64_t tile = pick_tile(p, g);
+    while (tile > 64 && vc::combine_lds_bytes(tile) > g->max_lds) tile -= 64;
+    vc_status st = dense_partition(g, tile, stream);
+    if (st != VC_OK) return st;
+    VC_TRY(vc::launch_combine((int)op, g->off, g->off64, g->dst, n, m, g->dense_tiles_p, tile, g->dense_ntiles, inv,
+                              words, active, box, has, stream));
+  }
+  VC_TRY(hipStreamSynchronize(stream));
+  return VC_OK;
+}
+
 // ---------------------------------------------------------------- batches
 
 struct vc_batch_s {

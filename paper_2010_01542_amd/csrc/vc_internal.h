@@ -180,6 +180,26 @@ hipError_t launch_rl_pull(int C, const int64_t* in_off, const int32_t* in_src, i
 hipError_t launch_rl_apply(const void* off, bool off64, const int32_t* ids, int64_t n, int ceff,
                            const RankLane* lanes, unsigned long long* contrib, unsigned long long* mb, hipStream_t s);
 
+// ---------------------------------------------------------------- generic combiner
+size_t combine_lds_bytes(int64_t tile);
+size_t combine_pull_lds_bytes(int64_t tile);
+// ctr->edges += out-edges of the vertices x with active[inv[x]] != 0.
+hipError_t launch_active_edges(const void* off, bool off64, int64_t n, const int32_t* inv, const uint8_t* active,
+                               Counters* ctr, hipStream_t s);
+// Pull form over the transpose (in_off / in_src, partition tile_v); flag /
+// mailbox zero on entry.
+hipError_t launch_combine_pull(int op, const int64_t* in_off, const int32_t* in_src, int64_t n, int64_t m,
+                               const int32_t* tile_v, int64_t tile, int64_t ntiles, const int32_t* inv,
+                               const unsigned long long* msg, const uint8_t* active, unsigned long long* mailbox,
+                               uint32_t* flag, hipStream_t s);
+// One push superstep over the CSR merge-path partition tile_v (tile items);
+// inv maps internal ids to the caller's (NULL: identity).  flag / mailbox
+// must be zero on entry.
+hipError_t launch_combine(int op, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
+                          const int32_t* tile_v, int64_t tile, int64_t ntiles, const int32_t* inv,
+                          const unsigned long long* msg, const uint8_t* active, unsigned long long* mailbox,
+                          uint32_t* flag, hipStream_t s);
+
 // In-place exclusive scan of P[0..count) with P[count] = total; `blocks`
 // is scratch of scan_scratch_entries(count) int64 values.
 int64_t scan_scratch_entries(int64_t count);

@@ -26,6 +26,7 @@ GRAPH_BORROW, GRAPH_VALIDATE, GRAPH_SYMMETRIC, GRAPH_NO_RELABEL = 1, 2, 4, 8
 OPT_NO_HUB_AGGREGATION, OPT_NO_TEST_BEFORE_ATOMIC, OPT_F32_ACCUMULATE, OPT_GRAPH_CAPTURE = 1, 2, 4, 8
 UNREACHED = 0xFFFFFFFF
 ROUTE_AUTO, ROUTE_LANES, ROUTE_WORKER = 0, 1, 2
+COMBINERS = {"sum_u64": 0, "prod_u64": 1, "max_f64": 2, "minarg": 3, "sum_f64": 4}
 ROUTES = {"auto": ROUTE_AUTO, "lanes": ROUTE_LANES, "worker": ROUTE_WORKER}
 
 OK, ERR_INVALID_ARG, ERR_BAD_GRAPH, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_UNSUPPORTED, ERR_NOT_CONVERGED = range(7)
@@ -34,7 +35,7 @@ EXPORTS = ("vc_graph_create", "vc_graph_destroy", "vc_graph_footprint", "vc_run"
            "vc_status_string", "vc_last_error", "vc_abi_version", "vc_batch_create", "vc_batch_layout",
            "vc_batch_run", "vc_batch_destroy", "vc_run_multi_source", "vc_graph_autotune", "vc_batch_autotune",
            "vc_server_create", "vc_server_add_graph", "vc_server_submit", "vc_server_poll", "vc_server_drain",
-           "vc_server_info_get", "vc_server_destroy")
+           "vc_server_info_get", "vc_server_destroy", "vc_combine")
 
 
 class GraphDesc(ctypes.Structure):
@@ -133,6 +134,8 @@ def load(path: str = LIB_PATH):
     lib.vc_run_multi_source.restype = i32
     lib.vc_run_multi_source.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(Params), vp, vp,
                                         ctypes.POINTER(StatsStruct)]
+    lib.vc_combine.restype = i32
+    lib.vc_combine.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     lib.vc_server_create.restype = i32
     lib.vc_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
     lib.vc_server_add_graph.restype = i32
@@ -289,6 +292,27 @@ class Graph:
                                         _stream_handle(stream), ctypes.byref(st) if st is not None else None)
         _check(rc, "vc_run_multi_source")
         return out, _stats_result(st, arrays, capacity)
+
+    def combine(self, op, msg, active=None, mailbox=None, has=None, stream=None):
+        """vc_combine: one superstep with combiner `op` (COMBINERS); msg: N 8-byte
+        words (int64 / uint64 / float64 tensor), active: optional N uint8 / bool.
+        Returns (mailbox as int64 words, has as int32)."""
+        import torch
+        code = COMBINERS[op] if isinstance(op, str) else int(op)
+        if not msg.is_cuda or not msg.is_contiguous() or msg.numel() != self.n or msg.element_size() != 8:
+            raise TypeError("msg must be a contiguous CUDA tensor of N 8-byte elements")
+        if active is not None:
+            if active.dtype == torch.bool:
+                active = active.to(torch.uint8)
+            if not active.is_cuda or not active.is_contiguous() or active.numel() != self.n or active.element_size() != 1:
+                raise TypeError("active must be a contiguous CUDA tensor of N bytes")
+        if mailbox is None:
+            mailbox = torch.empty(self.n, dtype=torch.int64, device=self.device)
+        if has is None:
+            has = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        _check(load().vc_combine(self._h, code, msg.data_ptr(), None if active is None else active.data_ptr(),
+                                 mailbox.data_ptr(), has.data_ptr(), _stream_handle(stream)), "vc_combine")
+        return mailbox, has
 
     def run(self, program, out=None, *, T: int = 10, damping: float = 0.85, source: int = 0,
             max_supersteps: int = 0, schedule="auto", tile: int = 0, options: int = 0, pull_fraction: float = 0.0,
