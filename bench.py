@@ -291,166 +291,211 @@ def bench_combine(args, dev):
     }
 
 
-SERVE_GRAPHS = (  # name, scale, directed, weighted, lanes, share of SSSP / PPR traffic, rank lanes
-    ("s18", 18, True, True, 256, 0.50, 256),
-    ("s22", 22, True, True, 256, 0.35, 128),
-    ("s24", 24, True, True, 256, 0.15, 64),
+SERVE_RESIDENT = (  # name, scale, SSSP / PPR share among resident requests, lanes, rank lanes
+    ("s18", 18, 0.50, 256, 256),
+    ("s22", 22, 0.35, 256, 128),
+    ("s24", 24, 0.15, 256, 64),
 )
-SERVE_CC = ("cc-s20", 20, False, False, 64)
+SERVE_TWIN_LANES = 64       # CC lanes of each symmetrised twin
+SERVE_POOL = 64             # graphs of scale 10..14 uploaded on first use
+SERVE_POOL_SHARE = 0.2      # share of requests on the uploaded pool
+SERVE_LOADS = (0.5, 1.0, 2.0, 4.0)  # offered load, times the sequential capacity
 
 
-def serve_requests(count, graphs, seed):
-    """Seeded request stream: 70% SSSP, 20% PPR (T = 20), 10% CC; SSSP and PPR
-    pick a graph by its share and a uniform source with out-edges; CC runs on
-    the symmetrised graph."""
+def serve_requests(count, graphs, pool, seed):
+    """Seeded request stream: 70% SSSP, 20% PPR (T = 20), 10% CC.  A request
+    targets the uploaded pool with probability SERVE_POOL_SHARE (uniform
+    graph), else a resident graph by its share; CC runs on the graph's
+    symmetrised twin; sources are uniform among vertices with out-edges."""
     rng = np.random.default_rng(seed)
-    names = [g[0] for g in SERVE_GRAPHS]
-    share = np.array([g[5] for g in SERVE_GRAPHS])
+    names = [g[0] for g in SERVE_RESIDENT]
+    share = np.array([g[2] for g in SERVE_RESIDENT])
     senders = {k: np.flatnonzero(c.outdeg > 0) for k, c in graphs.items()}
     reqs = []
     for _ in range(count):
         u = rng.random()
-        if u < 0.1:
-            reqs.append((SERVE_CC[0], "cc", 0))
-            continue
-        name = names[int(rng.choice(len(names), p=share))]
-        src = int(rng.choice(senders[name]))
-        reqs.append((name, "sssp" if u < 0.8 else "ppr", src))
+        prog = "cc" if u < 0.1 else ("sssp" if u < 0.8 else "ppr")
+        if rng.random() < SERVE_POOL_SHARE:
+            base = f"pool{int(rng.integers(0, len(pool)))}"
+        else:
+            base = names[int(rng.choice(len(names), p=share))]
+        name = base + "u" if prog == "cc" else base
+        src = 0 if prog == "cc" else int(rng.choice(senders[name]))
+        reqs.append((name, prog, src))
     return reqs
 
 
 def bench_serve(args, dev):
-    """Request serving on resident graphs.  Baseline: every request run alone
-    with vc_run, one after another (first-come-first-served, one stream).
-    Server: lane tables (continuous batching) and worker threads, CC / SSSP
-    routed between them by expected completion time, PPR on the workers.  Reports saturation throughput (all requests queued at once) and the
-    latency of an open-loop Poisson arrival stream at 80% of the baseline's
-    capacity, the baseline's latencies simulated from its measured service
-    times on the same arrival times."""
+    """Request serving (continuous batching) against the plain path.
+
+    Resident graphs: directed weighted R-MAT scales 18, 22 and 24 (edge
+    factor 16), each with a symmetrised twin for CC; a seeded pool of scale
+    10..14 graphs is uploaded on first use.  The plain path runs every request
+    alone with vc_run, first come first served, on one stream; its measured
+    capacity (requests/s) sets the offered loads.  For each load in
+    SERVE_LOADS a fresh server (lane tables, rank-lane tables, worker
+    threads; requests routed by expected completion) receives the same
+    request stream with seeded Poisson arrivals; latency runs from arrival
+    until the poller on the host sees the completion.  The plain path's
+    latency at the same arrivals comes from a first-come-first-served queue
+    over its measured service times."""
     import torch
     import rmatgen
     from paper_2010_01542_amd import Graph, Server, vc
     t = time.time()
     csrs = {}
-    for name, scale, directed, weighted, _, _, _ in SERVE_GRAPHS:
-        csrs[name] = rmatgen.rmat(scale, 16, seed=rmatgen.BASE_SEED + scale, directed=directed, weighted=weighted,
-                                  threads=args.gen_threads)
-    name, scale, directed, weighted, _ = SERVE_CC
-    csrs[name] = rmatgen.rmat(scale, 16, seed=rmatgen.BASE_SEED + 100 + scale, directed=directed,
-                              weighted=weighted, threads=args.gen_threads)
+    for name, scale, _, _, _ in SERVE_RESIDENT:
+        csrs[name] = rmatgen.rmat(scale, 16, seed=rmatgen.BASE_SEED + scale, weighted=True, threads=args.gen_threads)
+        csrs[name + "u"] = rmatgen.rmat(scale, 16, seed=rmatgen.BASE_SEED + scale, directed=False,
+                                        threads=args.gen_threads)
+    prng = np.random.default_rng(rmatgen.BASE_SEED + 8)
+    pool = []
+    for j in range(SERVE_POOL):
+        sc, ef = int(prng.integers(10, 15)), int(prng.integers(8, 33))
+        csrs[f"pool{j}"] = rmatgen.rmat(sc, ef, seed=rmatgen.BASE_SEED + 9000 + j, weighted=True)
+        csrs[f"pool{j}u"] = rmatgen.rmat(sc, ef, seed=rmatgen.BASE_SEED + 9000 + j, directed=False)
+        pool.append(f"pool{j}")
     log(f"generated serving graphs in {time.time() - t:.1f}s: " +
-        ", ".join(f"{k} n={c.n} m={c.m}" for k, c in csrs.items()))
-    graphs = {k: Graph.from_csr(c, device=dev, symmetric=(k == SERVE_CC[0])) for k, c in csrs.items()}
-    reqs = serve_requests(args.requests, csrs, rmatgen.BASE_SEED + 5)
-    lanes_of = {x[0]: x[4] for x in SERVE_GRAPHS}
-    lanes_of[SERVE_CC[0]] = SERVE_CC[4]
-    rank_lanes_of = {x[0]: x[6] for x in SERVE_GRAPHS}
-    rank_lanes_of[SERVE_CC[0]] = 0
-    pool = {}
+        ", ".join(f"{k} n={csrs[k].n} m={csrs[k].m}" for k in csrs if not k.startswith("pool")))
+    resident = [k for k in csrs if not k.startswith("pool")]
+    graphs = {k: Graph.from_csr(csrs[k], device=dev, symmetric=k.endswith("u")) for k in resident}
+    lanes_of = {x[0]: x[3] for x in SERVE_RESIDENT}
+    rank_lanes_of = {x[0]: x[4] for x in SERVE_RESIDENT}
+    for x in SERVE_RESIDENT:
+        lanes_of[x[0] + "u"] = SERVE_TWIN_LANES
+        rank_lanes_of[x[0] + "u"] = 0
+    reqs = serve_requests(args.requests, csrs, pool, rmatgen.BASE_SEED + 5)
+    outs = []
+    for name, prog, _ in reqs:
+        outs.append(torch.empty(csrs[name].n, dtype=torch.float32 if prog == "ppr" else torch.int32, device=dev))
 
-    def out_for(i, name, prog):
-        key = (name, prog == "ppr", i)
-        if key not in pool:
-            pool[key] = torch.empty(csrs[name].n, dtype=torch.float32 if prog == "ppr" else torch.int32, device=dev)
-        return pool[key]
+    def upload(name):
+        return Graph.from_csr(csrs[name], device=dev, symmetric=name.endswith("u"))
 
-    # baseline: each request alone, in order (warm-up: one of each kind first)
-    for name, prog, src in {(r[0], r[1]): r for r in reqs}.values():
-        graphs[name].run(prog, out_for(0, name, prog), source=src, T=20)
+    # plain path: every request alone, in order; pool graphs created on first use
+    for name in resident:  # warm-up of every kind: transposes, workspaces
+        for prog in ("sssp", "ppr") if not name.endswith("u") else ("cc",):
+            graphs[name].run(prog, T=20)
     torch.cuda.synchronize()
     service = np.zeros(len(reqs))
+    live = dict(graphs)
     t0 = time.perf_counter()
     for i, (name, prog, src) in enumerate(reqs):
         a = time.perf_counter()
-        graphs[name].run(prog, out_for(0, name, prog), source=src, T=20)
+        if name not in live:
+            live[name] = upload(name)
+        live[name].run(prog, outs[i], source=src, T=20)
         service[i] = time.perf_counter() - a
     base_s = time.perf_counter() - t0
-    log(f"sequential: {len(reqs)} requests in {base_s:.2f}s")
-    checks = [i for i in range(len(reqs)) if reqs[i][1] != "ppr"][:8]
-    ref = {}
-    for i in checks:
-        name, prog, src = reqs[i]
-        ref[i] = graphs[name].run(prog, source=src)[0].cpu()
+    capacity = len(reqs) / base_s
+    log(f"plain path: {len(reqs)} requests in {base_s:.2f}s ({capacity:.1f} requests/s)")
+
+    def kind(i):
+        name, prog, _ = reqs[i]
+        return f"{prog}@{'pool' if name.startswith('pool') else name}"
+
+    plain_by_kind = {}
+    for i in range(len(reqs)):
+        k = plain_by_kind.setdefault(kind(i), [0, 0.0])
+        k[0] += 1
+        k[1] += service[i] * 1e3
+    plain_by_kind = {k: {"requests": v[0], "total_ms": round(v[1], 1), "mean_ms": round(v[1] / v[0], 3)}
+                     for k, v in sorted(plain_by_kind.items())}
+    log(f"plain path by kind: {json.dumps(plain_by_kind)}")
+    checks = [i for i in range(len(reqs))][:: max(1, len(reqs) // 24)]
+    ref = {i: outs[i].cpu() for i in checks}
+    del live
 
     def run_server(arrivals):
-        """Submits request i at arrivals[i] (seconds from start); returns the
-        makespan and per-request latencies (submit -> result complete)."""
+        """Submits request i at arrivals[i] (seconds from the start) from this
+        thread while a second thread polls completions (the poll call
+        releases the interpreter lock), so latency is arrival to the moment
+        the host sees the completion."""
+        import threading
         srv = Server(workers=args.workers)
         ids = {k: srv.add_graph(g, lanes=lanes_of[k], rank_lanes=rank_lanes_of[k]) for k, g in graphs.items()}
-        outs = [out_for(i, name, prog) for i, (name, prog, _) in enumerate(reqs)]
+        uploaded = {}
         lat = np.zeros(len(reqs))
-        lanes_used = 0
         tick = {}
+        state = {"got": 0, "lanes": 0, "error": None}
+        lock = threading.Lock()
         t_start = time.perf_counter()
-        got = 0
-        for i, (name, prog, src) in enumerate(reqs):
-            wait = arrivals[i] - (time.perf_counter() - t_start)
-            while wait > 0:
-                for c in srv.poll(timeout_ms=max(1, int(wait * 1e3)), cap=1024):
-                    lat[tick[c.ticket]] = c.latency_ms
-                    lanes_used += c.lane >= 0
-                    got += 1
-                    assert c.status == vc.OK, c.message
+
+        def poller():
+            while state["got"] < len(reqs) and state["error"] is None:
+                for c in srv.poll(timeout_ms=50, cap=1024):
+                    now = time.perf_counter() - t_start
+                    with lock:
+                        i = tick[c.ticket]
+                    lat[i] = (now - arrivals[i]) * 1e3
+                    state["lanes"] += c.lane >= 0
+                    state["got"] += 1
+                    if c.status != vc.OK:
+                        state["error"] = c.message
+
+        th = threading.Thread(target=poller)
+        th.start()
+        try:
+            for i, (name, prog, src) in enumerate(reqs):
                 wait = arrivals[i] - (time.perf_counter() - t_start)
-            tick[srv.submit(ids[name], prog, outs[i], source=src, T=20)] = i
-        while got < len(reqs):
-            for c in srv.poll(timeout_ms=1000, cap=1024):
-                lat[tick[c.ticket]] = c.latency_ms
-                lanes_used += c.lane >= 0
-                got += 1
-                assert c.status == vc.OK, c.message
+                if wait > 0:
+                    time.sleep(wait)
+                if name not in ids:  # first use of a pool graph: upload and register
+                    uploaded[name] = upload(name)
+                    ids[name] = srv.add_graph(uploaded[name])
+                with lock:
+                    tick[srv.submit(ids[name], prog, outs[i], source=src, T=20)] = i
+        finally:
+            th.join()
+        assert state["error"] is None, state["error"]
         span = time.perf_counter() - t_start
         info = srv.info()
         srv.close()
         for i in checks:
-            assert torch.equal(outs[i].cpu(), ref[i]), f"served request {i} differs from its alone run"
-        return span, lat, info, lanes_used
-
-    span, lat_sat, info, lanes_used = run_server(np.zeros(len(reqs)))
-    log(f"server, all queued: {len(reqs)} requests in {span:.2f}s; {info}")
-    rate = 0.8 * len(reqs) / base_s
-    gaps = np.random.default_rng(rmatgen.BASE_SEED + 6).exponential(1.0 / rate, len(reqs))
-    arrivals = np.cumsum(gaps) - gaps[0]
-    span_open, lat_open, info_open, lanes_open = run_server(arrivals)
-    # the baseline on the same arrivals: one FIFO server with the measured service times
-    fin, lat_base = 0.0, np.zeros(len(reqs))
-    for i in range(len(reqs)):
-        fin = max(fin, arrivals[i]) + service[i]
-        lat_base[i] = (fin - arrivals[i]) * 1e3
-    kinds = {}
-    for (name, prog, _), s in zip(reqs, service):
-        kinds.setdefault(f"{prog}@{name}", []).append(s * 1e3)
+            assert torch.equal(outs[i].cpu(), ref[i]), f"served request {i} differs from its plain run"
+        return span, lat, info, state["lanes"]
 
     def pct(a, q):
         return round(float(np.percentile(a, q)), 3)
 
-    def by_kind(lat):
-        out = {}
-        for i, (name, prog, _) in enumerate(reqs):
-            out.setdefault(f"{prog}@{name}", []).append(lat[i])
-        return {k: [pct(v, 50), pct(v, 99)] for k, v in sorted(out.items())}
-
+    points = []
+    for load in (args.loads or SERVE_LOADS):
+        rate = load * capacity
+        gaps = np.random.default_rng(rmatgen.BASE_SEED + 6).exponential(1.0 / rate, len(reqs))
+        arrivals = np.cumsum(gaps) - gaps[0]
+        span, lat, info, lanes_used = run_server(arrivals)
+        fin, lat_plain = 0.0, np.zeros(len(reqs))
+        for i in range(len(reqs)):
+            fin = max(fin, arrivals[i]) + service[i]
+            lat_plain[i] = (fin - arrivals[i]) * 1e3
+        plain_span = fin
+        by = {}
+        for i in range(len(reqs)):
+            by.setdefault(kind(i), []).append(lat[i])
+        pt = {"offered_load": load, "arrival_rate_per_s": round(rate, 2),
+              "requests_per_s": round(len(reqs) / span, 2),
+              "latency_ms_p50": pct(lat, 50), "latency_ms_p99": pct(lat, 99),
+              "plain_requests_per_s": round(len(reqs) / plain_span, 2),
+              "plain_latency_ms_p50": pct(lat_plain, 50), "plain_latency_ms_p99": pct(lat_plain, 99),
+              "lane_requests": lanes_used, "lane_supersteps": info["lane_supersteps"],
+              "rank_supersteps": info["rank_supersteps"],
+              "latency_ms_p50_by_kind": {k: pct(v, 50) for k, v in sorted(by.items())}}
+        log(f"load {load}: {json.dumps(pt)}")
+        points.append(pt)
+    best = max(points, key=lambda x: x["requests_per_s"])
     return {
-        "metric": "served requests/s (70% SSSP, 20% PPR T=20, 10% CC on resident R-MAT graphs)",
-        "value": round(len(reqs) / span, 2), "unit": "requests/s", "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": round(span * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u32+f32", "data": "synthetic R-MAT (seeded)",
-        "config": {"workload": f"serve-{len(reqs)}", "graphs": {k: [c.n, c.m] for k, c in csrs.items()},
+        "metric": "served requests/s (70% SSSP, 20% PPR T=20, 10% CC; resident R-MAT graphs and an uploaded pool)",
+        "value": best["requests_per_s"], "unit": "requests/s", "n_gpus": 1, "steps": len(SERVE_LOADS), "warmup": 1,
+        "ms_per_step": round(1e3 * len(reqs) / best["requests_per_s"], 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32+f32", "data": "synthetic R-MAT (seeded)",
+        "config": {"workload": f"serve-{len(reqs)}", "requests": len(reqs),
+                   "graphs": {k: [csrs[k].n, csrs[k].m] for k in resident},
+                   "uploaded_pool": {"graphs": SERVE_POOL, "scales": "10..14", "share": SERVE_POOL_SHARE},
                    "lanes": lanes_of, "rank_lanes": rank_lanes_of, "workers": args.workers,
                    "hw_queues": args.hw_queues},
-        "sequential": {"requests_per_s": round(len(reqs) / base_s, 2),
-                       "service_ms_mean": {k: round(float(np.mean(v)), 3) for k, v in kinds.items()}},
-        "speedup_vs_sequential": round(base_s / span, 2),
-        "saturated": {"latency_ms_p50": pct(lat_sat, 50), "latency_ms_p99": pct(lat_sat, 99),
-                      "p50_p99_by_kind": by_kind(lat_sat),
-                      "lane_requests": lanes_used, "lane_supersteps": info["lane_supersteps"],
-                      "rank_supersteps": info["rank_supersteps"]},
-        "open_loop": {"arrival_rate_per_s": round(rate, 2), "latency_ms_p50": pct(lat_open, 50),
-                      "latency_ms_p99": pct(lat_open, 99), "sequential_latency_ms_p50": pct(lat_base, 50),
-                      "sequential_latency_ms_p99": pct(lat_base, 99), "makespan_s": round(span_open, 3),
-                      "lane_requests": lanes_open, "lane_supersteps": info_open["lane_supersteps"],
-                      "rank_supersteps": info_open["rank_supersteps"],
-                      "p50_p99_by_kind": by_kind(lat_open), "sequential_p50_p99_by_kind": by_kind(lat_base)},
+        "plain": {"requests_per_s": round(capacity, 2), "by_kind": plain_by_kind},
+        "speedup_vs_plain_at_best_load": round(best["requests_per_s"] / capacity, 2),
+        "loads": points,
     }
 
 
@@ -462,8 +507,10 @@ def main():
     ap.add_argument("--workload", default="sssp-s26", choices=["sssp-s26", "cc-s22", "pr-s16", "batch", "multi", "serve", "combine"])
     ap.add_argument("--sources", type=int, default=256, help="multi workload: SSSP sources")
     ap.add_argument("--members", type=int, default=1024, help="batch workload: number of graphs")
-    ap.add_argument("--requests", type=int, default=600, help="serve workload: number of requests")
+    ap.add_argument("--requests", type=int, default=2000, help="serve workload: requests per offered load")
     ap.add_argument("--workers", type=int, default=4, help="serve workload: worker threads")
+    ap.add_argument("--loads", type=float, nargs="*", default=None,
+                    help="serve workload: offered loads (times the plain capacity); default 0.5 1 2 4")
     ap.add_argument("--hw-queues", type=int, default=None,
                     help="serve workload: hardware queues of the process (GPU_MAX_HW_QUEUES, at most 32); "
                          "lane tables, rank tables and workers each use their own stream")

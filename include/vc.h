@@ -81,9 +81,27 @@ typedef enum { VC_PAGERANK = 0, VC_CC_HASHMIN = 1, VC_SSSP = 2, VC_PPR = 3 } vc_
  *                    the transposed graph and combine in place (paper,
  *                    Section VI-C: single-broadcast); needs the transpose,
  *                    which the library builds on first use;
+ *   VC_SCHED_BLOCKED PageRank / PPR only, fixed-point sums: the pull
+ *                    combination by propagation blocking.  Edges are laid
+ *                    out once by (source tile of 2^14 vertices, destination
+ *                    bin of 2^12); each superstep stages a tile's messages
+ *                    in LDS and copies them into its edges' slots, then
+ *                    folds each bin's slots in LDS.  Both passes stream
+ *                    (4 bytes of indices and 16 of message slots per edge)
+ *                    instead of gathering one message per edge from HBM.
+ *                    The layout (12 bytes per edge plus 16 per bucket,
+ *                    buckets = tiles x bins) is built on first use; graphs
+ *                    beyond about 2^27 vertices are refused
+ *                    (VC_ERR_UNSUPPORTED);
  *   VC_SCHED_AUTO    per superstep: pull for dense frontiers, edge-centric
  *                    push otherwise (vertex push for tiny ones). */
-typedef enum { VC_SCHED_AUTO = 0, VC_SCHED_VERTEX = 1, VC_SCHED_EDGE = 2, VC_SCHED_PULL = 3 } vc_schedule;
+typedef enum {
+  VC_SCHED_AUTO = 0,
+  VC_SCHED_VERTEX = 1,
+  VC_SCHED_EDGE = 2,
+  VC_SCHED_PULL = 3,
+  VC_SCHED_BLOCKED = 4
+} vc_schedule;
 
 typedef enum { VC_IDX_I32 = 0, VC_IDX_I64 = 1 } vc_index_type;
 
@@ -330,11 +348,13 @@ vc_status vc_combine(vc_graph g, vc_combiner op, const uint64_t* msg, const uint
  * VC_OPT_F32_ACCUMULATE or T = 0 run on workers.
  *
  * Lanes pay off under load: a superstep costs about the same however many
- * lanes are busy.  With VC_ROUTE_AUTO a CC / SSSP request goes to the lane
- * table only while its expected completion there (running means of the
- * table's superstep time and supersteps per request) beats the worker path
- * (the backlog of queued and running worker jobs plus the mean worker time
- * of the program on that graph).
+ * lanes are busy.  With VC_ROUTE_AUTO a request joins its lane table's
+ * running generation when that is expected to finish sooner than the worker
+ * path (running means of the table's superstep time and supersteps per
+ * request against the worker backlog plus the program's mean worker time);
+ * otherwise it queues for a worker, and once the queued lane-eligible
+ * requests of one graph would together take longer alone than one lane
+ * generation, they move to the lane table as a batch.
  *
  * Every other request (PageRank, PPR, and min programs routed to workers)
  * runs on one of `workers` threads, each with its own stream and a

@@ -5,6 +5,7 @@
 // update, then (CC / SSSP) reads back the size of the next frontier to decide
 // termination and the work distribution of the next broadcast (Section V:
 // one thread per vertex, or edge-balanced merge-path tiles).
+#include <algorithm>
 #include <chrono>
 #include <cstdlib>
 #include <cstdio>
@@ -246,6 +247,125 @@ vc_status internal_id(vc_graph g, int64_t v, hipStream_t s, int64_t* out) {
 
 // ---------------------------------------------------------------- PageRank / PPR
 
+// Builds the propagation-blocking layout once per graph: bucket counts by
+// (source tile, destination bin), their exclusive scan (bucket starts), the
+// edge slots (source offset in the tile, destination offset in the bin) by
+// atomic cursors, then on the host the spread items (each tile's slot range
+// cut into pieces), the bin-major run tables and the fold items (each bin's
+// runs cut into pieces of about the same number of edges, so that a bin of
+// hubs spreads over many workgroups).
+vc_status ensure_pb(vc_graph g, hipStream_t s) {
+  if (g->pb_ready) return VC_OK;
+  const int64_t n = g->n, m = g->m;
+  const int shift = vc::pb_src_shift(g->max_lds);
+  if (shift == 0) return fail(VC_ERR_UNSUPPORTED, "the blocked schedule needs 8 KiB of LDS per workgroup");
+  const int64_t bins = vc::pb_bins(n), tiles = vc::pb_tiles(n, shift), nb = bins * tiles;
+  if (nb > vc::kPbMaxBuckets)
+    return fail(VC_ERR_UNSUPPORTED, "the blocked schedule supports graphs of up to about 2^27 vertices");
+  vc_params p;
+  vc_params_default(&p);
+  const int64_t tile = pick_tile(p, g);
+  vc_status st = dense_partition(g, tile, s);
+  if (st != VC_OK) return st;
+  DevBuf cnt, blocks, starts_d;
+  VC_TRY(cnt.ensure((size_t)(nb + 1) * 8));
+  VC_TRY(blocks.ensure((size_t)vc::scan_scratch_entries(nb) * 8));
+  VC_TRY(starts_d.ensure((size_t)(nb + 1) * 8));
+  VC_TRY(g->pb_srcl.ensure((size_t)m * 2 + 4));
+  VC_TRY(g->pb_dstl.ensure((size_t)m * 2 + 4));
+  VC_TRY(g->pb_vals.ensure((size_t)m * 8 + 8));
+  VC_TRY(vc::launch_fill_u32(cnt.as<uint32_t>(), 2 * (nb + 1), 0u, s));
+  VC_TRY(vc::launch_pb_count(g->off, g->off64, g->dst, n, m, g->dense_tiles_p, tile, g->dense_ntiles, shift,
+                             cnt.as<unsigned long long>(), s));
+  VC_TRY(vc::launch_exclusive_scan(cnt.as<int64_t>(), nb, blocks.as<int64_t>(), s));
+  VC_TRY(hipMemcpyAsync(starts_d.p, cnt.p, (size_t)(nb + 1) * 8, hipMemcpyDeviceToDevice, s));
+  VC_TRY(vc::launch_pb_fill(g->off, g->off64, g->dst, n, m, g->dense_tiles_p, tile, g->dense_ntiles, shift,
+                            cnt.as<unsigned long long>(), g->pb_srcl.as<uint16_t>(), g->pb_dstl.as<uint16_t>(), s));
+  std::vector<int64_t> starts((size_t)nb + 1);
+  VC_TRY(hipMemcpyAsync(starts.data(), starts_d.p, (size_t)(nb + 1) * 8, hipMemcpyDeviceToHost, s));
+  VC_TRY(hipStreamSynchronize(s));
+  cnt.release();
+  blocks.release();
+  starts_d.release();
+  // spread items: a tile's slots are contiguous; pieces of up to scap slots
+  // (the tile's messages are loaded once per piece)
+  const int64_t scap = std::min<int64_t>(1 << 18, std::max<int64_t>(1 << 14, m / 1024));
+  std::vector<vc::PbSpreadItem> sitems;
+  for (int64_t t = 0; t < tiles; ++t) {
+    const int64_t k0 = starts[(size_t)(t * bins)], k1 = starts[(size_t)((t + 1) * bins)];
+    for (int64_t k = k0; k < k1; k += scap) sitems.push_back(vc::PbSpreadItem{(int32_t)t, 0, k, std::min(k1, k + scap)});
+  }
+  // run tables, bin-major: pre[b][t] = edges of bin b in tiles < t,
+  // base[b][t] = slot of position pre[b][t] (run t's first slot) - pre[b][t]
+  // (a transpose of the tile-major starts, done 16 tiles at a time so that
+  // both sides are read and written a cache line at a time)
+  std::vector<int64_t> pre((size_t)(bins * (tiles + 1))), base((size_t)(bins * tiles)), acc((size_t)bins, 0);
+  for (int64_t t0 = 0; t0 < tiles; t0 += 16) {
+    const int64_t t1 = std::min(tiles, t0 + 16);
+    for (int64_t b = 0; b < bins; ++b) {
+      int64_t a = acc[(size_t)b];
+      int64_t* P = &pre[(size_t)(b * (tiles + 1))];
+      int64_t* B = &base[(size_t)(b * tiles)];
+      for (int64_t t = t0; t < t1; ++t) {
+        const size_t q = (size_t)(t * bins + b);
+        P[t] = a;
+        B[t] = starts[q] - a;
+        a += starts[q + 1] - starts[q];
+      }
+      acc[(size_t)b] = a;
+    }
+  }
+  for (int64_t b = 0; b < bins; ++b) pre[(size_t)(b * (tiles + 1) + tiles)] = acc[(size_t)b];
+  starts = std::vector<int64_t>();
+  // fold items: about 4096 in all, 4 Ki to 64 Ki edges each
+  const int64_t fcap = std::min<int64_t>(65536, std::max<int64_t>(4096, m / 4096));
+  std::vector<vc::PbFoldItem> fitems;
+  for (int64_t b = 0; b < bins; ++b) {
+    const int64_t* P = &pre[(size_t)(b * (tiles + 1))];
+    const int64_t total = P[tiles];
+    const size_t first = fitems.size();
+    int64_t r = 0;  // run holding position v: last r with P[r] <= v
+    for (int64_t v = 0; v < total; v += fcap) {
+      const int64_t v1 = std::min(total, v + fcap);
+      while (P[r + 1] <= v) ++r;
+      int64_t r1 = r;
+      while (P[r1 + 1] <= v1 - 1) ++r1;
+      fitems.push_back(vc::PbFoldItem{(int32_t)b, 0, r, r1 + 1, v, v1});
+    }
+    if (fitems.size() == first + 1) fitems.back().whole = 1;
+  }
+  VC_TRY(g->pb_pre.ensure(pre.size() * 8));
+  VC_TRY(g->pb_base.ensure(base.size() * 8 + 8));
+  VC_TRY(g->pb_spread.ensure((sitems.size() + 1) * sizeof(vc::PbSpreadItem)));
+  VC_TRY(g->pb_fold.ensure((fitems.size() + 1) * sizeof(vc::PbFoldItem)));
+  VC_TRY(hipMemcpyAsync(g->pb_pre.p, pre.data(), pre.size() * 8, hipMemcpyHostToDevice, s));
+  if (!base.empty()) VC_TRY(hipMemcpyAsync(g->pb_base.p, base.data(), base.size() * 8, hipMemcpyHostToDevice, s));
+  if (!sitems.empty())
+    VC_TRY(hipMemcpyAsync(g->pb_spread.p, sitems.data(), sitems.size() * sizeof(vc::PbSpreadItem),
+                          hipMemcpyHostToDevice, s));
+  if (!fitems.empty())
+    VC_TRY(hipMemcpyAsync(g->pb_fold.p, fitems.data(), fitems.size() * sizeof(vc::PbFoldItem), hipMemcpyHostToDevice,
+                          s));
+  VC_TRY(hipStreamSynchronize(s));
+  g->pb_shift = shift;
+  g->pb_tiles = tiles;
+  g->pb_nspread = (int64_t)sitems.size();
+  g->pb_nfold = (int64_t)fitems.size();
+  g->pb_ready = true;
+  return VC_OK;
+}
+
+// One broadcast + combine of the blocked schedule: spread, then fold.
+hipError_t pb_superstep(vc_graph g, const void* contrib, void* mb, hipStream_t s) {
+  hipError_t e = vc::launch_pb_spread(g->pb_spread.as<vc::PbSpreadItem>(), g->pb_nspread, g->n, g->pb_shift,
+                                      g->pb_srcl.as<uint16_t>(), static_cast<const unsigned long long*>(contrib),
+                                      g->pb_vals.as<unsigned long long>(), s);
+  if (e != hipSuccess) return e;
+  return vc::launch_pb_fold(g->pb_fold.as<vc::PbFoldItem>(), g->pb_nfold, g->pb_tiles, g->n,
+                            g->pb_pre.as<int64_t>(), g->pb_base.as<int64_t>(), g->pb_vals.as<unsigned long long>(),
+                            g->pb_dstl.as<uint16_t>(), static_cast<unsigned long long*>(mb), s);
+}
+
 vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hipStream_t s, Recorder& rec,
                    int32_t* supersteps) {
   const int64_t n = g->n, T = p.max_supersteps;
@@ -278,6 +398,8 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
   const double teleport = personal ? (1.0 - d) : (1.0 - d) / (double)n;
   const int64_t tile = pick_tile(p, g);
   const int sched = p.schedule == VC_SCHED_AUTO ? VC_SCHED_PULL : p.schedule;
+  if (sched == VC_SCHED_BLOCKED && !fx)
+    return fail(VC_ERR_UNSUPPORTED, "the blocked schedule sums in fixed point; drop VC_OPT_F32_ACCUMULATE");
   if (g->m > 0) {
     vc_status st = VC_OK;
     if (sched == VC_SCHED_PULL) {
@@ -285,6 +407,8 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
       if (st == VC_OK) st = csc_partition(g, vc::pull_tile(tile), s);
     } else if (sched == VC_SCHED_EDGE) {
       st = dense_partition(g, tile, s);
+    } else if (sched == VC_SCHED_BLOCKED) {
+      st = ensure_pb(g, s);
     }
     if (st != VC_OK) return st;
   }
@@ -306,10 +430,12 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
       hipError_t e = vc::launch_pr_init(fx, g->off, g->off64, n, r0, source, contrib, mb, nullptr, cs);
       for (int64_t step = 0; step < T && e == hipSuccess; ++step) {
         if (g->m > 0) {
-          if (sched == VC_SCHED_PULL)
+          if (sched == VC_SCHED_PULL) {
             e = vc::launch_pr_pull(fx, g->csc_off_p, g->in_src, n, g->m, g->csc_tiles_p,
                                    g->csc_tile, g->csc_ntiles, contrib, mb, cs);
-          else if (sched == VC_SCHED_EDGE)
+          } else if (sched == VC_SCHED_BLOCKED) {
+            e = pb_superstep(g, contrib, mb, cs);
+          } else if (sched == VC_SCHED_EDGE)
             e = vc::launch_pr_scatter_mp(fx, g->off, g->off64, g->dst, n, g->m, g->dense_tiles_p, tile,
                                          g->dense_ntiles, contrib, mb, cs);
           else
@@ -345,10 +471,12 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
     const bool timed = rec.want_time(step);
     if (timed) VC_TRY(hipEventRecord(g->events[3 * step], s));
     if (g->m > 0) {
-      if (sched == VC_SCHED_PULL)
+      if (sched == VC_SCHED_PULL) {
         VC_TRY(vc::launch_pr_pull(fx, g->csc_off_p, g->in_src, n, g->m, g->csc_tiles_p,
                                   g->csc_tile, g->csc_ntiles, contrib, mb, s));
-      else if (sched == VC_SCHED_EDGE)
+      } else if (sched == VC_SCHED_BLOCKED) {
+        VC_TRY(pb_superstep(g, contrib, mb, s));
+      } else if (sched == VC_SCHED_EDGE)
         VC_TRY(vc::launch_pr_scatter_mp(fx, g->off, g->off64, g->dst, n, g->m, g->dense_tiles_p, tile,
                                         g->dense_ntiles, contrib, mb, s));
       else
@@ -646,7 +774,9 @@ namespace vc {
 
 bool valid_params(const vc_params& p, vc_program prog, int64_t n, std::string* why) {
   if (p.struct_size != sizeof(vc_params)) return *why = "vc_params.struct_size mismatch", false;
-  if (p.schedule < VC_SCHED_AUTO || p.schedule > VC_SCHED_PULL) return *why = "bad schedule", false;
+  if (p.schedule < VC_SCHED_AUTO || p.schedule > VC_SCHED_BLOCKED) return *why = "bad schedule", false;
+  if (p.schedule == VC_SCHED_BLOCKED && prog != VC_PAGERANK && prog != VC_PPR)
+    return *why = "the blocked schedule is for PageRank / PPR", false;
   if (p.tile < 0) return *why = "negative tile", false;
   if (!(p.pull_fraction >= 0.0f)) return *why = "negative pull_fraction", false;
   if (prog == VC_PAGERANK || prog == VC_PPR) {
@@ -660,9 +790,8 @@ bool valid_params(const vc_params& p, vc_program prog, int64_t n, std::string* w
 }
 
 
-vc_status make_view(vc_graph base, hipStream_t s, vc_graph* out) {
-  if (!base || !out) return fail(VC_ERR_INVALID_ARG, "null graph or out");
-  if (base->is_view) return fail(VC_ERR_INVALID_ARG, "a view cannot serve as the base of another view");
+vc_status prepare_shared(vc_graph base, hipStream_t s) {
+  if (!base || base->is_view) return fail(VC_ERR_INVALID_ARG, "not a graph handle");
   vc_params p;
   vc_params_default(&p);
   const int64_t tile = pick_tile(p, base);
@@ -671,6 +800,14 @@ vc_status make_view(vc_graph base, hipStream_t s, vc_graph* out) {
   if (st == VC_OK) st = dense_partition(base, tile, s);
   if (st != VC_OK) return st;
   VC_TRY(hipStreamSynchronize(s));
+  return VC_OK;
+}
+
+vc_status make_view(vc_graph base, hipStream_t s, vc_graph* out) {
+  if (!base || !out) return fail(VC_ERR_INVALID_ARG, "null graph or out");
+  if (base->is_view) return fail(VC_ERR_INVALID_ARG, "a view cannot serve as the base of another view");
+  vc_status st = prepare_shared(base, s);
+  if (st != VC_OK) return st;
   vc_graph v = new (std::nothrow) vc_graph_s();
   if (!v) return fail(VC_ERR_OUT_OF_MEMORY, "host allocation failed");
   v->n = base->n;
@@ -827,7 +964,8 @@ vc_status vc_graph_destroy(vc_graph g) {
   for (DevBuf* b : {&g->own_off, &g->own_dst, &g->own_w, &g->perm, &g->inv, &g->rel_off, &g->rel_dst, &g->rel_w,
                     &g->contrib, &g->mb, &g->vm, &g->bitmap, &g->bitmap2,
                     &g->fq, &g->prefix, &g->scan_blocks, &g->list_tiles, &g->csc_off, &g->csc_src,
-                    &g->csc_w, &g->ms_src, &g->counters})
+                    &g->csc_w, &g->ms_src, &g->counters, &g->pb_srcl, &g->pb_dstl, &g->pb_vals,
+                    &g->pb_pre, &g->pb_base, &g->pb_spread, &g->pb_fold})
     b->release();
   g->ms.release();
   g->dense_parts.release();
@@ -854,7 +992,8 @@ vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held,
                 g->rel_off.bytes + g->rel_dst.bytes + g->rel_w.bytes;
   for (const DevBuf* b : {&g->contrib, &g->mb, &g->vm, &g->bitmap, &g->bitmap2, &g->fq, &g->prefix, &g->scan_blocks,
                           &g->list_tiles, &g->csc_off, &g->csc_src, &g->csc_w,
-                          &g->ms_src, &g->counters})
+                          &g->ms_src, &g->counters, &g->pb_srcl, &g->pb_dstl, &g->pb_vals, &g->pb_pre, &g->pb_base,
+                          &g->pb_spread, &g->pb_fold})
     held += b->bytes;
   held += g->ms.bytes();
   held += g->dense_parts.bytes() + g->csc_parts.bytes();

@@ -156,6 +156,13 @@ struct vc_graph_s {
   bool csc_ready = false;
   int64_t csc_tile = 0, csc_ntiles = 0;
   vc::MsState ms;                                 // many-source SSSP
+  // propagation-blocking layout (PageRank): per edge slot its source and
+  // destination offset in its bin, bucket starts, fold items, message slots
+  // propagation-blocking layout (PageRank / PPR, built on first use)
+  vc::DevBuf pb_srcl, pb_dstl, pb_vals, pb_pre, pb_base, pb_spread, pb_fold;
+  int64_t pb_nspread = 0, pb_nfold = 0, pb_tiles = 0;
+  int pb_shift = 0;
+  bool pb_ready = false;
   vc::DevBuf ms_src;
   // captured superstep loops (HIP graphs), replayed on the caller's stream
   hipStream_t cap_stream = nullptr;
@@ -184,6 +191,9 @@ vc_status csc_partition(vc_graph g, int64_t tile, hipStream_t s);
 int64_t pick_tile(const vc_params& p, vc_graph g);
 // Checks params for a run of prog on a graph of n vertices; *why on failure.
 bool valid_params(const vc_params& p, vc_program prog, int64_t n, std::string* why);
+// Builds base's transpose and default partitions (on s, synchronised), the
+// read-only arrays views share.
+vc_status prepare_shared(vc_graph base, hipStream_t s);
 // A graph object that shares every read-only array of `base` (structure,
 // relabelling, transpose, partitions) and owns only its own workspace,
 // events and streams.  The base must outlive the view.  The base's transpose

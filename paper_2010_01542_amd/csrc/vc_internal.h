@@ -200,6 +200,47 @@ hipError_t launch_combine(int op, const void* off, bool off64, const int32_t* ds
                           const unsigned long long* msg, const uint8_t* active, unsigned long long* mailbox,
                           uint32_t* flag, hipStream_t s);
 
+// ---------------------------------------------------------------- propagation blocking
+// PageRank by two streaming passes over edges laid out by bucket (source
+// tile of 2^shift vertices, destination bin of 2^kPbDstShift vertices),
+// buckets in tile-major order: bucket (t, b) = t * bins + b.
+constexpr int kPbDstShift = 12;
+constexpr int64_t kPbMaxBuckets = 1ll << 28;
+// Spread item: slots [k0, k1) of source tile t.
+struct PbSpreadItem {
+  int32_t t, pad;
+  int64_t k0, k1;
+};
+// Fold item: positions [v0, v1) of the concatenation of bin b's runs (run t
+// = bucket (t, b)), which lie in runs [r0, r1); whole marks the only item of
+// its bin.
+struct PbFoldItem {
+  int32_t b, whole;
+  int64_t r0, r1, v0, v1;
+};
+// Largest source tile whose messages fit the LDS limit (<= 2^14 vertices).
+int pb_src_shift(size_t max_lds);
+int64_t pb_bins(int64_t n);
+int64_t pb_tiles(int64_t n, int shift);
+// cnt: bins * tiles + 1 zeroed counters.
+hipError_t launch_pb_count(const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
+                           const int32_t* tile_v, int64_t tile, int64_t ntiles, int shift, unsigned long long* cnt,
+                           hipStream_t s);
+// cursor: bucket starts (consumed); writes each edge's source offset in its
+// tile and destination offset in its bin at the next slot of its bucket.
+hipError_t launch_pb_fill(const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
+                          const int32_t* tile_v, int64_t tile, int64_t ntiles, int shift, unsigned long long* cursor,
+                          uint16_t* srcl, uint16_t* dstl, hipStream_t s);
+// vals[k] = msg[tile's first vertex + srcl[k]] for every slot of every item.
+hipError_t launch_pb_spread(const PbSpreadItem* items, int64_t nitems, int64_t n, int shift, const uint16_t* srcl,
+                            const unsigned long long* msg, unsigned long long* vals, hipStream_t s);
+// pre: bins x (tiles + 1) run prefix sums, base: bins x tiles (slot of
+// position v in run t of bin b = base[b * tiles + t] + v).  Adds every
+// item's messages into mb (stores for whole bins); mb zero on entry.
+hipError_t launch_pb_fold(const PbFoldItem* items, int64_t nitems, int64_t tiles, int64_t n, const int64_t* pre,
+                          const int64_t* base, const unsigned long long* vals, const uint16_t* dstl,
+                          unsigned long long* mb, hipStream_t s);
+
 // In-place exclusive scan of P[0..count) with P[count] = total; `blocks`
 // is scratch of scan_scratch_entries(count) int64 values.
 int64_t scan_scratch_entries(int64_t count);

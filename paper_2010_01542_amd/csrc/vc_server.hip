@@ -42,7 +42,8 @@ struct Job {
   uint64_t ticket = 0;
   vc_request req{};
   Clock::time_point submitted, started;
-  double est_ms = 0;  // expected worker service time, counted in the worker backlog
+  double est_ms = 0;     // expected worker service time, counted in the worker backlog
+  bool movable = false;  // routed automatically: may move from the worker queue to a lane table
 };
 
 // Running estimate (exponentially weighted mean).
@@ -717,6 +718,63 @@ bool lane_is_faster(vc_server s, const GraphEntry& ge, const vc_request& r) {
   return kLaneMargin * rounds * steps * step < worker;
 }
 
+bool lane_eligible(const GraphEntry& ge, const vc_request& r, bool rank) {
+  if (rank)
+    return ge.ranks && (r.program == VC_PAGERANK || r.program == VC_PPR) && r.params.max_supersteps > 0 &&
+           !(r.params.options & VC_OPT_F32_ACCUMULATE);
+  return ge.lanes && (r.program == VC_CC_HASHMIN || r.program == VC_SSSP);
+}
+
+// Batching trigger.  A lane generation costs about the same GPU time however
+// many lanes are busy, so it pays once the requests it would serve would cost
+// more run alone: when the automatically routed, lane-eligible requests of
+// graph gid waiting in the worker queue add up (in expected worker time) to
+// one generation's time (supersteps per request times superstep time for
+// the lane chunks they fill; T updates for rank lanes), they move to the
+// lane table together.  Caller holds s->mu.
+void batch_from_queue(vc_server s, int32_t gid, bool rank) {
+  GraphEntry& ge = s->graphs[gid];
+  int64_t count = 0, max_t = 0;
+  double alone = 0;
+  for (const Job& j : s->queue)
+    if (j.movable && j.req.graph == gid && lane_eligible(ge, j.req, rank)) {
+      ++count;
+      alone += j.est_ms;
+      if (j.req.params.max_supersteps > max_t) max_t = j.req.params.max_supersteps;
+    }
+  if (count < 2) return;
+  double generation;
+  if (rank) {
+    const RankTable& t = *ge.ranks;
+    const int64_t want = count < t.K ? count : t.K;
+    const double c = (double)((want + 63) / 64);
+    const double step = t.step_ms.n ? t.step_ms.v
+                                    : ((double)t.g->m * 512.0 * c + (double)t.g->n * c * 64.0 * 24.0) / 3e9;
+    generation = (double)max_t * step * (double)((count + t.K - 1) / t.K);
+  } else {
+    const LaneTable& t = *ge.lanes;
+    const int64_t want = count < t.K ? count : t.K;
+    const double c = (double)((want + 63) / 64);
+    const double step = t.step_ms.n ? t.step_ms.v : ((double)t.g->m * 64.0 + (double)t.g->n * c * 1024.0) / 2e9;
+    const double steps = t.steps.n ? t.steps.v : 20.0;
+    generation = steps * step * (double)((count + t.K - 1) / t.K);
+  }
+  if (alone < generation) return;
+  std::deque<Job>& dest = rank ? ge.ranks->queue : ge.lanes->queue;
+  for (auto it = s->queue.begin(); it != s->queue.end();) {
+    if (it->movable && it->req.graph == gid && lane_eligible(ge, it->req, rank)) {
+      s->backlog_ms -= it->est_ms;
+      it->est_ms = 0;
+      dest.push_back(std::move(*it));
+      it = s->queue.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  ++s->epoch;
+  s->cv_work.notify_all();
+}
+
 }  // namespace
 
 extern "C" {
@@ -766,17 +824,16 @@ vc_status vc_server_add_graph(vc_server s, vc_graph g, int32_t lanes, int32_t ra
     return fail(VC_ERR_INVALID_ARG, "rank_lanes must be 0, 64, 128, 192 or 256");
   if (g->is_view) return fail(VC_ERR_INVALID_ARG, "not a graph handle");
   if (g->device != s->device) return fail(VC_ERR_INVALID_ARG, "graph lives on another device than the server");
-  std::lock_guard<std::mutex> lk(s->mu);
-  if (s->stopping) return fail(VC_ERR_INVALID_ARG, "server is shutting down");
+  // the shared read-only arrays (transpose, default partitions) are built
+  // before the graph is registered, outside the lock: nothing else uses it yet
   (void)hipSetDevice(s->device);
   hipStream_t st = nullptr;
   VC_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-  // builds the shared read-only arrays once (transpose, default partitions)
-  vc_graph probe = nullptr;
-  vc_status rc = vc::make_view(g, st, &probe);
+  vc_status rc = vc::prepare_shared(g, st);
   (void)hipStreamDestroy(st);
   if (rc != VC_OK) return rc;
-  vc_graph_destroy(probe);
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stopping) return fail(VC_ERR_INVALID_ARG, "server is shutting down");
   GraphEntry e;
   e.g = g;
   if (lanes > 0) {
@@ -837,21 +894,27 @@ vc_status vc_server_submit(vc_server s, const vc_request* req, uint64_t* ticket)
   j.req = *req;
   j.submitted = Clock::now();
   if (req->route < VC_ROUTE_AUTO || req->route > VC_ROUTE_WORKER) return fail(VC_ERR_INVALID_ARG, "bad route");
-  const bool min_prog = req->program == VC_CC_HASHMIN || req->program == VC_SSSP;
-  bool lane = ge.lanes && min_prog && req->route != VC_ROUTE_WORKER;
-  if (lane && req->route == VC_ROUTE_AUTO) lane = lane_is_faster(s, ge, *req);
-  // rank lanes sum in exact fixed point: binary32 requests and T = 0 stay on workers
-  bool rank = ge.ranks && !min_prog && req->route != VC_ROUTE_WORKER && req->params.max_supersteps > 0 &&
-              !(req->params.options & VC_OPT_F32_ACCUMULATE);
-  if (rank && req->route == VC_ROUTE_AUTO) rank = rank_lane_is_faster(s, ge, *req);
+  // Automatic routing: join a lane table's running generation when that
+  // finishes sooner than the worker path; otherwise queue for a worker,
+  // where the batching trigger may gather it into a new generation.  Rank
+  // lanes sum in exact fixed point: binary32 requests and T = 0 stay on
+  // workers.
+  bool lane = req->route != VC_ROUTE_WORKER && lane_eligible(ge, *req, false);
+  bool rank = req->route != VC_ROUTE_WORKER && lane_eligible(ge, *req, true);
+  if (req->route == VC_ROUTE_AUTO) {
+    lane = lane && ge.lanes->busy > 0 && lane_is_faster(s, ge, *req);
+    rank = rank && ge.ranks->busy > 0 && rank_lane_is_faster(s, ge, *req);
+  }
   if (lane) {
     ge.lanes->queue.push_back(j);
   } else if (rank) {
     ge.ranks->queue.push_back(j);
   } else {
     j.est_ms = worker_estimate(ge, *req);
+    j.movable = req->route == VC_ROUTE_AUTO && (lane_eligible(ge, *req, false) || lane_eligible(ge, *req, true));
     s->backlog_ms += j.est_ms;
     s->queue.push_back(j);
+    if (j.movable) batch_from_queue(s, req->graph, lane_eligible(ge, *req, true));
   }
   ++s->submitted;
   ++s->epoch;

@@ -19,8 +19,9 @@ LIB_PATH = os.path.join(_PKG, "libvc.so")
 PAGERANK, CC_HASHMIN, SSSP, PPR = 0, 1, 2, 3
 PROGRAMS = {"pagerank": PAGERANK, "pr": PAGERANK, "cc": CC_HASHMIN, "cc_hashmin": CC_HASHMIN, "sssp": SSSP,
             "ppr": PPR}
-SCHED_AUTO, SCHED_VERTEX, SCHED_EDGE, SCHED_PULL = 0, 1, 2, 3
-SCHEDULES = {"auto": SCHED_AUTO, "vertex": SCHED_VERTEX, "edge": SCHED_EDGE, "pull": SCHED_PULL}
+SCHED_AUTO, SCHED_VERTEX, SCHED_EDGE, SCHED_PULL, SCHED_BLOCKED = 0, 1, 2, 3, 4
+SCHEDULES = {"auto": SCHED_AUTO, "vertex": SCHED_VERTEX, "edge": SCHED_EDGE, "pull": SCHED_PULL,
+             "blocked": SCHED_BLOCKED}
 IDX_I32, IDX_I64 = 0, 1
 GRAPH_BORROW, GRAPH_VALIDATE, GRAPH_SYMMETRIC, GRAPH_NO_RELABEL = 1, 2, 4, 8
 OPT_NO_HUB_AGGREGATION, OPT_NO_TEST_BEFORE_ATOMIC, OPT_F32_ACCUMULATE, OPT_GRAPH_CAPTURE = 1, 2, 4, 8

@@ -6,7 +6,9 @@ Bars: bit-exact mailboxes and flags for the integer, maximum and
 inputs; for the binary64 sum, whose rounding depends on the order of
 additions, |device - oracle| <= 2 k eps sum|m| per receiver of k messages
 (the classical bound for two orders of the same sum), with exact flags.
-Contention: every leaf of a 20,000-leaf in-star sends to the centre.
+Contention: every leaf of a 20,000-leaf in-star sends to the centre.  Both
+forms run: pull when the senders' out-edges reach a tenth of the edges
+(receivers fold their in-edges), push for sparser sender sets.
 """
 import numpy as np
 import pytest
@@ -65,8 +67,9 @@ def test_combine_rmat(device, op, relabel):
     d = rmatgen.rmat(11, 10, seed=31)
     g = make(d, relabel=relabel)
     rng = np.random.default_rng(7)
-    check(d, g, op, rng)
-    check(d, g, op, rng, active=rng.random(d.n) < 0.3)
+    check(d, g, op, rng)                                  # pull form (every vertex sends)
+    check(d, g, op, rng, active=rng.random(d.n) < 0.3)    # pull form
+    check(d, g, op, rng, active=rng.random(d.n) < 0.01)   # push form: few senders
 
 
 @pytest.mark.parametrize("op", OPS)
@@ -78,6 +81,7 @@ def test_combine_contention_and_hand_graphs(device, op):
         g = make(c)
         check(c, g, op, rng)
         check(c, g, op, rng, active=rng.random(c.n) < 0.5)
+        check(c, g, op, rng, active=rng.random(c.n) < 0.03)  # push form, still contended at the star centre
 
 
 def test_combine_mid_size_exact(device):

@@ -174,7 +174,34 @@ def test_fixed_point_pagerank_is_order_independent(device):
     b = run_gpu(g, "pagerank", T=10, schedule="edge", tile=256)[0]
     c = run_gpu(g, "pagerank", T=10, schedule="edge", tile=4096)[0]
     d2 = run_gpu(g, "pagerank", T=10, schedule="pull", tile=512)[0]
-    assert np.array_equal(a, b) and np.array_equal(a, c) and np.array_equal(a, d2)
+    e = run_gpu(g, "pagerank", T=10, schedule="blocked")[0]
+    assert np.array_equal(a, b) and np.array_equal(a, c) and np.array_equal(a, d2) and np.array_equal(a, e)
+
+
+@pytest.mark.parametrize("relabel", [True, False])
+def test_blocked_pagerank_matches_oracle_and_pull(device, relabel):
+    """Propagation blocking: several source tiles (2^18 vertices each), bins
+    split over several fold items (hot destinations), vertices without
+    out-edges, PPR from a hub; ranks equal the pull form's bit for bit."""
+    print(f"case blocked pagerank s19 relabel={relabel}", flush=True)
+    d = rmatgen.rmat(19, 12, seed=8)
+    g = make(d, relabel=relabel)
+    check_rank(d, g, "pagerank", T=4, schedule="blocked")
+    check_rank(d, g, "ppr", T=5, source=0, schedule="blocked")
+    a = run_gpu(g, "pagerank", T=6, schedule="blocked")[0]
+    b = run_gpu(g, "pagerank", T=6, schedule="pull")[0]
+    assert np.array_equal(a, b)
+    for c in (rmatgen.in_star(40000), rmatgen.cycle(5), rmatgen.raw_csr(6, [0, 0, 1, 5, 5], [1, 1, 1, 0, 2])):
+        check_rank(c, make(c, relabel=relabel), "pagerank", T=3, schedule="blocked")
+
+
+def test_blocked_schedule_rejects_min_programs_and_f32(device):
+    from paper_2010_01542_amd import VcError, vc
+    g = make(rmatgen.path(8, directed=True))
+    with pytest.raises(VcError):
+        g.run("sssp", schedule="blocked")
+    with pytest.raises(VcError):
+        g.run("pagerank", schedule="blocked", options=vc.OPT_F32_ACCUMULATE)
 
 
 @pytest.mark.parametrize("program", ["pagerank", "ppr"])

@@ -76,6 +76,15 @@ def test_s26_pagerank_t3_against_oracle(s26):
     check_rank(csr, g, "pagerank", T=3)
 
 
+def test_s26_blocked_pagerank_equals_pull(s26):
+    csr, g = s26
+    print("case sssp-s26 pagerank T=3 blocked vs oracle, T=20 blocked vs pull", flush=True)
+    check_rank(csr, g, "pagerank", T=3, schedule="blocked")
+    a = run_gpu(g, "pagerank", T=20, schedule="blocked")[0]
+    b = run_gpu(g, "pagerank", T=20, schedule="pull")[0]
+    assert np.array_equal(a, b)
+
+
 def test_s26_pagerank_t20_last_update(s26):
     """r(20) = (1-d)/N + d * A^T D^-1 r(19), recomputed in binary64 from the
     device's own r(19), for every vertex; plus the dangling-mass invariant."""
