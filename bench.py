@@ -52,26 +52,30 @@ def host_info():
     return info
 
 
-def kernel_source_hash():
+KERNEL_SOURCES = {"pull": ("vc_pull.hip", "vc_device.h"), "blocked": ("vc_blocked.hip", "vc_device.h")}
+
+
+def kernel_source_hash(form):
     import hashlib
     h = hashlib.sha256()
-    for f in ("paper_2010_01542_amd/csrc/vc_pull.hip", "paper_2010_01542_amd/csrc/vc_device.h"):
-        with open(os.path.join(ROOT, f), "rb") as fh:
+    for f in KERNEL_SOURCES[form]:
+        with open(os.path.join(ROOT, "paper_2010_01542_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch of the PageRank pull kernel from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE runs, or None when the kernel source
-    changed since they were taken (or none exist for this workload)."""
-    path = os.path.join(ROOT, "profiles", "pr_pull_s26_traffic.json")
+def measured_traffic(workload, form):
+    """HBM bytes per PageRank broadcast+combine of the pull or blocked form
+    from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs, or None when
+    the kernel source changed since they were taken (or none exist for this
+    workload)."""
+    path = os.path.join(ROOT, "profiles", f"pr_{form}_s26_traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
     except OSError:
         return None
-    if rec.get("workload") != workload or rec.get("source_hash") != kernel_source_hash():
+    if rec.get("workload") != workload or rec.get("source_hash") != kernel_source_hash(form):
         return None
     return int(rec["traffic_bytes_per_launch"])
 
@@ -515,7 +519,7 @@ def main():
                     help="serve workload: hardware queues of the process (GPU_MAX_HW_QUEUES, at most 32); "
                          "lane tables, rank tables and workers each use their own stream")
     ap.add_argument("--scale", type=int, default=None, help="override the graph scale (same shape)")
-    ap.add_argument("--schedule", default="auto", choices=["auto", "vertex", "edge", "pull"])
+    ap.add_argument("--schedule", default="auto", choices=["auto", "vertex", "edge", "pull", "blocked"])
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--f32-accumulate", action="store_true", help="binary32 PageRank combiner (float atomics)")
@@ -591,7 +595,10 @@ def main():
         res = {}
         for prog, pk in jobs:
             out = out_f if prog in ("pagerank", "ppr") else out_u
-            _, st = g.run(prog, out, stats=True, timing=timing, **pk, **kw)
+            pkw = dict(kw)
+            if kw["schedule"] == "blocked" and prog not in ("pagerank", "ppr"):
+                pkw["schedule"] = "auto"  # the blocked form is PageRank's only
+            _, st = g.run(prog, out, stats=True, timing=timing, **pk, **pkw)
             res[prog] = st
         return res
 
@@ -634,8 +641,10 @@ def main():
         bytes_launch = pr_scatter_bytes(n, m, off_bytes)
         achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
         sched = records[0]["pagerank"].schedule[0]
-        kname = {1: "k_pr_scatter_vertex", 2: "k_pr_scatter_mp", 3: "k_pr_pull"}.get(int(sched), "?")
-        traffic = measured_traffic(csr.name) if (kname == "k_pr_pull" and not args.f32_accumulate) else None
+        kname = {1: "k_pr_scatter_vertex", 2: "k_pr_scatter_mp", 3: "k_pr_pull",
+                 4: "k_pb_spread + k_pb_fold"}.get(int(sched), "?")
+        form = {3: "pull", 4: "blocked"}.get(int(sched))
+        traffic = measured_traffic(csr.name, form) if (form and not args.f32_accumulate) else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": f"{kname} (PageRank broadcast+combine)", "launches": int(scat.size),

@@ -93,8 +93,12 @@ typedef enum { VC_PAGERANK = 0, VC_CC_HASHMIN = 1, VC_SSSP = 2, VC_PPR = 3 } vc_
  *                    buckets = tiles x bins) is built on first use; graphs
  *                    beyond about 2^27 vertices are refused
  *                    (VC_ERR_UNSUPPORTED);
- *   VC_SCHED_AUTO    per superstep: pull for dense frontiers, edge-centric
- *                    push otherwise (vertex push for tiny ones). */
+ *   VC_SCHED_AUTO    CC / SSSP, per superstep: pull for dense frontiers,
+ *                    edge-centric push otherwise (vertex push for tiny
+ *                    ones).  PageRank / PPR in fixed point: BLOCKED on graphs
+ *                    of 2^20 vertices and more (the first such run builds
+ *                    the layout), PULL below; with VC_OPT_F32_ACCUMULATE:
+ *                    PULL. */
 typedef enum {
   VC_SCHED_AUTO = 0,
   VC_SCHED_VERTEX = 1,

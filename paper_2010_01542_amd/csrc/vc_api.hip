@@ -247,13 +247,42 @@ vc_status internal_id(vc_graph g, int64_t v, hipStream_t s, int64_t* out) {
 
 // ---------------------------------------------------------------- PageRank / PPR
 
-// Builds the propagation-blocking layout once per graph: bucket counts by
-// (source tile, destination bin), their exclusive scan (bucket starts), the
-// edge slots (source offset in the tile, destination offset in the bin) by
-// atomic cursors, then on the host the spread items (each tile's slot range
-// cut into pieces), the bin-major run tables and the fold items (each bin's
-// runs cut into pieces of about the same number of edges, so that a bin of
-// hubs spreads over many workgroups).
+// Whether the blocked layout of g is within the library's limits, and its
+// size in bytes (slots, run tables, items).
+bool pb_supported(vc_graph g) {
+  const int shift = vc::pb_src_shift(g->max_lds);
+  return shift != 0 && vc::pb_bins(g->n) * vc::pb_tiles(g->n, shift) <= vc::kPbMaxBuckets;
+}
+
+size_t pb_layout_bytes(vc_graph g) {
+  const int shift = vc::pb_src_shift(g->max_lds);
+  if (shift == 0) return 0;
+  const size_t bins = (size_t)vc::pb_bins(g->n), tiles = (size_t)vc::pb_tiles(g->n, shift), m = (size_t)g->m;
+  return m * 12 + bins * (2 * tiles + 1) * 8 + (m / 4096 + bins + 2) * sizeof(vc::PbFoldItem) +
+         (m / 16384 + tiles + 2) * sizeof(vc::PbSpreadItem);
+}
+
+// The schedule of a PageRank / PPR run.  AUTO takes the blocked schedule for
+// fixed-point runs on graphs of 2^20 vertices and more, where the message
+// array no longer stays in the caches and the pull form's gathers go to
+// HBM (on R-MAT graphs the two forms meet near 2^20 vertices, and the
+// blocked layout builds faster than the transpose), and the pull form
+// otherwise.  Views keep the pull form: they would each build a layout of
+// their own.
+int rank_schedule(vc_graph g, const vc_params& p, bool fx) {
+  if (p.schedule != VC_SCHED_AUTO) return p.schedule;
+  if (fx && !g->is_view && g->n >= (1 << 20) && g->m > 0 && pb_supported(g)) return VC_SCHED_BLOCKED;
+  return VC_SCHED_PULL;
+}
+
+// Builds the propagation-blocking layout once per graph, on the device:
+// first edge of every source tile, every edge's source offset in its tile,
+// bucket counts (LDS histograms per chunk of edges), their exclusive scan
+// (bucket starts), the slots (each chunk reserves its share of a bucket with
+// one atomic), the bin-major run tables and the fold items (each bin's runs
+// cut into pieces of about the same number of edges, so that a bin of hubs
+// spreads over many workgroups).  The spread items (each tile's slot range
+// cut into pieces) are made on the host from the tile starts.
 vc_status ensure_pb(vc_graph g, hipStream_t s) {
   if (g->pb_ready) return VC_OK;
   const int64_t n = g->n, m = g->m;
@@ -267,90 +296,64 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
   const int64_t tile = pick_tile(p, g);
   vc_status st = dense_partition(g, tile, s);
   if (st != VC_OK) return st;
-  DevBuf cnt, blocks, starts_d;
-  VC_TRY(cnt.ensure((size_t)(nb + 1) * 8));
-  VC_TRY(blocks.ensure((size_t)vc::scan_scratch_entries(nb) * 8));
-  VC_TRY(starts_d.ensure((size_t)(nb + 1) * 8));
+  DevBuf te_d, cnt, blocks, starts_d, nitems;
+  VC_TRY(te_d.ensure((size_t)(tiles + 1) * 8));
+  VC_TRY(vc::launch_pb_tile_edges(g->off, g->off64, n, shift, tiles, te_d.as<int64_t>(), s));
+  std::vector<int64_t> te((size_t)tiles + 1);
+  VC_TRY(hipMemcpyAsync(te.data(), te_d.p, te.size() * 8, hipMemcpyDeviceToHost, s));
+  VC_TRY(hipStreamSynchronize(s));
+  for (int64_t t = 0; t < tiles; ++t)
+    if (te[(size_t)t + 1] - te[(size_t)t] >= (1ll << 32))
+      return fail(VC_ERR_UNSUPPORTED, "the blocked schedule needs fewer than 2^32 out-edges per source tile");
   VC_TRY(g->pb_srcl.ensure((size_t)m * 2 + 4));
   VC_TRY(g->pb_dstl.ensure((size_t)m * 2 + 4));
   VC_TRY(g->pb_vals.ensure((size_t)m * 8 + 8));
+  uint16_t* srcl_csr = g->pb_vals.as<uint16_t>();  // the message slots are free until the first superstep
+  VC_TRY(vc::launch_pb_expand(g->off, g->off64, n, m, g->dense_tiles_p, tile, g->dense_ntiles, shift, srcl_csr, s));
+  VC_TRY(cnt.ensure((size_t)(nb + 1) * 8));
+  VC_TRY(blocks.ensure((size_t)vc::scan_scratch_entries(std::max(nb, bins)) * 8));
+  VC_TRY(starts_d.ensure((size_t)(nb + 1) * 8));
   VC_TRY(vc::launch_fill_u32(cnt.as<uint32_t>(), 2 * (nb + 1), 0u, s));
-  VC_TRY(vc::launch_pb_count(g->off, g->off64, g->dst, n, m, g->dense_tiles_p, tile, g->dense_ntiles, shift,
-                             cnt.as<unsigned long long>(), s));
+  const int pass_bins = (int)std::min<int64_t>(bins, std::max<int64_t>(64, (int64_t)(g->max_lds / 8) & ~63ll));
+  const int64_t chunk = std::min<int64_t>(1 << 18, std::max<int64_t>(1 << 14, m / 2048));
+  VC_TRY(vc::launch_pb_build(false, te_d.as<int64_t>(), tiles, g->dst, m, chunk, bins, pass_bins,
+                             cnt.as<unsigned long long>(), nullptr, nullptr, nullptr, s));
   VC_TRY(vc::launch_exclusive_scan(cnt.as<int64_t>(), nb, blocks.as<int64_t>(), s));
   VC_TRY(hipMemcpyAsync(starts_d.p, cnt.p, (size_t)(nb + 1) * 8, hipMemcpyDeviceToDevice, s));
-  VC_TRY(vc::launch_pb_fill(g->off, g->off64, g->dst, n, m, g->dense_tiles_p, tile, g->dense_ntiles, shift,
-                            cnt.as<unsigned long long>(), g->pb_srcl.as<uint16_t>(), g->pb_dstl.as<uint16_t>(), s));
-  std::vector<int64_t> starts((size_t)nb + 1);
-  VC_TRY(hipMemcpyAsync(starts.data(), starts_d.p, (size_t)(nb + 1) * 8, hipMemcpyDeviceToHost, s));
+  VC_TRY(vc::launch_pb_build(true, te_d.as<int64_t>(), tiles, g->dst, m, chunk, bins, pass_bins,
+                             cnt.as<unsigned long long>(), srcl_csr, g->pb_srcl.as<uint16_t>(),
+                             g->pb_dstl.as<uint16_t>(), s));
+  // run tables and fold items: about 4096 items in all, 4 Ki to 64 Ki edges each
+  const int64_t fcap = std::min<int64_t>(65536, std::max<int64_t>(4096, m / 4096));
+  VC_TRY(g->pb_pre.ensure((size_t)(bins * (tiles + 1)) * 8));
+  VC_TRY(g->pb_base.ensure((size_t)(bins * tiles) * 8));
+  VC_TRY(nitems.ensure((size_t)(bins + 1) * 8));
+  VC_TRY(vc::launch_pb_tables(starts_d.as<int64_t>(), bins, tiles, fcap, g->pb_pre.as<int64_t>(),
+                              g->pb_base.as<int64_t>(), nitems.as<int64_t>(), s));
+  VC_TRY(vc::launch_exclusive_scan(nitems.as<int64_t>(), bins, blocks.as<int64_t>(), s));
+  int64_t nfold = 0;
+  VC_TRY(hipMemcpyAsync(&nfold, nitems.as<int64_t>() + bins, 8, hipMemcpyDeviceToHost, s));
   VC_TRY(hipStreamSynchronize(s));
-  cnt.release();
-  blocks.release();
-  starts_d.release();
+  VC_TRY(g->pb_fold.ensure((size_t)(nfold + 1) * sizeof(vc::PbFoldItem)));
+  VC_TRY(vc::launch_pb_fold_items(g->pb_pre.as<int64_t>(), bins, tiles, fcap, nitems.as<int64_t>(),
+                                  g->pb_fold.as<vc::PbFoldItem>(), s));
   // spread items: a tile's slots are contiguous; pieces of up to scap slots
   // (the tile's messages are loaded once per piece)
   const int64_t scap = std::min<int64_t>(1 << 18, std::max<int64_t>(1 << 14, m / 1024));
   std::vector<vc::PbSpreadItem> sitems;
   for (int64_t t = 0; t < tiles; ++t) {
-    const int64_t k0 = starts[(size_t)(t * bins)], k1 = starts[(size_t)((t + 1) * bins)];
+    const int64_t k0 = te[(size_t)t], k1 = te[(size_t)t + 1];
     for (int64_t k = k0; k < k1; k += scap) sitems.push_back(vc::PbSpreadItem{(int32_t)t, 0, k, std::min(k1, k + scap)});
   }
-  // run tables, bin-major: pre[b][t] = edges of bin b in tiles < t,
-  // base[b][t] = slot of position pre[b][t] (run t's first slot) - pre[b][t]
-  // (a transpose of the tile-major starts, done 16 tiles at a time so that
-  // both sides are read and written a cache line at a time)
-  std::vector<int64_t> pre((size_t)(bins * (tiles + 1))), base((size_t)(bins * tiles)), acc((size_t)bins, 0);
-  for (int64_t t0 = 0; t0 < tiles; t0 += 16) {
-    const int64_t t1 = std::min(tiles, t0 + 16);
-    for (int64_t b = 0; b < bins; ++b) {
-      int64_t a = acc[(size_t)b];
-      int64_t* P = &pre[(size_t)(b * (tiles + 1))];
-      int64_t* B = &base[(size_t)(b * tiles)];
-      for (int64_t t = t0; t < t1; ++t) {
-        const size_t q = (size_t)(t * bins + b);
-        P[t] = a;
-        B[t] = starts[q] - a;
-        a += starts[q + 1] - starts[q];
-      }
-      acc[(size_t)b] = a;
-    }
-  }
-  for (int64_t b = 0; b < bins; ++b) pre[(size_t)(b * (tiles + 1) + tiles)] = acc[(size_t)b];
-  starts = std::vector<int64_t>();
-  // fold items: about 4096 in all, 4 Ki to 64 Ki edges each
-  const int64_t fcap = std::min<int64_t>(65536, std::max<int64_t>(4096, m / 4096));
-  std::vector<vc::PbFoldItem> fitems;
-  for (int64_t b = 0; b < bins; ++b) {
-    const int64_t* P = &pre[(size_t)(b * (tiles + 1))];
-    const int64_t total = P[tiles];
-    const size_t first = fitems.size();
-    int64_t r = 0;  // run holding position v: last r with P[r] <= v
-    for (int64_t v = 0; v < total; v += fcap) {
-      const int64_t v1 = std::min(total, v + fcap);
-      while (P[r + 1] <= v) ++r;
-      int64_t r1 = r;
-      while (P[r1 + 1] <= v1 - 1) ++r1;
-      fitems.push_back(vc::PbFoldItem{(int32_t)b, 0, r, r1 + 1, v, v1});
-    }
-    if (fitems.size() == first + 1) fitems.back().whole = 1;
-  }
-  VC_TRY(g->pb_pre.ensure(pre.size() * 8));
-  VC_TRY(g->pb_base.ensure(base.size() * 8 + 8));
   VC_TRY(g->pb_spread.ensure((sitems.size() + 1) * sizeof(vc::PbSpreadItem)));
-  VC_TRY(g->pb_fold.ensure((fitems.size() + 1) * sizeof(vc::PbFoldItem)));
-  VC_TRY(hipMemcpyAsync(g->pb_pre.p, pre.data(), pre.size() * 8, hipMemcpyHostToDevice, s));
-  if (!base.empty()) VC_TRY(hipMemcpyAsync(g->pb_base.p, base.data(), base.size() * 8, hipMemcpyHostToDevice, s));
   if (!sitems.empty())
     VC_TRY(hipMemcpyAsync(g->pb_spread.p, sitems.data(), sitems.size() * sizeof(vc::PbSpreadItem),
                           hipMemcpyHostToDevice, s));
-  if (!fitems.empty())
-    VC_TRY(hipMemcpyAsync(g->pb_fold.p, fitems.data(), fitems.size() * sizeof(vc::PbFoldItem), hipMemcpyHostToDevice,
-                          s));
   VC_TRY(hipStreamSynchronize(s));
   g->pb_shift = shift;
   g->pb_tiles = tiles;
   g->pb_nspread = (int64_t)sitems.size();
-  g->pb_nfold = (int64_t)fitems.size();
+  g->pb_nfold = nfold;
   g->pb_ready = true;
   return VC_OK;
 }
@@ -397,7 +400,7 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
   const double d = p.damping;
   const double teleport = personal ? (1.0 - d) : (1.0 - d) / (double)n;
   const int64_t tile = pick_tile(p, g);
-  const int sched = p.schedule == VC_SCHED_AUTO ? VC_SCHED_PULL : p.schedule;
+  const int sched = rank_schedule(g, p, fx);
   if (sched == VC_SCHED_BLOCKED && !fx)
     return fail(VC_ERR_UNSUPPORTED, "the blocked schedule sums in fixed point; drop VC_OPT_F32_ACCUMULATE");
   if (g->m > 0) {
@@ -999,7 +1002,8 @@ vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held,
   held += g->dense_parts.bytes() + g->csc_parts.bytes();
   if (bytes_held) *bytes_held = held;
   if (bytes_run) {
-    // workspace of the program plus the transpose the pull form reads
+    // workspace of the program plus the transpose the pull form reads (or,
+    // for PageRank / PPR on large graphs, the blocked layout)
     const size_t want = workspace_bytes(g->n, g->m, program, vc::kDefaultTile);
     size_t have = 0;
     if (program == VC_PAGERANK || program == VC_PPR)
@@ -1010,8 +1014,17 @@ vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held,
     const size_t csc_want = (size_t)(g->n + 1) * 8 + (size_t)((g->n + g->m) / vc::kDefaultTile + 2) * 4 +
                             ((g->flags & VC_GRAPH_SYMMETRIC) ? 0 : (size_t)g->m * (g->w ? 8 : 4));
     const size_t csc_have = g->csc_off.bytes + g->csc_src.bytes + g->csc_w.bytes + g->csc_parts.bytes();
-    const size_t csc_need = g->csc_ready ? 0 : (csc_want > csc_have ? csc_want - csc_have : 0);
-    *bytes_run = (want > have ? want - have : 0) + csc_need;
+    size_t csc_need = g->csc_ready ? 0 : (csc_want > csc_have ? csc_want - csc_have : 0);
+    size_t pb_need = 0;
+    if (program == VC_PAGERANK || program == VC_PPR) {
+      vc_params dp;
+      vc_params_default(&dp);
+      if (rank_schedule(g, dp, true) == VC_SCHED_BLOCKED) {
+        csc_need = 0;  // the blocked schedule reads its own layout, not the transpose
+        pb_need = g->pb_ready ? 0 : pb_layout_bytes(g);
+      }
+    }
+    *bytes_run = (want > have ? want - have : 0) + csc_need + pb_need;
   }
   return VC_OK;
 }

@@ -26,11 +26,28 @@ using namespace dev;
 
 constexpr int kMaxSrcShift = 14;
 
-// Merge-path walk over the CSR: calls f(u, v) for every edge of tile t.
-template <class OffT, class F>
-__device__ __forceinline__ void for_tile_edges(const OffT* __restrict__ off, const int32_t* __restrict__ dst, int64_t n,
-                                               int64_t m, const int32_t* __restrict__ tile_v, int64_t tile,
-                                               int64_t* s_off, F f) {
+// ---------------------------------------------------------------- layout build
+// Source tile t holds vertices [t << shift, (t + 1) << shift); its out-edges
+// are the CSR edges [te[t], te[t + 1]) with te[t] = off[t << shift], and in
+// tile-major order its slots are that same range.  The build counts each
+// bucket with per-workgroup LDS histograms, reserves a sub-range of each
+// bucket per workgroup with one global atomic, and places the edges.
+
+template <class OffT>
+__global__ __launch_bounds__(kWG) void k_pb_tile_edges(const OffT* __restrict__ off, int64_t n, int shift,
+                                                       int64_t tiles, int64_t* __restrict__ te) {
+  const int64_t t = gid();
+  if (t > tiles) return;
+  const int64_t v = (t << shift) < n ? (t << shift) : n;
+  te[t] = (int64_t)off[v];
+}
+
+// srcl_csr[e] = offset of edge e's source in its tile, by a merge-path walk.
+template <class OffT>
+__global__ __launch_bounds__(kWG) void k_pb_expand(const OffT* __restrict__ off, int64_t n, int64_t m,
+                                                   const int32_t* __restrict__ tile_v, int64_t tile, int shift,
+                                                   uint16_t* __restrict__ srcl_csr) {
+  extern __shared__ __align__(16) int64_t s_off[];
   const int64_t t = blockIdx.x;
   const int64_t k0 = t * tile;
   const int64_t k1 = (k0 + tile < n + m) ? k0 + tile : n + m;
@@ -41,6 +58,7 @@ __device__ __forceinline__ void for_tile_edges(const OffT* __restrict__ off, con
   const int cnt = (int)(ilast - i0 + 1);
   for (int x = threadIdx.x; x <= cnt; x += kWG) s_off[x] = (int64_t)off[i0 + x];
   __syncthreads();
+  const int64_t mask = (1ll << shift) - 1;
   for (int64_t e = j0 + threadIdx.x; e < j1; e += kWG) {
     int lo = 0, hi = cnt - 1;
     while (lo < hi) {
@@ -50,33 +68,120 @@ __device__ __forceinline__ void for_tile_edges(const OffT* __restrict__ off, con
       else
         hi = mid - 1;
     }
-    f(i0 + lo, (int64_t)dst[e]);
+    srcl_csr[e] = (uint16_t)((i0 + lo) & mask);
   }
 }
 
-template <class OffT>
-__global__ __launch_bounds__(kWG) void k_pb_count(const OffT* __restrict__ off, const int32_t* __restrict__ dst,
-                                                  int64_t n, int64_t m, const int32_t* __restrict__ tile_v,
-                                                  int64_t tile, int shift, int64_t bins,
-                                                  unsigned long long* __restrict__ cnt) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  for_tile_edges(off, dst, n, m, tile_v, tile, reinterpret_cast<int64_t*>(smem), [&](int64_t u, int64_t v) {
-    atomicAdd(&cnt[(u >> shift) * bins + (v >> kPbDstShift)], 1ull);
-  });
+constexpr int kBuildWG = 1024;
+
+// Tile of edge c0: last t with te[t] <= c0 (te[0] = 0 <= c0 < m = te[tiles]).
+__device__ __forceinline__ int64_t tile_of(const int64_t* __restrict__ te, int64_t tiles, int64_t c0) {
+  int64_t lo = 0, hi = tiles - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (te[mid] <= c0)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
 }
 
-template <class OffT>
-__global__ __launch_bounds__(kWG) void k_pb_fill(const OffT* __restrict__ off, const int32_t* __restrict__ dst,
-                                                 int64_t n, int64_t m, const int32_t* __restrict__ tile_v,
-                                                 int64_t tile, int shift, int64_t bins,
-                                                 unsigned long long* __restrict__ cursor, uint16_t* __restrict__ srcl,
-                                                 uint16_t* __restrict__ dstl) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  for_tile_edges(off, dst, n, m, tile_v, tile, reinterpret_cast<int64_t*>(smem), [&](int64_t u, int64_t v) {
-    const unsigned long long k = atomicAdd(&cursor[(u >> shift) * bins + (v >> kPbDstShift)], 1ull);
-    srcl[k] = (uint16_t)(u & ((1 << shift) - 1));
-    dstl[k] = (uint16_t)(v & ((1 << kPbDstShift) - 1));
-  });
+// Per workgroup: edges [c0, c1) of the CSR, split by source tile; per tile
+// and per range of pass_bins bins, an LDS histogram of destination bins.
+// PLACE = false adds the histogram into cnt (bucket counts); PLACE = true
+// reserves each bucket's share at cursor and writes the slots.
+template <bool PLACE>
+__global__ __launch_bounds__(kBuildWG) void k_pb_build(const int64_t* __restrict__ te, int64_t tiles,
+                                                       const int32_t* __restrict__ dst, int64_t m, int64_t chunk,
+                                                       int64_t bins, int pass_bins,
+                                                       unsigned long long* __restrict__ cnt,
+                                                       const uint16_t* __restrict__ srcl_csr,
+                                                       uint16_t* __restrict__ srcl, uint16_t* __restrict__ dstl) {
+  extern __shared__ __align__(16) uint32_t hist[];  // pass_bins counters, then (PLACE) pass_bins offsets
+  uint32_t* rel = hist + pass_bins;
+  const int64_t c0 = (int64_t)blockIdx.x * chunk;
+  const int64_t c1 = (c0 + chunk < m) ? c0 + chunk : m;
+  for (int64_t t = tile_of(te, tiles, c0); t < tiles && te[t] < c1; ++t) {
+    const int64_t e0 = te[t] > c0 ? te[t] : c0;
+    const int64_t e1 = te[t + 1] < c1 ? te[t + 1] : c1;
+    if (e0 >= e1) continue;
+    for (int64_t b_lo = 0; b_lo < bins; b_lo += pass_bins) {
+      const int nb = (int)((bins - b_lo < pass_bins) ? bins - b_lo : pass_bins);
+      for (int i = threadIdx.x; i < nb; i += kBuildWG) hist[i] = 0u;
+      __syncthreads();
+      for (int64_t e = e0 + threadIdx.x; e < e1; e += kBuildWG) {
+        const int64_t b = (int64_t)(dst[e] >> kPbDstShift) - b_lo;
+        if (b >= 0 && b < nb) atomicAdd(&hist[b], 1u);
+      }
+      __syncthreads();
+      unsigned long long* C = cnt + t * bins + b_lo;
+      for (int i = threadIdx.x; i < nb; i += kBuildWG) {
+        const uint32_t h = hist[i];
+        if (!PLACE) {
+          if (h) atomicAdd(&C[i], (unsigned long long)h);
+        } else {
+          rel[i] = h ? (uint32_t)(atomicAdd(&C[i], (unsigned long long)h) - (unsigned long long)te[t]) : 0u;
+          hist[i] = 0u;
+        }
+      }
+      __syncthreads();
+      if (PLACE) {
+        // every slot reserved here lies in the tile's range [te[t], te[t + 1])
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kBuildWG) {
+          const int32_t v = dst[e];
+          const int64_t b = (int64_t)(v >> kPbDstShift) - b_lo;
+          if (b >= 0 && b < nb) {
+            const int64_t k = te[t] + (int64_t)rel[b] + (int64_t)atomicAdd(&hist[b], 1u);
+            srcl[k] = srcl_csr[e];
+            dstl[k] = (uint16_t)(v & ((1 << kPbDstShift) - 1));
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+// Per bin b (one thread): run prefix sums pre[b][t], slot bases base[b][t]
+// and the number of fold items of the bin.
+__global__ __launch_bounds__(kWG) void k_pb_tables(const int64_t* __restrict__ starts, int64_t bins, int64_t tiles,
+                                                   int64_t fcap, int64_t* __restrict__ pre,
+                                                   int64_t* __restrict__ base, int64_t* __restrict__ nitems) {
+  const int64_t b = gid();
+  if (b >= bins) return;
+  int64_t* P = pre + b * (tiles + 1);
+  int64_t* B = base + b * tiles;
+  int64_t acc = 0;
+  for (int64_t t = 0; t < tiles; ++t) {
+    const int64_t q = t * bins + b;
+    const int64_t s0 = starts[q], s1 = starts[q + 1];
+    P[t] = acc;
+    B[t] = s0 - acc;
+    acc += s1 - s0;
+  }
+  P[tiles] = acc;
+  nitems[b] = (acc + fcap - 1) / fcap;
+}
+
+// Per bin b (one thread): its fold items, positions [i fcap, (i+1) fcap).
+__global__ __launch_bounds__(kWG) void k_pb_fold_items(const int64_t* __restrict__ pre, int64_t bins, int64_t tiles,
+                                                       int64_t fcap, const int64_t* __restrict__ item_off,
+                                                       PbFoldItem* __restrict__ items) {
+  const int64_t b = gid();
+  if (b >= bins) return;
+  const int64_t* P = pre + b * (tiles + 1);
+  const int64_t total = P[tiles];
+  const int64_t first = item_off[b], count = item_off[b + 1] - item_off[b];
+  int64_t r = 0;  // run holding position v: last r with P[r] <= v (v < total = P[tiles])
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t v0 = i * fcap;
+    const int64_t v1 = (v0 + fcap < total) ? v0 + fcap : total;
+    while (P[r + 1] <= v0) ++r;
+    int64_t r1 = r;
+    while (P[r1 + 1] <= v1 - 1) ++r1;
+    items[first + i] = PbFoldItem{(int32_t)b, count == 1 ? 1 : 0, r, r1 + 1, v0, v1};
+  }
 }
 
 // Pass 1: one workgroup per spread item; the tile's messages in LDS.
@@ -203,33 +308,55 @@ int pb_src_shift(size_t max_lds) {
 int64_t pb_bins(int64_t n) { return (n + (1 << kPbDstShift) - 1) >> kPbDstShift; }
 int64_t pb_tiles(int64_t n, int shift) { return (n + (1ll << shift) - 1) >> shift; }
 
-hipError_t launch_pb_count(const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
-                           const int32_t* tile_v, int64_t tile, int64_t ntiles, int shift, unsigned long long* cnt,
-                           hipStream_t s) {
-  if (ntiles <= 0 || m <= 0) return hipSuccess;
-  const size_t lds = (size_t)(tile + 2) * 8;
-  const int64_t bins = pb_bins(n);
+hipError_t launch_pb_tile_edges(const void* off, bool off64, int64_t n, int shift, int64_t tiles, int64_t* te,
+                                hipStream_t s) {
   if (off64)
-    hipLaunchKernelGGL(k_pb_count<int64_t>, dim3((unsigned)ntiles), dim3(kWG), lds, s, (const int64_t*)off, dst, n, m,
-                       tile_v, tile, shift, bins, cnt);
+    hipLaunchKernelGGL(k_pb_tile_edges<int64_t>, dim3(grid_for(tiles + 1)), dim3(kWG), 0, s, (const int64_t*)off, n,
+                       shift, tiles, te);
   else
-    hipLaunchKernelGGL(k_pb_count<int32_t>, dim3((unsigned)ntiles), dim3(kWG), lds, s, (const int32_t*)off, dst, n, m,
-                       tile_v, tile, shift, bins, cnt);
+    hipLaunchKernelGGL(k_pb_tile_edges<int32_t>, dim3(grid_for(tiles + 1)), dim3(kWG), 0, s, (const int32_t*)off, n,
+                       shift, tiles, te);
   return hipGetLastError();
 }
 
-hipError_t launch_pb_fill(const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
-                          const int32_t* tile_v, int64_t tile, int64_t ntiles, int shift, unsigned long long* cursor,
-                          uint16_t* srcl, uint16_t* dstl, hipStream_t s) {
+hipError_t launch_pb_expand(const void* off, bool off64, int64_t n, int64_t m, const int32_t* tile_v, int64_t tile,
+                            int64_t ntiles, int shift, uint16_t* srcl_csr, hipStream_t s) {
   if (ntiles <= 0 || m <= 0) return hipSuccess;
   const size_t lds = (size_t)(tile + 2) * 8;
-  const int64_t bins = pb_bins(n);
   if (off64)
-    hipLaunchKernelGGL(k_pb_fill<int64_t>, dim3((unsigned)ntiles), dim3(kWG), lds, s, (const int64_t*)off, dst, n, m,
-                       tile_v, tile, shift, bins, cursor, srcl, dstl);
+    hipLaunchKernelGGL(k_pb_expand<int64_t>, dim3((unsigned)ntiles), dim3(kWG), lds, s, (const int64_t*)off, n, m,
+                       tile_v, tile, shift, srcl_csr);
   else
-    hipLaunchKernelGGL(k_pb_fill<int32_t>, dim3((unsigned)ntiles), dim3(kWG), lds, s, (const int32_t*)off, dst, n, m,
-                       tile_v, tile, shift, bins, cursor, srcl, dstl);
+    hipLaunchKernelGGL(k_pb_expand<int32_t>, dim3((unsigned)ntiles), dim3(kWG), lds, s, (const int32_t*)off, n, m,
+                       tile_v, tile, shift, srcl_csr);
+  return hipGetLastError();
+}
+
+hipError_t launch_pb_build(bool place, const int64_t* te, int64_t tiles, const int32_t* dst, int64_t m, int64_t chunk,
+                           int64_t bins, int pass_bins, unsigned long long* cnt, const uint16_t* srcl_csr,
+                           uint16_t* srcl, uint16_t* dstl, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  if (pass_bins < 1 || chunk < 1) return hipErrorInvalidValue;
+  const int64_t grid = (m + chunk - 1) / chunk;
+  const size_t lds = (size_t)pass_bins * (place ? 8 : 4);
+  if (place)
+    hipLaunchKernelGGL(k_pb_build<true>, dim3((unsigned)grid), dim3(kBuildWG), lds, s, te, tiles, dst, m, chunk, bins,
+                       pass_bins, cnt, srcl_csr, srcl, dstl);
+  else
+    hipLaunchKernelGGL(k_pb_build<false>, dim3((unsigned)grid), dim3(kBuildWG), lds, s, te, tiles, dst, m, chunk, bins,
+                       pass_bins, cnt, srcl_csr, srcl, dstl);
+  return hipGetLastError();
+}
+
+hipError_t launch_pb_tables(const int64_t* starts, int64_t bins, int64_t tiles, int64_t fcap, int64_t* pre,
+                            int64_t* base, int64_t* nitems, hipStream_t s) {
+  hipLaunchKernelGGL(k_pb_tables, dim3(grid_for(bins)), dim3(kWG), 0, s, starts, bins, tiles, fcap, pre, base, nitems);
+  return hipGetLastError();
+}
+
+hipError_t launch_pb_fold_items(const int64_t* pre, int64_t bins, int64_t tiles, int64_t fcap, const int64_t* item_off,
+                                PbFoldItem* items, hipStream_t s) {
+  hipLaunchKernelGGL(k_pb_fold_items, dim3(grid_for(bins)), dim3(kWG), 0, s, pre, bins, tiles, fcap, item_off, items);
   return hipGetLastError();
 }
 

@@ -222,15 +222,28 @@ struct PbFoldItem {
 int pb_src_shift(size_t max_lds);
 int64_t pb_bins(int64_t n);
 int64_t pb_tiles(int64_t n, int shift);
-// cnt: bins * tiles + 1 zeroed counters.
-hipError_t launch_pb_count(const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
-                           const int32_t* tile_v, int64_t tile, int64_t ntiles, int shift, unsigned long long* cnt,
-                           hipStream_t s);
-// cursor: bucket starts (consumed); writes each edge's source offset in its
-// tile and destination offset in its bin at the next slot of its bucket.
-hipError_t launch_pb_fill(const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
-                          const int32_t* tile_v, int64_t tile, int64_t ntiles, int shift, unsigned long long* cursor,
-                          uint16_t* srcl, uint16_t* dstl, hipStream_t s);
+// te[t] = off[min(n, t << shift)] for t = 0..tiles (first edge of each
+// source tile; also its first slot).
+hipError_t launch_pb_tile_edges(const void* off, bool off64, int64_t n, int shift, int64_t tiles, int64_t* te,
+                                hipStream_t s);
+// srcl_csr[e] = offset of edge e's source in its tile (CSR order).
+hipError_t launch_pb_expand(const void* off, bool off64, int64_t n, int64_t m, const int32_t* tile_v, int64_t tile,
+                            int64_t ntiles, int shift, uint16_t* srcl_csr, hipStream_t s);
+// One workgroup per `chunk` CSR edges.  place = false: adds bucket counts
+// into cnt (bins * tiles zeroed counters).  place = true: cnt holds the
+// bucket starts (consumed as cursors); writes each edge's source offset
+// (srcl) and destination offset in its bin (dstl) at a slot of its bucket.
+// pass_bins: bins per LDS pass (pass_bins * 8 bytes of LDS).
+hipError_t launch_pb_build(bool place, const int64_t* te, int64_t tiles, const int32_t* dst, int64_t m, int64_t chunk,
+                           int64_t bins, int pass_bins, unsigned long long* cnt, const uint16_t* srcl_csr,
+                           uint16_t* srcl, uint16_t* dstl, hipStream_t s);
+// From the bucket starts: the run tables (see launch_pb_fold) and each
+// bin's number of fold items of up to fcap positions.
+hipError_t launch_pb_tables(const int64_t* starts, int64_t bins, int64_t tiles, int64_t fcap, int64_t* pre,
+                            int64_t* base, int64_t* nitems, hipStream_t s);
+// Fold items of every bin; item_off: exclusive scan of the item counts.
+hipError_t launch_pb_fold_items(const int64_t* pre, int64_t bins, int64_t tiles, int64_t fcap, const int64_t* item_off,
+                                PbFoldItem* items, hipStream_t s);
 // vals[k] = msg[tile's first vertex + srcl[k]] for every slot of every item.
 hipError_t launch_pb_spread(const PbSpreadItem* items, int64_t nitems, int64_t n, int shift, const uint16_t* srcl,
                             const unsigned long long* msg, unsigned long long* vals, hipStream_t s);
