@@ -64,18 +64,19 @@ def kernel_source_hash(form):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, form):
+def measured_traffic(workload, form, options):
     """HBM bytes per PageRank broadcast+combine of the pull or blocked form
     from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs, or None when
     the kernel source changed since they were taken (or none exist for this
-    workload)."""
+    workload and these options)."""
     path = os.path.join(ROOT, "profiles", f"pr_{form}_s26_traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
     except OSError:
         return None
-    if rec.get("workload") != workload or rec.get("source_hash") != kernel_source_hash(form):
+    if (rec.get("workload") != workload or rec.get("source_hash") != kernel_source_hash(form)
+            or rec.get("options", 0) != options):
         return None
     return int(rec["traffic_bytes_per_launch"])
 
@@ -523,6 +524,9 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--f32-accumulate", action="store_true", help="binary32 PageRank combiner (float atomics)")
+    ap.add_argument("--messages", default="u64", choices=["u64", "f32"],
+                    help="PageRank message type with exact fixed-point sums: uint64 multiples of 2^-62, or "
+                         "binary32 (VC_OPT_F32_MESSAGES)")
     ap.add_argument("--gen-threads", type=int, default=16)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for traffic counters)")
@@ -567,7 +571,11 @@ def main():
     off_bytes = csr.off.dtype.itemsize
     n, m = csr.n, csr.m
     from paper_2010_01542_amd import vc
-    kw = dict(schedule=args.schedule, tile=args.tile, options=vc.OPT_F32_ACCUMULATE if args.f32_accumulate else 0)
+    if args.f32_accumulate and args.messages == "f32":
+        sys.exit("--f32-accumulate and --messages f32 exclude each other")
+    rank_options = vc.OPT_F32_ACCUMULATE if args.f32_accumulate else (
+        vc.OPT_F32_MESSAGES if args.messages == "f32" else 0)
+    kw = dict(schedule=args.schedule, tile=args.tile, options=0)
 
     if args.workload == "sssp-s26":
         jobs = [("sssp", dict(source=0)), ("pagerank", dict(T=20))]
@@ -596,7 +604,9 @@ def main():
         for prog, pk in jobs:
             out = out_f if prog in ("pagerank", "ppr") else out_u
             pkw = dict(kw)
-            if kw["schedule"] == "blocked" and prog not in ("pagerank", "ppr"):
+            if prog in ("pagerank", "ppr"):
+                pkw["options"] = rank_options
+            elif kw["schedule"] == "blocked":
                 pkw["schedule"] = "auto"  # the blocked form is PageRank's only
             _, st = g.run(prog, out, stats=True, timing=timing, **pk, **pkw)
             res[prog] = st
@@ -644,7 +654,7 @@ def main():
         kname = {1: "k_pr_scatter_vertex", 2: "k_pr_scatter_mp", 3: "k_pr_pull",
                  4: "k_pb_spread + k_pb_fold"}.get(int(sched), "?")
         form = {3: "pull", 4: "blocked"}.get(int(sched))
-        traffic = measured_traffic(csr.name, form) if (form and not args.f32_accumulate) else None
+        traffic = measured_traffic(csr.name, form, rank_options) if form else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": f"{kname} (PageRank broadcast+combine)", "launches": int(scat.size),
@@ -679,7 +689,10 @@ def main():
         "config": {"workload": csr.name, "vertices": n, "edges": m,
                    "offsets": "int64" if off_bytes == 8 else "int32",
                    "steps": " + ".join(f"{p}{'(T=%d)' % k['T'] if 'T' in k else ''}" for p, k in jobs),
-                   "schedule": args.schedule, "tile": args.tile or "default"},
+                   "schedule": args.schedule, "tile": args.tile or "default",
+                   "rank_messages": "f32 (binary32, exact fixed-point sums)" if args.messages == "f32" and
+                   not args.f32_accumulate else ("f32 atomics" if args.f32_accumulate else
+                                                 "u64 (fixed point 2^-62, exact sums)")},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "detail": detail,

@@ -31,7 +31,9 @@
  * message is a uint64 multiple of 2^-62 (ranks never exceed 1), mailboxes add
  * them with 64-bit integer atomics, the vertex update runs in binary64 and
  * only the returned rank is rounded to binary32, so results do not depend on
- * message arrival order.  VC_OPT_F32_ACCUMULATE selects binary32 messages and
+ * message arrival order.  VC_OPT_F32_MESSAGES rounds each message to binary32
+ * before the same exact sum (half the message bytes, still order- and
+ * schedule-independent).  VC_OPT_F32_ACCUMULATE selects binary32 messages and
  * float atomics instead (half the mailbox bytes, order-dependent rounding).
  *
  * Memory: every pointer named "device" is device memory of the GPU that is
@@ -87,7 +89,8 @@ typedef enum { VC_PAGERANK = 0, VC_CC_HASHMIN = 1, VC_SSSP = 2, VC_PPR = 3 } vc_
  *                    bin of 2^12); each superstep stages a tile's messages
  *                    in LDS and copies them into its edges' slots, then
  *                    folds each bin's slots in LDS.  Both passes stream
- *                    (4 bytes of indices and 16 of message slots per edge)
+ *                    (4 bytes of indices and 16 of message slots per edge,
+ *                    8 with VC_OPT_F32_MESSAGES)
  *                    instead of gathering one message per edge from HBM.
  *                    The layout (12 bytes per edge plus 16 per bucket,
  *                    buckets = tiles x bins) is built on first use; graphs
@@ -95,10 +98,10 @@ typedef enum { VC_PAGERANK = 0, VC_CC_HASHMIN = 1, VC_SSSP = 2, VC_PPR = 3 } vc_
  *                    (VC_ERR_UNSUPPORTED);
  *   VC_SCHED_AUTO    CC / SSSP, per superstep: pull for dense frontiers,
  *                    edge-centric push otherwise (vertex push for tiny
- *                    ones).  PageRank / PPR in fixed point: BLOCKED on graphs
- *                    of 2^20 vertices and more (the first such run builds
- *                    the layout), PULL below; with VC_OPT_F32_ACCUMULATE:
- *                    PULL. */
+ *                    ones).  PageRank / PPR with fixed-point sums (default
+ *                    or VC_OPT_F32_MESSAGES): BLOCKED on graphs of 2^20
+ *                    vertices and more (the first such run builds the
+ *                    layout), PULL below; with VC_OPT_F32_ACCUMULATE: PULL. */
 typedef enum {
   VC_SCHED_AUTO = 0,
   VC_SCHED_VERTEX = 1,
@@ -127,12 +130,17 @@ enum {
   VC_OPT_NO_HUB_AGGREGATION = 1u, /* disable workgroup-level pre-combination for hub targets */
   VC_OPT_NO_TEST_BEFORE_ATOMIC = 2u, /* min programs: skip the mailbox read before the atomic (for measurement) */
   VC_OPT_F32_ACCUMULATE = 4u,        /* PageRank / PPR: binary32 messages and float atomics */
-  VC_OPT_GRAPH_CAPTURE = 8u          /* run the superstep loop as a captured HIP graph: PageRank /
+  VC_OPT_GRAPH_CAPTURE = 8u,         /* run the superstep loop as a captured HIP graph: PageRank /
                                         PPR as one graph of all T supersteps; CC / SSSP from
                                         superstep 1 on as pull supersteps with termination decided
                                         on the device (no per-superstep host round trip).  Graphs
                                         are cached per graph object; per-superstep timings are not
                                         recorded in this mode */
+  VC_OPT_F32_MESSAGES = 16u          /* PageRank / PPR: each message rounded once to binary32,
+                                        sums still exact in fixed point (half the message bytes;
+                                        results independent of order and schedule, within one
+                                        binary32 rounding per message of the default).  Excludes
+                                        VC_OPT_F32_ACCUMULATE */
 };
 
 typedef struct vc_graph_s* vc_graph;
@@ -349,7 +357,7 @@ vc_status vc_combine(vc_graph g, vc_combiner op, const uint64_t* msg, const uint
  * batched the same way: every busy lane takes one rank update per superstep
  * (sum combiner in exact fixed point, so a lane's ranks equal the request
  * run alone bit for bit) and retires after its T-th.  Requests with
- * VC_OPT_F32_ACCUMULATE or T = 0 run on workers.
+ * VC_OPT_F32_ACCUMULATE, VC_OPT_F32_MESSAGES or T = 0 run on workers.
  *
  * Lanes pay off under load: a superstep costs about the same however many
  * lanes are busy.  With VC_ROUTE_AUTO a request joins its lane table's

@@ -258,7 +258,8 @@ size_t pb_layout_bytes(vc_graph g) {
   const int shift = vc::pb_src_shift(g->max_lds);
   if (shift == 0) return 0;
   const size_t bins = (size_t)vc::pb_bins(g->n), tiles = (size_t)vc::pb_tiles(g->n, shift), m = (size_t)g->m;
-  return m * 12 + bins * (2 * tiles + 1) * 8 + (m / 4096 + bins + 2) * sizeof(vc::PbFoldItem) +
+  const size_t runs = std::min(bins * tiles, m);  // non-empty buckets
+  return m * 12 + runs * 16 + (bins + 1) * 16 + (m / 4096 + bins + 2) * sizeof(vc::PbFoldItem) +
          (m / 16384 + tiles + 2) * sizeof(vc::PbSpreadItem);
 }
 
@@ -323,20 +324,28 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
   VC_TRY(vc::launch_pb_build(true, te_d.as<int64_t>(), tiles, g->dst, m, chunk, bins, pass_bins,
                              cnt.as<unsigned long long>(), srcl_csr, g->pb_srcl.as<uint16_t>(),
                              g->pb_dstl.as<uint16_t>(), s));
-  // run tables and fold items: about 4096 items in all, 4 Ki to 64 Ki edges each
+  // run tables (non-empty buckets per bin) and fold items: about 4096 items
+  // in all, 4 Ki to 64 Ki edges each
   const int64_t fcap = std::min<int64_t>(65536, std::max<int64_t>(4096, m / 4096));
-  VC_TRY(g->pb_pre.ensure((size_t)(bins * (tiles + 1)) * 8));
-  VC_TRY(g->pb_base.ensure((size_t)(bins * tiles) * 8));
   VC_TRY(nitems.ensure((size_t)(bins + 1) * 8));
-  VC_TRY(vc::launch_pb_tables(starts_d.as<int64_t>(), bins, tiles, fcap, g->pb_pre.as<int64_t>(),
-                              g->pb_base.as<int64_t>(), nitems.as<int64_t>(), s));
+  VC_TRY(g->pb_run_off.ensure((size_t)(bins + 1) * 8));
+  VC_TRY(g->pb_btotal.ensure((size_t)bins * 8));
+  VC_TRY(vc::launch_pb_tables(false, starts_d.as<int64_t>(), bins, tiles, fcap, g->pb_run_off.as<int64_t>(),
+                              g->pb_btotal.as<int64_t>(), nitems.as<int64_t>(), nullptr, nullptr, nullptr, s));
+  VC_TRY(vc::launch_exclusive_scan(g->pb_run_off.as<int64_t>(), bins, blocks.as<int64_t>(), s));
   VC_TRY(vc::launch_exclusive_scan(nitems.as<int64_t>(), bins, blocks.as<int64_t>(), s));
-  int64_t nfold = 0;
-  VC_TRY(hipMemcpyAsync(&nfold, nitems.as<int64_t>() + bins, 8, hipMemcpyDeviceToHost, s));
+  int64_t totals[2] = {0, 0};  // runs, fold items
+  VC_TRY(hipMemcpyAsync(&totals[0], g->pb_run_off.as<int64_t>() + bins, 8, hipMemcpyDeviceToHost, s));
+  VC_TRY(hipMemcpyAsync(&totals[1], nitems.as<int64_t>() + bins, 8, hipMemcpyDeviceToHost, s));
   VC_TRY(hipStreamSynchronize(s));
+  const int64_t nfold = totals[1];
+  VC_TRY(g->pb_rpre.ensure((size_t)(totals[0] + 1) * 8));
+  VC_TRY(g->pb_rbase.ensure((size_t)(totals[0] + 1) * 8));
+  VC_TRY(vc::launch_pb_tables(true, starts_d.as<int64_t>(), bins, tiles, fcap, nullptr, nullptr, nullptr,
+                              g->pb_run_off.as<int64_t>(), g->pb_rpre.as<int64_t>(), g->pb_rbase.as<int64_t>(), s));
   VC_TRY(g->pb_fold.ensure((size_t)(nfold + 1) * sizeof(vc::PbFoldItem)));
-  VC_TRY(vc::launch_pb_fold_items(g->pb_pre.as<int64_t>(), bins, tiles, fcap, nitems.as<int64_t>(),
-                                  g->pb_fold.as<vc::PbFoldItem>(), s));
+  VC_TRY(vc::launch_pb_fold_items(g->pb_run_off.as<int64_t>(), g->pb_rpre.as<int64_t>(), g->pb_btotal.as<int64_t>(),
+                                  bins, fcap, nitems.as<int64_t>(), g->pb_fold.as<vc::PbFoldItem>(), s));
   // spread items: a tile's slots are contiguous; pieces of up to scap slots
   // (the tile's messages are loaded once per piece)
   const int64_t scap = std::min<int64_t>(1 << 18, std::max<int64_t>(1 << 14, m / 1024));
@@ -359,14 +368,13 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
 }
 
 // One broadcast + combine of the blocked schedule: spread, then fold.
-hipError_t pb_superstep(vc_graph g, const void* contrib, void* mb, hipStream_t s) {
-  hipError_t e = vc::launch_pb_spread(g->pb_spread.as<vc::PbSpreadItem>(), g->pb_nspread, g->n, g->pb_shift,
-                                      g->pb_srcl.as<uint16_t>(), static_cast<const unsigned long long*>(contrib),
-                                      g->pb_vals.as<unsigned long long>(), s);
+hipError_t pb_superstep(vc_graph g, bool f32msg, const void* contrib, void* mb, hipStream_t s) {
+  hipError_t e = vc::launch_pb_spread(f32msg, g->pb_spread.as<vc::PbSpreadItem>(), g->pb_nspread, g->n, g->pb_shift,
+                                      g->pb_srcl.as<uint16_t>(), contrib, g->pb_vals.p, s);
   if (e != hipSuccess) return e;
-  return vc::launch_pb_fold(g->pb_fold.as<vc::PbFoldItem>(), g->pb_nfold, g->pb_tiles, g->n,
-                            g->pb_pre.as<int64_t>(), g->pb_base.as<int64_t>(), g->pb_vals.as<unsigned long long>(),
-                            g->pb_dstl.as<uint16_t>(), static_cast<unsigned long long*>(mb), s);
+  return vc::launch_pb_fold(f32msg, g->pb_fold.as<vc::PbFoldItem>(), g->pb_nfold, g->pb_run_off.as<int64_t>(),
+                            g->pb_btotal.as<int64_t>(), g->pb_rpre.as<int64_t>(), g->pb_rbase.as<int64_t>(), g->n,
+                            g->pb_vals.p, g->pb_dstl.as<uint16_t>(), static_cast<unsigned long long*>(mb), s);
 }
 
 vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hipStream_t s, Recorder& rec,
@@ -377,10 +385,13 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
     vc_status st = internal_id(g, (int64_t)p.source, s, &source);
     if (st != VC_OK) return st;
   }
-  const bool fx = !(p.options & VC_OPT_F32_ACCUMULATE);
-  const size_t vb = fx ? 8 : 4;
-  VC_TRY(g->contrib.ensure((size_t)n * vb));
-  VC_TRY(g->mb.ensure((size_t)n * vb));
+  // valid_params rejects VC_OPT_F32_ACCUMULATE together with VC_OPT_F32_MESSAGES
+  const int mode = (p.options & VC_OPT_F32_ACCUMULATE)  ? vc::kRankF32
+                   : (p.options & VC_OPT_F32_MESSAGES) ? vc::kRankF32Msg
+                                                        : vc::kRankFixed;
+  const bool fx = mode != vc::kRankF32;  // sums in fixed point
+  VC_TRY(g->contrib.ensure((size_t)n * (mode == vc::kRankFixed ? 8 : 4)));
+  VC_TRY(g->mb.ensure((size_t)n * (fx ? 8 : 4)));
   void* contrib = g->contrib.p;
   void* mb = g->mb.p;
   const double r0 = 1.0 / (double)n;
@@ -388,7 +399,7 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
   // message buffer (no longer needed at the last step) and un-permute
   float* rank_out = g->relabeled ? static_cast<float*>(contrib) : out;
   if (T == 0) {
-    VC_TRY(vc::launch_pr_init(fx, g->off, g->off64, n, r0, source, contrib, mb, rank_out, s));
+    VC_TRY(vc::launch_pr_init(mode, g->off, g->off64, n, r0, source, contrib, mb, rank_out, s));
     if (g->relabeled)
       VC_TRY(vc::launch_unpermute(reinterpret_cast<const uint32_t*>(rank_out), 1, g->perm_p, n,
                                   reinterpret_cast<uint32_t*>(out), s));
@@ -420,7 +431,7 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
     // buffer (fixed address) and are copied / un-permuted afterwards
     float* stage = static_cast<float*>(contrib);
     char keybuf[160];
-    std::snprintf(keybuf, sizeof keybuf, "%d/%lld/%lld/%.17g/%d/%lld", (int)fx, (long long)T, (long long)source, d,
+    std::snprintf(keybuf, sizeof keybuf, "%d/%lld/%lld/%.17g/%d/%lld", mode, (long long)T, (long long)source, d,
                   sched, (long long)tile);
     if (g->pr_exec && g->pr_exec_key != keybuf) {
       VC_TRY(hipGraphExecDestroy(g->pr_exec));
@@ -430,22 +441,22 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
       VC_TRY(ensure_capture_stream(g));
       hipStream_t cs = g->cap_stream;
       VC_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      hipError_t e = vc::launch_pr_init(fx, g->off, g->off64, n, r0, source, contrib, mb, nullptr, cs);
+      hipError_t e = vc::launch_pr_init(mode, g->off, g->off64, n, r0, source, contrib, mb, nullptr, cs);
       for (int64_t step = 0; step < T && e == hipSuccess; ++step) {
         if (g->m > 0) {
           if (sched == VC_SCHED_PULL) {
-            e = vc::launch_pr_pull(fx, g->csc_off_p, g->in_src, n, g->m, g->csc_tiles_p,
+            e = vc::launch_pr_pull(mode, g->csc_off_p, g->in_src, n, g->m, g->csc_tiles_p,
                                    g->csc_tile, g->csc_ntiles, contrib, mb, cs);
           } else if (sched == VC_SCHED_BLOCKED) {
-            e = pb_superstep(g, contrib, mb, cs);
+            e = pb_superstep(g, mode == vc::kRankF32Msg, contrib, mb, cs);
           } else if (sched == VC_SCHED_EDGE)
-            e = vc::launch_pr_scatter_mp(fx, g->off, g->off64, g->dst, n, g->m, g->dense_tiles_p, tile,
+            e = vc::launch_pr_scatter_mp(mode, g->off, g->off64, g->dst, n, g->m, g->dense_tiles_p, tile,
                                          g->dense_ntiles, contrib, mb, cs);
           else
-            e = vc::launch_pr_scatter_vertex(fx, g->off, g->off64, g->dst, n, contrib, mb, cs);
+            e = vc::launch_pr_scatter_vertex(mode, g->off, g->off64, g->dst, n, contrib, mb, cs);
         }
         if (e == hipSuccess)
-          e = vc::launch_pr_apply(fx, g->off, g->off64, n, teleport, d, source, mb, contrib, stage, step + 1 == T, cs);
+          e = vc::launch_pr_apply(mode, g->off, g->off64, n, teleport, d, source, mb, contrib, stage, step + 1 == T, cs);
       }
       hipGraph_t graph = nullptr;
       const hipError_t e2 = hipStreamEndCapture(cs, &graph);
@@ -469,24 +480,24 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
     return VC_OK;
   }
   if (rec.timed) VC_TRY(ensure_events(g, (size_t)(3 * T)));
-  VC_TRY(vc::launch_pr_init(fx, g->off, g->off64, n, r0, source, contrib, mb, nullptr, s));
+  VC_TRY(vc::launch_pr_init(mode, g->off, g->off64, n, r0, source, contrib, mb, nullptr, s));
   for (int64_t step = 0; step < T; ++step) {
     const bool timed = rec.want_time(step);
     if (timed) VC_TRY(hipEventRecord(g->events[3 * step], s));
     if (g->m > 0) {
       if (sched == VC_SCHED_PULL) {
-        VC_TRY(vc::launch_pr_pull(fx, g->csc_off_p, g->in_src, n, g->m, g->csc_tiles_p,
+        VC_TRY(vc::launch_pr_pull(mode, g->csc_off_p, g->in_src, n, g->m, g->csc_tiles_p,
                                   g->csc_tile, g->csc_ntiles, contrib, mb, s));
       } else if (sched == VC_SCHED_BLOCKED) {
-        VC_TRY(pb_superstep(g, contrib, mb, s));
+        VC_TRY(pb_superstep(g, mode == vc::kRankF32Msg, contrib, mb, s));
       } else if (sched == VC_SCHED_EDGE)
-        VC_TRY(vc::launch_pr_scatter_mp(fx, g->off, g->off64, g->dst, n, g->m, g->dense_tiles_p, tile,
+        VC_TRY(vc::launch_pr_scatter_mp(mode, g->off, g->off64, g->dst, n, g->m, g->dense_tiles_p, tile,
                                         g->dense_ntiles, contrib, mb, s));
       else
-        VC_TRY(vc::launch_pr_scatter_vertex(fx, g->off, g->off64, g->dst, n, contrib, mb, s));
+        VC_TRY(vc::launch_pr_scatter_vertex(mode, g->off, g->off64, g->dst, n, contrib, mb, s));
     }
     if (timed) VC_TRY(hipEventRecord(g->events[3 * step + 1], s));
-    VC_TRY(vc::launch_pr_apply(fx, g->off, g->off64, n, teleport, d, source, mb, contrib, rank_out, step + 1 == T, s));
+    VC_TRY(vc::launch_pr_apply(mode, g->off, g->off64, n, teleport, d, source, mb, contrib, rank_out, step + 1 == T, s));
     if (timed) VC_TRY(hipEventRecord(g->events[3 * step + 2], s));
     rec.step(step, n, g->m, sched);
   }
@@ -782,6 +793,8 @@ bool valid_params(const vc_params& p, vc_program prog, int64_t n, std::string* w
     return *why = "the blocked schedule is for PageRank / PPR", false;
   if (p.tile < 0) return *why = "negative tile", false;
   if (!(p.pull_fraction >= 0.0f)) return *why = "negative pull_fraction", false;
+  if ((p.options & VC_OPT_F32_ACCUMULATE) && (p.options & VC_OPT_F32_MESSAGES))
+    return *why = "VC_OPT_F32_ACCUMULATE and VC_OPT_F32_MESSAGES exclude each other", false;
   if (prog == VC_PAGERANK || prog == VC_PPR) {
     if (p.max_supersteps < 0) return *why = "PageRank needs T >= 0", false;
     if (!(p.damping >= 0.0 && p.damping <= 1.0)) return *why = "damping outside [0, 1]", false;
@@ -968,7 +981,7 @@ vc_status vc_graph_destroy(vc_graph g) {
                     &g->contrib, &g->mb, &g->vm, &g->bitmap, &g->bitmap2,
                     &g->fq, &g->prefix, &g->scan_blocks, &g->list_tiles, &g->csc_off, &g->csc_src,
                     &g->csc_w, &g->ms_src, &g->counters, &g->pb_srcl, &g->pb_dstl, &g->pb_vals,
-                    &g->pb_pre, &g->pb_base, &g->pb_spread, &g->pb_fold})
+                    &g->pb_run_off, &g->pb_btotal, &g->pb_rpre, &g->pb_rbase, &g->pb_spread, &g->pb_fold})
     b->release();
   g->ms.release();
   g->dense_parts.release();
@@ -995,8 +1008,8 @@ vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held,
                 g->rel_off.bytes + g->rel_dst.bytes + g->rel_w.bytes;
   for (const DevBuf* b : {&g->contrib, &g->mb, &g->vm, &g->bitmap, &g->bitmap2, &g->fq, &g->prefix, &g->scan_blocks,
                           &g->list_tiles, &g->csc_off, &g->csc_src, &g->csc_w,
-                          &g->ms_src, &g->counters, &g->pb_srcl, &g->pb_dstl, &g->pb_vals, &g->pb_pre, &g->pb_base,
-                          &g->pb_spread, &g->pb_fold})
+                          &g->ms_src, &g->counters, &g->pb_srcl, &g->pb_dstl, &g->pb_vals, &g->pb_run_off,
+                          &g->pb_btotal, &g->pb_rpre, &g->pb_rbase, &g->pb_spread, &g->pb_fold})
     held += b->bytes;
   held += g->ms.bytes();
   held += g->dense_parts.bytes() + g->csc_parts.bytes();

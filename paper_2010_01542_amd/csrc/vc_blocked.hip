@@ -17,6 +17,7 @@
 //      array (added atomically when a bin of hubs is split over several
 //      workgroups).
 // Sums stay exact (uint64 fixed point), so results equal the pull form's.
+// Messages are uint64 fixed point or binary32 (half the slot bytes).
 #include "vc_device.h"
 
 namespace vc {
@@ -143,43 +144,60 @@ __global__ __launch_bounds__(kBuildWG) void k_pb_build(const int64_t* __restrict
   }
 }
 
-// Per bin b (one thread): run prefix sums pre[b][t], slot bases base[b][t]
-// and the number of fold items of the bin.
+// Run tables, one thread per bin b; runs are the non-empty buckets (t, b)
+// in tile order.  Count pass: number of runs, edges of the bin (btotal)
+// and fold items of up to fcap positions.  Fill pass: for run i of bin b
+// (index run_off[b] + i), rpre = its first position in the concatenation
+// of the bin's runs and rbase = its first slot minus rpre.
+template <bool FILL>
 __global__ __launch_bounds__(kWG) void k_pb_tables(const int64_t* __restrict__ starts, int64_t bins, int64_t tiles,
-                                                   int64_t fcap, int64_t* __restrict__ pre,
-                                                   int64_t* __restrict__ base, int64_t* __restrict__ nitems) {
+                                                   int64_t fcap, int64_t* __restrict__ nruns,
+                                                   int64_t* __restrict__ btotal, int64_t* __restrict__ nitems,
+                                                   const int64_t* __restrict__ run_off, int64_t* __restrict__ rpre,
+                                                   int64_t* __restrict__ rbase) {
   const int64_t b = gid();
   if (b >= bins) return;
-  int64_t* P = pre + b * (tiles + 1);
-  int64_t* B = base + b * tiles;
-  int64_t acc = 0;
+  int64_t acc = 0, runs = 0;
+  const int64_t r0 = FILL ? run_off[b] : 0;
   for (int64_t t = 0; t < tiles; ++t) {
     const int64_t q = t * bins + b;
-    const int64_t s0 = starts[q], s1 = starts[q + 1];
-    P[t] = acc;
-    B[t] = s0 - acc;
-    acc += s1 - s0;
+    const int64_t s0 = starts[q], len = starts[q + 1] - s0;
+    if (len == 0) continue;
+    if (FILL) {
+      rpre[r0 + runs] = acc;
+      rbase[r0 + runs] = s0 - acc;
+    }
+    acc += len;
+    ++runs;
   }
-  P[tiles] = acc;
-  nitems[b] = (acc + fcap - 1) / fcap;
+  if (!FILL) {
+    nruns[b] = runs;
+    btotal[b] = acc;
+    nitems[b] = (acc + fcap - 1) / fcap;
+  }
 }
 
-// Per bin b (one thread): its fold items, positions [i fcap, (i+1) fcap).
-__global__ __launch_bounds__(kWG) void k_pb_fold_items(const int64_t* __restrict__ pre, int64_t bins, int64_t tiles,
+// Per bin b (one thread): its fold items, positions [i fcap, (i+1) fcap),
+// with the runs [r0, r1) (indices in the bin's run list) they touch.
+__global__ __launch_bounds__(kWG) void k_pb_fold_items(const int64_t* __restrict__ run_off,
+                                                       const int64_t* __restrict__ rpre,
+                                                       const int64_t* __restrict__ btotal, int64_t bins,
                                                        int64_t fcap, const int64_t* __restrict__ item_off,
                                                        PbFoldItem* __restrict__ items) {
   const int64_t b = gid();
   if (b >= bins) return;
-  const int64_t* P = pre + b * (tiles + 1);
-  const int64_t total = P[tiles];
+  const int64_t* P = rpre + run_off[b];
+  const int64_t nr = run_off[b + 1] - run_off[b];
+  const int64_t total = btotal[b];
   const int64_t first = item_off[b], count = item_off[b + 1] - item_off[b];
-  int64_t r = 0;  // run holding position v: last r with P[r] <= v (v < total = P[tiles])
+  auto start = [&](int64_t r) { return r < nr ? P[r] : total; };
+  int64_t r = 0;  // run holding position v: last r with start(r) <= v (v < total, so r < nr)
   for (int64_t i = 0; i < count; ++i) {
     const int64_t v0 = i * fcap;
     const int64_t v1 = (v0 + fcap < total) ? v0 + fcap : total;
-    while (P[r + 1] <= v0) ++r;
+    while (start(r + 1) <= v0) ++r;
     int64_t r1 = r;
-    while (P[r1 + 1] <= v1 - 1) ++r1;
+    while (start(r1 + 1) <= v1 - 1) ++r1;
     items[first + i] = PbFoldItem{(int32_t)b, count == 1 ? 1 : 0, r, r1 + 1, v0, v1};
   }
 }
@@ -187,12 +205,13 @@ __global__ __launch_bounds__(kWG) void k_pb_fold_items(const int64_t* __restrict
 // Pass 1: one workgroup per spread item; the tile's messages in LDS.
 constexpr int kSpreadWG = 1024;
 
+template <class M>
 __global__ __launch_bounds__(kSpreadWG) void k_pb_spread(const PbSpreadItem* __restrict__ items, int64_t n, int shift,
-                                                         const uint16_t* __restrict__ srcl,
-                                                         const unsigned long long* __restrict__ msg,
-                                                         unsigned long long* __restrict__ vals) {
+                                                         const uint16_t* __restrict__ srcl, const M* __restrict__ msg,
+                                                         M* __restrict__ vals) {
   constexpr int U = 8;
-  extern __shared__ __align__(16) unsigned long long win[];
+  extern __shared__ __align__(16) unsigned char smem[];
+  M* win = reinterpret_cast<M*>(smem);
   const PbSpreadItem it = items[blockIdx.x];
   const int64_t u0 = (int64_t)it.t << shift;
   const int64_t wl = (n - u0 < (1ll << shift)) ? n - u0 : (1ll << shift);
@@ -213,77 +232,105 @@ __global__ __launch_bounds__(kSpreadWG) void k_pb_spread(const PbSpreadItem* __r
   }
 }
 
-// Pass 2: one workgroup per fold item.  Runs are staged kFoldRuns at a
-// time (prefix sums and slot bases in LDS); each lane takes U positions 64
-// apart, finds the run of the first by binary search, steps forward for the
-// rest, and adds the U messages into the LDS mailboxes.  Items are
-// handed out so that each of the 8 XCDs takes a contiguous range of bins:
-// runs of neighbouring bins share cache lines at their ends, which then
-// meet in the same L2.
+// Pass 2: one workgroup per fold item.  The item's runs are staged
+// kFoldRuns at a time in LDS (start positions s_pre, slot bases s_base).
+// Wavefronts take ranges of 64 U consecutive positions, 64 at a time, lane
+// l the position p + l, so every load instruction reads 64 consecutive
+// slots.  Lane l's run is found without a per-lane search: the wavefront
+// holds the starts of the next 64 runs, one per lane (S); the runs starting
+// at or before p are counted with one ballot, the run starts inside
+// (p, p + 63] are flagged per position through a 64-entry LDS array, and a
+// lane adds the flags at or below its own position (a masked popcount).
+// Runs are never empty, so their starts increase strictly and 64 of them
+// cover any 64 positions.  Items are handed out so that each of the 8 XCDs
+// takes a contiguous range of bins: runs of neighbouring bins share cache
+// lines at their ends, which then meet in the same L2.
 constexpr int kFoldWG = 512;
 constexpr int kFoldRuns = 1024;
 
+template <class M>
 __global__ __launch_bounds__(kFoldWG) void k_pb_fold(const PbFoldItem* __restrict__ items, int64_t nitems,
-                                                     int64_t tiles, int64_t n, const int64_t* __restrict__ pre,
-                                                     const int64_t* __restrict__ base,
-                                                     const unsigned long long* __restrict__ vals,
-                                                     const uint16_t* __restrict__ dstl,
+                                                     const int64_t* __restrict__ run_off,
+                                                     const int64_t* __restrict__ btotal,
+                                                     const int64_t* __restrict__ rpre,
+                                                     const int64_t* __restrict__ rbase, int64_t n,
+                                                     const M* __restrict__ vals, const uint16_t* __restrict__ dstl,
                                                      unsigned long long* __restrict__ mb) {
   constexpr int U = 8;
+  constexpr int kNone = 0x7fffffff;
   __shared__ unsigned long long box[1 << kPbDstShift];
-  __shared__ int64_t s_pre[kFoldRuns + 1];
-  __shared__ int64_t s_base[kFoldRuns];
+  __shared__ int32_t s_pre[kFoldRuns + 1];  // run starts relative to the item's first position, clamped
+  __shared__ int64_t s_base[kFoldRuns];     // slot of the item's first position in each run's frame
+  __shared__ uint32_t s_flag[kFoldWG];
   const int64_t per = (nitems + 7) >> 3;
   const int64_t j = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (j >= nitems) return;
   const PbFoldItem it = items[j];
   for (int i = threadIdx.x; i < (1 << kPbDstShift); i += kFoldWG) box[i] = 0ull;
-  const int64_t* P = pre + (int64_t)it.b * (tiles + 1);
-  const int64_t* B = base + (int64_t)it.b * tiles;
+  const int64_t R0 = run_off[it.b], nr = run_off[it.b + 1] - R0, total = btotal[it.b];
+  const int len = (int)(it.v1 - it.v0);  // positions of the item, relative: [0, len), len <= 2^16
+  const int lane = threadIdx.x & 63;
+  uint32_t* flag = s_flag + (threadIdx.x & ~63);
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);  // lanes 0..lane
   for (int64_t w0 = it.r0; w0 < it.r1; w0 += kFoldRuns) {
     const int wn = (int)((it.r1 - w0 < kFoldRuns) ? it.r1 - w0 : kFoldRuns);
     for (int i = threadIdx.x; i <= wn; i += kFoldWG) {
-      s_pre[i] = P[w0 + i];  // w0 + wn <= r1 <= tiles
-      if (i < wn) s_base[i] = B[w0 + i];
+      // starts before the item clamp to -1 and after it to kNone: order
+      // against positions 0..len-1 is kept, which is all the lookup uses
+      const int64_t st = (w0 + i < nr ? rpre[R0 + w0 + i] : total) - it.v0;
+      s_pre[i] = st < 0 ? -1 : (st > len ? kNone : (int32_t)st);
+      if (i < wn) s_base[i] = rbase[R0 + w0 + i] + it.v0;
     }
     __syncthreads();
-    const int64_t a = it.v0 > s_pre[0] ? it.v0 : s_pre[0];
-    const int64_t z = it.v1 < s_pre[wn] ? it.v1 : s_pre[wn];
-    // wavefront w takes positions [g0, g0 + 64 U) of every kFoldWG U, lane l
-    // the positions g0 + 64 u + l: each load instruction reads 64 consecutive slots
-    const int lane = threadIdx.x & 63;
-    for (int64_t g0 = a + (int64_t)(threadIdx.x >> 6) * 64 * U; g0 < z; g0 += (int64_t)kFoldWG * U) {
-      const int64_t e0 = g0 + lane;
-      int lo = 0, hi = wn - 1;  // last run r with s_pre[r] <= e0 (or <= g0 when e0 >= z)
-      const int64_t key = e0 < z ? e0 : g0;
+    const int a = s_pre[0] > 0 ? s_pre[0] : 0;
+    const int z = s_pre[wn] < len ? s_pre[wn] : len;
+    for (int g = a + (threadIdx.x >> 6) * 64 * U; g < z; g += kFoldWG * U) {
+      int lo = 0, hi = wn - 1;  // rb = run of position g (wavefront-uniform)
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (s_pre[mid] <= key)
+        if (s_pre[mid] <= g)
           lo = mid;
         else
           hi = mid - 1;
       }
-      int r = lo;
+      int rb = lo;
+      int S = rb + lane <= wn ? s_pre[rb + lane] : kNone;
       int64_t k[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int64_t e = e0 + (int64_t)u * 64;
+        const int p = g + u * 64;
         k[u] = -1;
-        if (e < z) {
-          while (s_pre[r + 1] <= e) ++r;  // e < z <= s_pre[wn], so r stays below wn
-          k[u] = s_base[r] + e;
+        if (p >= z) continue;  // uniform
+        unsigned long long below = __ballot(S <= p);  // runs starting at or before p: lanes 0..c0-1
+        if (__builtin_amdgcn_readlane(S, 63) < p + 63) {  // a start in (p, p + 63] lies past the window
+          rb += __popcll(below) - 1;
+          S = rb + lane <= wn ? s_pre[rb + lane] : kNone;
+          below = __ballot(S <= p);
         }
+        const int d = S - p;
+        flag[lane] = 0u;
+        __builtin_amdgcn_wave_barrier();
+        if (d >= 1 && d <= 63) flag[d] = 1u;
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t f = flag[lane];
+        __builtin_amdgcn_wave_barrier();
+        const unsigned long long starts = __ballot(f != 0u);
+        const int r = rb + __popcll(below) - 1 + __popcll(starts & upto);
+        const int q = p + lane;
+        if (q < z) k[u] = s_base[r] + q;
       }
-      uint16_t d[U];
-      unsigned long long x[U];
+      uint16_t dl[U];
+      M raw[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {  // all loads first, then the conversions and adds
+        dl[u] = k[u] >= 0 ? dstl[k[u]] : 0;
+        raw[u] = k[u] >= 0 ? vals[k[u]] : M(0);
+      }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        d[u] = k[u] >= 0 ? dstl[k[u]] : 0;
-        x[u] = k[u] >= 0 ? vals[k[u]] : 0ull;
+        const unsigned long long x = msg_to_sum<M, unsigned long long>(raw[u]);
+        if (x) atomicAdd(&box[dl[u]], x);
       }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (x[u]) atomicAdd(&box[d[u]], x[u]);
     }
     __syncthreads();
   }
@@ -348,34 +395,49 @@ hipError_t launch_pb_build(bool place, const int64_t* te, int64_t tiles, const i
   return hipGetLastError();
 }
 
-hipError_t launch_pb_tables(const int64_t* starts, int64_t bins, int64_t tiles, int64_t fcap, int64_t* pre,
-                            int64_t* base, int64_t* nitems, hipStream_t s) {
-  hipLaunchKernelGGL(k_pb_tables, dim3(grid_for(bins)), dim3(kWG), 0, s, starts, bins, tiles, fcap, pre, base, nitems);
+hipError_t launch_pb_tables(bool fill, const int64_t* starts, int64_t bins, int64_t tiles, int64_t fcap,
+                            int64_t* nruns, int64_t* btotal, int64_t* nitems, const int64_t* run_off, int64_t* rpre,
+                            int64_t* rbase, hipStream_t s) {
+  if (fill)
+    hipLaunchKernelGGL(k_pb_tables<true>, dim3(grid_for(bins)), dim3(kWG), 0, s, starts, bins, tiles, fcap, nruns,
+                       btotal, nitems, run_off, rpre, rbase);
+  else
+    hipLaunchKernelGGL(k_pb_tables<false>, dim3(grid_for(bins)), dim3(kWG), 0, s, starts, bins, tiles, fcap, nruns,
+                       btotal, nitems, run_off, rpre, rbase);
   return hipGetLastError();
 }
 
-hipError_t launch_pb_fold_items(const int64_t* pre, int64_t bins, int64_t tiles, int64_t fcap, const int64_t* item_off,
-                                PbFoldItem* items, hipStream_t s) {
-  hipLaunchKernelGGL(k_pb_fold_items, dim3(grid_for(bins)), dim3(kWG), 0, s, pre, bins, tiles, fcap, item_off, items);
+hipError_t launch_pb_fold_items(const int64_t* run_off, const int64_t* rpre, const int64_t* btotal, int64_t bins,
+                                int64_t fcap, const int64_t* item_off, PbFoldItem* items, hipStream_t s) {
+  hipLaunchKernelGGL(k_pb_fold_items, dim3(grid_for(bins)), dim3(kWG), 0, s, run_off, rpre, btotal, bins, fcap,
+                     item_off, items);
   return hipGetLastError();
 }
 
-hipError_t launch_pb_spread(const PbSpreadItem* items, int64_t nitems, int64_t n, int shift, const uint16_t* srcl,
-                            const unsigned long long* msg, unsigned long long* vals, hipStream_t s) {
+hipError_t launch_pb_spread(bool f32msg, const PbSpreadItem* items, int64_t nitems, int64_t n, int shift,
+                            const uint16_t* srcl, const void* msg, void* vals, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   if (shift < 10 || shift > kMaxSrcShift) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pb_spread, dim3((unsigned)nitems), dim3(kSpreadWG), (size_t)8 << shift, s, items, n, shift,
-                     srcl, msg, vals);
+  if (f32msg)
+    hipLaunchKernelGGL(k_pb_spread<float>, dim3((unsigned)nitems), dim3(kSpreadWG), (size_t)4 << shift, s, items, n,
+                       shift, srcl, (const float*)msg, (float*)vals);
+  else
+    hipLaunchKernelGGL(k_pb_spread<unsigned long long>, dim3((unsigned)nitems), dim3(kSpreadWG), (size_t)8 << shift,
+                       s, items, n, shift, srcl, (const unsigned long long*)msg, (unsigned long long*)vals);
   return hipGetLastError();
 }
 
-hipError_t launch_pb_fold(const PbFoldItem* items, int64_t nitems, int64_t tiles, int64_t n, const int64_t* pre,
-                          const int64_t* base, const unsigned long long* vals, const uint16_t* dstl,
-                          unsigned long long* mb, hipStream_t s) {
+hipError_t launch_pb_fold(bool f32msg, const PbFoldItem* items, int64_t nitems, const int64_t* run_off,
+                          const int64_t* btotal, const int64_t* rpre, const int64_t* rbase, int64_t n,
+                          const void* vals, const uint16_t* dstl, unsigned long long* mb, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   const int64_t per = (nitems + 7) >> 3;
-  hipLaunchKernelGGL(k_pb_fold, dim3((unsigned)(8 * per)), dim3(kFoldWG), 0, s, items, nitems, tiles, n, pre, base,
-                     vals, dstl, mb);
+  if (f32msg)
+    hipLaunchKernelGGL(k_pb_fold<float>, dim3((unsigned)(8 * per)), dim3(kFoldWG), 0, s, items, nitems, run_off,
+                       btotal, rpre, rbase, n, (const float*)vals, dstl, mb);
+  else
+    hipLaunchKernelGGL(k_pb_fold<unsigned long long>, dim3((unsigned)(8 * per)), dim3(kFoldWG), 0, s, items, nitems,
+                       run_off, btotal, rpre, rbase, n, (const unsigned long long*)vals, dstl, mb);
   return hipGetLastError();
 }
 

@@ -68,6 +68,44 @@ __device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
   return s < a ? kInf : s;
 }
 
+// ------------------------------------------------- PageRank messages and sums
+// Sums (mailboxes) S are uint64 multiples of 2^-62 (exact, associative; ranks
+// and their sums never exceed 1) or binary32 (float atomics).  Messages M
+// are uint64 multiples of 2^-62 or binary32; a binary32 message summed in
+// fixed point is scaled by 2^62 (exact) and rounded to an integer, so its
+// sum is still exact and order-independent.
+constexpr double kFixScale = 4611686018427387904.0;  // 2^62
+constexpr double kFixInv = 1.0 / 4611686018427387904.0;
+
+template <class M, class S>
+__device__ __forceinline__ S msg_to_sum(M m) {
+  if constexpr (sizeof(M) == 4 && sizeof(S) == 8) {
+    // m = f * 2^(e - 150) with the 24-bit significand f (0 <= m <= 1):
+    // m * 2^62 = f * 2^(e - 88), exact for m >= 2^-38 and truncated below
+    // (an error under 2^-62 per message).  Zero and subnormal messages
+    // shift out entirely.  Branch-free, so that a caller's loads are not
+    // split by control flow.
+    const uint32_t b = __float_as_uint(m);
+    const int sh = (int)(b >> 23) - 88;
+    const unsigned long long f = (unsigned long long)((b & 0x7fffffu) | 0x800000u);
+    return sh >= 0 ? f << sh : f >> (-sh < 63 ? -sh : 63);
+  } else {
+    return (S)m;
+  }
+}
+
+// The message a vertex of out-degree deg and rank r sends on each edge.
+template <class M, class S>
+__device__ __forceinline__ M rank_msg(double r, int64_t deg) {
+  if (deg <= 0) return M(0);
+  if constexpr (sizeof(M) == 8)
+    return __double2ull_rn(r / (double)deg * kFixScale);
+  else if constexpr (sizeof(S) == 8)
+    return (float)(r / (double)deg);  // one rounding
+  else
+    return (float)r / (float)deg;
+}
+
 // Byte offset of the next LDS sub-array: rounded up to 16 bytes.
 __host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 

@@ -159,7 +159,7 @@ struct vc_graph_s {
   // propagation-blocking layout (PageRank): per edge slot its source and
   // destination offset in its bin, bucket starts, fold items, message slots
   // propagation-blocking layout (PageRank / PPR, built on first use)
-  vc::DevBuf pb_srcl, pb_dstl, pb_vals, pb_pre, pb_base, pb_spread, pb_fold;
+  vc::DevBuf pb_srcl, pb_dstl, pb_vals, pb_run_off, pb_btotal, pb_rpre, pb_rbase, pb_spread, pb_fold;
   int64_t pb_nspread = 0, pb_nfold = 0, pb_tiles = 0;
   int pb_shift = 0;
   bool pb_ready = false;

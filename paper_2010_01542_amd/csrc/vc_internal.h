@@ -53,16 +53,21 @@ hipError_t launch_mp_partition(const void* P, bool p64, int64_t items, int64_t t
                                int32_t* tile_v, hipStream_t s);
 
 // PageRank / PPR.  `source` < 0 selects PageRank, else PPR from `source`.
-// fx selects the fixed-point (uint64, 2^-62) combiner, else binary32; the
-// contrib and mb buffers hold 8- or 4-byte values accordingly.
-hipError_t launch_pr_init(bool fx, const void* off, bool off64, int64_t n, double r0, int64_t source, void* contrib,
+// mode: message / mailbox types; contrib holds the messages (8 bytes per
+// vertex for kRankFixed, else 4), mb the sums (4 bytes for kRankF32, else 8).
+enum RankMode : int {
+  kRankFixed = 0,   // uint64 multiples of 2^-62 for both
+  kRankF32 = 1,     // binary32 for both, float atomics
+  kRankF32Msg = 2,  // binary32 messages, uint64 fixed-point sums
+};
+hipError_t launch_pr_init(int mode, const void* off, bool off64, int64_t n, double r0, int64_t source, void* contrib,
                           void* mb, float* out_if_t0, hipStream_t s);
-hipError_t launch_pr_scatter_vertex(bool fx, const void* off, bool off64, const int32_t* dst, int64_t n,
+hipError_t launch_pr_scatter_vertex(int mode, const void* off, bool off64, const int32_t* dst, int64_t n,
                                     const void* contrib, void* mb, hipStream_t s);
-hipError_t launch_pr_scatter_mp(bool fx, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
+hipError_t launch_pr_scatter_mp(int mode, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
                                 const int32_t* tile_v, int64_t tile, int64_t ntiles, const void* contrib, void* mb,
                                 hipStream_t s);
-hipError_t launch_pr_apply(bool fx, const void* off, bool off64, int64_t n, double teleport, double damping,
+hipError_t launch_pr_apply(int mode, const void* off, bool off64, int64_t n, double teleport, double damping,
                            int64_t source, void* mb, void* contrib, float* out, bool last, hipStream_t s);
 
 // Hash-min CC and SSSP.  vm holds (value, mailbox) pairs.
@@ -110,7 +115,7 @@ hipError_t launch_csc_fill(const void* off, bool off64, const int32_t* dst, cons
 size_t pull_lds_bytes(int64_t tile);
 // Tile size the pull kernels use for a requested tile: kWG * {4, 8, 16}.
 int64_t pull_tile(int64_t requested);
-hipError_t launch_pr_pull(bool fx, const int64_t* in_off, const int32_t* in_src, int64_t n, int64_t m,
+hipError_t launch_pr_pull(int mode, const int64_t* in_off, const int32_t* in_src, int64_t n, int64_t m,
                           const int32_t* tile_v, int64_t tile, int64_t ntiles, const void* contrib, void* mb,
                           hipStream_t s);
 // active = NULL: every vertex broadcast this superstep.
@@ -211,9 +216,9 @@ struct PbSpreadItem {
   int32_t t, pad;
   int64_t k0, k1;
 };
-// Fold item: positions [v0, v1) of the concatenation of bin b's runs (run t
-// = bucket (t, b)), which lie in runs [r0, r1); whole marks the only item of
-// its bin.
+// Fold item: positions [v0, v1) of the concatenation of bin b's runs (the
+// non-empty buckets (t, b) in tile order), which lie in runs [r0, r1) of the
+// bin's run list; whole marks the only item of its bin.
 struct PbFoldItem {
   int32_t b, whole;
   int64_t r0, r1, v0, v1;
@@ -237,22 +242,28 @@ hipError_t launch_pb_expand(const void* off, bool off64, int64_t n, int64_t m, c
 hipError_t launch_pb_build(bool place, const int64_t* te, int64_t tiles, const int32_t* dst, int64_t m, int64_t chunk,
                            int64_t bins, int pass_bins, unsigned long long* cnt, const uint16_t* srcl_csr,
                            uint16_t* srcl, uint16_t* dstl, hipStream_t s);
-// From the bucket starts: the run tables (see launch_pb_fold) and each
-// bin's number of fold items of up to fcap positions.
-hipError_t launch_pb_tables(const int64_t* starts, int64_t bins, int64_t tiles, int64_t fcap, int64_t* pre,
-                            int64_t* base, int64_t* nitems, hipStream_t s);
+// Run tables from the bucket starts (runs = non-empty buckets of a bin, in
+// tile order).  fill = false: per bin, nruns (runs), btotal (edges) and
+// nitems (fold items of up to fcap positions).  fill = true, with run_off
+// the exclusive scan of nruns: rpre / rbase of every run (see
+// launch_pb_fold).
+hipError_t launch_pb_tables(bool fill, const int64_t* starts, int64_t bins, int64_t tiles, int64_t fcap,
+                            int64_t* nruns, int64_t* btotal, int64_t* nitems, const int64_t* run_off, int64_t* rpre,
+                            int64_t* rbase, hipStream_t s);
 // Fold items of every bin; item_off: exclusive scan of the item counts.
-hipError_t launch_pb_fold_items(const int64_t* pre, int64_t bins, int64_t tiles, int64_t fcap, const int64_t* item_off,
-                                PbFoldItem* items, hipStream_t s);
-// vals[k] = msg[tile's first vertex + srcl[k]] for every slot of every item.
-hipError_t launch_pb_spread(const PbSpreadItem* items, int64_t nitems, int64_t n, int shift, const uint16_t* srcl,
-                            const unsigned long long* msg, unsigned long long* vals, hipStream_t s);
-// pre: bins x (tiles + 1) run prefix sums, base: bins x tiles (slot of
-// position v in run t of bin b = base[b * tiles + t] + v).  Adds every
+hipError_t launch_pb_fold_items(const int64_t* run_off, const int64_t* rpre, const int64_t* btotal, int64_t bins,
+                                int64_t fcap, const int64_t* item_off, PbFoldItem* items, hipStream_t s);
+// vals[k] = msg[tile's first vertex + srcl[k]] for every slot of every item;
+// msg / vals hold binary32 messages when f32msg, else uint64 fixed point.
+hipError_t launch_pb_spread(bool f32msg, const PbSpreadItem* items, int64_t nitems, int64_t n, int shift,
+                            const uint16_t* srcl, const void* msg, void* vals, hipStream_t s);
+// Runs of bin b are run_off[b] .. run_off[b + 1] - 1; run i starts at
+// position rpre[i] of the concatenation of the bin's runs (btotal[b]
+// positions) and position v of it sits at slot rbase[i] + v.  Adds every
 // item's messages into mb (stores for whole bins); mb zero on entry.
-hipError_t launch_pb_fold(const PbFoldItem* items, int64_t nitems, int64_t tiles, int64_t n, const int64_t* pre,
-                          const int64_t* base, const unsigned long long* vals, const uint16_t* dstl,
-                          unsigned long long* mb, hipStream_t s);
+hipError_t launch_pb_fold(bool f32msg, const PbFoldItem* items, int64_t nitems, const int64_t* run_off,
+                          const int64_t* btotal, const int64_t* rpre, const int64_t* rbase, int64_t n,
+                          const void* vals, const uint16_t* dstl, unsigned long long* mb, hipStream_t s);
 
 // In-place exclusive scan of P[0..count) with P[count] = total; `blocks`
 // is scratch of scan_scratch_entries(count) int64 values.

@@ -76,44 +76,32 @@ __global__ __launch_bounds__(kWG) void k_mp_partition(const PT* __restrict__ P, 
 }
 
 // ------------------------------------------------------------------ PageRank
-// Two combiners for the sum mailboxes:
-//  * fixed point (default): messages and mailboxes are uint64 multiples of
-//    2^-62 (ranks and their sums never exceed 1).  Integer addition is exact
-//    and associative, so a mailbox holds the exact sum of its messages in any
-//    arrival order; the vertex update runs in binary64 and only the final
-//    result is rounded to binary32.
-//  * binary32: float messages combined with hardware float atomics (rounding
-//    at every combination, in arrival order).
-constexpr double kFxScale = 4611686018427387904.0;  // 2^62
-constexpr double kFxInv = 1.0 / 4611686018427387904.0;
+// Three forms of the sum combiner (message type M, mailbox type S):
+//  * fixed point (default, M = S = uint64 multiples of 2^-62): integer
+//    addition is exact and associative, so a mailbox holds the exact sum of
+//    its messages in any arrival order; the vertex update runs in binary64
+//    and only the final result is rounded to binary32;
+//  * binary32 messages, fixed-point sums (M = float, S = uint64): each
+//    message rounded once to binary32, then summed exactly as above (half
+//    the message bytes, still order-independent);
+//  * binary32 (M = S = float): float messages combined with hardware float
+//    atomics (rounding at every combination, in arrival order).
 
-template <class V>
-__device__ __forceinline__ void sum_combine(V* __restrict__ mb, int32_t d, V msg);
+template <class S>
+__device__ __forceinline__ void sum_combine(S* __restrict__ mb, int32_t d, S x);
 template <>
-__device__ __forceinline__ void sum_combine<float>(float* __restrict__ mb, int32_t d, float msg) {
-  unsafeAtomicAdd(&mb[d], msg);
+__device__ __forceinline__ void sum_combine<float>(float* __restrict__ mb, int32_t d, float x) {
+  unsafeAtomicAdd(&mb[d], x);
 }
 template <>
 __device__ __forceinline__ void sum_combine<unsigned long long>(unsigned long long* __restrict__ mb, int32_t d,
-                                                                unsigned long long msg) {
-  atomicAdd(&mb[d], msg);
+                                                                unsigned long long x) {
+  atomicAdd(&mb[d], x);
 }
 
-// The message a vertex with out-degree `deg` and rank r sends on each edge.
-template <class V>
-__device__ __forceinline__ V rank_message(double r, int64_t deg);
-template <>
-__device__ __forceinline__ float rank_message<float>(double r, int64_t deg) {
-  return deg > 0 ? (float)r / (float)deg : 0.0f;
-}
-template <>
-__device__ __forceinline__ unsigned long long rank_message<unsigned long long>(double r, int64_t deg) {
-  return deg > 0 ? __double2ull_rn(r / (double)deg * kFxScale) : 0ull;
-}
-
-template <class OffT, class V>
+template <class OffT, class M, class S>
 __global__ __launch_bounds__(kWG) void k_pr_init(const OffT* __restrict__ off, int64_t n, double r0, int64_t source,
-                                                 V* __restrict__ contrib, V* __restrict__ mb,
+                                                 M* __restrict__ contrib, S* __restrict__ mb,
                                                  float* __restrict__ out_if_t0) {
   const int64_t v = gid();
   if (v >= n) return;
@@ -123,29 +111,29 @@ __global__ __launch_bounds__(kWG) void k_pr_init(const OffT* __restrict__ off, i
     return;
   }
   const int64_t deg = (int64_t)off[v + 1] - (int64_t)off[v];
-  contrib[v] = rank_message<V>(r, deg);
-  mb[v] = V(0);
+  contrib[v] = rank_msg<M, S>(r, deg);
+  mb[v] = S(0);
 }
 
 // Vertex-per-thread broadcast: thread v sends contrib[v] along its out-edges.
-template <class OffT, class V>
+template <class OffT, class M, class S>
 __global__ __launch_bounds__(kWG) void k_pr_scatter_vertex(const OffT* __restrict__ off,
                                                            const int32_t* __restrict__ dst, int64_t n,
-                                                           const V* __restrict__ contrib, V* __restrict__ mb) {
+                                                           const M* __restrict__ contrib, S* __restrict__ mb) {
   const int64_t v = gid();
   if (v >= n) return;
-  const V c = contrib[v];
-  if (c == V(0)) return;  // adding zero changes no sum (PPR vertices the walk has not reached)
+  const S c = msg_to_sum<M, S>(contrib[v]);
+  if (c == S(0)) return;  // adding zero changes no sum (PPR vertices the walk has not reached)
   const int64_t e1 = (int64_t)off[v + 1];
-  for (int64_t e = (int64_t)off[v]; e < e1; ++e) sum_combine<V>(mb, dst[e], c);
+  for (int64_t e = (int64_t)off[v]; e < e1; ++e) sum_combine<S>(mb, dst[e], c);
 }
 
 // Merge-path broadcast: workgroup t owns merged positions [t*tile, (t+1)*tile).
-template <class OffT, class V>
+template <class OffT, class M, class S>
 __global__ __launch_bounds__(kWG) void k_pr_scatter_mp(const OffT* __restrict__ off, const int32_t* __restrict__ dst,
                                                        int64_t n, int64_t m, const int32_t* __restrict__ tile_v,
-                                                       int64_t tile, const V* __restrict__ contrib,
-                                                       V* __restrict__ mb) {
+                                                       int64_t tile, const M* __restrict__ contrib,
+                                                       S* __restrict__ mb) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t t = blockIdx.x;
   const int64_t k0 = t * tile;
@@ -155,10 +143,10 @@ __global__ __launch_bounds__(kWG) void k_pr_scatter_mp(const OffT* __restrict__ 
   if (j1 <= j0) return;  // only vertex-ends in this tile (uniform over the workgroup)
   const int64_t ilast = i1 < n ? i1 : n - 1;
   const int cnt = (int)(ilast - i0 + 1);  // vertices i0..ilast own the tile's edges
-  V* s_val = reinterpret_cast<V*>(smem);                                         // tile + 1
-  OffT* s_off = reinterpret_cast<OffT*>(smem + align16((tile + 1) * sizeof(V)));  // tile + 2
+  S* s_val = reinterpret_cast<S*>(smem);                                         // tile + 1
+  OffT* s_off = reinterpret_cast<OffT*>(smem + align16((tile + 1) * sizeof(S)));  // tile + 2
   for (int x = threadIdx.x; x <= cnt; x += kWG) s_off[x] = off[i0 + x];
-  for (int x = threadIdx.x; x < cnt; x += kWG) s_val[x] = contrib[i0 + x];
+  for (int x = threadIdx.x; x < cnt; x += kWG) s_val[x] = msg_to_sum<M, S>(contrib[i0 + x]);
   __syncthreads();
   for (int64_t e = j0 + threadIdx.x; e < j1; e += kWG) {
     int lo = 0, hi = cnt - 1;  // owner = last x with s_off[x] <= e
@@ -169,23 +157,23 @@ __global__ __launch_bounds__(kWG) void k_pr_scatter_mp(const OffT* __restrict__ 
       else
         hi = mid - 1;
     }
-    const V c = s_val[lo];
+    const S c = s_val[lo];
     const int32_t d = dst[e];
-    if (c != V(0)) sum_combine<V>(mb, d, c);
+    if (c != S(0)) sum_combine<S>(mb, d, c);
   }
 }
 
 // rank = teleport + d * (sum of messages); reset the mailbox; next message.
-template <class OffT, class V>
+template <class OffT, class M, class S>
 __global__ __launch_bounds__(kWG) void k_pr_apply(const OffT* __restrict__ off, int64_t n, double teleport,
-                                                  double damping, int64_t source, V* __restrict__ mb,
-                                                  V* __restrict__ contrib, float* __restrict__ out, int last) {
+                                                  double damping, int64_t source, S* __restrict__ mb,
+                                                  M* __restrict__ contrib, float* __restrict__ out, int last) {
   const int64_t v = gid();
   if (v >= n) return;
   const double tele = source >= 0 ? (v == source ? teleport : 0.0) : teleport;
   double r;
-  if constexpr (sizeof(V) == 8) {
-    r = fma(damping, (double)mb[v] * kFxInv, tele);
+  if constexpr (sizeof(S) == 8) {
+    r = fma(damping, (double)mb[v] * kFixInv, tele);
   } else {
     r = (double)fmaf((float)damping, mb[v], (float)tele);
   }
@@ -193,9 +181,9 @@ __global__ __launch_bounds__(kWG) void k_pr_apply(const OffT* __restrict__ off, 
     out[v] = (float)r;
     return;
   }
-  mb[v] = V(0);
+  mb[v] = S(0);
   const int64_t deg = (int64_t)off[v + 1] - (int64_t)off[v];
-  contrib[v] = rank_message<V>(r, deg);
+  contrib[v] = rank_msg<M, S>(r, deg);
 }
 
 // ------------------------------------------------------------------ CC / SSSP
@@ -490,83 +478,91 @@ hipError_t launch_mp_partition(const void* P, bool p64, int64_t items, int64_t t
 }
 
 namespace {
-template <class V>
+template <class M, class S>
 hipError_t pr_launch_all(int what, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
                          const int32_t* tile_v, int64_t tile, int64_t ntiles, double a, double b, int64_t source,
                          void* contrib, void* mb, float* out, bool last, hipStream_t s) {
-  V* c = static_cast<V*>(contrib);
-  V* mbx = static_cast<V*>(mb);
+  M* c = static_cast<M*>(contrib);
+  S* mbx = static_cast<S*>(mb);
   switch (what) {
     case 0:  // init; a = r0
       if (off64)
-        hipLaunchKernelGGL((k_pr_init<int64_t, V>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int64_t*)off, n, a,
+        hipLaunchKernelGGL((k_pr_init<int64_t, M, S>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int64_t*)off, n, a,
                            source, c, mbx, out);
       else
-        hipLaunchKernelGGL((k_pr_init<int32_t, V>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int32_t*)off, n, a,
+        hipLaunchKernelGGL((k_pr_init<int32_t, M, S>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int32_t*)off, n, a,
                            source, c, mbx, out);
       break;
     case 1:  // vertex-per-thread broadcast
       if (off64)
-        hipLaunchKernelGGL((k_pr_scatter_vertex<int64_t, V>), dim3(grid_for(n)), dim3(kWG), 0, s,
+        hipLaunchKernelGGL((k_pr_scatter_vertex<int64_t, M, S>), dim3(grid_for(n)), dim3(kWG), 0, s,
                            (const int64_t*)off, dst, n, c, mbx);
       else
-        hipLaunchKernelGGL((k_pr_scatter_vertex<int32_t, V>), dim3(grid_for(n)), dim3(kWG), 0, s,
+        hipLaunchKernelGGL((k_pr_scatter_vertex<int32_t, M, S>), dim3(grid_for(n)), dim3(kWG), 0, s,
                            (const int32_t*)off, dst, n, c, mbx);
       break;
     case 2: {  // merge-path broadcast
-      const size_t lds = align16((size_t)(tile + 1) * sizeof(V)) + (size_t)(tile + 2) * (off64 ? 8 : 4);
+      const size_t lds = align16((size_t)(tile + 1) * sizeof(S)) + (size_t)(tile + 2) * (off64 ? 8 : 4);
       if (off64)
-        hipLaunchKernelGGL((k_pr_scatter_mp<int64_t, V>), dim3((unsigned)ntiles), dim3(kWG), lds, s,
+        hipLaunchKernelGGL((k_pr_scatter_mp<int64_t, M, S>), dim3((unsigned)ntiles), dim3(kWG), lds, s,
                            (const int64_t*)off, dst, n, m, tile_v, tile, c, mbx);
       else
-        hipLaunchKernelGGL((k_pr_scatter_mp<int32_t, V>), dim3((unsigned)ntiles), dim3(kWG), lds, s,
+        hipLaunchKernelGGL((k_pr_scatter_mp<int32_t, M, S>), dim3((unsigned)ntiles), dim3(kWG), lds, s,
                            (const int32_t*)off, dst, n, m, tile_v, tile, c, mbx);
       break;
     }
     default:  // apply; a = teleport, b = damping
       if (off64)
-        hipLaunchKernelGGL((k_pr_apply<int64_t, V>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int64_t*)off, n, a,
-                           b, source, mbx, c, out, (int)last);
+        hipLaunchKernelGGL((k_pr_apply<int64_t, M, S>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int64_t*)off, n,
+                           a, b, source, mbx, c, out, (int)last);
       else
-        hipLaunchKernelGGL((k_pr_apply<int32_t, V>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int32_t*)off, n, a,
-                           b, source, mbx, c, out, (int)last);
+        hipLaunchKernelGGL((k_pr_apply<int32_t, M, S>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int32_t*)off, n,
+                           a, b, source, mbx, c, out, (int)last);
   }
   return hipGetLastError();
 }
 
-inline hipError_t pr_launch(bool fx, int what, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
+inline hipError_t pr_launch(int mode, int what, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
                             const int32_t* tile_v, int64_t tile, int64_t ntiles, double a, double b, int64_t source,
                             void* contrib, void* mb, float* out, bool last, hipStream_t s) {
-  return fx ? pr_launch_all<unsigned long long>(what, off, off64, dst, n, m, tile_v, tile, ntiles, a, b, source,
-                                                contrib, mb, out, last, s)
-            : pr_launch_all<float>(what, off, off64, dst, n, m, tile_v, tile, ntiles, a, b, source, contrib, mb, out,
-                                   last, s);
+  switch (mode) {
+    case kRankFixed:
+      return pr_launch_all<unsigned long long, unsigned long long>(what, off, off64, dst, n, m, tile_v, tile, ntiles,
+                                                                   a, b, source, contrib, mb, out, last, s);
+    case kRankF32Msg:
+      return pr_launch_all<float, unsigned long long>(what, off, off64, dst, n, m, tile_v, tile, ntiles, a, b, source,
+                                                      contrib, mb, out, last, s);
+    case kRankF32:
+      return pr_launch_all<float, float>(what, off, off64, dst, n, m, tile_v, tile, ntiles, a, b, source, contrib, mb,
+                                         out, last, s);
+  }
+  return hipErrorInvalidValue;
 }
 }  // namespace
 
-hipError_t launch_pr_init(bool fx, const void* off, bool off64, int64_t n, double r0, int64_t source, void* contrib,
+hipError_t launch_pr_init(int mode, const void* off, bool off64, int64_t n, double r0, int64_t source, void* contrib,
                           void* mb, float* out_if_t0, hipStream_t s) {
-  return pr_launch(fx, 0, off, off64, nullptr, n, 0, nullptr, 0, 0, r0, 0, source, contrib, mb, out_if_t0, false, s);
+  return pr_launch(mode, 0, off, off64, nullptr, n, 0, nullptr, 0, 0, r0, 0, source, contrib, mb, out_if_t0, false, s);
 }
 
-hipError_t launch_pr_scatter_vertex(bool fx, const void* off, bool off64, const int32_t* dst, int64_t n,
+hipError_t launch_pr_scatter_vertex(int mode, const void* off, bool off64, const int32_t* dst, int64_t n,
                                     const void* contrib, void* mb, hipStream_t s) {
-  return pr_launch(fx, 1, off, off64, dst, n, 0, nullptr, 0, 0, 0, 0, -1, const_cast<void*>(contrib), mb, nullptr,
+  return pr_launch(mode, 1, off, off64, dst, n, 0, nullptr, 0, 0, 0, 0, -1, const_cast<void*>(contrib), mb, nullptr,
                    false, s);
 }
 
-hipError_t launch_pr_scatter_mp(bool fx, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
+hipError_t launch_pr_scatter_mp(int mode, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
                                 const int32_t* tile_v, int64_t tile, int64_t ntiles, const void* contrib, void* mb,
                                 hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  return pr_launch(fx, 2, off, off64, dst, n, m, tile_v, tile, ntiles, 0, 0, -1, const_cast<void*>(contrib), mb,
+  return pr_launch(mode, 2, off, off64, dst, n, m, tile_v, tile, ntiles, 0, 0, -1, const_cast<void*>(contrib), mb,
                    nullptr, false, s);
 }
 
-hipError_t launch_pr_apply(bool fx, const void* off, bool off64, int64_t n, double teleport, double damping,
+hipError_t launch_pr_apply(int mode, const void* off, bool off64, int64_t n, double teleport, double damping,
                            int64_t source, void* mb, void* contrib, float* out, bool last, hipStream_t s) {
-  return pr_launch(fx, 3, off, off64, nullptr, n, 0, nullptr, 0, 0, teleport, damping, source, contrib, mb, out, last,
-                   s);
+  return pr_launch(mode, 3, off, off64, nullptr, n, 0, nullptr, 0, 0, teleport, damping, source, contrib, mb, out,
+                   last, s);
 }
 
 hipError_t launch_min_init(int kind, int64_t n, int64_t source, const int32_t* ids, uint2* vm, hipStream_t s) {

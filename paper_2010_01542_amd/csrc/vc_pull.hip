@@ -132,10 +132,10 @@ __device__ __forceinline__ void global_add<unsigned long long>(unsigned long lon
 // every mailbox at zero).  Tiles hold kWG * VT items, so a thread's run is at
 // most VT in-edges: all of its source ids are loaded first, then all of its
 // gathers are issued back to back, and only then combined.
-template <class V, int VT>
+template <class M, class V, int VT>
 __global__ __launch_bounds__(kWG) void k_pr_pull(const int64_t* __restrict__ in_off, const int32_t* __restrict__ in_src,
                                                  int64_t n, int64_t m, const int32_t* __restrict__ tile_v,
-                                                 const V* __restrict__ contrib, V* __restrict__ mb) {
+                                                 const M* __restrict__ contrib, V* __restrict__ mb) {
   constexpr int64_t tile = (int64_t)kWG * VT;
   extern __shared__ __align__(16) unsigned char smem[];
   Tile tl;
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kWG) void k_pr_pull(const int64_t* __restrict__ in_
   for (int k = 0; k < VT; ++k) src[k] = k < run_len ? __builtin_nontemporal_load(&in_src[e0 + k]) : 0;
   V c[VT];
 #pragma unroll
-  for (int k = 0; k < VT; ++k) c[k] = k < run_len ? contrib[src[k]] : V(0);
+  for (int k = 0; k < VT; ++k) c[k] = k < run_len ? msg_to_sum<M, V>(contrib[src[k]]) : V(0);
   __syncthreads();
   if (run_len > 0) {
     int x = owner_of(s_off, tl.cnt, e0);
@@ -336,13 +336,23 @@ hipError_t launch_csc_fill(const void* off, bool off64, const int32_t* dst, cons
 }
 
 namespace {
-template <class V, int VT>
+template <class M, class V, int VT>
 void pr_pull_launch(const int64_t* in_off, const int32_t* in_src, int64_t n, int64_t m, const int32_t* tile_v,
                     int64_t ntiles, const void* contrib, void* mb, hipStream_t s) {
   const int64_t tile = (int64_t)kWG * VT;
   const size_t lds = align16((size_t)(tile + 1) * sizeof(V)) + (size_t)(tile + 2) * 8;
-  hipLaunchKernelGGL((k_pr_pull<V, VT>), dim3((unsigned)ntiles), dim3(kWG), lds, s, in_off, in_src, n, m, tile_v,
-                     (const V*)contrib, (V*)mb);
+  hipLaunchKernelGGL((k_pr_pull<M, V, VT>), dim3((unsigned)ntiles), dim3(kWG), lds, s, in_off, in_src, n, m, tile_v,
+                     (const M*)contrib, (V*)mb);
+}
+template <class M, class V>
+void pr_pull_vt(int64_t tile, const int64_t* in_off, const int32_t* in_src, int64_t n, int64_t m,
+                const int32_t* tile_v, int64_t ntiles, const void* contrib, void* mb, hipStream_t s) {
+  if (tile == kWG * 4)
+    pr_pull_launch<M, V, 4>(in_off, in_src, n, m, tile_v, ntiles, contrib, mb, s);
+  else if (tile == kWG * 8)
+    pr_pull_launch<M, V, 8>(in_off, in_src, n, m, tile_v, ntiles, contrib, mb, s);
+  else
+    pr_pull_launch<M, V, 16>(in_off, in_src, n, m, tile_v, ntiles, contrib, mb, s);
 }
 template <int KIND, int VT>
 void min_pull_launch(bool check, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w, int64_t n,
@@ -370,19 +380,17 @@ void min_pull_vt(int64_t tile, bool check, const int64_t* in_off, const int32_t*
 }
 }  // namespace
 
-hipError_t launch_pr_pull(bool fx, const int64_t* in_off, const int32_t* in_src, int64_t n, int64_t m,
+hipError_t launch_pr_pull(int mode, const int64_t* in_off, const int32_t* in_src, int64_t n, int64_t m,
                           const int32_t* tile_v, int64_t tile, int64_t ntiles, const void* contrib, void* mb,
                           hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (tile != pull_tile(tile)) return hipErrorInvalidValue;
-  if (fx) {
-    if (tile == kWG * 4) pr_pull_launch<unsigned long long, 4>(in_off, in_src, n, m, tile_v, ntiles, contrib, mb, s);
-    else if (tile == kWG * 8) pr_pull_launch<unsigned long long, 8>(in_off, in_src, n, m, tile_v, ntiles, contrib, mb, s);
-    else pr_pull_launch<unsigned long long, 16>(in_off, in_src, n, m, tile_v, ntiles, contrib, mb, s);
-  } else {
-    if (tile == kWG * 4) pr_pull_launch<float, 4>(in_off, in_src, n, m, tile_v, ntiles, contrib, mb, s);
-    else if (tile == kWG * 8) pr_pull_launch<float, 8>(in_off, in_src, n, m, tile_v, ntiles, contrib, mb, s);
-    else pr_pull_launch<float, 16>(in_off, in_src, n, m, tile_v, ntiles, contrib, mb, s);
+  using U64 = unsigned long long;
+  switch (mode) {
+    case kRankFixed: pr_pull_vt<U64, U64>(tile, in_off, in_src, n, m, tile_v, ntiles, contrib, mb, s); break;
+    case kRankF32Msg: pr_pull_vt<float, U64>(tile, in_off, in_src, n, m, tile_v, ntiles, contrib, mb, s); break;
+    case kRankF32: pr_pull_vt<float, float>(tile, in_off, in_src, n, m, tile_v, ntiles, contrib, mb, s); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

@@ -721,7 +721,7 @@ bool lane_is_faster(vc_server s, const GraphEntry& ge, const vc_request& r) {
 bool lane_eligible(const GraphEntry& ge, const vc_request& r, bool rank) {
   if (rank)
     return ge.ranks && (r.program == VC_PAGERANK || r.program == VC_PPR) && r.params.max_supersteps > 0 &&
-           !(r.params.options & VC_OPT_F32_ACCUMULATE);
+           !(r.params.options & (VC_OPT_F32_ACCUMULATE | VC_OPT_F32_MESSAGES));
   return ge.lanes && (r.program == VC_CC_HASHMIN || r.program == VC_SSSP);
 }
 

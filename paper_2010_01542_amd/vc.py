@@ -25,6 +25,7 @@ SCHEDULES = {"auto": SCHED_AUTO, "vertex": SCHED_VERTEX, "edge": SCHED_EDGE, "pu
 IDX_I32, IDX_I64 = 0, 1
 GRAPH_BORROW, GRAPH_VALIDATE, GRAPH_SYMMETRIC, GRAPH_NO_RELABEL = 1, 2, 4, 8
 OPT_NO_HUB_AGGREGATION, OPT_NO_TEST_BEFORE_ATOMIC, OPT_F32_ACCUMULATE, OPT_GRAPH_CAPTURE = 1, 2, 4, 8
+OPT_F32_MESSAGES = 16
 UNREACHED = 0xFFFFFFFF
 ROUTE_AUTO, ROUTE_LANES, ROUTE_WORKER = 0, 1, 2
 COMBINERS = {"sum_u64": 0, "prod_u64": 1, "max_f64": 2, "minarg": 3, "sum_f64": 4}

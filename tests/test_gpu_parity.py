@@ -195,6 +195,36 @@ def test_blocked_pagerank_matches_oracle_and_pull(device, relabel):
         check_rank(c, make(c, relabel=relabel), "pagerank", T=3, schedule="blocked")
 
 
+@pytest.mark.parametrize("relabel", [True, False])
+def test_f32_messages_meet_tolerance_and_agree_across_schedules(device, relabel):
+    """Binary32 messages summed exactly in fixed point: within the PageRank
+    bars of the oracle, and one result for every schedule (each message is
+    rounded once, then the sum is exact in any order), captured or not."""
+    from paper_2010_01542_amd import vc
+    print(f"case f32 messages s19 relabel={relabel}", flush=True)
+    d = rmatgen.rmat(19, 12, seed=8)
+    g = make(d, relabel=relabel)
+    opt = vc.OPT_F32_MESSAGES
+    outs = [check_rank(d, g, "pagerank", T=6, schedule=s, options=opt)[0]
+            for s in ("vertex", "edge", "pull", "blocked", "auto")]
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+    cap = run_gpu(g, "pagerank", T=6, schedule="blocked", options=opt | vc.OPT_GRAPH_CAPTURE)[0]
+    assert np.array_equal(outs[0], cap)
+    ppr = [check_rank(d, g, "ppr", T=6, source=0, schedule=s, options=opt)[0] for s in ("pull", "blocked")]
+    assert np.array_equal(ppr[0], ppr[1])
+    # the one extra rounding per message moves ranks by far less than the bars
+    fixed = run_gpu(g, "pagerank", T=6)[0].astype(np.float64)
+    assert np.abs(outs[0] - fixed).max() <= 4 * np.spacing(np.float32(fixed.max()))
+
+
+def test_f32_options_exclude_each_other(device):
+    from paper_2010_01542_amd import VcError, vc
+    g = make(rmatgen.cycle(8))
+    with pytest.raises(VcError):
+        g.run("pagerank", options=vc.OPT_F32_MESSAGES | vc.OPT_F32_ACCUMULATE)
+
+
 def test_blocked_schedule_rejects_min_programs_and_f32(device):
     from paper_2010_01542_amd import VcError, vc
     g = make(rmatgen.path(8, directed=True))

@@ -77,22 +77,32 @@ def test_s26_pagerank_t3_against_oracle(s26):
 
 
 def test_s26_blocked_pagerank_equals_pull(s26):
+    """The blocked form (AUTO's choice at this size) against the pull form,
+    bit for bit, with uint64 and with binary32 messages; binary32 messages
+    against the oracle."""
+    from paper_2010_01542_amd import vc
     csr, g = s26
-    print("case sssp-s26 pagerank T=3 blocked vs oracle, T=20 blocked vs pull", flush=True)
-    check_rank(csr, g, "pagerank", T=3, schedule="blocked")
-    a = run_gpu(g, "pagerank", T=20, schedule="blocked")[0]
-    b = run_gpu(g, "pagerank", T=20, schedule="pull")[0]
-    assert np.array_equal(a, b)
+    print("case sssp-s26 pagerank T=3 f32 messages vs oracle, T=20 blocked vs pull", flush=True)
+    check_rank(csr, g, "pagerank", T=3, schedule="blocked", options=vc.OPT_F32_MESSAGES)
+    for opt in (0, vc.OPT_F32_MESSAGES):
+        a = run_gpu(g, "pagerank", T=20, schedule="blocked", options=opt)[0]
+        b = run_gpu(g, "pagerank", T=20, schedule="pull", options=opt)[0]
+        assert np.array_equal(a, b), opt
 
 
-def test_s26_pagerank_t20_last_update(s26):
+@pytest.mark.parametrize("f32_messages", [False, True])
+def test_s26_pagerank_t20_last_update(s26, f32_messages):
     """r(20) = (1-d)/N + d * A^T D^-1 r(19), recomputed in binary64 from the
-    device's own r(19), for every vertex; plus the dangling-mass invariant."""
+    device's own r(19), for every vertex; plus the dangling-mass invariant.
+    With binary32 messages each message carries one more rounding (relative
+    2^-24), which stays inside the same bound."""
+    from paper_2010_01542_amd import vc
     csr, g = s26
-    print("case sssp-s26 pagerank T=20 last-update check", flush=True)
+    opt = vc.OPT_F32_MESSAGES if f32_messages else 0
+    print(f"case sssp-s26 pagerank T=20 last-update check options={opt}", flush=True)
     d = 0.85
-    r19 = run_gpu(g, "pagerank", T=19)[0].astype(np.float64)
-    r20 = run_gpu(g, "pagerank", T=20)[0].astype(np.float64)
+    r19 = run_gpu(g, "pagerank", T=19, options=opt)[0].astype(np.float64)
+    r20 = run_gpu(g, "pagerank", T=20, options=opt)[0].astype(np.float64)
     deg = csr.outdeg
     contrib = np.where(deg > 0, r19 / np.maximum(deg, 1), 0.0)
     acc = np.zeros(csr.n)
