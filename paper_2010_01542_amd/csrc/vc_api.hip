@@ -324,8 +324,9 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
   VC_TRY(vc::launch_pb_build(true, te_d.as<int64_t>(), tiles, g->dst, m, chunk, bins, pass_bins,
                              cnt.as<unsigned long long>(), srcl_csr, g->pb_srcl.as<uint16_t>(),
                              g->pb_dstl.as<uint16_t>(), s));
-  // run tables (non-empty buckets per bin) and fold items: about 4096 items
-  // in all, 4 Ki to 64 Ki edges each
+  // run tables (non-empty buckets per bin) and fold items: at least about
+  // 4096 items in all, at most 64 Ki edges each (a bin of fewer edges is one
+  // item and stores its mailboxes instead of adding them)
   const int64_t fcap = std::min<int64_t>(65536, std::max<int64_t>(4096, m / 4096));
   VC_TRY(nitems.ensure((size_t)(bins + 1) * 8));
   VC_TRY(g->pb_run_off.ensure((size_t)(bins + 1) * 8));
@@ -347,8 +348,10 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
   VC_TRY(vc::launch_pb_fold_items(g->pb_run_off.as<int64_t>(), g->pb_rpre.as<int64_t>(), g->pb_btotal.as<int64_t>(),
                                   bins, fcap, nitems.as<int64_t>(), g->pb_fold.as<vc::PbFoldItem>(), s));
   // spread items: a tile's slots are contiguous; pieces of up to scap slots
-  // (the tile's messages are loaded once per piece)
-  const int64_t scap = std::min<int64_t>(1 << 18, std::max<int64_t>(1 << 14, m / 1024));
+  // (the tile's messages are loaded once per piece; 64 Ki slots balance
+  // that load against the spread of work over the compute units best at
+  // scale 26)
+  const int64_t scap = std::min<int64_t>(1 << 16, std::max<int64_t>(1 << 14, m / 1024));
   std::vector<vc::PbSpreadItem> sitems;
   for (int64_t t = 0; t < tiles; ++t) {
     const int64_t k0 = te[(size_t)t], k1 = te[(size_t)t + 1];

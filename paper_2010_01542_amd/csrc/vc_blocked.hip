@@ -177,8 +177,9 @@ __global__ __launch_bounds__(kWG) void k_pb_tables(const int64_t* __restrict__ s
   }
 }
 
-// Per bin b (one thread): its fold items, positions [i fcap, (i+1) fcap),
-// with the runs [r0, r1) (indices in the bin's run list) they touch.
+// Per bin b (one thread): its fold items, count = ceil(total / fcap) equal
+// shares of the bin's positions, with the runs [r0, r1) (indices in the
+// bin's run list) they touch.
 __global__ __launch_bounds__(kWG) void k_pb_fold_items(const int64_t* __restrict__ run_off,
                                                        const int64_t* __restrict__ rpre,
                                                        const int64_t* __restrict__ btotal, int64_t bins,
@@ -192,9 +193,9 @@ __global__ __launch_bounds__(kWG) void k_pb_fold_items(const int64_t* __restrict
   const int64_t first = item_off[b], count = item_off[b + 1] - item_off[b];
   auto start = [&](int64_t r) { return r < nr ? P[r] : total; };
   int64_t r = 0;  // run holding position v: last r with start(r) <= v (v < total, so r < nr)
-  for (int64_t i = 0; i < count; ++i) {
-    const int64_t v0 = i * fcap;
-    const int64_t v1 = (v0 + fcap < total) ? v0 + fcap : total;
+  for (int64_t i = 0; i < count; ++i) {  // equal shares of the bin's positions
+    const int64_t v0 = total / count * i + (total % count) * i / count;
+    const int64_t v1 = total / count * (i + 1) + (total % count) * (i + 1) / count;
     while (start(r + 1) <= v0) ++r;
     int64_t r1 = r;
     while (start(r1 + 1) <= v1 - 1) ++r1;
