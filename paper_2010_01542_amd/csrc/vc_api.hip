@@ -254,12 +254,12 @@ bool pb_supported(vc_graph g) {
   return shift != 0 && vc::pb_bins(g->n) * vc::pb_tiles(g->n, shift) <= vc::kPbMaxBuckets;
 }
 
-size_t pb_layout_bytes(vc_graph g) {
+size_t pb_layout_bytes(vc_graph g) {  // the shared, read-only part
   const int shift = vc::pb_src_shift(g->max_lds);
   if (shift == 0) return 0;
   const size_t bins = (size_t)vc::pb_bins(g->n), tiles = (size_t)vc::pb_tiles(g->n, shift), m = (size_t)g->m;
   const size_t runs = std::min(bins * tiles, m);  // non-empty buckets
-  return m * 12 + runs * 16 + (bins + 1) * 16 + (m / 4096 + bins + 2) * sizeof(vc::PbFoldItem) +
+  return m * 4 + runs * 16 + (bins + 1) * 16 + (m / 4096 + bins + 2) * sizeof(vc::PbFoldItem) +
          (m / 16384 + tiles + 2) * sizeof(vc::PbSpreadItem);
 }
 
@@ -268,11 +268,10 @@ size_t pb_layout_bytes(vc_graph g) {
 // array no longer stays in the caches and the pull form's gathers go to
 // HBM (on R-MAT graphs the two forms meet near 2^20 vertices, and the
 // blocked layout builds faster than the transpose), and the pull form
-// otherwise.  Views keep the pull form: they would each build a layout of
-// their own.
+// otherwise.
 int rank_schedule(vc_graph g, const vc_params& p, bool fx) {
   if (p.schedule != VC_SCHED_AUTO) return p.schedule;
-  if (fx && !g->is_view && g->n >= (1 << 20) && g->m > 0 && pb_supported(g)) return VC_SCHED_BLOCKED;
+  if (fx && g->n >= (1 << 20) && g->m > 0 && pb_supported(g)) return VC_SCHED_BLOCKED;
   return VC_SCHED_PULL;
 }
 
@@ -285,7 +284,8 @@ int rank_schedule(vc_graph g, const vc_params& p, bool fx) {
 // spreads over many workgroups).  The spread items (each tile's slot range
 // cut into pieces) are made on the host from the tile starts.
 vc_status ensure_pb(vc_graph g, hipStream_t s) {
-  if (g->pb_ready) return VC_OK;
+  if (g->pb.ready) return VC_OK;
+  if (g->is_view) return fail(VC_ERR_INVALID_ARG, "a view cannot build the blocked layout");
   const int64_t n = g->n, m = g->m;
   const int shift = vc::pb_src_shift(g->max_lds);
   if (shift == 0) return fail(VC_ERR_UNSUPPORTED, "the blocked schedule needs 8 KiB of LDS per workgroup");
@@ -308,8 +308,9 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
       return fail(VC_ERR_UNSUPPORTED, "the blocked schedule needs fewer than 2^32 out-edges per source tile");
   VC_TRY(g->pb_srcl.ensure((size_t)m * 2 + 4));
   VC_TRY(g->pb_dstl.ensure((size_t)m * 2 + 4));
-  VC_TRY(g->pb_vals.ensure((size_t)m * 8 + 8));
-  uint16_t* srcl_csr = g->pb_vals.as<uint16_t>();  // the message slots are free until the first superstep
+  DevBuf srcl_tmp;
+  VC_TRY(srcl_tmp.ensure((size_t)m * 2 + 4));
+  uint16_t* srcl_csr = srcl_tmp.as<uint16_t>();
   VC_TRY(vc::launch_pb_expand(g->off, g->off64, n, m, g->dense_tiles_p, tile, g->dense_ntiles, shift, srcl_csr, s));
   VC_TRY(cnt.ensure((size_t)(nb + 1) * 8));
   VC_TRY(blocks.ensure((size_t)vc::scan_scratch_entries(std::max(nb, bins)) * 8));
@@ -362,22 +363,46 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
     VC_TRY(hipMemcpyAsync(g->pb_spread.p, sitems.data(), sitems.size() * sizeof(vc::PbSpreadItem),
                           hipMemcpyHostToDevice, s));
   VC_TRY(hipStreamSynchronize(s));
-  g->pb_shift = shift;
-  g->pb_tiles = tiles;
-  g->pb_nspread = (int64_t)sitems.size();
-  g->pb_nfold = nfold;
-  g->pb_ready = true;
+  vc::PbShared& pb = g->pb;
+  pb.srcl = g->pb_srcl.as<uint16_t>();
+  pb.dstl = g->pb_dstl.as<uint16_t>();
+  pb.run_off = g->pb_run_off.as<int64_t>();
+  pb.btotal = g->pb_btotal.as<int64_t>();
+  pb.rpre = g->pb_rpre.as<int64_t>();
+  pb.rbase = g->pb_rbase.as<int64_t>();
+  pb.spread = g->pb_spread.as<vc::PbSpreadItem>();
+  pb.fold = g->pb_fold.as<vc::PbFoldItem>();
+  pb.shift = shift;
+  pb.tiles = tiles;
+  pb.nspread = (int64_t)sitems.size();
+  pb.nfold = nfold;
+  pb.ready = true;
+  return VC_OK;
+}
+
+// The blocked layout for a run on g: a graph builds its own on first use; a
+// view takes its base's, building it there first if no view has (under the
+// base's lock, on the view's stream, synchronised).  Each object owns its
+// message slots.
+vc_status use_pb(vc_graph g, hipStream_t s) {
+  if (!g->pb.ready) {
+    vc_graph owner = g->is_view ? g->base : g;
+    std::lock_guard<std::mutex> lock(owner->pb_mu);
+    vc_status st = ensure_pb(owner, s);
+    if (st != VC_OK) return st;
+    g->pb = owner->pb;
+  }
+  VC_TRY(g->pb_vals.ensure((size_t)g->m * 8 + 8));
   return VC_OK;
 }
 
 // One broadcast + combine of the blocked schedule: spread, then fold.
 hipError_t pb_superstep(vc_graph g, bool f32msg, const void* contrib, void* mb, hipStream_t s) {
-  hipError_t e = vc::launch_pb_spread(f32msg, g->pb_spread.as<vc::PbSpreadItem>(), g->pb_nspread, g->n, g->pb_shift,
-                                      g->pb_srcl.as<uint16_t>(), contrib, g->pb_vals.p, s);
+  const vc::PbShared& pb = g->pb;
+  hipError_t e = vc::launch_pb_spread(f32msg, pb.spread, pb.nspread, g->n, pb.shift, pb.srcl, contrib, g->pb_vals.p, s);
   if (e != hipSuccess) return e;
-  return vc::launch_pb_fold(f32msg, g->pb_fold.as<vc::PbFoldItem>(), g->pb_nfold, g->pb_run_off.as<int64_t>(),
-                            g->pb_btotal.as<int64_t>(), g->pb_rpre.as<int64_t>(), g->pb_rbase.as<int64_t>(), g->n,
-                            g->pb_vals.p, g->pb_dstl.as<uint16_t>(), static_cast<unsigned long long*>(mb), s);
+  return vc::launch_pb_fold(f32msg, pb.fold, pb.nfold, pb.run_off, pb.btotal, pb.rpre, pb.rbase, g->n, g->pb_vals.p,
+                            pb.dstl, static_cast<unsigned long long*>(mb), s);
 }
 
 vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hipStream_t s, Recorder& rec,
@@ -425,7 +450,7 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
     } else if (sched == VC_SCHED_EDGE) {
       st = dense_partition(g, tile, s);
     } else if (sched == VC_SCHED_BLOCKED) {
-      st = ensure_pb(g, s);
+      st = use_pb(g, s);
     }
     if (st != VC_OK) return st;
   }
@@ -851,6 +876,8 @@ vc_status make_view(vc_graph base, hipStream_t s, vc_graph* out) {
   v->in_w = base->in_w;
   v->csc_ready = base->csc_ready;
   v->max_lds = base->max_lds;
+  v->base = base;
+  v->pb = base->pb;  // if built; else the view's first blocked run builds it on the base
   for (int i = 0; i < 4; ++i) {
     v->tuned[i] = base->tuned[i];
     v->tuned_params[i] = base->tuned_params[i];
@@ -1037,7 +1064,9 @@ vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held,
       vc_params_default(&dp);
       if (rank_schedule(g, dp, true) == VC_SCHED_BLOCKED) {
         csc_need = 0;  // the blocked schedule reads its own layout, not the transpose
-        pb_need = g->pb_ready ? 0 : pb_layout_bytes(g);
+        const vc_graph owner = g->is_view ? g->base : g;
+        pb_need = (owner->pb.ready ? 0 : pb_layout_bytes(g)) +
+                  (g->pb_vals.bytes >= (size_t)g->m * 8 ? 0 : (size_t)g->m * 8 + 8);
       }
     }
     *bytes_run = (want > have ? want - have : 0) + csc_need + pb_need;

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <memory>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -119,6 +120,22 @@ vc_status ms_reset(MsState& st, vc_graph g, int cs, hipStream_t s);
 vc_status ms_superstep(MsState& st, vc_graph g, int cur, int ceff, int64_t next_edges, bool force_pull,
                        const LaneMask& zero, unsigned long long* live, bool* pushed, hipStream_t s);
 
+// Read-only part of the blocked PageRank layout (see vc_blocked.hip); a
+// view copies its base's once the base has built it.
+struct PbShared {
+  const uint16_t* srcl = nullptr;
+  const uint16_t* dstl = nullptr;
+  const int64_t* run_off = nullptr;
+  const int64_t* btotal = nullptr;
+  const int64_t* rpre = nullptr;
+  const int64_t* rbase = nullptr;
+  const PbSpreadItem* spread = nullptr;
+  const PbFoldItem* fold = nullptr;
+  int64_t nspread = 0, nfold = 0, tiles = 0;
+  int shift = 0;
+  bool ready = false;
+};
+
 }  // namespace vc
 
 struct vc_graph_s {
@@ -156,13 +173,14 @@ struct vc_graph_s {
   bool csc_ready = false;
   int64_t csc_tile = 0, csc_ntiles = 0;
   vc::MsState ms;                                 // many-source SSSP
-  // propagation-blocking layout (PageRank): per edge slot its source and
-  // destination offset in its bin, bucket starts, fold items, message slots
-  // propagation-blocking layout (PageRank / PPR, built on first use)
-  vc::DevBuf pb_srcl, pb_dstl, pb_vals, pb_run_off, pb_btotal, pb_rpre, pb_rbase, pb_spread, pb_fold;
-  int64_t pb_nspread = 0, pb_nfold = 0, pb_tiles = 0;
-  int pb_shift = 0;
-  bool pb_ready = false;
+  // propagation-blocking layout (PageRank / PPR, built on first use): the
+  // read-only part in buffers owned by the base graph, referenced by `pb`
+  // in the base and in its views; each object owns its message slots
+  vc::DevBuf pb_srcl, pb_dstl, pb_run_off, pb_btotal, pb_rpre, pb_rbase, pb_spread, pb_fold;
+  vc::PbShared pb;
+  vc::DevBuf pb_vals;
+  std::mutex pb_mu;         // base: serialises the layout build between views
+  vc_graph base = nullptr;  // views: the graph they share arrays with
   vc::DevBuf ms_src;
   // captured superstep loops (HIP graphs), replayed on the caller's stream
   hipStream_t cap_stream = nullptr;

@@ -162,6 +162,33 @@ def test_mixed_programs_on_workers_and_lanes(device, route):
             assert l1 <= L1_TOL and mx <= MAX_ABS_TOL
 
 
+def test_worker_views_share_the_blocked_layout(device):
+    """PageRank / PPR on a graph of 2^20 vertices run in the blocked form;
+    worker views share the base graph's layout, built once by whichever view
+    needs it first while the others wait.  Results equal the alone runs bit
+    for bit, with uint64 and with binary32 messages."""
+    import torch
+    from paper_2010_01542_amd import Server, vc
+    print("case serve blocked layout shared by worker views (scale 20)", flush=True)
+    d = rmatgen.rmat(20, 4, seed=41)
+    g = make(d)
+    reqs = [("ppr" if i % 3 else "pagerank", int(i * 7919) % d.n, 3 + i % 4,
+             vc.OPT_F32_MESSAGES if i % 2 else 0) for i in range(12)]
+    with Server(workers=4) as srv:
+        gid = srv.add_graph(g)
+        outs, tickets = [], []
+        for prog, src, T, opt in reqs:
+            o = torch.full((d.n,), -7.0, dtype=torch.float32, device=device)
+            outs.append(o)
+            tickets.append(srv.submit(gid, prog, o, source=src, T=T, options=opt, route="worker"))
+        done = collect(srv, len(reqs))
+    for (prog, src, T, opt), o, t in zip(reqs, outs, tickets):
+        assert done[t].status == vc.OK, done[t]
+        ref, status, steps = alone(d, prog, source=src, T=T, options=opt)
+        assert np.array_equal(o.cpu().numpy(), ref), (prog, src, T, opt)
+        assert done[t].supersteps == steps
+
+
 def test_admission_under_a_small_budget(device):
     import torch
     from paper_2010_01542_amd import Server, VcError, vc
