@@ -83,25 +83,28 @@ typedef enum { VC_PAGERANK = 0, VC_CC_HASHMIN = 1, VC_SSSP = 2, VC_PPR = 3 } vc_
  *                    the transposed graph and combine in place (paper,
  *                    Section VI-C: single-broadcast); needs the transpose,
  *                    which the library builds on first use;
- *   VC_SCHED_BLOCKED PageRank / PPR only, fixed-point sums: the pull
- *                    combination by propagation blocking.  Edges are laid
- *                    out once by (source tile of 2^14 vertices, destination
- *                    bin of 2^12); each superstep stages a tile's messages
- *                    in LDS and copies them into its edges' slots, then
- *                    folds each bin's slots in LDS.  Both passes stream
- *                    (4 bytes of indices and 16 of message slots per edge,
- *                    8 with VC_OPT_F32_MESSAGES)
- *                    instead of gathering one message per edge from HBM.
- *                    The layout (12 bytes per edge plus 16 per bucket,
- *                    buckets = tiles x bins) is built on first use; graphs
- *                    beyond about 2^27 vertices are refused
- *                    (VC_ERR_UNSUPPORTED);
- *   VC_SCHED_AUTO    CC / SSSP, per superstep: pull for dense frontiers,
- *                    edge-centric push otherwise (vertex push for tiny
- *                    ones).  PageRank / PPR with fixed-point sums (default
- *                    or VC_OPT_F32_MESSAGES): BLOCKED on graphs of 2^20
- *                    vertices and more (the first such run builds the
- *                    layout), PULL below; with VC_OPT_F32_ACCUMULATE: PULL. */
+ *   VC_SCHED_BLOCKED PageRank / PPR (fixed-point sums) and CC / SSSP: the
+ *                    pull combination by propagation blocking.  Edges are
+ *                    laid out once by (source tile of 2^14 vertices,
+ *                    destination bin of 2^12); each superstep stages a
+ *                    tile's values in LDS and writes each edge's message
+ *                    into its slot, then folds each bin's slots in LDS (sum,
+ *                    or minimum with the pull form's mailbox rule; a source
+ *                    outside the CC / SSSP frontier sends "unreached").
+ *                    Both passes stream instead of gathering one message per
+ *                    edge from HBM.  Memory: 4 bytes of indices per edge (8
+ *                    with weights) and 16 per non-empty (tile, bin) pair,
+ *                    shared by a graph's views, plus 8 bytes of message
+ *                    slots per edge per graph object; built on first use.
+ *                    Graphs beyond about 2^27 vertices are refused
+ *                    (VC_ERR_UNSUPPORTED), as is vc_run_multi_source;
+ *   VC_SCHED_AUTO    CC / SSSP, per superstep: pull for dense frontiers
+ *                    (BLOCKED instead on graphs of 2^20 vertices and more,
+ *                    except in captured loops), edge-centric push otherwise
+ *                    (vertex push for tiny ones).  PageRank / PPR with
+ *                    fixed-point sums (default or VC_OPT_F32_MESSAGES):
+ *                    BLOCKED on graphs of 2^20 vertices and more, PULL
+ *                    below; with VC_OPT_F32_ACCUMULATE: PULL. */
 typedef enum {
   VC_SCHED_AUTO = 0,
   VC_SCHED_VERTEX = 1,

@@ -259,7 +259,7 @@ size_t pb_layout_bytes(vc_graph g) {  // the shared, read-only part
   if (shift == 0) return 0;
   const size_t bins = (size_t)vc::pb_bins(g->n), tiles = (size_t)vc::pb_tiles(g->n, shift), m = (size_t)g->m;
   const size_t runs = std::min(bins * tiles, m);  // non-empty buckets
-  return m * 4 + runs * 16 + (bins + 1) * 16 + (m / 4096 + bins + 2) * sizeof(vc::PbFoldItem) +
+  return m * (g->w ? 8 : 4) + runs * 16 + (bins + 1) * 16 + (m / 4096 + bins + 2) * sizeof(vc::PbFoldItem) +
          (m / 16384 + tiles + 2) * sizeof(vc::PbSpreadItem);
 }
 
@@ -319,12 +319,13 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
   const int pass_bins = (int)std::min<int64_t>(bins, std::max<int64_t>(64, (int64_t)(g->max_lds / 8) & ~63ll));
   const int64_t chunk = std::min<int64_t>(1 << 18, std::max<int64_t>(1 << 14, m / 2048));
   VC_TRY(vc::launch_pb_build(false, te_d.as<int64_t>(), tiles, g->dst, m, chunk, bins, pass_bins,
-                             cnt.as<unsigned long long>(), nullptr, nullptr, nullptr, s));
+                             cnt.as<unsigned long long>(), nullptr, nullptr, nullptr, nullptr, nullptr, s));
+  if (g->w) VC_TRY(g->pb_w.ensure((size_t)m * 4 + 4));
   VC_TRY(vc::launch_exclusive_scan(cnt.as<int64_t>(), nb, blocks.as<int64_t>(), s));
   VC_TRY(hipMemcpyAsync(starts_d.p, cnt.p, (size_t)(nb + 1) * 8, hipMemcpyDeviceToDevice, s));
   VC_TRY(vc::launch_pb_build(true, te_d.as<int64_t>(), tiles, g->dst, m, chunk, bins, pass_bins,
                              cnt.as<unsigned long long>(), srcl_csr, g->pb_srcl.as<uint16_t>(),
-                             g->pb_dstl.as<uint16_t>(), s));
+                             g->pb_dstl.as<uint16_t>(), g->w, g->w ? g->pb_w.as<uint32_t>() : nullptr, s));
   // run tables (non-empty buckets per bin) and fold items: at least about
   // 4096 items in all, at most 64 Ki edges each (a bin of fewer edges is one
   // item and stores its mailboxes instead of adding them)
@@ -366,6 +367,7 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
   vc::PbShared& pb = g->pb;
   pb.srcl = g->pb_srcl.as<uint16_t>();
   pb.dstl = g->pb_dstl.as<uint16_t>();
+  pb.w = g->w ? g->pb_w.as<uint32_t>() : nullptr;
   pb.run_off = g->pb_run_off.as<int64_t>();
   pb.btotal = g->pb_btotal.as<int64_t>();
   pb.rpre = g->pb_rpre.as<int64_t>();
@@ -378,6 +380,13 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
   pb.nfold = nfold;
   pb.ready = true;
   return VC_OK;
+}
+
+// Whether a dense CC / SSSP superstep that AUTO would pull takes the blocked
+// form instead: the same size rule as PageRank's, outside captured loops
+// (whose pull supersteps run on the device).
+bool min_blocked(vc_graph g, bool capture) {
+  return !capture && g->n >= (1 << 20) && g->m > 0 && pb_supported(g);
 }
 
 // The blocked layout for a run on g: a graph builds its own on first use; a
@@ -729,7 +738,7 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
     int sched = p.schedule;
     if (sched == VC_SCHED_AUTO) {
       if ((double)edges >= pull_threshold(p) * (double)m)
-        sched = VC_SCHED_PULL;
+        sched = min_blocked(g, capture) ? VC_SCHED_BLOCKED : VC_SCHED_PULL;
       else
         sched = edges <= 256 ? VC_SCHED_VERTEX : VC_SCHED_EDGE;
     }
@@ -737,7 +746,17 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
     const bool timed = rec.want_time(step);
     if (timed) VC_TRY(hipEventRecord(g->events[0], s));
     uint32_t* improved = bits[cur];
-    if (sched == VC_SCHED_PULL) {
+    if (sched == VC_SCHED_BLOCKED) {
+      vc_status st = use_pb(g, s);
+      if (st != VC_OK) return st;
+      const vc::PbShared& pb = g->pb;
+      uint32_t* slot_msg = g->pb_vals.as<uint32_t>();
+      if (timed) VC_TRY(hipEventRecord(g->events[1], s));
+      VC_TRY(vc::launch_pb_spread_min(kind, pb.spread, pb.nspread, n, pb.shift, pb.srcl, pb.w, vm,
+                                      dense ? nullptr : bits[1 - cur], slot_msg, s));
+      VC_TRY(vc::launch_pb_fold_min(pb.fold, pb.nfold, pb.run_off, pb.btotal, pb.rpre, pb.rbase, n, slot_msg, pb.dstl,
+                                    vm, improved, s));
+    } else if (sched == VC_SCHED_PULL) {
       vc_status st = ensure_csc(g, s);
       if (st == VC_OK) st = csc_partition(g, vc::pull_tile(tile), s);
       if (st != VC_OK) return st;
@@ -817,8 +836,7 @@ namespace vc {
 bool valid_params(const vc_params& p, vc_program prog, int64_t n, std::string* why) {
   if (p.struct_size != sizeof(vc_params)) return *why = "vc_params.struct_size mismatch", false;
   if (p.schedule < VC_SCHED_AUTO || p.schedule > VC_SCHED_BLOCKED) return *why = "bad schedule", false;
-  if (p.schedule == VC_SCHED_BLOCKED && prog != VC_PAGERANK && prog != VC_PPR)
-    return *why = "the blocked schedule is for PageRank / PPR", false;
+
   if (p.tile < 0) return *why = "negative tile", false;
   if (!(p.pull_fraction >= 0.0f)) return *why = "negative pull_fraction", false;
   if ((p.options & VC_OPT_F32_ACCUMULATE) && (p.options & VC_OPT_F32_MESSAGES))
@@ -1010,7 +1028,7 @@ vc_status vc_graph_destroy(vc_graph g) {
   for (DevBuf* b : {&g->own_off, &g->own_dst, &g->own_w, &g->perm, &g->inv, &g->rel_off, &g->rel_dst, &g->rel_w,
                     &g->contrib, &g->mb, &g->vm, &g->bitmap, &g->bitmap2,
                     &g->fq, &g->prefix, &g->scan_blocks, &g->list_tiles, &g->csc_off, &g->csc_src,
-                    &g->csc_w, &g->ms_src, &g->counters, &g->pb_srcl, &g->pb_dstl, &g->pb_vals,
+                    &g->csc_w, &g->ms_src, &g->counters, &g->pb_srcl, &g->pb_dstl, &g->pb_w, &g->pb_vals,
                     &g->pb_run_off, &g->pb_btotal, &g->pb_rpre, &g->pb_rbase, &g->pb_spread, &g->pb_fold})
     b->release();
   g->ms.release();
@@ -1038,7 +1056,7 @@ vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held,
                 g->rel_off.bytes + g->rel_dst.bytes + g->rel_w.bytes;
   for (const DevBuf* b : {&g->contrib, &g->mb, &g->vm, &g->bitmap, &g->bitmap2, &g->fq, &g->prefix, &g->scan_blocks,
                           &g->list_tiles, &g->csc_off, &g->csc_src, &g->csc_w,
-                          &g->ms_src, &g->counters, &g->pb_srcl, &g->pb_dstl, &g->pb_vals, &g->pb_run_off,
+                          &g->ms_src, &g->counters, &g->pb_srcl, &g->pb_dstl, &g->pb_w, &g->pb_vals, &g->pb_run_off,
                           &g->pb_btotal, &g->pb_rpre, &g->pb_rbase, &g->pb_spread, &g->pb_fold})
     held += b->bytes;
   held += g->ms.bytes();
@@ -1322,6 +1340,8 @@ vc_status vc_run_multi_source(vc_graph g, const uint32_t* sources, int32_t k, co
   p.source = 0;
   std::string why;
   if (!valid_params(p, VC_SSSP, g->n, &why)) return fail(VC_ERR_INVALID_ARG, why);
+  if (p.schedule == VC_SCHED_BLOCKED)
+    return fail(VC_ERR_UNSUPPORTED, "many-source runs choose push or pull per superstep; the blocked form is not one");
   if (stats) {
     if (stats->struct_size != sizeof(vc_stats) || stats->capacity < 0) return fail(VC_ERR_INVALID_ARG, "bad vc_stats");
     stats->supersteps = 0;

@@ -17,7 +17,11 @@
 //      array (added atomically when a bin of hubs is split over several
 //      workgroups).
 // Sums stay exact (uint64 fixed point), so results equal the pull form's.
-// Messages are uint64 fixed point or binary32 (half the slot bytes).
+// Messages are uint64 fixed point or binary32 (half the slot bytes).  The
+// same two passes serve the dense supersteps of the min programs (CC,
+// SSSP): the spread writes each slot's message (unreached for a source
+// outside the frontier), the fold takes minima in LDS and applies the pull
+// form's mailbox and improvement rule.
 #include "vc_device.h"
 
 namespace vc {
@@ -91,14 +95,16 @@ __device__ __forceinline__ int64_t tile_of(const int64_t* __restrict__ te, int64
 // Per workgroup: edges [c0, c1) of the CSR, split by source tile; per tile
 // and per range of pass_bins bins, an LDS histogram of destination bins.
 // PLACE = false adds the histogram into cnt (bucket counts); PLACE = true
-// reserves each bucket's share at cursor and writes the slots.
+// reserves each bucket's share at cursor and writes the slots (and the
+// edge weights in slot order when w is given).
 template <bool PLACE>
 __global__ __launch_bounds__(kBuildWG) void k_pb_build(const int64_t* __restrict__ te, int64_t tiles,
                                                        const int32_t* __restrict__ dst, int64_t m, int64_t chunk,
                                                        int64_t bins, int pass_bins,
                                                        unsigned long long* __restrict__ cnt,
                                                        const uint16_t* __restrict__ srcl_csr,
-                                                       uint16_t* __restrict__ srcl, uint16_t* __restrict__ dstl) {
+                                                       uint16_t* __restrict__ srcl, uint16_t* __restrict__ dstl,
+                                                       const uint32_t* __restrict__ w, uint32_t* __restrict__ wslot) {
   extern __shared__ __align__(16) uint32_t hist[];  // pass_bins counters, then (PLACE) pass_bins offsets
   uint32_t* rel = hist + pass_bins;
   const int64_t c0 = (int64_t)blockIdx.x * chunk;
@@ -136,6 +142,7 @@ __global__ __launch_bounds__(kBuildWG) void k_pb_build(const int64_t* __restrict
             const int64_t k = te[t] + (int64_t)rel[b] + (int64_t)atomicAdd(&hist[b], 1u);
             srcl[k] = srcl_csr[e];
             dstl[k] = (uint16_t)(v & ((1 << kPbDstShift) - 1));
+            if (w) wslot[k] = w[e];
           }
         }
         __syncthreads();
@@ -233,6 +240,49 @@ __global__ __launch_bounds__(kSpreadWG) void k_pb_spread(const PbSpreadItem* __r
   }
 }
 
+// Pass 1 of a min program (CC, SSSP): the tile's values in LDS, a source
+// that is not in the frontier (bit clear in `active`; NULL: every vertex)
+// reading as unreached, then vals[k] = the message on slot k: the value
+// (CC) or the value plus the edge's weight (SSSP, saturating; unweighted:
+// plus 1), unreached (kInf) for an inactive source.
+template <int KIND>
+__global__ __launch_bounds__(kSpreadWG) void k_pb_spread_min(const PbSpreadItem* __restrict__ items, int64_t n,
+                                                             int shift, const uint16_t* __restrict__ srcl,
+                                                             const uint32_t* __restrict__ wslot,
+                                                             const uint2* __restrict__ vm,
+                                                             const uint32_t* __restrict__ active,
+                                                             uint32_t* __restrict__ vals) {
+  constexpr int U = 8;
+  extern __shared__ __align__(16) uint32_t wmin[];
+  const PbSpreadItem it = items[blockIdx.x];
+  const int64_t u0 = (int64_t)it.t << shift;
+  const int64_t wl = (n - u0 < (1ll << shift)) ? n - u0 : (1ll << shift);
+  for (int64_t i = threadIdx.x; i < wl; i += kSpreadWG) {
+    const int64_t u = u0 + i;
+    const bool on = !active || ((active[u >> 5] >> (u & 31)) & 1u);
+    wmin[i] = on ? vm[u].x : kInf;
+  }
+  __syncthreads();
+  for (int64_t base = it.k0 + threadIdx.x; base < it.k1; base += (int64_t)kSpreadWG * U) {
+    uint16_t x[U];
+    uint32_t wv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t k = base + (int64_t)u * kSpreadWG;
+      x[u] = k < it.k1 ? srcl[k] : 0;
+      wv[u] = (KIND == kSsspWeighted && k < it.k1) ? wslot[k] : 1u;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t k = base + (int64_t)u * kSpreadWG;
+      if (k < it.k1) {
+        const uint32_t val = wmin[x[u]];
+        vals[k] = KIND == kCC ? val : sat_add(val, wv[u]);  // kInf stays kInf
+      }
+    }
+  }
+}
+
 // Pass 2: one workgroup per fold item.  The item's runs are staged
 // kFoldRuns at a time in LDS (start positions s_pre, slot bases s_base).
 // Wavefronts take ranges of 64 U consecutive positions, 64 at a time, lane
@@ -249,17 +299,84 @@ __global__ __launch_bounds__(kSpreadWG) void k_pb_spread(const PbSpreadItem* __r
 constexpr int kFoldWG = 512;
 constexpr int kFoldRuns = 1024;
 
+// The combiners of the fold.  Sum (PageRank): exact fixed-point mailboxes,
+// stored for a bin that is one item, added otherwise.  Min (CC, SSSP): as the
+// pull form, a receiver whose best message lowers its value takes it into
+// its mailbox (stored for a bin that is one item, an atomic min otherwise)
+// and its improvement bit is set.
 template <class M>
+struct FoldSum {
+  using Val = M;
+  using Box = unsigned long long;
+  unsigned long long* mb;
+  static constexpr Box kEmpty = 0ull;
+  __device__ __forceinline__ static void add(Box* box, uint16_t d, Val v) {
+    const unsigned long long x = msg_to_sum<M, unsigned long long>(v);
+    if (x) atomicAdd(&box[d], x);
+  }
+  __device__ __forceinline__ void flush(const PbFoldItem& it, const Box* box, int64_t n) const {
+    const int64_t v0 = (int64_t)it.b << kPbDstShift;
+    for (int i = threadIdx.x; i < (1 << kPbDstShift) && v0 + i < n; i += kFoldWG) {
+      const unsigned long long x = box[i];
+      if (!x) continue;
+      if (it.whole)
+        mb[v0 + i] = x;  // the only item of this bin
+      else
+        atomicAdd(&mb[v0 + i], x);
+    }
+  }
+};
+
+struct FoldMin {
+  using Val = uint32_t;
+  using Box = uint32_t;
+  uint2* vm;
+  uint32_t* improved;
+  static constexpr Box kEmpty = kInf;
+  __device__ __forceinline__ static void add(Box* box, uint16_t d, Val v) {
+    if (v != kInf) atomicMin(&box[d], v);
+  }
+  __device__ __forceinline__ void flush(const PbFoldItem& it, const Box* box, int64_t n) const {
+    const int64_t v0 = (int64_t)it.b << kPbDstShift;  // a multiple of 64: lanes 0..31 and 32..63 fill one word each
+    const int lane = threadIdx.x & 63;
+    for (int i = threadIdx.x; i < (1 << kPbDstShift); i += kFoldWG) {  // every lane runs every round
+      const int64_t v = v0 + i;
+      bool imp = false;
+      if (v < n) {
+        const uint32_t best = box[i];
+        if (best != kInf) {
+          const uint2 cur = vm[v];
+          if (best < cur.x) {
+            if (it.whole) {
+              vm[v].y = best;
+              imp = true;
+            } else if (best < cur.y) {
+              const uint32_t old = atomicMin(&reinterpret_cast<uint32_t*>(vm)[2 * v + 1], best);
+              imp = old == kInf;  // the first improver of v sets its bit
+            }
+          }
+        }
+      }
+      const unsigned long long mask = __ballot(imp);
+      if (lane == 0 && (uint32_t)mask) atomicOr(&improved[v >> 5], (uint32_t)mask);
+      if (lane == 32 && (uint32_t)(mask >> 32)) atomicOr(&improved[v >> 5], (uint32_t)(mask >> 32));
+    }
+  }
+};
+
+template <class Op>
 __global__ __launch_bounds__(kFoldWG) void k_pb_fold(const PbFoldItem* __restrict__ items, int64_t nitems,
                                                      const int64_t* __restrict__ run_off,
                                                      const int64_t* __restrict__ btotal,
                                                      const int64_t* __restrict__ rpre,
                                                      const int64_t* __restrict__ rbase, int64_t n,
-                                                     const M* __restrict__ vals, const uint16_t* __restrict__ dstl,
-                                                     unsigned long long* __restrict__ mb) {
+                                                     const typename Op::Val* __restrict__ vals,
+                                                     const uint16_t* __restrict__ dstl, Op op) {
+  using M = typename Op::Val;
+  using Box = typename Op::Box;
   constexpr int U = 8;
   constexpr int kNone = 0x7fffffff;
-  __shared__ unsigned long long box[1 << kPbDstShift];
+  __shared__ Box box[1 << kPbDstShift];
   __shared__ int32_t s_pre[kFoldRuns + 1];  // run starts relative to the item's first position, clamped
   __shared__ int64_t s_base[kFoldRuns];     // slot of the item's first position in each run's frame
   __shared__ uint32_t s_flag[kFoldWG];
@@ -267,7 +384,7 @@ __global__ __launch_bounds__(kFoldWG) void k_pb_fold(const PbFoldItem* __restric
   const int64_t j = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (j >= nitems) return;
   const PbFoldItem it = items[j];
-  for (int i = threadIdx.x; i < (1 << kPbDstShift); i += kFoldWG) box[i] = 0ull;
+  for (int i = threadIdx.x; i < (1 << kPbDstShift); i += kFoldWG) box[i] = Op::kEmpty;
   const int64_t R0 = run_off[it.b], nr = run_off[it.b + 1] - R0, total = btotal[it.b];
   const int len = (int)(it.v1 - it.v0);  // positions of the item, relative: [0, len), len <= 2^16
   const int lane = threadIdx.x & 63;
@@ -328,22 +445,12 @@ __global__ __launch_bounds__(kFoldWG) void k_pb_fold(const PbFoldItem* __restric
         raw[u] = k[u] >= 0 ? vals[k[u]] : M(0);
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const unsigned long long x = msg_to_sum<M, unsigned long long>(raw[u]);
-        if (x) atomicAdd(&box[dl[u]], x);
-      }
+      for (int u = 0; u < U; ++u)
+        if (k[u] >= 0) Op::add(box, dl[u], raw[u]);
     }
     __syncthreads();
   }
-  const int64_t v0 = (int64_t)it.b << kPbDstShift;
-  for (int i = threadIdx.x; i < (1 << kPbDstShift) && v0 + i < n; i += kFoldWG) {
-    const unsigned long long x = box[i];
-    if (!x) continue;
-    if (it.whole)
-      mb[v0 + i] = x;  // the only item of this bin
-    else
-      atomicAdd(&mb[v0 + i], x);
-  }
+  op.flush(it, box, n);
 }
 
 }  // namespace
@@ -382,17 +489,17 @@ hipError_t launch_pb_expand(const void* off, bool off64, int64_t n, int64_t m, c
 
 hipError_t launch_pb_build(bool place, const int64_t* te, int64_t tiles, const int32_t* dst, int64_t m, int64_t chunk,
                            int64_t bins, int pass_bins, unsigned long long* cnt, const uint16_t* srcl_csr,
-                           uint16_t* srcl, uint16_t* dstl, hipStream_t s) {
+                           uint16_t* srcl, uint16_t* dstl, const uint32_t* w, uint32_t* wslot, hipStream_t s) {
   if (m <= 0) return hipSuccess;
   if (pass_bins < 1 || chunk < 1) return hipErrorInvalidValue;
   const int64_t grid = (m + chunk - 1) / chunk;
   const size_t lds = (size_t)pass_bins * (place ? 8 : 4);
   if (place)
     hipLaunchKernelGGL(k_pb_build<true>, dim3((unsigned)grid), dim3(kBuildWG), lds, s, te, tiles, dst, m, chunk, bins,
-                       pass_bins, cnt, srcl_csr, srcl, dstl);
+                       pass_bins, cnt, srcl_csr, srcl, dstl, w, wslot);
   else
     hipLaunchKernelGGL(k_pb_build<false>, dim3((unsigned)grid), dim3(kBuildWG), lds, s, te, tiles, dst, m, chunk, bins,
-                       pass_bins, cnt, srcl_csr, srcl, dstl);
+                       pass_bins, cnt, srcl_csr, srcl, dstl, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -434,11 +541,48 @@ hipError_t launch_pb_fold(bool f32msg, const PbFoldItem* items, int64_t nitems, 
   if (nitems <= 0) return hipSuccess;
   const int64_t per = (nitems + 7) >> 3;
   if (f32msg)
-    hipLaunchKernelGGL(k_pb_fold<float>, dim3((unsigned)(8 * per)), dim3(kFoldWG), 0, s, items, nitems, run_off,
-                       btotal, rpre, rbase, n, (const float*)vals, dstl, mb);
+    hipLaunchKernelGGL(k_pb_fold<FoldSum<float>>, dim3((unsigned)(8 * per)), dim3(kFoldWG), 0, s, items, nitems,
+                       run_off, btotal, rpre, rbase, n, (const float*)vals, dstl, FoldSum<float>{mb});
   else
-    hipLaunchKernelGGL(k_pb_fold<unsigned long long>, dim3((unsigned)(8 * per)), dim3(kFoldWG), 0, s, items, nitems,
-                       run_off, btotal, rpre, rbase, n, (const unsigned long long*)vals, dstl, mb);
+    hipLaunchKernelGGL(k_pb_fold<FoldSum<unsigned long long>>, dim3((unsigned)(8 * per)), dim3(kFoldWG), 0, s, items,
+                       nitems, run_off, btotal, rpre, rbase, n, (const unsigned long long*)vals, dstl,
+                       FoldSum<unsigned long long>{mb});
+  return hipGetLastError();
+}
+
+hipError_t launch_pb_spread_min(int kind, const PbSpreadItem* items, int64_t nitems, int64_t n, int shift,
+                                const uint16_t* srcl, const uint32_t* wslot, const uint2* vm, const uint32_t* active,
+                                uint32_t* vals, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  if (shift < 10 || shift > kMaxSrcShift) return hipErrorInvalidValue;
+  if (kind == kSsspWeighted && !wslot) return hipErrorInvalidValue;
+  const size_t lds = (size_t)4 << shift;
+  switch (kind) {
+    case kCC:
+      hipLaunchKernelGGL(k_pb_spread_min<kCC>, dim3((unsigned)nitems), dim3(kSpreadWG), lds, s, items, n, shift, srcl,
+                         wslot, vm, active, vals);
+      break;
+    case kSsspUnit:
+      hipLaunchKernelGGL(k_pb_spread_min<kSsspUnit>, dim3((unsigned)nitems), dim3(kSpreadWG), lds, s, items, n, shift,
+                         srcl, wslot, vm, active, vals);
+      break;
+    case kSsspWeighted:
+      hipLaunchKernelGGL(k_pb_spread_min<kSsspWeighted>, dim3((unsigned)nitems), dim3(kSpreadWG), lds, s, items, n,
+                         shift, srcl, wslot, vm, active, vals);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pb_fold_min(const PbFoldItem* items, int64_t nitems, const int64_t* run_off, const int64_t* btotal,
+                              const int64_t* rpre, const int64_t* rbase, int64_t n, const uint32_t* vals,
+                              const uint16_t* dstl, uint2* vm, uint32_t* improved, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  const int64_t per = (nitems + 7) >> 3;
+  hipLaunchKernelGGL(k_pb_fold<FoldMin>, dim3((unsigned)(8 * per)), dim3(kFoldWG), 0, s, items, nitems, run_off,
+                     btotal, rpre, rbase, n, vals, dstl, FoldMin{vm, improved});
   return hipGetLastError();
 }
 

@@ -125,6 +125,7 @@ vc_status ms_superstep(MsState& st, vc_graph g, int cur, int ceff, int64_t next_
 struct PbShared {
   const uint16_t* srcl = nullptr;
   const uint16_t* dstl = nullptr;
+  const uint32_t* w = nullptr;  // edge weights in slot order (weighted graphs)
   const int64_t* run_off = nullptr;
   const int64_t* btotal = nullptr;
   const int64_t* rpre = nullptr;
@@ -176,7 +177,7 @@ struct vc_graph_s {
   // propagation-blocking layout (PageRank / PPR, built on first use): the
   // read-only part in buffers owned by the base graph, referenced by `pb`
   // in the base and in its views; each object owns its message slots
-  vc::DevBuf pb_srcl, pb_dstl, pb_run_off, pb_btotal, pb_rpre, pb_rbase, pb_spread, pb_fold;
+  vc::DevBuf pb_srcl, pb_dstl, pb_w, pb_run_off, pb_btotal, pb_rpre, pb_rbase, pb_spread, pb_fold;
   vc::PbShared pb;
   vc::DevBuf pb_vals;
   std::mutex pb_mu;         // base: serialises the layout build between views

@@ -225,13 +225,44 @@ def test_f32_options_exclude_each_other(device):
         g.run("pagerank", options=vc.OPT_F32_MESSAGES | vc.OPT_F32_ACCUMULATE)
 
 
-def test_blocked_schedule_rejects_min_programs_and_f32(device):
+def test_blocked_schedule_rejects_f32_atomics(device):
     from paper_2010_01542_amd import VcError, vc
     g = make(rmatgen.path(8, directed=True))
     with pytest.raises(VcError):
-        g.run("sssp", schedule="blocked")
-    with pytest.raises(VcError):
         g.run("pagerank", schedule="blocked", options=vc.OPT_F32_ACCUMULATE)
+
+
+@pytest.mark.parametrize("relabel", [True, False])
+def test_blocked_min_programs_bit_exact(device, relabel):
+    """Every superstep of CC / SSSP in the blocked form (spread of each slot's
+    message, LDS minima per destination bin, the pull form's mailbox and
+    improvement rule): values, superstep counts and per-superstep frontier
+    and message counts equal the oracle's.  Several source tiles, bins split
+    over items (hubs), weighted, unit-weight and symmetric graphs."""
+    print(f"case blocked min programs s19 relabel={relabel}", flush=True)
+    dw = rmatgen.rmat(19, 8, seed=12, weighted=True)
+    gw = make(dw, relabel=relabel)
+    for src in (0, 77):
+        check_min(dw, gw, "sssp", source=src, schedule="blocked")
+    du = rmatgen.rmat(18, 8, seed=13)
+    check_min(du, make(du, relabel=relabel), "sssp", source=3, schedule="blocked")
+    sym = rmatgen.rmat(18, 8, seed=14, directed=False)
+    check_min(sym, make(sym, symmetric=True, relabel=relabel), "cc", schedule="blocked")
+    for c in (rmatgen.in_star(40000), rmatgen.path(9, directed=True), rmatgen.cycle(5),
+              rmatgen.raw_csr(6, [0, 0, 1, 5, 5], [1, 1, 1, 0, 2])):
+        check_min(c, make(c, relabel=relabel), "sssp", source=0, schedule="blocked")
+        check_min(c, make(c, relabel=relabel), "cc", schedule="blocked")
+
+
+def test_auto_takes_the_blocked_form_for_dense_min_supersteps(device):
+    print("case auto blocked min s20", flush=True)
+    d = rmatgen.rmat(20, 8, seed=15, weighted=True)
+    g = make(d)
+    got, st, ref = check_min(d, g, "sssp", source=0)
+    assert 4 in set(st.schedule.tolist()), st.schedule
+    sym = rmatgen.rmat(20, 4, seed=16, directed=False)
+    got, st, ref = check_min(sym, make(sym, symmetric=True), "cc")
+    assert 4 in set(st.schedule.tolist()), st.schedule
 
 
 @pytest.mark.parametrize("program", ["pagerank", "ppr"])
