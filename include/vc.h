@@ -178,8 +178,9 @@ typedef struct {
   vc_schedule schedule;   /* VC_SCHED_AUTO picks per superstep from |F| and E_F */
   int32_t tile;           /* merge-path items per workgroup tile; 0 = library default */
   uint32_t options;       /* VC_OPT_* */
-  float pull_fraction;    /* CC / SSSP with VC_SCHED_AUTO: pull a superstep once its frontier's
-                             out-edges reach this fraction of all edges; 0 = library default (0.1) */
+  float pull_fraction;    /* CC / SSSP with VC_SCHED_AUTO: pull (or take the blocked form) once a
+                             superstep's frontier out-edges reach this fraction of all edges;
+                             0 = library default (0.1 for pull, 0.25 for the blocked form) */
 } vc_params;
 
 /* Per-run statistics.  The caller owns every array (host memory) and sets

@@ -558,6 +558,10 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
 // Fraction of the edges above which a CC / SSSP superstep is pulled: the
 // pull form streams every in-edge, the push form only the frontier's
 // out-edges, so pull pays off once the frontier carries a large share of them.
+// Share of the edges from which AUTO takes the blocked form for a CC / SSSP
+// superstep (unless params set pull_fraction).
+constexpr double kBlockedFraction = 0.25;
+
 double pull_threshold(const vc_params& p) {
   if (p.pull_fraction > 0.0f) return (double)p.pull_fraction;
   static const double v = [] {
@@ -737,8 +741,13 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
     }
     int sched = p.schedule;
     if (sched == VC_SCHED_AUTO) {
-      if ((double)edges >= pull_threshold(p) * (double)m)
-        sched = min_blocked(g, capture) ? VC_SCHED_BLOCKED : VC_SCHED_PULL;
+      // a blocked superstep costs a full pass over the edges, so it takes
+      // over from push later than the pull form would (scale-26 SSSP: push
+      // 1.9 ms vs blocked 4.4 ms at 12 % of the edges, 6.5 vs 4.5 ms at 46 %)
+      const bool blocked = min_blocked(g, capture);
+      const double thr = (p.pull_fraction > 0.0f || !blocked) ? pull_threshold(p) : kBlockedFraction;
+      if ((double)edges >= thr * (double)m)
+        sched = blocked ? VC_SCHED_BLOCKED : VC_SCHED_PULL;
       else
         sched = edges <= 256 ? VC_SCHED_VERTEX : VC_SCHED_EDGE;
     }
