@@ -285,15 +285,19 @@ __global__ __launch_bounds__(kWG) void k_min_scatter_mp(const OffT* __restrict__
   }
 }
 
-// Vertex update + frontier compaction.  One thread per bitmap word: every
-// improved vertex adopts its mailbox (value = mailbox, mailbox = neutral);
-// those with out-edges are appended, in id order within the workgroup, to
-// the broadcast list with their degree (for the next merge-path prefix).
-// `bitmap` (this superstep's improvements) is kept: it is the next
-// superstep's active set for the pull form.  `stale` (the previous active
-// set) is cleared so it can collect the next improvements.
-// With `seed` set the values are already in place (the initial senders of a
-// seeded run) and only the list and counters are built.
+// Vertex update + frontier compaction.  Every improved vertex adopts its
+// mailbox (value = mailbox, mailbox = neutral); those with out-edges are
+// appended, in id order within the workgroup, to the broadcast list with
+// their degree (for the next merge-path prefix).  A workgroup covers kWG
+// bitmap words; each wavefront takes its 64 words (2,048 vertices) in 32
+// rounds of 64 consecutive vertices, one per lane, so vertex values and
+// offsets are read and written coalesced; a round's listed vertices are
+// one ballot, whose popcounts place them in the list.  `bitmap` (this
+// superstep's improvements) is kept: it is the next superstep's active set
+// for the pull form.  `stale` (the previous active set) is cleared so it can
+// collect the next improvements.  With `seed` set the values are already in
+// place (the initial senders of a seeded run) and only the list and
+// counters are built.
 template <class OffT>
 __global__ __launch_bounds__(kWG) void k_min_compact(const OffT* __restrict__ off, int64_t n, uint2* __restrict__ vm,
                                                      const uint32_t* __restrict__ bitmap, uint32_t* __restrict__ stale,
@@ -301,29 +305,37 @@ __global__ __launch_bounds__(kWG) void k_min_compact(const OffT* __restrict__ of
                                                      int64_t* __restrict__ P, Counters* __restrict__ ctr, int seed,
                                                      const LoopState* loop) {
   if (loop && loop->done) return;  // device-driven loop already quiescent
-  const int64_t wi = gid();
-  uint32_t word = 0;
+  const int lane = (int)(threadIdx.x & 63);
+  const int64_t wbase = (int64_t)blockIdx.x * kWG + (int64_t)(threadIdx.x & ~63u);  // first word of the wavefront
+  const int64_t wi = wbase + lane;
+  uint32_t myword = 0;
   if (wi < nwords) {
-    word = bitmap[wi];
+    myword = bitmap[wi];
     if (stale[wi]) stale[wi] = 0;
   }
-  uint32_t active = 0, listed = 0;
-  unsigned long long edges = 0;
-  for (uint32_t bits = word; bits; bits &= bits - 1) {
-    const int64_t v = wi * 32 + (__ffs(bits) - 1);
-    if (!seed) {
-      const uint2 p = vm[v];
-      vm[v] = make_uint2(p.y, kInf);
-    }
-    const int64_t deg = (int64_t)off[v + 1] - (int64_t)off[v];
-    ++active;
-    if (deg > 0) {
-      ++listed;
+  uint32_t active = 0, wave_listed = 0;
+  unsigned long long edges = 0, mymask = 0;  // lane i keeps round i's listed mask
+  for (int i = 0; i < 32; ++i) {
+    // vertex wbase*32 + 64 i + lane: word 2 i + lane / 32 of the wavefront, bit lane % 32
+    const uint32_t w = __shfl(myword, 2 * i + (lane >> 5), 64);
+    bool listed = false;
+    if ((w >> (lane & 31)) & 1u) {
+      const int64_t v = wbase * 32 + (int64_t)i * 64 + lane;
+      if (!seed) {
+        const uint2 p = vm[v];
+        vm[v] = make_uint2(p.y, kInf);
+      }
+      const int64_t deg = (int64_t)off[v + 1] - (int64_t)off[v];
+      ++active;
       edges += (unsigned long long)deg;
+      listed = deg > 0;
     }
+    const unsigned long long mk = __ballot(listed);
+    if (lane == i) mymask = mk;
+    wave_listed += (uint32_t)__popcll(mk);
   }
   uint32_t tot_listed;
-  uint32_t pos = block_excl_scan<uint32_t>(listed, &tot_listed);
+  const uint32_t before = block_excl_scan<uint32_t>(lane == 0 ? wave_listed : 0u, &tot_listed);
   const uint32_t tot_active = block_sum<uint32_t>(active);
   const unsigned long long tot_edges = block_sum<unsigned long long>(edges);
   __shared__ unsigned long long s_base;
@@ -333,16 +345,17 @@ __global__ __launch_bounds__(kWG) void k_min_compact(const OffT* __restrict__ of
     if (tot_edges) atomicAdd(&ctr->edges, tot_edges);
   }
   __syncthreads();
-  if (!listed) return;
-  int64_t at = (int64_t)s_base + pos;
-  for (uint32_t bits = word; bits; bits &= bits - 1) {
-    const int64_t v = wi * 32 + (__ffs(bits) - 1);
-    const int64_t deg = (int64_t)off[v + 1] - (int64_t)off[v];
-    if (deg > 0) {
-      fq[at] = (int32_t)v;
-      P[at] = deg;
-      ++at;
+  if (!wave_listed) return;  // uniform over the wavefront; no barrier follows
+  int64_t at = (int64_t)s_base + (int64_t)__shfl(before, 0, 64);
+  for (int i = 0; i < 32; ++i) {
+    const unsigned long long mk = __shfl(mymask, i, 64);
+    if ((mk >> lane) & 1ull) {
+      const int64_t v = wbase * 32 + (int64_t)i * 64 + lane;
+      const int64_t pos = at + __popcll(mk & ((1ull << lane) - 1ull));
+      fq[pos] = (int32_t)v;
+      P[pos] = (int64_t)off[v + 1] - (int64_t)off[v];
     }
+    at += __popcll(mk);
   }
 }
 
