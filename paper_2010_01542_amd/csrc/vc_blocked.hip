@@ -296,8 +296,9 @@ __global__ __launch_bounds__(kSpreadWG) void k_pb_spread_min(const PbSpreadItem*
 // cover any 64 positions.  Items are handed out so that each of the 8 XCDs
 // takes a contiguous range of bins: runs of neighbouring bins share cache
 // lines at their ends, which then meet in the same L2.
-constexpr int kFoldWG = 512;
+constexpr int kFoldWG = 1024;
 constexpr int kFoldRuns = 1024;
+static_assert((1 << kPbDstShift) % kFoldWG == 0, "the min fold's flush runs every lane in every round");
 
 // The combiners of the fold.  Sum (PageRank): exact fixed-point mailboxes,
 // stored for a bin that is one item, added otherwise.  Min (CC, SSSP): as the

@@ -4,13 +4,17 @@
            T=10 against the binary64 oracle, every schedule, both combiners.
 * cc-s22   (symmetrised R-MAT scale 22, edge factor 16): hash-min CC
            bit-exact with identical per-superstep frontiers, vertex-centric,
-           edge-centric, pull and automatic schedules.
+           edge-centric, pull, blocked and automatic schedules.
 * sssp-s26 (directed R-MAT scale 26, edge factor 16, int64 offsets, uint32
            weights): SSSP from vertex 0 bit-exact against the oracle;
            PageRank T=3 against the oracle end to end; PageRank T=20 (the
            benchmark's run, default launch configuration) checked by
            recomputing its last update in binary64 from the device's T=19
            ranks, plus the dangling-mass invariant.
+* scale 27 (directed R-MAT, edge factor 1, weighted): 32,768 destination
+           bins, so the blocked layout's histograms take two LDS passes;
+           blocked SSSP and PageRank equal the push and pull forms bit for
+           bit (the oracle is not run at this size).
 """
 import numpy as np
 import pytest
@@ -48,7 +52,7 @@ def cc22(device):
     return g, make(g, symmetric=True), oracle.run_csr("cc", g)
 
 
-@pytest.mark.parametrize("sched", ["auto", "pull", "edge", "vertex"])
+@pytest.mark.parametrize("sched", ["auto", "pull", "edge", "vertex", "blocked"])
 def test_cc_s22_bit_exact(cc22, sched):
     csr, g, ref = cc22
     print(f"case cc-s22 schedule={sched}", flush=True)
@@ -120,3 +124,22 @@ def test_s26_pagerank_t20_last_update(s26, f32_messages):
     # binary64 re-evaluation of one update agrees to the rounding of the result
     assert mx <= 4 * np.spacing(np.float32(expect.max()))
     assert r20.sum() == pytest.approx((1 - d) + d * r19[deg > 0].sum(), rel=1e-6)
+
+
+@pytest.fixture(scope="module")
+def s27(device):
+    g = rmatgen.rmat(27, 1, seed=rmatgen.BASE_SEED + 27, weighted=True, threads=16)
+    return g, make(g)
+
+
+def test_s27_blocked_layout_in_two_histogram_passes(s27):
+    csr, g = s27
+    print(f"case scale 27 n={csr.n} m={csr.m}: blocked vs edge SSSP, blocked vs pull PageRank", flush=True)
+    a, sa = run_gpu(g, "sssp", source=0, schedule="blocked")
+    b, sb = run_gpu(g, "sssp", source=0, schedule="edge")
+    assert np.array_equal(a, b), int((a != b).sum())
+    assert sa.frontier.tolist() == sb.frontier.tolist()
+    assert sa.edges.tolist() == sb.edges.tolist()
+    p = run_gpu(g, "pagerank", T=3, schedule="blocked")[0]
+    q = run_gpu(g, "pagerank", T=3, schedule="pull")[0]
+    assert np.array_equal(p, q)
