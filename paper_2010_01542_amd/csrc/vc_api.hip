@@ -319,13 +319,26 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
   const int pass_bins = (int)std::min<int64_t>(bins, std::max<int64_t>(64, (int64_t)(g->max_lds / 8) & ~63ll));
   const int64_t chunk = std::min<int64_t>(1 << 18, std::max<int64_t>(1 << 14, m / 2048));
   VC_TRY(vc::launch_pb_build(false, te_d.as<int64_t>(), tiles, g->dst, m, chunk, bins, pass_bins,
-                             cnt.as<unsigned long long>(), nullptr, nullptr, nullptr, nullptr, nullptr, s));
-  if (g->w) VC_TRY(g->pb_w.ensure((size_t)m * 4 + 4));
+                             cnt.as<unsigned long long>(), nullptr, nullptr, nullptr, nullptr, nullptr, 4, s));
+  // weights in slot order: one byte each when every weight fits (weights of
+  // 1..255, as the benchmark graphs have, save 3 bytes per edge and superstep)
+  int wbytes = 4;
+  if (g->w) {
+    DevBuf wmax;
+    VC_TRY(wmax.ensure(4));
+    VC_TRY(vc::launch_fill_u32(wmax.as<uint32_t>(), 1, 0u, s));
+    VC_TRY(vc::launch_pb_wmax(g->w, m, wmax.as<uint32_t>(), s));
+    uint32_t mx = 0;
+    VC_TRY(hipMemcpyAsync(&mx, wmax.p, 4, hipMemcpyDeviceToHost, s));
+    VC_TRY(hipStreamSynchronize(s));
+    wbytes = mx <= 255 ? 1 : 4;
+    VC_TRY(g->pb_w.ensure((size_t)m * wbytes + 4));
+  }
   VC_TRY(vc::launch_exclusive_scan(cnt.as<int64_t>(), nb, blocks.as<int64_t>(), s));
   VC_TRY(hipMemcpyAsync(starts_d.p, cnt.p, (size_t)(nb + 1) * 8, hipMemcpyDeviceToDevice, s));
   VC_TRY(vc::launch_pb_build(true, te_d.as<int64_t>(), tiles, g->dst, m, chunk, bins, pass_bins,
                              cnt.as<unsigned long long>(), srcl_csr, g->pb_srcl.as<uint16_t>(),
-                             g->pb_dstl.as<uint16_t>(), g->w, g->w ? g->pb_w.as<uint32_t>() : nullptr, s));
+                             g->pb_dstl.as<uint16_t>(), g->w, g->w ? g->pb_w.p : nullptr, wbytes, s));
   // run tables (non-empty buckets per bin) and fold items: at least about
   // 4096 items in all, at most 64 Ki edges each (a bin of fewer edges is one
   // item and stores its mailboxes instead of adding them)
@@ -367,7 +380,8 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
   vc::PbShared& pb = g->pb;
   pb.srcl = g->pb_srcl.as<uint16_t>();
   pb.dstl = g->pb_dstl.as<uint16_t>();
-  pb.w = g->w ? g->pb_w.as<uint32_t>() : nullptr;
+  pb.w = g->w ? g->pb_w.p : nullptr;
+  pb.wbytes = wbytes;
   pb.run_off = g->pb_run_off.as<int64_t>();
   pb.btotal = g->pb_btotal.as<int64_t>();
   pb.rpre = g->pb_rpre.as<int64_t>();
@@ -761,7 +775,7 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
       const vc::PbShared& pb = g->pb;
       uint32_t* slot_msg = g->pb_vals.as<uint32_t>();
       if (timed) VC_TRY(hipEventRecord(g->events[1], s));
-      VC_TRY(vc::launch_pb_spread_min(kind, pb.spread, pb.nspread, n, pb.shift, pb.srcl, pb.w, vm,
+      VC_TRY(vc::launch_pb_spread_min(kind, pb.spread, pb.nspread, n, pb.shift, pb.srcl, pb.w, pb.wbytes, vm,
                                       dense ? nullptr : bits[1 - cur], slot_msg, s));
       VC_TRY(vc::launch_pb_fold_min(pb.fold, pb.nfold, pb.run_off, pb.btotal, pb.rpre, pb.rbase, n, slot_msg, pb.dstl,
                                     vm, improved, s));

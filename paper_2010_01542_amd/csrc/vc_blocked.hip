@@ -79,6 +79,18 @@ __global__ __launch_bounds__(kWG) void k_pb_expand(const OffT* __restrict__ off,
 
 constexpr int kBuildWG = 1024;
 
+// *out = max(*out, largest of the m weights).
+__global__ __launch_bounds__(kWG) void k_pb_wmax(const uint32_t* __restrict__ w, int64_t m, uint32_t* __restrict__ out) {
+  uint32_t x = 0;
+  for (int64_t e = gid(); e < m; e += grid_threads()) x = w[e] > x ? w[e] : x;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t y = __shfl_xor(x, o, 64);
+    x = y > x ? y : x;
+  }
+  if (lane_id() == 0 && x) atomicMax(out, x);
+}
+
 // Tile of edge c0: last t with te[t] <= c0 (te[0] = 0 <= c0 < m = te[tiles]).
 __device__ __forceinline__ int64_t tile_of(const int64_t* __restrict__ te, int64_t tiles, int64_t c0) {
   int64_t lo = 0, hi = tiles - 1;
@@ -96,7 +108,7 @@ __device__ __forceinline__ int64_t tile_of(const int64_t* __restrict__ te, int64
 // and per range of pass_bins bins, an LDS histogram of destination bins.
 // PLACE = false adds the histogram into cnt (bucket counts); PLACE = true
 // reserves each bucket's share at cursor and writes the slots (and the
-// edge weights in slot order when w is given).
+// edge weights in slot order when w is given, as bytes when wbytes is 1).
 template <bool PLACE>
 __global__ __launch_bounds__(kBuildWG) void k_pb_build(const int64_t* __restrict__ te, int64_t tiles,
                                                        const int32_t* __restrict__ dst, int64_t m, int64_t chunk,
@@ -104,7 +116,8 @@ __global__ __launch_bounds__(kBuildWG) void k_pb_build(const int64_t* __restrict
                                                        unsigned long long* __restrict__ cnt,
                                                        const uint16_t* __restrict__ srcl_csr,
                                                        uint16_t* __restrict__ srcl, uint16_t* __restrict__ dstl,
-                                                       const uint32_t* __restrict__ w, uint32_t* __restrict__ wslot) {
+                                                       const uint32_t* __restrict__ w, void* __restrict__ wslot,
+                                                       int wbytes) {
   extern __shared__ __align__(16) uint32_t hist[];  // pass_bins counters, then (PLACE) pass_bins offsets
   uint32_t* rel = hist + pass_bins;
   const int64_t c0 = (int64_t)blockIdx.x * chunk;
@@ -142,7 +155,12 @@ __global__ __launch_bounds__(kBuildWG) void k_pb_build(const int64_t* __restrict
             const int64_t k = te[t] + (int64_t)rel[b] + (int64_t)atomicAdd(&hist[b], 1u);
             srcl[k] = srcl_csr[e];
             dstl[k] = (uint16_t)(v & ((1 << kPbDstShift) - 1));
-            if (w) wslot[k] = w[e];
+            if (w) {
+              if (wbytes == 1)
+                static_cast<uint8_t*>(wslot)[k] = (uint8_t)w[e];
+              else
+                static_cast<uint32_t*>(wslot)[k] = w[e];
+            }
           }
         }
         __syncthreads();
@@ -244,11 +262,12 @@ __global__ __launch_bounds__(kSpreadWG) void k_pb_spread(const PbSpreadItem* __r
 // that is not in the frontier (bit clear in `active`; NULL: every vertex)
 // reading as unreached, then vals[k] = the message on slot k: the value
 // (CC) or the value plus the edge's weight (SSSP, saturating; unweighted:
-// plus 1), unreached (kInf) for an inactive source.
-template <int KIND>
+// plus 1), unreached (kInf) for an inactive source.  Slot weights are bytes
+// (WT = uint8_t) when every weight of the graph fits one.
+template <int KIND, class WT>
 __global__ __launch_bounds__(kSpreadWG) void k_pb_spread_min(const PbSpreadItem* __restrict__ items, int64_t n,
                                                              int shift, const uint16_t* __restrict__ srcl,
-                                                             const uint32_t* __restrict__ wslot,
+                                                             const WT* __restrict__ wslot,
                                                              const uint2* __restrict__ vm,
                                                              const uint32_t* __restrict__ active,
                                                              uint32_t* __restrict__ vals) {
@@ -270,7 +289,7 @@ __global__ __launch_bounds__(kSpreadWG) void k_pb_spread_min(const PbSpreadItem*
     for (int u = 0; u < U; ++u) {
       const int64_t k = base + (int64_t)u * kSpreadWG;
       x[u] = k < it.k1 ? srcl[k] : 0;
-      wv[u] = (KIND == kSsspWeighted && k < it.k1) ? wslot[k] : 1u;
+      wv[u] = (KIND == kSsspWeighted && k < it.k1) ? (uint32_t)wslot[k] : 1u;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -488,19 +507,26 @@ hipError_t launch_pb_expand(const void* off, bool off64, int64_t n, int64_t m, c
   return hipGetLastError();
 }
 
+hipError_t launch_pb_wmax(const uint32_t* w, int64_t m, uint32_t* out, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pb_wmax, dim3(grid_stride_for(m)), dim3(kWG), 0, s, w, m, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_pb_build(bool place, const int64_t* te, int64_t tiles, const int32_t* dst, int64_t m, int64_t chunk,
                            int64_t bins, int pass_bins, unsigned long long* cnt, const uint16_t* srcl_csr,
-                           uint16_t* srcl, uint16_t* dstl, const uint32_t* w, uint32_t* wslot, hipStream_t s) {
+                           uint16_t* srcl, uint16_t* dstl, const uint32_t* w, void* wslot, int wbytes,
+                           hipStream_t s) {
   if (m <= 0) return hipSuccess;
   if (pass_bins < 1 || chunk < 1) return hipErrorInvalidValue;
   const int64_t grid = (m + chunk - 1) / chunk;
   const size_t lds = (size_t)pass_bins * (place ? 8 : 4);
   if (place)
     hipLaunchKernelGGL(k_pb_build<true>, dim3((unsigned)grid), dim3(kBuildWG), lds, s, te, tiles, dst, m, chunk, bins,
-                       pass_bins, cnt, srcl_csr, srcl, dstl, w, wslot);
+                       pass_bins, cnt, srcl_csr, srcl, dstl, w, wslot, wbytes);
   else
     hipLaunchKernelGGL(k_pb_build<false>, dim3((unsigned)grid), dim3(kBuildWG), lds, s, te, tiles, dst, m, chunk, bins,
-                       pass_bins, cnt, srcl_csr, srcl, dstl, nullptr, nullptr);
+                       pass_bins, cnt, srcl_csr, srcl, dstl, nullptr, nullptr, 4);
   return hipGetLastError();
 }
 
@@ -551,30 +577,43 @@ hipError_t launch_pb_fold(bool f32msg, const PbFoldItem* items, int64_t nitems, 
   return hipGetLastError();
 }
 
-hipError_t launch_pb_spread_min(int kind, const PbSpreadItem* items, int64_t nitems, int64_t n, int shift,
-                                const uint16_t* srcl, const uint32_t* wslot, const uint2* vm, const uint32_t* active,
-                                uint32_t* vals, hipStream_t s) {
-  if (nitems <= 0) return hipSuccess;
-  if (shift < 10 || shift > kMaxSrcShift) return hipErrorInvalidValue;
-  if (kind == kSsspWeighted && !wslot) return hipErrorInvalidValue;
+namespace {
+template <class WT>
+hipError_t spread_min_launch(int kind, const PbSpreadItem* items, int64_t nitems, int64_t n, int shift,
+                             const uint16_t* srcl, const WT* wslot, const uint2* vm, const uint32_t* active,
+                             uint32_t* vals, hipStream_t s) {
   const size_t lds = (size_t)4 << shift;
   switch (kind) {
     case kCC:
-      hipLaunchKernelGGL(k_pb_spread_min<kCC>, dim3((unsigned)nitems), dim3(kSpreadWG), lds, s, items, n, shift, srcl,
-                         wslot, vm, active, vals);
-      break;
-    case kSsspUnit:
-      hipLaunchKernelGGL(k_pb_spread_min<kSsspUnit>, dim3((unsigned)nitems), dim3(kSpreadWG), lds, s, items, n, shift,
+      hipLaunchKernelGGL((k_pb_spread_min<kCC, WT>), dim3((unsigned)nitems), dim3(kSpreadWG), lds, s, items, n, shift,
                          srcl, wslot, vm, active, vals);
       break;
-    case kSsspWeighted:
-      hipLaunchKernelGGL(k_pb_spread_min<kSsspWeighted>, dim3((unsigned)nitems), dim3(kSpreadWG), lds, s, items, n,
+    case kSsspUnit:
+      hipLaunchKernelGGL((k_pb_spread_min<kSsspUnit, WT>), dim3((unsigned)nitems), dim3(kSpreadWG), lds, s, items, n,
                          shift, srcl, wslot, vm, active, vals);
+      break;
+    case kSsspWeighted:
+      hipLaunchKernelGGL((k_pb_spread_min<kSsspWeighted, WT>), dim3((unsigned)nitems), dim3(kSpreadWG), lds, s, items,
+                         n, shift, srcl, wslot, vm, active, vals);
       break;
     default:
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_pb_spread_min(int kind, const PbSpreadItem* items, int64_t nitems, int64_t n, int shift,
+                                const uint16_t* srcl, const void* wslot, int wbytes, const uint2* vm,
+                                const uint32_t* active, uint32_t* vals, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  if (shift < 10 || shift > kMaxSrcShift) return hipErrorInvalidValue;
+  if (kind == kSsspWeighted && !wslot) return hipErrorInvalidValue;
+  if (wbytes == 1)
+    return spread_min_launch(kind, items, nitems, n, shift, srcl, static_cast<const uint8_t*>(wslot), vm, active, vals,
+                             s);
+  return spread_min_launch(kind, items, nitems, n, shift, srcl, static_cast<const uint32_t*>(wslot), vm, active, vals,
+                           s);
 }
 
 hipError_t launch_pb_fold_min(const PbFoldItem* items, int64_t nitems, const int64_t* run_off, const int64_t* btotal,

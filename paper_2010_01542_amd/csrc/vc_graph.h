@@ -125,7 +125,8 @@ vc_status ms_superstep(MsState& st, vc_graph g, int cur, int ceff, int64_t next_
 struct PbShared {
   const uint16_t* srcl = nullptr;
   const uint16_t* dstl = nullptr;
-  const uint32_t* w = nullptr;  // edge weights in slot order (weighted graphs)
+  const void* w = nullptr;  // edge weights in slot order (weighted graphs), wbytes each
+  int wbytes = 4;
   const int64_t* run_off = nullptr;
   const int64_t* btotal = nullptr;
   const int64_t* rpre = nullptr;

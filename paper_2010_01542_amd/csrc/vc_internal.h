@@ -238,11 +238,14 @@ hipError_t launch_pb_expand(const void* off, bool off64, int64_t n, int64_t m, c
 // into cnt (bins * tiles zeroed counters).  place = true: cnt holds the
 // bucket starts (consumed as cursors); writes each edge's source offset
 // (srcl) and destination offset in its bin (dstl) at a slot of its bucket,
-// and its weight (wslot) when w is not NULL.
+// and its weight (wslot, wbytes = 1: uint8, else uint32) when w is not NULL.
 // pass_bins: bins per LDS pass (pass_bins * 8 bytes of LDS).
 hipError_t launch_pb_build(bool place, const int64_t* te, int64_t tiles, const int32_t* dst, int64_t m, int64_t chunk,
                            int64_t bins, int pass_bins, unsigned long long* cnt, const uint16_t* srcl_csr,
-                           uint16_t* srcl, uint16_t* dstl, const uint32_t* w, uint32_t* wslot, hipStream_t s);
+                           uint16_t* srcl, uint16_t* dstl, const uint32_t* w, void* wslot, int wbytes,
+                           hipStream_t s);
+// *out = max(*out, largest of the m weights w).
+hipError_t launch_pb_wmax(const uint32_t* w, int64_t m, uint32_t* out, hipStream_t s);
 // Run tables from the bucket starts (runs = non-empty buckets of a bin, in
 // tile order).  fill = false: per bin, nruns (runs), btotal (edges) and
 // nitems (fold items of up to fcap positions).  fill = true, with run_off
@@ -267,10 +270,11 @@ hipError_t launch_pb_fold(bool f32msg, const PbFoldItem* items, int64_t nitems, 
                           const void* vals, const uint16_t* dstl, unsigned long long* mb, hipStream_t s);
 // Min programs (kind: kCC, kSsspUnit, kSsspWeighted): vals[k] = message on
 // slot k from the current values (kInf for sources outside `active`; NULL:
-// all).  wslot: weights in slot order (kSsspWeighted only).
+// all).  wslot: weights in slot order, wbytes (1 or 4) each (kSsspWeighted
+// only).
 hipError_t launch_pb_spread_min(int kind, const PbSpreadItem* items, int64_t nitems, int64_t n, int shift,
-                                const uint16_t* srcl, const uint32_t* wslot, const uint2* vm, const uint32_t* active,
-                                uint32_t* vals, hipStream_t s);
+                                const uint16_t* srcl, const void* wslot, int wbytes, const uint2* vm,
+                                const uint32_t* active, uint32_t* vals, hipStream_t s);
 // Per receiver v, best = the minimum message of its in-edges; when best <
 // value(v) the mailbox takes it and v's bit in `improved` is set (the
 // outcome of launch_min_pull).  Mailboxes unreached on entry.

@@ -191,7 +191,8 @@ def test_blocked_pagerank_matches_oracle_and_pull(device, relabel):
     a = run_gpu(g, "pagerank", T=6, schedule="blocked")[0]
     b = run_gpu(g, "pagerank", T=6, schedule="pull")[0]
     assert np.array_equal(a, b)
-    for c in (rmatgen.in_star(40000), rmatgen.cycle(5), rmatgen.raw_csr(6, [0, 0, 1, 5, 5], [1, 1, 1, 0, 2])):
+    for c in (rmatgen.in_star(40000), rmatgen.cycle(5), rmatgen.raw_csr(6, [0, 0, 1, 5, 5], [1, 1, 1, 0, 2]),
+              rmatgen.raw_csr(7, [], [])):
         check_rank(c, make(c, relabel=relabel), "pagerank", T=3, schedule="blocked")
 
 
@@ -249,9 +250,12 @@ def test_blocked_min_programs_bit_exact(device, relabel):
     sym = rmatgen.rmat(18, 8, seed=14, directed=False)
     check_min(sym, make(sym, symmetric=True, relabel=relabel), "cc", schedule="blocked")
     for c in (rmatgen.in_star(40000), rmatgen.path(9, directed=True), rmatgen.cycle(5),
-              rmatgen.raw_csr(6, [0, 0, 1, 5, 5], [1, 1, 1, 0, 2])):
+              rmatgen.raw_csr(6, [0, 0, 1, 5, 5], [1, 1, 1, 0, 2]), rmatgen.raw_csr(7, [], [])):
         check_min(c, make(c, relabel=relabel), "sssp", source=0, schedule="blocked")
         check_min(c, make(c, relabel=relabel), "cc", schedule="blocked")
+    # weights beyond one byte: the layout keeps them 4 bytes wide
+    big = rmatgen.Csr(dw.n, dw.m, dw.off, dw.dst, (dw.w.astype(np.uint32) * np.uint32(1000)).astype(np.uint32))
+    check_min(big, make(big, relabel=relabel), "sssp", source=0, schedule="blocked")
 
 
 def test_auto_takes_the_blocked_form_for_dense_min_supersteps(device):
