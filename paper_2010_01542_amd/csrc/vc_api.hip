@@ -259,7 +259,8 @@ size_t pb_layout_bytes(vc_graph g) {  // the shared, read-only part
   if (shift == 0) return 0;
   const size_t bins = (size_t)vc::pb_bins(g->n), tiles = (size_t)vc::pb_tiles(g->n, shift), m = (size_t)g->m;
   const size_t runs = std::min(bins * tiles, m);  // non-empty buckets
-  return m * (g->w ? 8 : 4) + runs * 16 + (bins + 1) * 16 + (m / 4096 + bins + 2) * sizeof(vc::PbFoldItem) +
+  return m * (g->w ? 8 : 4) + runs * 16 + (bins + 1) * 24 + (m / 64 + bins + 1) * sizeof(vc::PbChunk) +
+         (m / 4096 + bins + 2) * sizeof(vc::PbFoldItem) +
          (m / 16384 + tiles + 2) * sizeof(vc::PbSpreadItem);
 }
 
@@ -342,7 +343,7 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
   // run tables (non-empty buckets per bin) and fold items: at least about
   // 4096 items in all, at most 64 Ki edges each (a bin of fewer edges is one
   // item and stores its mailboxes instead of adding them)
-  const int64_t fcap = std::min<int64_t>(65536, std::max<int64_t>(4096, m / 4096));
+  const int64_t fcap = std::min<int64_t>(vc::kPbMaxItemPositions, std::max<int64_t>(4096, m / 4096));
   VC_TRY(nitems.ensure((size_t)(bins + 1) * 8));
   VC_TRY(g->pb_run_off.ensure((size_t)(bins + 1) * 8));
   VC_TRY(g->pb_btotal.ensure((size_t)bins * 8));
@@ -360,8 +361,18 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
   VC_TRY(vc::launch_pb_tables(true, starts_d.as<int64_t>(), bins, tiles, fcap, nullptr, nullptr, nullptr,
                               g->pb_run_off.as<int64_t>(), g->pb_rpre.as<int64_t>(), g->pb_rbase.as<int64_t>(), s));
   VC_TRY(g->pb_fold.ensure((size_t)(nfold + 1) * sizeof(vc::PbFoldItem)));
-  VC_TRY(vc::launch_pb_fold_items(g->pb_run_off.as<int64_t>(), g->pb_rpre.as<int64_t>(), g->pb_btotal.as<int64_t>(),
-                                  bins, fcap, nitems.as<int64_t>(), g->pb_fold.as<vc::PbFoldItem>(), s));
+  VC_TRY(vc::launch_pb_fold_items(g->pb_btotal.as<int64_t>(), bins, nitems.as<int64_t>(),
+                                  g->pb_fold.as<vc::PbFoldItem>(), s));
+  // chunks of 64 positions: each names its first run and the run starts inside
+  VC_TRY(g->pb_chunk_off.ensure((size_t)(bins + 1) * 8));
+  VC_TRY(vc::launch_pb_chunk_counts(g->pb_btotal.as<int64_t>(), bins, g->pb_chunk_off.as<int64_t>(), s));
+  VC_TRY(vc::launch_exclusive_scan(g->pb_chunk_off.as<int64_t>(), bins, blocks.as<int64_t>(), s));
+  int64_t nchunks = 0;
+  VC_TRY(hipMemcpyAsync(&nchunks, g->pb_chunk_off.as<int64_t>() + bins, 8, hipMemcpyDeviceToHost, s));
+  VC_TRY(hipStreamSynchronize(s));
+  VC_TRY(g->pb_chunks.ensure((size_t)(nchunks + 1) * sizeof(vc::PbChunk)));
+  VC_TRY(vc::launch_pb_chunks(g->pb_run_off.as<int64_t>(), g->pb_rpre.as<int64_t>(), g->pb_chunk_off.as<int64_t>(),
+                              bins, g->pb_chunks.as<vc::PbChunk>(), s));
   // spread items: a tile's slots are contiguous; pieces of up to scap slots
   // (the tile's messages are loaded once per piece; 64 Ki slots balance
   // that load against the spread of work over the compute units best at
@@ -386,6 +397,8 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
   pb.btotal = g->pb_btotal.as<int64_t>();
   pb.rpre = g->pb_rpre.as<int64_t>();
   pb.rbase = g->pb_rbase.as<int64_t>();
+  pb.chunk_off = g->pb_chunk_off.as<int64_t>();
+  pb.chunks = g->pb_chunks.as<vc::PbChunk>();
   pb.spread = g->pb_spread.as<vc::PbSpreadItem>();
   pb.fold = g->pb_fold.as<vc::PbFoldItem>();
   pb.shift = shift;
@@ -424,8 +437,8 @@ hipError_t pb_superstep(vc_graph g, bool f32msg, const void* contrib, void* mb, 
   const vc::PbShared& pb = g->pb;
   hipError_t e = vc::launch_pb_spread(f32msg, pb.spread, pb.nspread, g->n, pb.shift, pb.srcl, contrib, g->pb_vals.p, s);
   if (e != hipSuccess) return e;
-  return vc::launch_pb_fold(f32msg, pb.fold, pb.nfold, pb.run_off, pb.btotal, pb.rpre, pb.rbase, g->n, g->pb_vals.p,
-                            pb.dstl, static_cast<unsigned long long*>(mb), s);
+  return vc::launch_pb_fold(f32msg, pb.fold, pb.nfold, pb.run_off, pb.rpre, pb.btotal, pb.chunk_off, pb.chunks,
+                            pb.rbase, g->n, g->pb_vals.p, pb.dstl, static_cast<unsigned long long*>(mb), s);
 }
 
 vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hipStream_t s, Recorder& rec,
@@ -777,8 +790,8 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
       if (timed) VC_TRY(hipEventRecord(g->events[1], s));
       VC_TRY(vc::launch_pb_spread_min(kind, pb.spread, pb.nspread, n, pb.shift, pb.srcl, pb.w, pb.wbytes, vm,
                                       dense ? nullptr : bits[1 - cur], slot_msg, s));
-      VC_TRY(vc::launch_pb_fold_min(pb.fold, pb.nfold, pb.run_off, pb.btotal, pb.rpre, pb.rbase, n, slot_msg, pb.dstl,
-                                    vm, improved, s));
+      VC_TRY(vc::launch_pb_fold_min(pb.fold, pb.nfold, pb.run_off, pb.rpre, pb.btotal, pb.chunk_off, pb.chunks,
+                                    pb.rbase, n, slot_msg, pb.dstl, vm, improved, s));
     } else if (sched == VC_SCHED_PULL) {
       vc_status st = ensure_csc(g, s);
       if (st == VC_OK) st = csc_partition(g, vc::pull_tile(tile), s);
@@ -1052,7 +1065,8 @@ vc_status vc_graph_destroy(vc_graph g) {
                     &g->contrib, &g->mb, &g->vm, &g->bitmap, &g->bitmap2,
                     &g->fq, &g->prefix, &g->scan_blocks, &g->list_tiles, &g->csc_off, &g->csc_src,
                     &g->csc_w, &g->ms_src, &g->counters, &g->pb_srcl, &g->pb_dstl, &g->pb_w, &g->pb_vals,
-                    &g->pb_run_off, &g->pb_btotal, &g->pb_rpre, &g->pb_rbase, &g->pb_spread, &g->pb_fold})
+                    &g->pb_run_off, &g->pb_btotal, &g->pb_rpre, &g->pb_rbase, &g->pb_chunk_off, &g->pb_chunks,
+                    &g->pb_spread, &g->pb_fold})
     b->release();
   g->ms.release();
   g->dense_parts.release();
@@ -1080,7 +1094,8 @@ vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held,
   for (const DevBuf* b : {&g->contrib, &g->mb, &g->vm, &g->bitmap, &g->bitmap2, &g->fq, &g->prefix, &g->scan_blocks,
                           &g->list_tiles, &g->csc_off, &g->csc_src, &g->csc_w,
                           &g->ms_src, &g->counters, &g->pb_srcl, &g->pb_dstl, &g->pb_w, &g->pb_vals, &g->pb_run_off,
-                          &g->pb_btotal, &g->pb_rpre, &g->pb_rbase, &g->pb_spread, &g->pb_fold})
+                          &g->pb_btotal, &g->pb_rpre, &g->pb_rbase, &g->pb_chunk_off, &g->pb_chunks,
+                          &g->pb_spread, &g->pb_fold})
     held += b->bytes;
   held += g->ms.bytes();
   held += g->dense_parts.bytes() + g->csc_parts.bytes();

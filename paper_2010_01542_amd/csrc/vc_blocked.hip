@@ -203,28 +203,49 @@ __global__ __launch_bounds__(kWG) void k_pb_tables(const int64_t* __restrict__ s
 }
 
 // Per bin b (one thread): its fold items, count = ceil(total / fcap) equal
-// shares of the bin's positions, with the runs [r0, r1) (indices in the
-// bin's run list) they touch.
-__global__ __launch_bounds__(kWG) void k_pb_fold_items(const int64_t* __restrict__ run_off,
-                                                       const int64_t* __restrict__ rpre,
-                                                       const int64_t* __restrict__ btotal, int64_t bins,
-                                                       int64_t fcap, const int64_t* __restrict__ item_off,
+// shares of the bin's positions, cut at multiples of 64 (a share is at least
+// 2,048 positions when a bin has several).
+__global__ __launch_bounds__(kWG) void k_pb_fold_items(const int64_t* __restrict__ btotal, int64_t bins,
+                                                       const int64_t* __restrict__ item_off,
                                                        PbFoldItem* __restrict__ items) {
+  const int64_t b = gid();
+  if (b >= bins) return;
+  const int64_t total = btotal[b];
+  const int64_t first = item_off[b], count = item_off[b + 1] - item_off[b];
+  auto cut = [&](int64_t i) {
+    if (i == count) return total;
+    return (total / count * i + (total % count) * i / count) & ~(int64_t)63;
+  };
+  for (int64_t i = 0; i < count; ++i) items[first + i] = PbFoldItem{(int32_t)b, count == 1 ? 1 : 0, cut(i), cut(i + 1)};
+}
+
+// Per bin b: chunks of 64 positions, ceil(total / 64) of them.
+__global__ __launch_bounds__(kWG) void k_pb_chunk_counts(const int64_t* __restrict__ btotal, int64_t bins,
+                                                         int64_t* __restrict__ nchunks) {
+  const int64_t b = gid();
+  if (b < bins) nchunks[b] = (btotal[b] + 63) >> 6;
+}
+
+// Per bin b (one thread): for chunk c (positions 64 c .. 64 c + 63 of the
+// bin's concatenation of runs), the run holding position 64 c and a mask of
+// the run starts inside it (bit i: a run starts at 64 c + i, i >= 1).  The
+// fold then finds any position's run with one masked popcount.
+__global__ __launch_bounds__(kWG) void k_pb_chunks(const int64_t* __restrict__ run_off,
+                                                   const int64_t* __restrict__ rpre,
+                                                   const int64_t* __restrict__ chunk_off, int64_t bins,
+                                                   PbChunk* __restrict__ chunks) {
   const int64_t b = gid();
   if (b >= bins) return;
   const int64_t* P = rpre + run_off[b];
   const int64_t nr = run_off[b + 1] - run_off[b];
-  const int64_t total = btotal[b];
-  const int64_t first = item_off[b], count = item_off[b + 1] - item_off[b];
-  auto start = [&](int64_t r) { return r < nr ? P[r] : total; };
-  int64_t r = 0;  // run holding position v: last r with start(r) <= v (v < total, so r < nr)
-  for (int64_t i = 0; i < count; ++i) {  // equal shares of the bin's positions
-    const int64_t v0 = total / count * i + (total % count) * i / count;
-    const int64_t v1 = total / count * (i + 1) + (total % count) * (i + 1) / count;
-    while (start(r + 1) <= v0) ++r;
-    int64_t r1 = r;
-    while (start(r1 + 1) <= v1 - 1) ++r1;
-    items[first + i] = PbFoldItem{(int32_t)b, count == 1 ? 1 : 0, r, r1 + 1, v0, v1};
+  const int64_t c0 = chunk_off[b], nch = chunk_off[b + 1] - c0;
+  int64_t r = 0;  // run holding position 64 c (P[0] = 0, runs non-empty)
+  for (int64_t c = 0; c < nch; ++c) {
+    const int64_t base = c * 64;
+    while (r + 1 < nr && P[r + 1] <= base) ++r;
+    unsigned long long starts = 0;
+    for (int64_t t = r + 1; t < nr && P[t] <= base + 63; ++t) starts |= 1ull << (P[t] - base);
+    chunks[c0 + c] = PbChunk{(int32_t)r, 0, starts};
   }
 }
 
@@ -302,21 +323,20 @@ __global__ __launch_bounds__(kSpreadWG) void k_pb_spread_min(const PbSpreadItem*
   }
 }
 
-// Pass 2: one workgroup per fold item.  The item's runs are staged
-// kFoldRuns at a time in LDS (start positions s_pre, slot bases s_base).
-// Wavefronts take ranges of 64 U consecutive positions, 64 at a time, lane
-// l the position p + l, so every load instruction reads 64 consecutive
-// slots.  Lane l's run is found without a per-lane search: the wavefront
-// holds the starts of the next 64 runs, one per lane (S); the runs starting
-// at or before p are counted with one ballot, the run starts inside
-// (p, p + 63] are flagged per position through a 64-entry LDS array, and a
-// lane adds the flags at or below its own position (a masked popcount).
-// Runs are never empty, so their starts increase strictly and 64 of them
-// cover any 64 positions.  Items are handed out so that each of the 8 XCDs
-// takes a contiguous range of bins: runs of neighbouring bins share cache
-// lines at their ends, which then meet in the same L2.
+// Pass 2: one workgroup per fold item.  The item's chunk descriptors (one
+// per 64 positions: first run, run starts inside) are staged in LDS once;
+// its runs' slot bases in windows of kFoldRuns runs.  Per window,
+// wavefronts take the chunks overlapping the window's positions round
+// robin, U at a time, lane l the position 64 c + l, so every load
+// instruction reads 64 consecutive positions; a lane's run is its chunk's
+// first run plus the run starts at or below its position (one masked
+// popcount) and its slot that run's base plus the position.  Items are
+// handed out so that each of the 8 XCDs takes a contiguous range of bins:
+// runs of neighbouring bins share cache lines at their ends, which then
+// meet in the same L2.
 constexpr int kFoldWG = 1024;
 constexpr int kFoldRuns = 1024;
+constexpr int kFoldChunks = (int)(kPbMaxItemPositions / 64 + 1);  // an item's chunks, from a multiple of 64
 static_assert((1 << kPbDstShift) % kFoldWG == 0, "the min fold's flush runs every lane in every round");
 
 // The combiners of the fold.  Sum (PageRank): exact fixed-point mailboxes,
@@ -387,75 +407,53 @@ struct FoldMin {
 template <class Op>
 __global__ __launch_bounds__(kFoldWG) void k_pb_fold(const PbFoldItem* __restrict__ items, int64_t nitems,
                                                      const int64_t* __restrict__ run_off,
-                                                     const int64_t* __restrict__ btotal,
                                                      const int64_t* __restrict__ rpre,
+                                                     const int64_t* __restrict__ btotal,
+                                                     const int64_t* __restrict__ chunk_off,
+                                                     const PbChunk* __restrict__ chunks,
                                                      const int64_t* __restrict__ rbase, int64_t n,
                                                      const typename Op::Val* __restrict__ vals,
                                                      const uint16_t* __restrict__ dstl, Op op) {
   using M = typename Op::Val;
   using Box = typename Op::Box;
   constexpr int U = 8;
-  constexpr int kNone = 0x7fffffff;
+  constexpr int W = kFoldWG / 64;  // wavefronts
   __shared__ Box box[1 << kPbDstShift];
-  __shared__ int32_t s_pre[kFoldRuns + 1];  // run starts relative to the item's first position, clamped
-  __shared__ int64_t s_base[kFoldRuns];     // slot of the item's first position in each run's frame
-  __shared__ uint32_t s_flag[kFoldWG];
+  __shared__ int64_t s_base[kFoldRuns];
+  __shared__ PbChunk s_chunk[kFoldChunks];
   const int64_t per = (nitems + 7) >> 3;
   const int64_t j = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (j >= nitems) return;
   const PbFoldItem it = items[j];
-  for (int i = threadIdx.x; i < (1 << kPbDstShift); i += kFoldWG) box[i] = Op::kEmpty;
   const int64_t R0 = run_off[it.b], nr = run_off[it.b + 1] - R0, total = btotal[it.b];
-  const int len = (int)(it.v1 - it.v0);  // positions of the item, relative: [0, len), len <= 2^16
+  const int64_t cfirst = it.v0 >> 6, c_end = (it.v1 + 63) >> 6;  // it.v0 is a multiple of 64
+  const int nch = (int)(c_end - cfirst);                           // <= kFoldChunks
+  for (int i = threadIdx.x; i < (1 << kPbDstShift); i += kFoldWG) box[i] = Op::kEmpty;
+  for (int i = threadIdx.x; i < nch; i += kFoldWG) s_chunk[i] = chunks[chunk_off[it.b] + cfirst + i];
+  __syncthreads();
   const int lane = threadIdx.x & 63;
-  uint32_t* flag = s_flag + (threadIdx.x & ~63);
-  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);  // lanes 0..lane
-  for (int64_t w0 = it.r0; w0 < it.r1; w0 += kFoldRuns) {
-    const int wn = (int)((it.r1 - w0 < kFoldRuns) ? it.r1 - w0 : kFoldRuns);
-    for (int i = threadIdx.x; i <= wn; i += kFoldWG) {
-      // starts before the item clamp to -1 and after it to kNone: order
-      // against positions 0..len-1 is kept, which is all the lookup uses
-      const int64_t st = (w0 + i < nr ? rpre[R0 + w0 + i] : total) - it.v0;
-      s_pre[i] = st < 0 ? -1 : (st > len ? kNone : (int32_t)st);
-      if (i < wn) s_base[i] = rbase[R0 + w0 + i] + it.v0;
-    }
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);  // bits 0..lane
+  const int64_t r_first = s_chunk[0].rb;
+  const int64_t r_last = s_chunk[nch - 1].rb + __popcll(s_chunk[nch - 1].starts);  // run of the item's last chunk's end
+  for (int64_t w0 = r_first; w0 <= r_last; w0 += kFoldRuns) {
+    const int wn = (int)((r_last + 1 - w0 < kFoldRuns) ? r_last + 1 - w0 : kFoldRuns);
+    for (int i = threadIdx.x; i < wn; i += kFoldWG) s_base[i] = rbase[R0 + w0 + i];
     __syncthreads();
-    const int a = s_pre[0] > 0 ? s_pre[0] : 0;
-    const int z = s_pre[wn] < len ? s_pre[wn] : len;
-    for (int g = a + (threadIdx.x >> 6) * 64 * U; g < z; g += kFoldWG * U) {
-      int lo = 0, hi = wn - 1;  // rb = run of position g (wavefront-uniform)
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_pre[mid] <= g)
-          lo = mid;
-        else
-          hi = mid - 1;
-      }
-      int rb = lo;
-      int S = rb + lane <= wn ? s_pre[rb + lane] : kNone;
+    // positions of the window's runs, within the item
+    const int64_t pa = rpre[R0 + w0], pz = w0 + wn < nr ? rpre[R0 + w0 + wn] : total;
+    const int64_t a = pa > it.v0 ? pa : it.v0, z = pz < it.v1 ? pz : it.v1;
+    for (int64_t c = (a >> 6) + wave; c <= ((z - 1) >> 6); c += (int64_t)W * U) {
       int64_t k[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int p = g + u * 64;
+        const int64_t cc = c + (int64_t)u * W;
         k[u] = -1;
-        if (p >= z) continue;  // uniform
-        unsigned long long below = __ballot(S <= p);  // runs starting at or before p: lanes 0..c0-1
-        if (__builtin_amdgcn_readlane(S, 63) < p + 63) {  // a start in (p, p + 63] lies past the window
-          rb += __popcll(below) - 1;
-          S = rb + lane <= wn ? s_pre[rb + lane] : kNone;
-          below = __ballot(S <= p);
+        const int64_t q = cc * 64 + lane;
+        if (cc <= ((z - 1) >> 6) && q >= a && q < z) {
+          const PbChunk ch = s_chunk[cc - cfirst];
+          k[u] = s_base[ch.rb + __popcll(ch.starts & upto) - w0] + q;  // the run lies in this window: q in [a, z)
         }
-        const int d = S - p;
-        flag[lane] = 0u;
-        __builtin_amdgcn_wave_barrier();
-        if (d >= 1 && d <= 63) flag[d] = 1u;
-        __builtin_amdgcn_wave_barrier();
-        const uint32_t f = flag[lane];
-        __builtin_amdgcn_wave_barrier();
-        const unsigned long long starts = __ballot(f != 0u);
-        const int r = rb + __popcll(below) - 1 + __popcll(starts & upto);
-        const int q = p + lane;
-        if (q < z) k[u] = s_base[r] + q;
       }
       uint16_t dl[U];
       M raw[U];
@@ -542,10 +540,20 @@ hipError_t launch_pb_tables(bool fill, const int64_t* starts, int64_t bins, int6
   return hipGetLastError();
 }
 
-hipError_t launch_pb_fold_items(const int64_t* run_off, const int64_t* rpre, const int64_t* btotal, int64_t bins,
-                                int64_t fcap, const int64_t* item_off, PbFoldItem* items, hipStream_t s) {
-  hipLaunchKernelGGL(k_pb_fold_items, dim3(grid_for(bins)), dim3(kWG), 0, s, run_off, rpre, btotal, bins, fcap,
-                     item_off, items);
+hipError_t launch_pb_fold_items(const int64_t* btotal, int64_t bins, const int64_t* item_off, PbFoldItem* items,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_pb_fold_items, dim3(grid_for(bins)), dim3(kWG), 0, s, btotal, bins, item_off, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_pb_chunk_counts(const int64_t* btotal, int64_t bins, int64_t* nchunks, hipStream_t s) {
+  hipLaunchKernelGGL(k_pb_chunk_counts, dim3(grid_for(bins)), dim3(kWG), 0, s, btotal, bins, nchunks);
+  return hipGetLastError();
+}
+
+hipError_t launch_pb_chunks(const int64_t* run_off, const int64_t* rpre, const int64_t* chunk_off, int64_t bins,
+                            PbChunk* chunks, hipStream_t s) {
+  hipLaunchKernelGGL(k_pb_chunks, dim3(grid_for(bins)), dim3(kWG), 0, s, run_off, rpre, chunk_off, bins, chunks);
   return hipGetLastError();
 }
 
@@ -563,17 +571,19 @@ hipError_t launch_pb_spread(bool f32msg, const PbSpreadItem* items, int64_t nite
 }
 
 hipError_t launch_pb_fold(bool f32msg, const PbFoldItem* items, int64_t nitems, const int64_t* run_off,
-                          const int64_t* btotal, const int64_t* rpre, const int64_t* rbase, int64_t n,
-                          const void* vals, const uint16_t* dstl, unsigned long long* mb, hipStream_t s) {
+                          const int64_t* rpre, const int64_t* btotal, const int64_t* chunk_off, const PbChunk* chunks,
+                          const int64_t* rbase, int64_t n, const void* vals, const uint16_t* dstl,
+                          unsigned long long* mb, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   const int64_t per = (nitems + 7) >> 3;
   if (f32msg)
     hipLaunchKernelGGL(k_pb_fold<FoldSum<float>>, dim3((unsigned)(8 * per)), dim3(kFoldWG), 0, s, items, nitems,
-                       run_off, btotal, rpre, rbase, n, (const float*)vals, dstl, FoldSum<float>{mb});
+                       run_off, rpre, btotal, chunk_off, chunks, rbase, n, (const float*)vals, dstl,
+                       FoldSum<float>{mb});
   else
     hipLaunchKernelGGL(k_pb_fold<FoldSum<unsigned long long>>, dim3((unsigned)(8 * per)), dim3(kFoldWG), 0, s, items,
-                       nitems, run_off, btotal, rpre, rbase, n, (const unsigned long long*)vals, dstl,
-                       FoldSum<unsigned long long>{mb});
+                       nitems, run_off, rpre, btotal, chunk_off, chunks, rbase, n,
+                       (const unsigned long long*)vals, dstl, FoldSum<unsigned long long>{mb});
   return hipGetLastError();
 }
 
@@ -616,13 +626,14 @@ hipError_t launch_pb_spread_min(int kind, const PbSpreadItem* items, int64_t nit
                            s);
 }
 
-hipError_t launch_pb_fold_min(const PbFoldItem* items, int64_t nitems, const int64_t* run_off, const int64_t* btotal,
-                              const int64_t* rpre, const int64_t* rbase, int64_t n, const uint32_t* vals,
+hipError_t launch_pb_fold_min(const PbFoldItem* items, int64_t nitems, const int64_t* run_off,
+                              const int64_t* rpre, const int64_t* btotal, const int64_t* chunk_off,
+                              const PbChunk* chunks, const int64_t* rbase, int64_t n, const uint32_t* vals,
                               const uint16_t* dstl, uint2* vm, uint32_t* improved, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   const int64_t per = (nitems + 7) >> 3;
   hipLaunchKernelGGL(k_pb_fold<FoldMin>, dim3((unsigned)(8 * per)), dim3(kFoldWG), 0, s, items, nitems, run_off,
-                     btotal, rpre, rbase, n, vals, dstl, FoldMin{vm, improved});
+                     rpre, btotal, chunk_off, chunks, rbase, n, vals, dstl, FoldMin{vm, improved});
   return hipGetLastError();
 }
 

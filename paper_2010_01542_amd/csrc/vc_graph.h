@@ -131,6 +131,8 @@ struct PbShared {
   const int64_t* btotal = nullptr;
   const int64_t* rpre = nullptr;
   const int64_t* rbase = nullptr;
+  const int64_t* chunk_off = nullptr;
+  const PbChunk* chunks = nullptr;
   const PbSpreadItem* spread = nullptr;
   const PbFoldItem* fold = nullptr;
   int64_t nspread = 0, nfold = 0, tiles = 0;
@@ -178,7 +180,8 @@ struct vc_graph_s {
   // propagation-blocking layout (PageRank / PPR, built on first use): the
   // read-only part in buffers owned by the base graph, referenced by `pb`
   // in the base and in its views; each object owns its message slots
-  vc::DevBuf pb_srcl, pb_dstl, pb_w, pb_run_off, pb_btotal, pb_rpre, pb_rbase, pb_spread, pb_fold;
+  vc::DevBuf pb_srcl, pb_dstl, pb_w, pb_run_off, pb_btotal, pb_rpre, pb_rbase, pb_chunk_off, pb_chunks, pb_spread,
+      pb_fold;
   vc::PbShared pb;
   vc::DevBuf pb_vals;
   std::mutex pb_mu;         // base: serialises the layout build between views

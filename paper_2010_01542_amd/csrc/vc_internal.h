@@ -211,17 +211,25 @@ hipError_t launch_combine(int op, const void* off, bool off64, const int32_t* ds
 // buckets in tile-major order: bucket (t, b) = t * bins + b.
 constexpr int kPbDstShift = 12;
 constexpr int64_t kPbMaxBuckets = 1ll << 28;
+constexpr int64_t kPbMaxItemPositions = 1ll << 16;  // positions per fold item (its chunk descriptors fit LDS)
 // Spread item: slots [k0, k1) of source tile t.
 struct PbSpreadItem {
   int32_t t, pad;
   int64_t k0, k1;
 };
 // Fold item: positions [v0, v1) of the concatenation of bin b's runs (the
-// non-empty buckets (t, b) in tile order), which lie in runs [r0, r1) of the
-// bin's run list; whole marks the only item of its bin.
+// non-empty buckets (t, b) in tile order), v0 a multiple of 64; whole marks
+// the only item of its bin.
 struct PbFoldItem {
   int32_t b, whole;
-  int64_t r0, r1, v0, v1;
+  int64_t v0, v1;
+};
+// Chunk c of a bin (positions 64 c .. 64 c + 63): rb = the run holding
+// position 64 c (index in the bin's run list), bit i of starts = a run
+// starts at 64 c + i.
+struct PbChunk {
+  int32_t rb, pad;
+  unsigned long long starts;
 };
 // Largest source tile whose messages fit the LDS limit (<= 2^14 vertices).
 int pb_src_shift(size_t max_lds);
@@ -255,19 +263,26 @@ hipError_t launch_pb_tables(bool fill, const int64_t* starts, int64_t bins, int6
                             int64_t* nruns, int64_t* btotal, int64_t* nitems, const int64_t* run_off, int64_t* rpre,
                             int64_t* rbase, hipStream_t s);
 // Fold items of every bin; item_off: exclusive scan of the item counts.
-hipError_t launch_pb_fold_items(const int64_t* run_off, const int64_t* rpre, const int64_t* btotal, int64_t bins,
-                                int64_t fcap, const int64_t* item_off, PbFoldItem* items, hipStream_t s);
+hipError_t launch_pb_fold_items(const int64_t* btotal, int64_t bins, const int64_t* item_off, PbFoldItem* items,
+                                hipStream_t s);
+// Chunks of 64 positions per bin (nchunks[b] = ceil(btotal[b] / 64)) and,
+// with chunk_off their exclusive scan, every chunk's PbChunk.
+hipError_t launch_pb_chunk_counts(const int64_t* btotal, int64_t bins, int64_t* nchunks, hipStream_t s);
+hipError_t launch_pb_chunks(const int64_t* run_off, const int64_t* rpre, const int64_t* chunk_off, int64_t bins,
+                            PbChunk* chunks, hipStream_t s);
 // vals[k] = msg[tile's first vertex + srcl[k]] for every slot of every item;
 // msg / vals hold binary32 messages when f32msg, else uint64 fixed point.
 hipError_t launch_pb_spread(bool f32msg, const PbSpreadItem* items, int64_t nitems, int64_t n, int shift,
                             const uint16_t* srcl, const void* msg, void* vals, hipStream_t s);
-// Runs of bin b are run_off[b] .. run_off[b + 1] - 1; run i starts at
-// position rpre[i] of the concatenation of the bin's runs (btotal[b]
-// positions) and position v of it sits at slot rbase[i] + v.  Adds every
-// item's messages into mb (stores for whole bins); mb zero on entry.
+// Runs of bin b are run_off[b] .. run_off[b + 1] - 1; run r starts at
+// position rpre[r] of the bin's concatenation of runs (btotal[b]
+// positions), position v in run r sits at slot rbase[r] + v, and v's chunk
+// (chunk_off[b] + v / 64) names r.  Adds every item's messages into mb
+// (stores for whole bins); mb zero on entry.
 hipError_t launch_pb_fold(bool f32msg, const PbFoldItem* items, int64_t nitems, const int64_t* run_off,
-                          const int64_t* btotal, const int64_t* rpre, const int64_t* rbase, int64_t n,
-                          const void* vals, const uint16_t* dstl, unsigned long long* mb, hipStream_t s);
+                          const int64_t* rpre, const int64_t* btotal, const int64_t* chunk_off, const PbChunk* chunks,
+                          const int64_t* rbase, int64_t n, const void* vals, const uint16_t* dstl,
+                          unsigned long long* mb, hipStream_t s);
 // Min programs (kind: kCC, kSsspUnit, kSsspWeighted): vals[k] = message on
 // slot k from the current values (kInf for sources outside `active`; NULL:
 // all).  wslot: weights in slot order, wbytes (1 or 4) each (kSsspWeighted
@@ -278,8 +293,9 @@ hipError_t launch_pb_spread_min(int kind, const PbSpreadItem* items, int64_t nit
 // Per receiver v, best = the minimum message of its in-edges; when best <
 // value(v) the mailbox takes it and v's bit in `improved` is set (the
 // outcome of launch_min_pull).  Mailboxes unreached on entry.
-hipError_t launch_pb_fold_min(const PbFoldItem* items, int64_t nitems, const int64_t* run_off, const int64_t* btotal,
-                              const int64_t* rpre, const int64_t* rbase, int64_t n, const uint32_t* vals,
+hipError_t launch_pb_fold_min(const PbFoldItem* items, int64_t nitems, const int64_t* run_off,
+                              const int64_t* rpre, const int64_t* btotal, const int64_t* chunk_off,
+                              const PbChunk* chunks, const int64_t* rbase, int64_t n, const uint32_t* vals,
                               const uint16_t* dstl, uint2* vm, uint32_t* improved, hipStream_t s);
 
 // In-place exclusive scan of P[0..count) with P[count] = total; `blocks`
