@@ -92,10 +92,11 @@ typedef enum { VC_PAGERANK = 0, VC_CC_HASHMIN = 1, VC_SSSP = 2, VC_PPR = 3 } vc_
  *                    or minimum with the pull form's mailbox rule; a source
  *                    outside the CC / SSSP frontier sends "unreached").
  *                    Both passes stream instead of gathering one message per
- *                    edge from HBM.  Memory: 4 bytes of indices per edge (8
- *                    with weights) and 16 per non-empty (tile, bin) pair,
- *                    shared by a graph's views, plus 8 bytes of message
- *                    slots per edge per graph object; built on first use.
+ *                    edge from HBM.  Memory: 4 bytes of indices per edge (5
+ *                    with weights below 256, 8 with larger ones), 16 per
+ *                    non-empty (tile, bin) pair and 16 per 64 edges, shared
+ *                    by a graph's views, plus 8 bytes of message slots per
+ *                    edge per graph object; built on first use.
  *                    Graphs beyond about 2^27 vertices are refused
  *                    (VC_ERR_UNSUPPORTED), as is vc_run_multi_source;
  *   VC_SCHED_AUTO    CC / SSSP, per superstep: pull for dense frontiers

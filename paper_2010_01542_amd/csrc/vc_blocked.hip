@@ -6,16 +6,16 @@
 // message array; on a billion-edge graph most of those gathers miss the
 // caches, and even those that hit cost one cache-line request per edge.
 // Here the edges are laid out once by bucket (source tile, destination bin):
-// a source tile's messages fit in LDS (2^14 vertices, 128 KiB), a
-// destination bin's mailboxes too (2^12 vertices, 32 KiB).  A superstep is
-// two streaming passes:
+// a source tile's messages fit in LDS (2^14 vertices: 64 KiB of binary32 or
+// 128 KiB of uint64 messages), a destination bin's mailboxes too (2^12
+// vertices, 32 KiB).  A superstep is two streaming passes:
 //   1. spread: per source tile, its messages are staged in LDS, then every
 //      slot of the tile's buckets (contiguous, tile-major order) gets
-//      vals[k] = message of its source: 2-byte index in, 8 bytes out;
-//   2. fold: per destination bin, its runs (one per source tile) are read
-//      and summed into LDS mailboxes, which are then written to the mailbox
-//      array (added atomically when a bin of hubs is split over several
-//      workgroups).
+//      vals[k] = message of its source: 2-byte index in, 4 or 8 bytes out;
+//   2. fold: per destination bin, its runs (one per source tile that has
+//      edges into it) are read and summed into LDS mailboxes, which are then
+//      written to the mailbox array (added atomically when a bin of hubs is
+//      split over several workgroups).
 // Sums stay exact (uint64 fixed point), so results equal the pull form's.
 // Messages are uint64 fixed point or binary32 (half the slot bytes).  The
 // same two passes serve the dense supersteps of the min programs (CC,
