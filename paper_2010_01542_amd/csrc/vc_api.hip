@@ -372,7 +372,7 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
   VC_TRY(hipStreamSynchronize(s));
   VC_TRY(g->pb_chunks.ensure((size_t)(nchunks + 1) * sizeof(vc::PbChunk)));
   VC_TRY(vc::launch_pb_chunks(g->pb_run_off.as<int64_t>(), g->pb_rpre.as<int64_t>(), g->pb_chunk_off.as<int64_t>(),
-                              bins, g->pb_chunks.as<vc::PbChunk>(), s));
+                              bins, nchunks, g->pb_chunks.as<vc::PbChunk>(), s));
   // spread items: a tile's slots are contiguous; pieces of up to scap slots
   // (the tile's messages are loaded once per piece; 64 Ki slots balance
   // that load against the spread of work over the compute units best at

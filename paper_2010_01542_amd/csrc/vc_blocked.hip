@@ -226,26 +226,41 @@ __global__ __launch_bounds__(kWG) void k_pb_chunk_counts(const int64_t* __restri
   if (b < bins) nchunks[b] = (btotal[b] + 63) >> 6;
 }
 
-// Per bin b (one thread): for chunk c (positions 64 c .. 64 c + 63 of the
-// bin's concatenation of runs), the run holding position 64 c and a mask of
-// the run starts inside it (bit i: a run starts at 64 c + i, i >= 1).  The
-// fold then finds any position's run with one masked popcount.
+// One thread per chunk: chunk c of bin b (positions 64 c .. 64 c + 63 of
+// the bin's concatenation of runs) gets the run holding position 64 c and a
+// mask of the run starts inside it (bit i: a run starts at 64 c + i,
+// i >= 1).  The fold then finds any position's run with one masked
+// popcount.  Bin and run are found by binary search (chunk_off: exclusive
+// scan of the bins' chunk counts, nchunks in all).
 __global__ __launch_bounds__(kWG) void k_pb_chunks(const int64_t* __restrict__ run_off,
                                                    const int64_t* __restrict__ rpre,
                                                    const int64_t* __restrict__ chunk_off, int64_t bins,
-                                                   PbChunk* __restrict__ chunks) {
-  const int64_t b = gid();
-  if (b >= bins) return;
-  const int64_t* P = rpre + run_off[b];
-  const int64_t nr = run_off[b + 1] - run_off[b];
-  const int64_t c0 = chunk_off[b], nch = chunk_off[b + 1] - c0;
-  int64_t r = 0;  // run holding position 64 c (P[0] = 0, runs non-empty)
-  for (int64_t c = 0; c < nch; ++c) {
-    const int64_t base = c * 64;
-    while (r + 1 < nr && P[r + 1] <= base) ++r;
+                                                   int64_t nchunks, PbChunk* __restrict__ chunks) {
+  for (int64_t g = gid(); g < nchunks; g += grid_threads()) {
+    int64_t lo = 0, hi = bins - 1;  // the bin: last b with chunk_off[b] <= g (a bin with chunks)
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (chunk_off[mid] <= g)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const int64_t b = lo;
+    const int64_t base = (g - chunk_off[b]) * 64;
+    const int64_t* P = rpre + run_off[b];
+    const int64_t nr = run_off[b + 1] - run_off[b];
+    lo = 0;
+    hi = nr - 1;  // the run: last r with P[r] <= base (P[0] = 0, runs non-empty)
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (P[mid] <= base)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
     unsigned long long starts = 0;
-    for (int64_t t = r + 1; t < nr && P[t] <= base + 63; ++t) starts |= 1ull << (P[t] - base);
-    chunks[c0 + c] = PbChunk{(int32_t)r, 0, starts};
+    for (int64_t t = lo + 1; t < nr && P[t] <= base + 63; ++t) starts |= 1ull << (P[t] - base);
+    chunks[g] = PbChunk{(int32_t)lo, 0, starts};
   }
 }
 
@@ -552,8 +567,10 @@ hipError_t launch_pb_chunk_counts(const int64_t* btotal, int64_t bins, int64_t* 
 }
 
 hipError_t launch_pb_chunks(const int64_t* run_off, const int64_t* rpre, const int64_t* chunk_off, int64_t bins,
-                            PbChunk* chunks, hipStream_t s) {
-  hipLaunchKernelGGL(k_pb_chunks, dim3(grid_for(bins)), dim3(kWG), 0, s, run_off, rpre, chunk_off, bins, chunks);
+                            int64_t nchunks, PbChunk* chunks, hipStream_t s) {
+  if (nchunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pb_chunks, dim3(grid_stride_for(nchunks)), dim3(kWG), 0, s, run_off, rpre, chunk_off, bins,
+                     nchunks, chunks);
   return hipGetLastError();
 }
 

@@ -269,7 +269,7 @@ hipError_t launch_pb_fold_items(const int64_t* btotal, int64_t bins, const int64
 // with chunk_off their exclusive scan, every chunk's PbChunk.
 hipError_t launch_pb_chunk_counts(const int64_t* btotal, int64_t bins, int64_t* nchunks, hipStream_t s);
 hipError_t launch_pb_chunks(const int64_t* run_off, const int64_t* rpre, const int64_t* chunk_off, int64_t bins,
-                            PbChunk* chunks, hipStream_t s);
+                            int64_t nchunks, PbChunk* chunks, hipStream_t s);
 // vals[k] = msg[tile's first vertex + srcl[k]] for every slot of every item;
 // msg / vals hold binary32 messages when f32msg, else uint64 fixed point.
 hipError_t launch_pb_spread(bool f32msg, const PbSpreadItem* items, int64_t nitems, int64_t n, int shift,
