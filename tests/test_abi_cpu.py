@@ -69,6 +69,35 @@ def test_struct_layout_matches_header(tmp_path):
             assert int(got[f"{cname} {fname}"]) == getattr(cls, fname).offset, (cname, fname)
 
 
+def test_enum_values_match_header(tmp_path):
+    """Every enumerator the binding mirrors has the header's value."""
+    names = {
+        "VC_OK": vc.OK, "VC_ERR_INVALID_ARG": vc.ERR_INVALID_ARG, "VC_ERR_BAD_GRAPH": vc.ERR_BAD_GRAPH,
+        "VC_ERR_OUT_OF_MEMORY": vc.ERR_OUT_OF_MEMORY, "VC_ERR_HIP": vc.ERR_HIP,
+        "VC_ERR_UNSUPPORTED": vc.ERR_UNSUPPORTED, "VC_ERR_NOT_CONVERGED": vc.ERR_NOT_CONVERGED,
+        "VC_PAGERANK": vc.PAGERANK, "VC_CC_HASHMIN": vc.CC_HASHMIN, "VC_SSSP": vc.SSSP, "VC_PPR": vc.PPR,
+        "VC_SCHED_AUTO": vc.SCHED_AUTO, "VC_SCHED_VERTEX": vc.SCHED_VERTEX, "VC_SCHED_EDGE": vc.SCHED_EDGE,
+        "VC_SCHED_PULL": vc.SCHED_PULL, "VC_SCHED_BLOCKED": vc.SCHED_BLOCKED,
+        "VC_OPT_NO_HUB_AGGREGATION": vc.OPT_NO_HUB_AGGREGATION,
+        "VC_OPT_NO_TEST_BEFORE_ATOMIC": vc.OPT_NO_TEST_BEFORE_ATOMIC,
+        "VC_OPT_F32_ACCUMULATE": vc.OPT_F32_ACCUMULATE, "VC_OPT_GRAPH_CAPTURE": vc.OPT_GRAPH_CAPTURE,
+        "VC_OPT_F32_MESSAGES": vc.OPT_F32_MESSAGES,
+        "VC_ROUTE_AUTO": vc.ROUTE_AUTO, "VC_ROUTE_LANES": vc.ROUTE_LANES, "VC_ROUTE_WORKER": vc.ROUTE_WORKER,
+    }
+    names.update({f"VC_COMBINE_{k.upper()}": v for k, v in vc.COMBINERS.items()})
+    lines = ["#include <stdio.h>", '#include "vc.h"', "int main(void) {"]
+    lines += [f'printf("{k} %ld\\n", (long){k});' for k in names]
+    lines.append("return 0; }")
+    src = tmp_path / "enums.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "enums"
+    subprocess.check_call(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"), "-I",
+                           "/opt/rocm/include", "-o", str(exe), str(src)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    for k, v in names.items():
+        assert int(got[k]) == v, k
+
+
 def test_argument_errors_need_no_device():
     lib = vc.load()
     h = ctypes.c_void_p()
