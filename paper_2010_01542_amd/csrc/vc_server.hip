@@ -729,9 +729,10 @@ bool lane_eligible(const GraphEntry& ge, const vc_request& r, bool rank) {
 // many lanes are busy, so it pays once the requests it would serve would cost
 // more run alone: when the automatically routed, lane-eligible requests of
 // graph gid waiting in the worker queue add up (in expected worker time) to
-// one generation's time (supersteps per request times superstep time for
-// the lane chunks they fill; T updates for rank lanes), they move to the
-// lane table together.  Caller holds s->mu.
+// kLaneMargin generations' time (supersteps per request times superstep
+// time for the lane chunks they fill; T updates for rank lanes), they move
+// to the lane table together.  The margin covers what the estimates miss:
+// a generation shares the GPU with the workers' runs.  Caller holds s->mu.
 void batch_from_queue(vc_server s, int32_t gid, bool rank) {
   GraphEntry& ge = s->graphs[gid];
   int64_t count = 0, max_t = 0;
@@ -759,7 +760,7 @@ void batch_from_queue(vc_server s, int32_t gid, bool rank) {
     const double steps = t.steps.n ? t.steps.v : 20.0;
     generation = steps * step * (double)((count + t.K - 1) / t.K);
   }
-  if (alone < generation) return;
+  if (alone < kLaneMargin * generation) return;
   std::deque<Job>& dest = rank ? ge.ranks->queue : ge.lanes->queue;
   for (auto it = s->queue.begin(); it != s->queue.end();) {
     if (it->movable && it->req.graph == gid && lane_eligible(ge, it->req, rank)) {
