@@ -1101,8 +1101,7 @@ vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held,
   held += g->dense_parts.bytes() + g->csc_parts.bytes();
   if (bytes_held) *bytes_held = held;
   if (bytes_run) {
-    // workspace of the program plus the transpose the pull form reads (or,
-    // for PageRank / PPR on large graphs, the blocked layout)
+    // workspace of the program plus the transpose the pull form reads
     const size_t want = workspace_bytes(g->n, g->m, program, vc::kDefaultTile);
     size_t have = 0;
     if (program == VC_PAGERANK || program == VC_PPR)
@@ -1114,16 +1113,22 @@ vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held,
                             ((g->flags & VC_GRAPH_SYMMETRIC) ? 0 : (size_t)g->m * (g->w ? 8 : 4));
     const size_t csc_have = g->csc_off.bytes + g->csc_src.bytes + g->csc_w.bytes + g->csc_parts.bytes();
     size_t csc_need = g->csc_ready ? 0 : (csc_want > csc_have ? csc_want - csc_have : 0);
+    // the blocked layout (shared with the base of a view) and this object's
+    // message slots, where AUTO would take the blocked form; CC / SSSP keep
+    // the transpose too (a captured loop pulls)
     size_t pb_need = 0;
+    const vc_graph owner = g->is_view ? g->base : g;
+    const size_t pb_more = (owner->pb.ready ? 0 : pb_layout_bytes(g)) +
+                           (g->pb_vals.bytes >= (size_t)g->m * 8 ? 0 : (size_t)g->m * 8 + 8);
     if (program == VC_PAGERANK || program == VC_PPR) {
       vc_params dp;
       vc_params_default(&dp);
       if (rank_schedule(g, dp, true) == VC_SCHED_BLOCKED) {
         csc_need = 0;  // the blocked schedule reads its own layout, not the transpose
-        const vc_graph owner = g->is_view ? g->base : g;
-        pb_need = (owner->pb.ready ? 0 : pb_layout_bytes(g)) +
-                  (g->pb_vals.bytes >= (size_t)g->m * 8 ? 0 : (size_t)g->m * 8 + 8);
+        pb_need = pb_more;
       }
+    } else if (min_blocked(g, false)) {
+      pb_need = pb_more;
     }
     *bytes_run = (want > have ? want - have : 0) + csc_need + pb_need;
   }
