@@ -305,7 +305,8 @@ vc_status vc_batch_destroy(vc_batch b);
 vc_status vc_batch_autotune(vc_batch b, const vc_params* base, hipStream_t stream, vc_params* best);
 
 /* Autotuner: times `program` on this graph under candidate work distributions
- * (schedule, merge-path tile, pull threshold, captured loop), keeps the
+ * (schedule, blocked form included for PageRank / PPR, merge-path tile, pull
+ * threshold, captured loop), keeps the
  * fastest as the graph's setting for that program (used by later runs with
  * VC_SCHED_AUTO, tile 0 and pull_fraction 0) and returns it in *best (host).
  * base (host, may be NULL) supplies T, damping and source.  Runs the program

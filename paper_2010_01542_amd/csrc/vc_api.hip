@@ -1461,13 +1461,16 @@ namespace {
 
 // Candidate distributions for a program: PageRank / PPR vary schedule, tile
 // and capture; CC / SSSP vary the pull threshold, tile and capture.
-std::vector<vc_params> tune_candidates(vc_program program, const vc_params& base) {
+std::vector<vc_params> tune_candidates(vc_program program, const vc_params& base, bool blocked_ok) {
   std::vector<vc_params> out;
   const int32_t tiles[] = {1024, 2048, 4096};
   for (uint32_t capture : {0u, (uint32_t)VC_OPT_GRAPH_CAPTURE})
     for (int32_t tile : tiles) {
       if (program == VC_PAGERANK || program == VC_PPR) {
-        for (vc_schedule sc : {VC_SCHED_PULL, VC_SCHED_EDGE}) {
+        for (vc_schedule sc : {VC_SCHED_PULL, VC_SCHED_EDGE, VC_SCHED_BLOCKED}) {
+          // the blocked form has no tile, and sums in fixed point only
+          if (sc == VC_SCHED_BLOCKED && (!blocked_ok || tile != tiles[0] || (base.options & VC_OPT_F32_ACCUMULATE)))
+            continue;
           vc_params p = base;
           p.schedule = sc;
           p.tile = tile;
@@ -1524,7 +1527,7 @@ vc_status vc_graph_autotune(vc_graph g, vc_program program, const vc_params* bas
   DevBuf out;
   VC_TRY(out.ensure((size_t)g->n * 4));
   vc_params pick = b;
-  vc_status st = pick_fastest(tune_candidates(program, b),
+  vc_status st = pick_fastest(tune_candidates(program, b, g->m > 0 && pb_supported(g)),
                               [&](const vc_params& c) { return vc_run(g, program, &c, out.p, stream, nullptr); }, &pick);
   if (st != VC_OK) return st;
   g->tuned[program] = true;
@@ -1547,7 +1550,7 @@ vc_status vc_batch_autotune(vc_batch b, const vc_params* base, hipStream_t strea
   VC_TRY(out.ensure((size_t)b->g->n * 4));
   vc_params pick = p;
   vc_status st = pick_fastest(
-      tune_candidates(VC_SSSP, p),
+      tune_candidates(VC_SSSP, p, false),
       [&](const vc_params& c) { return vc_batch_run(b, &c, out.as<uint32_t>(), stream, nullptr); }, &pick);
   if (st != VC_OK) return st;
   b->g->tuned[VC_SSSP] = true;
