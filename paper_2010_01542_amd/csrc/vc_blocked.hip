@@ -266,6 +266,7 @@ __global__ __launch_bounds__(kWG) void k_pb_chunks(const int64_t* __restrict__ r
 
 // Pass 1: one workgroup per spread item; the tile's messages in LDS.
 constexpr int kSpreadWG = 1024;
+constexpr int kStageU = 4;  // a min window's loads per thread in flight while staging
 
 template <class M>
 __global__ __launch_bounds__(kSpreadWG) void k_pb_spread(const PbSpreadItem* __restrict__ items, int64_t n, int shift,
@@ -294,6 +295,28 @@ __global__ __launch_bounds__(kSpreadWG) void k_pb_spread(const PbSpreadItem* __r
   }
 }
 
+// wmin[i] = value of vertex u0 + i, or kInf when ACT and its frontier bit
+// is clear, for i < wl (wl > 0).  Clamped loads, so they issue together.
+template <bool ACT>
+__device__ __forceinline__ void stage_min_window(uint32_t* wmin, const uint2* __restrict__ vm,
+                                                 const uint32_t* __restrict__ active, int64_t u0, int64_t wl) {
+  for (int64_t i0 = threadIdx.x; i0 < wl; i0 += (int64_t)kSpreadWG * kStageU) {
+    uint32_t v[kStageU], on[kStageU];
+#pragma unroll
+    for (int s = 0; s < kStageU; ++s) {
+      const int64_t i = i0 + (int64_t)s * kSpreadWG;
+      const int64_t u = u0 + (i < wl ? i : wl - 1);
+      v[s] = vm[u].x;
+      on[s] = ACT ? (active[u >> 5] >> (u & 31)) & 1u : 1u;
+    }
+#pragma unroll
+    for (int s = 0; s < kStageU; ++s) {
+      const int64_t i = i0 + (int64_t)s * kSpreadWG;
+      if (i < wl) wmin[i] = on[s] ? v[s] : kInf;
+    }
+  }
+}
+
 // Pass 1 of a min program (CC, SSSP): the tile's values in LDS, a source
 // that is not in the frontier (bit clear in `active`; NULL: every vertex)
 // reading as unreached, then vals[k] = the message on slot k: the value
@@ -312,20 +335,22 @@ __global__ __launch_bounds__(kSpreadWG) void k_pb_spread_min(const PbSpreadItem*
   const PbSpreadItem it = items[blockIdx.x];
   const int64_t u0 = (int64_t)it.t << shift;
   const int64_t wl = (n - u0 < (1ll << shift)) ? n - u0 : (1ll << shift);
-  for (int64_t i = threadIdx.x; i < wl; i += kSpreadWG) {
-    const int64_t u = u0 + i;
-    const bool on = !active || ((active[u >> 5] >> (u & 31)) & 1u);
-    wmin[i] = on ? vm[u].x : kInf;
-  }
+  if (active)
+    stage_min_window<true>(wmin, vm, active, u0, wl);
+  else
+    stage_min_window<false>(wmin, vm, active, u0, wl);
   __syncthreads();
   for (int64_t base = it.k0 + threadIdx.x; base < it.k1; base += (int64_t)kSpreadWG * U) {
     uint16_t x[U];
     uint32_t wv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+      // Slots past the item's end load its last slot (k1 > k0) and store
+      // nothing: unconditional loads all issue before the first wait.
       const int64_t k = base + (int64_t)u * kSpreadWG;
-      x[u] = k < it.k1 ? srcl[k] : 0;
-      wv[u] = (KIND == kSsspWeighted && k < it.k1) ? (uint32_t)wslot[k] : 1u;
+      const int64_t kc = k < it.k1 ? k : it.k1 - 1;
+      x[u] = srcl[kc];
+      wv[u] = KIND == kSsspWeighted ? (uint32_t)wslot[kc] : 1u;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -392,24 +417,28 @@ struct FoldMin {
     if (v != kInf) atomicMin(&box[d], v);
   }
   __device__ __forceinline__ void flush(const PbFoldItem& it, const Box* box, int64_t n) const {
+    constexpr int R = (1 << kPbDstShift) / kFoldWG;  // rounds; every lane runs every round
     const int64_t v0 = (int64_t)it.b << kPbDstShift;  // a multiple of 64: lanes 0..31 and 32..63 fill one word each
     const int lane = threadIdx.x & 63;
-    for (int i = threadIdx.x; i < (1 << kPbDstShift); i += kFoldWG) {  // every lane runs every round
-      const int64_t v = v0 + i;
+    uint32_t best[R];
+    uint2 cur[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {  // all rounds' loads first, clamped to vertex n - 1 (v0 < n), so they issue together
+      const int64_t v = v0 + threadIdx.x + r * kFoldWG;
+      best[r] = box[threadIdx.x + r * kFoldWG];
+      cur[r] = vm[v < n ? v : n - 1];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t v = v0 + threadIdx.x + r * kFoldWG;
       bool imp = false;
-      if (v < n) {
-        const uint32_t best = box[i];
-        if (best != kInf) {
-          const uint2 cur = vm[v];
-          if (best < cur.x) {
-            if (it.whole) {
-              vm[v].y = best;
-              imp = true;
-            } else if (best < cur.y) {
-              const uint32_t old = atomicMin(&reinterpret_cast<uint32_t*>(vm)[2 * v + 1], best);
-              imp = old == kInf;  // the first improver of v sets its bit
-            }
-          }
+      if (v < n && best[r] != kInf && best[r] < cur[r].x) {
+        if (it.whole) {
+          vm[v].y = best[r];
+          imp = true;
+        } else if (best[r] < cur[r].y) {
+          const uint32_t old = atomicMin(&reinterpret_cast<uint32_t*>(vm)[2 * v + 1], best[r]);
+          imp = old == kInf;  // the first improver of v sets its bit
         }
       }
       const unsigned long long mask = __ballot(imp);
