@@ -197,6 +197,36 @@ def test_blocked_pagerank_matches_oracle_and_pull(device, relabel):
 
 
 @pytest.mark.parametrize("relabel", [True, False])
+def test_blocked_pagerank_every_kind_of_bin(device, relabel):
+    """Destination bins of the blocked form come in three kinds: one fold
+    item (mailboxes stored), split over several items (mailboxes added) and
+    without in-edges (no item).  R-MAT plus a tail of isolated vertices
+    (three empty bins and a ragged last one) has all three in either vertex
+    order (int32 offsets when not relabelled).  Ranks equal the pull form's
+    bit for bit at every T from 1 to 3 for both message kinds, for PPR from
+    a hub, from a vertex without in-edges and from an isolated one, and for
+    runs that follow each other on one graph (a last superstep leaves its
+    sums in the mailboxes)."""
+    from paper_2010_01542_amd import vc
+    print(f"case blocked pagerank every kind of bin relabel={relabel}", flush=True)
+    r = rmatgen.rmat(17, 8, seed=3)
+    src = np.repeat(np.arange(r.n), np.diff(np.asarray(r.off, np.int64)))
+    d = rmatgen.raw_csr(r.n + 3 * 4096 + 100, src, r.dst, offset_dtype=np.int64 if relabel else np.int32)
+    g = make(d, relabel=relabel)
+    for T in (1, 2, 3):
+        for opt in (0, vc.OPT_F32_MESSAGES):
+            a = run_gpu(g, "pagerank", T=T, schedule="blocked", options=opt)[0]
+            b = run_gpu(g, "pagerank", T=T, schedule="pull", options=opt)[0]
+            assert np.array_equal(a, b), (T, opt)
+    indeg = np.bincount(np.asarray(d.dst), minlength=d.n)
+    for s in (int(indeg.argmax()), int(np.flatnonzero(indeg == 0)[0]), d.n - 1):
+        a = run_gpu(g, "ppr", T=4, source=s, schedule="blocked")[0]
+        b = run_gpu(g, "ppr", T=4, source=s, schedule="pull")[0]
+        assert np.array_equal(a, b), s
+    check_rank(d, g, "pagerank", T=5, schedule="blocked")
+
+
+@pytest.mark.parametrize("relabel", [True, False])
 def test_f32_messages_meet_tolerance_and_agree_across_schedules(device, relabel):
     """Binary32 messages summed exactly in fixed point: within the PageRank
     bars of the oracle, and one result for every schedule (each message is
