@@ -259,7 +259,7 @@ size_t pb_layout_bytes(vc_graph g) {  // the shared, read-only part
   if (shift == 0) return 0;
   const size_t bins = (size_t)vc::pb_bins(g->n), tiles = (size_t)vc::pb_tiles(g->n, shift), m = (size_t)g->m;
   const size_t runs = std::min(bins * tiles, m);  // non-empty buckets
-  return m * (g->w ? 8 : 4) + runs * 16 + (bins + 1) * 24 + (m / 64 + bins + 1) * sizeof(vc::PbChunk) +
+  return m * (g->w ? 8 : 4) + runs * 16 + (bins + 1) * 25 + (m / 64 + bins + 1) * sizeof(vc::PbChunk) +
          (m / 4096 + bins + 2) * sizeof(vc::PbFoldItem) +
          (m / 16384 + tiles + 2) * sizeof(vc::PbSpreadItem);
 }
@@ -356,6 +356,18 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
   VC_TRY(hipMemcpyAsync(&totals[1], nitems.as<int64_t>() + bins, 8, hipMemcpyDeviceToHost, s));
   VC_TRY(hipStreamSynchronize(s));
   const int64_t nfold = totals[1];
+  // each bin's kind from its item count (PageRank's update reads and resets
+  // only the mailboxes that need it)
+  std::vector<int64_t> item_off((size_t)bins + 1);
+  VC_TRY(hipMemcpyAsync(item_off.data(), nitems.p, item_off.size() * 8, hipMemcpyDeviceToHost, s));
+  VC_TRY(hipStreamSynchronize(s));
+  std::vector<uint8_t> kinds((size_t)bins);
+  for (int64_t b = 0; b < bins; ++b) {
+    const int64_t k = item_off[(size_t)b + 1] - item_off[(size_t)b];
+    kinds[(size_t)b] = k == 0 ? vc::kBinEmpty : k == 1 ? vc::kBinWhole : vc::kBinSplit;
+  }
+  VC_TRY(g->pb_kinds.ensure(kinds.size() + 16));
+  VC_TRY(hipMemcpyAsync(g->pb_kinds.p, kinds.data(), kinds.size(), hipMemcpyHostToDevice, s));
   VC_TRY(g->pb_rpre.ensure((size_t)(totals[0] + 1) * 8));
   VC_TRY(g->pb_rbase.ensure((size_t)(totals[0] + 1) * 8));
   VC_TRY(vc::launch_pb_tables(true, starts_d.as<int64_t>(), bins, tiles, fcap, nullptr, nullptr, nullptr,
@@ -401,6 +413,7 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
   pb.chunks = g->pb_chunks.as<vc::PbChunk>();
   pb.spread = g->pb_spread.as<vc::PbSpreadItem>();
   pb.fold = g->pb_fold.as<vc::PbFoldItem>();
+  pb.kinds = g->pb_kinds.as<uint8_t>();
   pb.shift = shift;
   pb.tiles = tiles;
   pb.nspread = (int64_t)sitems.size();
@@ -490,6 +503,9 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
     }
     if (st != VC_OK) return st;
   }
+  // the blocked form's fold stores every mailbox of a one-item bin and
+  // leaves bins without in-edges untouched: the update resets only the rest
+  const uint8_t* pb_kinds = sched == VC_SCHED_BLOCKED && g->m > 0 ? g->pb.kinds : nullptr;
   if (p.options & VC_OPT_GRAPH_CAPTURE) {
     // the whole loop as one captured HIP graph; ranks land in the staging
     // buffer (fixed address) and are copied / un-permuted afterwards
@@ -520,7 +536,8 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
             e = vc::launch_pr_scatter_vertex(mode, g->off, g->off64, g->dst, n, contrib, mb, cs);
         }
         if (e == hipSuccess)
-          e = vc::launch_pr_apply(mode, g->off, g->off64, n, teleport, d, source, mb, contrib, stage, step + 1 == T, cs);
+          e = vc::launch_pr_apply(mode, g->off, g->off64, n, teleport, d, source, mb, contrib, stage, step + 1 == T, cs,
+                                  pb_kinds);
       }
       hipGraph_t graph = nullptr;
       const hipError_t e2 = hipStreamEndCapture(cs, &graph);
@@ -561,7 +578,8 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
         VC_TRY(vc::launch_pr_scatter_vertex(mode, g->off, g->off64, g->dst, n, contrib, mb, s));
     }
     if (timed) VC_TRY(hipEventRecord(g->events[3 * step + 1], s));
-    VC_TRY(vc::launch_pr_apply(mode, g->off, g->off64, n, teleport, d, source, mb, contrib, rank_out, step + 1 == T, s));
+    VC_TRY(vc::launch_pr_apply(mode, g->off, g->off64, n, teleport, d, source, mb, contrib, rank_out, step + 1 == T, s,
+                               pb_kinds));
     if (timed) VC_TRY(hipEventRecord(g->events[3 * step + 2], s));
     rec.step(step, n, g->m, sched);
   }

@@ -380,7 +380,7 @@ constexpr int kFoldChunks = (int)(kPbMaxItemPositions / 64 + 1);  // an item's c
 static_assert((1 << kPbDstShift) % kFoldWG == 0, "the min fold's flush runs every lane in every round");
 
 // The combiners of the fold.  Sum (PageRank): exact fixed-point mailboxes,
-// stored for a bin that is one item, added otherwise.  Min (CC, SSSP): as the
+// all stored for a bin that is one item, added otherwise.  Min (CC, SSSP): as the
 // pull form, a receiver whose best message lowers its value takes it into
 // its mailbox (stored for a bin that is one item, an atomic min otherwise)
 // and its improvement bit is set.
@@ -398,10 +398,9 @@ struct FoldSum {
     const int64_t v0 = (int64_t)it.b << kPbDstShift;
     for (int i = threadIdx.x; i < (1 << kPbDstShift) && v0 + i < n; i += kFoldWG) {
       const unsigned long long x = box[i];
-      if (!x) continue;
       if (it.whole)
-        mb[v0 + i] = x;  // the only item of this bin
-      else
+        mb[v0 + i] = x;  // the only item of this bin: every mailbox stored, so none needs a reset
+      else if (x)
         atomicAdd(&mb[v0 + i], x);
     }
   }

@@ -135,6 +135,7 @@ struct PbShared {
   const PbChunk* chunks = nullptr;
   const PbSpreadItem* spread = nullptr;
   const PbFoldItem* fold = nullptr;
+  const uint8_t* kinds = nullptr;  // PbBinKind of every destination bin
   int64_t nspread = 0, nfold = 0, tiles = 0;
   int shift = 0;
   bool ready = false;
@@ -181,7 +182,7 @@ struct vc_graph_s {
   // read-only part in buffers owned by the base graph, referenced by `pb`
   // in the base and in its views; each object owns its message slots
   vc::DevBuf pb_srcl, pb_dstl, pb_w, pb_run_off, pb_btotal, pb_rpre, pb_rbase, pb_chunk_off, pb_chunks, pb_spread,
-      pb_fold;
+      pb_fold, pb_kinds;
   vc::PbShared pb;
   vc::DevBuf pb_vals;
   std::mutex pb_mu;         // base: serialises the layout build between views

@@ -67,8 +67,13 @@ hipError_t launch_pr_scatter_vertex(int mode, const void* off, bool off64, const
 hipError_t launch_pr_scatter_mp(int mode, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
                                 const int32_t* tile_v, int64_t tile, int64_t ntiles, const void* contrib, void* mb,
                                 hipStream_t s);
+// The vertex update: rank from the summed mailbox, then the next message (or
+// the rank into out when last).  kinds: NULL (every mailbox is read and
+// cleared), or the blocked layout's kind of every destination bin, which
+// says which mailboxes hold sums and which must be cleared (PbBinKind).
 hipError_t launch_pr_apply(int mode, const void* off, bool off64, int64_t n, double teleport, double damping,
-                           int64_t source, void* mb, void* contrib, float* out, bool last, hipStream_t s);
+                           int64_t source, void* mb, void* contrib, float* out, bool last, hipStream_t s,
+                           const uint8_t* kinds = nullptr);
 
 // Hash-min CC and SSSP.  vm holds (value, mailbox) pairs.
 // ids: the label each vertex starts CC with (its original id after
@@ -212,6 +217,11 @@ hipError_t launch_combine(int op, const void* off, bool off64, const int32_t* ds
 constexpr int kPbDstShift = 12;
 constexpr int64_t kPbMaxBuckets = 1ll << 28;
 constexpr int64_t kPbMaxItemPositions = 1ll << 16;  // positions per fold item (its chunk descriptors fit LDS)
+// Destination bins of the blocked form: without in-edges (no fold item; the
+// bin's mailboxes stay zero), one fold item (the fold stores every mailbox
+// of the bin, zeros included), or split over several items (the fold adds
+// into the mailboxes, which must be zero before it).
+enum PbBinKind : uint8_t { kBinEmpty = 0, kBinWhole = 1, kBinSplit = 2 };
 // Spread item: slots [k0, k1) of source tile t.
 struct PbSpreadItem {
   int32_t t, pad;

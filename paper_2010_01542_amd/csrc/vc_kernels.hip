@@ -164,24 +164,30 @@ __global__ __launch_bounds__(kWG) void k_pr_scatter_mp(const OffT* __restrict__ 
 }
 
 // rank = teleport + d * (sum of messages); reset the mailbox; next message.
+// With the blocked form's bin kinds, a bin without in-edges has sum zero
+// (its mailboxes are not read) and only split bins' mailboxes are reset
+// (the fold stores every mailbox of a one-item bin).
 template <class OffT, class M, class S>
 __global__ __launch_bounds__(kWG) void k_pr_apply(const OffT* __restrict__ off, int64_t n, double teleport,
                                                   double damping, int64_t source, S* __restrict__ mb,
-                                                  M* __restrict__ contrib, float* __restrict__ out, int last) {
+                                                  M* __restrict__ contrib, float* __restrict__ out, int last,
+                                                  const uint8_t* __restrict__ kinds) {
   const int64_t v = gid();
   if (v >= n) return;
+  const int kind = kinds ? kinds[v >> kPbDstShift] : kBinSplit;
+  const S x = kind != kBinEmpty ? mb[v] : S(0);
   const double tele = source >= 0 ? (v == source ? teleport : 0.0) : teleport;
   double r;
   if constexpr (sizeof(S) == 8) {
-    r = fma(damping, (double)mb[v] * kFixInv, tele);
+    r = fma(damping, (double)x * kFixInv, tele);
   } else {
-    r = (double)fmaf((float)damping, mb[v], (float)tele);
+    r = (double)fmaf((float)damping, x, (float)tele);
   }
   if (last) {
     out[v] = (float)r;
     return;
   }
-  mb[v] = S(0);
+  if (kind == kBinSplit) mb[v] = S(0);
   const int64_t deg = (int64_t)off[v + 1] - (int64_t)off[v];
   contrib[v] = rank_msg<M, S>(r, deg);
 }
@@ -494,7 +500,8 @@ namespace {
 template <class M, class S>
 hipError_t pr_launch_all(int what, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
                          const int32_t* tile_v, int64_t tile, int64_t ntiles, double a, double b, int64_t source,
-                         void* contrib, void* mb, float* out, bool last, hipStream_t s) {
+                         void* contrib, void* mb, float* out, bool last, hipStream_t s,
+                         const uint8_t* kinds = nullptr) {
   M* c = static_cast<M*>(contrib);
   S* mbx = static_cast<S*>(mb);
   switch (what) {
@@ -527,27 +534,28 @@ hipError_t pr_launch_all(int what, const void* off, bool off64, const int32_t* d
     default:  // apply; a = teleport, b = damping
       if (off64)
         hipLaunchKernelGGL((k_pr_apply<int64_t, M, S>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int64_t*)off, n,
-                           a, b, source, mbx, c, out, (int)last);
+                           a, b, source, mbx, c, out, (int)last, kinds);
       else
         hipLaunchKernelGGL((k_pr_apply<int32_t, M, S>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int32_t*)off, n,
-                           a, b, source, mbx, c, out, (int)last);
+                           a, b, source, mbx, c, out, (int)last, kinds);
   }
   return hipGetLastError();
 }
 
 inline hipError_t pr_launch(int mode, int what, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
                             const int32_t* tile_v, int64_t tile, int64_t ntiles, double a, double b, int64_t source,
-                            void* contrib, void* mb, float* out, bool last, hipStream_t s) {
+                            void* contrib, void* mb, float* out, bool last, hipStream_t s,
+                            const uint8_t* kinds = nullptr) {
   switch (mode) {
     case kRankFixed:
       return pr_launch_all<unsigned long long, unsigned long long>(what, off, off64, dst, n, m, tile_v, tile, ntiles,
-                                                                   a, b, source, contrib, mb, out, last, s);
+                                                                   a, b, source, contrib, mb, out, last, s, kinds);
     case kRankF32Msg:
       return pr_launch_all<float, unsigned long long>(what, off, off64, dst, n, m, tile_v, tile, ntiles, a, b, source,
-                                                      contrib, mb, out, last, s);
+                                                      contrib, mb, out, last, s, kinds);
     case kRankF32:
       return pr_launch_all<float, float>(what, off, off64, dst, n, m, tile_v, tile, ntiles, a, b, source, contrib, mb,
-                                         out, last, s);
+                                         out, last, s, kinds);
   }
   return hipErrorInvalidValue;
 }
@@ -573,9 +581,10 @@ hipError_t launch_pr_scatter_mp(int mode, const void* off, bool off64, const int
 }
 
 hipError_t launch_pr_apply(int mode, const void* off, bool off64, int64_t n, double teleport, double damping,
-                           int64_t source, void* mb, void* contrib, float* out, bool last, hipStream_t s) {
+                           int64_t source, void* mb, void* contrib, float* out, bool last, hipStream_t s,
+                           const uint8_t* kinds) {
   return pr_launch(mode, 3, off, off64, nullptr, n, 0, nullptr, 0, 0, teleport, damping, source, contrib, mb, out,
-                   last, s);
+                   last, s, kinds);
 }
 
 hipError_t launch_min_init(int kind, int64_t n, int64_t source, const int32_t* ids, uint2* vm, hipStream_t s) {
