@@ -102,3 +102,28 @@ def test_combine_rejects_bad_arguments(device):
         g.combine(9, msg)
     with pytest.raises(TypeError):
         g.combine("sum_u64", torch.zeros(3, dtype=torch.int64, device="cuda"))
+
+
+def test_golden_neutral_combination(device):
+    """Section III's case, written out by hand (tests/golden): messages whose
+    combination equals the combiner's neutral value still leave the receiver
+    flagged with that value; a receiver whose only sender is inactive, and
+    vertices without in-edges, have no message."""
+    import json
+    import os
+    import torch
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "neutral_combination.json")) as f:
+        fx = json.load(f)
+    gr = fx["graph"]
+    csr = rmatgen.raw_csr(gr["n"], np.repeat(np.arange(gr["n"]), np.diff(gr["off"])), gr["dst"])
+    g = make(csr)
+    act = torch.from_numpy(np.array(gr["active"], np.uint8)).cuda()
+    for case in fx["cases"]:
+        print(f"case golden neutral combination {case['op']}", flush=True)
+        words = np.array([int(x, 16) for x in case["msg"]], np.uint64)
+        box, has = g.combine(case["op"], torch.from_numpy(words.view(np.int64)).cuda(), act)
+        box = box.cpu().numpy().view(np.uint64)
+        has = has.cpu().numpy().astype(bool)
+        assert has.tolist() == [bool(h) for h in case["has"]], case["op"]
+        for v, want in enumerate(case["box"]):
+            assert int(box[v]) == (0 if want is None else int(want, 16)), (case["op"], v)

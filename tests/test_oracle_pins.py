@@ -452,6 +452,29 @@ def test_combine_float_max_and_ordered_sum(seed):
     assert not has[np.bincount(dst[keep], minlength=g.n) == 0].any()
 
 
+def load_golden(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)) as f:
+        return json.load(f)
+
+
+def test_combine_golden_neutral_combination():
+    """Section III's case, written out by hand (tests/golden): messages whose
+    combination equals the combiner's neutral value still leave the receiver
+    with a message, and a receiver whose only sender is inactive has none."""
+    fx = load_golden("neutral_combination.json")
+    gr = fx["graph"]
+    active = np.array(gr["active"], bool)
+    for case in fx["cases"]:
+        msg = np.array([int(x, 16) for x in case["msg"]], np.uint64)
+        box, has = oracle.combine(case["op"], gr["n"], gr["off"], gr["dst"], msg, active)
+        assert has.tolist() == [bool(h) for h in case["has"]], case["op"]
+        for v, want in enumerate(case["box"]):
+            if want is not None:
+                assert int(box[v]) == int(want, 16), (case["op"], v)
+
+
 def _pack(val32, ids):
     return (ids.astype(np.uint64) << np.uint64(32)) | val32.view(np.uint32).astype(np.uint64)
 
