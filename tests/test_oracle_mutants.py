@@ -6,6 +6,7 @@ temporary library and checks that a small battery of independent pins --
 closed forms, exact rationals, Dijkstra, union-find -- rejects it.  All of it
 runs on the CPU.
 """
+import json
 import os
 import subprocess
 
@@ -37,6 +38,10 @@ MUTANTS = {
     "minarg-tie-to-larger-id": ("(b == a && ib < ia)", "(b == a && ib > ia)"),
     "max-becomes-min": ("word_f64(msg) > word_f64(stored)", "word_f64(msg) < word_f64(stored)"),
     "inactive-vertices-send": ("if (active && !active[v]) continue;", "if (active && !active[v] && v < 0) continue;"),
+    # Section III's failure: "received" read as "mailbox differs from the neutral value"
+    "received-means-not-neutral": ("  }\n  return ORACLE_OK;\n}\n\n/* Library version tag",
+                                   "  }\n  for (int64_t u = 0; u < n; ++u) has[u] = has[u] && mailbox[u] != 0;\n"
+                                   "  return ORACLE_OK;\n}\n\n/* Library version tag"),
 }
 
 
@@ -114,6 +119,18 @@ def _pins_pass(lib) -> bool:
         for u in range(g.n):
             senders = src[(g.dst == u) & act[src]]
             if senders.size and box[u] != words[min(senders, key=lambda v: (v32[v], ids[v]))]:
+                return False
+        # Section III's neutral-value case, written out by hand (tests/golden)
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "neutral_combination.json")) as f:
+            fx = json.load(f)
+        gr = fx["graph"]
+        for case in fx["cases"]:
+            words = np.array([int(x, 16) for x in case["msg"]], np.uint64)
+            box, has = oracle.combine(case["op"], gr["n"], gr["off"], gr["dst"], words, np.array(gr["active"], bool),
+                                      lib=lib)
+            if has.tolist() != [bool(h) for h in case["has"]]:
+                return False
+            if any(w is not None and int(box[v]) != int(w, 16) for v, w in enumerate(case["box"])):
                 return False
     except oracle.OracleError:
         return False
