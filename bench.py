@@ -591,9 +591,17 @@ def main():
         a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
         torch.cuda.synchronize()
-        b.copy_(a)
+        b.copy_(a)  # the copy whose counters scale FETCH_SIZE / WRITE_SIZE
         torch.cuda.synchronize()
-        log("calibration copy: 1 GiB read + 1 GiB written")
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(5):
+            b.copy_(a)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / 5
+        log(f"calibration copy: 1 GiB read + 1 GiB written; five more take {ms:.3f} ms each = "
+            f"{2 * 2**30 / (ms * 1e-3) / 1e12:.2f} TB/s")
         del a, b
 
     out_f = torch.empty(n, dtype=torch.float32, device=dev)
