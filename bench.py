@@ -672,7 +672,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        sample_T = 1
+        sample_T = 2  # about 10-30 s of single-thread work at scale 26
         t = time.perf_counter()
         oracle.run_csr("pagerank", csr, T=sample_T)
         dt = time.perf_counter() - t
