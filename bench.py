@@ -90,6 +90,29 @@ def pr_scatter_bytes(n, m, off_bytes):
     return (n + 1) * off_bytes + 4 * n + 12 * m
 
 
+def pr_superstep_bytes(n, m, off_bytes):
+    """Algorithmic bytes of a whole PageRank superstep: the broadcast+combine
+    plus the vertex update's 4-byte rank write per vertex."""
+    return pr_scatter_bytes(n, m, off_bytes) + 4 * n
+
+
+def min_superstep_bytes(n, off_bytes, weighted, frontier, edges, receivers, dense0):
+    """Algorithmic bytes of every CC / SSSP superstep s (the method's nominal
+    traffic): per sender its id, value and two offsets, per message its
+    target, weight and a 4-byte mailbox read-modify-write, per receiver its
+    mailbox, value and flag, per vertex activated next its id and degree.
+    A dense superstep 0 (CC: every vertex sends) reads values and offsets by
+    vertex id instead: N (4 + o).  frontier / edges / receivers: |F_s|, E_s,
+    |R_s| per superstep (|F_{s+1}| is the next superstep's frontier)."""
+    w = 4 if weighted else 0
+    out = []
+    for s in range(len(frontier)):
+        nxt = frontier[s + 1] if s + 1 < len(frontier) else 0
+        senders = n * (4 + off_bytes) if (s == 0 and dense0) else frontier[s] * (8 + 2 * off_bytes)
+        out.append(int(senders + edges[s] * (12 + w) + receivers[s] * 12 + nxt * 8))
+    return out
+
+
 def batch_members(count, seed):
     """Seeded batch: scales uniform on [10, 16], edge factor uniform on [8, 32],
     each graph SSSP (directed, uint32 weights, source 0) or hash-min CC
@@ -567,15 +590,26 @@ def main():
     t = time.time()
     csr = rmatgen.workload(args.workload, scale=args.scale, threads=args.gen_threads)
     log(f"generated {csr.name}: n={csr.n} m={csr.m} in {time.time() - t:.1f}s")
-    t = time.time()
-    g = Graph.from_csr(csr, device=dev)
-    log(f"uploaded in {time.time() - t:.1f}s")
+    from paper_2010_01542_amd import vc
     off_bytes = csr.off.dtype.itemsize
     n, m = csr.n, csr.m
-    from paper_2010_01542_amd import vc
     rank_options = vc.OPT_F32_ACCUMULATE if args.f32_accumulate else (
         vc.OPT_F32_MESSAGES if args.messages == "f32" else 0)
     kw = dict(schedule=args.schedule, tile=args.tile, options=0)
+    # graph creation (upload, relabelled copy) and preparation (what a first
+    # run builds: blocked layout, transpose, partitions), timed apart
+    setup = {}
+    t = time.perf_counter()
+    off_t = torch.from_numpy(np.ascontiguousarray(csr.off)).to(dev)
+    dst_t = torch.from_numpy(np.ascontiguousarray(csr.dst)).to(dev)
+    w_t = None if csr.w is None else torch.from_numpy(np.ascontiguousarray(csr.w).view(np.int32)).to(dev)
+    torch.cuda.synchronize()
+    setup["upload_ms"] = round((time.perf_counter() - t) * 1e3, 1)
+    t = time.perf_counter()
+    g = Graph(off_t, dst_t, w_t, symmetric=args.workload == "cc-s22")
+    setup["graph_create_ms"] = round((time.perf_counter() - t) * 1e3, 1)
+    del off_t, dst_t, w_t
+    log(f"uploaded in {setup['upload_ms']:.0f} ms, graph created in {setup['graph_create_ms']:.0f} ms")
 
     if args.workload == "sssp-s26":
         jobs = [("sssp", dict(source=0)), ("pagerank", dict(T=20))]
@@ -603,6 +637,15 @@ def main():
         log(f"calibration copy: 1 GiB read + 1 GiB written; five more take {ms:.3f} ms each = "
             f"{2 * 2**30 / (ms * 1e-3) / 1e12:.2f} TB/s")
         del a, b
+
+    for prog, pk in jobs:
+        t = time.perf_counter()
+        pkw = dict(kw, options=rank_options) if prog in ("pagerank", "ppr") else dict(kw)
+        if prog not in ("pagerank", "ppr") and pkw["schedule"] == "blocked":
+            pkw["schedule"] = "auto"
+        g.prepare(prog, **{k: v for k, v in pk.items() if k in ("T", "source")}, **pkw)
+        setup[f"prepare_{prog}_ms"] = round((time.perf_counter() - t) * 1e3, 1)
+    log(f"setup: {setup}")
 
     out_f = torch.empty(n, dtype=torch.float32, device=dev)
     out_u = torch.empty(n, dtype=torch.int32, device=dev)
@@ -655,9 +698,12 @@ def main():
     roofline = None
     if dominant == "pagerank":
         scat = np.concatenate([r["pagerank"].scatter_ms[:-1] for r in records])
+        whole = np.concatenate([r["pagerank"].step_ms[:-1] for r in records])
         avg_ms = float(scat.mean())
         bytes_launch = pr_scatter_bytes(n, m, off_bytes)
         achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+        step_bytes = pr_superstep_bytes(n, m, off_bytes)
+        step_ms = float(whole.mean())
         sched = records[0]["pagerank"].schedule[0]
         kname = {1: "k_pr_scatter_vertex", 2: "k_pr_scatter_mp", 3: "k_pr_pull",
                  4: "k_pb_spread + k_pb_fold"}.get(int(sched), "?")
@@ -667,19 +713,75 @@ def main():
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": f"{kname} (PageRank broadcast+combine)", "launches": int(scat.size),
                     "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(bytes_launch),
-                    "gteps_per_launch": round(m / (avg_ms * 1e-3) / 1e9, 2)}
+                    "gteps_per_launch": round(m / (avg_ms * 1e-3) / 1e9, 2),
+                    "superstep": {"what": "broadcast+combine and the vertex update (rank write included)",
+                                  "algorithmic_bytes": int(step_bytes), "avg_ms": round(step_ms, 4),
+                                  "achieved": round(step_bytes / (step_ms * 1e-3) / 1e9, 1),
+                                  "frac": round(step_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
 
-    cpu = None
+    # the oracle: CPU baseline (one pinned host core) and the accuracy of this run
+    cpu, accuracy, min_ref = None, {}, {}
     if not args.no_cpu_baseline:
         import oracle
-        sample_T = 2  # about 10-30 s of single-thread work at scale 26
-        t = time.perf_counter()
-        oracle.run_csr("pagerank", csr, T=sample_T)
-        dt = time.perf_counter() - t
-        cpu = {"value": round(sample_T * m / dt / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-               "sample": f"oracle PageRank, {sample_T} broadcast+combine superstep(s) over the full graph "
-                         f"({sample_T * m} messages), single thread, {dt:.1f}s"}
-        log(f"cpu baseline: {cpu['value']} GTEPS in {dt:.1f}s")
+        prev = os.sched_getaffinity(0)
+        core = min(prev)
+        os.sched_setaffinity(0, {core})  # one core, as the baseline states
+        try:
+            samples, msgs, secs = [], 0, 0.0
+            for prog, pk in jobs:
+                if prog in ("pagerank", "ppr"):
+                    sample_T = 2  # the full T would take minutes of one core at scale 26
+                    t = time.perf_counter()
+                    ref = oracle.run_csr(prog, csr, T=sample_T, source=pk.get("source", 0))
+                    dt = time.perf_counter() - t
+                    msgs += sample_T * m
+                    samples.append(f"{prog} {sample_T} supersteps ({sample_T * m} messages) {dt:.1f}s")
+                    g.run(prog, out_f, T=sample_T, source=pk.get("source", 0), schedule=kw["schedule"],
+                          tile=kw["tile"], options=rank_options)
+                    diff = np.abs(out_f.cpu().numpy().astype(np.float64) - ref.values)
+                    accuracy[prog] = {"T": sample_T, "l1": float(diff.sum()), "max_abs": float(diff.max()),
+                                      "bars": {"l1": 1e-5, "max_abs": 1e-7},
+                                      "note": "device run with the timed options, against the binary64 oracle"}
+                else:
+                    t = time.perf_counter()
+                    ref = oracle.run_csr(prog, csr, source=pk.get("source", 0))
+                    dt = time.perf_counter() - t
+                    msgs += int(ref.messages.sum())
+                    samples.append(f"{prog} to quiescence ({int(ref.messages.sum())} messages) {dt:.1f}s")
+                    g.run(prog, out_u, source=pk.get("source", 0), schedule="auto", tile=kw["tile"])
+                    exact = bool(np.array_equal(out_u.cpu().numpy().view(np.uint32), ref.values))
+                    accuracy[prog] = {"bit_exact": exact,
+                                      "frontier_equal": records[0][prog].frontier.tolist() == ref.senders.tolist()}
+                    min_ref[prog] = ref
+                secs += dt
+        finally:
+            os.sched_setaffinity(0, prev)
+        cpu = {"value": round(msgs / secs / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+               "sample": "oracle (single thread pinned to one core) over the full graph: " + "; ".join(samples)}
+        log(f"cpu baseline: {cpu['value']} GTEPS in {secs:.1f}s; accuracy {accuracy}")
+
+    # CC / SSSP: per-superstep algorithmic bytes against the HBM peak, with
+    # |R_s| from the oracle's run
+    for prog, ref in min_ref.items():
+        st = records[0][prog]
+        steps_ms = np.median(np.concatenate([r[prog].step_ms for r in records]).reshape(len(records), -1), axis=0)
+        bs = min_superstep_bytes(n, off_bytes, prog == "sssp" and csr.w is not None, st.frontier.tolist(),
+                                 st.edges.tolist(), ref.receivers.tolist(), dense0=prog == "cc")
+        per = []
+        for s, (b, ms) in enumerate(zip(bs, steps_ms)):
+            if ms > 0:
+                per.append({"s": s, "bytes": b, "ms": round(float(ms), 4),
+                            "gbs": round(b / (ms * 1e-3) / 1e9, 1),
+                            "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                            "schedule": int(st.schedule[s])})
+        tot_b, tot_ms = sum(x["bytes"] for x in per), sum(x["ms"] for x in per)
+        detail[prog]["hbm"] = {"per_superstep": per, "bytes": int(tot_b), "ms": round(tot_ms, 4),
+                               "frac": round(tot_b / (tot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if tot_ms else None}
+        if dominant == prog and tot_ms:
+            roofline = {"bound": "hbm", "achieved": round(tot_b / (tot_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": detail[prog]["hbm"]["frac"], "traffic": None,
+                        "kernel": f"{prog} supersteps (broadcast+combine+update, every superstep of the run)",
+                        "algorithmic_bytes_per_run": int(tot_b), "ms_per_run": round(tot_ms, 4)}
 
     res = {
         "metric": "GTEPS & HBM GB/s vs peak per superstep; batched/served p50/p99 vs plain",
@@ -703,6 +805,9 @@ def main():
                                                  "u64 (fixed point 2^-62, exact sums)")},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "accuracy": accuracy,
+        "pagerank_error": accuracy.get("pagerank"),
+        "setup": setup,
         "detail": detail,
         "host": host_info(),
         "device": torch.cuda.get_device_name(0),

@@ -64,7 +64,7 @@ extern "C" {
 typedef enum {
   VC_OK = 0,
   VC_ERR_INVALID_ARG = 1,   /* null / misaligned pointer, bad enum, wrong struct_size, source >= N */
-  VC_ERR_BAD_GRAPH = 2,     /* CSR failed validation (see VC_GRAPH_VALIDATE) */
+  VC_ERR_BAD_GRAPH = 2,     /* CSR failed validation (see VC_GRAPH_VALIDATE, VC_GRAPH_SYMMETRIC) */
   VC_ERR_OUT_OF_MEMORY = 3, /* a device allocation failed */
   VC_ERR_HIP = 4,           /* a HIP runtime call failed; vc_last_error() names it */
   VC_ERR_UNSUPPORTED = 5,   /* the combination of arguments is not implemented */
@@ -121,7 +121,12 @@ enum {
   VC_GRAPH_BORROW = 1u,    /* keep the caller's device arrays instead of copying them */
   VC_GRAPH_VALIDATE = 2u,  /* check the CSR on the device at creation */
   VC_GRAPH_SYMMETRIC = 4u,  /* caller asserts the graph equals its transpose, weights included
-                               (not checked); the pull form then reads the CSR itself */
+                               (as multisets of (source, target, weight) edges); the pull form
+                               then reads the CSR itself.  Checked only together with
+                               VC_GRAPH_VALIDATE: one pass sums, for two independent 64-bit
+                               hashes h, h(u, v, w) - h(v, u, w) over every edge, and a graph
+                               whose sums are not both zero is refused with VC_ERR_BAD_GRAPH
+                               (an asymmetric graph passes only by a hash collision) */
   VC_GRAPH_NO_RELABEL = 8u  /* keep the input vertex order.  By default the library stores a
                                copy of the graph with vertices ordered by degree class,
                                highest first, so the most-accessed per-vertex data shares
@@ -131,7 +136,16 @@ enum {
 
 /* vc_params.options */
 enum {
-  VC_OPT_NO_HUB_AGGREGATION = 1u, /* disable workgroup-level pre-combination for hub targets */
+  VC_OPT_NO_HUB_AGGREGATION = 1u, /* push supersteps (VC_SCHED_VERTEX, VC_SCHED_EDGE and AUTO's push
+                                     supersteps; paper, Section III: combinations contend at the
+                                     mailboxes of high in-degree targets): by default a workgroup
+                                     combines the messages it sends to the lowest-id targets (8 KiB
+                                     of LDS: 2,048 targets for uint32 minima and binary32 sums, 1,024
+                                     for fixed-point sums; after the default relabelling these are the
+                                     highest-degree vertices) in LDS and merges each touched entry into
+                                     the global mailbox once.  This flag sends every message straight
+                                     to its global mailbox.  Results are the same either way (min, and
+                                     exact fixed-point sums; binary32 atomics round in another order) */
   VC_OPT_NO_TEST_BEFORE_ATOMIC = 2u, /* min programs: skip the mailbox read before the atomic (for measurement) */
   VC_OPT_F32_ACCUMULATE = 4u,        /* PageRank / PPR: binary32 messages and float atomics */
   VC_OPT_GRAPH_CAPTURE = 8u,         /* run the superstep loop as a captured HIP graph: PageRank /
@@ -218,7 +232,9 @@ typedef struct {
  * this call and no longer reads the caller's arrays afterwards (BORROW then
  * only avoids an intermediate copy).
  * Errors: VC_ERR_INVALID_ARG (null pointer, struct_size, N out of range,
- * int32 offsets with num_edges >= 2^31), VC_ERR_BAD_GRAPH (VALIDATE only),
+ * int32 offsets with num_edges >= 2^31), VC_ERR_BAD_GRAPH (VALIDATE only:
+ * offsets[0] != 0, offsets decreasing, offsets[N] != num_edges, a target out
+ * of range, or, with SYMMETRIC, a graph that differs from its transpose),
  * VC_ERR_OUT_OF_MEMORY, VC_ERR_HIP.  On error *out is left unchanged. */
 vc_status vc_graph_create(const vc_graph_desc* desc, hipStream_t stream, vc_graph* out);
 
@@ -245,6 +261,20 @@ vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held,
  * are unspecified. */
 vc_status vc_run(vc_graph g, vc_program program, const vc_params* params, void* out, hipStream_t stream,
                  vc_stats* stats);
+
+/* Builds now what a run of `program` with `params` would otherwise build on
+ * its first call (paper, Section V: the work distribution of a superstep):
+ * the transpose its pull supersteps read, the merge-path partition of the
+ * CSR, and the blocked layout where that form would be taken (AUTO on graphs
+ * of 2^20 vertices and more), so that the first run costs what later runs
+ * cost.  Read-only structures only; a graph's views share them.
+ *   params   host, may be NULL (defaults, as vc_run).
+ *   stream   the building work runs here; the call returns after it.
+ * Errors: VC_ERR_INVALID_ARG (null graph, bad program or params, graph on
+ * another device), VC_ERR_UNSUPPORTED (the blocked schedule with
+ * VC_OPT_F32_ACCUMULATE, or a graph beyond the blocked layout's limits),
+ * VC_ERR_OUT_OF_MEMORY, VC_ERR_HIP. */
+vc_status vc_graph_prepare(vc_graph g, vc_program program, const vc_params* params, hipStream_t stream);
 
 /* Many-source SSSP: k (1..256) SSSP programs on one graph, run side by side
  * in one superstep loop (paper, Section I) with the min combiner (Section

@@ -467,8 +467,12 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
                    : (p.options & VC_OPT_F32_MESSAGES) ? vc::kRankF32Msg
                                                         : vc::kRankFixed;
   const bool fx = mode != vc::kRankF32;  // sums in fixed point
-  VC_TRY(g->contrib.ensure((size_t)n * (mode == vc::kRankFixed ? 8 : 4)));
-  VC_TRY(g->mb.ensure((size_t)n * (fx ? 8 : 4)));
+  const bool hub = !(p.options & VC_OPT_NO_HUB_AGGREGATION);
+  // messages and sums take 8 bytes per vertex in every mode, so that a run in
+  // one mode never reallocates the buffers a captured graph of another mode
+  // was recorded with
+  VC_TRY(g->contrib.ensure((size_t)n * 8));
+  VC_TRY(g->mb.ensure((size_t)n * 8));
   void* contrib = g->contrib.p;
   void* mb = g->mb.p;
   const double r0 = 1.0 / (double)n;
@@ -510,9 +514,13 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
     // the whole loop as one captured HIP graph; ranks land in the staging
     // buffer (fixed address) and are copied / un-permuted afterwards
     float* stage = static_cast<float*>(contrib);
-    char keybuf[160];
-    std::snprintf(keybuf, sizeof keybuf, "%d/%lld/%lld/%.17g/%d/%lld", mode, (long long)T, (long long)source, d,
-                  sched, (long long)tile);
+    // the key names every device address the graph bakes in, so that a
+    // reallocated buffer or a rebuilt partition forces a new capture
+    char keybuf[320];
+    std::snprintf(keybuf, sizeof keybuf, "%d/%d/%lld/%lld/%.17g/%d/%lld/%p/%p/%p/%p/%p/%p/%p", mode, (int)hub, (long long)T,
+                  (long long)source, d, sched, (long long)tile, contrib, mb, g->pb_vals.p,
+                  (const void*)g->csc_tiles_p, (const void*)g->dense_tiles_p, (const void*)g->in_src,
+                  (const void*)g->pb.fold);
     if (g->pr_exec && g->pr_exec_key != keybuf) {
       VC_TRY(hipGraphExecDestroy(g->pr_exec));
       g->pr_exec = nullptr;
@@ -531,9 +539,9 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
             e = pb_superstep(g, mode == vc::kRankF32Msg, contrib, mb, cs);
           } else if (sched == VC_SCHED_EDGE)
             e = vc::launch_pr_scatter_mp(mode, g->off, g->off64, g->dst, n, g->m, g->dense_tiles_p, tile,
-                                         g->dense_ntiles, contrib, mb, cs);
+                                         g->dense_ntiles, contrib, mb, hub, cs);
           else
-            e = vc::launch_pr_scatter_vertex(mode, g->off, g->off64, g->dst, n, contrib, mb, cs);
+            e = vc::launch_pr_scatter_vertex(mode, g->off, g->off64, g->dst, n, contrib, mb, hub, cs);
         }
         if (e == hipSuccess)
           e = vc::launch_pr_apply(mode, g->off, g->off64, n, teleport, d, source, mb, contrib, stage, step + 1 == T, cs,
@@ -573,9 +581,9 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
         VC_TRY(pb_superstep(g, mode == vc::kRankF32Msg, contrib, mb, s));
       } else if (sched == VC_SCHED_EDGE)
         VC_TRY(vc::launch_pr_scatter_mp(mode, g->off, g->off64, g->dst, n, g->m, g->dense_tiles_p, tile,
-                                        g->dense_ntiles, contrib, mb, s));
+                                        g->dense_ntiles, contrib, mb, hub, s));
       else
-        VC_TRY(vc::launch_pr_scatter_vertex(mode, g->off, g->off64, g->dst, n, contrib, mb, s));
+        VC_TRY(vc::launch_pr_scatter_vertex(mode, g->off, g->off64, g->dst, n, contrib, mb, hub, s));
     }
     if (timed) VC_TRY(hipEventRecord(g->events[3 * step + 1], s));
     VC_TRY(vc::launch_pr_apply(mode, g->off, g->off64, n, teleport, d, source, mb, contrib, rank_out, step + 1 == T, s,
@@ -635,7 +643,11 @@ vc_status run_min_device_loop(vc_graph g, int kind, int64_t tile, int cur, int64
   vc::LoopState* loop = g->loop_state.as<vc::LoopState>();
   long long* steps = g->loop_steps.as<long long>();
   hipGraphExec_t& exec = g->min_exec[kind][cur];
-  if (exec && g->min_exec_tile[kind][cur] != g->csc_tile) {
+  char keybuf[256];
+  std::snprintf(keybuf, sizeof keybuf, "%lld/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p", (long long)g->csc_tile, (void*)vm,
+                (void*)bits[0], (void*)bits[1], (void*)fq, (void*)P, (void*)ctr, (void*)loop, (void*)steps,
+                (const void*)g->csc_tiles_p, (const void*)g->in_src);
+  if (exec && g->min_exec_key[kind][cur] != keybuf) {
     VC_TRY(hipGraphExecDestroy(exec));
     exec = nullptr;
   }
@@ -659,7 +671,7 @@ vc_status run_min_device_loop(vc_graph g, int kind, int64_t tile, int cur, int64
     const hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e3 != hipSuccess) return hip_fail(e3, "hipGraphInstantiate");
-    g->min_exec_tile[kind][cur] = g->csc_tile;
+    g->min_exec_key[kind][cur] = keybuf;
   }
   vc::LoopState init{0, step, cap, 0};
   *g->host_loop = init;
@@ -697,6 +709,7 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
   const int64_t n = g->n, m = g->m;
   const int64_t tile = pick_tile(p, g);
   const bool tba = !(p.options & VC_OPT_NO_TEST_BEFORE_ATOMIC);
+  const bool hub = !(p.options & VC_OPT_NO_HUB_AGGREGATION);
   const int64_t nwords = (n + 31) / 32;
   VC_TRY(g->vm.ensure((size_t)n * 8));
   VC_TRY(g->bitmap.ensure((size_t)nwords * 4));
@@ -823,21 +836,21 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
         vc_status st = dense_partition(g, tile, s);
         if (st != VC_OK) return st;
         if (timed) VC_TRY(hipEventRecord(g->events[1], s));
-        VC_TRY(vc::launch_min_scatter_mp(kind, false, tba, g->off, g->off64, g->dst, g->w, n, n + m, nullptr, nullptr,
-                                         g->dense_tiles_p, tile, g->dense_ntiles, vm, improved, s));
+        VC_TRY(vc::launch_min_scatter_mp(kind, false, tba, g->off, g->off64, g->dst, g->w, n, n, n + m, nullptr,
+                                         nullptr, g->dense_tiles_p, tile, g->dense_ntiles, vm, improved, hub, s));
       } else {
         if (!prefix_ready) VC_TRY(vc::launch_exclusive_scan(P, listed, g->scan_blocks.as<int64_t>(), s));
         const int64_t total = listed + edges;
         const int64_t ntiles = (total + tile - 1) / tile;
         VC_TRY(vc::launch_mp_partition(P, true, listed, total, tile, ntiles, list_tiles, s));
         if (timed) VC_TRY(hipEventRecord(g->events[1], s));
-        VC_TRY(vc::launch_min_scatter_mp(kind, true, tba, g->off, g->off64, g->dst, g->w, listed, total, P, fq,
-                                         list_tiles, tile, ntiles, vm, improved, s));
+        VC_TRY(vc::launch_min_scatter_mp(kind, true, tba, g->off, g->off64, g->dst, g->w, n, listed, total, P, fq,
+                                         list_tiles, tile, ntiles, vm, improved, hub, s));
       }
     } else {
       if (timed) VC_TRY(hipEventRecord(g->events[1], s));
-      VC_TRY(vc::launch_min_scatter_vertex(kind, !dense, tba, g->off, g->off64, g->dst, g->w, dense ? n : listed, fq,
-                                           vm, improved, s));
+      VC_TRY(vc::launch_min_scatter_vertex(kind, !dense, tba, g->off, g->off64, g->dst, g->w, n, dense ? n : listed,
+                                           fq, vm, improved, hub, s));
     }
     if (timed) VC_TRY(hipEventRecord(g->events[2], s));
     VC_TRY(vc::launch_min_compact(g->off, g->off64, n, vm, improved, bits[1 - cur], fq, P, ctr, false, nullptr, s));
@@ -1063,6 +1076,20 @@ vc_status vc_graph_create(const vc_graph_desc* d, hipStream_t stream, vc_graph* 
       if (h.flags & 8) why += " dst out of range;";
       return cleanup(fail(VC_ERR_BAD_GRAPH, "CSR validation failed:" + why));
     }
+    if ((d->flags & VC_GRAPH_SYMMETRIC) && g->m > 0) {
+      // the edge multiset against the reversed one, by multiset hashes
+      unsigned long long acc[2] = {1, 1};
+      auto* dacc = reinterpret_cast<unsigned long long*>(g->counters.p);
+      if ((e = vc::launch_fill_u32(reinterpret_cast<uint32_t*>(dacc), 4, 0u, stream)) != hipSuccess ||
+          (e = vc::launch_sym_hash(g->off, g->off64, g->dst, g->w, g->n, dacc, stream)) != hipSuccess ||
+          (e = hipMemcpyAsync(acc, dacc, sizeof acc, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+          (e = hipStreamSynchronize(stream)) != hipSuccess)
+        return cleanup(hip_fail(e, "symmetry validation"));
+      if (acc[0] != 0 || acc[1] != 0)
+        return cleanup(fail(VC_ERR_BAD_GRAPH,
+                            "graph declared VC_GRAPH_SYMMETRIC differs from its transpose (edge multisets, weights "
+                            "included, do not match)"));
+    }
   }
   if (!(d->flags & VC_GRAPH_NO_RELABEL)) {
     vc_status st = relabel(g, stream);
@@ -1193,6 +1220,53 @@ vc_status vc_run(vc_graph g, vc_program program, const vc_params* params, void* 
     stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   return st;
+}
+
+vc_status vc_graph_prepare(vc_graph g, vc_program program, const vc_params* params, hipStream_t stream) {
+  if (!g) return fail(VC_ERR_INVALID_ARG, "null graph");
+  if (program < VC_PAGERANK || program > VC_PPR) return fail(VC_ERR_INVALID_ARG, "bad program");
+  vc_params p;
+  if (params)
+    p = *params;
+  else
+    vc_params_default(&p);
+  std::string why;
+  if (!valid_params(p, program, g->n, &why)) return fail(VC_ERR_INVALID_ARG, why);
+  apply_tuned(g, program, &p);
+  int cur = 0;
+  VC_TRY(hipGetDevice(&cur));
+  if (cur != g->device) return fail(VC_ERR_INVALID_ARG, "graph lives on another device than the current one");
+  if (g->m == 0) return VC_OK;
+  const int64_t tile = pick_tile(p, g);
+  const bool capture = (p.options & VC_OPT_GRAPH_CAPTURE) != 0;
+  auto pull = [&]() {
+    vc_status st = ensure_csc(g, stream);
+    return st == VC_OK ? csc_partition(g, vc::pull_tile(tile), stream) : st;
+  };
+  vc_status st = VC_OK;
+  if (program == VC_PAGERANK || program == VC_PPR) {
+    const bool fx = !(p.options & VC_OPT_F32_ACCUMULATE);
+    const int sched = rank_schedule(g, p, fx);
+    if (sched == VC_SCHED_BLOCKED && !fx)
+      return fail(VC_ERR_UNSUPPORTED, "the blocked schedule sums in fixed point; drop VC_OPT_F32_ACCUMULATE");
+    if (sched == VC_SCHED_PULL) st = pull();
+    else if (sched == VC_SCHED_EDGE) st = dense_partition(g, tile, stream);
+    else if (sched == VC_SCHED_BLOCKED) st = use_pb(g, stream);
+  } else {
+    switch (p.schedule) {
+      case VC_SCHED_BLOCKED: st = use_pb(g, stream); break;
+      case VC_SCHED_PULL: st = pull(); break;
+      case VC_SCHED_EDGE: st = dense_partition(g, tile, stream); break;
+      case VC_SCHED_VERTEX: break;
+      default:  // AUTO: the dense form its dense supersteps take, the partition of a dense push
+        st = min_blocked(g, capture) ? use_pb(g, stream) : pull();
+        if (st == VC_OK) st = dense_partition(g, tile, stream);
+    }
+    if (st == VC_OK && capture) st = pull();
+  }
+  if (st != VC_OK) return st;
+  VC_TRY(hipStreamSynchronize(stream));
+  return VC_OK;
 }
 
 vc_status vc_combine(vc_graph g, vc_combiner op, const uint64_t* msg, const uint8_t* active, uint64_t* mailbox,

@@ -191,7 +191,7 @@ struct vc_graph_s {
   // captured superstep loops (HIP graphs), replayed on the caller's stream
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t min_exec[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
-  int64_t min_exec_tile[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  std::string min_exec_key[3][2];  // device addresses and tile each captured loop was recorded with
   hipGraphExec_t pr_exec = nullptr;
   std::string pr_exec_key;
   vc::DevBuf loop_state, loop_steps;

@@ -34,7 +34,14 @@ struct LoopState {
   long long capped;
 };
 
-// Bytes of dynamic LDS a merge-path scatter tile of `tile` items needs.
+// LDS of a push workgroup's hub table: messages to targets below
+// kHubBytes / (entry size) are combined there and flushed once per target
+// (hub_slots: that count, capped at n; 0 when aggregation is off).
+constexpr size_t kHubBytes = 8192;
+int hub_slots(int64_t n, size_t entry_bytes, bool hub);
+
+// Bytes of dynamic LDS a merge-path scatter tile of `tile` items needs
+// (hub table included).
 size_t pr_mp_lds_bytes(int64_t tile, bool off64);
 size_t min_mp_lds_bytes(int64_t tile, bool list);
 
@@ -45,6 +52,11 @@ size_t min_mp_lds_bytes(int64_t tile, bool list);
 hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t s);
 hipError_t launch_validate(const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m, Counters* ctr,
                            hipStream_t s);
+// acc[0..1] (zeroed by the caller) += sum over edges (u, v, w) of
+// h(u, v, w) - h(v, u, w) for two hashes: both stay 0 on a symmetric graph.
+// w may be NULL (unit weights).  Needs a validated CSR.
+hipError_t launch_sym_hash(const void* off, bool off64, const int32_t* dst, const uint32_t* w, int64_t n,
+                           unsigned long long* acc, hipStream_t s);
 
 // Merge-path partition of the merged (edge, vertex-end) sequence of a
 // non-decreasing prefix array P[0..items]: tile_v[t] = number of vertex-ends
@@ -62,11 +74,12 @@ enum RankMode : int {
 };
 hipError_t launch_pr_init(int mode, const void* off, bool off64, int64_t n, double r0, int64_t source, void* contrib,
                           void* mb, float* out_if_t0, hipStream_t s);
+// hub: combine messages to hub targets in LDS first (kHubBytes).
 hipError_t launch_pr_scatter_vertex(int mode, const void* off, bool off64, const int32_t* dst, int64_t n,
-                                    const void* contrib, void* mb, hipStream_t s);
+                                    const void* contrib, void* mb, bool hub, hipStream_t s);
 hipError_t launch_pr_scatter_mp(int mode, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
                                 const int32_t* tile_v, int64_t tile, int64_t ntiles, const void* contrib, void* mb,
-                                hipStream_t s);
+                                bool hub, hipStream_t s);
 // The vertex update: rank from the summed mailbox, then the next message (or
 // the rank into out when last).  kinds: NULL (every mailbox is read and
 // cleared), or the blocked layout's kind of every destination bin, which
@@ -81,13 +94,14 @@ hipError_t launch_pr_apply(int mode, const void* off, bool off64, int64_t n, dou
 hipError_t launch_min_init(int kind, int64_t n, int64_t source, const int32_t* ids, uint2* vm, hipStream_t s);
 hipError_t launch_min_seed_source(const void* off, bool off64, int64_t source, int32_t* fq, int64_t* P,
                                   uint32_t* active, hipStream_t s);
+// n: vertices of the graph (hub targets are ids below hub_slots(n, 4, hub)).
 hipError_t launch_min_scatter_vertex(int kind, bool list, bool tba, const void* off, bool off64, const int32_t* dst,
-                                     const uint32_t* w, int64_t items, const int32_t* fq, uint2* vm, uint32_t* bitmap,
-                                     hipStream_t s);
+                                     const uint32_t* w, int64_t n, int64_t items, const int32_t* fq, uint2* vm,
+                                     uint32_t* bitmap, bool hub, hipStream_t s);
 hipError_t launch_min_scatter_mp(int kind, bool list, bool tba, const void* off, bool off64, const int32_t* dst,
-                                 const uint32_t* w, int64_t items, int64_t total, const int64_t* P, const int32_t* fq,
-                                 const int32_t* tile_v, int64_t tile, int64_t ntiles, uint2* vm, uint32_t* bitmap,
-                                 hipStream_t s);
+                                 const uint32_t* w, int64_t n, int64_t items, int64_t total, const int64_t* P,
+                                 const int32_t* fq, const int32_t* tile_v, int64_t tile, int64_t ntiles, uint2* vm,
+                                 uint32_t* bitmap, bool hub, hipStream_t s);
 hipError_t launch_min_compact(const void* off, bool off64, int64_t n, uint2* vm, const uint32_t* bitmap,
                               uint32_t* stale, int32_t* fq, int64_t* P, Counters* ctr, bool seed,
                               const LoopState* loop, hipStream_t s);

@@ -55,6 +55,56 @@ __global__ __launch_bounds__(kWG) void k_validate(const OffT* __restrict__ off, 
   if (bad) atomicOr(&ctr->flags, bad);
 }
 
+// Symmetry check of a graph declared symmetric: the multiset of its edges
+// (u, v, w) must equal that of its reversed edges (v, u, w).  Each edge adds
+// h(u, v, w) - h(v, u, w) to a wrapping 64-bit sum, for two independent
+// hashes; both sums are zero for a symmetric graph, and an asymmetric one
+// leaves both at zero only by a hash collision.  The mixing step is the
+// 64-bit finaliser of MurmurHash3 (A. Appleby).  One wavefront per 64
+// consecutive vertices; its lanes read the offsets coalesced and then stride
+// over each vertex's edges.
+__device__ __forceinline__ unsigned long long fmix64(unsigned long long k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+__device__ __forceinline__ void sym_terms(unsigned long long u, unsigned long long v, unsigned long long w,
+                                          unsigned long long* a, unsigned long long* b) {
+  const unsigned long long f = (u << 32) | v, r = (v << 32) | u;
+  const unsigned long long sw = w * 0x9e3779b97f4a7c15ull;
+  *a += fmix64(f ^ sw) - fmix64(r ^ sw);
+  *b += fmix64(fmix64(f + 0x632be59bd9b4e019ull) ^ w) - fmix64(fmix64(r + 0x632be59bd9b4e019ull) ^ w);
+}
+
+template <class OffT>
+__global__ __launch_bounds__(kWG) void k_sym_hash(const OffT* __restrict__ off, const int32_t* __restrict__ dst,
+                                                  const uint32_t* __restrict__ w, int64_t n,
+                                                  unsigned long long* __restrict__ acc) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int64_t nwaves = grid_threads() >> 6;
+  unsigned long long a = 0, b = 0;
+  for (int64_t v0 = (gid() >> 6) * 64; v0 < n; v0 += nwaves * 64) {
+    const int64_t mv = v0 + lane;
+    const long long me0 = mv < n ? (long long)off[mv] : 0, me1 = mv < n ? (long long)off[mv + 1] : 0;
+    const int cnt = n - v0 < 64 ? (int)(n - v0) : 64;
+    for (int i = 0; i < cnt; ++i) {
+      const long long e0 = __shfl(me0, i, 64), e1 = __shfl(me1, i, 64);
+      for (long long e = e0 + lane; e < e1; e += 64)
+        sym_terms((unsigned long long)(v0 + i), (unsigned long long)(uint32_t)dst[e], w ? w[e] : 1u, &a, &b);
+    }
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if (lane == 0 && (a | b)) {
+    atomicAdd(&acc[0], a);
+    atomicAdd(&acc[1], b);
+  }
+}
+
 // tile_v[t] = #{x in [0, items) : P[x+1] + x + 1 <= k}, k = min(t * tile, total):
 // the number of vertex-ends that precede merged position k when edge e of
 // item x sits at position e + x and the end of item x at P[x+1] + x.
@@ -115,17 +165,54 @@ __global__ __launch_bounds__(kWG) void k_pr_init(const OffT* __restrict__ off, i
   mb[v] = S(0);
 }
 
+// Hub targets (paper, Section III: combinations contend at the recipient's
+// mailbox, most at high in-degree vertices).  A push workgroup combines the
+// messages addressed to targets 0 .. nhub-1 in an LDS table (after the
+// default hot-first relabelling these are the highest-degree vertices) and
+// flushes every touched entry with one global combination at its end;
+// nhub = 0 sends every message to its global mailbox.  The table is
+// kHubBytes of LDS; min tables start at the neutral value, sum tables at 0.
+template <class S>
+__device__ __forceinline__ void hub_init(S* __restrict__ s_hub, int nhub, S neutral) {
+  for (int x = threadIdx.x; x < nhub; x += kWG) s_hub[x] = neutral;
+}
+
+template <class S>
+__device__ __forceinline__ void hub_flush_sum(const S* __restrict__ s_hub, int nhub, S* __restrict__ mb) {
+  for (int x = threadIdx.x; x < nhub; x += kWG) {
+    const S c = s_hub[x];
+    if (c != S(0)) sum_combine<S>(mb, x, c);
+  }
+}
+
 // Vertex-per-thread broadcast: thread v sends contrib[v] along its out-edges.
 template <class OffT, class M, class S>
 __global__ __launch_bounds__(kWG) void k_pr_scatter_vertex(const OffT* __restrict__ off,
                                                            const int32_t* __restrict__ dst, int64_t n,
-                                                           const M* __restrict__ contrib, S* __restrict__ mb) {
+                                                           const M* __restrict__ contrib, S* __restrict__ mb,
+                                                           int nhub) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  S* s_hub = reinterpret_cast<S*>(smem);
+  if (nhub) {  // uniform over the grid
+    hub_init<S>(s_hub, nhub, S(0));
+    __syncthreads();
+  }
   const int64_t v = gid();
-  if (v >= n) return;
-  const S c = msg_to_sum<M, S>(contrib[v]);
-  if (c == S(0)) return;  // adding zero changes no sum (PPR vertices the walk has not reached)
-  const int64_t e1 = (int64_t)off[v + 1];
-  for (int64_t e = (int64_t)off[v]; e < e1; ++e) sum_combine<S>(mb, dst[e], c);
+  const S c = v < n ? msg_to_sum<M, S>(contrib[v]) : S(0);
+  if (c != S(0)) {  // adding zero changes no sum (PPR vertices the walk has not reached)
+    const int64_t e1 = (int64_t)off[v + 1];
+    for (int64_t e = (int64_t)off[v]; e < e1; ++e) {
+      const int32_t d = dst[e];
+      if (d < nhub)
+        atomicAdd(&s_hub[d], c);
+      else
+        sum_combine<S>(mb, d, c);
+    }
+  }
+  if (nhub) {
+    __syncthreads();
+    hub_flush_sum<S>(s_hub, nhub, mb);
+  }
 }
 
 // Merge-path broadcast: workgroup t owns merged positions [t*tile, (t+1)*tile).
@@ -133,7 +220,7 @@ template <class OffT, class M, class S>
 __global__ __launch_bounds__(kWG) void k_pr_scatter_mp(const OffT* __restrict__ off, const int32_t* __restrict__ dst,
                                                        int64_t n, int64_t m, const int32_t* __restrict__ tile_v,
                                                        int64_t tile, const M* __restrict__ contrib,
-                                                       S* __restrict__ mb) {
+                                                       S* __restrict__ mb, int nhub) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t t = blockIdx.x;
   const int64_t k0 = t * tile;
@@ -145,8 +232,10 @@ __global__ __launch_bounds__(kWG) void k_pr_scatter_mp(const OffT* __restrict__ 
   const int cnt = (int)(ilast - i0 + 1);  // vertices i0..ilast own the tile's edges
   S* s_val = reinterpret_cast<S*>(smem);                                         // tile + 1
   OffT* s_off = reinterpret_cast<OffT*>(smem + align16((tile + 1) * sizeof(S)));  // tile + 2
+  S* s_hub = reinterpret_cast<S*>(smem + align16((tile + 1) * sizeof(S)) + align16((tile + 2) * sizeof(OffT)));
   for (int x = threadIdx.x; x <= cnt; x += kWG) s_off[x] = off[i0 + x];
   for (int x = threadIdx.x; x < cnt; x += kWG) s_val[x] = msg_to_sum<M, S>(contrib[i0 + x]);
+  hub_init<S>(s_hub, nhub, S(0));
   __syncthreads();
   for (int64_t e = j0 + threadIdx.x; e < j1; e += kWG) {
     int lo = 0, hi = cnt - 1;  // owner = last x with s_off[x] <= e
@@ -159,7 +248,16 @@ __global__ __launch_bounds__(kWG) void k_pr_scatter_mp(const OffT* __restrict__ 
     }
     const S c = s_val[lo];
     const int32_t d = dst[e];
-    if (c != S(0)) sum_combine<S>(mb, d, c);
+    if (c != S(0)) {
+      if (d < nhub)
+        atomicAdd(&s_hub[d], c);
+      else
+        sum_combine<S>(mb, d, c);
+    }
+  }
+  if (nhub) {
+    __syncthreads();
+    hub_flush_sum<S>(s_hub, nhub, mb);
   }
 }
 
@@ -234,18 +332,47 @@ __device__ __forceinline__ void relax(uint2* __restrict__ vm, uint32_t* __restri
   }
 }
 
+// A hub entry's minimum goes through the same filter and atomic as a
+// single message would.
+template <bool TBA>
+__device__ __forceinline__ void hub_flush_min(const uint32_t* __restrict__ s_hub, int nhub, uint2* __restrict__ vm,
+                                              uint32_t* __restrict__ bitmap) {
+  for (int x = threadIdx.x; x < nhub; x += kWG) {
+    const uint32_t msg = s_hub[x];
+    if (msg != kInf) relax<TBA>(vm, bitmap, x, msg);
+  }
+}
+
 template <class OffT, int KIND, bool LIST, bool TBA>
 __global__ __launch_bounds__(kWG) void k_min_scatter_vertex(const OffT* __restrict__ off,
                                                             const int32_t* __restrict__ dst,
                                                             const uint32_t* __restrict__ w, int64_t items,
                                                             const int32_t* __restrict__ fq, uint2* __restrict__ vm,
-                                                            uint32_t* __restrict__ bitmap) {
+                                                            uint32_t* __restrict__ bitmap, int nhub) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint32_t* s_hub = reinterpret_cast<uint32_t*>(smem);
+  if (nhub) {  // uniform over the grid
+    hub_init<uint32_t>(s_hub, nhub, kInf);
+    __syncthreads();
+  }
   const int64_t x = gid();
-  if (x >= items) return;
-  const int64_t v = LIST ? (int64_t)fq[x] : x;
-  const uint32_t val = vm[v].x;
-  const int64_t e1 = (int64_t)off[v + 1];
-  for (int64_t e = (int64_t)off[v]; e < e1; ++e) relax<TBA>(vm, bitmap, dst[e], message<KIND>(val, w, e));
+  if (x < items) {
+    const int64_t v = LIST ? (int64_t)fq[x] : x;
+    const uint32_t val = vm[v].x;
+    const int64_t e1 = (int64_t)off[v + 1];
+    for (int64_t e = (int64_t)off[v]; e < e1; ++e) {
+      const int32_t d = dst[e];
+      const uint32_t msg = message<KIND>(val, w, e);
+      if (d < nhub)
+        atomicMin(&s_hub[d], msg);
+      else
+        relax<TBA>(vm, bitmap, d, msg);
+    }
+  }
+  if (nhub) {
+    __syncthreads();
+    hub_flush_min<TBA>(s_hub, nhub, vm, bitmap);
+  }
 }
 
 // Merge-path broadcast for the min programs.  Dense mode: items are all
@@ -257,7 +384,8 @@ __global__ __launch_bounds__(kWG) void k_min_scatter_mp(const OffT* __restrict__
                                                         const uint32_t* __restrict__ w, int64_t items, int64_t total,
                                                         const PT* __restrict__ P, const int32_t* __restrict__ fq,
                                                         const int32_t* __restrict__ tile_v, int64_t tile,
-                                                        uint2* __restrict__ vm, uint32_t* __restrict__ bitmap) {
+                                                        uint2* __restrict__ vm, uint32_t* __restrict__ bitmap,
+                                                        int nhub) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t t = blockIdx.x;
   const int64_t k0 = t * tile;
@@ -269,13 +397,15 @@ __global__ __launch_bounds__(kWG) void k_min_scatter_mp(const OffT* __restrict__
   const int cnt = (int)(ilast - i0 + 1);
   int64_t* s_p = reinterpret_cast<int64_t*>(smem);  // tile + 2 entries
   int64_t* s_base = s_p + tile + 2;                 // tile + 1 entries (list mode; 8-byte aligned)
-  uint32_t* s_val = reinterpret_cast<uint32_t*>(LIST ? s_base + tile + 1 : s_base);
+  uint32_t* s_val = reinterpret_cast<uint32_t*>(LIST ? s_base + tile + 1 : s_base);  // tile + 1 entries
+  uint32_t* s_hub = reinterpret_cast<uint32_t*>(reinterpret_cast<unsigned char*>(s_val) + align16((tile + 1) * 4));
   for (int x = threadIdx.x; x <= cnt; x += kWG) s_p[x] = (int64_t)P[i0 + x];
   for (int x = threadIdx.x; x < cnt; x += kWG) {
     const int64_t v = LIST ? (int64_t)fq[i0 + x] : i0 + x;
     if (LIST) s_base[x] = (int64_t)off[v] - (int64_t)P[i0 + x];
     s_val[x] = vm[v].x;
   }
+  hub_init<uint32_t>(s_hub, nhub, kInf);
   __syncthreads();
   for (int64_t j = j0 + threadIdx.x; j < j1; j += kWG) {
     int lo = 0, hi = cnt - 1;
@@ -287,7 +417,16 @@ __global__ __launch_bounds__(kWG) void k_min_scatter_mp(const OffT* __restrict__
         hi = mid - 1;
     }
     const int64_t pos = LIST ? j + s_base[lo] : j;
-    relax<TBA>(vm, bitmap, dst[pos], message<KIND>(s_val[lo], w, pos));
+    const int32_t d = dst[pos];
+    const uint32_t msg = message<KIND>(s_val[lo], w, pos);
+    if (d < nhub)
+      atomicMin(&s_hub[d], msg);
+    else
+      relax<TBA>(vm, bitmap, d, msg);
+  }
+  if (nhub) {
+    __syncthreads();
+    hub_flush_min<TBA>(s_hub, nhub, vm, bitmap);
   }
 }
 
@@ -455,11 +594,17 @@ __global__ __launch_bounds__(kWG) void k_scan_down(int64_t* __restrict__ P, int6
 // ------------------------------------------------------------------ launchers
 
 size_t pr_mp_lds_bytes(int64_t tile, bool off64) {
-  return align16((size_t)(tile + 1) * 8) + (size_t)(tile + 2) * (off64 ? 8 : 4);
+  return align16((size_t)(tile + 1) * 8) + align16((size_t)(tile + 2) * (off64 ? 8 : 4)) + kHubBytes;
 }
 
 size_t min_mp_lds_bytes(int64_t tile, bool list) {
-  return (size_t)(tile + 2) * 8 + (list ? (size_t)(tile + 1) * 8 : 0) + (size_t)(tile + 1) * 4;
+  return (size_t)(tile + 2) * 8 + (list ? (size_t)(tile + 1) * 8 : 0) + align16((size_t)(tile + 1) * 4) + kHubBytes;
+}
+
+int hub_slots(int64_t n, size_t entry_bytes, bool hub) {
+  if (!hub) return 0;
+  const int64_t cap = (int64_t)(kHubBytes / entry_bytes);
+  return (int)(n < cap ? n : cap);
 }
 
 hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t s) {
@@ -484,6 +629,16 @@ hipError_t launch_validate(const void* off, bool off64, const int32_t* dst, int6
   return hipGetLastError();
 }
 
+hipError_t launch_sym_hash(const void* off, bool off64, const int32_t* dst, const uint32_t* w, int64_t n,
+                           unsigned long long* acc, hipStream_t s) {
+  const unsigned g = grid_stride_for((n + 63) / 64 * 64);
+  if (off64)
+    hipLaunchKernelGGL(k_sym_hash<int64_t>, dim3(g), dim3(kWG), 0, s, (const int64_t*)off, dst, w, n, acc);
+  else
+    hipLaunchKernelGGL(k_sym_hash<int32_t>, dim3(g), dim3(kWG), 0, s, (const int32_t*)off, dst, w, n, acc);
+  return hipGetLastError();
+}
+
 hipError_t launch_mp_partition(const void* P, bool p64, int64_t items, int64_t total, int64_t tile, int64_t ntiles,
                                int32_t* tile_v, hipStream_t s) {
   const unsigned g = grid_for(ntiles + 1);
@@ -501,9 +656,10 @@ template <class M, class S>
 hipError_t pr_launch_all(int what, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
                          const int32_t* tile_v, int64_t tile, int64_t ntiles, double a, double b, int64_t source,
                          void* contrib, void* mb, float* out, bool last, hipStream_t s,
-                         const uint8_t* kinds = nullptr) {
+                         const uint8_t* kinds = nullptr, bool hub = false) {
   M* c = static_cast<M*>(contrib);
   S* mbx = static_cast<S*>(mb);
+  const int nhub = hub_slots(n, sizeof(S), hub);
   switch (what) {
     case 0:  // init; a = r0
       if (off64)
@@ -513,22 +669,25 @@ hipError_t pr_launch_all(int what, const void* off, bool off64, const int32_t* d
         hipLaunchKernelGGL((k_pr_init<int32_t, M, S>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int32_t*)off, n, a,
                            source, c, mbx, out);
       break;
-    case 1:  // vertex-per-thread broadcast
+    case 1: {  // vertex-per-thread broadcast
+      const size_t lds = (size_t)nhub * sizeof(S);
       if (off64)
-        hipLaunchKernelGGL((k_pr_scatter_vertex<int64_t, M, S>), dim3(grid_for(n)), dim3(kWG), 0, s,
-                           (const int64_t*)off, dst, n, c, mbx);
+        hipLaunchKernelGGL((k_pr_scatter_vertex<int64_t, M, S>), dim3(grid_for(n)), dim3(kWG), lds, s,
+                           (const int64_t*)off, dst, n, c, mbx, nhub);
       else
-        hipLaunchKernelGGL((k_pr_scatter_vertex<int32_t, M, S>), dim3(grid_for(n)), dim3(kWG), 0, s,
-                           (const int32_t*)off, dst, n, c, mbx);
+        hipLaunchKernelGGL((k_pr_scatter_vertex<int32_t, M, S>), dim3(grid_for(n)), dim3(kWG), lds, s,
+                           (const int32_t*)off, dst, n, c, mbx, nhub);
       break;
+    }
     case 2: {  // merge-path broadcast
-      const size_t lds = align16((size_t)(tile + 1) * sizeof(S)) + (size_t)(tile + 2) * (off64 ? 8 : 4);
+      const size_t lds = align16((size_t)(tile + 1) * sizeof(S)) + align16((size_t)(tile + 2) * (off64 ? 8 : 4)) +
+                         (size_t)nhub * sizeof(S);
       if (off64)
         hipLaunchKernelGGL((k_pr_scatter_mp<int64_t, M, S>), dim3((unsigned)ntiles), dim3(kWG), lds, s,
-                           (const int64_t*)off, dst, n, m, tile_v, tile, c, mbx);
+                           (const int64_t*)off, dst, n, m, tile_v, tile, c, mbx, nhub);
       else
         hipLaunchKernelGGL((k_pr_scatter_mp<int32_t, M, S>), dim3((unsigned)ntiles), dim3(kWG), lds, s,
-                           (const int32_t*)off, dst, n, m, tile_v, tile, c, mbx);
+                           (const int32_t*)off, dst, n, m, tile_v, tile, c, mbx, nhub);
       break;
     }
     default:  // apply; a = teleport, b = damping
@@ -545,17 +704,18 @@ hipError_t pr_launch_all(int what, const void* off, bool off64, const int32_t* d
 inline hipError_t pr_launch(int mode, int what, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
                             const int32_t* tile_v, int64_t tile, int64_t ntiles, double a, double b, int64_t source,
                             void* contrib, void* mb, float* out, bool last, hipStream_t s,
-                            const uint8_t* kinds = nullptr) {
+                            const uint8_t* kinds = nullptr, bool hub = false) {
   switch (mode) {
     case kRankFixed:
       return pr_launch_all<unsigned long long, unsigned long long>(what, off, off64, dst, n, m, tile_v, tile, ntiles,
-                                                                   a, b, source, contrib, mb, out, last, s, kinds);
+                                                                   a, b, source, contrib, mb, out, last, s, kinds,
+                                                                   hub);
     case kRankF32Msg:
       return pr_launch_all<float, unsigned long long>(what, off, off64, dst, n, m, tile_v, tile, ntiles, a, b, source,
-                                                      contrib, mb, out, last, s, kinds);
+                                                      contrib, mb, out, last, s, kinds, hub);
     case kRankF32:
       return pr_launch_all<float, float>(what, off, off64, dst, n, m, tile_v, tile, ntiles, a, b, source, contrib, mb,
-                                         out, last, s, kinds);
+                                         out, last, s, kinds, hub);
   }
   return hipErrorInvalidValue;
 }
@@ -567,17 +727,17 @@ hipError_t launch_pr_init(int mode, const void* off, bool off64, int64_t n, doub
 }
 
 hipError_t launch_pr_scatter_vertex(int mode, const void* off, bool off64, const int32_t* dst, int64_t n,
-                                    const void* contrib, void* mb, hipStream_t s) {
+                                    const void* contrib, void* mb, bool hub, hipStream_t s) {
   return pr_launch(mode, 1, off, off64, dst, n, 0, nullptr, 0, 0, 0, 0, -1, const_cast<void*>(contrib), mb, nullptr,
-                   false, s);
+                   false, s, nullptr, hub);
 }
 
 hipError_t launch_pr_scatter_mp(int mode, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
                                 const int32_t* tile_v, int64_t tile, int64_t ntiles, const void* contrib, void* mb,
-                                hipStream_t s) {
+                                bool hub, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   return pr_launch(mode, 2, off, off64, dst, n, m, tile_v, tile, ntiles, 0, 0, -1, const_cast<void*>(contrib), mb,
-                   nullptr, false, s);
+                   nullptr, false, s, nullptr, hub);
 }
 
 hipError_t launch_pr_apply(int mode, const void* off, bool off64, int64_t n, double teleport, double damping,
@@ -606,97 +766,104 @@ hipError_t launch_min_seed_source(const void* off, bool off64, int64_t source, i
 namespace {
 template <class OffT, int KIND, bool LIST, bool TBA>
 void vertex_launch(const void* off, const int32_t* dst, const uint32_t* w, int64_t items, const int32_t* fq,
-                   uint2* vm, uint32_t* bitmap, hipStream_t s) {
-  hipLaunchKernelGGL((k_min_scatter_vertex<OffT, KIND, LIST, TBA>), dim3(grid_for(items)), dim3(kWG), 0, s,
-                     (const OffT*)off, dst, w, items, fq, vm, bitmap);
+                   uint2* vm, uint32_t* bitmap, int nhub, hipStream_t s) {
+  hipLaunchKernelGGL((k_min_scatter_vertex<OffT, KIND, LIST, TBA>), dim3(grid_for(items)), dim3(kWG),
+                     (size_t)nhub * 4, s, (const OffT*)off, dst, w, items, fq, vm, bitmap, nhub);
 }
 
 template <class OffT, int KIND, bool LIST, bool TBA>
 void mp_launch(const void* off, const int32_t* dst, const uint32_t* w, int64_t items, int64_t total,
                const int64_t* P, const int32_t* fq, const int32_t* tile_v, int64_t tile, int64_t ntiles, uint2* vm,
-               uint32_t* bitmap, hipStream_t s) {
-  const size_t lds = min_mp_lds_bytes(tile, LIST);
+               uint32_t* bitmap, int nhub, hipStream_t s) {
+  const size_t lds = min_mp_lds_bytes(tile, LIST) - kHubBytes + (size_t)nhub * 4;
   if (LIST)
     hipLaunchKernelGGL((k_min_scatter_mp<int64_t, OffT, KIND, LIST, TBA>), dim3((unsigned)ntiles), dim3(kWG), lds,
-                       s, (const OffT*)off, dst, w, items, total, P, fq, tile_v, tile, vm, bitmap);
+                       s, (const OffT*)off, dst, w, items, total, P, fq, tile_v, tile, vm, bitmap, nhub);
   else  // dense: the prefix is the CSR offsets themselves
     hipLaunchKernelGGL((k_min_scatter_mp<OffT, OffT, KIND, LIST, TBA>), dim3((unsigned)ntiles), dim3(kWG), lds, s,
-                       (const OffT*)off, dst, w, items, total, (const OffT*)off, fq, tile_v, tile, vm, bitmap);
+                       (const OffT*)off, dst, w, items, total, (const OffT*)off, fq, tile_v, tile, vm, bitmap, nhub);
 }
 
 template <class OffT, int KIND>
 void vertex_dispatch(bool list, bool tba, const void* off, const int32_t* dst, const uint32_t* w, int64_t items,
-                     const int32_t* fq, uint2* vm, uint32_t* bitmap, hipStream_t s) {
+                     const int32_t* fq, uint2* vm, uint32_t* bitmap, int nhub, hipStream_t s) {
   if (list) {
     if (tba)
-      vertex_launch<OffT, KIND, true, true>(off, dst, w, items, fq, vm, bitmap, s);
+      vertex_launch<OffT, KIND, true, true>(off, dst, w, items, fq, vm, bitmap, nhub, s);
     else
-      vertex_launch<OffT, KIND, true, false>(off, dst, w, items, fq, vm, bitmap, s);
+      vertex_launch<OffT, KIND, true, false>(off, dst, w, items, fq, vm, bitmap, nhub, s);
   } else {
     if (tba)
-      vertex_launch<OffT, KIND, false, true>(off, dst, w, items, fq, vm, bitmap, s);
+      vertex_launch<OffT, KIND, false, true>(off, dst, w, items, fq, vm, bitmap, nhub, s);
     else
-      vertex_launch<OffT, KIND, false, false>(off, dst, w, items, fq, vm, bitmap, s);
+      vertex_launch<OffT, KIND, false, false>(off, dst, w, items, fq, vm, bitmap, nhub, s);
   }
 }
 
 template <class OffT, int KIND>
 void mp_dispatch(bool list, bool tba, const void* off, const int32_t* dst, const uint32_t* w, int64_t items,
                  int64_t total, const int64_t* P, const int32_t* fq, const int32_t* tile_v, int64_t tile,
-                 int64_t ntiles, uint2* vm, uint32_t* bitmap, hipStream_t s) {
+                 int64_t ntiles, uint2* vm, uint32_t* bitmap, int nhub, hipStream_t s) {
   if (list) {
     if (tba)
-      mp_launch<OffT, KIND, true, true>(off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap, s);
+      mp_launch<OffT, KIND, true, true>(off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap, nhub, s);
     else
-      mp_launch<OffT, KIND, true, false>(off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap, s);
+      mp_launch<OffT, KIND, true, false>(off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap, nhub, s);
   } else {
     if (tba)
-      mp_launch<OffT, KIND, false, true>(off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap, s);
+      mp_launch<OffT, KIND, false, true>(off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap, nhub, s);
     else
-      mp_launch<OffT, KIND, false, false>(off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap, s);
+      mp_launch<OffT, KIND, false, false>(off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap, nhub,
+                                          s);
   }
 }
 }  // namespace
 
 hipError_t launch_min_scatter_vertex(int kind, bool list, bool tba, const void* off, bool off64, const int32_t* dst,
-                                     const uint32_t* w, int64_t items, const int32_t* fq, uint2* vm, uint32_t* bitmap,
-                                     hipStream_t s) {
+                                     const uint32_t* w, int64_t n, int64_t items, const int32_t* fq, uint2* vm,
+                                     uint32_t* bitmap, bool hub, hipStream_t s) {
   if (items <= 0) return hipSuccess;
+  const int nhub = hub_slots(n, 4, hub);
   if (off64) {
-    if (kind == kCC) vertex_dispatch<int64_t, kCC>(list, tba, off, dst, w, items, fq, vm, bitmap, s);
-    else if (kind == kSsspUnit) vertex_dispatch<int64_t, kSsspUnit>(list, tba, off, dst, w, items, fq, vm, bitmap, s);
-    else vertex_dispatch<int64_t, kSsspWeighted>(list, tba, off, dst, w, items, fq, vm, bitmap, s);
+    if (kind == kCC) vertex_dispatch<int64_t, kCC>(list, tba, off, dst, w, items, fq, vm, bitmap, nhub, s);
+    else if (kind == kSsspUnit)
+      vertex_dispatch<int64_t, kSsspUnit>(list, tba, off, dst, w, items, fq, vm, bitmap, nhub, s);
+    else vertex_dispatch<int64_t, kSsspWeighted>(list, tba, off, dst, w, items, fq, vm, bitmap, nhub, s);
   } else {
-    if (kind == kCC) vertex_dispatch<int32_t, kCC>(list, tba, off, dst, w, items, fq, vm, bitmap, s);
-    else if (kind == kSsspUnit) vertex_dispatch<int32_t, kSsspUnit>(list, tba, off, dst, w, items, fq, vm, bitmap, s);
-    else vertex_dispatch<int32_t, kSsspWeighted>(list, tba, off, dst, w, items, fq, vm, bitmap, s);
+    if (kind == kCC) vertex_dispatch<int32_t, kCC>(list, tba, off, dst, w, items, fq, vm, bitmap, nhub, s);
+    else if (kind == kSsspUnit)
+      vertex_dispatch<int32_t, kSsspUnit>(list, tba, off, dst, w, items, fq, vm, bitmap, nhub, s);
+    else vertex_dispatch<int32_t, kSsspWeighted>(list, tba, off, dst, w, items, fq, vm, bitmap, nhub, s);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_min_scatter_mp(int kind, bool list, bool tba, const void* off, bool off64, const int32_t* dst,
-                                 const uint32_t* w, int64_t items, int64_t total, const int64_t* P, const int32_t* fq,
-                                 const int32_t* tile_v, int64_t tile, int64_t ntiles, uint2* vm, uint32_t* bitmap,
-                                 hipStream_t s) {
+                                 const uint32_t* w, int64_t n, int64_t items, int64_t total, const int64_t* P,
+                                 const int32_t* fq, const int32_t* tile_v, int64_t tile, int64_t ntiles, uint2* vm,
+                                 uint32_t* bitmap, bool hub, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
+  const int nhub = hub_slots(n, 4, hub);
   if (off64) {
     if (kind == kCC)
-      mp_dispatch<int64_t, kCC>(list, tba, off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap, s);
+      mp_dispatch<int64_t, kCC>(list, tba, off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap, nhub,
+                                s);
     else if (kind == kSsspUnit)
       mp_dispatch<int64_t, kSsspUnit>(list, tba, off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap,
-                                      s);
+                                      nhub, s);
     else
       mp_dispatch<int64_t, kSsspWeighted>(list, tba, off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm,
-                                          bitmap, s);
+                                          bitmap, nhub, s);
   } else {
     if (kind == kCC)
-      mp_dispatch<int32_t, kCC>(list, tba, off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap, s);
+      mp_dispatch<int32_t, kCC>(list, tba, off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap, nhub,
+                                s);
     else if (kind == kSsspUnit)
       mp_dispatch<int32_t, kSsspUnit>(list, tba, off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm, bitmap,
-                                      s);
+                                      nhub, s);
     else
       mp_dispatch<int32_t, kSsspWeighted>(list, tba, off, dst, w, items, total, P, fq, tile_v, tile, ntiles, vm,
-                                          bitmap, s);
+                                          bitmap, nhub, s);
   }
   return hipGetLastError();
 }

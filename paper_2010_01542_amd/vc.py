@@ -37,7 +37,7 @@ EXPORTS = ("vc_graph_create", "vc_graph_destroy", "vc_graph_footprint", "vc_run"
            "vc_status_string", "vc_last_error", "vc_abi_version", "vc_batch_create", "vc_batch_layout",
            "vc_batch_run", "vc_batch_destroy", "vc_run_multi_source", "vc_graph_autotune", "vc_batch_autotune",
            "vc_server_create", "vc_server_add_graph", "vc_server_submit", "vc_server_poll", "vc_server_drain",
-           "vc_server_info_get", "vc_server_destroy", "vc_combine")
+           "vc_server_info_get", "vc_server_destroy", "vc_combine", "vc_graph_prepare")
 
 
 class GraphDesc(ctypes.Structure):
@@ -113,6 +113,8 @@ def load(path: str = LIB_PATH):
     lib.vc_graph_footprint.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
     lib.vc_run.restype = i32
     lib.vc_run.argtypes = [vp, i32, ctypes.POINTER(Params), vp, vp, ctypes.POINTER(StatsStruct)]
+    lib.vc_graph_prepare.restype = i32
+    lib.vc_graph_prepare.argtypes = [vp, i32, ctypes.POINTER(Params), vp]
     lib.vc_params_default.restype = None
     lib.vc_params_default.argtypes = [ctypes.POINTER(Params)]
     lib.vc_status_string.restype = ctypes.c_char_p
@@ -268,6 +270,13 @@ class Graph:
         _check(load().vc_graph_footprint(self._h, _program(program), ctypes.byref(held), ctypes.byref(run)),
                "vc_graph_footprint")
         return held.value, run.value
+
+    def prepare(self, program, *, T: int = 10, source: int = 0, schedule="auto", tile: int = 0, options: int = 0,
+                stream=None):
+        """vc_graph_prepare: builds what a first run with these parameters would build."""
+        prog = _program(program)
+        p = _params(T if prog in (PAGERANK, PPR) else 0, 0.85, source, schedule, tile, options)
+        _check(load().vc_graph_prepare(self._h, prog, ctypes.byref(p), _stream_handle(stream)), "vc_graph_prepare")
 
     def autotune(self, program, *, T: int = 10, damping: float = 0.85, source: int = 0, stream=None) -> dict:
         """vc_graph_autotune: picks and keeps the fastest distribution for `program`."""

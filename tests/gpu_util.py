@@ -3,10 +3,15 @@ compare them to the stated bars.
 
 Bars:
 * CC labels and SSSP distances: bit-exact, and the per-superstep frontier
-  sizes |F_s| and message counts E_s equal the oracle's (the superstep model
-  is synchronous, so they are deterministic).
+  sizes |F_s| and message counts E_s, which the device counts in its
+  compaction kernel, equal the oracle's (the superstep model is synchronous,
+  so they are deterministic; the oracle's counts are pinned against dense
+  min-plus relaxation in test_oracle_pins).
 * PageRank / PPR: binary32 device ranks against the binary64 oracle,
   L1 = sum_v |r_dev - r_ora| <= 1e-5 and max_v |r_dev - r_ora| <= 1e-7.
+  The device reports |F_s| = N and E_s = M for every PageRank superstep by
+  definition (every vertex broadcasts), from the host, so those are not
+  compared: such a comparison could not fail.
 """
 import numpy as np
 
@@ -46,6 +51,4 @@ def check_rank(csr, graph, program="pagerank", T=10, source=0, **kw):
     print(f"{program} n={csr.n} m={csr.m} T={T} L1={l1:.3e} max_abs={mx:.3e}", flush=True)
     assert l1 <= L1_TOL and mx <= MAX_ABS_TOL, (l1, mx)
     assert st.supersteps == ref.supersteps
-    assert st.frontier.tolist() == ref.senders.tolist()
-    assert st.edges.tolist() == ref.messages.tolist()
     return got, st, (l1, mx)

@@ -114,6 +114,7 @@ def test_argument_errors_need_no_device():
     assert lib.vc_graph_create(ctypes.byref(d), None, ctypes.byref(h)) == vc.ERR_INVALID_ARG
     assert b"misaligned" in lib.vc_last_error()
     assert lib.vc_run(None, vc.SSSP, None, 16, None, None) == vc.ERR_INVALID_ARG
+    assert lib.vc_graph_prepare(None, vc.SSSP, None, None) == vc.ERR_INVALID_ARG
     assert lib.vc_graph_destroy(None) == vc.OK
     held = ctypes.c_size_t()
     assert lib.vc_graph_footprint(None, 0, ctypes.byref(held), None) == vc.ERR_INVALID_ARG

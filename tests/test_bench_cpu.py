@@ -37,3 +37,19 @@ def test_traffic_record_is_used_only_for_its_own_source_and_run(monkeypatch):
     assert bench.measured_traffic("cc-s22@s22", "blocked", 16) is None  # other workload
     monkeypatch.setattr(bench, "kernel_source_hash", lambda form: "0" * 16)
     assert bench.measured_traffic("sssp-s26@s26", "blocked", 16) is None  # kernel source changed
+
+
+def test_whole_pagerank_superstep_adds_the_rank_write():
+    n, m = 1 << 26, 1060380725
+    assert bench.pr_superstep_bytes(n, m, 8) == bench.pr_scatter_bytes(n, m, 8) + 4 * n
+
+
+def test_min_superstep_bytes_formula():
+    # SSSP on 10 vertices, int64 offsets, weighted: a source with 3 out-edges
+    # reaching 3 receivers, 2 of which improve; then those 2 send 5 messages
+    # to 4 receivers, 0 improve
+    got = bench.min_superstep_bytes(10, 8, True, [1, 2, 0], [3, 5, 0], [3, 4, 0], dense0=False)
+    assert got == [1 * 24 + 3 * 16 + 3 * 12 + 2 * 8, 2 * 24 + 5 * 16 + 4 * 12 + 0, 0]
+    # CC, int32 offsets, unweighted, superstep 0 dense: N (4 + o) for the senders
+    got = bench.min_superstep_bytes(10, 4, False, [10, 4], [30, 7], [9, 5], dense0=True)
+    assert got == [10 * 8 + 30 * 12 + 9 * 12 + 4 * 8, 4 * 16 + 7 * 12 + 5 * 12]

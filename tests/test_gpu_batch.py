@@ -68,3 +68,64 @@ def test_batch_rejects_bad_queries(device):
         Batch([c], [("pagerank", 0)])
     with pytest.raises(VcError):
         Batch([c], [("sssp", 4)])
+
+
+def union_stats(refs):
+    """Per-superstep senders and messages of the union: the members run in
+    lockstep supersteps, so the union's counts are the members' sums, each
+    member contributing zeros once it has quiesced."""
+    steps = max(r.supersteps for r in refs)
+    senders, messages = np.zeros(steps, np.int64), np.zeros(steps, np.int64)
+    for r in refs:
+        senders[: r.supersteps] += r.senders
+        messages[: r.supersteps] += r.messages
+    return steps, senders.tolist(), messages.tolist()
+
+
+@pytest.fixture(scope="module", params=[False, True], ids=["byte-weights", "wide-weights"])
+def big_union(request):
+    """A union of more than 2^20 vertices, the size at which AUTO takes the
+    blocked form for dense supersteps: 48 members of scales 14..16 (edge
+    factor 8..32), symmetrised CC and weighted SSSP in [1, 255] (the
+    benchmark's batch; the blocked layout then keeps one-byte slot weights)
+    or with some members' weights beyond a byte (four-byte slot weights),
+    plus an edgeless member and a lone vertex."""
+    wide = request.param
+    rng = np.random.default_rng(2024)
+    csrs, queries = [], []
+    for i in range(48):
+        sc, ef = int(rng.integers(14, 17)), int(rng.integers(8, 33))
+        if i % 2 == 0:
+            csrs.append(rmatgen.rmat(sc, ef, seed=7000 + i, directed=False))
+            queries.append(("cc", 0))
+        else:
+            c = rmatgen.rmat(sc, ef, seed=7000 + i, weighted=True)
+            if wide and i % 6 == 1:
+                c = rmatgen.Csr(c.n, c.m, c.off, c.dst, (c.w.astype(np.uint32) * 997).astype(np.uint32))
+            csrs.append(c)
+            queries.append(("sssp", int(rng.integers(0, c.n))))
+    csrs.append(rmatgen.raw_csr(300, [], []))
+    queries.append(("cc", 0))
+    csrs.append(rmatgen.raw_csr(1, [], []))
+    queries.append(("sssp", 0))
+    refs = [oracle.run(p, c.n, c.off, c.dst, c.w if p == "sssp" else None, source=s)
+            for c, (p, s) in zip(csrs, queries)]
+    return csrs, queries, refs
+
+
+@pytest.mark.parametrize("sched", ["blocked", "auto"])
+def test_large_union_takes_blocked_form_bit_exact(device, big_union, sched):
+    from paper_2010_01542_amd import Batch, vc
+    csrs, queries, refs = big_union
+    n = sum(c.n for c in csrs)
+    assert n >= 1 << 20
+    print(f"case batch union n={n} m={sum(c.m for c in csrs)} schedule={sched}", flush=True)
+    b = Batch(csrs, queries)
+    out, st = b.run(schedule=sched, stats=True)
+    for i, (c, (prog, src), got, ref) in enumerate(zip(csrs, queries, b.split(out), refs)):
+        assert np.array_equal(got, ref.values), (i, prog, c.n, c.m, int((got != ref.values).sum()))
+    steps, senders, messages = union_stats(refs)
+    assert st.supersteps == steps
+    assert st.frontier.tolist() == senders
+    assert st.edges.tolist() == messages
+    assert vc.SCHED_BLOCKED in st.schedule.tolist(), st.schedule.tolist()

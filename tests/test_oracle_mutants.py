@@ -17,6 +17,7 @@ from scipy.sparse.csgraph import connected_components, dijkstra
 
 import oracle
 import rmatgen
+from test_oracle_pins import hop_bounded_min
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
 
@@ -38,6 +39,10 @@ MUTANTS = {
     "minarg-tie-to-larger-id": ("(b == a && ib < ia)", "(b == a && ib > ia)"),
     "max-becomes-min": ("word_f64(msg) > word_f64(stored)", "word_f64(msg) < word_f64(stored)"),
     "inactive-vertices-send": ("if (active && !active[v]) continue;", "if (active && !active[v] && v < 0) continue;"),
+    # per-superstep counts: a message not counted, receivers read from the wrong mailbox flags
+    "messages-miscounted": ("    deliver_min(g, g->dst[e], m);\n    g->messages++;",
+                            "    deliver_min(g, g->dst[e], m);\n    if (e > g->off[v]) g->messages++;"),
+    "receivers-from-current-flags": ("receivers += g.has_next[v];", "receivers += g.has_cur[v];"),
     # Section III's failure: "received" read as "mailbox differs from the neutral value"
     "received-means-not-neutral": ("  }\n  return ORACLE_OK;\n}\n\n/* Library version tag",
                                    "  }\n  for (int64_t u = 0; u < n; ++u) has[u] = has[u] && mailbox[u] != 0;\n"
@@ -80,7 +85,13 @@ def _pins_pass(lib) -> bool:
         _, lab = connected_components(csr_matrix((np.ones(250), (s, t)), shape=(300, 300)), directed=False)
         mins = np.full(lab.max() + 1, 300)
         np.minimum.at(mins, lab, np.arange(300))
-        if not np.array_equal(oracle.run_csr("cc", g, lib=lib).values, mins[lab]):
+        r = oracle.run_csr("cc", g, lib=lib)
+        if not np.array_equal(r.values, mins[lab]):
+            return False
+        # its per-superstep senders, messages and receivers against dense label propagation
+        arcs = [(u, v, 0) for u, v in zip(np.repeat(np.arange(g.n), g.outdeg).tolist(), g.dst.tolist())]
+        if (r.senders.tolist(), r.messages.tolist(), r.receivers.tolist()) != hop_bounded_min(
+                g.n, arcs, np.arange(g.n), np.ones(g.n, bool)):
             return False
         # SSSP vs Dijkstra on a seeded weighted R-MAT graph
         g = rmatgen.rmat(9, 8, seed=4, weighted=True)

@@ -147,25 +147,45 @@ def hop_bounded_min(n, arcs, init, senders0):
     """Synchronous min-plus relaxation in dense form.
 
     value(s) = min(value(s-1), min_{u->v} value(s-1)[u] + w(u,v)); the vertices
-    whose value drops at step s are the step-s senders.  Returns the sender
-    counts per step, ending as the superstep model ends (see module doc).
+    whose value drops at step s are the step-s senders.  Per step it returns
+    the senders, the messages they send (their out-degrees, every arc of a
+    multigraph counted: one message per CSR edge, Section V's workload unit)
+    and the receivers (vertices with at least one arc from a sender), ending
+    as the superstep model ends (see module doc).
     """
     wmat = np.full((n, n), np.inf)
+    adj = np.zeros((n, n), dtype=bool)
+    outdeg = np.zeros(n, dtype=np.int64)
     for u, v, w in arcs:
         wmat[u, v] = min(wmat[u, v], w)
-    val = np.array(init, dtype=np.float64)
-    outdeg = np.zeros(n, dtype=np.int64)
-    for u, _, _ in arcs:
+        adj[u, v] = True
         outdeg[u] += 1
-    senders = [int(senders0.sum())]
+    val = np.array(init, dtype=np.float64)
     sending = senders0.copy()
-    while outdeg[sending].sum() > 0:
+    senders, messages, receivers = [], [], []
+
+    def record():
+        senders.append(int(sending.sum()))
+        messages.append(int(outdeg[sending].sum()))
+        receivers.append(int(adj[sending].any(axis=0).sum()))
+
+    record()
+    while messages[-1] > 0:
         cand = np.min(np.where(sending[:, None], val[:, None] + wmat, np.inf), axis=0)
         new = np.minimum(val, cand)
         sending = new < val
         val = new
-        senders.append(int(sending.sum()))
-    return senders
+        record()
+    return senders, messages, receivers
+
+
+def assert_stats_pinned(r, ref):
+    """The oracle's per-superstep senders, messages and receivers against
+    hop_bounded_min's (senders, messages, receivers)."""
+    senders, messages, receivers = ref
+    assert r.senders.tolist() == senders
+    assert r.messages.tolist() == messages
+    assert r.receivers.tolist() == receivers
 
 
 def graph_arcs(g, unit=False):
@@ -196,7 +216,7 @@ def test_cc_random_matches_scipy(seed):
     assert np.array_equal(r.values, min_id_components(n, s, d))
     # label propagation is min-plus relaxation with zero-weight arcs
     zero_arcs = [(u, v, 0) for u, v, _ in graph_arcs(g)]
-    assert r.senders.tolist() == hop_bounded_min(n, zero_arcs, np.arange(n), np.ones(n, bool))
+    assert_stats_pinned(r, hop_bounded_min(n, zero_arcs, np.arange(n), np.ones(n, bool)))
 
 
 def test_cc_rmat_invariants():
@@ -245,7 +265,8 @@ def test_sssp_exhaustive_4_vertex_digraphs():
         init[src] = 0
         start = np.zeros(4, bool)
         start[src] = True
-        assert r.senders.tolist() == hop_bounded_min(4, wa, init, start), (arcs, w, src)
+        ref = hop_bounded_min(4, wa, init, start)
+        assert (r.senders.tolist(), r.messages.tolist(), r.receivers.tolist()) == ref, (arcs, w, src)
 
 
 @pytest.mark.parametrize("seed", range(4))
@@ -261,7 +282,7 @@ def test_sssp_rmat_matches_dijkstra(seed):
         start = np.zeros(g.n, bool)
         start[src] = True
         if seed == 0 and src == 0:
-            assert r.senders.tolist() == hop_bounded_min(g.n, graph_arcs(g), init, start)
+            assert_stats_pinned(r, hop_bounded_min(g.n, graph_arcs(g), init, start))
 
 
 def test_sssp_unit_weights_are_bfs_levels():
