@@ -768,7 +768,7 @@ def main():
         bs = min_superstep_bytes(n, off_bytes, prog == "sssp" and csr.w is not None, st.frontier.tolist(),
                                  st.edges.tolist(), ref.receivers.tolist(), dense0=prog == "cc")
         per = []
-        for s, (b, ms) in enumerate(zip(bs, steps_ms)):
+        for s, (b, ms) in enumerate(zip(bs, steps_ms.tolist())):
             if ms > 0:
                 per.append({"s": s, "bytes": b, "ms": round(float(ms), 4),
                             "gbs": round(b / (ms * 1e-3) / 1e9, 1),

@@ -117,6 +117,26 @@ vc_status dense_partition(vc_graph g, int64_t tile, hipStream_t s) {
   return VC_OK;
 }
 
+// In-degree of every vertex of g into cnt (n + 1 uint64 entries, zero on
+// entry): binned in LDS where the graph qualifies, else one atomic per edge.
+vc_status count_in_degrees(vc_graph g, unsigned long long* cnt, hipStream_t s) {
+  IdPlan plan;
+  if (!id_binned(g->n, g->m, g->max_lds, &plan)) {
+    VC_TRY(launch_csc_count(g->dst, g->m, cnt, s));
+    return VC_OK;
+  }
+  DevBuf hist, bin_start, piece_pre, blocks, grouped;
+  VC_TRY(hist.ensure((size_t)plan.chunks * (size_t)plan.nb * 4));
+  VC_TRY(bin_start.ensure((size_t)(plan.nb + 1) * 8));
+  VC_TRY(piece_pre.ensure((size_t)(plan.nb + 1) * 8));
+  VC_TRY(blocks.ensure((size_t)scan_scratch_entries(plan.nb) * 8));
+  VC_TRY(grouped.ensure((size_t)g->m * 2 + 16));
+  VC_TRY(launch_id_binned(plan, g->dst, g->n, g->m, hist.as<uint32_t>(), bin_start.as<int64_t>(),
+                          piece_pre.as<int64_t>(), blocks.as<int64_t>(), grouped.as<uint16_t>(), cnt, s));
+  VC_TRY(hipStreamSynchronize(s));  // before the temporaries are freed
+  return VC_OK;
+}
+
 // Builds the transpose once per graph: in-degree histogram, exclusive scan,
 // then every edge placed at its target's cursor.  Symmetric graphs (flag)
 // read the CSR itself.
@@ -141,7 +161,8 @@ vc_status ensure_csc(vc_graph g, hipStream_t s) {
     VC_TRY(blocks.ensure((size_t)vc::scan_scratch_entries(n) * 8));
     VC_TRY(cursor.ensure((size_t)(n + 1) * 8));
     VC_TRY(vc::launch_fill_u32(reinterpret_cast<uint32_t*>(in_off), 2 * (n + 1), 0u, s));
-    VC_TRY(vc::launch_csc_count(g->dst, m, reinterpret_cast<unsigned long long*>(in_off), s));
+    vc_status cst = count_in_degrees(g, reinterpret_cast<unsigned long long*>(in_off), s);
+    if (cst != VC_OK) return cst;
     VC_TRY(vc::launch_exclusive_scan(in_off, n, blocks.as<int64_t>(), s));
     VC_TRY(hipMemcpyAsync(cursor.p, in_off, (size_t)(n + 1) * 8, hipMemcpyDeviceToDevice, s));
     const int64_t tile = vc::kDefaultTile;
@@ -205,7 +226,8 @@ vc_status relabel(vc_graph g, hipStream_t s) {
   if (g->w) VC_TRY(g->rel_w.ensure((size_t)m * 4 + 4));
   unsigned long long* deg_in = indeg.as<unsigned long long>();
   VC_TRY(vc::launch_fill_u32(reinterpret_cast<uint32_t*>(deg_in), 2 * (n + 1), 0u, s));
-  VC_TRY(vc::launch_csc_count(g->dst, m, deg_in, s));
+  vc_status cst = vc::count_in_degrees(g, deg_in, s);
+  if (cst != VC_OK) return cst;
   VC_TRY(vc::launch_relabel_perm(g->off, g->off64, deg_in, n, hist.as<int64_t>(), blocks.as<int64_t>(),
                                  perm, inv, s));
   int64_t* noff = g->rel_off.as<int64_t>();

@@ -79,16 +79,38 @@ __global__ __launch_bounds__(kWG) void k_pb_expand(const OffT* __restrict__ off,
 
 constexpr int kBuildWG = 1024;
 
-// *out = max(*out, largest of the m weights).
+// *out = max(*out, largest of the m weights).  A grid of a few workgroups
+// per CU streams the weights in 16-byte loads (after a head of up to three
+// words that brings the pointer to 16-byte alignment), reduces in each
+// wavefront and then in LDS, and issues one atomic per workgroup.
 __global__ __launch_bounds__(kWG) void k_pb_wmax(const uint32_t* __restrict__ w, int64_t m, uint32_t* __restrict__ out) {
+  __shared__ uint32_t s_w[kWG / 64];
+  const int64_t lead = (int64_t)(((16 - ((uintptr_t)w & 15)) & 15) >> 2);  // words before a 16-byte boundary
+  const int64_t head = lead < m ? lead : m;
   uint32_t x = 0;
-  for (int64_t e = gid(); e < m; e += grid_threads()) x = w[e] > x ? w[e] : x;
+  if (gid() < head) x = w[gid()];
+  const uint4* w4 = reinterpret_cast<const uint4*>(w + head);
+  const int64_t m4 = (m - head) >> 2;
+  for (int64_t i = gid(); i < m4; i += grid_threads()) {
+    const uint4 q = w4[i];
+    const uint32_t a = q.x > q.y ? q.x : q.y, b = q.z > q.w ? q.z : q.w;
+    const uint32_t c = a > b ? a : b;
+    x = c > x ? c : x;
+  }
+  for (int64_t e = head + (m4 << 2) + gid(); e < m; e += grid_threads()) x = w[e] > x ? w[e] : x;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     const uint32_t y = __shfl_xor(x, o, 64);
     x = y > x ? y : x;
   }
-  if (lane_id() == 0 && x) atomicMax(out, x);
+  if (lane_id() == 0) s_w[threadIdx.x >> 6] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int i = 0; i < kWG / 64; ++i) r = s_w[i] > r ? s_w[i] : r;
+    if (r) atomicMax(out, r);
+  }
 }
 
 // Tile of edge c0: last t with te[t] <= c0 (te[0] = 0 <= c0 < m = te[tiles]).
@@ -550,7 +572,8 @@ hipError_t launch_pb_expand(const void* off, bool off64, int64_t n, int64_t m, c
 
 hipError_t launch_pb_wmax(const uint32_t* w, int64_t m, uint32_t* out, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pb_wmax, dim3(grid_stride_for(m)), dim3(kWG), 0, s, w, m, out);
+  const int64_t g = (m / 4 + kWG - 1) / kWG;  // one 16-byte load per thread at most, 2,048 workgroups at most
+  hipLaunchKernelGGL(k_pb_wmax, dim3((unsigned)(g < 2048 ? (g > 0 ? g : 1) : 2048)), dim3(kWG), 0, s, w, m, out);
   return hipGetLastError();
 }
 

@@ -127,6 +127,29 @@ hipError_t launch_zero_counters(Counters* ctr, hipStream_t s);
 // Transpose: in-degree histogram (cnt: n + 1 zeroed entries), then placement
 // of every edge at cursor[dst]++ (cursor = exclusive scan of cnt).
 hipError_t launch_csc_count(const int32_t* dst, int64_t m, unsigned long long* cnt, hipStream_t s);
+// The same histogram without per-edge global atomics, for graphs of at least
+// kIdMinEdges edges (a counting sort of the targets by bins of 2^shift
+// vertices, every count taken in LDS).  id_binned fills the plan and says
+// whether the graph qualifies (m < 2^32, at most kIdMaxBins bins of at most
+// 2^14 vertices, LDS large enough); launch_id_binned then needs
+//   hist       chunks * nb uint32,
+//   bin_start  nb + 1 int64,  piece_pre nb + 1 int64,
+//   scan_blocks scan_scratch_entries(nb) int64,
+//   grouped    m uint16,
+// and cnt (n + 1 entries) zero on entry.
+constexpr int64_t kIdMinEdges = 1ll << 19;
+constexpr int kIdMaxBins = 16384;
+constexpr int64_t kIdMinChunk = 1ll << 16;  // edges per chunk of the first passes, at least
+constexpr int64_t kIdMaxChunks = 1024;
+constexpr int64_t kIdPiece = 1ll << 18;     // grouped targets counted per workgroup, at most
+struct IdPlan {
+  int shift = 12, nb = 0;
+  int64_t chunk = 0, chunks = 0, piece = 0, max_pieces = 0;
+};
+bool id_binned(int64_t n, int64_t m, size_t max_lds, IdPlan* plan);
+hipError_t launch_id_binned(const IdPlan& p, const int32_t* dst, int64_t n, int64_t m, uint32_t* hist,
+                            int64_t* bin_start, int64_t* piece_pre, int64_t* scan_blocks, uint16_t* grouped,
+                            unsigned long long* cnt, hipStream_t s);
 hipError_t launch_widen_offsets(const int32_t* a, int64_t count, int64_t* b, hipStream_t s);
 hipError_t launch_csc_fill(const void* off, bool off64, const int32_t* dst, const uint32_t* w, int64_t n, int64_t m,
                            const int32_t* tile_v, int64_t tile, int64_t ntiles, unsigned long long* cursor,

@@ -34,6 +34,145 @@ __global__ __launch_bounds__(kWG) void k_csc_count(const int32_t* __restrict__ d
   for (int64_t e = gid(); e < m; e += (int64_t)gridDim.x * kWG) atomicAdd(&cnt[dst[e]], 1ull);
 }
 
+// In-degree histogram without per-edge global atomics (a counting sort of
+// the targets by bin): targets are grouped into bins of 2^shift vertices,
+// (1) every chunk of edges counts its targets per bin in LDS, (2) a column
+// scan over the chunks gives each chunk its place inside every bin, (3) each
+// chunk writes its targets' offsets inside their bins (2 bytes each) to
+// those places, so the offsets end up grouped by bin, (4) each piece of at
+// most `piece` grouped offsets counts them per vertex in LDS and writes the
+// counts: stored where the bin is one piece, added where it spans several.
+constexpr int kIdWG = 1024;
+
+__global__ __launch_bounds__(kIdWG) void k_id_hist(const int32_t* __restrict__ dst, int64_t m, int64_t chunk,
+                                                   int nb, int shift, uint32_t* __restrict__ hist) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint32_t* h = reinterpret_cast<uint32_t*>(smem);
+  for (int b = threadIdx.x; b < nb; b += kIdWG) h[b] = 0;
+  __syncthreads();
+  const int64_t e0 = (int64_t)blockIdx.x * chunk;
+  const int64_t e1 = e0 + chunk < m ? e0 + chunk : m;
+  int64_t e = e0 + threadIdx.x;
+  for (; e + 3 * kIdWG < e1; e += 4 * kIdWG) {  // four loads in flight before the LDS adds
+    const int32_t a = dst[e], b = dst[e + kIdWG], c = dst[e + 2 * kIdWG], d = dst[e + 3 * kIdWG];
+    atomicAdd(&h[a >> shift], 1u);
+    atomicAdd(&h[b >> shift], 1u);
+    atomicAdd(&h[c >> shift], 1u);
+    atomicAdd(&h[d >> shift], 1u);
+  }
+  for (; e < e1; e += kIdWG) atomicAdd(&h[dst[e] >> shift], 1u);
+  __syncthreads();
+  uint32_t* row = hist + (int64_t)blockIdx.x * nb;
+  for (int b = threadIdx.x; b < nb; b += kIdWG) row[b] = h[b];
+}
+
+// Per bin b (one thread): hist[w][b] becomes the number of b's targets in
+// chunks before w, tot[b] the bin's size.
+__global__ __launch_bounds__(kWG) void k_id_colscan(uint32_t* __restrict__ hist, int64_t chunks, int nb,
+                                                    int64_t* __restrict__ tot) {
+  const int64_t b = gid();
+  if (b >= nb) return;
+  uint32_t run = 0;
+  int64_t w = 0;
+  for (; w + 8 <= chunks; w += 8) {
+    uint32_t x[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[i] = hist[(w + i) * nb + b];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      hist[(w + i) * nb + b] = run;
+      run += x[i];
+    }
+  }
+  for (; w < chunks; ++w) {
+    const uint32_t x = hist[w * nb + b];
+    hist[w * nb + b] = run;
+    run += x;
+  }
+  tot[b] = run;
+}
+
+// Writes every target's offset inside its bin at its chunk's next place in
+// the bin; positions are below m < 2^32.
+__global__ __launch_bounds__(kIdWG) void k_id_scatter(const int32_t* __restrict__ dst, int64_t m, int64_t chunk,
+                                                      int nb, int shift, const uint32_t* __restrict__ hist,
+                                                      const int64_t* __restrict__ bin_start,
+                                                      uint16_t* __restrict__ grouped) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint32_t* cur = reinterpret_cast<uint32_t*>(smem);
+  const uint32_t* row = hist + (int64_t)blockIdx.x * nb;
+  for (int b = threadIdx.x; b < nb; b += kIdWG) cur[b] = (uint32_t)bin_start[b] + row[b];
+  __syncthreads();
+  const int64_t e0 = (int64_t)blockIdx.x * chunk;
+  const int64_t e1 = e0 + chunk < m ? e0 + chunk : m;
+  const int32_t mask = (1 << shift) - 1;
+  int64_t e = e0 + threadIdx.x;
+  for (; e + 3 * kIdWG < e1; e += 4 * kIdWG) {
+    const int32_t a = dst[e], b = dst[e + kIdWG], c = dst[e + 2 * kIdWG], d = dst[e + 3 * kIdWG];
+    grouped[atomicAdd(&cur[a >> shift], 1u)] = (uint16_t)(a & mask);
+    grouped[atomicAdd(&cur[b >> shift], 1u)] = (uint16_t)(b & mask);
+    grouped[atomicAdd(&cur[c >> shift], 1u)] = (uint16_t)(c & mask);
+    grouped[atomicAdd(&cur[d >> shift], 1u)] = (uint16_t)(d & mask);
+  }
+  for (; e < e1; e += kIdWG) {
+    const int32_t a = dst[e];
+    grouped[atomicAdd(&cur[a >> shift], 1u)] = (uint16_t)(a & mask);
+  }
+}
+
+// pieces[b] = number of pieces of bin b (bin_start holds nb + 1 entries).
+__global__ __launch_bounds__(kWG) void k_id_pieces(const int64_t* __restrict__ bin_start, int nb, int64_t piece,
+                                                   int64_t* __restrict__ pieces) {
+  const int64_t b = gid();
+  if (b < nb) pieces[b] = (bin_start[b + 1] - bin_start[b] + piece - 1) / piece;
+}
+
+// One workgroup per piece (grid: an upper bound of the piece count; the rest
+// return at once).  cnt: n + 1 entries, zero on entry.
+__global__ __launch_bounds__(kIdWG) void k_id_count(const uint16_t* __restrict__ grouped,
+                                                    const int64_t* __restrict__ bin_start,
+                                                    const int64_t* __restrict__ piece_pre, int nb, int shift,
+                                                    int64_t piece, int64_t n, unsigned long long* __restrict__ cnt) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint32_t* c = reinterpret_cast<uint32_t*>(smem);
+  const int64_t w = blockIdx.x;
+  if (w >= piece_pre[nb]) return;  // uniform over the workgroup
+  int lo = 0, hi = nb - 1;         // bin: last b with piece_pre[b] <= w
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (piece_pre[mid] <= w)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int b = lo;
+  const int width = 1 << shift;
+  for (int x = threadIdx.x; x < width; x += kIdWG) c[x] = 0;
+  __syncthreads();
+  const int64_t s0 = bin_start[b] + (w - piece_pre[b]) * piece;
+  const int64_t s1 = s0 + piece < bin_start[b + 1] ? s0 + piece : bin_start[b + 1];
+  int64_t i = s0 + threadIdx.x;
+  for (; i + 3 * kIdWG < s1; i += 4 * kIdWG) {
+    const uint16_t a = grouped[i], bb = grouped[i + kIdWG], cc = grouped[i + 2 * kIdWG], d = grouped[i + 3 * kIdWG];
+    atomicAdd(&c[a], 1u);
+    atomicAdd(&c[bb], 1u);
+    atomicAdd(&c[cc], 1u);
+    atomicAdd(&c[d], 1u);
+  }
+  for (; i < s1; i += kIdWG) atomicAdd(&c[grouped[i]], 1u);
+  __syncthreads();
+  const bool whole = piece_pre[b + 1] - piece_pre[b] == 1;
+  const int64_t v0 = (int64_t)b << shift;
+  const int64_t vend = v0 + width < n ? v0 + width : n;
+  for (int64_t v = v0 + threadIdx.x; v < vend; v += kIdWG) {
+    const uint32_t x = c[v - v0];
+    if (whole)
+      cnt[v] = x;
+    else if (x)
+      atomicAdd(&cnt[v], (unsigned long long)x);
+  }
+}
+
 // Places every edge u->v at cursor[v]++ in the CSC.  Workgroups own merge-path
 // tiles of the CSR so hubs are split; the source of an edge is found by a
 // binary search over the tile's offsets staged in LDS.
@@ -318,6 +457,39 @@ hipError_t launch_csc_count(const int32_t* dst, int64_t m, unsigned long long* c
   if (m <= 0) return hipSuccess;
   const int64_t blocks = (m + kWG - 1) / kWG;
   hipLaunchKernelGGL(k_csc_count, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(kWG), 0, s, dst, m, cnt);
+  return hipGetLastError();
+}
+
+bool id_binned(int64_t n, int64_t m, size_t max_lds, IdPlan* plan) {
+  if (m < kIdMinEdges || m >= (1ll << 32)) return false;
+  int shift = 12;
+  while (((n + (1ll << shift) - 1) >> shift) > kIdMaxBins) ++shift;
+  if (shift > 14 || ((size_t)4 << shift) > max_lds || (size_t)kIdMaxBins * 4 > max_lds) return false;
+  plan->shift = shift;
+  plan->nb = (int)((n + (1ll << shift) - 1) >> shift);
+  plan->chunk = std::max<int64_t>(kIdMinChunk, (m + kIdMaxChunks - 1) / kIdMaxChunks);
+  plan->chunks = (m + plan->chunk - 1) / plan->chunk;
+  plan->piece = kIdPiece;
+  plan->max_pieces = plan->nb + (m + plan->piece - 1) / plan->piece;
+  return true;
+}
+
+hipError_t launch_id_binned(const IdPlan& p, const int32_t* dst, int64_t n, int64_t m, uint32_t* hist,
+                            int64_t* bin_start, int64_t* piece_pre, int64_t* scan_blocks, uint16_t* grouped,
+                            unsigned long long* cnt, hipStream_t s) {
+  const size_t lds_bins = (size_t)p.nb * 4;
+  hipLaunchKernelGGL(k_id_hist, dim3((unsigned)p.chunks), dim3(kIdWG), lds_bins, s, dst, m, p.chunk, p.nb, p.shift,
+                     hist);
+  hipLaunchKernelGGL(k_id_colscan, dim3(grid_for(p.nb)), dim3(kWG), 0, s, hist, p.chunks, p.nb, bin_start);
+  hipError_t e = launch_exclusive_scan(bin_start, p.nb, scan_blocks, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_id_scatter, dim3((unsigned)p.chunks), dim3(kIdWG), lds_bins, s, dst, m, p.chunk, p.nb,
+                     p.shift, hist, bin_start, grouped);
+  hipLaunchKernelGGL(k_id_pieces, dim3(grid_for(p.nb)), dim3(kWG), 0, s, bin_start, p.nb, p.piece, piece_pre);
+  e = launch_exclusive_scan(piece_pre, p.nb, scan_blocks, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_id_count, dim3((unsigned)p.max_pieces), dim3(kIdWG), (size_t)4 << p.shift, s, grouped,
+                     bin_start, piece_pre, p.nb, p.shift, p.piece, n, cnt);
   return hipGetLastError();
 }
 
