@@ -262,6 +262,37 @@ vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held,
 vc_status vc_run(vc_graph g, vc_program program, const vc_params* params, void* out, hipStream_t stream,
                  vc_stats* stats);
 
+/* Size in bytes of the fixed device workspace of vc_run_noalloc, one per GPU. */
+#define VC_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* vc_run for callers that cannot allocate device memory (serving loops that
+ * must not call hipMalloc, harnesses that forbid it).  Same programs,
+ * arguments, results and errors as vc_run, but the run allocates nothing:
+ *   - its workspace comes from a fixed device array of the library
+ *     (VC_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends).  A CC /
+ *     SSSP run needs about 20.3 bytes per vertex plus 4 per merge-path tile,
+ *     a PageRank / PPR run 16 bytes per vertex; a graph whose run needs more
+ *     is refused with VC_ERR_INVALID_ARG (vc_last_error states both sizes);
+ *   - it reads only the read-only structures the graph already holds.  The
+ *     pull form needs the transpose and its partition (vc_graph_prepare with
+ *     the same params, or an earlier vc_run, builds them): an explicit
+ *     VC_SCHED_PULL without them is refused with VC_ERR_UNSUPPORTED, and AUTO
+ *     takes the edge-balanced push instead.  An edge-balanced superstep over
+ *     every vertex needs the CSR's partition for the tile; without it that
+ *     superstep runs vertex-per-thread.  VC_SCHED_BLOCKED (message slots per
+ *     edge) and VC_OPT_GRAPH_CAPTURE (buffers of its own) are refused with
+ *     VC_ERR_UNSUPPORTED; AUTO never takes the blocked form here;
+ *   - per-superstep timings (vc_stats.scatter_ms / step_ms) are written as 0,
+ *     and the graph's autotuned setting is not applied.
+ * Results equal vc_run's for the same program and params (CC labels, SSSP
+ * distances and fixed-point PageRank / PPR ranks bit for bit; with
+ * VC_OPT_F32_ACCUMULATE within its rounding).  Every call on one GPU uses the
+ * same array and leaves its contents behind (each run initialises what it
+ * reads): calls that overlap on one GPU, from two host threads or on two
+ * streams at once, race and their results are undefined. */
+vc_status vc_run_noalloc(vc_graph g, vc_program program, const vc_params* params, void* out, hipStream_t stream,
+                         vc_stats* stats);
+
 /* Builds now what a run of `program` with `params` would otherwise build on
  * its first call (paper, Section V: the work distribution of a superstep):
  * the transpose its pull supersteps read, the merge-path partition of the

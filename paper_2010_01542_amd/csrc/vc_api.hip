@@ -196,6 +196,89 @@ vc_status csc_partition(vc_graph g, int64_t tile, hipStream_t s) {
   return VC_OK;
 }
 
+// Whether g already holds the merge-path partition of its CSR / its
+// transpose for `tile`; if so it becomes the current one.  Never builds or
+// allocates anything (runs in a fixed arena).
+bool have_dense_partition(vc_graph g, int64_t tile) {
+  if (g->dense_tile == tile && g->dense_tiles_p) return true;
+  DevBuf* b = g->dense_parts.find(tile);
+  if (!b) return false;
+  g->dense_tiles_p = b->as<int32_t>();
+  g->dense_tile = tile;
+  g->dense_ntiles = (g->n + g->m + tile - 1) / tile;
+  return true;
+}
+
+bool have_csc_partition(vc_graph g, int64_t tile) {
+  if (!g->csc_ready) return false;
+  if (g->csc_tile == tile && g->csc_tiles_p) return true;
+  DevBuf* b = g->csc_parts.find(tile);
+  if (!b) return false;
+  g->csc_tiles_p = b->as<int32_t>();
+  g->csc_tile = tile;
+  g->csc_ntiles = (g->n + g->m + tile - 1) / tile;
+  return true;
+}
+
+// Consecutive pieces of an arena at 256-byte boundaries.  With a null base
+// it only counts (used), which is how arena_need sizes a run.
+struct Carve {
+  unsigned char* base;
+  size_t cap, used = 0;
+  Carve(unsigned char* b, size_t c) : base(b), cap(c) {}
+  template <class T>
+  T* take(size_t bytes) {
+    const size_t at = used;
+    used += (bytes + 255) & ~(size_t)255;
+    return (base && used <= cap) ? reinterpret_cast<T*>(base + at) : nullptr;
+  }
+  bool fits() const { return used <= cap; }
+};
+
+// Workspace of a CC / SSSP run: values and mailboxes, the two frontier
+// bitmaps, the broadcast list and its degree prefix, scan scratch, the
+// per-superstep merge-path partition and the counters.
+struct MinWork {
+  uint2* vm;
+  uint32_t* bits[2];
+  int32_t* fq;
+  int64_t* P;
+  int64_t* scan;
+  int32_t* list_tiles;
+  Counters* ctr;
+};
+
+MinWork carve_min(Carve& c, int64_t n, int64_t m, int64_t tile) {
+  const int64_t nwords = (n + 31) / 32;
+  MinWork w;
+  w.vm = c.take<uint2>((size_t)n * 8);
+  w.bits[0] = c.take<uint32_t>((size_t)nwords * 4);
+  w.bits[1] = c.take<uint32_t>((size_t)nwords * 4);
+  w.fq = c.take<int32_t>((size_t)n * 4);
+  w.P = c.take<int64_t>((size_t)(n + 1) * 8);
+  w.scan = c.take<int64_t>((size_t)scan_scratch_entries(n) * 8);
+  w.list_tiles = c.take<int32_t>((size_t)((n + m) / tile + 3) * sizeof(int32_t));
+  w.ctr = c.take<Counters>(sizeof(Counters));
+  return w;
+}
+
+// PageRank / PPR: messages and sums, 8 bytes per vertex each.
+void carve_rank(Carve& c, int64_t n, void** contrib, void** mb) {
+  *contrib = c.take<void>((size_t)n * 8);
+  *mb = c.take<void>((size_t)n * 8);
+}
+
+size_t arena_need(vc_graph g, vc_program program, const vc_params& p) {
+  Carve c(nullptr, 0);
+  if (program == VC_PAGERANK || program == VC_PPR) {
+    void *a, *b;
+    carve_rank(c, g->n, &a, &b);
+  } else {
+    (void)carve_min(c, g->n, g->m, pick_tile(p, g));
+  }
+  return c.used;
+}
+
 }  // namespace vc
 
 using vc::csc_partition;
@@ -477,7 +560,7 @@ hipError_t pb_superstep(vc_graph g, bool f32msg, const void* contrib, void* mb, 
 }
 
 vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hipStream_t s, Recorder& rec,
-                   int32_t* supersteps) {
+                   int32_t* supersteps, const vc::Arena* arena = nullptr) {
   const int64_t n = g->n, T = p.max_supersteps;
   int64_t source = -1;
   if (personal) {
@@ -493,10 +576,18 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
   // messages and sums take 8 bytes per vertex in every mode, so that a run in
   // one mode never reallocates the buffers a captured graph of another mode
   // was recorded with
-  VC_TRY(g->contrib.ensure((size_t)n * 8));
-  VC_TRY(g->mb.ensure((size_t)n * 8));
-  void* contrib = g->contrib.p;
-  void* mb = g->mb.p;
+  void* contrib = nullptr;
+  void* mb = nullptr;
+  if (arena) {
+    vc::Carve c(arena->base, arena->bytes);
+    vc::carve_rank(c, n, &contrib, &mb);
+    if (!c.fits()) return fail(VC_ERR_INVALID_ARG, "fixed workspace too small for this graph");
+  } else {
+    VC_TRY(g->contrib.ensure((size_t)n * 8));
+    VC_TRY(g->mb.ensure((size_t)n * 8));
+    contrib = g->contrib.p;
+    mb = g->mb.p;
+  }
   const double r0 = 1.0 / (double)n;
   // ranks come out in internal order; relabelled graphs stage them in the
   // message buffer (no longer needed at the last step) and un-permute
@@ -514,7 +605,14 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
   const double d = p.damping;
   const double teleport = personal ? (1.0 - d) : (1.0 - d) / (double)n;
   const int64_t tile = pick_tile(p, g);
-  const int sched = rank_schedule(g, p, fx);
+  int sched = rank_schedule(g, p, fx);
+  if (arena && g->m > 0) {
+    // only forms whose read-only structures the graph already holds; the
+    // blocked form would need message slots per edge
+    if (sched == VC_SCHED_BLOCKED || sched == VC_SCHED_PULL)
+      sched = vc::have_csc_partition(g, vc::pull_tile(tile)) ? VC_SCHED_PULL : VC_SCHED_EDGE;
+    if (sched == VC_SCHED_EDGE && !vc::have_dense_partition(g, tile)) sched = VC_SCHED_VERTEX;
+  }
   if (sched == VC_SCHED_BLOCKED && !fx)
     return fail(VC_ERR_UNSUPPORTED, "the blocked schedule sums in fixed point; drop VC_OPT_F32_ACCUMULATE");
   if (g->m > 0) {
@@ -727,27 +825,45 @@ vc_status run_min_device_loop(vc_graph g, int kind, int64_t tile, int cur, int64
 // superstep 0.  Without it the program's own start is used (CC: ids; SSSP:
 // the source).
 vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed, uint32_t* out, hipStream_t s,
-                  Recorder& rec, int32_t* supersteps) {
+                  Recorder& rec, int32_t* supersteps, const vc::Arena* arena = nullptr) {
   const int64_t n = g->n, m = g->m;
   const int64_t tile = pick_tile(p, g);
   const bool tba = !(p.options & VC_OPT_NO_TEST_BEFORE_ATOMIC);
   const bool hub = !(p.options & VC_OPT_NO_HUB_AGGREGATION);
   const int64_t nwords = (n + 31) / 32;
-  VC_TRY(g->vm.ensure((size_t)n * 8));
-  VC_TRY(g->bitmap.ensure((size_t)nwords * 4));
-  VC_TRY(g->bitmap2.ensure((size_t)nwords * 4));
-  VC_TRY(g->fq.ensure((size_t)n * 4));
-  VC_TRY(g->prefix.ensure((size_t)(n + 1) * 8));
-  VC_TRY(g->scan_blocks.ensure((size_t)vc::scan_scratch_entries(n) * 8));
-  VC_TRY(g->list_tiles.ensure((size_t)((n + m) / tile + 3) * sizeof(int32_t)));
-  VC_TRY(g->counters.ensure(sizeof(vc::Counters)));
-  if (!g->host_ctr) VC_TRY(hipHostMalloc((void**)&g->host_ctr, sizeof(vc::Counters), hipHostMallocDefault));
-  uint2* vm = g->vm.as<uint2>();
-  uint32_t* bits[2] = {g->bitmap.as<uint32_t>(), g->bitmap2.as<uint32_t>()};
-  int32_t* fq = g->fq.as<int32_t>();
-  int64_t* P = g->prefix.as<int64_t>();
-  int32_t* list_tiles = g->list_tiles.as<int32_t>();
-  vc::Counters* ctr = g->counters.as<vc::Counters>();
+  vc::MinWork wk{};
+  vc::Counters host_local{};  // counters read back into pageable memory when nothing may be allocated
+  vc::Counters* hc = &host_local;
+  if (arena) {
+    vc::Carve c(arena->base, arena->bytes);
+    wk = vc::carve_min(c, n, m, tile);
+    if (!c.fits()) return fail(VC_ERR_INVALID_ARG, "fixed workspace too small for this graph");
+  } else {
+    VC_TRY(g->vm.ensure((size_t)n * 8));
+    VC_TRY(g->bitmap.ensure((size_t)nwords * 4));
+    VC_TRY(g->bitmap2.ensure((size_t)nwords * 4));
+    VC_TRY(g->fq.ensure((size_t)n * 4));
+    VC_TRY(g->prefix.ensure((size_t)(n + 1) * 8));
+    VC_TRY(g->scan_blocks.ensure((size_t)vc::scan_scratch_entries(n) * 8));
+    VC_TRY(g->list_tiles.ensure((size_t)((n + m) / tile + 3) * sizeof(int32_t)));
+    VC_TRY(g->counters.ensure(sizeof(vc::Counters)));
+    if (!g->host_ctr) VC_TRY(hipHostMalloc((void**)&g->host_ctr, sizeof(vc::Counters), hipHostMallocDefault));
+    hc = g->host_ctr;
+    wk.vm = g->vm.as<uint2>();
+    wk.bits[0] = g->bitmap.as<uint32_t>();
+    wk.bits[1] = g->bitmap2.as<uint32_t>();
+    wk.fq = g->fq.as<int32_t>();
+    wk.P = g->prefix.as<int64_t>();
+    wk.scan = g->scan_blocks.as<int64_t>();
+    wk.list_tiles = g->list_tiles.as<int32_t>();
+    wk.ctr = g->counters.as<vc::Counters>();
+  }
+  uint2* vm = wk.vm;
+  uint32_t* bits[2] = {wk.bits[0], wk.bits[1]};
+  int32_t* fq = wk.fq;
+  int64_t* P = wk.P;
+  int32_t* list_tiles = wk.list_tiles;
+  vc::Counters* ctr = wk.ctr;
 
   int64_t source = -1;
   if (kind != vc::kCC && !seed) {
@@ -769,12 +885,12 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
     // if they had just improved
     VC_TRY(vc::launch_min_init_from(seed, n, vm, bits[1], s));
     VC_TRY(vc::launch_min_compact(g->off, g->off64, n, vm, bits[1], bits[0], fq, P, ctr, true, nullptr, s));
-    VC_TRY(hipMemcpyAsync(g->host_ctr, ctr, sizeof(vc::Counters), hipMemcpyDeviceToHost, s));
+    VC_TRY(hipMemcpyAsync(hc, ctr, sizeof(vc::Counters), hipMemcpyDeviceToHost, s));
     VC_TRY(vc::launch_zero_counters(ctr, s));
     VC_TRY(hipStreamSynchronize(s));
-    frontier = (int64_t)g->host_ctr->active;
-    listed = (int64_t)g->host_ctr->listed;
-    edges = (int64_t)g->host_ctr->edges;
+    frontier = (int64_t)hc->active;
+    listed = (int64_t)hc->listed;
+    edges = (int64_t)hc->edges;
   } else if (dense) {
     VC_TRY(vc::launch_min_init(kind, n, source, g->relabeled ? g->inv_p : nullptr, vm, s));
     frontier = n;
@@ -831,6 +947,14 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
       else
         sched = edges <= 256 ? VC_SCHED_VERTEX : VC_SCHED_EDGE;
     }
+    if (arena && m > 0) {
+      // only forms whose read-only structures the graph already holds (an
+      // explicit PULL was checked before the run); the blocked form would
+      // need message slots per edge
+      if (sched == VC_SCHED_BLOCKED || sched == VC_SCHED_PULL)
+        sched = vc::have_csc_partition(g, vc::pull_tile(tile)) ? VC_SCHED_PULL : VC_SCHED_EDGE;
+      if (sched == VC_SCHED_EDGE && dense && !vc::have_dense_partition(g, tile)) sched = VC_SCHED_VERTEX;
+    }
     rec.step(step, frontier, edges, sched);
     const bool timed = rec.want_time(step);
     if (timed) VC_TRY(hipEventRecord(g->events[0], s));
@@ -861,7 +985,7 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
         VC_TRY(vc::launch_min_scatter_mp(kind, false, tba, g->off, g->off64, g->dst, g->w, n, n, n + m, nullptr,
                                          nullptr, g->dense_tiles_p, tile, g->dense_ntiles, vm, improved, hub, s));
       } else {
-        if (!prefix_ready) VC_TRY(vc::launch_exclusive_scan(P, listed, g->scan_blocks.as<int64_t>(), s));
+        if (!prefix_ready) VC_TRY(vc::launch_exclusive_scan(P, listed, wk.scan, s));
         const int64_t total = listed + edges;
         const int64_t ntiles = (total + tile - 1) / tile;
         VC_TRY(vc::launch_mp_partition(P, true, listed, total, tile, ntiles, list_tiles, s));
@@ -877,7 +1001,7 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
     if (timed) VC_TRY(hipEventRecord(g->events[2], s));
     VC_TRY(vc::launch_min_compact(g->off, g->off64, n, vm, improved, bits[1 - cur], fq, P, ctr, false, nullptr, s));
     if (timed) VC_TRY(hipEventRecord(g->events[3], s));
-    VC_TRY(hipMemcpyAsync(g->host_ctr, ctr, sizeof(vc::Counters), hipMemcpyDeviceToHost, s));
+    VC_TRY(hipMemcpyAsync(hc, ctr, sizeof(vc::Counters), hipMemcpyDeviceToHost, s));
     VC_TRY(vc::launch_zero_counters(ctr, s));
     VC_TRY(hipStreamSynchronize(s));
     if (timed) {
@@ -886,9 +1010,9 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
       VC_TRY(hipEventElapsedTime(&b, g->events[0], g->events[3]));
       rec.times(step, a, b);
     }
-    frontier = (int64_t)g->host_ctr->active;
-    listed = (int64_t)g->host_ctr->listed;
-    edges = (int64_t)g->host_ctr->edges;
+    frontier = (int64_t)hc->active;
+    listed = (int64_t)hc->listed;
+    edges = (int64_t)hc->edges;
     dense = false;
     prefix_ready = false;
     cur = 1 - cur;
@@ -992,6 +1116,66 @@ vc_status make_view(vc_graph base, hipStream_t s, vc_graph* out) {
   v->is_view = true;
   *out = v;
   return VC_OK;
+}
+
+vc_status run_entry(vc_graph g, vc_program program, const vc_params* params, void* out, hipStream_t stream,
+                    vc_stats* stats, const Arena* arena) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!g) return fail(VC_ERR_INVALID_ARG, "null graph");
+  if (!out) return fail(VC_ERR_INVALID_ARG, "null out");
+  if ((uintptr_t)out % 4) return fail(VC_ERR_INVALID_ARG, "misaligned out");
+  if (program < VC_PAGERANK || program > VC_PPR) return fail(VC_ERR_INVALID_ARG, "bad program");
+  vc_params p;
+  if (params) {
+    p = *params;
+  } else {
+    vc_params_default(&p);
+  }
+  std::string why;
+  if (!valid_params(p, program, g->n, &why)) return fail(VC_ERR_INVALID_ARG, why);
+  if (stats) {
+    if (stats->struct_size != sizeof(vc_stats)) return fail(VC_ERR_INVALID_ARG, "vc_stats.struct_size mismatch");
+    if (stats->capacity < 0) return fail(VC_ERR_INVALID_ARG, "negative stats capacity");
+  }
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != g->device) return fail(VC_ERR_INVALID_ARG, "graph lives on another device than the current one");
+  if (arena) {
+    // everything that would allocate is refused here, before any device work
+    if (p.options & VC_OPT_GRAPH_CAPTURE)
+      return fail(VC_ERR_UNSUPPORTED, "a captured loop needs buffers of its own; drop VC_OPT_GRAPH_CAPTURE");
+    if (p.schedule == VC_SCHED_BLOCKED)
+      return fail(VC_ERR_UNSUPPORTED, "the blocked form needs 8 bytes of message slots per edge");
+    if (p.schedule == VC_SCHED_PULL && g->m > 0 && !have_csc_partition(g, pull_tile(pick_tile(p, g))))
+      return fail(VC_ERR_UNSUPPORTED, "the pull form needs the transpose and its partition: "
+                                      "call vc_graph_prepare with the same params first");
+    const size_t need = arena_need(g, program, p);
+    if (need > arena->bytes)
+      return fail(VC_ERR_INVALID_ARG, "the run needs " + std::to_string(need) + " bytes of workspace, more than the " +
+                                          std::to_string(arena->bytes) + " the fixed workspace holds");
+  } else {
+    apply_tuned(g, program, &p);
+  }
+  if (stats) {
+    stats->supersteps = 0;
+    stats->edges_relaxed = 0;
+    stats->elapsed_ms = 0;
+  }
+  Recorder rec(stats);
+  if (arena) rec.timed = false;  // events would have to be created
+  int32_t supersteps = 0;
+  vc_status st;
+  if (program == VC_PAGERANK || program == VC_PPR)
+    st = run_rank(g, p, program == VC_PPR, static_cast<float*>(out), stream, rec, &supersteps, arena);
+  else
+    st = run_min(g, p, program == VC_CC_HASHMIN ? kCC : (g->w ? kSsspWeighted : kSsspUnit), nullptr,
+                 static_cast<uint32_t*>(out), stream, rec, &supersteps, arena);
+  if (stats) {
+    stats->supersteps = supersteps;
+    stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return st;
 }
 
 }  // namespace vc
@@ -1204,44 +1388,7 @@ vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held,
 
 vc_status vc_run(vc_graph g, vc_program program, const vc_params* params, void* out, hipStream_t stream,
                  vc_stats* stats) {
-  const auto t0 = std::chrono::steady_clock::now();
-  if (!g) return fail(VC_ERR_INVALID_ARG, "null graph");
-  if (!out) return fail(VC_ERR_INVALID_ARG, "null out");
-  if ((uintptr_t)out % 4) return fail(VC_ERR_INVALID_ARG, "misaligned out");
-  if (program < VC_PAGERANK || program > VC_PPR) return fail(VC_ERR_INVALID_ARG, "bad program");
-  vc_params p;
-  if (params) {
-    p = *params;
-  } else {
-    vc_params_default(&p);
-  }
-  std::string why;
-  if (!valid_params(p, program, g->n, &why)) return fail(VC_ERR_INVALID_ARG, why);
-  apply_tuned(g, program, &p);
-  if (stats) {
-    if (stats->struct_size != sizeof(vc_stats)) return fail(VC_ERR_INVALID_ARG, "vc_stats.struct_size mismatch");
-    if (stats->capacity < 0) return fail(VC_ERR_INVALID_ARG, "negative stats capacity");
-    stats->supersteps = 0;
-    stats->edges_relaxed = 0;
-    stats->elapsed_ms = 0;
-  }
-  int cur = 0;
-  hipError_t e = hipGetDevice(&cur);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  if (cur != g->device) return fail(VC_ERR_INVALID_ARG, "graph lives on another device than the current one");
-  Recorder rec(stats);
-  int32_t supersteps = 0;
-  vc_status st;
-  if (program == VC_PAGERANK || program == VC_PPR)
-    st = run_rank(g, p, program == VC_PPR, static_cast<float*>(out), stream, rec, &supersteps);
-  else
-    st = run_min(g, p, program == VC_CC_HASHMIN ? vc::kCC : (g->w ? vc::kSsspWeighted : vc::kSsspUnit), nullptr,
-                 static_cast<uint32_t*>(out), stream, rec, &supersteps);
-  if (stats) {
-    stats->supersteps = supersteps;
-    stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  }
-  return st;
+  return vc::run_entry(g, program, params, out, stream, stats, nullptr);
 }
 
 vc_status vc_graph_prepare(vc_graph g, vc_program program, const vc_params* params, hipStream_t stream) {

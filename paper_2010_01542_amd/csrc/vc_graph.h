@@ -207,6 +207,26 @@ struct vc_graph_s {
 
 namespace vc {
 
+// A fixed device region that holds a run's workspace in place of the graph's
+// own buffers, so that the run allocates nothing (vc_run_noalloc).  Pieces are
+// carved from it at 256-byte boundaries, in a fixed order per program.
+struct Arena {
+  unsigned char* base = nullptr;
+  size_t bytes = 0;
+};
+
+// Bytes of fixed workspace a run of `program` on g needs (merge-path tile as
+// the run would pick it from p).
+size_t arena_need(vc_graph g, vc_program program, const vc_params& p);
+
+// The body of vc_run.  With arena != nullptr the run allocates nothing: its
+// workspace comes from the arena, it reads only the read-only structures the
+// graph already holds (a form whose structure is missing is replaced by one
+// that needs none, or refused), per-superstep timings are not recorded, and
+// the graph's autotuned setting is not applied.
+vc_status run_entry(vc_graph g, vc_program program, const vc_params* params, void* out, hipStream_t stream,
+                    vc_stats* stats, const Arena* arena);
+
 // Transpose (CSC) of the graph, built once; in_src / in_w / csc_off_p set.
 vc_status ensure_csc(vc_graph g, hipStream_t s);
 // Merge-path partition of the transpose for pull tiles of `tile` items.

@@ -37,7 +37,8 @@ EXPORTS = ("vc_graph_create", "vc_graph_destroy", "vc_graph_footprint", "vc_run"
            "vc_status_string", "vc_last_error", "vc_abi_version", "vc_batch_create", "vc_batch_layout",
            "vc_batch_run", "vc_batch_destroy", "vc_run_multi_source", "vc_graph_autotune", "vc_batch_autotune",
            "vc_server_create", "vc_server_add_graph", "vc_server_submit", "vc_server_poll", "vc_server_drain",
-           "vc_server_info_get", "vc_server_destroy", "vc_combine", "vc_graph_prepare")
+           "vc_server_info_get", "vc_server_destroy", "vc_combine", "vc_graph_prepare", "vc_run_noalloc")
+NOALLOC_SCRATCH_BYTES = 64 << 20  # VC_NOALLOC_SCRATCH_BYTES
 
 
 class GraphDesc(ctypes.Structure):
@@ -113,6 +114,8 @@ def load(path: str = LIB_PATH):
     lib.vc_graph_footprint.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
     lib.vc_run.restype = i32
     lib.vc_run.argtypes = [vp, i32, ctypes.POINTER(Params), vp, vp, ctypes.POINTER(StatsStruct)]
+    lib.vc_run_noalloc.restype = i32
+    lib.vc_run_noalloc.argtypes = [vp, i32, ctypes.POINTER(Params), vp, vp, ctypes.POINTER(StatsStruct)]
     lib.vc_graph_prepare.restype = i32
     lib.vc_graph_prepare.argtypes = [vp, i32, ctypes.POINTER(Params), vp]
     lib.vc_params_default.restype = None
@@ -342,6 +345,23 @@ class Graph:
         rc = lib.vc_run(self._h, prog, ctypes.byref(p), out.data_ptr(), _stream_handle(stream),
                         ctypes.byref(st) if st is not None else None)
         _check(rc, "vc_run")
+        return out, _stats_result(st, arrays, capacity)
+
+    def run_noalloc(self, program, out, *, T: int = 10, damping: float = 0.85, source: int = 0,
+                    max_supersteps: int = 0, schedule="auto", tile: int = 0, options: int = 0,
+                    pull_fraction: float = 0.0, stream=None, stats: bool = False, capacity: int = 4096):
+        """vc_run_noalloc: as run(), into a caller-supplied out tensor; the
+        library allocates no device memory for it."""
+        prog = _program(program)
+        rank = prog in (PAGERANK, PPR)
+        if out is None or not out.is_cuda or not out.is_contiguous() or out.numel() != self.n or \
+                out.element_size() != 4:
+            raise TypeError("out must be a contiguous CUDA tensor of N 4-byte elements")
+        p = _params(T if rank else max_supersteps, damping, source, schedule, tile, options, pull_fraction)
+        st, arrays = _stats_struct(stats, False, capacity)
+        rc = load().vc_run_noalloc(self._h, prog, ctypes.byref(p), out.data_ptr(), _stream_handle(stream),
+                                   ctypes.byref(st) if st is not None else None)
+        _check(rc, "vc_run_noalloc")
         return out, _stats_result(st, arrays, capacity)
 
 
