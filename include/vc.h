@@ -149,11 +149,14 @@ enum {
   VC_OPT_NO_TEST_BEFORE_ATOMIC = 2u, /* min programs: skip the mailbox read before the atomic (for measurement) */
   VC_OPT_F32_ACCUMULATE = 4u,        /* PageRank / PPR: binary32 messages and float atomics */
   VC_OPT_GRAPH_CAPTURE = 8u,         /* run the superstep loop as a captured HIP graph: PageRank /
-                                        PPR as one graph of all T supersteps; CC / SSSP from
-                                        superstep 1 on as pull supersteps with termination decided
-                                        on the device (no per-superstep host round trip).  Graphs
-                                        are cached per graph object; per-superstep timings are not
-                                        recorded in this mode */
+                                        PPR as one graph of all T supersteps (AUTO PageRank does so
+                                        by itself on graphs below 2^24 edges, where launch gaps weigh;
+                                        timed runs report the graph's time divided by T as every
+                                        superstep's step_ms, and scatter_ms 0); CC / SSSP from
+                                        superstep 1 on as pull supersteps with
+                                        termination decided on the device (no per-superstep host
+                                        round trip; per-superstep timings are not recorded).
+                                        Graphs are cached per graph object */
   VC_OPT_F32_MESSAGES = 16u          /* PageRank / PPR: each message rounded once to binary32,
                                         sums still exact in fixed point (half the message bytes;
                                         results independent of order and schedule, within one

@@ -559,6 +559,18 @@ hipError_t pb_superstep(vc_graph g, bool f32msg, const void* contrib, void* mb, 
                             pb.rbase, g->n, g->pb_vals.p, pb.dstl, static_cast<unsigned long long*>(mb), s);
 }
 
+// Edges below which AUTO PageRank / PPR runs capture their superstep loop
+// (VC_PR_CAPTURE_EDGES overrides; 0 turns it off).
+constexpr int64_t kRankCaptureEdges = 1ll << 24;
+
+bool auto_rank_capture(vc_graph g) {
+  static const int64_t limit = [] {
+    const char* e = std::getenv("VC_PR_CAPTURE_EDGES");
+    return e ? (int64_t)std::atoll(e) : kRankCaptureEdges;
+  }();
+  return g->m < limit;
+}
+
 vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hipStream_t s, Recorder& rec,
                    int32_t* supersteps, const vc::Arena* arena = nullptr) {
   const int64_t n = g->n, T = p.max_supersteps;
@@ -630,15 +642,27 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
   // the blocked form's fold stores every mailbox of a one-item bin and
   // leaves bins without in-edges untouched: the update resets only the rest
   const uint8_t* pb_kinds = sched == VC_SCHED_BLOCKED && g->m > 0 ? g->pb.kinds : nullptr;
-  if (p.options & VC_OPT_GRAPH_CAPTURE) {
+  // a captured loop: on request, or by default for PageRank (AUTO) where a
+  // superstep is short enough that launch gaps weigh (graphs below
+  // kRankCaptureEdges edges; PPR bakes its source into the graph, so a
+  // request stream with changing sources would capture every run); never in
+  // a fixed arena
+  const bool capture = !arena && ((p.options & VC_OPT_GRAPH_CAPTURE) ||
+                                  (!personal && p.schedule == VC_SCHED_AUTO && auto_rank_capture(g)));
+  if (capture) {
     // the whole loop as one captured HIP graph; ranks land in the staging
-    // buffer (fixed address) and are copied / un-permuted afterwards
+    // buffer (fixed address) and are copied / un-permuted afterwards.  A
+    // timed run times the graph's launch with two events on the stream (the
+    // kernels inside cannot be timed apart): every superstep reports the
+    // average, and no broadcast+combine time.
     float* stage = static_cast<float*>(contrib);
+    const bool timed = rec.timed;
+    if (timed) VC_TRY(ensure_events(g, 2));
     // the key names every device address the graph bakes in, so that a
     // reallocated buffer or a rebuilt partition forces a new capture
-    char keybuf[320];
-    std::snprintf(keybuf, sizeof keybuf, "%d/%d/%lld/%lld/%.17g/%d/%lld/%p/%p/%p/%p/%p/%p/%p", mode, (int)hub, (long long)T,
-                  (long long)source, d, sched, (long long)tile, contrib, mb, g->pb_vals.p,
+    char keybuf[352];
+    std::snprintf(keybuf, sizeof keybuf, "%d/%d/%lld/%lld/%.17g/%d/%lld/%p/%p/%p/%p/%p/%p/%p", mode, (int)hub,
+                  (long long)T, (long long)source, d, sched, (long long)tile, contrib, mb, g->pb_vals.p,
                   (const void*)g->csc_tiles_p, (const void*)g->dense_tiles_p, (const void*)g->in_src,
                   (const void*)g->pb.fold);
     if (g->pr_exec && g->pr_exec_key != keybuf) {
@@ -676,7 +700,9 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
       if (e3 != hipSuccess) return hip_fail(e3, "hipGraphInstantiate");
       g->pr_exec_key = keybuf;
     }
+    if (timed) VC_TRY(hipEventRecord(g->events[0], s));
     VC_TRY(hipGraphLaunch(g->pr_exec, s));
+    if (timed) VC_TRY(hipEventRecord(g->events[1], s));
     for (int64_t step = 0; step < T; ++step) rec.step(step, n, g->m, sched);
     rec.step(T, 0, 0, 0);
     if (g->relabeled)
@@ -685,6 +711,11 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
     else
       VC_TRY(hipMemcpyAsync(out, stage, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
     VC_TRY(hipStreamSynchronize(s));
+    if (timed) {
+      float all = 0;
+      VC_TRY(hipEventElapsedTime(&all, g->events[0], g->events[1]));
+      for (int64_t step = 0; step < T; ++step) rec.times(step, 0.0f, all / (float)T);
+    }
     *supersteps = (int32_t)(T + 1);
     return VC_OK;
   }

@@ -130,20 +130,24 @@ hipError_t launch_csc_count(const int32_t* dst, int64_t m, unsigned long long* c
 // The same histogram without per-edge global atomics, for graphs of at least
 // kIdMinEdges edges (a counting sort of the targets by bins of 2^shift
 // vertices, every count taken in LDS).  id_binned fills the plan and says
-// whether the graph qualifies (m < 2^32, at most kIdMaxBins bins of at most
-// 2^14 vertices, LDS large enough); launch_id_binned then needs
+// whether the graph qualifies (m < 2^32, at most kIdMaxBins bins of 2^14
+// vertices, LDS large enough); launch_id_binned then needs
 //   hist       chunks * nb uint32,
 //   bin_start  nb + 1 int64,  piece_pre nb + 1 int64,
 //   scan_blocks scan_scratch_entries(nb) int64,
 //   grouped    m uint16,
 // and cnt (n + 1 entries) zero on entry.
 constexpr int64_t kIdMinEdges = 1ll << 19;
+// Bins of 2^14 vertices: few enough that each chunk writes runs of hundreds
+// of targets per bin (4,096 bins at 2^26 vertices), and a bin's counters
+// (64 KiB) fit one workgroup's LDS.
+constexpr int kIdBinShift = 14;
 constexpr int kIdMaxBins = 16384;
 constexpr int64_t kIdMinChunk = 1ll << 16;  // edges per chunk of the first passes, at least
 constexpr int64_t kIdMaxChunks = 1024;
-constexpr int64_t kIdPiece = 1ll << 18;     // grouped targets counted per workgroup, at most
+constexpr int64_t kIdPiece = 1ll << 20;     // grouped targets counted per workgroup, at most
 struct IdPlan {
-  int shift = 12, nb = 0;
+  int shift = kIdBinShift, nb = 0;
   int64_t chunk = 0, chunks = 0, piece = 0, max_pieces = 0;
 };
 bool id_binned(int64_t n, int64_t m, size_t max_lds, IdPlan* plan);

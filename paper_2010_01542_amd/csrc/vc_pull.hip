@@ -462,11 +462,11 @@ hipError_t launch_csc_count(const int32_t* dst, int64_t m, unsigned long long* c
 
 bool id_binned(int64_t n, int64_t m, size_t max_lds, IdPlan* plan) {
   if (m < kIdMinEdges || m >= (1ll << 32)) return false;
-  int shift = 12;
-  while (((n + (1ll << shift) - 1) >> shift) > kIdMaxBins) ++shift;
-  if (shift > 14 || ((size_t)4 << shift) > max_lds || (size_t)kIdMaxBins * 4 > max_lds) return false;
+  const int shift = kIdBinShift;
+  const int64_t nb = (n + (1ll << shift) - 1) >> shift;
+  if (nb > kIdMaxBins || ((size_t)4 << shift) > max_lds || (size_t)nb * 4 > max_lds) return false;
   plan->shift = shift;
-  plan->nb = (int)((n + (1ll << shift) - 1) >> shift);
+  plan->nb = (int)nb;
   plan->chunk = std::max<int64_t>(kIdMinChunk, (m + kIdMaxChunks - 1) / kIdMaxChunks);
   plan->chunks = (m + plan->chunk - 1) / plan->chunk;
   plan->piece = kIdPiece;

@@ -161,8 +161,11 @@ def test_superstep_cap(device):
 def test_timing_stats_are_recorded(device):
     d = rmatgen.rmat(14, 16, seed=2, weighted=True)
     g = make(d)
-    _, st = g.run("pagerank", T=5, timing=True)
+    _, st = g.run("pagerank", T=5, timing=True, schedule="pull")  # eager loop: every kernel timed
     assert st.scatter_ms.shape[0] == 6 and np.all(st.scatter_ms[:5] > 0) and np.all(st.step_ms[:5] >= st.scatter_ms[:5])
+    # AUTO on a small graph captures the loop: the graph's time averaged over the supersteps
+    _, st = g.run("pagerank", T=5, timing=True)
+    assert np.all(st.scatter_ms[:5] == 0) and np.all(st.step_ms[:5] > 0) and np.ptp(st.step_ms[:5]) == 0
     _, st = g.run("sssp", source=0, timing=True)
     assert np.all(st.scatter_ms[: st.supersteps - 1] > 0)
 
