@@ -172,18 +172,39 @@ def bench_batch(args, dev):
     del graphs
     torch.cuda.empty_cache()
     b = Batch(csrs, queries, device=dev)
+    out = torch.empty(b.n, dtype=torch.int32, device=dev)
+    # the host-driven and the captured superstep loop (forms switched on the
+    # device), AUTO's defaults, before the autotuner picks its setting
+    forms = {}
+    for name, opt in (("eager", 0), ("captured", vc.OPT_GRAPH_CAPTURE)):
+        for _ in range(max(1, args.warmup)):
+            b.run(out, options=opt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            b.run(out, options=opt)
+        torch.cuda.synchronize()
+        forms[name] = round((time.perf_counter() - t0) / args.steps * 1e3, 3)
+    log(f"batch loop forms (ms per batch): {forms}")
     tuned = b.autotune()
     log(f"batch autotune picked {tuned}")
-    out = torch.empty(b.n, dtype=torch.int32, device=dev)
     for _ in range(args.warmup):
         b.run(out)
     torch.cuda.synchronize()
+    blat = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        a = time.perf_counter()
         _, st = b.run(out, stats=True)
+        blat.append(time.perf_counter() - a)
     torch.cuda.synchronize()
     batch_s = (time.perf_counter() - t0) / args.steps
     assert st.edges_relaxed == edges_plain, (st.edges_relaxed, edges_plain)
+    # every member's batched result against its plain run (outs hold the plain runs' results)
+    same = sum(bool(np.array_equal(x, o.cpu().numpy().view(np.uint32))) for x, o in zip(b.split(out), outs))
+    if same != len(csrs):
+        raise SystemExit(f"batched results differ from the plain runs for {len(csrs) - same} members")
+    blat_ms = np.array(blat) * 1e3
     lat_ms = np.array(lat) * 1e3
     return {
         "metric": "GTEPS & HBM GB/s vs peak per superstep; batched/served p50/p99 vs plain",
@@ -194,7 +215,11 @@ def bench_batch(args, dev):
                    "queries": {"sssp": sum(q[0] == "sssp" for q in queries),
                                "cc": sum(q[0] == "cc" for q in queries)}},
         "batched": {"ms": round(batch_s * 1e3, 3), "gteps": round(edges_plain / batch_s / 1e9, 3),
-                    "queries_per_s": round(len(csrs) / batch_s, 1), "supersteps": st.supersteps},
+                    "queries_per_s": round(len(csrs) / batch_s, 1), "supersteps": st.supersteps,
+                    "latency_ms_p50": round(float(np.percentile(blat_ms, 50)), 3),
+                    "latency_ms_p99": round(float(np.percentile(blat_ms, 99)), 3),
+                    "members_equal_plain": f"{same}/{len(csrs)}"},
+        "batched_loop_ms": forms,
         "plain": {"ms": round(plain_s * 1e3, 3), "gteps": round(edges_plain / plain_s / 1e9, 3),
                   "queries_per_s": round(len(csrs) / plain_s, 1),
                   "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 3),

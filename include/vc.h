@@ -100,8 +100,8 @@ typedef enum { VC_PAGERANK = 0, VC_CC_HASHMIN = 1, VC_SSSP = 2, VC_PPR = 3 } vc_
  *                    Graphs beyond about 2^27 vertices are refused
  *                    (VC_ERR_UNSUPPORTED), as is vc_run_multi_source;
  *   VC_SCHED_AUTO    CC / SSSP, per superstep: pull for dense frontiers
- *                    (BLOCKED instead on graphs of 2^20 vertices and more,
- *                    except in captured loops), edge-centric push otherwise
+ *                    (BLOCKED instead on graphs of 2^20 vertices and more),
+ *                    edge-centric push otherwise
  *                    (vertex push for tiny ones).  PageRank / PPR with
  *                    fixed-point sums (default or VC_OPT_F32_MESSAGES):
  *                    BLOCKED on graphs of 2^20 vertices and more, PULL
@@ -152,11 +152,15 @@ enum {
                                         PPR as one graph of all T supersteps (AUTO PageRank does so
                                         by itself on graphs below 2^24 edges, where launch gaps weigh;
                                         timed runs report the graph's time divided by T as every
-                                        superstep's step_ms, and scatter_ms 0); CC / SSSP from
-                                        superstep 1 on as pull supersteps with
-                                        termination decided on the device (no per-superstep host
-                                        round trip; per-superstep timings are not recorded).
-                                        Graphs are cached per graph object */
+                                        superstep's step_ms, and scatter_ms 0).  CC / SSSP from
+                                        superstep 1 on as a graph of several supersteps replayed
+                                        until the device reports quiescence, with each superstep's
+                                        form picked on the device from its message count: on graphs
+                                        where AUTO takes the blocked form, the blocked form for dense
+                                        supersteps and the edge-balanced push otherwise; below that
+                                        size the pull in every superstep; explicit schedules fix the
+                                        form (VERTEX pushes edge-balanced).  Per-superstep timings
+                                        are not recorded.  Graphs are cached per graph object */
   VC_OPT_F32_MESSAGES = 16u          /* PageRank / PPR: each message rounded once to binary32,
                                         sums still exact in fixed point (half the message bytes;
                                         results independent of order and schedule, within one

@@ -6,6 +6,8 @@
 // termination and the work distribution of the next broadcast (Section V:
 // one thread per vertex, or edge-balanced merge-path tiles).
 #include <algorithm>
+#include <climits>
+#include <cmath>
 #include <chrono>
 #include <cstdlib>
 #include <cstdio>
@@ -528,11 +530,8 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
 }
 
 // Whether a dense CC / SSSP superstep that AUTO would pull takes the blocked
-// form instead: the same size rule as PageRank's, outside captured loops
-// (whose pull supersteps run on the device).
-bool min_blocked(vc_graph g, bool capture) {
-  return !capture && g->n >= (1 << 20) && g->m > 0 && pb_supported(g);
-}
+// form instead: the same size rule as PageRank's.
+bool min_blocked(vc_graph g) { return g->n >= (1 << 20) && g->m > 0 && pb_supported(g); }
 
 // The blocked layout for a run on g: a graph builds its own on first use; a
 // view takes its base's, building it there first if no view has (under the
@@ -778,26 +777,82 @@ double pull_threshold(const vc_params& p) {
 
 constexpr int64_t kMaxRecordedSteps = 1 << 16;
 
+// How a captured CC / SSSP loop delivers each superstep: the dense form
+// (blocked or pull) from dense_edges messages on, else the edge-balanced
+// push.  Explicit schedules fix the form: PULL / BLOCKED always dense,
+// EDGE / VERTEX always pushed (edge-balanced).  AUTO switches per superstep
+// on graphs large enough for the blocked form; below that it pulls every
+// superstep, as a superstep there costs little more than the launches of
+// the forms it would not take (measured: 1,024 captured runs on graphs of
+// 2^10..2^16 vertices took 540 ms switching, 444 ms pulling).
+struct LoopForms {
+  int dense_mode;          // VC_SCHED_BLOCKED or VC_SCHED_PULL
+  long long dense_edges;   // messages from which a superstep takes dense_mode
+  int per_replay;          // supersteps per replay of the captured graph (even: the bitmaps alternate)
+};
+
+LoopForms loop_forms(vc_graph g, const vc_params& p) {
+  const bool blocked = p.schedule == VC_SCHED_BLOCKED || (p.schedule == VC_SCHED_AUTO && min_blocked(g));
+  LoopForms f;
+  f.dense_mode = blocked ? VC_SCHED_BLOCKED : VC_SCHED_PULL;
+  if (p.schedule == VC_SCHED_PULL || p.schedule == VC_SCHED_BLOCKED || (p.schedule == VC_SCHED_AUTO && !blocked)) {
+    f.dense_edges = 0;
+  } else if (p.schedule == VC_SCHED_EDGE || p.schedule == VC_SCHED_VERTEX) {
+    f.dense_edges = LLONG_MAX;
+  } else {
+    const double thr = p.pull_fraction > 0.0f ? pull_threshold(p) : kBlockedFraction;
+    const double e = thr * (double)g->m;
+    f.dense_edges = e < 1.0 ? 1 : (long long)std::ceil(e);  // edges >= thr * m
+  }
+  // a replay ends with one read of the loop state; the supersteps of a
+  // replay left after quiescence return at once, which costs more in the
+  // longer graphs of the push form
+  f.per_replay = (f.dense_edges == 0 && !blocked) ? 2 : 8;
+  return f;
+}
+
 // Runs supersteps `step`.. of a CC / SSSP program as a captured HIP graph of
-// two pull supersteps (one per bitmap parity), replayed until the step-end
-// kernel reports quiescence or the cap; one 32-byte read per replay.
-vc_status run_min_device_loop(vc_graph g, int kind, int64_t tile, int cur, int64_t step, int64_t cap, uint2* vm,
-                              uint32_t* bits[2], int32_t* fq, int64_t* P, vc::Counters* ctr, hipStream_t s,
-                              Recorder& rec, int32_t* supersteps, bool* capped) {
+// forms.per_replay supersteps, replayed until the step-end kernel reports
+// quiescence or the cap; one read of the loop state per replay.  Every
+// superstep holds the kernels of its possible forms (the edge-balanced push:
+// scan, partition, scatter; the dense form: blocked spread and fold, or the
+// pull), and each returns at once unless the step-end kernel of the previous
+// superstep picked its form, so the direction switch happens on the device.
+vc_status run_min_device_loop(vc_graph g, const vc_params& p, int kind, int64_t tile, bool tba, bool hub, int cur,
+                              int64_t step, int64_t frontier, int64_t listed, int64_t edges, int64_t cap, uint2* vm,
+                              uint32_t* bits[2],
+                              int32_t* fq, int64_t* P, int64_t* scan, int32_t* list_tiles, vc::Counters* ctr,
+                              hipStream_t s, Recorder& rec, int32_t* supersteps, bool* capped) {
   const int64_t n = g->n, m = g->m;
-  vc_status st = ensure_csc(g, s);
-  if (st == VC_OK) st = csc_partition(g, vc::pull_tile(tile), s);
+  const LoopForms forms = loop_forms(g, p);
+  const bool blocked = forms.dense_mode == VC_SCHED_BLOCKED;
+  vc_status st = VC_OK;
+  if (forms.dense_edges != LLONG_MAX) {
+    if (blocked) {
+      st = use_pb(g, s);
+    } else {
+      st = ensure_csc(g, s);
+      if (st == VC_OK) st = csc_partition(g, vc::pull_tile(tile), s);
+    }
+  }
   if (st != VC_OK) return st;
+  const int64_t max_tiles = (n + m) / tile + 1;  // list_tiles holds (n + m) / tile + 3 entries
   VC_TRY(g->loop_state.ensure(sizeof(vc::LoopState)));
-  VC_TRY(g->loop_steps.ensure((size_t)kMaxRecordedSteps * 16));
+  VC_TRY(g->loop_steps.ensure((size_t)kMaxRecordedSteps * 24));
   if (!g->host_loop) VC_TRY(hipHostMalloc((void**)&g->host_loop, sizeof(vc::LoopState), hipHostMallocDefault));
   vc::LoopState* loop = g->loop_state.as<vc::LoopState>();
   long long* steps = g->loop_steps.as<long long>();
+  const vc::PbShared& pb = g->pb;
+  uint32_t* slot_msg = blocked ? g->pb_vals.as<uint32_t>() : nullptr;
   hipGraphExec_t& exec = g->min_exec[kind][cur];
-  char keybuf[256];
-  std::snprintf(keybuf, sizeof keybuf, "%lld/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p", (long long)g->csc_tile, (void*)vm,
-                (void*)bits[0], (void*)bits[1], (void*)fq, (void*)P, (void*)ctr, (void*)loop, (void*)steps,
-                (const void*)g->csc_tiles_p, (const void*)g->in_src);
+  // every device address and setting the graph bakes in
+  char keybuf[512];
+  std::snprintf(keybuf, sizeof keybuf,
+                "%lld/%d/%lld/%d/%d/%d/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p/%lld", (long long)tile,
+                forms.dense_mode, forms.dense_edges, forms.per_replay, (int)tba, (int)hub, (void*)vm, (void*)bits[0], (void*)bits[1],
+                (void*)fq, (void*)P, (void*)scan, (void*)list_tiles, (void*)ctr, (void*)loop, (void*)steps,
+                (const void*)g->csc_tiles_p, (const void*)g->in_src, (const void*)slot_msg, (const void*)pb.fold,
+                (const void*)pb.spread, g->off, (const void*)g->dst, (long long)g->csc_tile);
   if (exec && g->min_exec_key[kind][cur] != keybuf) {
     VC_TRY(hipGraphExecDestroy(exec));
     exec = nullptr;
@@ -807,13 +862,31 @@ vc_status run_min_device_loop(vc_graph g, int kind, int64_t tile, int cur, int64
     hipStream_t cs = g->cap_stream;
     VC_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int half = 0; half < 2 && e == hipSuccess; ++half) {
-      const int a = half == 0 ? cur : 1 - cur;
-      e = vc::launch_min_pull(kind, g->csc_off_p, g->in_src, g->in_w, n, m, g->csc_tiles_p,
-                              g->csc_tile, g->csc_ntiles, vm, bits[1 - a], bits[a], loop, cs);
+    for (int k = 0; k < forms.per_replay && e == hipSuccess; ++k) {
+      const int a = (k & 1) ? 1 - cur : cur;  // improvements go to bits[a]; bits[1 - a] holds the frontier
+      if (forms.dense_edges != 0) {  // the edge-balanced push
+        e = vc::launch_loop_scan(P, n, scan, loop, cs);
+        if (e == hipSuccess) e = vc::launch_loop_partition(P, tile, max_tiles, list_tiles, loop, cs);
+        if (e == hipSuccess)
+          e = vc::launch_loop_scatter_mp(kind, tba, g->off, g->off64, g->dst, g->w, n, P, fq, list_tiles, tile,
+                                         max_tiles, vm, bits[a], hub, loop, cs);
+      }
+      if (e == hipSuccess && forms.dense_edges != LLONG_MAX) {  // the dense form
+        if (blocked) {
+          e = vc::launch_pb_spread_min(kind, pb.spread, pb.nspread, n, pb.shift, pb.srcl, pb.w, pb.wbytes, vm,
+                                       bits[1 - a], slot_msg, loop, cs);
+          if (e == hipSuccess)
+            e = vc::launch_pb_fold_min(pb.fold, pb.nfold, pb.run_off, pb.rpre, pb.btotal, pb.chunk_off, pb.chunks,
+                                       pb.rbase, n, slot_msg, pb.dstl, vm, bits[a], loop, cs);
+        } else {
+          e = vc::launch_min_pull(kind, g->csc_off_p, g->in_src, g->in_w, n, m, g->csc_tiles_p, g->csc_tile,
+                                  g->csc_ntiles, vm, bits[1 - a], bits[a], loop, cs);
+        }
+      }
       if (e == hipSuccess)
         e = vc::launch_min_compact(g->off, g->off64, n, vm, bits[a], bits[1 - a], fq, P, ctr, false, loop, cs);
-      if (e == hipSuccess) e = vc::launch_loop_step(ctr, loop, steps, kMaxRecordedSteps, cs);
+      if (e == hipSuccess)
+        e = vc::launch_loop_step(ctr, loop, steps, kMaxRecordedSteps, forms.dense_edges, forms.dense_mode, cs);
     }
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(cs, &graph);
@@ -824,7 +897,10 @@ vc_status run_min_device_loop(vc_graph g, int kind, int64_t tile, int cur, int64
     if (e3 != hipSuccess) return hip_fail(e3, "hipGraphInstantiate");
     g->min_exec_key[kind][cur] = keybuf;
   }
-  vc::LoopState init{0, step, cap, 0};
+  // the form of superstep `step`, by the same rule the step-end kernel applies
+  const long long mode0 = (long long)edges >= forms.dense_edges ? forms.dense_mode : VC_SCHED_EDGE;
+  rec.step(step, frontier, edges, (int)mode0);
+  vc::LoopState init{0, step, cap, 0, mode0, listed, edges};
   *g->host_loop = init;
   VC_TRY(hipMemcpyAsync(loop, g->host_loop, sizeof init, hipMemcpyHostToDevice, s));
   for (;;) {
@@ -837,13 +913,13 @@ vc_status run_min_device_loop(vc_graph g, int kind, int64_t tile, int cur, int64
   const int64_t first = step + 1;
   const int64_t upto = last < kMaxRecordedSteps ? last : kMaxRecordedSteps - 1;
   if (upto >= first) {
-    std::vector<long long> h((size_t)(2 * (upto - first + 1)));
-    VC_TRY(hipMemcpyAsync(h.data(), steps + 2 * first, h.size() * 8, hipMemcpyDeviceToHost, s));
+    std::vector<long long> h((size_t)(3 * (upto - first + 1)));
+    VC_TRY(hipMemcpyAsync(h.data(), steps + 3 * first, h.size() * 8, hipMemcpyDeviceToHost, s));
     VC_TRY(hipStreamSynchronize(s));
     for (int64_t t = first; t <= upto; ++t) {
-      const long long f = h[2 * (t - first)], e = h[2 * (t - first) + 1];
+      const long long f = h[3 * (t - first)], ed = h[3 * (t - first) + 1], md = h[3 * (t - first) + 2];
       if (g->host_loop->capped && t == last) break;
-      rec.step(t, f, e, (f > 0 && e > 0) ? VC_SCHED_PULL : 0);
+      rec.step(t, f, ed, (int)md);
     }
   }
   *capped = g->host_loop->capped != 0;
@@ -957,11 +1033,10 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
       break;
     }
     if (capture && step >= 1) {
-      // the rest runs on the device: pull every superstep, termination checked there
-      rec.step(step, frontier, edges, VC_SCHED_PULL);
+      // the rest runs on the device: form switch and termination decided there
       bool capped = false;
-      vc_status st = run_min_device_loop(g, kind, tile, cur, step, cap, vm, bits, fq, P, ctr, s, rec, supersteps,
-                                         &capped);
+      vc_status st = run_min_device_loop(g, p, kind, tile, tba, hub, cur, step, frontier, listed, edges, cap, vm, bits,
+                                         fq, P, wk.scan, list_tiles, ctr, s, rec, supersteps, &capped);
       if (st != VC_OK) return st;
       if (capped) status = fail(VC_ERR_NOT_CONVERGED, "superstep cap reached before quiescence");
       break;
@@ -971,7 +1046,7 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
       // a blocked superstep costs a full pass over the edges, so it takes
       // over from push later than the pull form would (scale-26 SSSP: push
       // 1.9 ms vs blocked 4.4 ms at 12 % of the edges, 6.5 vs 4.5 ms at 46 %)
-      const bool blocked = min_blocked(g, capture);
+      const bool blocked = min_blocked(g);
       const double thr = (p.pull_fraction > 0.0f || !blocked) ? pull_threshold(p) : kBlockedFraction;
       if ((double)edges >= thr * (double)m)
         sched = blocked ? VC_SCHED_BLOCKED : VC_SCHED_PULL;
@@ -997,9 +1072,9 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
       uint32_t* slot_msg = g->pb_vals.as<uint32_t>();
       if (timed) VC_TRY(hipEventRecord(g->events[1], s));
       VC_TRY(vc::launch_pb_spread_min(kind, pb.spread, pb.nspread, n, pb.shift, pb.srcl, pb.w, pb.wbytes, vm,
-                                      dense ? nullptr : bits[1 - cur], slot_msg, s));
+                                      dense ? nullptr : bits[1 - cur], slot_msg, nullptr, s));
       VC_TRY(vc::launch_pb_fold_min(pb.fold, pb.nfold, pb.run_off, pb.rpre, pb.btotal, pb.chunk_off, pb.chunks,
-                                    pb.rbase, n, slot_msg, pb.dstl, vm, improved, s));
+                                    pb.rbase, n, slot_msg, pb.dstl, vm, improved, nullptr, s));
     } else if (sched == VC_SCHED_PULL) {
       vc_status st = ensure_csc(g, s);
       if (st == VC_OK) st = csc_partition(g, vc::pull_tile(tile), s);
@@ -1409,7 +1484,7 @@ vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held,
         csc_need = 0;  // the blocked schedule reads its own layout, not the transpose
         pb_need = pb_more;
       }
-    } else if (min_blocked(g, false)) {
+    } else if (min_blocked(g)) {
       pb_need = pb_more;
     }
     *bytes_run = (want > have ? want - have : 0) + csc_need + pb_need;
@@ -1459,10 +1534,10 @@ vc_status vc_graph_prepare(vc_graph g, vc_program program, const vc_params* para
       case VC_SCHED_EDGE: st = dense_partition(g, tile, stream); break;
       case VC_SCHED_VERTEX: break;
       default:  // AUTO: the dense form its dense supersteps take, the partition of a dense push
-        st = min_blocked(g, capture) ? use_pb(g, stream) : pull();
+        st = min_blocked(g) ? use_pb(g, stream) : pull();
         if (st == VC_OK) st = dense_partition(g, tile, stream);
     }
-    if (st == VC_OK && capture) st = pull();
+    (void)capture;  // a captured loop takes the same forms
   }
   if (st != VC_OK) return st;
   VC_TRY(hipStreamSynchronize(stream));
@@ -1770,7 +1845,7 @@ std::vector<vc_params> tune_candidates(vc_program program, const vc_params& base
           out.push_back(p);
         }
       } else {
-        for (float frac : {0.03f, 0.1f, 0.3f, 2.0f}) {
+        for (float frac : {0.0f, 0.03f, 0.1f, 0.3f, 2.0f}) {  // 0: the library default
           vc_params p = base;
           p.schedule = VC_SCHED_AUTO;
           p.tile = tile;

@@ -351,9 +351,11 @@ __global__ __launch_bounds__(kSpreadWG) void k_pb_spread_min(const PbSpreadItem*
                                                              const WT* __restrict__ wslot,
                                                              const uint2* __restrict__ vm,
                                                              const uint32_t* __restrict__ active,
-                                                             uint32_t* __restrict__ vals) {
+                                                             uint32_t* __restrict__ vals,
+                                                             const LoopState* __restrict__ loop) {
   constexpr int U = 8;
   extern __shared__ __align__(16) uint32_t wmin[];
+  if (loop && (loop->done || loop->mode != VC_SCHED_BLOCKED)) return;  // uniform: another form runs this superstep
   const PbSpreadItem it = items[blockIdx.x];
   const int64_t u0 = (int64_t)it.t << shift;
   const int64_t wl = (n - u0 < (1ll << shift)) ? n - u0 : (1ll << shift);
@@ -478,7 +480,8 @@ __global__ __launch_bounds__(kFoldWG) void k_pb_fold(const PbFoldItem* __restric
                                                      const PbChunk* __restrict__ chunks,
                                                      const int64_t* __restrict__ rbase, int64_t n,
                                                      const typename Op::Val* __restrict__ vals,
-                                                     const uint16_t* __restrict__ dstl, Op op) {
+                                                     const uint16_t* __restrict__ dstl, Op op,
+                                                     const LoopState* __restrict__ loop) {
   using M = typename Op::Val;
   using Box = typename Op::Box;
   constexpr int U = 8;
@@ -486,6 +489,7 @@ __global__ __launch_bounds__(kFoldWG) void k_pb_fold(const PbFoldItem* __restric
   __shared__ Box box[1 << kPbDstShift];
   __shared__ int64_t s_base[kFoldRuns];
   __shared__ PbChunk s_chunk[kFoldChunks];
+  if (loop && (loop->done || loop->mode != VC_SCHED_BLOCKED)) return;  // uniform: another form runs this superstep
   const int64_t per = (nitems + 7) >> 3;
   const int64_t j = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (j >= nitems) return;
@@ -647,11 +651,11 @@ hipError_t launch_pb_fold(bool f32msg, const PbFoldItem* items, int64_t nitems, 
   if (f32msg)
     hipLaunchKernelGGL(k_pb_fold<FoldSum<float>>, dim3((unsigned)(8 * per)), dim3(kFoldWG), 0, s, items, nitems,
                        run_off, rpre, btotal, chunk_off, chunks, rbase, n, (const float*)vals, dstl,
-                       FoldSum<float>{mb});
+                       FoldSum<float>{mb}, nullptr);
   else
     hipLaunchKernelGGL(k_pb_fold<FoldSum<unsigned long long>>, dim3((unsigned)(8 * per)), dim3(kFoldWG), 0, s, items,
                        nitems, run_off, rpre, btotal, chunk_off, chunks, rbase, n,
-                       (const unsigned long long*)vals, dstl, FoldSum<unsigned long long>{mb});
+                       (const unsigned long long*)vals, dstl, FoldSum<unsigned long long>{mb}, nullptr);
   return hipGetLastError();
 }
 
@@ -659,20 +663,20 @@ namespace {
 template <class WT>
 hipError_t spread_min_launch(int kind, const PbSpreadItem* items, int64_t nitems, int64_t n, int shift,
                              const uint16_t* srcl, const WT* wslot, const uint2* vm, const uint32_t* active,
-                             uint32_t* vals, hipStream_t s) {
+                             uint32_t* vals, const LoopState* loop, hipStream_t s) {
   const size_t lds = (size_t)4 << shift;
   switch (kind) {
     case kCC:
       hipLaunchKernelGGL((k_pb_spread_min<kCC, WT>), dim3((unsigned)nitems), dim3(kSpreadWG), lds, s, items, n, shift,
-                         srcl, wslot, vm, active, vals);
+                         srcl, wslot, vm, active, vals, loop);
       break;
     case kSsspUnit:
       hipLaunchKernelGGL((k_pb_spread_min<kSsspUnit, WT>), dim3((unsigned)nitems), dim3(kSpreadWG), lds, s, items, n,
-                         shift, srcl, wslot, vm, active, vals);
+                         shift, srcl, wslot, vm, active, vals, loop);
       break;
     case kSsspWeighted:
       hipLaunchKernelGGL((k_pb_spread_min<kSsspWeighted, WT>), dim3((unsigned)nitems), dim3(kSpreadWG), lds, s, items,
-                         n, shift, srcl, wslot, vm, active, vals);
+                         n, shift, srcl, wslot, vm, active, vals, loop);
       break;
     default:
       return hipErrorInvalidValue;
@@ -683,25 +687,26 @@ hipError_t spread_min_launch(int kind, const PbSpreadItem* items, int64_t nitems
 
 hipError_t launch_pb_spread_min(int kind, const PbSpreadItem* items, int64_t nitems, int64_t n, int shift,
                                 const uint16_t* srcl, const void* wslot, int wbytes, const uint2* vm,
-                                const uint32_t* active, uint32_t* vals, hipStream_t s) {
+                                const uint32_t* active, uint32_t* vals, const LoopState* loop, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   if (shift < 10 || shift > kMaxSrcShift) return hipErrorInvalidValue;
   if (kind == kSsspWeighted && !wslot) return hipErrorInvalidValue;
   if (wbytes == 1)
     return spread_min_launch(kind, items, nitems, n, shift, srcl, static_cast<const uint8_t*>(wslot), vm, active, vals,
-                             s);
+                             loop, s);
   return spread_min_launch(kind, items, nitems, n, shift, srcl, static_cast<const uint32_t*>(wslot), vm, active, vals,
-                           s);
+                           loop, s);
 }
 
 hipError_t launch_pb_fold_min(const PbFoldItem* items, int64_t nitems, const int64_t* run_off,
                               const int64_t* rpre, const int64_t* btotal, const int64_t* chunk_off,
                               const PbChunk* chunks, const int64_t* rbase, int64_t n, const uint32_t* vals,
-                              const uint16_t* dstl, uint2* vm, uint32_t* improved, hipStream_t s) {
+                              const uint16_t* dstl, uint2* vm, uint32_t* improved, const LoopState* loop,
+                              hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   const int64_t per = (nitems + 7) >> 3;
   hipLaunchKernelGGL(k_pb_fold<FoldMin>, dim3((unsigned)(8 * per)), dim3(kFoldWG), 0, s, items, nitems, run_off,
-                     rpre, btotal, chunk_off, chunks, rbase, n, vals, dstl, FoldMin{vm, improved});
+                     rpre, btotal, chunk_off, chunks, rbase, n, vals, dstl, FoldMin{vm, improved}, loop);
   return hipGetLastError();
 }
 

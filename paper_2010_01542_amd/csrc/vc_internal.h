@@ -25,13 +25,18 @@ struct Counters {
 enum MinKind { kCC = 0, kSsspUnit = 1, kSsspWeighted = 2 };
 
 // State of a device-driven superstep loop (captured HIP graph): kernels of a
-// superstep return at once when `done` is set; the step-end kernel records
-// |F_s|, E_s and sets `done` at quiescence or at the cap.
+// superstep return at once when `done` is set, and the kernels of every form
+// but the one in `mode` return at once too; the step-end kernel records
+// |F_s|, E_s, decides `done` at quiescence or at the cap, and picks the next
+// superstep's form from its message count.
 struct LoopState {
   long long done;
-  long long step;   // index of the superstep whose frontier was computed last
-  long long cap;    // superstep cap
+  long long step;    // index of the superstep whose frontier was computed last
+  long long cap;     // superstep cap
   long long capped;
+  long long mode;    // form of the next superstep: VC_SCHED_EDGE, VC_SCHED_PULL or VC_SCHED_BLOCKED
+  long long listed;  // its broadcast list length (vertices with out-edges)
+  long long edges;   // its messages
 };
 
 // LDS of a push workgroup's hub table: messages to targets below
@@ -63,6 +68,11 @@ hipError_t launch_sym_hash(const void* off, bool off64, const int32_t* dst, cons
 // before position min(t * tile, items + P[items]).
 hipError_t launch_mp_partition(const void* P, bool p64, int64_t items, int64_t total, int64_t tile, int64_t ntiles,
                                int32_t* tile_v, hipStream_t s);
+// The same over the broadcast list of a device-driven loop's next
+// superstep (items = loop->listed, total = listed + loop->edges), for
+// up to max_tiles tiles; nothing unless loop->mode is VC_SCHED_EDGE.
+hipError_t launch_loop_partition(const int64_t* P, int64_t tile, int64_t max_tiles, int32_t* tile_v,
+                                 const LoopState* loop, hipStream_t s);
 
 // PageRank / PPR.  `source` < 0 selects PageRank, else PPR from `source`.
 // mode: message / mailbox types; contrib holds the messages (8 bytes per
@@ -105,8 +115,19 @@ hipError_t launch_min_scatter_mp(int kind, bool list, bool tba, const void* off,
 hipError_t launch_min_compact(const void* off, bool off64, int64_t n, uint2* vm, const uint32_t* bitmap,
                               uint32_t* stale, int32_t* fq, int64_t* P, Counters* ctr, bool seed,
                               const LoopState* loop, hipStream_t s);
-// steps[2s], steps[2s+1] = |F_s|, E_s for s < max_recorded.
-hipError_t launch_loop_step(Counters* ctr, LoopState* loop, long long* steps, int64_t max_recorded, hipStream_t s);
+// Edge-balanced push of a device-driven loop's superstep (list mode:
+// broadcast list fq, degree prefix P, partition tile_v of at most max_tiles
+// tiles), over a fixed grid that takes the tiles round robin; nothing
+// unless loop->mode is VC_SCHED_EDGE.
+hipError_t launch_loop_scatter_mp(int kind, bool tba, const void* off, bool off64, const int32_t* dst,
+                                  const uint32_t* w, int64_t n, const int64_t* P, const int32_t* fq,
+                                  const int32_t* tile_v, int64_t tile, int64_t max_tiles, uint2* vm, uint32_t* bitmap,
+                                  bool hub, const LoopState* loop, hipStream_t s);
+// steps[3s], steps[3s+1], steps[3s+2] = |F_s|, E_s and the form of superstep
+// s (0 when it sends nothing) for s < max_recorded.  The next superstep
+// takes dense_mode when its messages reach dense_edges, else VC_SCHED_EDGE.
+hipError_t launch_loop_step(Counters* ctr, LoopState* loop, long long* steps, int64_t max_recorded,
+                            long long dense_edges, int dense_mode, hipStream_t s);
 // Seeded start: vm = (init, neutral); bitmap word = vertices with init < 0xFFFFFFFF.
 hipError_t launch_min_init_from(const uint32_t* init, int64_t n, uint2* vm, uint32_t* bitmap, hipStream_t s);
 
@@ -338,20 +359,25 @@ hipError_t launch_pb_fold(bool f32msg, const PbFoldItem* items, int64_t nitems, 
 // slot k from the current values (kInf for sources outside `active`; NULL:
 // all).  wslot: weights in slot order, wbytes (1 or 4) each (kSsspWeighted
 // only).
+// loop (may be NULL): in a device-driven loop, nothing unless loop->mode is
+// VC_SCHED_BLOCKED (both passes).
 hipError_t launch_pb_spread_min(int kind, const PbSpreadItem* items, int64_t nitems, int64_t n, int shift,
                                 const uint16_t* srcl, const void* wslot, int wbytes, const uint2* vm,
-                                const uint32_t* active, uint32_t* vals, hipStream_t s);
+                                const uint32_t* active, uint32_t* vals, const LoopState* loop, hipStream_t s);
 // Per receiver v, best = the minimum message of its in-edges; when best <
 // value(v) the mailbox takes it and v's bit in `improved` is set (the
 // outcome of launch_min_pull).  Mailboxes unreached on entry.
 hipError_t launch_pb_fold_min(const PbFoldItem* items, int64_t nitems, const int64_t* run_off,
                               const int64_t* rpre, const int64_t* btotal, const int64_t* chunk_off,
                               const PbChunk* chunks, const int64_t* rbase, int64_t n, const uint32_t* vals,
-                              const uint16_t* dstl, uint2* vm, uint32_t* improved, hipStream_t s);
+                              const uint16_t* dstl, uint2* vm, uint32_t* improved, const LoopState* loop, hipStream_t s);
 
 // In-place exclusive scan of P[0..count) with P[count] = total; `blocks`
 // is scratch of scan_scratch_entries(count) int64 values.
 int64_t scan_scratch_entries(int64_t count);
 hipError_t launch_exclusive_scan(int64_t* P, int64_t count, int64_t* blocks, hipStream_t s);
+// The same over loop->listed entries (at most max_count) in a device-driven
+// loop; nothing unless loop->mode is VC_SCHED_EDGE.
+hipError_t launch_loop_scan(int64_t* P, int64_t max_count, int64_t* blocks, const LoopState* loop, hipStream_t s);
 
 }  // namespace vc

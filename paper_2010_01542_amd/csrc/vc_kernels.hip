@@ -109,10 +109,8 @@ __global__ __launch_bounds__(kWG) void k_sym_hash(const OffT* __restrict__ off, 
 // the number of vertex-ends that precede merged position k when edge e of
 // item x sits at position e + x and the end of item x at P[x+1] + x.
 template <class PT>
-__global__ __launch_bounds__(kWG) void k_mp_partition(const PT* __restrict__ P, int64_t items, int64_t total,
-                                                      int64_t tile, int64_t ntiles, int32_t* __restrict__ tile_v) {
-  const int64_t t = gid();
-  if (t > ntiles) return;
+__device__ __forceinline__ int32_t mp_tile_start(const PT* __restrict__ P, int64_t items, int64_t total, int64_t tile,
+                                                 int64_t t) {
   const int64_t k = t * tile < total ? t * tile : total;
   int64_t lo = 0, hi = items;
   while (lo < hi) {
@@ -122,7 +120,27 @@ __global__ __launch_bounds__(kWG) void k_mp_partition(const PT* __restrict__ P, 
     else
       hi = mid;
   }
-  tile_v[t] = (int32_t)lo;
+  return (int32_t)lo;
+}
+
+template <class PT>
+__global__ __launch_bounds__(kWG) void k_mp_partition(const PT* __restrict__ P, int64_t items, int64_t total,
+                                                      int64_t tile, int64_t ntiles, int32_t* __restrict__ tile_v) {
+  const int64_t t = gid();
+  if (t > ntiles) return;
+  tile_v[t] = mp_tile_start(P, items, total, tile, t);
+}
+
+// The partition of a device-driven loop's broadcast list, sized from the
+// loop state (grid-stride over at most max_tiles + 1 tile starts).
+__global__ __launch_bounds__(kWG) void k_loop_partition(const int64_t* __restrict__ P, int64_t tile,
+                                                        int64_t max_tiles, int32_t* __restrict__ tile_v,
+                                                        const LoopState* __restrict__ loop) {
+  if (loop->done || loop->mode != VC_SCHED_EDGE) return;
+  const int64_t items = loop->listed, total = items + loop->edges;
+  int64_t ntiles = (total + tile - 1) / tile;
+  if (ntiles > max_tiles) ntiles = max_tiles;  // cannot happen for a valid loop state; keeps writes in bounds
+  for (int64_t t = gid(); t <= ntiles; t += grid_threads()) tile_v[t] = mp_tile_start(P, items, total, tile, t);
 }
 
 // ------------------------------------------------------------------ PageRank
@@ -379,15 +397,12 @@ __global__ __launch_bounds__(kWG) void k_min_scatter_vertex(const OffT* __restri
 // vertices and P is the CSR offsets.  List mode: items are the broadcast
 // list fq and P its degree prefix; item x's edges start at off[fq[x]].
 template <class PT, class OffT, int KIND, bool LIST, bool TBA>
-__global__ __launch_bounds__(kWG) void k_min_scatter_mp(const OffT* __restrict__ off,
-                                                        const int32_t* __restrict__ dst,
-                                                        const uint32_t* __restrict__ w, int64_t items, int64_t total,
-                                                        const PT* __restrict__ P, const int32_t* __restrict__ fq,
-                                                        const int32_t* __restrict__ tile_v, int64_t tile,
-                                                        uint2* __restrict__ vm, uint32_t* __restrict__ bitmap,
-                                                        int nhub) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int64_t t = blockIdx.x;
+__device__ __forceinline__ void min_scatter_mp_tile(int64_t t, unsigned char* smem, const OffT* __restrict__ off,
+                                                    const int32_t* __restrict__ dst,
+                                                    const uint32_t* __restrict__ w, int64_t items, int64_t total,
+                                                    const PT* __restrict__ P, const int32_t* __restrict__ fq,
+                                                    const int32_t* __restrict__ tile_v, int64_t tile,
+                                                    uint2* __restrict__ vm, uint32_t* __restrict__ bitmap, int nhub) {
   const int64_t k0 = t * tile;
   const int64_t k1 = (k0 + tile < total) ? k0 + tile : total;
   const int64_t i0 = tile_v[t], i1 = tile_v[t + 1];
@@ -427,6 +442,44 @@ __global__ __launch_bounds__(kWG) void k_min_scatter_mp(const OffT* __restrict__
   if (nhub) {
     __syncthreads();
     hub_flush_min<TBA>(s_hub, nhub, vm, bitmap);
+  }
+}
+
+template <class PT, class OffT, int KIND, bool LIST, bool TBA>
+__global__ __launch_bounds__(kWG) void k_min_scatter_mp(const OffT* __restrict__ off,
+                                                        const int32_t* __restrict__ dst,
+                                                        const uint32_t* __restrict__ w, int64_t items, int64_t total,
+                                                        const PT* __restrict__ P, const int32_t* __restrict__ fq,
+                                                        const int32_t* __restrict__ tile_v, int64_t tile,
+                                                        uint2* __restrict__ vm, uint32_t* __restrict__ bitmap,
+                                                        int nhub) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  min_scatter_mp_tile<PT, OffT, KIND, LIST, TBA>(blockIdx.x, smem, off, dst, w, items, total, P, fq, tile_v, tile, vm,
+                                                 bitmap, nhub);
+}
+
+// List-mode merge-path broadcast of a device-driven loop: the list length and
+// message count come from the loop state, and a fixed grid takes the tiles
+// round robin (the tile count is known only on the device).
+template <class OffT, int KIND, bool TBA>
+__global__ __launch_bounds__(kWG) void k_loop_scatter_mp(const OffT* __restrict__ off,
+                                                         const int32_t* __restrict__ dst,
+                                                         const uint32_t* __restrict__ w,
+                                                         const int64_t* __restrict__ P,
+                                                         const int32_t* __restrict__ fq,
+                                                         const int32_t* __restrict__ tile_v, int64_t tile,
+                                                         int64_t max_tiles, uint2* __restrict__ vm,
+                                                         uint32_t* __restrict__ bitmap, int nhub,
+                                                         const LoopState* __restrict__ loop) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (loop->done || loop->mode != VC_SCHED_EDGE) return;  // uniform
+  const int64_t items = loop->listed, total = items + loop->edges;
+  int64_t ntiles = (total + tile - 1) / tile;
+  if (ntiles > max_tiles) ntiles = max_tiles;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    min_scatter_mp_tile<int64_t, OffT, KIND, true, TBA>(t, smem, off, dst, w, items, total, P, fq, tile_v, tile, vm,
+                                                        bitmap, nhub);
+    __syncthreads();  // the next tile restages the LDS
   }
 }
 
@@ -532,23 +585,41 @@ __global__ __launch_bounds__(kWG) void k_min_output(int64_t n, const uint2* __re
 constexpr int kScanPer = 8;
 constexpr int64_t kScanItems = (int64_t)kWG * kScanPer;
 
+// loop (may be NULL): in a device-driven loop the count is the broadcast
+// list's length and the kernels run only for an edge-balanced push; a fixed
+// grid then takes the blocks round robin.
+__device__ __forceinline__ bool scan_count(const LoopState* loop, int64_t* count) {
+  if (!loop) return true;
+  if (loop->done || loop->mode != VC_SCHED_EDGE) return false;
+  *count = loop->listed;
+  return true;
+}
+
 __global__ __launch_bounds__(kWG) void k_scan_reduce(const int64_t* __restrict__ P, int64_t count,
-                                                     int64_t* __restrict__ blocks) {
-  const int64_t base = (int64_t)blockIdx.x * kScanItems;
-  long long acc = 0;
-  for (int k = 0; k < kScanPer; ++k) {
-    const int64_t i = base + (int64_t)k * kWG + threadIdx.x;
-    if (i < count) acc += P[i];
+                                                     int64_t* __restrict__ blocks, const LoopState* loop) {
+  if (!scan_count(loop, &count)) return;
+  const int64_t nb = (count + kScanItems - 1) / kScanItems;
+  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int64_t base = b * kScanItems;
+    long long acc = 0;
+    for (int k = 0; k < kScanPer; ++k) {
+      const int64_t i = base + (int64_t)k * kWG + threadIdx.x;
+      if (i < count) acc += P[i];
+    }
+    acc = block_sum<long long>(acc);  // ends with a barrier, so the next block may reuse its LDS
+    if (threadIdx.x == 0) blocks[b] = acc;
   }
-  acc = block_sum<long long>(acc);
-  if (threadIdx.x == 0) blocks[blockIdx.x] = acc;
 }
 
 // One workgroup scans the block sums in place and writes P[count] = total.
 __global__ __launch_bounds__(1024) void k_scan_top(int64_t* __restrict__ blocks, int64_t nblocks,
-                                                   int64_t* __restrict__ P, int64_t count) {
+                                                   int64_t* __restrict__ P, int64_t count, const LoopState* loop) {
   __shared__ long long s_w[1024 / 64];
   __shared__ long long s_carry;
+  if (loop) {
+    if (!scan_count(loop, &count)) return;
+    nblocks = (count + kScanItems - 1) / kScanItems;
+  }
   if (threadIdx.x == 0) s_carry = 0;
   __syncthreads();
   for (int64_t b0 = 0; b0 < nblocks; b0 += 1024) {
@@ -571,21 +642,25 @@ __global__ __launch_bounds__(1024) void k_scan_top(int64_t* __restrict__ blocks,
 }
 
 __global__ __launch_bounds__(kWG) void k_scan_down(int64_t* __restrict__ P, int64_t count,
-                                                   const int64_t* __restrict__ blocks) {
-  const int64_t base = (int64_t)blockIdx.x * kScanItems + (int64_t)threadIdx.x * kScanPer;
-  long long v[kScanPer];
-  long long sum = 0;
+                                                   const int64_t* __restrict__ blocks, const LoopState* loop) {
+  if (!scan_count(loop, &count)) return;
+  const int64_t nb = (count + kScanItems - 1) / kScanItems;
+  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int64_t base = b * kScanItems + (int64_t)threadIdx.x * kScanPer;
+    long long v[kScanPer];
+    long long sum = 0;
 #pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
-    v[k] = (base + k < count) ? P[base + k] : 0;
-    sum += v[k];
-  }
-  long long tot;
-  long long run = block_excl_scan<long long>(sum, &tot) + blocks[blockIdx.x];
+    for (int k = 0; k < kScanPer; ++k) {
+      v[k] = (base + k < count) ? P[base + k] : 0;
+      sum += v[k];
+    }
+    long long tot;
+    long long run = block_excl_scan<long long>(sum, &tot) + blocks[b];  // ends with a barrier
 #pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
-    if (base + k < count) P[base + k] = run;
-    run += v[k];
+    for (int k = 0; k < kScanPer; ++k) {
+      if (base + k < count) P[base + k] = run;
+      run += v[k];
+    }
   }
 }
 
@@ -648,6 +723,14 @@ hipError_t launch_mp_partition(const void* P, bool p64, int64_t items, int64_t t
   else
     hipLaunchKernelGGL(k_mp_partition<int32_t>, dim3(g), dim3(kWG), 0, s, (const int32_t*)P, items, total, tile,
                        ntiles, tile_v);
+  return hipGetLastError();
+}
+
+hipError_t launch_loop_partition(const int64_t* P, int64_t tile, int64_t max_tiles, int32_t* tile_v,
+                                 const LoopState* loop, hipStream_t s) {
+  const int64_t want = max_tiles + 1;
+  const unsigned g = grid_for(want < 65536 ? want : 65536);
+  hipLaunchKernelGGL(k_loop_partition, dim3(g), dim3(kWG), 0, s, P, tile, max_tiles, tile_v, loop);
   return hipGetLastError();
 }
 
@@ -868,6 +951,47 @@ hipError_t launch_min_scatter_mp(int kind, bool list, bool tba, const void* off,
   return hipGetLastError();
 }
 
+namespace {
+template <class OffT, int KIND>
+void loop_mp_launch(bool tba, const void* off, const int32_t* dst, const uint32_t* w, const int64_t* P,
+                    const int32_t* fq, const int32_t* tile_v, int64_t tile, int64_t max_tiles, uint2* vm,
+                    uint32_t* bitmap, int nhub, const LoopState* loop, hipStream_t s) {
+  const size_t lds = min_mp_lds_bytes(tile, true) - kHubBytes + (size_t)nhub * 4;
+  const unsigned g = (unsigned)(max_tiles < 4096 ? (max_tiles > 0 ? max_tiles : 1) : 4096);
+  if (tba)
+    hipLaunchKernelGGL((k_loop_scatter_mp<OffT, KIND, true>), dim3(g), dim3(kWG), lds, s, (const OffT*)off, dst, w, P,
+                       fq, tile_v, tile, max_tiles, vm, bitmap, nhub, loop);
+  else
+    hipLaunchKernelGGL((k_loop_scatter_mp<OffT, KIND, false>), dim3(g), dim3(kWG), lds, s, (const OffT*)off, dst, w,
+                       P, fq, tile_v, tile, max_tiles, vm, bitmap, nhub, loop);
+}
+}  // namespace
+
+hipError_t launch_loop_scatter_mp(int kind, bool tba, const void* off, bool off64, const int32_t* dst,
+                                  const uint32_t* w, int64_t n, const int64_t* P, const int32_t* fq,
+                                  const int32_t* tile_v, int64_t tile, int64_t max_tiles, uint2* vm, uint32_t* bitmap,
+                                  bool hub, const LoopState* loop, hipStream_t s) {
+  const int nhub = hub_slots(n, 4, hub);
+  if (off64) {
+    if (kind == kCC)
+      loop_mp_launch<int64_t, kCC>(tba, off, dst, w, P, fq, tile_v, tile, max_tiles, vm, bitmap, nhub, loop, s);
+    else if (kind == kSsspUnit)
+      loop_mp_launch<int64_t, kSsspUnit>(tba, off, dst, w, P, fq, tile_v, tile, max_tiles, vm, bitmap, nhub, loop, s);
+    else
+      loop_mp_launch<int64_t, kSsspWeighted>(tba, off, dst, w, P, fq, tile_v, tile, max_tiles, vm, bitmap, nhub, loop,
+                                             s);
+  } else {
+    if (kind == kCC)
+      loop_mp_launch<int32_t, kCC>(tba, off, dst, w, P, fq, tile_v, tile, max_tiles, vm, bitmap, nhub, loop, s);
+    else if (kind == kSsspUnit)
+      loop_mp_launch<int32_t, kSsspUnit>(tba, off, dst, w, P, fq, tile_v, tile, max_tiles, vm, bitmap, nhub, loop, s);
+    else
+      loop_mp_launch<int32_t, kSsspWeighted>(tba, off, dst, w, P, fq, tile_v, tile, max_tiles, vm, bitmap, nhub, loop,
+                                             s);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_min_compact(const void* off, bool off64, int64_t n, uint2* vm, const uint32_t* bitmap,
                               uint32_t* stale, int32_t* fq, int64_t* P, Counters* ctr, bool seed,
                               const LoopState* loop, hipStream_t s) {
@@ -881,22 +1005,28 @@ hipError_t launch_min_compact(const void* off, bool off64, int64_t n, uint2* vm,
   return hipGetLastError();
 }
 
-// End of a device-driven superstep: record |F|, E of the next superstep,
-// decide termination, reset the counters.
+// End of a device-driven superstep: record |F|, E of the next superstep and
+// the form it takes (dense_mode from dense_edges messages on, else the
+// edge-balanced push), decide termination, reset the counters.
 __global__ void k_loop_step(Counters* __restrict__ ctr, LoopState* __restrict__ loop, long long* __restrict__ steps,
-                            int64_t max_recorded) {
+                            int64_t max_recorded, long long dense_edges, int dense_mode) {
   if (threadIdx.x != 0 || blockIdx.x != 0 || loop->done) return;
   const long long s = loop->step + 1;
-  const long long f = (long long)ctr->active, e = (long long)ctr->edges;
+  const long long f = (long long)ctr->active, l = (long long)ctr->listed, e = (long long)ctr->edges;
+  const long long mode = (f == 0 || e == 0) ? 0 : (e >= dense_edges ? dense_mode : VC_SCHED_EDGE);
   if (s < max_recorded) {
-    steps[2 * s] = f;
-    steps[2 * s + 1] = e;
+    steps[3 * s] = f;
+    steps[3 * s + 1] = e;
+    steps[3 * s + 2] = mode;
   }
   loop->step = s;
+  loop->listed = l;
+  loop->edges = e;
+  loop->mode = mode;
   ctr->active = 0;
   ctr->listed = 0;
   ctr->edges = 0;
-  if (f == 0 || e == 0) {
+  if (mode == 0) {
     loop->done = 1;
   } else if (s >= loop->cap) {
     loop->done = 1;
@@ -904,8 +1034,9 @@ __global__ void k_loop_step(Counters* __restrict__ ctr, LoopState* __restrict__ 
   }
 }
 
-hipError_t launch_loop_step(Counters* ctr, LoopState* loop, long long* steps, int64_t max_recorded, hipStream_t s) {
-  hipLaunchKernelGGL(k_loop_step, dim3(1), dim3(64), 0, s, ctr, loop, steps, max_recorded);
+hipError_t launch_loop_step(Counters* ctr, LoopState* loop, long long* steps, int64_t max_recorded,
+                            long long dense_edges, int dense_mode, hipStream_t s) {
+  hipLaunchKernelGGL(k_loop_step, dim3(1), dim3(64), 0, s, ctr, loop, steps, max_recorded, dense_edges, dense_mode);
   return hipGetLastError();
 }
 
@@ -924,9 +1055,19 @@ int64_t scan_scratch_entries(int64_t count) { return (count + kScanItems - 1) / 
 
 hipError_t launch_exclusive_scan(int64_t* P, int64_t count, int64_t* blocks, hipStream_t s) {
   const int64_t nb = (count + kScanItems - 1) / kScanItems;
-  if (nb > 0) hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kWG), 0, s, P, count, blocks);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, blocks, nb, P, count);
-  if (nb > 0) hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kWG), 0, s, P, count, blocks);
+  const LoopState* none = nullptr;
+  if (nb > 0) hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kWG), 0, s, P, count, blocks, none);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, blocks, nb, P, count, none);
+  if (nb > 0) hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kWG), 0, s, P, count, blocks, none);
+  return hipGetLastError();
+}
+
+hipError_t launch_loop_scan(int64_t* P, int64_t max_count, int64_t* blocks, const LoopState* loop, hipStream_t s) {
+  const int64_t nb_max = (max_count + kScanItems - 1) / kScanItems;
+  const unsigned g = (unsigned)(nb_max < 1024 ? (nb_max > 0 ? nb_max : 1) : 1024);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(g), dim3(kWG), 0, s, P, max_count, blocks, loop);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, blocks, nb_max, P, max_count, loop);
+  hipLaunchKernelGGL(k_scan_down, dim3(g), dim3(kWG), 0, s, P, max_count, blocks, loop);
   return hipGetLastError();
 }
 

@@ -352,7 +352,7 @@ __global__ __launch_bounds__(kWG) void k_min_pull(const int64_t* __restrict__ in
                                                   uint32_t* __restrict__ improved, const LoopState* loop) {
   constexpr int64_t tile = (int64_t)kWG * VT;
   extern __shared__ __align__(16) unsigned char smem[];
-  if (loop && loop->done) return;  // device-driven loop already quiescent
+  if (loop && (loop->done || loop->mode != VC_SCHED_PULL)) return;  // quiescent, or another form this superstep
   Tile tl;
   if (!tile_bounds(tile_v, tile, n, m, &tl)) return;
   uint32_t* s_min = reinterpret_cast<uint32_t*>(smem);                          // tile + 1

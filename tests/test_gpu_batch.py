@@ -113,15 +113,20 @@ def big_union(request):
     return csrs, queries, refs
 
 
-@pytest.mark.parametrize("sched", ["blocked", "auto"])
+@pytest.mark.parametrize("sched", ["blocked", "auto", "auto-captured"])
 def test_large_union_takes_blocked_form_bit_exact(device, big_union, sched):
+    """The union at the size where AUTO takes the blocked form, in the host
+    loop and in the captured loop (whose forms are picked on the device)."""
     from paper_2010_01542_amd import Batch, vc
     csrs, queries, refs = big_union
     n = sum(c.n for c in csrs)
     assert n >= 1 << 20
     print(f"case batch union n={n} m={sum(c.m for c in csrs)} schedule={sched}", flush=True)
     b = Batch(csrs, queries)
-    out, st = b.run(schedule=sched, stats=True)
+    opts = vc.OPT_GRAPH_CAPTURE if sched.endswith("captured") else 0
+    out, st = b.run(schedule=sched.split("-")[0], options=opts, stats=True)
+    if opts:  # a second replay of the cached graph
+        out, st = b.run(schedule="auto", options=opts, stats=True)
     for i, (c, (prog, src), got, ref) in enumerate(zip(csrs, queries, b.split(out), refs)):
         assert np.array_equal(got, ref.values), (i, prog, c.n, c.m, int((got != ref.values).sum()))
     steps, senders, messages = union_stats(refs)

@@ -2,7 +2,11 @@
 
 A captured run must give the oracle's values and the oracle's per-superstep
 frontier sizes (recorded on the device); replays are interleaved with eager
-work and re-captures, and every replay is checked."""
+work and re-captures, and every replay is checked.  Captured CC / SSSP loops
+pick each superstep's form on the device (edge-balanced push below the
+dense threshold, the pull or, from 2^20 vertices, the blocked form above
+it): the forms they record must be the ones the host loop picks, and every
+form alone (explicit schedules) must give the same results."""
 import numpy as np
 import pytest
 
@@ -89,3 +93,51 @@ def test_autotune_keeps_results_exact(device):
     for c, (prog, src), got in zip(csrs, queries, b.split(out)):
         ref = oracle.run(prog, c.n, c.off, c.dst, c.w if prog == "sssp" else None, source=src)
         assert np.array_equal(got, ref.values)
+
+
+@pytest.mark.parametrize("sched", ["edge", "pull", "vertex"])
+def test_captured_loop_with_fixed_forms(device, sched):
+    """Explicit schedules fix the captured loop's form: pushed (edge-balanced,
+    for "edge" and "vertex") or pulled in every superstep."""
+    from paper_2010_01542_amd import vc
+    cap = vc.OPT_GRAPH_CAPTURE
+    d = rmatgen.rmat(14, 12, seed=31, weighted=True)
+    u = rmatgen.rmat(14, 12, seed=32, directed=False)
+    gd, gu = make(d), make(u, symmetric=True)
+    print(f"case captured loop schedule={sched}", flush=True)
+    want = vc.SCHED_PULL if sched == "pull" else vc.SCHED_EDGE
+    for g, c, prog in ((gd, d, "sssp"), (gu, u, "cc")):
+        for _ in range(2):
+            _, st, _ = check_min(c, g, prog, source=3, schedule=sched, options=cap)
+            used = [x for x in st.schedule.tolist()[1:] if x]
+            assert used and set(used) == {want}, st.schedule.tolist()
+
+
+@pytest.fixture(scope="module")
+def big_pair():
+    """Graphs of 2^20 vertices, where AUTO's dense supersteps take the blocked form."""
+    d = rmatgen.rmat(20, 6, seed=33, weighted=True)
+    u = rmatgen.rmat(20, 3, seed=34, directed=False)
+    return d, u
+
+
+def test_captured_loop_switches_forms_on_the_device(device, big_pair):
+    """AUTO in a captured loop on a 2^20-vertex graph: the device picks the
+    blocked form for dense supersteps and the push for the rest, exactly as
+    the host loop does, with the oracle's values and frontier sizes."""
+    from paper_2010_01542_amd import vc
+    cap = vc.OPT_GRAPH_CAPTURE
+    d, u = big_pair
+    gd, gu = make(d), make(u, symmetric=True)
+    for g, c, prog in ((gd, d, "sssp"), (gu, u, "cc")):
+        print(f"case captured loop 2^20 {prog}", flush=True)
+        _, host, _ = check_min(c, g, prog, source=0)
+        # the host loop pushes tiny frontiers vertex-per-thread, the captured one edge-balanced
+        want = [vc.SCHED_EDGE if x == vc.SCHED_VERTEX else x for x in host.schedule.tolist()]
+        for _ in range(2):
+            _, st, _ = check_min(c, g, prog, source=0, options=cap)
+            assert st.schedule.tolist()[1:] == want[1:], (st.schedule.tolist(), host.schedule.tolist())
+        used = set(st.schedule.tolist()[1:])
+        assert vc.SCHED_BLOCKED in used and vc.SCHED_EDGE in used, st.schedule.tolist()
+        _, st, _ = check_min(c, g, prog, source=0, schedule="blocked", options=cap)
+        assert set(x for x in st.schedule.tolist()[1:] if x) == {vc.SCHED_BLOCKED}
