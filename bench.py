@@ -113,6 +113,46 @@ def min_superstep_bytes(n, off_bytes, weighted, frontier, edges, receivers, dens
     return out
 
 
+def cpu_pool_cores():
+    """Host cores a pool of oracle runs may use: the ones this process may
+    run on, at most 16 (one GPU's share of the machine's CPUs)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def cpu_pool_baseline(tasks, what, expect=None):
+    """CPU throughput baseline for many independent queries: the oracle (a
+    single-threaded C engine that releases the interpreter lock while it
+    runs) on every task, `cores` at a time on a thread pool.  tasks: (program,
+    csr, source, T) tuples.  Reports messages and queries per second of wall
+    time.  expect (optional): expect(i) gives the device's values for task i,
+    which must equal the oracle's (CC labels, SSSP distances), or None where
+    no such check applies; "equal_device" counts the equal ones."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    cores = cpu_pool_cores()
+
+    def one(i):
+        prog, c, src, T = tasks[i]
+        r = oracle.run(prog, c.n, c.off, c.dst, c.w if prog == "sssp" else None, source=src, T=T)
+        dev_vals = None if expect is None else expect(i)
+        ok = dev_vals is None or bool(np.array_equal(dev_vals, r.values))
+        return int(r.messages.sum()), ok, dev_vals is not None
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as pool:
+        res = list(pool.map(one, range(len(tasks))))
+    wall = time.perf_counter() - t0
+    msgs = sum(r[0] for r in res)
+    equal = sum(r[1] and r[2] for r in res)
+    checked = sum(r[2] for r in res)
+    log(f"cpu pool baseline ({what}): {len(tasks)} queries, {msgs} messages in {wall:.1f}s on {cores} threads")
+    return {"value": round(msgs / wall / 1e9, 4), "unit": "GTEPS", "cores": cores, "kind": "oracle",
+            "queries_per_s": round(len(tasks) / wall, 2),
+            "equal_device": None if expect is None else f"{equal}/{checked}",
+            "sample": f"{what}: {len(tasks)} independent oracle runs ({msgs} messages) on a pool of {cores} "
+                      f"threads, one query per thread at a time, {wall:.1f}s wall"}
+
+
 def batch_members(count, seed):
     """Seeded batch: scales uniform on [10, 16], edge factor uniform on [8, 32],
     each graph SSSP (directed, uint32 weights, source 0) or hash-min CC
@@ -206,6 +246,8 @@ def bench_batch(args, dev):
         raise SystemExit(f"batched results differ from the plain runs for {len(csrs) - same} members")
     blat_ms = np.array(blat) * 1e3
     lat_ms = np.array(lat) * 1e3
+    cpu = None if args.no_cpu_baseline else cpu_pool_baseline(
+        [(prog, c, src, 10) for c, (prog, src) in zip(csrs, queries)], "every member of the batch")
     return {
         "metric": "GTEPS & HBM GB/s vs peak per superstep; batched/served p50/p99 vs plain",
         "value": round(edges_plain / batch_s / 1e9, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
@@ -228,6 +270,7 @@ def bench_batch(args, dev):
                            "latency_ms_p50": round(float(np.percentile(np.array(lat_cap) * 1e3, 50)), 3),
                            "latency_ms_p99": round(float(np.percentile(np.array(lat_cap) * 1e3, 99)), 3)},
         "batch_autotuned": tuned,
+        "cpu_baseline": cpu,
         "speedup_vs_plain": round(plain_s / batch_s, 2),
         "edges_relaxed": int(edges_plain),
     }
@@ -269,6 +312,15 @@ def bench_multi(args, dev):
     # spot check: the last plain run's source column is identical
     assert torch.equal(outk[:, -1].contiguous(), out1), "many-source column differs from the plain run"
     lat_ms = np.array(lat) * 1e3
+    cpu = None
+    if not args.no_cpu_baseline:
+        k = min(64, len(sources))
+        cols = outk[:, :k].cpu().numpy().view(np.uint32)  # the many-source run's first k columns
+        cpu = cpu_pool_baseline([("sssp", csr, int(x), 0) for x in sources[:k]],
+                                f"SSSP from the first {k} of the {len(sources)} sources",
+                                expect=lambda i: cols[:, i])
+        if cpu["equal_device"] != f"{k}/{k}":
+            raise SystemExit(f"many-source distances differ from the oracle: {cpu['equal_device']}")
     return {
         "metric": "GTEPS & HBM GB/s vs peak per superstep; batched/served p50/p99 vs plain",
         "value": round(edges_plain / multi_s / 1e9, 3), "unit": "GTEPS (plain-equivalent messages)", "n_gpus": 1,
@@ -283,6 +335,7 @@ def bench_multi(args, dev):
                   "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 3),
                   "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 3)},
         "speedup_vs_plain": round(plain_s / multi_s, 2),
+        "cpu_baseline": cpu,
     }
 
 
@@ -538,6 +591,21 @@ def bench_serve(args, dev):
         log(f"load {load}: {json.dumps(pt)}")
         points.append(pt)
     best = max(points, key=lambda x: x["requests_per_s"])
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle on a seeded sample of the request stream; the plain
+        # path's CC / SSSP results (kept in outs) must equal it
+        pick = np.sort(np.random.default_rng(rmatgen.BASE_SEED + 10).choice(len(reqs), size=min(32, len(reqs)),
+                                                                         replace=False))
+        tasks = [(reqs[i][1], csrs[reqs[i][0]], reqs[i][2], 20) for i in pick]
+
+        def expect(j):
+            i = pick[j]
+            return None if reqs[i][1] == "ppr" else outs[i].cpu().numpy().view(np.uint32)
+
+        cpu = cpu_pool_baseline(tasks, f"a seeded sample of {len(tasks)} of the {len(reqs)} requests", expect)
+        # throughput of the oracle serving the whole stream at that rate
+        cpu["requests_per_s"] = cpu["queries_per_s"]
     return {
         "metric": "served requests/s (70% SSSP, 20% PPR T=20, 10% CC; resident R-MAT graphs and an uploaded pool)",
         "value": best["requests_per_s"], "unit": "requests/s", "n_gpus": 1, "steps": len(SERVE_LOADS), "warmup": 1,
@@ -551,6 +619,7 @@ def bench_serve(args, dev):
         "plain": {"requests_per_s": round(capacity, 2), "by_kind": plain_by_kind},
         "speedup_vs_plain_at_best_load": round(best["requests_per_s"] / capacity, 2),
         "loads": points,
+        "cpu_baseline": cpu,
     }
 
 
@@ -754,6 +823,22 @@ def main():
                         "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(bytes_launch),
                         "gteps_per_launch": round(m / (avg_ms * 1e-3) / 1e9, 2), "superstep": superstep}
 
+    # hash-min CC: the vertex-centric and edge-centric work distributions
+    # (and the dense forms) each run alone, every superstep in one form
+    schedules = None
+    if args.workload == "cc-s22":
+        schedules = {}
+        for sc in ("vertex", "edge", "pull", "blocked", "auto"):
+            ms, sts = [], None
+            for _ in range(3):
+                _, sts = g.run("cc", out_u, schedule=sc, stats=True, timing=True)
+                ms.append(sts.elapsed_ms)
+            schedules[sc] = {"run_ms_median": round(float(np.median(ms)), 3),
+                             "kernel_ms": round(float(sts.step_ms.sum()), 3),
+                             "gteps": round(sts.edges_relaxed / (float(np.median(ms)) * 1e-3) / 1e9, 2),
+                             "schedule_per_superstep": sts.schedule.tolist()}
+        log(f"cc schedules: { {k: v['run_ms_median'] for k, v in schedules.items()} }")
+
     # the oracle: CPU baseline (one pinned host core) and the accuracy of this run
     cpu, accuracy, min_ref = None, {}, {}
     if not args.no_cpu_baseline:
@@ -843,6 +928,7 @@ def main():
         "accuracy": accuracy,
         "pagerank_error": accuracy.get("pagerank"),
         "setup": setup,
+        "schedules": schedules,
         "detail": detail,
         "host": host_info(),
         "device": torch.cuda.get_device_name(0),

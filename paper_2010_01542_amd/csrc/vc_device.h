@@ -109,6 +109,42 @@ __device__ __forceinline__ M rank_msg(double r, int64_t deg) {
 // Byte offset of the next LDS sub-array: rounded up to 16 bytes.
 __host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 
+// A merge-path tile of the merged (edge, item-end) sequence: workgroup
+// blockIdx.x owns merged positions [t * tile, (t + 1) * tile), i.e. the
+// edges j0 .. j1 - 1 of items i0 .. i0 + cnt - 1 (tile_v from the partition
+// kernel).  Returns whether the tile holds any edge.
+struct Tile {
+  int64_t i0, j0, j1;
+  int cnt;
+};
+
+__device__ __forceinline__ bool tile_bounds(const int32_t* __restrict__ tile_v, int64_t tile, int64_t items,
+                                            int64_t edges, Tile* tl) {
+  const int64_t t = blockIdx.x;
+  const int64_t k0 = t * tile;
+  const int64_t k1 = (k0 + tile < items + edges) ? k0 + tile : items + edges;
+  const int64_t i0 = tile_v[t], i1 = tile_v[t + 1];
+  tl->i0 = i0;
+  tl->j0 = k0 - i0;
+  tl->j1 = k1 - i1;
+  const int64_t ilast = i1 < items ? i1 : items - 1;
+  tl->cnt = (int)(ilast - i0 + 1);
+  return tl->j1 > tl->j0;
+}
+
+// Owner (local item index) of edge e: last x with s_off[x] <= e.
+__device__ __forceinline__ int owner_of(const int64_t* __restrict__ s_off, int cnt, int64_t e) {
+  int lo = 0, hi = cnt - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_off[mid] <= e)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 inline unsigned grid_for(int64_t count) { return (unsigned)((count + kWG - 1) / kWG); }
 
 // Grid of a grid-stride loop over `count` items.  A dispatch counts its

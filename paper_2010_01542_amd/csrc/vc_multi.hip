@@ -26,36 +26,6 @@ namespace {
 
 using namespace dev;
 
-struct Tile {
-  int64_t i0, j0, j1;
-  int cnt;
-};
-
-__device__ __forceinline__ bool tile_bounds(const int32_t* __restrict__ tile_v, int64_t tile, int64_t items,
-                                            int64_t edges, Tile* tl) {
-  const int64_t t = blockIdx.x;
-  const int64_t k0 = t * tile;
-  const int64_t k1 = (k0 + tile < items + edges) ? k0 + tile : items + edges;
-  const int64_t i0 = tile_v[t], i1 = tile_v[t + 1];
-  tl->i0 = i0;
-  tl->j0 = k0 - i0;
-  tl->j1 = k1 - i1;
-  const int64_t ilast = i1 < items ? i1 : items - 1;
-  tl->cnt = (int)(ilast - i0 + 1);
-  return tl->j1 > tl->j0;
-}
-
-__device__ __forceinline__ int owner_of(const int64_t* __restrict__ s_off, int cnt, int64_t e) {
-  int lo = 0, hi = cnt - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (s_off[mid] <= e)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
 
 // Row of chunk c of vertex v in a chunk-major value array.
 __device__ __forceinline__ int64_t row(int c, int64_t n, int64_t v) { return ((int64_t)c * n + v) * 64; }

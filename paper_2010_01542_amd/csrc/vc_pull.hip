@@ -210,38 +210,6 @@ __global__ __launch_bounds__(kWG) void k_csc_fill(const OffT* __restrict__ off, 
   }
 }
 
-// --------------------------------------------------------------- tile set-up
-struct Tile {
-  int64_t i0, j0, j1;
-  int cnt;
-};
-
-__device__ __forceinline__ bool tile_bounds(const int32_t* __restrict__ tile_v, int64_t tile, int64_t items,
-                                            int64_t edges, Tile* tl) {
-  const int64_t t = blockIdx.x;
-  const int64_t k0 = t * tile;
-  const int64_t k1 = (k0 + tile < items + edges) ? k0 + tile : items + edges;
-  const int64_t i0 = tile_v[t], i1 = tile_v[t + 1];
-  tl->i0 = i0;
-  tl->j0 = k0 - i0;
-  tl->j1 = k1 - i1;
-  const int64_t ilast = i1 < items ? i1 : items - 1;
-  tl->cnt = (int)(ilast - i0 + 1);
-  return tl->j1 > tl->j0;
-}
-
-// Owner (local receiver index) of in-edge e: last x with s_off[x] <= e.
-__device__ __forceinline__ int owner_of(const int64_t* __restrict__ s_off, int cnt, int64_t e) {
-  int lo = 0, hi = cnt - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (s_off[mid] <= e)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
 
 // --------------------------------------------------------------- PageRank pull
 
