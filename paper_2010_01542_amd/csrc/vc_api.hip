@@ -431,6 +431,7 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
   // weights in slot order: one byte each when every weight fits (weights of
   // 1..255, as the benchmark graphs have, save 3 bytes per edge and superstep)
   int wbytes = 4;
+  uint32_t wmax_all = 1;
   if (g->w) {
     DevBuf wmax;
     VC_TRY(wmax.ensure(4));
@@ -440,6 +441,7 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
     VC_TRY(hipMemcpyAsync(&mx, wmax.p, 4, hipMemcpyDeviceToHost, s));
     VC_TRY(hipStreamSynchronize(s));
     wbytes = mx <= 255 ? 1 : 4;
+    wmax_all = mx;
     VC_TRY(g->pb_w.ensure((size_t)m * wbytes + 4));
   }
   VC_TRY(vc::launch_exclusive_scan(cnt.as<int64_t>(), nb, blocks.as<int64_t>(), s));
@@ -512,6 +514,7 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
   pb.dstl = g->pb_dstl.as<uint16_t>();
   pb.w = g->w ? g->pb_w.p : nullptr;
   pb.wbytes = wbytes;
+  pb.wmax = wmax_all;
   pb.run_off = g->pb_run_off.as<int64_t>();
   pb.btotal = g->pb_btotal.as<int64_t>();
   pb.rpre = g->pb_rpre.as<int64_t>();
@@ -688,7 +691,7 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
         }
         if (e == hipSuccess)
           e = vc::launch_pr_apply(mode, g->off, g->off64, n, teleport, d, source, mb, contrib, stage, step + 1 == T, cs,
-                                  pb_kinds);
+                                  pb_kinds, step > 0);
       }
       hipGraph_t graph = nullptr;
       const hipError_t e2 = hipStreamEndCapture(cs, &graph);
@@ -737,7 +740,7 @@ vc_status run_rank(vc_graph g, const vc_params& p, bool personal, float* out, hi
     }
     if (timed) VC_TRY(hipEventRecord(g->events[3 * step + 1], s));
     VC_TRY(vc::launch_pr_apply(mode, g->off, g->off64, n, teleport, d, source, mb, contrib, rank_out, step + 1 == T, s,
-                               pb_kinds));
+                               pb_kinds, step > 0));
     if (timed) VC_TRY(hipEventRecord(g->events[3 * step + 2], s));
     rec.step(step, n, g->m, sched);
   }
@@ -873,11 +876,12 @@ vc_status run_min_device_loop(vc_graph g, const vc_params& p, int kind, int64_t 
       }
       if (e == hipSuccess && forms.dense_edges != LLONG_MAX) {  // the dense form
         if (blocked) {
+          // 4-byte slots: the graph is replayed for any superstep
           e = vc::launch_pb_spread_min(kind, pb.spread, pb.nspread, n, pb.shift, pb.srcl, pb.w, pb.wbytes, vm,
-                                       bits[1 - a], slot_msg, loop, cs);
+                                       bits[1 - a], slot_msg, false, loop, cs);
           if (e == hipSuccess)
             e = vc::launch_pb_fold_min(pb.fold, pb.nfold, pb.run_off, pb.rpre, pb.btotal, pb.chunk_off, pb.chunks,
-                                       pb.rbase, n, slot_msg, pb.dstl, vm, bits[a], loop, cs);
+                                       pb.rbase, n, slot_msg, false, pb.dstl, vm, bits[a], loop, cs);
         } else {
           e = vc::launch_min_pull(kind, g->csc_off_p, g->in_src, g->in_w, n, m, g->csc_tiles_p, g->csc_tile,
                                   g->csc_ntiles, vm, bits[1 - a], bits[a], loop, cs);
@@ -1071,10 +1075,14 @@ vc_status run_min(vc_graph g, const vc_params& p, int kind, const uint32_t* seed
       const vc::PbShared& pb = g->pb;
       uint32_t* slot_msg = g->pb_vals.as<uint32_t>();
       if (timed) VC_TRY(hipEventRecord(g->events[1], s));
+      // single-source SSSP: a value set at superstep t is a path of at most t
+      // edges, so superstep `step` sends messages of at most (step + 1) *
+      // wmax; below 0xFFFF they travel in 2-byte slots
+      const bool narrow = kind != vc::kCC && !seed && (double)(step + 1) * (double)pb.wmax < 65535.0;
       VC_TRY(vc::launch_pb_spread_min(kind, pb.spread, pb.nspread, n, pb.shift, pb.srcl, pb.w, pb.wbytes, vm,
-                                      dense ? nullptr : bits[1 - cur], slot_msg, nullptr, s));
+                                      dense ? nullptr : bits[1 - cur], slot_msg, narrow, nullptr, s));
       VC_TRY(vc::launch_pb_fold_min(pb.fold, pb.nfold, pb.run_off, pb.rpre, pb.btotal, pb.chunk_off, pb.chunks,
-                                    pb.rbase, n, slot_msg, pb.dstl, vm, improved, nullptr, s));
+                                    pb.rbase, n, slot_msg, narrow, pb.dstl, vm, improved, nullptr, s));
     } else if (sched == VC_SCHED_PULL) {
       vc_status st = ensure_csc(g, s);
       if (st == VC_OK) st = csc_partition(g, vc::pull_tile(tile), s);

@@ -344,14 +344,24 @@ __device__ __forceinline__ void stage_min_window(uint32_t* wmin, const uint2* __
 // reading as unreached, then vals[k] = the message on slot k: the value
 // (CC) or the value plus the edge's weight (SSSP, saturating; unweighted:
 // plus 1), unreached (kInf) for an inactive source.  Slot weights are bytes
-// (WT = uint8_t) when every weight of the graph fits one.
-template <int KIND, class WT>
+// (WT = uint8_t) when every weight of the graph fits one.  Slot messages are
+// MT: uint32_t, or uint16_t when the caller knows every message of the
+// superstep is below 0xFFFF, which then stands for unreached.
+template <class MT>
+__device__ __forceinline__ MT slot_msg(uint32_t m) {
+  if constexpr (sizeof(MT) == 2)
+    return (MT)(m < 0xFFFFu ? m : 0xFFFFu);
+  else
+    return m;
+}
+
+template <int KIND, class WT, class MT>
 __global__ __launch_bounds__(kSpreadWG) void k_pb_spread_min(const PbSpreadItem* __restrict__ items, int64_t n,
                                                              int shift, const uint16_t* __restrict__ srcl,
                                                              const WT* __restrict__ wslot,
                                                              const uint2* __restrict__ vm,
                                                              const uint32_t* __restrict__ active,
-                                                             uint32_t* __restrict__ vals,
+                                                             MT* __restrict__ vals,
                                                              const LoopState* __restrict__ loop) {
   constexpr int U = 8;
   extern __shared__ __align__(16) uint32_t wmin[];
@@ -381,7 +391,7 @@ __global__ __launch_bounds__(kSpreadWG) void k_pb_spread_min(const PbSpreadItem*
       const int64_t k = base + (int64_t)u * kSpreadWG;
       if (k < it.k1) {
         const uint32_t val = wmin[x[u]];
-        vals[k] = KIND == kCC ? val : sat_add(val, wv[u]);  // kInf stays kInf
+        vals[k] = slot_msg<MT>(KIND == kCC ? val : sat_add(val, wv[u]));  // kInf stays unreached
       }
     }
   }
@@ -430,14 +440,15 @@ struct FoldSum {
   }
 };
 
-struct FoldMin {
-  using Val = uint32_t;
+template <class V>
+struct FoldMinT {
+  using Val = V;  // slot messages: uint32_t, or uint16_t with 0xFFFF for unreached
   using Box = uint32_t;
   uint2* vm;
   uint32_t* improved;
   static constexpr Box kEmpty = kInf;
   __device__ __forceinline__ static void add(Box* box, uint16_t d, Val v) {
-    if (v != kInf) atomicMin(&box[d], v);
+    if (v != Val(~Val(0))) atomicMin(&box[d], (uint32_t)v);
   }
   __device__ __forceinline__ void flush(const PbFoldItem& it, const Box* box, int64_t n) const {
     constexpr int R = (1 << kPbDstShift) / kFoldWG;  // rounds; every lane runs every round
@@ -470,6 +481,8 @@ struct FoldMin {
     }
   }
 };
+using FoldMin = FoldMinT<uint32_t>;
+using FoldMin16 = FoldMinT<uint16_t>;
 
 template <class Op>
 __global__ __launch_bounds__(kFoldWG) void k_pb_fold(const PbFoldItem* __restrict__ items, int64_t nitems,
@@ -660,53 +673,72 @@ hipError_t launch_pb_fold(bool f32msg, const PbFoldItem* items, int64_t nitems, 
 }
 
 namespace {
-template <class WT>
+template <class WT, class MT>
 hipError_t spread_min_launch(int kind, const PbSpreadItem* items, int64_t nitems, int64_t n, int shift,
                              const uint16_t* srcl, const WT* wslot, const uint2* vm, const uint32_t* active,
-                             uint32_t* vals, const LoopState* loop, hipStream_t s) {
+                             MT* vals, const LoopState* loop, hipStream_t s) {
   const size_t lds = (size_t)4 << shift;
   switch (kind) {
     case kCC:
-      hipLaunchKernelGGL((k_pb_spread_min<kCC, WT>), dim3((unsigned)nitems), dim3(kSpreadWG), lds, s, items, n, shift,
-                         srcl, wslot, vm, active, vals, loop);
-      break;
-    case kSsspUnit:
-      hipLaunchKernelGGL((k_pb_spread_min<kSsspUnit, WT>), dim3((unsigned)nitems), dim3(kSpreadWG), lds, s, items, n,
+      hipLaunchKernelGGL((k_pb_spread_min<kCC, WT, MT>), dim3((unsigned)nitems), dim3(kSpreadWG), lds, s, items, n,
                          shift, srcl, wslot, vm, active, vals, loop);
       break;
-    case kSsspWeighted:
-      hipLaunchKernelGGL((k_pb_spread_min<kSsspWeighted, WT>), dim3((unsigned)nitems), dim3(kSpreadWG), lds, s, items,
+    case kSsspUnit:
+      hipLaunchKernelGGL((k_pb_spread_min<kSsspUnit, WT, MT>), dim3((unsigned)nitems), dim3(kSpreadWG), lds, s, items,
                          n, shift, srcl, wslot, vm, active, vals, loop);
+      break;
+    case kSsspWeighted:
+      hipLaunchKernelGGL((k_pb_spread_min<kSsspWeighted, WT, MT>), dim3((unsigned)nitems), dim3(kSpreadWG), lds, s,
+                         items, n, shift, srcl, wslot, vm, active, vals, loop);
       break;
     default:
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
+
+template <class WT>
+hipError_t spread_min_width(bool narrow, int kind, const PbSpreadItem* items, int64_t nitems, int64_t n, int shift,
+                            const uint16_t* srcl, const WT* wslot, const uint2* vm, const uint32_t* active,
+                            void* vals, const LoopState* loop, hipStream_t s) {
+  if (narrow)
+    return spread_min_launch(kind, items, nitems, n, shift, srcl, wslot, vm, active, static_cast<uint16_t*>(vals),
+                             loop, s);
+  return spread_min_launch(kind, items, nitems, n, shift, srcl, wslot, vm, active, static_cast<uint32_t*>(vals), loop,
+                           s);
+}
 }  // namespace
 
 hipError_t launch_pb_spread_min(int kind, const PbSpreadItem* items, int64_t nitems, int64_t n, int shift,
                                 const uint16_t* srcl, const void* wslot, int wbytes, const uint2* vm,
-                                const uint32_t* active, uint32_t* vals, const LoopState* loop, hipStream_t s) {
+                                const uint32_t* active, void* vals, bool narrow, const LoopState* loop,
+                                hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   if (shift < 10 || shift > kMaxSrcShift) return hipErrorInvalidValue;
   if (kind == kSsspWeighted && !wslot) return hipErrorInvalidValue;
+  if (narrow && kind == kCC) return hipErrorInvalidValue;  // labels are vertex ids
   if (wbytes == 1)
-    return spread_min_launch(kind, items, nitems, n, shift, srcl, static_cast<const uint8_t*>(wslot), vm, active, vals,
-                             loop, s);
-  return spread_min_launch(kind, items, nitems, n, shift, srcl, static_cast<const uint32_t*>(wslot), vm, active, vals,
-                           loop, s);
+    return spread_min_width(narrow, kind, items, nitems, n, shift, srcl, static_cast<const uint8_t*>(wslot), vm,
+                            active, vals, loop, s);
+  return spread_min_width(narrow, kind, items, nitems, n, shift, srcl, static_cast<const uint32_t*>(wslot), vm, active,
+                          vals, loop, s);
 }
 
 hipError_t launch_pb_fold_min(const PbFoldItem* items, int64_t nitems, const int64_t* run_off,
                               const int64_t* rpre, const int64_t* btotal, const int64_t* chunk_off,
-                              const PbChunk* chunks, const int64_t* rbase, int64_t n, const uint32_t* vals,
+                              const PbChunk* chunks, const int64_t* rbase, int64_t n, const void* vals, bool narrow,
                               const uint16_t* dstl, uint2* vm, uint32_t* improved, const LoopState* loop,
                               hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   const int64_t per = (nitems + 7) >> 3;
-  hipLaunchKernelGGL(k_pb_fold<FoldMin>, dim3((unsigned)(8 * per)), dim3(kFoldWG), 0, s, items, nitems, run_off,
-                     rpre, btotal, chunk_off, chunks, rbase, n, vals, dstl, FoldMin{vm, improved}, loop);
+  if (narrow)
+    hipLaunchKernelGGL(k_pb_fold<FoldMin16>, dim3((unsigned)(8 * per)), dim3(kFoldWG), 0, s, items, nitems, run_off,
+                       rpre, btotal, chunk_off, chunks, rbase, n, static_cast<const uint16_t*>(vals), dstl,
+                       FoldMin16{vm, improved}, loop);
+  else
+    hipLaunchKernelGGL(k_pb_fold<FoldMin>, dim3((unsigned)(8 * per)), dim3(kFoldWG), 0, s, items, nitems, run_off,
+                       rpre, btotal, chunk_off, chunks, rbase, n, static_cast<const uint32_t*>(vals), dstl,
+                       FoldMin{vm, improved}, loop);
   return hipGetLastError();
 }
 

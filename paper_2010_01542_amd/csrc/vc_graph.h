@@ -127,6 +127,7 @@ struct PbShared {
   const uint16_t* dstl = nullptr;
   const void* w = nullptr;  // edge weights in slot order (weighted graphs), wbytes each
   int wbytes = 4;
+  uint32_t wmax = 1;        // largest edge weight (1 when unweighted)
   const int64_t* run_off = nullptr;
   const int64_t* btotal = nullptr;
   const int64_t* rpre = nullptr;

@@ -94,9 +94,12 @@ hipError_t launch_pr_scatter_mp(int mode, const void* off, bool off64, const int
 // the rank into out when last).  kinds: NULL (every mailbox is read and
 // cleared), or the blocked layout's kind of every destination bin, which
 // says which mailboxes hold sums and which must be cleared (PbBinKind).
+// keep_empty (with kinds, not last): the messages of vertices in bins
+// without in-edges are left as an earlier update wrote them (they do not
+// change after the first update).
 hipError_t launch_pr_apply(int mode, const void* off, bool off64, int64_t n, double teleport, double damping,
                            int64_t source, void* mb, void* contrib, float* out, bool last, hipStream_t s,
-                           const uint8_t* kinds = nullptr);
+                           const uint8_t* kinds = nullptr, bool keep_empty = false);
 
 // Hash-min CC and SSSP.  vm holds (value, mailbox) pairs.
 // ids: the label each vertex starts CC with (its original id after
@@ -359,17 +362,20 @@ hipError_t launch_pb_fold(bool f32msg, const PbFoldItem* items, int64_t nitems, 
 // slot k from the current values (kInf for sources outside `active`; NULL:
 // all).  wslot: weights in slot order, wbytes (1 or 4) each (kSsspWeighted
 // only).
-// loop (may be NULL): in a device-driven loop, nothing unless loop->mode is
-// VC_SCHED_BLOCKED (both passes).
+// narrow (SSSP only): slot messages are uint16_t, 0xFFFF standing for
+// unreached; the caller guarantees every message of the superstep is below
+// 0xFFFF (the fold then reads the same width).  loop (may be NULL): in a
+// device-driven loop, nothing unless loop->mode is VC_SCHED_BLOCKED (both
+// passes).
 hipError_t launch_pb_spread_min(int kind, const PbSpreadItem* items, int64_t nitems, int64_t n, int shift,
                                 const uint16_t* srcl, const void* wslot, int wbytes, const uint2* vm,
-                                const uint32_t* active, uint32_t* vals, const LoopState* loop, hipStream_t s);
+                                const uint32_t* active, void* vals, bool narrow, const LoopState* loop, hipStream_t s);
 // Per receiver v, best = the minimum message of its in-edges; when best <
 // value(v) the mailbox takes it and v's bit in `improved` is set (the
 // outcome of launch_min_pull).  Mailboxes unreached on entry.
 hipError_t launch_pb_fold_min(const PbFoldItem* items, int64_t nitems, const int64_t* run_off,
                               const int64_t* rpre, const int64_t* btotal, const int64_t* chunk_off,
-                              const PbChunk* chunks, const int64_t* rbase, int64_t n, const uint32_t* vals,
+                              const PbChunk* chunks, const int64_t* rbase, int64_t n, const void* vals, bool narrow,
                               const uint16_t* dstl, uint2* vm, uint32_t* improved, const LoopState* loop, hipStream_t s);
 
 // In-place exclusive scan of P[0..count) with P[count] = total; `blocks`

@@ -283,14 +283,19 @@ __global__ __launch_bounds__(kWG) void k_pr_scatter_mp(const OffT* __restrict__ 
 // With the blocked form's bin kinds, a bin without in-edges has sum zero
 // (its mailboxes are not read) and only split bins' mailboxes are reset
 // (the fold stores every mailbox of a one-item bin).
+// keep_empty: the messages of vertices in bins without in-edges are already
+// in contrib and stay as they are (such a vertex's rank is the teleport
+// term at every update, so its message is the same from the first update
+// on): the update skips those bins (a workgroup's vertices share one bin).
 template <class OffT, class M, class S>
 __global__ __launch_bounds__(kWG) void k_pr_apply(const OffT* __restrict__ off, int64_t n, double teleport,
                                                   double damping, int64_t source, S* __restrict__ mb,
                                                   M* __restrict__ contrib, float* __restrict__ out, int last,
-                                                  const uint8_t* __restrict__ kinds) {
+                                                  const uint8_t* __restrict__ kinds, int keep_empty) {
   const int64_t v = gid();
   if (v >= n) return;
   const int kind = kinds ? kinds[v >> kPbDstShift] : kBinSplit;
+  if (keep_empty && kind == kBinEmpty) return;
   const S x = kind != kBinEmpty ? mb[v] : S(0);
   const double tele = source >= 0 ? (v == source ? teleport : 0.0) : teleport;
   double r;
@@ -739,7 +744,7 @@ template <class M, class S>
 hipError_t pr_launch_all(int what, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
                          const int32_t* tile_v, int64_t tile, int64_t ntiles, double a, double b, int64_t source,
                          void* contrib, void* mb, float* out, bool last, hipStream_t s,
-                         const uint8_t* kinds = nullptr, bool hub = false) {
+                         const uint8_t* kinds = nullptr, bool hub = false, bool keep_empty = false) {
   M* c = static_cast<M*>(contrib);
   S* mbx = static_cast<S*>(mb);
   const int nhub = hub_slots(n, sizeof(S), hub);
@@ -776,10 +781,10 @@ hipError_t pr_launch_all(int what, const void* off, bool off64, const int32_t* d
     default:  // apply; a = teleport, b = damping
       if (off64)
         hipLaunchKernelGGL((k_pr_apply<int64_t, M, S>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int64_t*)off, n,
-                           a, b, source, mbx, c, out, (int)last, kinds);
+                           a, b, source, mbx, c, out, (int)last, kinds, (int)keep_empty);
       else
         hipLaunchKernelGGL((k_pr_apply<int32_t, M, S>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int32_t*)off, n,
-                           a, b, source, mbx, c, out, (int)last, kinds);
+                           a, b, source, mbx, c, out, (int)last, kinds, (int)keep_empty);
   }
   return hipGetLastError();
 }
@@ -787,18 +792,18 @@ hipError_t pr_launch_all(int what, const void* off, bool off64, const int32_t* d
 inline hipError_t pr_launch(int mode, int what, const void* off, bool off64, const int32_t* dst, int64_t n, int64_t m,
                             const int32_t* tile_v, int64_t tile, int64_t ntiles, double a, double b, int64_t source,
                             void* contrib, void* mb, float* out, bool last, hipStream_t s,
-                            const uint8_t* kinds = nullptr, bool hub = false) {
+                            const uint8_t* kinds = nullptr, bool hub = false, bool keep_empty = false) {
   switch (mode) {
     case kRankFixed:
       return pr_launch_all<unsigned long long, unsigned long long>(what, off, off64, dst, n, m, tile_v, tile, ntiles,
                                                                    a, b, source, contrib, mb, out, last, s, kinds,
-                                                                   hub);
+                                                                   hub, keep_empty);
     case kRankF32Msg:
       return pr_launch_all<float, unsigned long long>(what, off, off64, dst, n, m, tile_v, tile, ntiles, a, b, source,
-                                                      contrib, mb, out, last, s, kinds, hub);
+                                                      contrib, mb, out, last, s, kinds, hub, keep_empty);
     case kRankF32:
       return pr_launch_all<float, float>(what, off, off64, dst, n, m, tile_v, tile, ntiles, a, b, source, contrib, mb,
-                                         out, last, s, kinds, hub);
+                                         out, last, s, kinds, hub, keep_empty);
   }
   return hipErrorInvalidValue;
 }
@@ -825,9 +830,9 @@ hipError_t launch_pr_scatter_mp(int mode, const void* off, bool off64, const int
 
 hipError_t launch_pr_apply(int mode, const void* off, bool off64, int64_t n, double teleport, double damping,
                            int64_t source, void* mb, void* contrib, float* out, bool last, hipStream_t s,
-                           const uint8_t* kinds) {
+                           const uint8_t* kinds, bool keep_empty) {
   return pr_launch(mode, 3, off, off64, nullptr, n, 0, nullptr, 0, 0, teleport, damping, source, contrib, mb, out,
-                   last, s, kinds);
+                   last, s, kinds, false, keep_empty && kinds && !last);
 }
 
 hipError_t launch_min_init(int kind, int64_t n, int64_t source, const int32_t* ids, uint2* vm, hipStream_t s) {

@@ -291,6 +291,26 @@ def test_blocked_min_programs_bit_exact(device, relabel):
     check_min(big, make(big, relabel=relabel), "sssp", source=0, schedule="blocked")
 
 
+def test_blocked_sssp_slot_width_switch(device):
+    """Single-source SSSP's blocked supersteps carry messages in 2-byte slots
+    while every message of the superstep is bounded below 0xFFFF ((superstep
+    + 1) times the largest weight) and in 4-byte slots after: a weighted path
+    whose distances pass 65,535 switches width in mid-run; an R-MAT graph
+    with weights up to 30,000 switches after two supersteps; one with
+    weights beyond 65,535 never narrows.  Bit-exact against the oracle."""
+    print("case blocked SSSP slot width switch", flush=True)
+    n = 300
+    path = rmatgen.raw_csr(n, np.arange(n - 1), np.arange(1, n), np.full(n - 1, 997, np.uint32))
+    check_min(path, make(path), "sssp", source=0, schedule="blocked")
+    check_min(path, make(path, relabel=False), "sssp", source=5, schedule="blocked")
+    d = rmatgen.rmat(16, 8, seed=41, weighted=True)
+    rng = np.random.default_rng(41)
+    for top in (30000, 1 << 20):
+        c = rmatgen.Csr(d.n, d.m, d.off, d.dst, rng.integers(1, top, d.m, dtype=np.uint32))
+        check_min(c, make(c), "sssp", source=0, schedule="blocked")
+        check_min(c, make(c), "sssp", source=0)  # AUTO: push and pull at this size
+
+
 def test_auto_takes_the_blocked_form_for_dense_min_supersteps(device):
     print("case auto blocked min s20", flush=True)
     d = rmatgen.rmat(20, 8, seed=15, weighted=True)
