@@ -450,7 +450,7 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
                              cnt.as<unsigned long long>(), srcl_csr, g->pb_srcl.as<uint16_t>(),
                              g->pb_dstl.as<uint16_t>(), g->w, g->w ? g->pb_w.p : nullptr, wbytes, s));
   // run tables (non-empty buckets per bin) and fold items: at least about
-  // 4096 items in all, at most 64 Ki edges each (a bin of fewer edges is one
+  // 4096 items in all, at most 128 Ki edges each (a bin of fewer edges is one
   // item and stores its mailboxes instead of adding them)
   const int64_t fcap = std::min<int64_t>(vc::kPbMaxItemPositions, std::max<int64_t>(4096, m / 4096));
   VC_TRY(nitems.ensure((size_t)(bins + 1) * 8));

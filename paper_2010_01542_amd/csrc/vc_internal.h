@@ -281,7 +281,7 @@ hipError_t launch_combine(int op, const void* off, bool off64, const int32_t* ds
 // buckets in tile-major order: bucket (t, b) = t * bins + b.
 constexpr int kPbDstShift = 12;
 constexpr int64_t kPbMaxBuckets = 1ll << 28;
-constexpr int64_t kPbMaxItemPositions = 1ll << 16;  // positions per fold item (its chunk descriptors fit LDS)
+constexpr int64_t kPbMaxItemPositions = 1ll << 17;  // positions per fold item (its chunk descriptors fit LDS)
 // Destination bins of the blocked form: without in-edges (no fold item; the
 // bin's mailboxes stay zero), one fold item (the fold stores every mailbox
 // of the bin, zeros included), or split over several items (the fold adds
