@@ -61,3 +61,19 @@ def test_multi_source_rejects_bad_arguments(device):
         g.run_multi_source([4])
     with pytest.raises(VcError):
         g.run_multi_source(np.zeros(257, np.uint32))
+
+
+@pytest.mark.parametrize("wmax", [20000, 40000, 65535, 1000000])
+def test_multi_source_large_weights(device, wmax):
+    """Weights up to wmax (the largest exactly wmax): distances well above
+    2^16 come out exact in every column."""
+    print(f"case multi-source large weights wmax={wmax}", flush=True)
+    d = rmatgen.rmat(11, 12, seed=9, weighted=True)
+    w = (d.w.astype(np.uint64) * 2654435761 % wmax + 1).astype(np.uint32)
+    w[np.argmax(d.outdeg > 0)] = wmax
+    c = rmatgen.Csr(d.n, d.m, d.off, d.dst, w)
+    sources = np.random.default_rng(wmax).integers(0, c.n, 100)
+    got, st = check_columns(c, make(c), sources)
+    assert st.supersteps > 4
+    if wmax >= 40000:
+        assert got[got != 0xFFFFFFFF].max() > 0xFFFF
