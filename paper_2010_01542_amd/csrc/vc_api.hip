@@ -386,8 +386,11 @@ int rank_schedule(vc_graph g, const vc_params& p, bool fx) {
 // Builds the propagation-blocking layout once per graph, on the device:
 // first edge of every source tile, every edge's source offset in its tile,
 // bucket counts (LDS histograms per chunk of edges), their exclusive scan
-// (bucket starts), the slots (each chunk reserves its share of a bucket with
-// one atomic), the bin-major run tables and the fold items (each bin's runs
+// (bucket starts), the slots (placed in two levels: by groups of 128 bins,
+// then, per piece of a group sorted in LDS, into the buckets; a device
+// whose LDS cannot hold that takes the one-level placement, each chunk
+// reserving its share of a bucket with one atomic), the bin-major run
+// tables and the fold items (each bin's runs
 // cut into pieces of about the same number of edges, so that a bin of hubs
 // spreads over many workgroups).  The spread items (each tile's slot range
 // cut into pieces) are made on the host from the tile starts.
@@ -446,9 +449,34 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
   }
   VC_TRY(vc::launch_exclusive_scan(cnt.as<int64_t>(), nb, blocks.as<int64_t>(), s));
   VC_TRY(hipMemcpyAsync(starts_d.p, cnt.p, (size_t)(nb + 1) * 8, hipMemcpyDeviceToDevice, s));
-  VC_TRY(vc::launch_pb_build(true, te_d.as<int64_t>(), tiles, g->dst, m, chunk, bins, pass_bins,
-                             cnt.as<unsigned long long>(), srcl_csr, g->pb_srcl.as<uint16_t>(),
-                             g->pb_dstl.as<uint16_t>(), g->w, g->w ? g->pb_w.p : nullptr, wbytes, s));
+  const int64_t groups = vc::pb_groups(bins), segs = tiles * groups;
+  if ((size_t)groups * 12 <= g->max_lds && vc::pb_place_lds(g->w != nullptr, wbytes) <= g->max_lds) {
+    // two-level placement: by groups of bins into transient arrays, then
+    // into the buckets (whole lines written instead of scattered bytes)
+    DevBuf gcur, poff, tdst, tsrcl, tw;
+    VC_TRY(gcur.ensure((size_t)segs * 8));
+    VC_TRY(poff.ensure((size_t)(segs + 1) * 8));
+    VC_TRY(vc::launch_pb_group_starts(starts_d.as<int64_t>(), tiles, bins, gcur.as<unsigned long long>(),
+                                      poff.as<int64_t>(), s));
+    VC_TRY(vc::launch_exclusive_scan(poff.as<int64_t>(), segs, blocks.as<int64_t>(), s));
+    int64_t npieces = 0;
+    VC_TRY(hipMemcpyAsync(&npieces, poff.as<int64_t>() + segs, 8, hipMemcpyDeviceToHost, s));
+    VC_TRY(hipStreamSynchronize(s));
+    VC_TRY(tdst.ensure((size_t)m * 4 + 4));
+    VC_TRY(tsrcl.ensure((size_t)m * 2 + 4));
+    if (g->w) VC_TRY(tw.ensure((size_t)m * wbytes + 4));
+    VC_TRY(vc::launch_pb_group(te_d.as<int64_t>(), tiles, g->dst, m, chunk, bins, gcur.as<unsigned long long>(),
+                               srcl_csr, g->w, wbytes, tdst.as<int32_t>(), tsrcl.as<uint16_t>(), tw.p, s));
+    VC_TRY(vc::launch_pb_place(poff.as<int64_t>(), tiles, bins, npieces, starts_d.as<int64_t>(),
+                               cnt.as<unsigned long long>(), tdst.as<int32_t>(), tsrcl.as<uint16_t>(), tw.p, wbytes,
+                               g->w != nullptr, g->pb_srcl.as<uint16_t>(), g->pb_dstl.as<uint16_t>(),
+                               g->w ? g->pb_w.p : nullptr, s));
+    VC_TRY(hipStreamSynchronize(s));
+  } else {
+    VC_TRY(vc::launch_pb_build(true, te_d.as<int64_t>(), tiles, g->dst, m, chunk, bins, pass_bins,
+                               cnt.as<unsigned long long>(), srcl_csr, g->pb_srcl.as<uint16_t>(),
+                               g->pb_dstl.as<uint16_t>(), g->w, g->w ? g->pb_w.p : nullptr, wbytes, s));
+  }
   // run tables (non-empty buckets per bin) and fold items: at least about
   // 4096 items in all, at most 128 Ki edges each (a bin of fewer edges is one
   // item and stores its mailboxes instead of adding them)

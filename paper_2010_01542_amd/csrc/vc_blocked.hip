@@ -191,6 +191,168 @@ __global__ __launch_bounds__(kBuildWG) void k_pb_build(const int64_t* __restrict
   }
 }
 
+// Two-level placement.  Placing each edge straight into its bucket writes
+// a few bytes at a time into runs of about 16 edges spread over thousands
+// of open lines per workgroup (8x the bytes placed reach HBM).  Instead:
+// level 1 sorts each tile's edges into groups of kPbGroupBins bins, whose
+// slot ranges (tile-major, bins in order) are contiguous, writing each
+// edge's target, source offset and weight at a free position of its group
+// (runs of thousands of edges per workgroup); level 2 takes each group in
+// pieces of up to kPbPiece edges and places them into their buckets.
+constexpr int kPbGroupShift = 7;
+constexpr int kPbGroupBins = 1 << kPbGroupShift;
+constexpr int64_t kPbPiece = 8192;
+
+// gcur[t * groups + g] = first slot of bucket (t, g * kPbGroupBins).
+__global__ __launch_bounds__(kWG) void k_pb_group_starts(const int64_t* __restrict__ starts, int64_t tiles,
+                                                         int64_t bins, int64_t groups,
+                                                         unsigned long long* __restrict__ gcur,
+                                                         int64_t* __restrict__ pieces) {
+  const int64_t i = gid();
+  if (i >= tiles * groups) return;
+  const int64_t t = i / groups, g = i - t * groups;
+  const int64_t b1 = (g + 1) * kPbGroupBins < bins ? (g + 1) * kPbGroupBins : bins;
+  const int64_t s0 = starts[t * bins + g * kPbGroupBins], s1 = starts[t * bins + b1];
+  gcur[i] = (unsigned long long)s0;
+  pieces[i] = (s1 - s0 + kPbPiece - 1) / kPbPiece;
+}
+
+// Level 1: per workgroup, CSR edges [c0, c1) split by tile; LDS histogram
+// of groups, one global atomic per (tile, group) to reserve, then each
+// edge's record at its group position.
+__global__ __launch_bounds__(kBuildWG) void k_pb_group(const int64_t* __restrict__ te, int64_t tiles,
+                                                       const int32_t* __restrict__ dst, int64_t m, int64_t chunk,
+                                                       int64_t groups, unsigned long long* __restrict__ gcur,
+                                                       const uint16_t* __restrict__ srcl_csr,
+                                                       const uint32_t* __restrict__ w, int wbytes,
+                                                       int32_t* __restrict__ tdst, uint16_t* __restrict__ tsrcl,
+                                                       void* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  unsigned long long* base = reinterpret_cast<unsigned long long*>(smem);  // groups
+  uint32_t* hist = reinterpret_cast<uint32_t*>(base + groups);             // groups
+  const int64_t c0 = (int64_t)blockIdx.x * chunk;
+  const int64_t c1 = (c0 + chunk < m) ? c0 + chunk : m;
+  for (int64_t t = tile_of(te, tiles, c0); t < tiles && te[t] < c1; ++t) {
+    const int64_t e0 = te[t] > c0 ? te[t] : c0;
+    const int64_t e1 = te[t + 1] < c1 ? te[t + 1] : c1;
+    if (e0 >= e1) continue;
+    for (int64_t i = threadIdx.x; i < groups; i += kBuildWG) hist[i] = 0u;
+    __syncthreads();
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kBuildWG)
+      atomicAdd(&hist[dst[e] >> (kPbDstShift + kPbGroupShift)], 1u);
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < groups; i += kBuildWG) {
+      const uint32_t h = hist[i];
+      base[i] = h ? atomicAdd(&gcur[t * groups + i], (unsigned long long)h) : 0ull;
+      hist[i] = 0u;
+    }
+    __syncthreads();
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kBuildWG) {
+      const int32_t v = dst[e];
+      const int g = v >> (kPbDstShift + kPbGroupShift);
+      const int64_t k = (int64_t)base[g] + (int64_t)atomicAdd(&hist[g], 1u);
+      tdst[k] = v;
+      tsrcl[k] = srcl_csr[e];
+      if (w) {
+        if (wbytes == 1)
+          static_cast<uint8_t*>(tw)[k] = (uint8_t)w[e];
+        else
+          static_cast<uint32_t*>(tw)[k] = w[e];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Level 2: workgroup j takes piece j (poff: exclusive scan of the pieces
+// per (tile, group), tiles * groups + 1 entries) and places its edges in
+// their buckets.  The piece is sorted by bin in LDS (histogram, scan,
+// scatter into LDS), then written out in slot order, so consecutive lanes
+// write consecutive slots.  A piece that is its group's only one owns the
+// group's whole slot range (bucket starts from `starts`); otherwise each
+// bucket's share is reserved with one global atomic on its cursor in cnt.
+__global__ __launch_bounds__(kBuildWG) void k_pb_place(const int64_t* __restrict__ poff, int64_t segs,
+                                                       int64_t groups, int64_t bins,
+                                                       const int64_t* __restrict__ starts,
+                                                       unsigned long long* __restrict__ cnt,
+                                                       const int32_t* __restrict__ tdst,
+                                                       const uint16_t* __restrict__ tsrcl, const void* __restrict__ tw,
+                                                       int wbytes, bool weighted, uint16_t* __restrict__ srcl,
+                                                       uint16_t* __restrict__ dstl, void* __restrict__ wslot) {
+  __shared__ unsigned long long base[kPbGroupBins];  // first slot of each bin's share
+  __shared__ uint32_t hist[kPbGroupBins], lpos[kPbGroupBins + 1];
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint16_t* s_srcl = reinterpret_cast<uint16_t*>(smem);  // kPbPiece each, in bin order
+  uint16_t* s_dstl = s_srcl + kPbPiece;
+  unsigned char* s_w = reinterpret_cast<unsigned char*>(s_dstl + kPbPiece);  // kPbPiece * wbytes
+  const int64_t j = blockIdx.x;
+  int64_t lo = 0, hi = segs - 1;  // last segment with poff <= j
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (poff[mid] <= j)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int64_t sg = lo, t = sg / groups, g = sg - t * groups;
+  const int64_t b0 = g * kPbGroupBins, b1 = b0 + kPbGroupBins < bins ? b0 + kPbGroupBins : bins;
+  const int64_t s1 = starts[t * bins + b1];
+  const int64_t a = starts[t * bins + b0] + (j - poff[sg]) * kPbPiece;
+  const int64_t z = a + kPbPiece < s1 ? a + kPbPiece : s1;
+  const int cnt_here = (int)(z - a);
+  for (int i = threadIdx.x; i < kPbGroupBins; i += kBuildWG) hist[i] = 0u;
+  __syncthreads();
+  for (int64_t k = a + threadIdx.x; k < z; k += kBuildWG) atomicAdd(&hist[(tdst[k] >> kPbDstShift) - b0], 1u);
+  __syncthreads();
+  const bool alone = poff[sg + 1] - poff[sg] == 1;  // the group's only piece: its buckets are all ours
+  if (threadIdx.x == 0) {  // exclusive scan of the piece's bin counts (128 entries)
+    uint32_t acc = 0;
+    for (int i = 0; i < kPbGroupBins; ++i) {
+      lpos[i] = acc;
+      acc += hist[i];
+    }
+    lpos[kPbGroupBins] = acc;
+  }
+  for (int i = threadIdx.x; i < kPbGroupBins; i += kBuildWG) {
+    const uint32_t h = hist[i];
+    if (alone)
+      base[i] = b0 + i < bins ? (unsigned long long)starts[t * bins + b0 + i] : 0ull;
+    else
+      base[i] = h ? atomicAdd(&cnt[t * bins + b0 + i], (unsigned long long)h) : 0ull;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kPbGroupBins; i += kBuildWG) hist[i] = lpos[i];  // LDS cursors
+  __syncthreads();
+  for (int64_t k = a + threadIdx.x; k < z; k += kBuildWG) {
+    const int32_t v = tdst[k];
+    const int i = (v >> kPbDstShift) - (int)b0;
+    const uint32_t p = atomicAdd(&hist[i], 1u);
+    s_srcl[p] = tsrcl[k];
+    s_dstl[p] = (uint16_t)(v & ((1 << kPbDstShift) - 1));
+    if (weighted) {
+      if (wbytes == 1)
+        s_w[p] = static_cast<const uint8_t*>(tw)[k];
+      else
+        reinterpret_cast<uint32_t*>(s_w)[p] = static_cast<const uint32_t*>(tw)[k];
+    }
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < cnt_here; p += kBuildWG) {
+    int b = 0;  // bin of sorted position p: last b with lpos[b] <= p
+    for (int step = kPbGroupBins / 2; step > 0; step >>= 1)
+      if (lpos[b + step] <= (uint32_t)p) b += step;
+    const int64_t q = (int64_t)base[b] + (int64_t)(p - (int)lpos[b]);
+    srcl[q] = s_srcl[p];
+    dstl[q] = s_dstl[p];
+    if (weighted) {
+      if (wbytes == 1)
+        static_cast<uint8_t*>(wslot)[q] = s_w[p];
+      else
+        static_cast<uint32_t*>(wslot)[q] = reinterpret_cast<const uint32_t*>(s_w)[p];
+    }
+  }
+}
+
 // Run tables, one thread per bin b; runs are the non-empty buckets (t, b)
 // in tile order.  Count pass: number of runs, edges of the bin (btotal)
 // and fold items of up to fcap positions.  Fill pass: for run i of bin b
@@ -608,6 +770,43 @@ hipError_t launch_pb_build(bool place, const int64_t* te, int64_t tiles, const i
   else
     hipLaunchKernelGGL(k_pb_build<false>, dim3((unsigned)grid), dim3(kBuildWG), lds, s, te, tiles, dst, m, chunk, bins,
                        pass_bins, cnt, srcl_csr, srcl, dstl, nullptr, nullptr, 4);
+  return hipGetLastError();
+}
+
+int64_t pb_groups(int64_t bins) { return (bins + kPbGroupBins - 1) / kPbGroupBins; }
+size_t pb_place_lds(bool weighted, int wbytes) {
+  return (size_t)kPbPiece * (4 + (weighted ? (size_t)wbytes : 0)) + 2048;  // + the static part
+}
+
+hipError_t launch_pb_group_starts(const int64_t* starts, int64_t tiles, int64_t bins, unsigned long long* gcur,
+                                  int64_t* pieces, hipStream_t s) {
+  const int64_t groups = pb_groups(bins);
+  if (tiles * groups <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pb_group_starts, dim3(grid_for(tiles * groups)), dim3(kWG), 0, s, starts, tiles, bins, groups,
+                     gcur, pieces);
+  return hipGetLastError();
+}
+
+hipError_t launch_pb_group(const int64_t* te, int64_t tiles, const int32_t* dst, int64_t m, int64_t chunk,
+                           int64_t bins, unsigned long long* gcur, const uint16_t* srcl_csr, const uint32_t* w,
+                           int wbytes, int32_t* tdst, uint16_t* tsrcl, void* tw, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  if (chunk < 1) return hipErrorInvalidValue;
+  const int64_t groups = pb_groups(bins);
+  const int64_t grid = (m + chunk - 1) / chunk;
+  hipLaunchKernelGGL(k_pb_group, dim3((unsigned)grid), dim3(kBuildWG), (size_t)groups * 12, s, te, tiles, dst, m,
+                     chunk, groups, gcur, srcl_csr, w, wbytes, tdst, tsrcl, tw);
+  return hipGetLastError();
+}
+
+hipError_t launch_pb_place(const int64_t* poff, int64_t tiles, int64_t bins, int64_t npieces, const int64_t* starts,
+                           unsigned long long* cnt, const int32_t* tdst, const uint16_t* tsrcl, const void* tw,
+                           int wbytes, bool weighted, uint16_t* srcl, uint16_t* dstl, void* wslot, hipStream_t s) {
+  if (npieces <= 0) return hipSuccess;
+  const int64_t groups = pb_groups(bins);
+  const size_t lds = pb_place_lds(weighted, wbytes) - 2048;
+  hipLaunchKernelGGL(k_pb_place, dim3((unsigned)npieces), dim3(kBuildWG), lds, s, poff, tiles * groups, groups, bins,
+                     starts, cnt, tdst, tsrcl, tw, wbytes, weighted, srcl, dstl, wslot);
   return hipGetLastError();
 }
 

@@ -327,6 +327,25 @@ hipError_t launch_pb_build(bool place, const int64_t* te, int64_t tiles, const i
                            int64_t bins, int pass_bins, unsigned long long* cnt, const uint16_t* srcl_csr,
                            uint16_t* srcl, uint16_t* dstl, const uint32_t* w, void* wslot, int wbytes,
                            hipStream_t s);
+// Two-level placement (replaces launch_pb_build(true, ...) when the group
+// histogram fits LDS: pb_groups(bins) * 12 bytes).  cnt holds the bucket
+// starts (consumed as cursors) and starts a copy of them.  group_starts:
+// gcur[t * groups + g] = first slot of group g of tile t, pieces[...] =
+// ceil(group edges / 8192).  group: each edge's target, source offset and
+// weight (wbytes each, when w is not NULL) at a free position of its group
+// in tdst / tsrcl / tw.  place: with poff the exclusive scan of pieces
+// (npieces in all), every edge into its bucket (srcl, dstl, wslot).
+int64_t pb_groups(int64_t bins);
+// LDS bytes a placement workgroup needs.
+size_t pb_place_lds(bool weighted, int wbytes);
+hipError_t launch_pb_group_starts(const int64_t* starts, int64_t tiles, int64_t bins, unsigned long long* gcur,
+                                  int64_t* pieces, hipStream_t s);
+hipError_t launch_pb_group(const int64_t* te, int64_t tiles, const int32_t* dst, int64_t m, int64_t chunk,
+                           int64_t bins, unsigned long long* gcur, const uint16_t* srcl_csr, const uint32_t* w,
+                           int wbytes, int32_t* tdst, uint16_t* tsrcl, void* tw, hipStream_t s);
+hipError_t launch_pb_place(const int64_t* poff, int64_t tiles, int64_t bins, int64_t npieces, const int64_t* starts,
+                           unsigned long long* cnt, const int32_t* tdst, const uint16_t* tsrcl, const void* tw,
+                           int wbytes, bool weighted, uint16_t* srcl, uint16_t* dstl, void* wslot, hipStream_t s);
 // *out = max(*out, largest of the m weights w).
 hipError_t launch_pb_wmax(const uint32_t* w, int64_t m, uint32_t* out, hipStream_t s);
 // Run tables from the bucket starts (runs = non-empty buckets of a bin, in
