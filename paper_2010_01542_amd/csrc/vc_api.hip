@@ -371,6 +371,19 @@ size_t pb_layout_bytes(vc_graph g) {  // the shared, read-only part
          (m / 16384 + tiles + 2) * sizeof(vc::PbSpreadItem);
 }
 
+// Device bytes the layout build holds only while it runs (the source
+// offsets in CSR order, bucket counts and starts, scan scratch, and the
+// two-level placement's group cursors and transient records), an upper
+// bound: weights are counted at 4 bytes.
+size_t pb_build_transient_bytes(vc_graph g) {
+  const int shift = vc::pb_src_shift(g->max_lds);
+  if (shift == 0) return 0;
+  const size_t bins = (size_t)vc::pb_bins(g->n), tiles = (size_t)vc::pb_tiles(g->n, shift), m = (size_t)g->m;
+  const size_t nb = bins * tiles, segs = (size_t)vc::pb_groups((int64_t)bins) * tiles;
+  return m * 2 + (nb + 1) * 16 + (size_t)vc::scan_scratch_entries((int64_t)nb) * 8 + (segs + 1) * 16 +
+         m * (g->w ? 10 : 6);
+}
+
 // The schedule of a PageRank / PPR run.  AUTO takes the blocked schedule for
 // fixed-point runs on graphs of 2^20 vertices and more, where the message
 // array no longer stays in the caches and the pull form's gathers go to
@@ -1511,7 +1524,7 @@ vc_status vc_graph_footprint(vc_graph g, vc_program program, size_t* bytes_held,
     // the transpose too (a captured loop pulls)
     size_t pb_need = 0;
     const vc_graph owner = g->is_view ? g->base : g;
-    const size_t pb_more = (owner->pb.ready ? 0 : pb_layout_bytes(g)) +
+    const size_t pb_more = (owner->pb.ready ? 0 : pb_layout_bytes(g) + pb_build_transient_bytes(g)) +
                            (g->pb_vals.bytes >= (size_t)g->m * 8 ? 0 : (size_t)g->m * 8 + 8);
     if (program == VC_PAGERANK || program == VC_PPR) {
       vc_params dp;
