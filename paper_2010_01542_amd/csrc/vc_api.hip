@@ -396,6 +396,26 @@ int rank_schedule(vc_graph g, const vc_params& p, bool fx) {
   return VC_SCHED_PULL;
 }
 
+// Largest edge weight of g (1 when unweighted), computed once per graph.
+vc_status weight_max(vc_graph g, hipStream_t s, uint32_t* out) {
+  if (!g->w || g->m == 0) {
+    *out = 1;
+    return VC_OK;
+  }
+  if (!g->wmax) {
+    DevBuf wmax;
+    VC_TRY(wmax.ensure(4));
+    VC_TRY(vc::launch_fill_u32(wmax.as<uint32_t>(), 1, 0u, s));
+    VC_TRY(vc::launch_pb_wmax(g->w, g->m, wmax.as<uint32_t>(), s));
+    uint32_t mx = 0;
+    VC_TRY(hipMemcpyAsync(&mx, wmax.p, 4, hipMemcpyDeviceToHost, s));
+    VC_TRY(hipStreamSynchronize(s));
+    g->wmax = mx > 0 ? mx : 1;
+  }
+  *out = g->wmax;
+  return VC_OK;
+}
+
 // Builds the propagation-blocking layout once per graph, on the device:
 // first edge of every source tile, every edge's source offset in its tile,
 // bucket counts (LDS histograms per chunk of edges), their exclusive scan
@@ -449,15 +469,9 @@ vc_status ensure_pb(vc_graph g, hipStream_t s) {
   int wbytes = 4;
   uint32_t wmax_all = 1;
   if (g->w) {
-    DevBuf wmax;
-    VC_TRY(wmax.ensure(4));
-    VC_TRY(vc::launch_fill_u32(wmax.as<uint32_t>(), 1, 0u, s));
-    VC_TRY(vc::launch_pb_wmax(g->w, m, wmax.as<uint32_t>(), s));
-    uint32_t mx = 0;
-    VC_TRY(hipMemcpyAsync(&mx, wmax.p, 4, hipMemcpyDeviceToHost, s));
-    VC_TRY(hipStreamSynchronize(s));
-    wbytes = mx <= 255 ? 1 : 4;
-    wmax_all = mx;
+    st = weight_max(g, s, &wmax_all);
+    if (st != VC_OK) return st;
+    wbytes = wmax_all <= 255 ? 1 : 4;
     VC_TRY(g->pb_w.ensure((size_t)m * wbytes + 4));
   }
   VC_TRY(vc::launch_exclusive_scan(cnt.as<int64_t>(), nb, blocks.as<int64_t>(), s));
@@ -1811,9 +1825,13 @@ vc_status vc_run_multi_source(vc_graph g, const uint32_t* sources, int32_t k, co
   const int C = vc::ms_chunks(k);
   const int64_t nwords = (n + 31) / 32;
   VC_TRY(g->ms_src.ensure((size_t)k * 4));
+  // the pull reads a 2-byte copy of the distances while they cannot reach
+  // 0xFFFF: after superstep s they are at most s times the largest weight
+  uint32_t wmax = 1;
   {
     vc_status st = ensure_csc(g, s);
-    if (st == VC_OK) st = vc::ms_reset(g->ms, g, C, s);
+    if (st == VC_OK) st = weight_max(g, s, &wmax);
+    if (st == VC_OK) st = vc::ms_reset(g->ms, g, C, s, wmax < 0xFFFFu);
     if (st != VC_OK) return st;
   }
   vc::MsState& ms = g->ms;
@@ -1821,7 +1839,8 @@ vc_status vc_run_multi_source(vc_graph g, const uint32_t* sources, int32_t k, co
   VC_TRY(vc::launch_zero_counters(ctr, s));
   VC_TRY(hipMemcpyAsync(g->ms_src.p, sources, (size_t)k * 4, hipMemcpyHostToDevice, s));
   VC_TRY(vc::launch_ms_seed(g->ms_src.as<int32_t>(), g->relabeled ? g->perm_p : nullptr, k, n, ms.D.as<uint32_t>(),
-                            ms.A[0].as<unsigned long long>(), ms.bits.as<uint32_t>(), s));
+                            ms.shadow ? ms.D16.as<uint16_t>() : nullptr, ms.A[0].as<unsigned long long>(),
+                            ms.bits.as<uint32_t>(), s));
   VC_TRY(vc::launch_ms_count(g->off, g->off64, n, ms.bits.as<uint32_t>(), ctr, s));
   VC_TRY(vc::launch_fill_u32(ms.bits.as<uint32_t>(), nwords, 0u, s));
   VC_TRY(hipMemcpyAsync(ms.host, ctr, sizeof(vc::Counters), hipMemcpyDeviceToHost, s));
@@ -1839,6 +1858,7 @@ vc_status vc_run_multi_source(vc_graph g, const uint32_t* sources, int32_t k, co
       supersteps = (int32_t)(step + 1);
       break;
     }
+    if (ms.shadow && (double)(step + 1) * (double)wmax >= 65535.0) ms.shadow = false;
     const bool timed = rec.want_time(step);
     if (timed) VC_TRY(hipEventRecord(g->events[0], s));
     bool pushed = false;

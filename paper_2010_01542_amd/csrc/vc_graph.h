@@ -87,6 +87,8 @@ struct MsState {
   int64_t n = 0, m = 0;
   int cs = 0;
   DevBuf D, MB, A[2], bits, list, P, scan_blocks, push_tiles, ctr;
+  DevBuf D16;                        // 2-byte copy of D read by the pull (while `shadow`)
+  bool shadow = false;
   DevBuf pull_tiles[4];              // pull partitions for 1..4 chunks
   int64_t pull_ntiles[4] = {0, 0, 0, 0};
   int dirty[2] = {0, 0};             // chunks of A[b] that may hold set bits
@@ -109,8 +111,11 @@ constexpr int64_t kMsPushTile = 256;
 constexpr double kMsPullFraction = 0.05;
 
 // Allocates st for (g, cs) and resets every lane to unreached with no
-// active vertex.  Needs g's transpose.
-vc_status ms_reset(MsState& st, vc_graph g, int cs, hipStream_t s);
+// active vertex.  Needs g's transpose.  shadow: also keep a 2-byte copy of
+// the values (0xFFFF: unreached) for the pull to read; valid while every
+// distance stays below 0xFFFF, and the caller clears st.shadow before the
+// first superstep where one might not.
+vc_status ms_reset(MsState& st, vc_graph g, int cs, hipStream_t s, bool shadow = false);
 // One superstep over the first ceff chunks (seeds already in A[cur]): push
 // from a compacted broadcast list when force_pull is false and the active
 // vertices' out-edges (next_edges estimates them; counted exactly before a
@@ -186,6 +191,7 @@ struct vc_graph_s {
       pb_fold, pb_kinds;
   vc::PbShared pb;
   vc::DevBuf pb_vals;
+  uint32_t wmax = 0;        // largest edge weight once computed (0: not yet)
   std::mutex pb_mu;         // base: serialises the layout build between views
   vc_graph base = nullptr;  // views: the graph they share arrays with
   vc::DevBuf ms_src;

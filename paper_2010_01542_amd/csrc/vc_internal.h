@@ -219,7 +219,8 @@ int ms_chunks(int k);
 struct LaneMask {
   unsigned long long bits[4];
 };
-hipError_t launch_ms_seed(const int32_t* src, const int32_t* perm, int k_real, int64_t n, uint32_t* D,
+// D16 (may be NULL): the values' 2-byte copy, seeded too.
+hipError_t launch_ms_seed(const int32_t* src, const int32_t* perm, int k_real, int64_t n, uint32_t* D, uint16_t* D16,
                           unsigned long long* A, uint32_t* bits, hipStream_t s);
 hipError_t launch_ms_count(const void* off, bool off64, int64_t n, const uint32_t* bits, Counters* ctr,
                            hipStream_t s);

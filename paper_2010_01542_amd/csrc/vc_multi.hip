@@ -32,11 +32,13 @@ __device__ __forceinline__ int64_t row(int c, int64_t n, int64_t v) { return ((i
 
 // Source k (internal id src[k]) starts at distance 0 with lane k active.
 __global__ void k_ms_seed(const int32_t* __restrict__ src, const int32_t* __restrict__ perm, int k_real, int64_t n,
-                          uint32_t* __restrict__ D, unsigned long long* __restrict__ A, uint32_t* __restrict__ bits) {
+                          uint32_t* __restrict__ D, uint16_t* __restrict__ D16, unsigned long long* __restrict__ A,
+                          uint32_t* __restrict__ bits) {
   const int k = threadIdx.x + blockIdx.x * blockDim.x;
   if (k >= k_real) return;
   const int64_t x = perm ? (int64_t)perm[src[k]] : (int64_t)src[k];
   D[row(k >> 6, n, x) + (k & 63)] = 0u;
+  if (D16) D16[row(k >> 6, n, x) + (k & 63)] = 0;
   atomicOr(&A[(int64_t)(k >> 6) * n + x], 1ull << (k & 63));
   atomicOr(&bits[x >> 5], 1u << (x & 31));
 }
@@ -117,6 +119,163 @@ __global__ __launch_bounds__(64 * C) void k_ms_pull(const int64_t* __restrict__ 
     }
   }
   flush(x, run);
+}
+
+// 2-byte copies of R consecutive lane values, and 4-byte lane values, as
+// one load each (R = 1, 2, 4).
+template <int R>
+struct LanePart;
+template <>
+struct LanePart<1> {
+  using T16 = uint16_t;
+  using T32 = uint32_t;
+  __device__ __forceinline__ static uint32_t h(const T16& x, int) { return x; }
+  __device__ __forceinline__ static uint32_t w(const T32& x, int) { return x; }
+  __device__ __forceinline__ static void setw(T32& x, int, uint32_t v) { x = v; }
+};
+template <>
+struct LanePart<2> {
+  using T16 = uint32_t;
+  using T32 = uint2;
+  __device__ __forceinline__ static uint32_t h(const T16& x, int j) { return j ? x >> 16 : x & 0xFFFFu; }
+  __device__ __forceinline__ static uint32_t w(const T32& x, int j) { return j ? x.y : x.x; }
+  __device__ __forceinline__ static void setw(T32& x, int j, uint32_t v) {
+    if (j) x.y = v; else x.x = v;
+  }
+};
+template <>
+struct LanePart<4> {
+  using T16 = uint2;
+  using T32 = uint4;
+  __device__ __forceinline__ static uint32_t h(const T16& x, int j) {
+    const uint32_t q = j < 2 ? x.x : x.y;
+    return (j & 1) ? q >> 16 : q & 0xFFFFu;
+  }
+  __device__ __forceinline__ static uint32_t w(const T32& x, int j) {
+    return j == 0 ? x.x : j == 1 ? x.y : j == 2 ? x.z : x.w;
+  }
+  __device__ __forceinline__ static void setw(T32& x, int j, uint32_t v) {
+    if (j == 0) x.x = v; else if (j == 1) x.y = v; else if (j == 2) x.z = v; else x.w = v;
+  }
+};
+
+// Pull from the 2-byte copy D16 of the lane values (every value below
+// 0xFFFF, which stands for unreached; the host uses this form only while
+// no distance can reach it).  One wavefront per tile covers every chunk:
+// chunk r's row is read by lanes r * 64 / R .. (r + 1) * 64 / R - 1, R
+// values each, so one load instruction per in-edge brings the 2-byte rows
+// of all R chunks (R = 4: 8 bytes per lane, 512 bytes per edge).  A row
+// gather is bounded by the load pipeline's bytes per instruction, not by
+// HBM (the 4-byte rows: 11 % L2 hits and ~7 TB/s from the memory side at
+// 69 % texture-addresser busy), so half the bytes per edge is the point.
+// Receivers are compared with, and written to, the 4-byte D and MB as in
+// k_ms_pull.  Chunks at or past ceff are left alone.
+template <int R, bool WEIGHTED>
+__global__ __launch_bounds__(64) void k_ms_pull16(const int64_t* __restrict__ in_off,
+                                                  const int32_t* __restrict__ in_src,
+                                                  const uint32_t* __restrict__ in_w, int64_t n, int64_t m,
+                                                  const int32_t* __restrict__ tile_v, int64_t tile,
+                                                  const uint16_t* __restrict__ D16, const uint32_t* __restrict__ D,
+                                                  uint32_t* __restrict__ MB, uint32_t* __restrict__ improved,
+                                                  LaneMask zero, int ceff) {
+  using P = LanePart<R>;
+  using T16 = typename P::T16;
+  using T32 = typename P::T32;
+  constexpr int L = 64 / R;  // lanes per row
+  constexpr int U = 8;
+  extern __shared__ __align__(16) unsigned char smem[];
+  Tile tl;
+  if (!tile_bounds(tile_v, tile, n, m, &tl)) return;
+  int64_t* s_off = reinterpret_cast<int64_t*>(smem);
+  for (int x = threadIdx.x; x <= tl.cnt; x += 64) s_off[x] = in_off[tl.i0 + x];
+  __syncthreads();
+  const int lane = threadIdx.x;
+  const int r = lane / L, q = lane % L;
+  const bool on = r < ceff;
+  const int rr = on ? r : 0;  // rows past ceff read chunk 0 (in bounds) and are never used
+  unsigned zmask = 0;         // values of this lane that travel without cost (CC lanes)
+#pragma unroll
+  for (int j = 0; j < R; ++j) zmask |= (unsigned)((zero.bits[rr] >> (q * R + j)) & 1ull) << j;
+  const T16* Hr = reinterpret_cast<const T16*>(D16 + row(rr, n, 0)) + q;
+  const T32* Dr = reinterpret_cast<const T32*>(D + row(rr, n, 0)) + q;
+  T32* MBr = reinterpret_cast<T32*>(MB + row(rr, n, 0)) + q;
+  int x = owner_of(s_off, tl.cnt, tl.j0);
+  int64_t next = s_off[x + 1];
+  uint32_t run[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) run[j] = kInf;
+  auto flush = [&](int xo) {  // uniform over the wavefront
+    const int64_t v = tl.i0 + xo;
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < R; ++j) any |= run[j] != kInf;
+    bool imp = false;
+    if (on && any) {
+      const T32 d = Dr[v * L];
+      if (s_off[xo] >= tl.j0 && s_off[xo + 1] <= tl.j1) {  // every in-edge of v is in this tile
+        T32 nb = d;
+        bool lowered = false;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          const bool lower = run[j] < P::w(d, j);
+          P::setw(nb, j, lower ? run[j] : kInf);  // the mailbox was empty
+          lowered |= lower;
+        }
+        if (lowered) {
+          MBr[v * L] = nb;
+          imp = true;
+        }
+      } else {
+        const T32 mb = MBr[v * L];
+        uint32_t* mp = reinterpret_cast<uint32_t*>(MBr + v * L);
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+          if (run[j] < P::w(d, j) && run[j] < P::w(mb, j)) {
+            atomicMin(mp + j, run[j]);
+            imp = true;
+          }
+      }
+    }
+    if (__ballot(imp) && lane == 0) atomicOr(&improved[v >> 5], 1u << (v & 31));
+  };
+  for (int64_t e0 = tl.j0; e0 < tl.j1; e0 += U) {
+    int32_t u[U];
+    uint32_t wv[U];
+    T16 val[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) u[k] = e0 + k < tl.j1 ? in_src[e0 + k] : 0;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {  // unconditional (vertex 0's rows past the end): all loads issue first
+      wv[k] = (WEIGHTED && e0 + k < tl.j1) ? in_w[e0 + k] : 1u;
+      val[k] = Hr[(int64_t)u[k] * L];
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int64_t e = e0 + k;
+      if (e < tl.j1) {
+        if (e >= next) {  // receiver changes (uniform over the wavefront)
+          flush(x);
+#pragma unroll
+          for (int j = 0; j < R; ++j) run[j] = kInf;
+          ++x;
+          next = s_off[x + 1];
+          while (e >= next) {  // receivers without in-edges here
+            ++x;
+            next = s_off[x + 1];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          const uint32_t dv = P::h(val[k], j);
+          if (dv != 0xFFFFu) {
+            const uint32_t cand = ((zmask >> j) & 1u) ? dv : dv + wv[k];
+            run[j] = cand < run[j] ? cand : run[j];
+          }
+        }
+      }
+    }
+  }
+  flush(x);
 }
 
 // Push: the listed vertices (list[0..items), out-degree prefix P) broadcast
@@ -212,7 +371,8 @@ __global__ __launch_bounds__(64 * C) void k_ms_push(const OffT* __restrict__ off
 // bit.
 template <int C, class OffT>
 __global__ __launch_bounds__(kWG) void k_ms_apply(const OffT* __restrict__ off, int64_t n, int64_t nwords, int cs,
-                                                  uint32_t* __restrict__ D, uint32_t* __restrict__ MB,
+                                                  uint32_t* __restrict__ D, uint16_t* __restrict__ D16,
+                                                  uint32_t* __restrict__ MB,
                                                   unsigned long long* __restrict__ A_next,
                                                   uint32_t* __restrict__ improved, Counters* __restrict__ ctr,
                                                   unsigned long long* __restrict__ live) {
@@ -234,7 +394,10 @@ __global__ __launch_bounds__(kWG) void k_ms_apply(const OffT* __restrict__ off, 
     const int64_t idx = row(c, n, v) + lane;
     const uint32_t mb = MB[idx];
     const bool act = mb < D[idx];
-    if (act) D[idx] = mb;
+    if (act) {
+      D[idx] = mb;
+      if (D16) D16[idx] = (uint16_t)(mb < 0xFFFFu ? mb : 0xFFFFu);
+    }
     if (mb != kInf) MB[idx] = kInf;
     const bool sends = off[v + 1] > off[v];
     const unsigned long long mask = sends ? __ballot(act) : 0ull;
@@ -426,17 +589,48 @@ hipError_t ms_push_launch(bool weighted, const OffT* off, const int32_t* dst, co
 }
 
 template <int C>
-hipError_t ms_apply_launch(const void* off, bool off64, int64_t n, int cs, uint32_t* D, uint32_t* MB,
+hipError_t ms_apply_launch(const void* off, bool off64, int64_t n, int cs, uint32_t* D, uint16_t* D16, uint32_t* MB,
                            unsigned long long* A_next, uint32_t* improved, Counters* ctr, unsigned long long* live,
                            hipStream_t s) {
   const int64_t nwords = (n + 31) / 32;
   if (off64)
     hipLaunchKernelGGL((k_ms_apply<C, int64_t>), dim3((unsigned)nwords), dim3(kWG), 0, s, (const int64_t*)off, n,
-                       nwords, cs, D, MB, A_next, improved, ctr, live);
+                       nwords, cs, D, D16, MB, A_next, improved, ctr, live);
   else
     hipLaunchKernelGGL((k_ms_apply<C, int32_t>), dim3((unsigned)nwords), dim3(kWG), 0, s, (const int32_t*)off, n,
-                       nwords, cs, D, MB, A_next, improved, ctr, live);
+                       nwords, cs, D, D16, MB, A_next, improved, ctr, live);
   return hipGetLastError();
+}
+
+template <int R>
+hipError_t ms_pull16_launch(bool weighted, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w,
+                            int64_t n, int64_t m, const int32_t* tile_v, int64_t tile, int64_t ntiles,
+                            const uint16_t* D16, const uint32_t* D, uint32_t* MB, uint32_t* improved,
+                            const LaneMask& zero, int ceff, hipStream_t s) {
+  const size_t lds = (size_t)(tile + 2) * 8;
+  if (weighted)
+    hipLaunchKernelGGL((k_ms_pull16<R, true>), dim3((unsigned)ntiles), dim3(64), lds, s, in_off, in_src, in_w, n, m,
+                       tile_v, tile, D16, D, MB, improved, zero, ceff);
+  else
+    hipLaunchKernelGGL((k_ms_pull16<R, false>), dim3((unsigned)ntiles), dim3(64), lds, s, in_off, in_src, in_w, n, m,
+                       tile_v, tile, D16, D, MB, improved, zero, ceff);
+  return hipGetLastError();
+}
+
+// ceff chunks from the 2-byte copy, R = 1, 2 or 4 values per lane (three
+// chunks take the four-chunk layout with its last row idle).
+hipError_t launch_ms_pull16(int C, bool weighted, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w,
+                            int64_t n, int64_t m, const int32_t* tile_v, int64_t tile, int64_t ntiles,
+                            const uint16_t* D16, const uint32_t* D, uint32_t* MB, uint32_t* improved,
+                            const LaneMask& zero, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  switch (C) {
+    case 1: return ms_pull16_launch<1>(weighted, in_off, in_src, in_w, n, m, tile_v, tile, ntiles, D16, D, MB, improved, zero, C, s);
+    case 2: return ms_pull16_launch<2>(weighted, in_off, in_src, in_w, n, m, tile_v, tile, ntiles, D16, D, MB, improved, zero, C, s);
+    case 3:
+    case 4: return ms_pull16_launch<4>(weighted, in_off, in_src, in_w, n, m, tile_v, tile, ntiles, D16, D, MB, improved, zero, C, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_ms_pull(int C, bool weighted, const int64_t* in_off, const int32_t* in_src, const uint32_t* in_w,
@@ -467,14 +661,14 @@ hipError_t launch_ms_push(int C, bool weighted, const OffT* off, const int32_t* 
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_ms_apply(int C, int cs, const void* off, bool off64, int64_t n, uint32_t* D, uint32_t* MB,
-                           unsigned long long* A_next, uint32_t* improved, Counters* ctr, unsigned long long* live,
-                           hipStream_t s) {
+hipError_t launch_ms_apply(int C, int cs, const void* off, bool off64, int64_t n, uint32_t* D, uint16_t* D16,
+                           uint32_t* MB, unsigned long long* A_next, uint32_t* improved, Counters* ctr,
+                           unsigned long long* live, hipStream_t s) {
   switch (C) {
-    case 1: return ms_apply_launch<1>(off, off64, n, cs, D, MB, A_next, improved, ctr, live, s);
-    case 2: return ms_apply_launch<2>(off, off64, n, cs, D, MB, A_next, improved, ctr, live, s);
-    case 3: return ms_apply_launch<3>(off, off64, n, cs, D, MB, A_next, improved, ctr, live, s);
-    case 4: return ms_apply_launch<4>(off, off64, n, cs, D, MB, A_next, improved, ctr, live, s);
+    case 1: return ms_apply_launch<1>(off, off64, n, cs, D, D16, MB, A_next, improved, ctr, live, s);
+    case 2: return ms_apply_launch<2>(off, off64, n, cs, D, D16, MB, A_next, improved, ctr, live, s);
+    case 3: return ms_apply_launch<3>(off, off64, n, cs, D, D16, MB, A_next, improved, ctr, live, s);
+    case 4: return ms_apply_launch<4>(off, off64, n, cs, D, D16, MB, A_next, improved, ctr, live, s);
   }
   return hipErrorInvalidValue;
 }
@@ -494,9 +688,9 @@ hipError_t launch_ms_compact(const void* off, bool off64, const unsigned long lo
 
 int ms_chunks(int k) { return (k + 63) / 64; }
 
-hipError_t launch_ms_seed(const int32_t* src, const int32_t* perm, int k_real, int64_t n, uint32_t* D,
+hipError_t launch_ms_seed(const int32_t* src, const int32_t* perm, int k_real, int64_t n, uint32_t* D, uint16_t* D16,
                           unsigned long long* A, uint32_t* bits, hipStream_t s) {
-  hipLaunchKernelGGL(k_ms_seed, dim3(1), dim3(256), 0, s, src, perm, k_real, n, D, A, bits);
+  hipLaunchKernelGGL(k_ms_seed, dim3(1), dim3(256), 0, s, src, perm, k_real, n, D, D16, A, bits);
   return hipGetLastError();
 }
 
@@ -558,7 +752,7 @@ hipError_t launch_lane_clear(unsigned long long* A, int64_t n, int cs, const Lan
 // ---------------------------------------------------------------- host loop
 
 void MsState::release() {
-  for (DevBuf* b : {&D, &MB, &A[0], &A[1], &bits, &list, &P, &scan_blocks, &push_tiles, &ctr, &pull_tiles[0],
+  for (DevBuf* b : {&D, &MB, &D16, &A[0], &A[1], &bits, &list, &P, &scan_blocks, &push_tiles, &ctr, &pull_tiles[0],
                     &pull_tiles[1], &pull_tiles[2], &pull_tiles[3]})
     b->release();
   if (host) (void)hipHostFree(host);
@@ -569,13 +763,13 @@ void MsState::release() {
 
 size_t MsState::bytes() const {
   size_t b = 0;
-  for (const DevBuf* x : {&D, &MB, &A[0], &A[1], &bits, &list, &P, &scan_blocks, &push_tiles, &ctr, &pull_tiles[0],
+  for (const DevBuf* x : {&D, &MB, &D16, &A[0], &A[1], &bits, &list, &P, &scan_blocks, &push_tiles, &ctr, &pull_tiles[0],
                           &pull_tiles[1], &pull_tiles[2], &pull_tiles[3]})
     b += x->bytes;
   return b;
 }
 
-vc_status ms_reset(MsState& st, vc_graph g, int cs, hipStream_t s) {
+vc_status ms_reset(MsState& st, vc_graph g, int cs, hipStream_t s, bool shadow) {
   if (cs < 1 || cs > 4) return fail(VC_ERR_INVALID_ARG, "lane chunks must be 1..4");
   if (!g->csc_ready) return fail(VC_ERR_INVALID_ARG, "many-lane loop needs the transpose");
   if (push_lds_bytes(kMsPushTile) > g->max_lds || (size_t)(4 * kMsPullTilePerChunk + 2) * 8 > g->max_lds)
@@ -616,6 +810,11 @@ vc_status ms_reset(MsState& st, vc_graph g, int cs, hipStream_t s) {
   VC_TRY(launch_fill_u32(st.A[1].as<uint32_t>(), (int64_t)rows * 2, 0u, s));
   VC_TRY(launch_fill_u32(st.bits.as<uint32_t>(), (n + 31) / 32, 0u, s));
   st.dirty[0] = st.dirty[1] = 0;
+  st.shadow = shadow;
+  if (shadow) {  // 0xFFFF (unreached) in both halves of every word
+    VC_TRY(st.D16.ensure(rows * 64 * 2));
+    VC_TRY(launch_fill_u32(st.D16.as<uint32_t>(), (int64_t)rows * 32, kInf, s));
+  }
   return VC_OK;
 }
 
@@ -657,7 +856,11 @@ vc_status ms_superstep(MsState& st, vc_graph g, int cur, int ceff, int64_t next_
       *pushed = true;
     }
   }
-  if (pull)
+  if (pull && st.shadow)
+    VC_TRY(launch_ms_pull16(ceff, g->w != nullptr, g->csc_off_p, g->in_src, g->in_w, n, m,
+                            st.pull_tiles[0].as<int32_t>(), kMsPullTilePerChunk, st.pull_ntiles[0],
+                            st.D16.as<uint16_t>(), D, MB, bits, zero, s));
+  else if (pull)
     VC_TRY(launch_ms_pull(ceff, g->w != nullptr, g->csc_off_p, g->in_src, g->in_w, n, m,
                           st.pull_tiles[ceff - 1].as<int32_t>(), kMsPullTilePerChunk * ceff, st.pull_ntiles[ceff - 1],
                           D, MB, bits, zero, s));
@@ -665,7 +868,8 @@ vc_status ms_superstep(MsState& st, vc_graph g, int cur, int ceff, int64_t next_
   VC_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(Anext), 2 * n * clear, 0u, s));
   st.dirty[1 - cur] = ceff;
   VC_TRY(launch_zero_counters(dctr, s));
-  VC_TRY(launch_ms_apply(ceff, st.cs, g->off, g->off64, n, D, MB, Anext, bits, dctr, live, s));
+  VC_TRY(launch_ms_apply(ceff, st.cs, g->off, g->off64, n, D, st.shadow ? st.D16.as<uint16_t>() : nullptr, MB, Anext,
+                         bits, dctr, live, s));
   VC_TRY(hipMemcpyAsync(st.host, dctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
   return VC_OK;
 }
