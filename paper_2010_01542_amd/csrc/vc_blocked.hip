@@ -22,6 +22,8 @@
 // SSSP): the spread writes each slot's message (unreached for a source
 // outside the frontier), the fold takes minima in LDS and applies the pull
 // form's mailbox and improvement rule.
+#include <type_traits>
+
 #include "vc_device.h"
 
 namespace vc {
@@ -456,7 +458,6 @@ template <class M>
 __global__ __launch_bounds__(kSpreadWG) void k_pb_spread(const PbSpreadItem* __restrict__ items, int64_t n, int shift,
                                                          const uint16_t* __restrict__ srcl, const M* __restrict__ msg,
                                                          M* __restrict__ vals) {
-  constexpr int U = 8;
   extern __shared__ __align__(16) unsigned char smem[];
   M* win = reinterpret_cast<M*>(smem);
   const PbSpreadItem it = items[blockIdx.x];
@@ -464,17 +465,43 @@ __global__ __launch_bounds__(kSpreadWG) void k_pb_spread(const PbSpreadItem* __r
   const int64_t wl = (n - u0 < (1ll << shift)) ? n - u0 : (1ll << shift);
   for (int64_t i = threadIdx.x; i < wl; i += kSpreadWG) win[i] = msg[u0 + i];
   __syncthreads();
-  for (int64_t base = it.k0 + threadIdx.x; base < it.k1; base += (int64_t)kSpreadWG * U) {
-    uint16_t x[U];
+  // slots [a, z) (multiples of 4) four per lane: one 8-byte load of source
+  // offsets and one store of four messages; the at most 3 + 3 slots
+  // outside go one per thread.  (One slot per lane made the 2-byte loads
+  // cost the texture addresser as much per byte-moved as 8-byte ones: it
+  // was busy about 80 % of the pass.)
+  const int64_t au = (it.k0 + 3) & ~(int64_t)3, zd = it.k1 & ~(int64_t)3;
+  const int64_t a = au < it.k1 ? au : it.k1, z = zd > a ? zd : a;  // head [k0, a), body [a, z), tail [z, k1)
+  if (threadIdx.x < 4) {
+    const int64_t k = it.k0 + threadIdx.x;
+    if (k < a) vals[k] = win[srcl[k]];
+  } else if (threadIdx.x < 8) {
+    const int64_t k = z + (threadIdx.x - 4);
+    if (k < it.k1) vals[k] = win[srcl[k]];
+  }
+  if (z <= a) return;
+  const int64_t g0 = a >> 2, g1 = z >> 2;
+  constexpr int U4 = 2;
+  for (int64_t base = g0 + threadIdx.x; base < g1; base += (int64_t)kSpreadWG * U4) {
+    uint2 x[U4];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t k = base + (int64_t)u * kSpreadWG;
-      x[u] = k < it.k1 ? srcl[k] : 0;
+    for (int u = 0; u < U4; ++u) {
+      const int64_t g = base + (int64_t)u * kSpreadWG;
+      x[u] = reinterpret_cast<const uint2*>(srcl)[g < g1 ? g : g1 - 1];
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t k = base + (int64_t)u * kSpreadWG;
-      if (k < it.k1) vals[k] = win[x[u]];
+    for (int u = 0; u < U4; ++u) {
+      const int64_t g = base + (int64_t)u * kSpreadWG;
+      if (g < g1) {
+        const M m0 = win[x[u].x & 0xFFFFu], m1 = win[x[u].x >> 16], m2 = win[x[u].y & 0xFFFFu], m3 = win[x[u].y >> 16];
+        if constexpr (sizeof(M) == 4) {
+          reinterpret_cast<float4*>(vals)[g] = make_float4(m0, m1, m2, m3);
+        } else {
+          ulonglong2* o = reinterpret_cast<ulonglong2*>(vals) + 2 * g;
+          o[0] = make_ulonglong2(m0, m1);
+          o[1] = make_ulonglong2(m2, m3);
+        }
+      }
     }
   }
 }
@@ -525,7 +552,6 @@ __global__ __launch_bounds__(kSpreadWG) void k_pb_spread_min(const PbSpreadItem*
                                                              const uint32_t* __restrict__ active,
                                                              MT* __restrict__ vals,
                                                              const LoopState* __restrict__ loop) {
-  constexpr int U = 8;
   extern __shared__ __align__(16) uint32_t wmin[];
   if (loop && (loop->done || loop->mode != VC_SCHED_BLOCKED)) return;  // uniform: another form runs this superstep
   const PbSpreadItem it = items[blockIdx.x];
@@ -536,24 +562,59 @@ __global__ __launch_bounds__(kSpreadWG) void k_pb_spread_min(const PbSpreadItem*
   else
     stage_min_window<false>(wmin, vm, active, u0, wl);
   __syncthreads();
-  for (int64_t base = it.k0 + threadIdx.x; base < it.k1; base += (int64_t)kSpreadWG * U) {
-    uint16_t x[U];
-    uint32_t wv[U];
+  auto msg_of = [&](uint32_t src, uint32_t w) -> MT {
+    const uint32_t val = wmin[src];
+    return slot_msg<MT>(KIND == kCC ? val : sat_add(val, w));  // kInf stays unreached
+  };
+  // slots [a, z) (multiples of 4) four per lane: one load of source offsets,
+  // one of weights and one store of four messages; the at most 3 + 3 slots
+  // outside go one per thread
+  const int64_t au = (it.k0 + 3) & ~(int64_t)3, zd = it.k1 & ~(int64_t)3;
+  const int64_t a = au < it.k1 ? au : it.k1, z = zd > a ? zd : a;  // head [k0, a), body [a, z), tail [z, k1)
+  if (threadIdx.x < 8) {
+    const int64_t k = threadIdx.x < 4 ? it.k0 + threadIdx.x : z + (threadIdx.x - 4);
+    if (threadIdx.x < 4 ? k < a : k < it.k1)
+      vals[k] = msg_of(srcl[k], KIND == kSsspWeighted ? (uint32_t)wslot[k] : 1u);
+  }
+  if (z <= a) return;
+  const int64_t g0 = a >> 2, g1 = z >> 2;
+  constexpr int U4 = 2;
+  using W4 = typename std::conditional<sizeof(WT) == 1, uint32_t, uint4>::type;
+  for (int64_t base = g0 + threadIdx.x; base < g1; base += (int64_t)kSpreadWG * U4) {
+    uint2 x[U4];
+    W4 wq[U4];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      // Slots past the item's end load its last slot (k1 > k0) and store
-      // nothing: unconditional loads all issue before the first wait.
-      const int64_t k = base + (int64_t)u * kSpreadWG;
-      const int64_t kc = k < it.k1 ? k : it.k1 - 1;
-      x[u] = srcl[kc];
-      wv[u] = KIND == kSsspWeighted ? (uint32_t)wslot[kc] : 1u;
+    for (int u = 0; u < U4; ++u) {  // unconditional (clamped) loads: all issue before the first wait
+      const int64_t g = base + (int64_t)u * kSpreadWG;
+      const int64_t gc = g < g1 ? g : g1 - 1;
+      x[u] = reinterpret_cast<const uint2*>(srcl)[gc];
+      if (KIND == kSsspWeighted) wq[u] = reinterpret_cast<const W4*>(wslot)[gc];
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t k = base + (int64_t)u * kSpreadWG;
-      if (k < it.k1) {
-        const uint32_t val = wmin[x[u]];
-        vals[k] = slot_msg<MT>(KIND == kCC ? val : sat_add(val, wv[u]));  // kInf stays unreached
+    for (int u = 0; u < U4; ++u) {
+      const int64_t g = base + (int64_t)u * kSpreadWG;
+      if (g < g1) {
+        uint32_t w0 = 1u, w1 = 1u, w2 = 1u, w3 = 1u;
+        if constexpr (KIND == kSsspWeighted) {
+          if constexpr (sizeof(WT) == 1) {
+            w0 = wq[u] & 0xFFu;
+            w1 = (wq[u] >> 8) & 0xFFu;
+            w2 = (wq[u] >> 16) & 0xFFu;
+            w3 = wq[u] >> 24;
+          } else {
+            w0 = wq[u].x;
+            w1 = wq[u].y;
+            w2 = wq[u].z;
+            w3 = wq[u].w;
+          }
+        }
+        const MT m0 = msg_of(x[u].x & 0xFFFFu, w0), m1 = msg_of(x[u].x >> 16, w1);
+        const MT m2 = msg_of(x[u].y & 0xFFFFu, w2), m3 = msg_of(x[u].y >> 16, w3);
+        if constexpr (sizeof(MT) == 2)
+          reinterpret_cast<uint2*>(vals)[g] = make_uint2((uint32_t)m0 | ((uint32_t)m1 << 16),
+                                                         (uint32_t)m2 | ((uint32_t)m3 << 16));
+        else
+          reinterpret_cast<uint4*>(vals)[g] = make_uint4(m0, m1, m2, m3);
       }
     }
   }
