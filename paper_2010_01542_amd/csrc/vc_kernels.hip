@@ -287,30 +287,96 @@ __global__ __launch_bounds__(kWG) void k_pr_scatter_mp(const OffT* __restrict__ 
 // in contrib and stay as they are (such a vertex's rank is the teleport
 // term at every update, so its message is the same from the first update
 // on): the update skips those bins (a workgroup's vertices share one bin).
-template <class OffT, class M, class S>
-__global__ __launch_bounds__(kWG) void k_pr_apply(const OffT* __restrict__ off, int64_t n, double teleport,
-                                                  double damping, int64_t source, S* __restrict__ mb,
-                                                  M* __restrict__ contrib, float* __restrict__ out, int last,
-                                                  const uint8_t* __restrict__ kinds, int keep_empty) {
-  const int64_t v = gid();
-  if (v >= n) return;
-  const int kind = kinds ? kinds[v >> kPbDstShift] : kBinSplit;
-  if (keep_empty && kind == kBinEmpty) return;
-  const S x = kind != kBinEmpty ? mb[v] : S(0);
-  const double tele = source >= 0 ? (v == source ? teleport : 0.0) : teleport;
-  double r;
-  if constexpr (sizeof(S) == 8) {
-    r = fma(damping, (double)x * kFixInv, tele);
-  } else {
-    r = (double)fmaf((float)damping, x, (float)tele);
+// Four consecutive vertices per thread (one bin, since bins are aligned to
+// 4096 vertices): mailboxes and messages move as 16-byte vectors, a quarter
+// of the load and store instructions for the texture addresser (the
+// offsets are read one by one, since a borrowed offset array need not be
+// 16-byte aligned; so are the final ranks when the caller's buffer is not).
+// The last n % 4 vertices go one per thread.
+template <class S>
+struct Vec4;
+template <>
+struct Vec4<unsigned long long> {
+  __device__ __forceinline__ static void load(const unsigned long long* p, unsigned long long* x) {
+    const ulonglong2 a = reinterpret_cast<const ulonglong2*>(p)[0], b = reinterpret_cast<const ulonglong2*>(p)[1];
+    x[0] = a.x; x[1] = a.y; x[2] = b.x; x[3] = b.y;
   }
-  if (last) {
-    out[v] = (float)r;
+  __device__ __forceinline__ static void store(unsigned long long* p, const unsigned long long* x) {
+    reinterpret_cast<ulonglong2*>(p)[0] = make_ulonglong2(x[0], x[1]);
+    reinterpret_cast<ulonglong2*>(p)[1] = make_ulonglong2(x[2], x[3]);
+  }
+};
+template <>
+struct Vec4<float> {
+  __device__ __forceinline__ static void load(const float* p, float* x) {
+    const float4 a = reinterpret_cast<const float4*>(p)[0];
+    x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+  }
+  __device__ __forceinline__ static void store(float* p, const float* x) {
+    reinterpret_cast<float4*>(p)[0] = make_float4(x[0], x[1], x[2], x[3]);
+  }
+};
+
+template <class OffT, class M, class S>
+__global__ __launch_bounds__(kWG) void k_pr_apply4(const OffT* __restrict__ off, int64_t n, double teleport,
+                                                   double damping, int64_t source, S* __restrict__ mb,
+                                                   M* __restrict__ contrib, float* __restrict__ out, int last,
+                                                   const uint8_t* __restrict__ kinds, int keep_empty) {
+  const int64_t v0 = gid() * 4;
+  if (v0 >= n) return;
+  if (v0 + 4 > n) {  // the tail, one vertex at a time
+    for (int64_t v = v0; v < n; ++v) {
+      const int kind = kinds ? kinds[v >> kPbDstShift] : kBinSplit;
+      if (keep_empty && kind == kBinEmpty) continue;
+      const S x = kind != kBinEmpty ? mb[v] : S(0);
+      const double tele = source >= 0 ? (v == source ? teleport : 0.0) : teleport;
+      double r;
+      if constexpr (sizeof(S) == 8)
+        r = fma(damping, (double)x * kFixInv, tele);
+      else
+        r = (double)fmaf((float)damping, x, (float)tele);
+      if (last) {
+        out[v] = (float)r;
+        continue;
+      }
+      if (kind == kBinSplit) mb[v] = S(0);
+      contrib[v] = rank_msg<M, S>(r, (int64_t)off[v + 1] - (int64_t)off[v]);
+    }
     return;
   }
-  if (kind == kBinSplit) mb[v] = S(0);
-  const int64_t deg = (int64_t)off[v + 1] - (int64_t)off[v];
-  contrib[v] = rank_msg<M, S>(r, deg);
+  const int kind = kinds ? kinds[v0 >> kPbDstShift] : kBinSplit;
+  if (keep_empty && kind == kBinEmpty) return;
+  S x[4] = {S(0), S(0), S(0), S(0)};
+  if (kind != kBinEmpty) Vec4<S>::load(mb + v0, x);
+  double r[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const double tele = source >= 0 ? (v0 + j == source ? teleport : 0.0) : teleport;
+    if constexpr (sizeof(S) == 8)
+      r[j] = fma(damping, (double)x[j] * kFixInv, tele);
+    else
+      r[j] = (double)fmaf((float)damping, x[j], (float)tele);
+  }
+  if (last) {
+    if ((reinterpret_cast<uintptr_t>(out) & 15) == 0) {  // uniform: the caller's buffer may be 4-byte aligned only
+      reinterpret_cast<float4*>(out + v0)[0] = make_float4((float)r[0], (float)r[1], (float)r[2], (float)r[3]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) out[v0 + j] = (float)r[j];
+    }
+    return;
+  }
+  if (kind == kBinSplit) {
+    const S z[4] = {S(0), S(0), S(0), S(0)};
+    Vec4<S>::store(mb + v0, z);
+  }
+  int64_t o[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) o[j] = (int64_t)off[v0 + j];
+  M msg[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) msg[j] = rank_msg<M, S>(r[j], o[j + 1] - o[j]);
+  Vec4<M>::store(contrib + v0, msg);
 }
 
 // ------------------------------------------------------------------ CC / SSSP
@@ -780,11 +846,11 @@ hipError_t pr_launch_all(int what, const void* off, bool off64, const int32_t* d
     }
     default:  // apply; a = teleport, b = damping
       if (off64)
-        hipLaunchKernelGGL((k_pr_apply<int64_t, M, S>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int64_t*)off, n,
-                           a, b, source, mbx, c, out, (int)last, kinds, (int)keep_empty);
+        hipLaunchKernelGGL((k_pr_apply4<int64_t, M, S>), dim3(grid_for((n + 3) / 4)), dim3(kWG), 0, s,
+                           (const int64_t*)off, n, a, b, source, mbx, c, out, (int)last, kinds, (int)keep_empty);
       else
-        hipLaunchKernelGGL((k_pr_apply<int32_t, M, S>), dim3(grid_for(n)), dim3(kWG), 0, s, (const int32_t*)off, n,
-                           a, b, source, mbx, c, out, (int)last, kinds, (int)keep_empty);
+        hipLaunchKernelGGL((k_pr_apply4<int32_t, M, S>), dim3(grid_for((n + 3) / 4)), dim3(kWG), 0, s,
+                           (const int32_t*)off, n, a, b, source, mbx, c, out, (int)last, kinds, (int)keep_empty);
   }
   return hipGetLastError();
 }
