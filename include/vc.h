@@ -325,7 +325,10 @@ vc_status vc_graph_prepare(vc_graph g, vc_program program, const vc_params* para
  *            unreached).
  *   stats    |F_s| counts vertices with at least one improved source.
  * The device state is N x 64*ceil(k/64) distances and mailboxes (8 bytes per
- * vertex and source), kept with the graph for reuse.
+ * vertex and source) and, when the largest edge weight is below 0xFFFF, a
+ * 2-byte copy of the distances that the pull reads while no distance can
+ * reach 0xFFFF (2 more bytes per vertex and source), kept with the graph for
+ * reuse.
  * Errors: VC_ERR_INVALID_ARG (null, k outside 1..256, source >= N),
  * VC_ERR_NOT_CONVERGED, VC_ERR_OUT_OF_MEMORY, VC_ERR_HIP. */
 vc_status vc_run_multi_source(vc_graph g, const uint32_t* sources, int32_t k, const vc_params* params, uint32_t* out,
